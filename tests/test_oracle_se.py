@@ -1,0 +1,280 @@
+"""Pins of the discrete Spectral Ewald oracle (oracle/se_discrete.py):
+numbers the paper prints, closed forms checked by quadrature, limits, an
+exact special case of the adaptive FFT, and agreement with the direct Ewald
+oracle within the paper's error estimates."""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, special
+
+import workloads as wl
+from oracle import direct
+from oracle import se_discrete as se
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+# --- numbers printed in the paper -----------------------------------------
+
+def test_kp_kspace_estimate_printed_value():
+    """Section 7.1: N=1e5, Q=3.32e4, L=1, xi=8, M=32 -> truncation error
+    around 1.65e-17 by Eq. (KP_fourier_space)."""
+    e = se.kp_kspace_error(3.32e4, 8.0, 1.0, 32)
+    assert abs(e - 1.65e-17) / 1.65e-17 < 0.01
+
+
+def test_kp_relative_estimates_printed_values():
+    """Caption of the error-pollution figure: N=1000, L=5, xi=6, Q=334 and
+    M=70/100/140 give relative truncation errors 1.5e-8, 7.4e-15, 1.7e-26.
+    Relative means divided by B (Section 5.2); the paper does not state its
+    normalisation exactly, so agreement within 10 percent is asked."""
+    B = se.B_scale(334.0, 6.0, 5.0)
+    for M, printed in ((70, 1.5e-8), (100, 7.4e-15), (140, 1.7e-26)):
+        r = se.kp_kspace_error(334.0, 6.0, 5.0, M) / B
+        assert abs(r - printed) / printed < 0.10
+
+
+def test_vandermonde_condition_number():
+    """Section 4.1: the Chebyshev-point Vandermonde matrix has condition
+    number about 0.6 x 10^{0.38 nu}, 1.6e3 at nu = 9."""
+    for nu in (4, 6, 9, 12):
+        k = np.arange(1, nu + 2)
+        xb = np.cos(np.pi * (k - 0.5) / (nu + 1))
+        V = xb[:, None] ** np.arange(nu + 1)[None, :]
+        c = np.linalg.cond(V)
+        assert 0.5 < c / (0.6 * 10 ** (0.38 * nu)) < 2.0
+        if nu == 9:
+            assert 1.0e3 < c < 2.0e3
+
+
+# --- windows ----------------------------------------------------------------
+
+def test_pkb_fit_converges_to_kb():
+    """The PKB window reproduces the KB window to the accuracy its degree
+    allows; error falls fast with nu (Section 4.1, Fig. poldeg-vs-P)."""
+    P, beta = 8, 20.0
+    errs = []
+    for nu in (4, 6, 9):
+        p = se.Params(D=3, L=1.0, xi=8.0, M=32, P=P, window="pkb", nu=nu)
+        t = np.random.default_rng(0).random(2000) * 32
+        _, W, _ = se.weights_1d(t, p)
+        pk = se.Params(D=3, L=1.0, xi=8.0, M=32, P=P, window="kb")
+        _, Wk, _ = se.weights_1d(t, pk)
+        errs.append(np.abs(W - Wk).max())
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[1] < 1e-5 and errs[2] < 1e-9
+
+
+def test_pkb_derivative_matches_kb_derivative():
+    P = 8
+    t = np.random.default_rng(1).random(500) * 32
+    p = se.Params(D=3, L=1.0, xi=8.0, M=32, P=P, window="pkb", nu=9)
+    pk = se.Params(D=3, L=1.0, xi=8.0, M=32, P=P, window="kb")
+    _, _, d = se.weights_1d(t, p)
+    _, _, dk = se.weights_1d(t, pk)
+    assert np.abs(d - dk).max() < 1e-6 * np.abs(dk).max()
+
+
+def test_kb_fourier_transform_closed_form():
+    """Eq. (kaiser_ft) against quadrature of Eq. (kaiser_window)."""
+    P, h, beta = 8, 1.0 / 32, 20.0
+    w = P * h / 2
+    for k in (0.0, 30.0, 150.0, 300.0):
+        f = lambda xx: special.i0(beta * math.sqrt(max(0.0, 1 - (xx / w) ** 2))) / special.i0(beta) * math.cos(k * xx)
+        ref = 2 * integrate.quad(f, 0, w, limit=200, epsabs=1e-15, epsrel=1e-13)[0]
+        val = float(se.window_ft(k, h, P, "kb", beta))
+        assert abs(val - ref) <= 1e-9 * abs(se.window_ft(0.0, h, P, "kb", beta))
+
+
+def test_gaussian_fourier_transform_untruncated():
+    P, h = 8, 1.0 / 32
+    a = (math.pi / 2) * P * 0.91
+    w = P * h / 2
+    for k in (0.0, 50.0, 200.0):
+        f = lambda xx: math.exp(-a * (xx / w) ** 2) * math.cos(k * xx)
+        ref = 2 * integrate.quad(f, 0, 20 * w, limit=200, epsabs=1e-15)[0]
+        assert abs(float(se.window_ft(k, h, P, "gaussian", a)) - ref) < 1e-12
+
+
+# --- modified Green's functions (Section 3.1, Appendix A) -------------------
+
+def test_green_limits():
+    R = 1.7
+    k = 1e-3   # small enough for the O(k^2 R^2) deviation, large enough to avoid cancellation
+    assert abs(float(se.G_hat_0P(k, R)) - R * R / 2) < 1e-5 * R * R
+    assert abs(float(se.G_hat_1P_zero(k, R)) - R * R / 4 * (1 - 2 * math.log(R))) < 1e-5 * R * R
+    assert abs(float(se.G_hat_2P_zero(k, R)) + R * R / 2) < 1e-5 * R * R
+
+
+def test_green_2p_appendix_a_quadrature():
+    """Appendix A: FT of the truncated G(z) = -|z|/2 over |z| <= R."""
+    R = 1.9
+    for kap in (0.3, 2.0, 7.5, 40.0):
+        ref = integrate.quad(lambda z: -abs(z) / 2 * math.cos(kap * z), -R, R, limit=400)[0]
+        assert abs(float(se.G_hat_2P_zero(kap, R)) - ref) < 1e-10
+
+
+def test_green_0p_quadrature():
+    """FT of 1/(4 pi r) truncated at r <= R: int_0^R sin(k r)/k dr."""
+    R = 2.3
+    for k in (0.5, 3.0, 17.0):
+        ref = integrate.quad(lambda r: math.sin(k * r) / k, 0, R, limit=400)[0]
+        assert abs(float(se.G_hat_0P(k, R)) - ref) < 1e-12
+
+
+def test_green_1p_quadrature():
+    """FT of the 2D Green's function -(1/2 pi) log(rho) truncated at rho <= R:
+    -int_0^R rho log(rho) J0(kappa rho) d rho."""
+    R = 1.6
+    for kap in (0.4, 3.0, 11.0):
+        ref = -integrate.quad(lambda r: r * math.log(r) * special.j0(kap * r), 0, R, limit=400)[0]
+        assert abs(float(se.G_hat_1P_zero(kap, R)) - ref) < 1e-10
+
+
+# --- parameter rules --------------------------------------------------------
+
+def test_extended_grid_rule():
+    """Mt = 2 ceil((M + lambda P)/2), then rounded up to a 7-smooth even size."""
+    p = se.Params(D=2, L=1.0, xi=10.0, M=96, P=8, s=2.0, n_l=4)
+    assert 2 * math.ceil((96 + 2.4 * 8) / 2) == 116
+    assert p.Mt == 120           # 116 = 4*29 -> 120
+    p0 = se.Params(D=0, L=1.0, xi=10.0, M=64, P=8)
+    assert p0.Mt == 80 and p0.n0 == 224
+    for n in (2, 14, 22, 26, 34, 38, 46, 62, 74, 76, 116, 298, 496):
+        m = se.smooth_even_up(n)
+        assert m >= n and m % 2 == 0
+        r = m
+        for f in (2, 3, 5, 7):
+            while r % f == 0:
+                r //= f
+        assert r == 1
+
+
+def test_workload_xi_values():
+    """The xi of each configuration: the KP k-space estimate over B reaches
+    the stated level at the given M, capped by the pollution bound."""
+    from scipy.optimize import brentq
+    cases = [("C1_3P", 1e-8, "gaussian"), ("C2_0P", 1e-8, "pkb"), ("C3_2P", 1e-7, "pkb"),
+             ("C4_1P", 1e-7, "pkb")]
+    for name, level, win in cases:
+        c = wl.CONFIGS[name]
+        N, L, M, P = c["N"], c["L"], c["M"], c["P"]
+        Q = float(N)   # +-1 charges; normal charges have E[q^2] = 1
+        f = lambda xi: math.log(se.kp_kspace_error(Q, xi, L, M) / se.B_scale(Q, xi, L)) - math.log(level)
+        xi_kp = brentq(f, M / 8.0, 500.0)
+        xstar = brentq(lambda xx: se.pollution_bound(win, xx) - P, 0.1, 100.0)
+        xi_poll = M / (xstar * L)
+        assert abs(min(xi_kp, xi_poll) - c["xi"]) < 0.006
+
+
+# --- the discrete algorithm --------------------------------------------------
+
+def _sys(D, N=150, seed=5):
+    x, q = wl.system(N, 1.0, seed + D, "uniform")
+    return x, q, float((q * q).sum())
+
+
+@pytest.mark.parametrize("D", [3, 2, 1, 0])
+@pytest.mark.parametrize("win,P", [("pkb", 8), ("gaussian", 8), ("pkb", 6)])
+def test_error_within_paper_estimate(D, win, P):
+    """With truncation and AFT errors negligible, the relative rms error of
+    the SE potential is about 10 e^{-2.5P} (PKB) or 2 e^{-(pi/2) P c}
+    (Gaussian) (Section 5.2, Fig. AB_test); asked: within a factor 4."""
+    x, q, Q = _sys(D)
+    L, xi, M = 1.0, 8.0, 32
+    B = se.B_scale(Q, xi, L)
+    p = se.with_aft_estimates(D, L, xi, M, P, Q, 1e-15 * B, window=win)
+    phi, _ = se.spectral_ewald(x, q, p, grad=False)
+    ref, _ = direct.kspace(D, L, xi, x, q)
+    est = 10 * math.exp(-2.5 * P) if win == "pkb" else 2 * math.exp(-(math.pi / 2) * P * math.sqrt(0.91))
+    err = math.sqrt(np.mean((phi - ref) ** 2)) / B
+    assert est / 4 < err < 4 * est
+
+
+@pytest.mark.parametrize("D", [3, 2, 1, 0])
+def test_high_accuracy_against_direct(D):
+    """PKB P=16 with nu=9: the SE result equals the direct sum to ~1e-12."""
+    x, q, Q = _sys(D, N=120)
+    L, xi, M = 1.0, 8.0, 40
+    B = se.B_scale(Q, xi, L)
+    p = se.with_aft_estimates(D, L, xi, M, 16, Q, 1e-16 * B, window="pkb")
+    phi, g = se.spectral_ewald(x, q, p)
+    ref, gref = direct.kspace(D, L, xi, x, q)
+    assert rel(phi, ref) < 5e-12
+    assert rel(g, gref) < 5e-10
+
+
+def test_aft_special_case_equals_global_upsampling():
+    """Section 3.4: with n_l = k_inf and s = s0 the AFT is a plain FFT with
+    global upsampling s0 in the free directions.  The reference here pads the
+    whole grid and scales with one mask-free expression."""
+    for D in (2, 1):
+        x, q, Q = _sys(D, N=60)
+        p = se.Params(D=D, L=1.0, xi=8.0, M=24, P=8, window="pkb", s=None, n_l=12,
+                      s0=2.5) if False else None
+        p = se.Params(D=D, L=1.0, xi=8.0, M=24, P=8, window="pkb", s=2.5, n_l=12, s0=2.5)
+        H, _ = se.gridding(x, q, p)
+        Ht = se.scaled_convolution(H, p)
+        # global upsampling reference
+        n = p.n0
+        assert n == p.nI
+        free = tuple(range(D, 3))
+        s = [H.shape[d] if d < D else n for d in range(3)]
+        Hh = np.fft.fftn(H, s=s, axes=(0, 1, 2))
+        ks = []
+        for d in range(3):
+            if d < D:
+                ks.append(2 * np.pi * np.fft.fftfreq(p.M, d=p.h))
+            else:
+                ks.append(2 * np.pi * np.fft.fftfreq(n, d=p.h))
+        KX, KY, KZ = np.meshgrid(*ks, indexing="ij")
+        K2 = KX ** 2 + KY ** 2 + KZ ** 2
+        kp2 = sum([KX, KY, KZ][d] ** 2 for d in range(D))
+        kf = np.sqrt(sum([KX, KY, KZ][d] ** 2 for d in range(D, 3)))
+        with np.errstate(divide="ignore", invalid="ignore"):
+            Gk = 1.0 / K2
+        G0 = se.G_hat_2P_zero(kf, p.R) if D == 2 else se.G_hat_1P_zero(kf, p.R)
+        G = np.where(kp2 == 0, G0, Gk)
+        S = np.ones_like(K2)
+        for kk in (KX, KY, KZ):
+            S = S * np.exp(-kk ** 2 / (4 * p.xi ** 2)) / se.window_ft(kk, p.h, p.P, p.window, p.shape) ** 2
+        out = np.fft.ifftn(S * G * Hh)[: H.shape[0], : H.shape[1], : H.shape[2]].real
+        assert rel(Ht, out) < 1e-13
+
+
+@pytest.mark.parametrize("D", [3, 2, 1, 0])
+def test_operator_symmetry(D):
+    """phi = A q with A symmetric: <A u, v> = <u, A v> (same window for
+    gridding and gathering, real even scaling)."""
+    x, _, _ = _sys(D, N=80)
+    rng = np.random.default_rng(D)
+    u = rng.standard_normal(80); u -= u.mean()
+    v = rng.standard_normal(80); v -= v.mean()
+    p = se.with_aft_estimates(D, 1.0, 8.0, 32, 8, 80.0, 1e-10, window="pkb")
+    GR = se.precompute_0P(p) if D == 0 else None
+    Au, _ = se.spectral_ewald(x, u, p, grad=False, GR=GR)
+    Av, _ = se.spectral_ewald(x, v, p, grad=False, GR=GR)
+    assert abs(np.dot(Au, v) - np.dot(u, Av)) < 1e-12 * abs(np.dot(Au, v))
+
+
+@pytest.mark.parametrize("D", [3, 0])
+def test_gradient_is_energy_derivative(D):
+    """q_m grad phi_m = dE/dx_m for the discrete energy E = 1/2 q.phi,
+    with the exact derivative of the PKB polynomial (central differences,
+    steps well inside one grid subinterval)."""
+    x, q, Q = _sys(D, N=40)
+    p = se.with_aft_estimates(D, 1.0, 8.0, 32, 8, Q, 1e-10, window="pkb")
+    GR = se.precompute_0P(p) if D == 0 else None
+    phi, g = se.spectral_ewald(x, q, p, GR=GR)
+    eps = 1e-7
+    for m in (0, 5):
+        for d in range(3):
+            xp = x.copy(); xp[m, d] += eps
+            xm = x.copy(); xm[m, d] -= eps
+            ep = se.energy(q, se.spectral_ewald(xp, q, p, grad=False, GR=GR)[0])
+            em = se.energy(q, se.spectral_ewald(xm, q, p, grad=False, GR=GR)[0])
+            fd = (ep - em) / (2 * eps)
+            assert abs(fd - q[m] * g[m, d]) < 1e-6 * max(1.0, abs(fd))

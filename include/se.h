@@ -1,0 +1,185 @@
+/*
+ * se.h -- C ABI of the MI355X Spectral Ewald k-space library.
+ *
+ * The library computes the Fourier-space (k-space) part of the electrostatic
+ * potential of N point charges with periodicity D in {3,2,1,0}, by the
+ * Spectral Ewald method of Shamshirgar, Bagge and Tornberg, "Fast Ewald
+ * summation for electrostatic potentials with arbitrary periodicity"
+ * (arXiv:1712.04732):
+ *
+ *   problem      Section 2, Eq. (potential): charges q_n at x_n in [0,L)^3,
+ *                lattice P_D of periodic images; the k-space part is
+ *                Eq. (fourier_space_nonzero_ewald), the self term Section 2.
+ *   method       Algorithm 4 (gridding, FFT / adaptive FFT (Algorithm 1) /
+ *                zero-padded FFT, scaling by Eq. (scale) with the modified
+ *                Green's functions of Section 3.1, IFFT / AIFT (Algorithm 2),
+ *                gathering by the trapezoidal rule of Eq. (complete_integral)).
+ *   precompute   Algorithm 3 (free space), done once per plan in FP64.
+ *   windows      Section 4: truncated Gaussian, Eq. (gaussian); KB window
+ *                Eq. (kaiser_window) evaluated as the piecewise polynomial
+ *                (PKB) of Section 4.1.
+ *   parameters   Section 6 (Table lambda, Eqs. estimate-s, estimate-nl).
+ *   forces       Section 7.2, method 1, Eq. (force-method-1).
+ *
+ * Conventions shared by every entry point
+ *   - Device pointers are HIP device addresses on the device current when the
+ *     plan was created.  Host pointers are marked "host".
+ *   - Positions: N x 3, row-major (x0,y0,z0,x1,...).  Periodic directions are
+ *     the first D coordinates (x; x,y; x,y,z).  Periodic coordinates may lie
+ *     anywhere (they are wrapped into [0,L)); free coordinates must lie in
+ *     [0,L).
+ *   - Position and charge arrays are float64, or float32 when the flag
+ *     SE_IN_F32 is given.  Potentials and gradients are written in the plan's
+ *     compute precision (se_params.prec).  Energies are always float64.
+ *   - All work is enqueued on the HIP stream passed in (NULL = the default
+ *     stream) and returns without waiting, except where SE_SYNC_CHECK is set.
+ *   - Nothing is allocated or freed during se_eval; plans own their device
+ *     memory from se_plan_create until se_plan_destroy.
+ *   - No exceptions cross the ABI; every call returns an se_status.
+ */
+#ifndef SE_MI355X_H
+#define SE_MI355X_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SE_OK = 0,
+  SE_ERR_ARG = 1,         /* NULL pointer, negative size, bad flag combination   */
+  SE_ERR_PARAM = 2,       /* parameters violate Section 3.3 / Section 6 rules    */
+  SE_ERR_NONNEUTRAL = 3,  /* |sum q| > 1e-10 sum |q| for D = 1, 2, 3 (Section 2) */
+  SE_ERR_OUT_OF_BOX = 4,  /* a free-direction coordinate outside [0, L)           */
+  SE_ERR_NONFINITE = 5,   /* NaN or Inf in positions or charges                   */
+  SE_ERR_DEVICE = 6,      /* a HIP runtime call failed                            */
+  SE_ERR_NOMEM = 7,       /* device allocation failed in se_plan_create           */
+  SE_ERR_UNSUPPORTED = 8  /* valid request this build does not implement           */
+} se_status;
+
+typedef enum { SE_WIN_GAUSSIAN = 0, SE_WIN_PKB = 1 } se_window;
+typedef enum { SE_F64 = 0, SE_F32 = 1 } se_precision;
+
+/* Parameters of one system (Algorithm 4 input list, Section 6 rules).
+ * Fields marked "<= 0 -> default" take the paper's rule when left at 0. */
+typedef struct {
+  int D;              /* periodic directions: 3, 2, 1 or 0                       */
+  double L;           /* cubic box side, > 0                                     */
+  double xi;          /* Ewald parameter xi > 0 (Eq. gamma)                      */
+  int M;              /* grid intervals per periodic side, even, 7-smooth        */
+  int P;              /* window support in grid intervals, even, 2..16, P <= M   */
+  se_window window;
+  double shape;       /* alpha (Gaussian) / beta (KB); <= 0 -> (pi/2) P 0.91 / 2.5 P */
+  int nu;             /* PKB polynomial degree; <= 0 -> min(P/2 + 2, 9)          */
+  double lambda;      /* free-direction extension factor; <= 0 -> Table lambda   */
+  double s0;          /* zero-mode / free-space upsampling; <= 0 -> 2 / 2.5 / 2.8 */
+  double s;           /* AFT upsampling of the set I (Eq. I); <= 0 -> Eq. estimate-s */
+  int n_l;            /* size of the set I; < 0 -> Eq. estimate-nl                */
+  double tol;         /* absolute rms tolerance for the s, n_l estimates          */
+  double Q;           /* sum of q^2, used by the s, n_l estimates (B, Section 5.2) */
+  se_precision prec;  /* compute precision of grid, FFT, gather                   */
+  int tile;           /* spread/gather tile edge in grid points; <= 0 -> automatic */
+} se_params;
+
+/* Derived sizes of a plan (read-only report). */
+typedef struct {
+  int D, M, P, nu;
+  int Mt;             /* extended free-direction grid, Section 3.3 (rounded, see below) */
+  int n0;             /* length of the zero-mode (2P/1P) or precompute (0P) transform  */
+  int nI;             /* length of the set-I transforms (2P/1P)                        */
+  int n_l;            /* size of the set I                                             */
+  int grid[3];        /* gridding grid points in x, y, z                               */
+  int nfft[3];        /* transform lengths of the periodic / 0P padded directions      */
+  int tile;
+  double h, shape, lambda, s0, s, R;
+  size_t device_bytes; /* device memory held by the plan                               */
+} se_plan_info;
+
+typedef struct se_plan se_plan;
+
+/* eval flags */
+#define SE_IN_F32      0x1u  /* positions and charges are float32               */
+#define SE_ADD_SELF    0x2u  /* add phi_self = -2 xi/sqrt(pi) q (Section 2)     */
+#define SE_SYNC_CHECK  0x4u  /* wait for the stream and report device-side errors */
+#define SE_OUT_GRAD    0x8u  /* 'force' receives grad phi instead of -q grad phi */
+#define SE_ALLOW_NONNEUTRAL 0x10u /* skip the neutrality check (adjoint passes whose
+                                     'charges' are cotangents)                     */
+#define SE_PROFILE     0x20u  /* record a HIP event pair around every kernel launch */
+
+/* Fill *out with the paper's parameter rules (Section 6) for a system of N
+ * charges with sum of squares Q: shape, nu, lambda, s0, and s, n_l from the
+ * absolute tolerance tol (Eqs. estimate-s, estimate-nl).  M and P are taken
+ * as given (the grid and support that the caller chose).
+ * Errors: SE_ERR_ARG for out == NULL; SE_ERR_PARAM for invalid D, L, xi,
+ * M, P or tol. */
+se_status se_params_default(int D, double L, double xi, int M, int P, se_window window,
+                            double Q, double tol, se_precision prec, se_params* out);
+
+/* Validate the parameters, derive the grids (Section 3.3: Mt = 2 ceil((M +
+ * lambda P)/2); Mt, s0 Mt and s Mt are rounded up to even integers with prime
+ * factors 2, 3, 5, 7 only), build the FP64 tables (PKB coefficients by the
+ * Vandermonde solve of Eq. polynomial-linsys, separable scaling vectors of
+ * Eq. scale, Green's-function tables of Eqs. G_hat_0d..G_hat_3d), allocate
+ * device memory for up to n_max particles, and for D = 0 run Algorithm 3 on
+ * the GPU in FP64.  hip_stream: the hipStream_t used for the setup work.
+ * On success *out owns device memory until se_plan_destroy.
+ * Errors: SE_ERR_ARG, SE_ERR_PARAM, SE_ERR_NOMEM, SE_ERR_DEVICE. */
+se_status se_plan_create(const se_params* params, long n_max, void* hip_stream, se_plan** out);
+
+/* Copy the derived sizes of a plan into *info (host). */
+se_status se_plan_get_info(const se_plan* plan, se_plan_info* info);
+
+/* One evaluation of Algorithm 4 for N <= n_max charges.
+ *   xyz    device, N x 3 positions (float64, or float32 with SE_IN_F32)
+ *   q      device, N charges (same dtype as xyz)
+ *   phi    device, N potentials phi~^{D,F} (+ phi_self with SE_ADD_SELF), or NULL
+ *   force  device, N x 3 forces -q grad phi (Eq. force-method-1, gradient of the
+ *          gathering window), or grad phi with SE_OUT_GRAD, or NULL
+ *   energy device, one float64: E = 1/2 sum_m q_m phi_m (+ the self energy
+ *          -xi/sqrt(pi) sum q^2 with SE_ADD_SELF), or NULL
+ * The energy is one half of the paper's E^F = sum q phi (Section 7.2): with the
+ * half, dE/dq = phi and -dE/dx = the forces above.
+ * Errors: SE_ERR_ARG (bad pointers, N > n_max); with SE_SYNC_CHECK also
+ * SE_ERR_NONFINITE, SE_ERR_OUT_OF_BOX, SE_ERR_NONNEUTRAL, SE_ERR_DEVICE.
+ * Without SE_SYNC_CHECK device-side errors are latched and reported by
+ * se_get_device_status; outputs of such a call are not meaningful. */
+se_status se_eval(se_plan* plan, long N, const void* xyz, const void* q, void* phi, void* force,
+                  double* energy, unsigned flags, void* hip_stream);
+
+/* Wait for the stream, then report (and clear) the device-side status word of
+ * the plan's last evaluations. */
+se_status se_get_device_status(se_plan* plan, void* hip_stream);
+
+/* Per-launch timing record (tracing subsystem).  bytes and flops are the
+ * algorithmic counts of one launch: each array element the step must read or
+ * write counted once, and the arithmetic of the step itself (window weights,
+ * stencil sums, 5 n log2 n per length-n complex transform). */
+typedef struct {
+  char name[32];
+  int launches;       /* launches accumulated since the last reset            */
+  double ms_total;    /* summed duration from HIP events on the eval stream   */
+  double bytes;       /* algorithmic bytes per launch                         */
+  double flops;       /* algorithmic flops per launch                         */
+} se_stage_record;
+
+/* Wait for the stream, then aggregate the event pairs recorded by every
+ * se_eval call with SE_PROFILE since the last reset into at most 'cap'
+ * records (host array 'out'), one per launch site; *n receives the count.
+ * reset != 0 drops the recorded events afterwards.  The event pool holds
+ * 4096 pairs; launches beyond it are not recorded.
+ * Errors: SE_ERR_ARG, SE_ERR_DEVICE. */
+se_status se_plan_profile(se_plan* plan, void* hip_stream, se_stage_record* out, int cap, int* n,
+                          int reset);
+
+/* Release all device memory of the plan.  NULL is accepted. */
+se_status se_plan_destroy(se_plan* plan);
+
+/* Static English text of a status code. */
+const char* se_status_string(se_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SE_MI355X_H */

@@ -1,0 +1,10 @@
+"""MI355X-native Spectral Ewald k-space library (arXiv:1712.04732).
+
+The computation runs in libse_mi355x.so (hand-written gfx950 HIP kernels behind
+the C ABI of include/se.h).  This package holds the ctypes binding (_lib), the
+torch-facing plan and autograd adjoint (api), and the build script (build_lib).
+"""
+from . import _lib
+from .api import SEEnergy, SEPotential, SpectralEwald, self_potential
+
+__all__ = ["SpectralEwald", "SEEnergy", "SEPotential", "self_potential", "_lib"]

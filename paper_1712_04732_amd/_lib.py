@@ -1,0 +1,200 @@
+"""ctypes binding of libse_mi355x.so with the names of include/se.h.
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Loading fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libse_mi355x.so")
+
+# se_status
+SE_OK = 0
+SE_ERR_ARG = 1
+SE_ERR_PARAM = 2
+SE_ERR_NONNEUTRAL = 3
+SE_ERR_OUT_OF_BOX = 4
+SE_ERR_NONFINITE = 5
+SE_ERR_DEVICE = 6
+SE_ERR_NOMEM = 7
+SE_ERR_UNSUPPORTED = 8
+
+SE_WIN_GAUSSIAN = 0
+SE_WIN_PKB = 1
+SE_F64 = 0
+SE_F32 = 1
+
+SE_IN_F32 = 0x1
+SE_ADD_SELF = 0x2
+SE_SYNC_CHECK = 0x4
+SE_OUT_GRAD = 0x8
+SE_ALLOW_NONNEUTRAL = 0x10
+SE_PROFILE = 0x20
+
+
+class se_params(ctypes.Structure):
+    _fields_ = [
+        ("D", ctypes.c_int),
+        ("L", ctypes.c_double),
+        ("xi", ctypes.c_double),
+        ("M", ctypes.c_int),
+        ("P", ctypes.c_int),
+        ("window", ctypes.c_int),
+        ("shape", ctypes.c_double),
+        ("nu", ctypes.c_int),
+        ("lambda_", ctypes.c_double),
+        ("s0", ctypes.c_double),
+        ("s", ctypes.c_double),
+        ("n_l", ctypes.c_int),
+        ("tol", ctypes.c_double),
+        ("Q", ctypes.c_double),
+        ("prec", ctypes.c_int),
+        ("tile", ctypes.c_int),
+    ]
+
+
+class se_plan_info(ctypes.Structure):
+    _fields_ = [
+        ("D", ctypes.c_int),
+        ("M", ctypes.c_int),
+        ("P", ctypes.c_int),
+        ("nu", ctypes.c_int),
+        ("Mt", ctypes.c_int),
+        ("n0", ctypes.c_int),
+        ("nI", ctypes.c_int),
+        ("n_l", ctypes.c_int),
+        ("grid", ctypes.c_int * 3),
+        ("nfft", ctypes.c_int * 3),
+        ("tile", ctypes.c_int),
+        ("h", ctypes.c_double),
+        ("shape", ctypes.c_double),
+        ("lambda_", ctypes.c_double),
+        ("s0", ctypes.c_double),
+        ("s", ctypes.c_double),
+        ("R", ctypes.c_double),
+        ("device_bytes", ctypes.c_size_t),
+    ]
+
+
+class se_stage_record(ctypes.Structure):
+    _fields_ = [
+        ("name", ctypes.c_char * 32),
+        ("launches", ctypes.c_int),
+        ("ms_total", ctypes.c_double),
+        ("bytes", ctypes.c_double),
+        ("flops", ctypes.c_double),
+    ]
+
+
+class SEError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {se_status_string(status)} (status {status})")
+
+
+_lib = None
+
+_SIGS = {
+    "se_params_default": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                         ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_int, ctypes.POINTER(se_params)]),
+    "se_plan_create": (ctypes.c_int, [ctypes.POINTER(se_params), ctypes.c_long, ctypes.c_void_p,
+                                      ctypes.POINTER(ctypes.c_void_p)]),
+    "se_plan_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(se_plan_info)]),
+    "se_eval": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_long, ctypes.c_void_p, ctypes.c_void_p,
+                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint,
+                               ctypes.c_void_p]),
+    "se_get_device_status": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "se_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "se_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "se_plan_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(se_stage_record),
+                                       ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
+}
+
+
+def load():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with python -m paper_1712_04732_amd.build_lib")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def se_status_string(status: int) -> str:
+    return load().se_status_string(int(status)).decode()
+
+
+def _check(status: int, what: str):
+    if status != SE_OK:
+        raise SEError(status, what)
+
+
+def se_params_default(D, L, xi, M, P, window, Q, tol, prec):
+    out = se_params()
+    _check(load().se_params_default(int(D), float(L), float(xi), int(M), int(P), int(window),
+                                    float(Q), float(tol), int(prec), ctypes.byref(out)),
+           "se_params_default")
+    return out
+
+
+def se_plan_create(params: se_params, n_max: int, stream: int = 0) -> ctypes.c_void_p:
+    plan = ctypes.c_void_p()
+    _check(load().se_plan_create(ctypes.byref(params), int(n_max), ctypes.c_void_p(stream),
+                                 ctypes.byref(plan)), "se_plan_create")
+    return plan
+
+
+def se_plan_get_info(plan) -> se_plan_info:
+    info = se_plan_info()
+    _check(load().se_plan_get_info(plan, ctypes.byref(info)), "se_plan_get_info")
+    return info
+
+
+def se_eval(plan, N, xyz_ptr, q_ptr, phi_ptr, force_ptr, energy_ptr, flags, stream) -> int:
+    """Returns the status (callers decide whether to raise)."""
+    return load().se_eval(plan, int(N), ctypes.c_void_p(xyz_ptr), ctypes.c_void_p(q_ptr),
+                          ctypes.c_void_p(phi_ptr), ctypes.c_void_p(force_ptr),
+                          ctypes.c_void_p(energy_ptr), ctypes.c_uint(flags), ctypes.c_void_p(stream))
+
+
+def se_get_device_status(plan, stream) -> int:
+    return load().se_get_device_status(plan, ctypes.c_void_p(stream))
+
+
+def se_plan_profile(plan, stream, reset=True):
+    """List of dicts {name, launches, ms_total, ms_avg, bytes, flops} per launch site."""
+    cap = 64
+    arr = (se_stage_record * cap)()
+    n = ctypes.c_int()
+    _check(load().se_plan_profile(plan, ctypes.c_void_p(stream), arr, cap, ctypes.byref(n), int(reset)),
+           "se_plan_profile")
+    out = []
+    for i in range(n.value):
+        r = arr[i]
+        out.append(dict(name=r.name.decode(), launches=r.launches, ms_total=r.ms_total,
+                        ms_avg=r.ms_total / max(r.launches, 1), bytes=r.bytes, flops=r.flops))
+    return out
+
+
+def se_plan_destroy(plan) -> int:
+    return load().se_plan_destroy(plan)
+
+
+def declared_functions(header: str | None = None):
+    """Names of the functions declared in include/se.h."""
+    import re
+    if header is None:
+        header = os.path.join(os.path.dirname(_HERE), "include", "se.h")
+    text = open(header).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\*?(se_\w+)\s*\(", text, re.M)))

@@ -1,0 +1,179 @@
+"""PyTorch face of the library: plans over torch device memory and streams,
+and the hand-written adjoint behind torch.autograd.Function.
+
+Every computation is a call of the HIP library through the C ABI; torch only
+provides device tensors and the current stream.
+"""
+from __future__ import annotations
+
+import math
+
+import torch
+
+from . import _lib as L
+
+_WINDOWS = {"gaussian": L.SE_WIN_GAUSSIAN, "pkb": L.SE_WIN_PKB}
+_PRECS = {"f64": L.SE_F64, "f32": L.SE_F32}
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+class SpectralEwald:
+    """A plan for one system size class: periodicity D, box L, Ewald xi, grid M,
+    window support P.  Parameters left as None follow the paper's rules
+    (Section 6); s and n_l need either explicit values or Q and tol.
+
+    Call it with positions x (N,3) and charges q (N,) on the GPU.
+    """
+
+    def __init__(self, D, L_box, xi, M, P, *, window="pkb", prec="f64", n_max=1 << 20,
+                 Q=None, tol=None, shape=None, nu=None, lam=None, s0=None, s=None, n_l=None,
+                 tile=0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("SpectralEwald needs a HIP device")
+        L.load()
+        w = _WINDOWS[window]
+        pr = _PRECS[prec]
+        if Q is not None and tol is not None:
+            p = L.se_params_default(D, L_box, xi, M, P, w, Q, tol, pr)
+        else:
+            p = L.se_params()
+            p.D, p.L, p.xi, p.M, p.P, p.window, p.prec = D, L_box, xi, M, P, w, pr
+            p.n_l = -1
+        if shape is not None:
+            p.shape = shape
+        if nu is not None:
+            p.nu = nu
+        if lam is not None:
+            p.lambda_ = lam
+        if s0 is not None:
+            p.s0 = s0
+        if s is not None:
+            p.s = s
+        if n_l is not None:
+            p.n_l = n_l
+        p.tile = tile
+        self.params = p
+        self.n_max = int(n_max)
+        self.prec = prec
+        self.dtype = torch.float64 if prec == "f64" else torch.float32
+        self.D, self.L, self.xi = D, L_box, xi
+        self._plan = L.se_plan_create(p, self.n_max, _stream())
+        self.info = L.se_plan_get_info(self._plan)
+
+    def __del__(self):
+        plan = getattr(self, "_plan", None)
+        if plan is not None and plan.value:
+            try:
+                L.se_plan_destroy(plan)
+            except Exception:
+                pass
+            self._plan = None
+
+    def profile(self, reset=True):
+        """Per-launch-site timings of the evaluations made with profile=True."""
+        return L.se_plan_profile(self._plan, _stream(), reset)
+
+    def evaluate(self, x, q, *, phi=True, force=True, energy=True, add_self=False,
+                 out_grad=False, check=True, allow_nonneutral=False, profile=False, out=None):
+        """One evaluation of Algorithm 4.  Returns (phi, force_or_grad, energy);
+        entries not requested are None."""
+        if x.dim() != 2 or x.shape[1] != 3 or q.dim() != 1 or q.shape[0] != x.shape[0]:
+            raise ValueError("x must be (N,3) and q (N,)")
+        if x.dtype != q.dtype or x.dtype not in (torch.float32, torch.float64):
+            raise ValueError("x and q must share dtype float32 or float64")
+        if not (x.is_cuda and q.is_cuda):
+            raise ValueError("x and q must be device tensors")
+        x = x.contiguous()
+        q = q.contiguous()
+        N = x.shape[0]
+        dev = x.device
+        if out is not None:
+            out_phi, out_f, out_e = out
+        else:
+            out_phi = torch.empty(N, dtype=self.dtype, device=dev) if phi else None
+            out_f = torch.empty((N, 3), dtype=self.dtype, device=dev) if force else None
+            out_e = torch.empty((), dtype=torch.float64, device=dev) if energy else None
+        phi, force, energy = out_phi is not None, out_f is not None, out_e is not None
+        flags = 0
+        if x.dtype == torch.float32:
+            flags |= L.SE_IN_F32
+        if add_self:
+            flags |= L.SE_ADD_SELF
+        if out_grad:
+            flags |= L.SE_OUT_GRAD
+        if check:
+            flags |= L.SE_SYNC_CHECK
+        if allow_nonneutral:
+            flags |= L.SE_ALLOW_NONNEUTRAL
+        if profile:
+            flags |= L.SE_PROFILE
+        st = L.se_eval(self._plan, N, x.data_ptr(), q.data_ptr(),
+                       out_phi.data_ptr() if phi else 0, out_f.data_ptr() if force else 0,
+                       out_e.data_ptr() if energy else 0, flags, _stream())
+        if st != L.SE_OK:
+            raise L.SEError(st, "se_eval")
+        return out_phi, out_f, out_e
+
+    __call__ = evaluate
+
+
+class SEEnergy(torch.autograd.Function):
+    """E = 1/2 sum_m q_m phi_m (k-space part, plus the self energy when
+    add_self).  Backward: dE/dq = phi, dE/dx_m = q_m grad phi(x_m), the
+    gradient of the gathering window (Eq. force-method-1)."""
+
+    @staticmethod
+    def forward(ctx, x, q, plan: SpectralEwald, add_self: bool = False):
+        phi, grad, E = plan.evaluate(x.detach(), q.detach(), out_grad=True, add_self=add_self)
+        ctx.save_for_backward(q.detach(), phi, grad)
+        ctx.xdtype = x.dtype
+        return E
+
+    @staticmethod
+    def backward(ctx, gE):
+        q, phi, grad = ctx.saved_tensors
+        gx = gq = None
+        if ctx.needs_input_grad[0]:
+            gx = (gE * q.to(torch.float64)[:, None] * grad.to(torch.float64)).to(ctx.xdtype)
+        if ctx.needs_input_grad[1]:
+            gq = (gE * phi.to(torch.float64)).to(q.dtype)
+        return gx, gq, None, None
+
+
+class SEPotential(torch.autograd.Function):
+    """phi = A(x) q.  The discrete operator A (spread, scale, gather with one
+    window) is symmetric, so for a cotangent g:
+        dL/dq   = A g
+        dL/dx_m = g_m grad phi(x_m) + q_m grad (A g)(x_m)."""
+
+    @staticmethod
+    def forward(ctx, x, q, plan: SpectralEwald, add_self: bool = False):
+        phi, grad, _ = plan.evaluate(x.detach(), q.detach(), out_grad=True, energy=False,
+                                     add_self=add_self)
+        ctx.save_for_backward(x.detach(), q.detach(), grad)
+        ctx.plan = plan
+        ctx.add_self = add_self
+        return phi
+
+    @staticmethod
+    def backward(ctx, g):
+        x, q, grad = ctx.saved_tensors
+        plan = ctx.plan
+        g = g.contiguous()
+        gin = g.to(x.dtype)
+        ag, agrad, _ = plan.evaluate(x, gin, out_grad=True, energy=False, add_self=ctx.add_self,
+                                     allow_nonneutral=True)
+        gq = ag.to(q.dtype) if ctx.needs_input_grad[1] else None
+        gx = None
+        if ctx.needs_input_grad[0]:
+            gx = (g.to(torch.float64)[:, None] * grad.to(torch.float64)
+                  + q.to(torch.float64)[:, None] * agrad.to(torch.float64)).to(x.dtype)
+        return gx, gq, None, None
+
+
+def self_potential(xi, q):
+    """phi_self = -2 xi / sqrt(pi) q (Section 2)."""
+    return -2.0 * xi / math.sqrt(math.pi) * q

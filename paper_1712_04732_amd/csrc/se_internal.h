@@ -1,0 +1,122 @@
+// Internal declarations shared by the host planner (se_plan.cpp) and the
+// gfx950 kernels (se_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace se {
+
+constexpr int kMaxStages = 16;
+constexpr int kMaxClasses = 3;
+constexpr int kMaxP = 16;
+constexpr int kMaxNu = 12;
+constexpr int kBlock = 256;      // threads per block of every kernel
+
+// Green's-function modes of the fused scaling pass (Eq. scale).
+enum GMode : int {
+  G_NONE = 0,
+  G_INVSQ = 1,  // 1/|k|^2 from squared-wavenumber tables; 0 where |k| = 0 (Eq. G_hat_3d)
+  G_TAB1 = 2,   // table over the pencil coordinate t (2P zero mode, Eq. G_hat_2d)
+  G_TAB2 = 3,   // folded table over (b0, t) (1P zero mode, Eq. G_hat_1d)
+  G_TAB3 = 4    // folded table over (b0, b1, t) (0P, Algorithm 3 output)
+};
+
+enum FftKind : int { K_C2C_FWD = 0, K_C2C_INV = 1, K_R2C = 2, K_C2R = 3, K_FUSED = 4 };
+
+// One group of pencils that share a transform length.  A pencil is addressed
+// by (b0, b1); its sample t sits at base + b0*s0 + b1*s1 + t*st (in complex
+// elements, or real elements for real input/output).
+struct FftClass {
+  int n, n_in, n_out;
+  int nst;
+  int rad[kMaxStages];
+  const void* tw;                 // n twiddles exp(-2 pi i k/n) in compute precision
+  const void* in;
+  void* out;
+  long long in_st, in_s0, in_s1;
+  long long out_st, out_s0, out_s1;
+  // scaling of the fused pass: S = sA[b0+offA] sB[b1+offB] sC[t] G
+  int gmode;
+  int offA, offB;
+  const void* sA;
+  const void* sB;
+  const void* sC;
+  const void* kA;
+  const void* kB;
+  const void* kC;
+  const void* gtab;
+  int gd1, gd2;                   // folded table row lengths
+  int fold1, fold2;               // transform lengths used to fold b1 and t
+  int fold0;                      // transform length used to fold b0 (0: b0 not folded)
+};
+
+struct FftPass {
+  FftClass cls[kMaxClasses];
+  const int4* items;              // per block: {class, b0_start, b1, count}
+  int nitems;
+  int B;                          // pencils per block
+  int nmax;                       // largest n (LDS sizing)
+  int kind;
+  double alg_bytes, alg_flops;    // algorithmic counts of one launch (tracing only)
+};
+
+// Geometry and window of the gridding / gathering kernels.
+struct GridGeom {
+  int D;
+  int G[3];           // grid points per direction (x, y, z)
+  int per[3];         // 1 if the direction is periodic
+  int d0[3];          // integer offset of the free-direction grid origin, (Mt - M)/2
+  int tile;           // tile edge in grid points
+  int chunk;          // particles staged in LDS per round (<= kBlock)
+  int nt[3];          // tiles per direction
+  int P, nu;
+  int window;         // 0 Gaussian, 1 PKB
+  double h, L, xi;
+  double alpha;       // Gaussian shape
+  double scale;       // 4 pi h^3 (trapezoidal rule of Eq. complete_integral)
+};
+
+// Device buffers of one evaluation.
+struct EvalBuffers {
+  int* tile_count;    // ntiles
+  int* tile_start;    // ntiles + 1
+  int* tile_cursor;   // ntiles
+  int* p_tile;        // n_max: tile of each particle (input order)
+  int* p_cell;        // n_max: packed cell of each particle (input order)
+  void* p_frac;       // n_max x 4 (fx, fy, fz, q) in compute precision (input order)
+  int* s_cell;        // n_max: sorted packed cells
+  int* s_idx;         // n_max: sorted original indices
+  void* s_fq;         // n_max x 4 sorted (fx, fy, fz, q)
+  double* qpart;      // per bin block: sum q, sum |q|, sum q^2
+  double* epart;      // per gather block: sum q phi
+  double* red;        // 4 doubles: Q, sum|q|, Q2, E
+  int* status;        // device status word
+  const void* wtab;   // window coefficient table (compute precision)
+  void* grid;         // real grid G[0]*G[1]*G[2]
+};
+
+// Launchers (se_kernels.hip).  All enqueue on 'st' and return the HIP error.
+hipError_t launch_bin(const GridGeom& g, const EvalBuffers& b, long N, const void* xyz,
+                      const void* q, bool in_f32, bool f64, int nblk, hipStream_t st);
+hipError_t launch_scan(const GridGeom& g, const EvalBuffers& b, int nblk_bin, int check_neutral,
+                       hipStream_t st);
+hipError_t launch_scatter(const GridGeom& g, const EvalBuffers& b, long N, bool f64, hipStream_t st);
+hipError_t launch_spread(const GridGeom& g, const EvalBuffers& b, bool f64, hipStream_t st);
+hipError_t launch_gather(const GridGeom& g, const EvalBuffers& b, bool f64, void* phi, void* force,
+                         int out_grad, double self_coef, hipStream_t st);
+hipError_t launch_energy(const GridGeom& g, const EvalBuffers& b, double* energy, double self_e,
+                         hipStream_t st);
+hipError_t launch_fft(const FftPass& p, bool f64, hipStream_t st);
+size_t fft_lds_bytes(const FftPass& p, bool f64);
+size_t spread_lds_bytes(const GridGeom& g, bool f64);
+size_t gather_lds_bytes(const GridGeom& g, bool f64);
+
+// 0P precompute helpers (FP64).
+hipError_t launch_g0p_fill(double* buf, int n0, double h, double R, hipStream_t st);
+hipError_t launch_g0p_truncate(const double* big, int n0, double* small, int Mt, hipStream_t st);
+hipError_t launch_g0p_fold(const double* full, int Mt, void* table, bool f64, hipStream_t st);
+
+}  // namespace se

@@ -1,0 +1,1056 @@
+// Host planner and C ABI of the Spectral Ewald k-space library (se.h).
+//
+// The planner applies the paper's parameter rules (Section 3.3, Section 6),
+// builds every FP64 table once (PKB coefficients of Section 4.1, separable
+// scaling vectors and Green's-function tables of Eq. scale / Section 3.1),
+// runs Algorithm 3 on the GPU for free space, allocates all device memory and
+// records the launch sequence of Algorithm 4 for one system.  se_eval only
+// enqueues kernels.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/se.h"
+#include "se_internal.h"
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+int smooth_even_up(long n) {
+  long m = std::max(2L, n);
+  if (m % 2) ++m;
+  for (;; m += 2) {
+    long r = m;
+    for (int p : {2, 3, 5, 7})
+      while (r % p == 0) r /= p;
+    if (r == 1) return (int)m;
+  }
+}
+
+bool is_smooth(long n) {
+  if (n < 1) return false;
+  for (int p : {2, 3, 5, 7})
+    while (n % p == 0) n /= p;
+  return n == 1;
+}
+
+// Radix sequence for the Stockham stages (radices 8, 4, 2, 3, 5, 7).
+bool radix_plan(int n, int* rad, int* nst) {
+  int k = 0, m = n;
+  for (int r : {8, 4, 2, 3, 5, 7}) {
+    while (m % r == 0) {
+      if (k >= se::kMaxStages) return false;
+      rad[k++] = r;
+      m /= r;
+    }
+  }
+  *nst = k;
+  return m == 1;
+}
+
+// Modified Bessel function I0 by its power series sum (x^2/4)^k / (k!)^2.
+double bessel_i0(double x) {
+  const double y = 0.25 * x * x;
+  double term = 1.0, s = 1.0;
+  for (int k = 1; k < 500; ++k) {
+    term *= y / ((double)k * k);
+    s += term;
+    if (term < 1e-17 * s) break;
+  }
+  return s;
+}
+
+// KB window in grid units u (w = P/2), Eq. (kaiser_window).
+double kb_window(double u, int P, double beta) {
+  const double z = 2.0 * u / P;
+  if (std::fabs(z) > 1.0) return 0.0;
+  return bessel_i0(beta * std::sqrt(1.0 - z * z)) / bessel_i0(beta);
+}
+
+// 1D Fourier transform of the window used in the scaling step: Eq. (kaiser_ft)
+// for KB, the untruncated Gaussian transform for the Gaussian (Section 4).
+double window_ft(double k, double h, int P, int window, double shape) {
+  const double w = P * h / 2.0;
+  if (window == SE_WIN_GAUSSIAN) return std::sqrt(kPi / shape) * w * std::exp(-k * k * w * w / (4.0 * shape));
+  const double d = shape * shape - k * k * w * w;
+  const double sd = std::sqrt(std::fabs(d));
+  double r;
+  if (sd == 0.0)
+    r = 1.0;
+  else
+    r = d > 0 ? std::sinh(sd) / sd : std::sin(sd) / sd;
+  return 2.0 * w * r / bessel_i0(shape);
+}
+
+// Solve V c = b for the (m x m) system by Gaussian elimination with partial pivoting.
+bool solve(std::vector<double> A, std::vector<double> b, int m, std::vector<double>& x) {
+  for (int c = 0; c < m; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < m; ++r)
+      if (std::fabs(A[r * m + c]) > std::fabs(A[piv * m + c])) piv = r;
+    if (A[piv * m + c] == 0.0) return false;
+    if (piv != c) {
+      for (int j = 0; j < m; ++j) std::swap(A[c * m + j], A[piv * m + j]);
+      std::swap(b[c], b[piv]);
+    }
+    for (int r = c + 1; r < m; ++r) {
+      const double f = A[r * m + c] / A[c * m + c];
+      for (int j = c; j < m; ++j) A[r * m + j] -= f * A[c * m + j];
+      b[r] -= f * b[c];
+    }
+  }
+  x.assign(m, 0.0);
+  for (int r = m - 1; r >= 0; --r) {
+    double s = b[r];
+    for (int j = r + 1; j < m; ++j) s -= A[r * m + j] * x[j];
+    x[r] = s / A[r * m + r];
+  }
+  return true;
+}
+
+// PKB coefficients (Section 4.1): on subinterval i of [-w, w] the KB window
+// is interpolated at the nu+1 Chebyshev points xbar_k = cos(pi (k - 1/2)/(nu+1))
+// by sum_j c_ij xbar^j (Eqs. polynomial-ansatz, polynomial-linsys).
+bool pkb_coefficients(int P, double beta, int nu, std::vector<double>& c) {
+  const int m = nu + 1;
+  std::vector<double> V(m * m), xb(m);
+  for (int k = 0; k < m; ++k) {
+    xb[k] = std::cos(kPi * (k + 0.5) / m);
+    double p = 1.0;
+    for (int j = 0; j < m; ++j) {
+      V[k * m + j] = p;
+      p *= xb[k];
+    }
+  }
+  c.assign((size_t)P * m, 0.0);
+  for (int i = 0; i < P; ++i) {
+    std::vector<double> rhs(m), sol;
+    for (int k = 0; k < m; ++k) rhs[k] = kb_window(-P / 2.0 + i + (xb[k] + 1.0) / 2.0, P, beta);
+    if (!solve(V, rhs, m, sol)) return false;
+    for (int j = 0; j < m; ++j) c[(size_t)i * m + j] = sol[j];
+  }
+  return true;
+}
+
+// Modified Green's functions at vanishing periodic wavenumber (Section 3.1).
+double g2p_zero(double kap, double R) {  // Eq. (G_hat_2d)
+  kap = std::fabs(kap);
+  if (kap == 0.0) return -R * R / 2.0;
+  return (1.0 - std::cos(R * kap) - R * kap * std::sin(R * kap)) / (kap * kap);
+}
+double g1p_zero(double kap, double R) {  // Eq. (G_hat_1d)
+  if (kap == 0.0) return R * R / 4.0 * (1.0 - 2.0 * std::log(R));
+  return (1.0 - ::j0(R * kap)) / (kap * kap) - R * std::log(R) * ::j1(R * kap) / kap;
+}
+
+int signed_freq(int t, int n) { return t < (n + 1) / 2 ? t : t - n; }
+
+const char* kStatusText[] = {"ok",
+                             "invalid argument",
+                             "invalid parameters",
+                             "charges are not neutral",
+                             "a free-direction coordinate lies outside [0, L)",
+                             "non-finite position or charge",
+                             "HIP runtime error",
+                             "device allocation failed",
+                             "not supported"};
+
+}  // namespace
+
+struct se_plan {
+  se_params p{};
+  se_plan_info info{};
+  bool f64 = true;
+  long n_max = 0;
+  int device = 0;
+  se::GridGeom geom{};
+  se::EvalBuffers buf{};
+  std::vector<void*> allocs;
+  std::vector<se::FftPass> passes;
+  int ntiles = 0;
+  // tracing: HIP event pairs around launches of SE_PROFILE evaluations
+  struct ProfRec {
+    int site;
+    int ev;
+    double bytes, flops;
+  };
+  std::vector<hipEvent_t> evpool;
+  int ev_used = 0;
+  std::vector<ProfRec> prof;
+  size_t lds_limit = 65536;   // soft budget: keeps several workgroups per CU
+  size_t lds_max = 65536;     // device maximum per workgroup
+  size_t bytes = 0;
+
+  ~se_plan() {
+    for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
+    for (void* a : allocs) (void)hipFree(a);
+  }
+
+  void* dalloc(size_t n) {
+    void* ptr = nullptr;
+    if (n == 0) n = 16;
+    if (hipMalloc(&ptr, n) != hipSuccess) return nullptr;
+    allocs.push_back(ptr);
+    bytes += n;
+    return ptr;
+  }
+
+  // Upload an FP64 host table in the compute precision.
+  const void* upload(const std::vector<double>& v) {
+    const size_t esz = f64 ? 8 : 4;
+    void* d = dalloc(v.size() * esz);
+    if (!d) return nullptr;
+    hipError_t e;
+    if (f64) {
+      e = hipMemcpy(d, v.data(), v.size() * 8, hipMemcpyHostToDevice);
+    } else {
+      std::vector<float> f(v.begin(), v.end());
+      e = hipMemcpy(d, f.data(), f.size() * 4, hipMemcpyHostToDevice);
+    }
+    return e == hipSuccess ? d : nullptr;
+  }
+
+  // Twiddles exp(-2 pi i k/n), k = 0..n-1, interleaved complex.
+  const void* twiddles(int n) {
+    std::vector<double> t(2 * (size_t)n);
+    for (int k = 0; k < n; ++k) {
+      const long double a = -2.0L * 3.141592653589793238462643383279502884L * k / n;
+      t[2 * k] = (double)std::cos(a);
+      t[2 * k + 1] = (double)std::sin(a);
+    }
+    return upload(t);
+  }
+
+  // Scaling vector of a direction transformed at length n over spacing h:
+  //   e^{-k^2/4xi^2} / What(k)^2 / n   with k = 2 pi m/(n h), m the signed frequency.
+  // The 1/n is the inverse transform's normalisation.
+  const void* sep_table(int n) {
+    std::vector<double> s(n);
+    for (int t = 0; t < n; ++t) {
+      const double k = 2.0 * kPi * signed_freq(t, n) / (n * info.h);
+      const double W = window_ft(k, info.h, p.P, p.window, p.shape);
+      s[t] = std::exp(-k * k / (4.0 * p.xi * p.xi)) / (W * W) / n;
+    }
+    return upload(s);
+  }
+
+  const void* k2_table(int n) {
+    std::vector<double> s(n);
+    for (int t = 0; t < n; ++t) {
+      const double k = 2.0 * kPi * signed_freq(t, n) / (n * info.h);
+      s[t] = k * k;
+    }
+    return upload(s);
+  }
+};
+
+namespace {
+
+se::FftClass make_class(int n, int n_in, int n_out, const void* tw, const void* in, void* out,
+                        long long in_st, long long in_s0, long long in_s1, long long out_st,
+                        long long out_s0, long long out_s1) {
+  se::FftClass c{};
+  c.n = n;
+  c.n_in = n_in;
+  c.n_out = n_out;
+  radix_plan(n, c.rad, &c.nst);
+  c.tw = tw;
+  c.in = in;
+  c.out = out;
+  c.in_st = in_st;
+  c.in_s0 = in_s0;
+  c.in_s1 = in_s1;
+  c.out_st = out_st;
+  c.out_s0 = out_s0;
+  c.out_s1 = out_s1;
+  return c;
+}
+
+void add_items(std::vector<int4>& items, int cls, int b0_lo, int b0_hi, int b1_lo, int b1_hi, int B) {
+  for (int b1 = b1_lo; b1 < b1_hi; ++b1)
+    for (int b0 = b0_lo; b0 < b0_hi; b0 += B) items.push_back(make_int4(cls, b0, b1, std::min(B, b0_hi - b0)));
+}
+
+}  // namespace
+
+// Finish a pass: pencils per block from the LDS budget, upload the work list.
+static bool finish_pass(se_plan* pl, se::FftPass& ps, int kind, int ncls,
+                        const std::vector<std::vector<int>>& ranges) {
+  ps.kind = kind;
+  ps.nmax = 0;
+  for (int c = 0; c < ncls; ++c) ps.nmax = std::max(ps.nmax, ps.cls[c].n);
+  const size_t esz = pl->f64 ? 16 : 8;
+  long B = ((long)(pl->lds_limit / esz) - ps.nmax) / (2L * ps.nmax);
+  if (B < 1) B = ((long)(pl->lds_max / esz) - ps.nmax) / (2L * ps.nmax);
+  if (B < 1) return false;
+  B = std::min(64L, B);
+  ps.B = (int)B;
+  std::vector<int4> items;
+  for (const auto& r : ranges) add_items(items, r[0], r[1], r[2], r[3], r[4], ps.B);
+  ps.nitems = (int)items.size();
+  // algorithmic counts: every input sample read once, every output sample
+  // written once; 5 n log2 n flops per complex length-n transform
+  {
+    const double re = pl->f64 ? 8.0 : 4.0, ce = 2.0 * re;
+    double by = 0.0, fl = 0.0;
+    for (const int4& it : items) {
+      const se::FftClass& c = ps.cls[it.x];
+      const double in_b = kind == se::K_R2C ? c.n_in * re : (kind == se::K_C2R ? (c.n / 2 + 1) * ce : c.n_in * ce);
+      const double out_b = kind == se::K_C2R ? c.n_out * re : c.n_out * ce;
+      by += it.w * (in_b + out_b);
+      fl += it.w * 5.0 * c.n * std::log2((double)c.n) * (kind == se::K_FUSED ? 2.0 : 1.0);
+    }
+    ps.alg_bytes = by;
+    ps.alg_flops = fl;
+  }
+  if (ps.nitems == 0) {
+    ps.items = nullptr;
+    return true;
+  }
+  void* d = pl->dalloc(items.size() * sizeof(int4));
+  if (!d) return false;
+  if (hipMemcpy(d, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess) return false;
+  ps.items = (const int4*)d;
+  return true;
+}
+
+extern "C" {
+
+const char* se_status_string(se_status s) {
+  if ((int)s < 0 || (int)s > 8) return "unknown status";
+  return kStatusText[(int)s];
+}
+
+static bool valid_base(int D, double L, double xi, int M, int P) {
+  if (D < 0 || D > 3) return false;
+  if (!(L > 0) || !std::isfinite(L) || !(xi > 0) || !std::isfinite(xi)) return false;
+  if (M < 2 || M % 2 || P < 2 || P % 2 || P > M || P > se::kMaxP) return false;
+  return true;
+}
+
+static double fc(double x) {  // Eq. (fc-expression)
+  return std::exp(-12.62 / (x * x)) * (0.8909 + 0.01411 * x + 4.315e-5 * x * x);
+}
+
+se_status se_params_default(int D, double L, double xi, int M, int P, se_window window, double Q,
+                            double tol, se_precision prec, se_params* out) {
+  if (!out) return SE_ERR_ARG;
+  if (!valid_base(D, L, xi, M, P) || !(tol > 0) || !(Q >= 0)) return SE_ERR_PARAM;
+  if (window != SE_WIN_GAUSSIAN && window != SE_WIN_PKB) return SE_ERR_PARAM;
+  se_params p{};
+  p.D = D;
+  p.L = L;
+  p.xi = xi;
+  p.M = M;
+  p.P = P;
+  p.window = window;
+  p.shape = window == SE_WIN_GAUSSIAN ? (kPi / 2.0) * P * 0.91 : 2.5 * P;
+  p.nu = window == SE_WIN_PKB ? std::min(P / 2 + 2, 9) : 0;
+  const double lam[2][3] = {{1.0, 1.5, 1.5}, {1.3, 2.4, 2.4}};  // Table lambda
+  const double s0[3] = {2.8, 2.5, 2.0};
+  p.lambda = D < 3 ? lam[window == SE_WIN_PKB][D] : 0.0;
+  p.s0 = D < 3 ? s0[D] : 0.0;
+  p.tol = tol;
+  p.Q = Q;
+  p.prec = prec;
+  p.s = 1.0;
+  p.n_l = 0;
+  if (D == 1 || D == 2) {
+    const int Mt = smooth_even_up(2L * (long)std::ceil((M + p.lambda * P) / 2.0));
+    const double B = std::sqrt(Q) * fc(xi * L) / L;  // Section 5.2
+    const double lg = std::log(B / (2.0 * tol)) / (2.0 * kPi);
+    p.s = std::max(1.0, (double)M / Mt * (1.0 + lg));                         // Eq. (estimate-s)
+    p.n_l = (int)std::ceil((double)M / (Mt - M) * lg - 1.0);                  // Eq. (estimate-nl)
+    p.n_l = std::max(0, std::min(M / 2, p.n_l));
+  }
+  p.tile = 0;
+  *out = p;
+  return SE_OK;
+}
+
+se_status se_plan_get_info(const se_plan* plan, se_plan_info* info) {
+  if (!plan || !info) return SE_ERR_ARG;
+  *info = plan->info;
+  info->device_bytes = plan->bytes;
+  return SE_OK;
+}
+
+se_status se_plan_destroy(se_plan* plan) {
+  if (plan) {
+    (void)hipSetDevice(plan->device);
+    delete plan;
+  }
+  return SE_OK;
+}
+
+static se_status build_passes(se_plan* pl);
+static se_status precompute_0p(se_plan* pl, hipStream_t st, const void** table);
+
+se_status se_plan_create(const se_params* params, long n_max, void* hip_stream, se_plan** out) {
+  if (!params || !out || n_max < 0 || n_max > (1L << 30)) return SE_ERR_ARG;
+  *out = nullptr;
+  se_params p = *params;
+  if (!valid_base(p.D, p.L, p.xi, p.M, p.P)) return SE_ERR_PARAM;
+  if (p.window != SE_WIN_GAUSSIAN && p.window != SE_WIN_PKB) return SE_ERR_PARAM;
+  if (p.prec != SE_F64 && p.prec != SE_F32) return SE_ERR_PARAM;
+  if (!is_smooth(p.M)) return SE_ERR_PARAM;
+  if (!(p.shape > 0)) p.shape = p.window == SE_WIN_GAUSSIAN ? (kPi / 2.0) * p.P * 0.91 : 2.5 * p.P;
+  if (p.window == SE_WIN_PKB) {
+    if (p.nu <= 0) p.nu = std::min(p.P / 2 + 2, 9);
+    if (p.nu > se::kMaxNu) return SE_ERR_PARAM;
+  } else {
+    p.nu = 0;
+  }
+  if (p.D < 3) {
+    const double lam[2][3] = {{1.0, 1.5, 1.5}, {1.3, 2.4, 2.4}};
+    const double s0[3] = {2.8, 2.5, 2.0};
+    if (!(p.lambda > 0)) p.lambda = lam[p.window == SE_WIN_PKB][p.D];
+    if (!(p.s0 > 0)) p.s0 = s0[p.D];
+    if (p.lambda < 1.0 || p.s0 < 1.0) return SE_ERR_PARAM;
+  }
+  if (p.D == 1 || p.D == 2) {
+    if (!(p.s > 0) || p.n_l < 0) {
+      if (!(p.tol > 0) || !(p.Q > 0)) return SE_ERR_PARAM;
+      se_params d;
+      se_status s = se_params_default(p.D, p.L, p.xi, p.M, p.P, p.window, p.Q, p.tol, p.prec, &d);
+      if (s != SE_OK) return s;
+      if (!(p.s > 0)) p.s = d.s;
+      if (p.n_l < 0) p.n_l = d.n_l;
+    }
+    if (p.s < 1.0) return SE_ERR_PARAM;
+    p.n_l = std::min(p.n_l, p.M / 2);
+  }
+
+  se_plan* pl = new (std::nothrow) se_plan();
+  if (!pl) return SE_ERR_NOMEM;
+  pl->p = p;
+  pl->f64 = (p.prec == SE_F64);
+  pl->n_max = n_max;
+  (void)hipGetDevice(&pl->device);
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, pl->device) == hipSuccess && lds > 0)
+    pl->lds_max = std::max<size_t>(pl->lds_limit, (size_t)lds);
+
+  // ---- derived sizes, Algorithm 4 step 0 and Section 6 ----
+  se_plan_info& I = pl->info;
+  I.D = p.D;
+  I.M = p.M;
+  I.P = p.P;
+  I.nu = p.nu;
+  I.h = p.L / p.M;
+  I.shape = p.shape;
+  I.lambda = p.lambda;
+  I.s0 = p.s0;
+  I.s = p.s;
+  I.n_l = (p.D == 1 || p.D == 2) ? p.n_l : 0;
+  I.Mt = p.D == 3 ? p.M : smooth_even_up(2L * (long)std::ceil((p.M + p.lambda * p.P) / 2.0 - 1e-12));
+  I.R = std::sqrt((double)(3 - p.D)) * I.h * I.Mt;
+  I.n0 = p.D < 3 ? smooth_even_up((long)std::ceil(p.s0 * I.Mt - 1e-9)) : 0;
+  I.nI = (p.D == 1 || p.D == 2) ? smooth_even_up((long)std::ceil(p.s * I.Mt - 1e-9)) : 0;
+  for (int d = 0; d < 3; ++d) {
+    I.grid[d] = d < p.D ? p.M : I.Mt;
+    I.nfft[d] = d < p.D ? p.M : (p.D == 0 ? 2 * I.Mt : I.Mt);
+  }
+  if (I.Mt >= 1024) {
+    delete pl;
+    return SE_ERR_PARAM;
+  }
+
+  // ---- geometry and tiles ----
+  se::GridGeom& g = pl->geom;
+  g.D = p.D;
+  for (int d = 0; d < 3; ++d) {
+    g.G[d] = I.grid[d];
+    g.per[d] = d < p.D;
+    g.d0[d] = d < p.D ? 0 : (I.Mt - p.M) / 2;
+  }
+  g.P = p.P;
+  g.nu = p.nu;
+  g.window = p.window == SE_WIN_PKB ? 1 : 0;
+  g.h = I.h;
+  g.L = p.L;
+  g.xi = p.xi;
+  g.alpha = p.shape;
+  g.scale = 4.0 * kPi * I.h * I.h * I.h;
+  {
+    // Largest tile (and particle chunk) whose spread and gather LDS fit, with
+    // at least 512 tiles when the grid allows it.
+    int best_t = 0, best_c = 0;
+    const int tiles[] = {16, 12, 8, 6, 4};
+    const int chunks[] = {64, 32, 16};
+    for (size_t budget : {pl->lds_limit, pl->lds_max}) {
+      for (int tt : tiles) {
+        if (p.tile > 0 && tt != p.tile) continue;
+        int cfit = 0;
+        for (int cc : chunks) {
+          g.tile = tt;
+          g.chunk = cc;
+          if (se::spread_lds_bytes(g, pl->f64) <= budget && se::gather_lds_bytes(g, pl->f64) <= budget) {
+            cfit = cc;
+            break;
+          }
+        }
+        if (!cfit) continue;
+        long nt = 1;
+        for (int d = 0; d < 3; ++d) nt *= (g.G[d] + tt - 1) / tt;
+        best_t = tt;
+        best_c = cfit;
+        if (p.tile > 0 || nt >= 512) break;
+      }
+      if (best_t) break;
+    }
+    if (!best_t) {
+      delete pl;
+      return SE_ERR_UNSUPPORTED;
+    }
+    g.tile = best_t;
+    g.chunk = best_c;
+  }
+  I.tile = g.tile;
+  for (int d = 0; d < 3; ++d) g.nt[d] = (g.G[d] + g.tile - 1) / g.tile;
+  pl->ntiles = g.nt[0] * g.nt[1] * g.nt[2];
+
+  hipStream_t st = (hipStream_t)hip_stream;
+  se_status rc = SE_OK;
+  do {
+    // ---- window table: coefficients and derivative coefficients ----
+    const int m = p.nu + 1;
+    std::vector<double> wt(2 * (size_t)p.P * m, 0.0);
+    if (p.window == SE_WIN_PKB) {
+      std::vector<double> c;
+      if (!pkb_coefficients(p.P, p.shape, p.nu, c)) {
+        rc = SE_ERR_PARAM;
+        break;
+      }
+      for (int i = 0; i < p.P; ++i)
+        for (int j = 0; j < m; ++j) {
+          wt[(size_t)i * m + j] = c[(size_t)i * m + j];
+          // d/dx of sum c_j xbar^j with xbar = 1 - 2 frac(x/h): chain factor -2/h
+          if (j + 1 < m) wt[(size_t)p.P * m + (size_t)i * m + j] = (j + 1) * c[(size_t)i * m + j + 1] * (-2.0 / I.h);
+        }
+    }
+    pl->buf.wtab = pl->upload(wt);
+    if (!pl->buf.wtab) {
+      rc = SE_ERR_NOMEM;
+      break;
+    }
+
+    // ---- particle and tile buffers ----
+    se::EvalBuffers& b = pl->buf;
+    const size_t esz = pl->f64 ? 8 : 4;
+    const long nm = std::max(1L, n_max);
+    const int nblk = (int)((nm + se::kBlock - 1) / se::kBlock);
+    b.tile_count = (int*)pl->dalloc(sizeof(int) * pl->ntiles);
+    b.tile_start = (int*)pl->dalloc(sizeof(int) * (pl->ntiles + 1));
+    b.tile_cursor = (int*)pl->dalloc(sizeof(int) * pl->ntiles);
+    b.p_tile = (int*)pl->dalloc(sizeof(int) * nm);
+    b.p_cell = (int*)pl->dalloc(sizeof(int) * nm);
+    b.p_frac = pl->dalloc(4 * esz * nm);
+    b.s_cell = (int*)pl->dalloc(sizeof(int) * nm);
+    b.s_idx = (int*)pl->dalloc(sizeof(int) * nm);
+    b.s_fq = pl->dalloc(4 * esz * nm);
+    b.qpart = (double*)pl->dalloc(sizeof(double) * 3 * nblk);
+    b.epart = (double*)pl->dalloc(sizeof(double) * pl->ntiles);
+    b.red = (double*)pl->dalloc(sizeof(double) * 4);
+    b.status = (int*)pl->dalloc(sizeof(int));
+    b.grid = pl->dalloc(esz * (size_t)g.G[0] * g.G[1] * g.G[2]);
+    if (!b.tile_count || !b.tile_start || !b.tile_cursor || !b.p_tile || !b.p_cell || !b.p_frac ||
+        !b.s_cell || !b.s_idx || !b.s_fq || !b.qpart || !b.epart || !b.red || !b.status || !b.grid) {
+      rc = SE_ERR_NOMEM;
+      break;
+    }
+    if (hipMemset(b.status, 0, sizeof(int)) != hipSuccess) {
+      rc = SE_ERR_DEVICE;
+      break;
+    }
+    rc = build_passes(pl);
+    if (rc != SE_OK) break;
+    (void)st;
+  } while (false);
+  if (rc == SE_OK && hipDeviceSynchronize() != hipSuccess) rc = SE_ERR_DEVICE;
+  if (rc != SE_OK) {
+    delete pl;
+    return rc;
+  }
+  I.device_bytes = pl->bytes;
+  *out = pl;
+  return SE_OK;
+}
+
+// Record the transform passes of Algorithm 4 steps 2-4 for this plan.
+static se_status build_passes(se_plan* pl) {
+  const se_params& p = pl->p;
+  const se_plan_info& I = pl->info;
+  const int D = p.D, M = p.M, Mt = I.Mt;
+  const int Gx = I.grid[0], Gy = I.grid[1], Gz = I.grid[2];
+  const size_t ce = pl->f64 ? 16 : 8;
+  std::vector<std::vector<int>> rg;
+  auto fail = [&]() { return SE_ERR_NOMEM; };
+
+  if (D == 3 || D == 2) {
+    const int nx = M, Kx = M / 2 + 1;
+    void* cb = pl->dalloc(ce * (size_t)Kx * Gy * Gz);
+    if (!cb) return fail();
+    const void* twM = pl->twiddles(M);
+    const void* sepM = pl->sep_table(M);
+    const void* k2M = pl->k2_table(M);
+    if (!twM || !sepM || !k2M) return fail();
+    // x: real-to-complex
+    se::FftPass p1{};
+    p1.cls[0] = make_class(nx, Gx, Kx, twM, pl->buf.grid, cb, 1, Gx, (long long)Gx * Gy, 1, Kx, (long long)Kx * Gy);
+    rg = {{0, 0, Gy, 0, Gz}};
+    if (!finish_pass(pl, p1, se::K_R2C, 1, rg)) return fail();
+    // y: complex forward
+    se::FftPass p2{};
+    p2.cls[0] = make_class(M, M, M, twM, cb, cb, Kx, 1, (long long)Kx * Gy, Kx, 1, (long long)Kx * Gy);
+    rg = {{0, 0, Kx, 0, Gz}};
+    if (!finish_pass(pl, p2, se::K_C2C_FWD, 1, rg)) return fail();
+    // z: fused forward / scale / inverse
+    se::FftPass p3{};
+    const long long zst = (long long)Kx * Gy;
+    if (D == 3) {
+      se::FftClass c = make_class(M, M, M, twM, cb, cb, zst, 1, Kx, zst, 1, Kx);
+      c.gmode = se::G_INVSQ;
+      c.sA = c.sB = c.sC = sepM;
+      c.kA = c.kB = c.kC = k2M;
+      p3.cls[0] = c;
+      rg = {{0, 0, Kx, 0, Gy}};
+      if (!finish_pass(pl, p3, se::K_FUSED, 1, rg)) return fail();
+    } else {
+      // 2P: AFT classes, Algorithm 1 steps 2-4 / Algorithm 2 steps 1-3
+      const int n0 = I.n0, nI = I.nI, nl = I.n_l;
+      const void* tw0 = pl->twiddles(n0);
+      const void* twI = pl->twiddles(nI);
+      const void* twJ = pl->twiddles(Mt);
+      const void* s0t = pl->sep_table(n0);
+      const void* sIt = pl->sep_table(nI);
+      const void* sJt = pl->sep_table(Mt);
+      const void* kIt = pl->k2_table(nI);
+      const void* kJt = pl->k2_table(Mt);
+      std::vector<double> g0(n0);
+      for (int t = 0; t < n0; ++t) g0[t] = g2p_zero(2.0 * kPi * signed_freq(t, n0) / (n0 * I.h), I.R);
+      const void* g0t = pl->upload(g0);
+      if (!tw0 || !twI || !twJ || !s0t || !sIt || !sJt || !kIt || !kJt || !g0t) return fail();
+      se::FftClass c0 = make_class(n0, Mt, Mt, tw0, cb, cb, zst, 1, Kx, zst, 1, Kx);
+      c0.gmode = se::G_TAB1;
+      c0.sA = c0.sB = sepM;
+      c0.sC = s0t;
+      c0.gtab = g0t;
+      se::FftClass cI = make_class(nI, Mt, Mt, twI, cb, cb, zst, 1, Kx, zst, 1, Kx);
+      cI.gmode = se::G_INVSQ;
+      cI.sA = cI.sB = sepM;
+      cI.kA = cI.kB = k2M;
+      cI.sC = sIt;
+      cI.kC = kIt;
+      se::FftClass cJ = make_class(Mt, Mt, Mt, twJ, cb, cb, zst, 1, Kx, zst, 1, Kx);
+      cJ.gmode = se::G_INVSQ;
+      cJ.sA = cJ.sB = sepM;
+      cJ.kA = cJ.kB = k2M;
+      cJ.sC = sJt;
+      cJ.kC = kJt;
+      p3.cls[0] = c0;
+      p3.cls[1] = cI;
+      p3.cls[2] = cJ;
+      rg.clear();
+      for (int ky = 0; ky < M; ++ky) {
+        const int sky = std::abs(signed_freq(ky, M) == M / 2 ? -M / 2 : signed_freq(ky, M));
+        if (sky <= nl) {
+          if (ky == 0) {
+            rg.push_back({0, 0, 1, ky, ky + 1});
+            if (nl >= 1) rg.push_back({1, 1, std::min(nl, Kx - 1) + 1, ky, ky + 1});
+          } else {
+            rg.push_back({1, 0, std::min(nl, Kx - 1) + 1, ky, ky + 1});
+          }
+          if (nl + 1 < Kx) rg.push_back({2, nl + 1, Kx, ky, ky + 1});
+        } else {
+          rg.push_back({2, 0, Kx, ky, ky + 1});
+        }
+      }
+      if (!finish_pass(pl, p3, se::K_FUSED, 3, rg)) return fail();
+    }
+    se::FftPass p4 = p2;
+    p4.kind = se::K_C2C_INV;
+    se::FftPass p5{};
+    p5.cls[0] = make_class(nx, Kx, Gx, twM, cb, pl->buf.grid, 1, Kx, (long long)Kx * Gy, 1, Gx, (long long)Gx * Gy);
+    rg = {{0, 0, Gy, 0, Gz}};
+    if (!finish_pass(pl, p5, se::K_C2R, 1, rg)) return fail();
+    pl->passes = {p1, p2, p3, p4, p5};
+    return SE_OK;
+  }
+
+  if (D == 0) {
+    const int n = 2 * Mt, Kx = Mt + 1;
+    void* cb = pl->dalloc(ce * (size_t)Kx * Mt * Mt);
+    void* cb2 = pl->dalloc(ce * (size_t)Kx * n * Mt);
+    if (!cb || !cb2) return fail();
+    const void* tw = pl->twiddles(n);
+    const void* sep = pl->sep_table(n);
+    if (!tw || !sep) return fail();
+    const void* table = nullptr;
+    se_status rc = precompute_0p(pl, nullptr, &table);
+    if (rc != SE_OK) return rc;
+    se::FftPass p1{};
+    p1.cls[0] = make_class(n, Mt, Kx, tw, pl->buf.grid, cb, 1, Mt, (long long)Mt * Mt, 1, Kx, (long long)Kx * Mt);
+    rg = {{0, 0, Mt, 0, Mt}};
+    if (!finish_pass(pl, p1, se::K_R2C, 1, rg)) return fail();
+    se::FftPass p2{};
+    p2.cls[0] = make_class(n, Mt, n, tw, cb, cb2, Kx, 1, (long long)Kx * Mt, Kx, 1, (long long)Kx * n);
+    rg = {{0, 0, Kx, 0, Mt}};
+    if (!finish_pass(pl, p2, se::K_C2C_FWD, 1, rg)) return fail();
+    se::FftPass p3{};
+    const long long zst = (long long)Kx * n;
+    se::FftClass c = make_class(n, Mt, Mt, tw, cb2, cb2, zst, 1, Kx, zst, 1, Kx);
+    c.gmode = se::G_TAB3;
+    c.sA = c.sB = c.sC = sep;
+    c.gtab = table;
+    c.gd1 = c.gd2 = Mt + 1;
+    c.fold0 = 0;
+    c.fold1 = c.fold2 = n;
+    p3.cls[0] = c;
+    rg = {{0, 0, Kx, 0, n}};
+    if (!finish_pass(pl, p3, se::K_FUSED, 1, rg)) return fail();
+    se::FftPass p4{};
+    p4.cls[0] = make_class(n, n, Mt, tw, cb2, cb, Kx, 1, (long long)Kx * n, Kx, 1, (long long)Kx * Mt);
+    rg = {{0, 0, Kx, 0, Mt}};
+    if (!finish_pass(pl, p4, se::K_C2C_INV, 1, rg)) return fail();
+    se::FftPass p5{};
+    p5.cls[0] = make_class(n, Kx, Mt, tw, cb, pl->buf.grid, 1, Kx, (long long)Kx * Mt, 1, Mt, (long long)Mt * Mt);
+    rg = {{0, 0, Mt, 0, Mt}};
+    if (!finish_pass(pl, p5, se::K_C2R, 1, rg)) return fail();
+    pl->passes = {p1, p2, p3, p4, p5};
+    return SE_OK;
+  }
+
+  // D == 1: periodic x, free y and z.  Classes over k_x: zero mode (n0),
+  // set I = 1..n_l (nI), set J = n_l+1..M/2 (Mt).
+  const int Kx = M / 2 + 1, n0 = I.n0, nI = I.nI;
+  const int nl = std::min(I.n_l, Kx - 1);
+  const int nJ = Kx - 1 - nl;
+  void* cb = pl->dalloc(ce * (size_t)Kx * Mt * Mt);
+  void* b0 = pl->dalloc(ce * (size_t)n0 * Mt);
+  void* bI = pl->dalloc(ce * (size_t)std::max(1, nl) * nI * Mt);
+  if (!cb || !b0 || !bI) return fail();
+  const void* twM = pl->twiddles(M);
+  const void* tw0 = pl->twiddles(n0);
+  const void* twI = pl->twiddles(nI);
+  const void* twJ = pl->twiddles(Mt);
+  const void* sepM = pl->sep_table(M);
+  const void* k2M = pl->k2_table(M);
+  const void* s0t = pl->sep_table(n0);
+  const void* sIt = pl->sep_table(nI);
+  const void* sJt = pl->sep_table(Mt);
+  const void* kIt = pl->k2_table(nI);
+  const void* kJt = pl->k2_table(Mt);
+  const int h0 = n0 / 2 + 1;
+  std::vector<double> g1((size_t)h0 * h0);
+  for (int i = 0; i < h0; ++i)
+    for (int j = 0; j < h0; ++j) {
+      const double ki = 2.0 * kPi * i / (n0 * I.h), kj = 2.0 * kPi * j / (n0 * I.h);
+      g1[(size_t)i * h0 + j] = g1p_zero(std::sqrt(ki * ki + kj * kj), I.R);
+    }
+  const void* g1t = pl->upload(g1);
+  if (!twM || !tw0 || !twI || !twJ || !sepM || !k2M || !s0t || !sIt || !sJt || !kIt || !kJt || !g1t)
+    return fail();
+  char* cbc = (char*)cb;
+  const long long mst = (long long)Kx * Mt;  // z stride of the main buffer
+  // x: real-to-complex
+  se::FftPass p1{};
+  p1.cls[0] = make_class(M, Gx, Kx, twM, pl->buf.grid, cb, 1, Gx, (long long)Gx * Gy, 1, Kx, mst);
+  rg = {{0, 0, Gy, 0, Gz}};
+  if (!finish_pass(pl, p1, se::K_R2C, 1, rg)) return fail();
+  // y: padded forward transforms per class (Algorithm 1 steps 2-4, first free direction)
+  se::FftPass p2{};
+  p2.cls[0] = make_class(n0, Mt, n0, tw0, cb, b0, Kx, 0, mst, 1, 0, n0);
+  p2.cls[1] = make_class(nI, Mt, nI, twI, cbc + ce * 1, bI, Kx, 1, mst, nl, 1, (long long)nI * nl);
+  p2.cls[2] = make_class(Mt, Mt, Mt, twJ, cbc + ce * (nl + 1), cbc + ce * (nl + 1), Kx, 1, mst, Kx, 1, mst);
+  rg = {{0, 0, 1, 0, Mt}};
+  if (nl > 0) rg.push_back({1, 0, nl, 0, Mt});
+  if (nJ > 0) rg.push_back({2, 0, nJ, 0, Mt});
+  if (!finish_pass(pl, p2, se::K_C2C_FWD, 3, rg)) return fail();
+  // z: fused forward / scale / inverse per class
+  se::FftPass p3{};
+  {
+    se::FftClass c0 = make_class(n0, Mt, Mt, tw0, b0, b0, n0, 1, 0, n0, 1, 0);
+    c0.gmode = se::G_TAB2;
+    c0.sA = s0t;
+    c0.sB = sepM;
+    c0.sC = s0t;
+    c0.gtab = g1t;
+    c0.gd2 = h0;
+    c0.fold0 = n0;
+    c0.fold2 = n0;
+    se::FftClass cI = make_class(nI, Mt, Mt, twI, bI, bI, (long long)nI * nl, 1, nl, (long long)nI * nl, 1, nl);
+    cI.gmode = se::G_INVSQ;
+    cI.sA = sepM;
+    cI.kA = k2M;
+    cI.offA = 1;
+    cI.sB = sIt;
+    cI.kB = kIt;
+    cI.sC = sIt;
+    cI.kC = kIt;
+    se::FftClass cJ = make_class(Mt, Mt, Mt, twJ, cbc + ce * (nl + 1), cbc + ce * (nl + 1), mst, 1, Kx, mst, 1, Kx);
+    cJ.gmode = se::G_INVSQ;
+    cJ.sA = sepM;
+    cJ.kA = k2M;
+    cJ.offA = nl + 1;
+    cJ.sB = sJt;
+    cJ.kB = kJt;
+    cJ.sC = sJt;
+    cJ.kC = kJt;
+    p3.cls[0] = c0;
+    p3.cls[1] = cI;
+    p3.cls[2] = cJ;
+  }
+  rg = {{0, 0, n0, 0, 1}};
+  if (nl > 0) rg.push_back({1, 0, nl, 0, nI});
+  if (nJ > 0) rg.push_back({2, 0, nJ, 0, Mt});
+  if (!finish_pass(pl, p3, se::K_FUSED, 3, rg)) return fail();
+  // y: inverse transforms with truncation back to Mt (Algorithm 2 steps 1-4)
+  se::FftPass p4{};
+  p4.cls[0] = make_class(n0, n0, Mt, tw0, b0, cb, 1, 0, n0, Kx, 0, mst);
+  p4.cls[1] = make_class(nI, nI, Mt, twI, bI, cbc + ce * 1, nl, 1, (long long)nI * nl, Kx, 1, mst);
+  p4.cls[2] = p2.cls[2];
+  rg = {{0, 0, 1, 0, Mt}};
+  if (nl > 0) rg.push_back({1, 0, nl, 0, Mt});
+  if (nJ > 0) rg.push_back({2, 0, nJ, 0, Mt});
+  if (!finish_pass(pl, p4, se::K_C2C_INV, 3, rg)) return fail();
+  // x: complex-to-real
+  se::FftPass p5{};
+  p5.cls[0] = make_class(M, Kx, Gx, twM, cb, pl->buf.grid, 1, Kx, mst, 1, Gx, (long long)Gx * Gy);
+  rg = {{0, 0, Gy, 0, Gz}};
+  if (!finish_pass(pl, p5, se::K_C2R, 1, rg)) return fail();
+  pl->passes = {p1, p2, p3, p4, p5};
+  return SE_OK;
+}
+
+// Algorithm 3 in FP64 on the GPU: sample G_hat^{0P} on the (s0 Mt)^3 grid,
+// inverse transform, keep the offsets -Mt..Mt-1, forward transform, keep the
+// real, even result as an octant table (Mt+1)^3 in the compute precision.
+static se_status precompute_0p(se_plan* pl, hipStream_t st, const void** table) {
+  const int Mt = pl->info.Mt, n0 = pl->info.n0, n = 2 * Mt;
+  const double h = pl->info.h, R = pl->info.R;
+  double* big = nullptr;
+  double* small = nullptr;
+  const size_t nb = (size_t)n0 * n0 * n0 * 16, ns = (size_t)n * n * n * 16;
+  if (hipMalloc(&big, nb) != hipSuccess) return SE_ERR_NOMEM;
+  if (hipMalloc(&small, ns) != hipSuccess) {
+    (void)hipFree(big);
+    return SE_ERR_NOMEM;
+  }
+  se_status rc = SE_OK;
+  const bool f64_saved = pl->f64;
+  do {
+    pl->f64 = true;  // twiddles of the precompute are FP64
+    const void* twb = pl->twiddles(n0);
+    const void* tws = pl->twiddles(n);
+    pl->f64 = f64_saved;
+    if (!twb || !tws) {
+      rc = SE_ERR_NOMEM;
+      break;
+    }
+    if (se::launch_g0p_fill(big, n0, h, R, st) != hipSuccess) {
+      rc = SE_ERR_DEVICE;
+      break;
+    }
+    // 3D complex transforms of an n^3 array: x (contiguous), y, z
+    auto run3 = [&](double* a, int len, const void* tw, int kind) -> bool {
+      const long long L1 = len, L2 = (long long)len * len;
+      const long long st_[3] = {1, L1, L2}, s0_[3] = {L1, 1, 1}, s1_[3] = {L2, L2, L1};
+      for (int ax = 0; ax < 3; ++ax) {
+        se::FftPass ps{};
+        ps.cls[0] = make_class(len, len, len, tw, a, a, st_[ax], s0_[ax], s1_[ax], st_[ax], s0_[ax], s1_[ax]);
+        const bool saved = pl->f64;
+        pl->f64 = true;
+        const bool ok = finish_pass(pl, ps, kind, 1, {{0, 0, len, 0, len}});
+        pl->f64 = saved;
+        if (!ok) return false;
+        if (se::launch_fft(ps, true, st) != hipSuccess) return false;
+      }
+      return true;
+    };
+    if (!run3(big, n0, twb, se::K_C2C_INV)) {
+      rc = SE_ERR_DEVICE;
+      break;
+    }
+    if (se::launch_g0p_truncate(big, n0, small, Mt, st) != hipSuccess) {
+      rc = SE_ERR_DEVICE;
+      break;
+    }
+    if (!run3(small, n, tws, se::K_C2C_FWD)) {
+      rc = SE_ERR_DEVICE;
+      break;
+    }
+    const size_t esz = pl->f64 ? 8 : 4;
+    void* tab = pl->dalloc(esz * (size_t)(Mt + 1) * (Mt + 1) * (Mt + 1));
+    if (!tab) {
+      rc = SE_ERR_NOMEM;
+      break;
+    }
+    if (se::launch_g0p_fold(small, Mt, tab, pl->f64, st) != hipSuccess) {
+      rc = SE_ERR_DEVICE;
+      break;
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) {
+      rc = SE_ERR_DEVICE;
+      break;
+    }
+    *table = tab;
+  } while (false);
+  pl->f64 = f64_saved;
+  (void)hipFree(big);
+  (void)hipFree(small);
+  return rc;
+}
+
+namespace {
+const char* kFftNames[] = {"fft_c2c_fwd", "fft_c2c_inv", "fft_r2c", "fft_c2r", "fft_fused_scale"};
+constexpr int kEventPool = 8192;
+}  // namespace
+
+se_status se_eval(se_plan* plan, long N, const void* xyz, const void* q, void* phi, void* force,
+                  double* energy, unsigned flags, void* hip_stream) {
+  if (!plan || N < 0 || N > plan->n_max) return SE_ERR_ARG;
+  if (N > 0 && (!xyz || !q)) return SE_ERR_ARG;
+  if (flags & ~(SE_IN_F32 | SE_ADD_SELF | SE_SYNC_CHECK | SE_OUT_GRAD | SE_ALLOW_NONNEUTRAL | SE_PROFILE))
+    return SE_ERR_ARG;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const se::GridGeom& g = plan->geom;
+  se::EvalBuffers& b = plan->buf;
+  const bool f64 = plan->f64;
+  const int nblk = (int)((N + se::kBlock - 1) / se::kBlock);
+  const double self_coef = (flags & SE_ADD_SELF) ? -2.0 * plan->p.xi / std::sqrt(kPi) : 0.0;
+
+  // tracing: an event pair around each launch site
+  const bool prof = (flags & SE_PROFILE) != 0;
+  if (prof && plan->evpool.empty()) {
+    plan->evpool.resize(kEventPool);
+    for (auto& e : plan->evpool)
+      if (hipEventCreate(&e) != hipSuccess) return SE_ERR_DEVICE;
+  }
+  int cur = -1;
+  auto begin = [&]() {
+    cur = -1;
+    if (prof && plan->ev_used + 2 <= (int)plan->evpool.size()) {
+      cur = plan->ev_used;
+      plan->ev_used += 2;
+      (void)hipEventRecord(plan->evpool[cur], st);
+    }
+  };
+  auto end = [&](int site, double bytes, double flops) {
+    if (cur >= 0) {
+      (void)hipEventRecord(plan->evpool[cur + 1], st);
+      plan->prof.push_back({site, cur, bytes, flops});
+    }
+  };
+  const double re = f64 ? 8.0 : 4.0;
+  const double in_e = (flags & SE_IN_F32) ? 4.0 : 8.0;
+  const double G = (double)g.G[0] * g.G[1] * g.G[2];
+  const int P = g.P, nu = std::max(g.nu, 5);
+
+  begin();
+  if (hipMemsetAsync(b.tile_count, 0, sizeof(int) * plan->ntiles, st) != hipSuccess) return SE_ERR_DEVICE;
+  if (se::launch_bin(g, b, N, xyz, q, (flags & SE_IN_F32) != 0, f64, nblk, st) != hipSuccess) return SE_ERR_DEVICE;
+  end(0, N * 4.0 * in_e, 0.0);
+  begin();
+  if (se::launch_scan(g, b, nblk, plan->p.D >= 1 && !(flags & SE_ALLOW_NONNEUTRAL), st) != hipSuccess)
+    return SE_ERR_DEVICE;
+  end(1, plan->ntiles * 8.0, 0.0);
+  begin();
+  if (se::launch_scatter(g, b, N, f64, st) != hipSuccess) return SE_ERR_DEVICE;
+  end(2, N * 2.0 * (8.0 + 4.0 * re), 0.0);
+  begin();
+  if (se::launch_spread(g, b, f64, st) != hipSuccess) return SE_ERR_DEVICE;
+  end(3, N * 4.0 * re + G * re, N * 2.0 * (3.0 * P * nu + P * P + (double)P * P * P));
+  for (size_t i = 0; i < plan->passes.size(); ++i) {
+    const se::FftPass& ps = plan->passes[i];
+    begin();
+    if (se::launch_fft(ps, f64, st) != hipSuccess) return SE_ERR_DEVICE;
+    end(4 + (int)i, ps.alg_bytes, ps.alg_flops);
+  }
+  const int s_gather = 4 + (int)plan->passes.size();
+  if (phi || force || energy) {
+    begin();
+    if (se::launch_gather(g, b, f64, phi, force, (flags & SE_OUT_GRAD) ? 1 : 0, self_coef, st) != hipSuccess)
+      return SE_ERR_DEVICE;
+    end(s_gather, N * 8.0 * re + G * re,
+        N * 2.0 * (6.0 * P * nu + 3.0 * P * P + (double)P * P * (2 * P + 4)));
+  }
+  if (energy) {
+    begin();
+    if (se::launch_energy(g, b, energy, 0.0, st) != hipSuccess) return SE_ERR_DEVICE;
+    end(s_gather + 1, plan->ntiles * 8.0 + 8.0, 0.0);
+  }
+  if (flags & SE_SYNC_CHECK) return se_get_device_status(plan, hip_stream);
+  return SE_OK;
+}
+
+se_status se_plan_profile(se_plan* plan, void* hip_stream, se_stage_record* out, int cap, int* n,
+                          int reset) {
+  if (!plan || !n || (cap > 0 && !out)) return SE_ERR_ARG;
+  if (hipStreamSynchronize((hipStream_t)hip_stream) != hipSuccess) return SE_ERR_DEVICE;
+  const int nsites = 6 + (int)plan->passes.size();
+  std::vector<se_stage_record> agg(nsites);
+  std::vector<double> bsum(nsites, 0.0), fsum(nsites, 0.0);
+  for (int s = 0; s < nsites; ++s) {
+    se_stage_record& r = agg[s];
+    std::memset(&r, 0, sizeof(r));
+    const char* nm;
+    char buf[32];
+    if (s == 0) nm = "bin";
+    else if (s == 1) nm = "scan";
+    else if (s == 2) nm = "scatter";
+    else if (s == 3) nm = "spread";
+    else if (s < 4 + (int)plan->passes.size()) {
+      std::snprintf(buf, sizeof(buf), "%s_%d", kFftNames[plan->passes[s - 4].kind], s - 3);
+      nm = buf;
+    } else if (s == 4 + (int)plan->passes.size()) nm = "gather";
+    else nm = "energy";
+    std::snprintf(r.name, sizeof(r.name), "%s", nm);
+  }
+  for (const auto& rec : plan->prof) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, plan->evpool[rec.ev], plan->evpool[rec.ev + 1]) != hipSuccess)
+      return SE_ERR_DEVICE;
+    se_stage_record& r = agg[rec.site];
+    r.launches += 1;
+    r.ms_total += ms;
+    bsum[rec.site] += rec.bytes;
+    fsum[rec.site] += rec.flops;
+  }
+  int k = 0;
+  for (int s = 0; s < nsites; ++s) {
+    if (agg[s].launches == 0) continue;
+    agg[s].bytes = bsum[s] / agg[s].launches;
+    agg[s].flops = fsum[s] / agg[s].launches;
+    if (k < cap) out[k] = agg[s];
+    ++k;
+  }
+  *n = std::min(k, cap);
+  if (reset) {
+    plan->prof.clear();
+    plan->ev_used = 0;
+  }
+  return SE_OK;
+}
+
+se_status se_get_device_status(se_plan* plan, void* hip_stream) {
+  if (!plan) return SE_ERR_ARG;
+  hipStream_t st = (hipStream_t)hip_stream;
+  int s = 0;
+  if (hipStreamSynchronize(st) != hipSuccess) return SE_ERR_DEVICE;
+  if (hipMemcpy(&s, plan->buf.status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return SE_ERR_DEVICE;
+  if (s && hipMemset(plan->buf.status, 0, sizeof(int)) != hipSuccess) return SE_ERR_DEVICE;
+  if (s & 1) return SE_ERR_NONFINITE;
+  if (s & 2) return SE_ERR_OUT_OF_BOX;
+  if (s & 4) return SE_ERR_NONNEUTRAL;
+  return SE_OK;
+}
+
+}  // extern "C"

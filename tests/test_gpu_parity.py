@@ -1,0 +1,194 @@
+"""GPU parity: the HIP path against the oracles, element by element.
+
+  * FP64 GPU vs the discrete SE oracle (same parameters): relative 1e-12 in phi,
+    1e-11 in grad phi, energy 1e-12 -- the two compute the same discrete
+    quantity, so only rounding differs.
+  * FP64 GPU vs the direct Ewald oracle at high-accuracy parameters (PKB
+    P = 16, nu = 9): relative rms 1e-10 (the stated bar for the FP64 path).
+  * FP32 GPU: error against FP64 reported and bounded.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import direct
+from oracle import se_discrete as se
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1712_04732_amd import SEEnergy, SEPotential, SpectralEwald, _lib  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def gpu_eval(plan, x, q, dtype=torch.float64, **kw):
+    xt = torch.tensor(x, dtype=dtype, device=DEV)
+    qt = torch.tensor(q, dtype=dtype, device=DEV)
+    phi, g, E = plan(xt, qt, out_grad=True, **kw)
+    torch.cuda.synchronize()
+    return phi.double().cpu().numpy(), g.double().cpu().numpy(), float(E)
+
+
+def make_pair(D, M, P, xi=8.0, L=1.0, window="pkb", prec="f64", n_max=4096, s=2.0, n_l=3, tile=0,
+              nu=None):
+    """A GPU plan and oracle parameters with identical inputs."""
+    kw = {}
+    if D in (1, 2):
+        kw = dict(s=s, n_l=n_l)
+    plan = SpectralEwald(D, L, xi, M, P, window=window, prec=prec, n_max=n_max, tile=tile, nu=nu,
+                         **kw)
+    p = se.Params(D=D, L=L, xi=xi, M=M, P=P, window=window, nu=nu,
+                  **({"s": s, "n_l": n_l} if D in (1, 2) else {}))
+    info = plan.info
+    assert info.Mt == p.Mt
+    if D < 3:
+        assert info.n0 == p.n0
+    if D in (1, 2):
+        assert info.nI == p.nI and info.n_l == p.n_l
+    return plan, p
+
+
+CASES = [
+    # D, M, P, N, window, tile
+    (3, 32, 8, 1000, "pkb", 0),
+    (3, 24, 6, 257, "gaussian", 4),
+    (3, 20, 8, 1, "pkb", 0),
+    (2, 24, 8, 500, "pkb", 0),
+    (2, 20, 6, 333, "gaussian", 6),
+    (1, 24, 8, 500, "pkb", 0),
+    (1, 16, 6, 129, "gaussian", 4),
+    (0, 24, 8, 400, "pkb", 0),
+    (0, 16, 4, 77, "gaussian", 8),
+]
+
+
+@pytest.mark.parametrize("D,M,P,N,window,tile", CASES)
+def test_fp64_matches_discrete_oracle(D, M, P, N, window, tile):
+    print(f"case D={D} M={M} P={P} N={N} {window} tile={tile}", flush=True)
+    x, q = wl.system(N, 1.0, 1000 + 10 * D + P, "uniform" if N > 1 else "raw_uniform")
+    if N == 1:
+        q = np.zeros(1)  # a lone neutral 'system'
+    plan, p = make_pair(D, M, P, window=window, tile=tile)
+    phi, g, E = gpu_eval(plan, x, q)
+    if N == 1:
+        assert np.all(phi == 0) and np.all(g == 0) and E == 0.0
+        return
+    ref, gref = se.spectral_ewald(x, q, p)
+    assert rel(phi, ref) < 1e-12
+    assert rel(g, gref) < 1e-11
+    Eref = se.energy(q, ref)
+    assert abs(E - Eref) <= 1e-12 * abs(Eref)
+
+
+@pytest.mark.parametrize("D", [3, 2, 1, 0])
+def test_fp64_matches_direct_oracle(D):
+    """High-accuracy parameters: PKB P=16, nu=9 (window error ~1e-15), M=40,
+    xi=8 (truncation ~1e-19), AFT s, n_l from a 1e-16 relative tolerance."""
+    print(f"case direct D={D}", flush=True)
+    N = 300
+    x, q = wl.system(N, 1.0, 77 + D, "uniform")
+    Q = float((q * q).sum())
+    xi, M, P = 8.0, 40, 16
+    pp = se.with_aft_estimates(D, 1.0, xi, M, P, Q, 1e-16 * se.B_scale(Q, xi, 1.0), window="pkb")
+    plan = SpectralEwald(D, 1.0, xi, M, P, window="pkb", prec="f64", n_max=N,
+                         **({"s": pp.s, "n_l": pp.n_l} if D in (1, 2) else {}))
+    phi, g, E = gpu_eval(plan, x, q)
+    ref, gref = direct.kspace(D, 1.0, xi, x, q)
+    assert rel(phi, ref) < 1e-10
+    assert rel(g, gref) < 1e-9
+
+
+@pytest.mark.parametrize("D", [3, 2, 1, 0])
+def test_fp32_against_fp64(D):
+    print(f"case fp32 D={D}", flush=True)
+    N = 2000
+    x, q = wl.system(N, 1.0, 300 + D, "pm1")
+    plan64, p = make_pair(D, 32, 8, xi=10.0, prec="f64", n_max=N)
+    plan32, _ = make_pair(D, 32, 8, xi=10.0, prec="f32", n_max=N)
+    phi64, g64, E64 = gpu_eval(plan64, x, q)
+    phi32, g32, E32 = gpu_eval(plan32, x, q, dtype=torch.float64)
+    phi32b, _, _ = gpu_eval(plan32, x, q, dtype=torch.float32)
+    e_phi, e_g, e_E = rel(phi32, phi64), rel(g32, g64), abs(E32 - E64) / abs(E64)
+    print(f"fp32 vs fp64 D={D}: phi {e_phi:.2e} grad {e_g:.2e} energy {e_E:.2e} "
+          f"(f32 inputs: phi {rel(phi32b, phi64):.2e})")
+    assert e_phi < 2e-6 and e_g < 5e-6 and e_E < 2e-6
+
+
+@pytest.mark.parametrize("D", [3, 0])
+def test_energy_backward_is_oracle_gradient(D):
+    print(f"case adjoint D={D}", flush=True)
+    N = 400
+    x, q = wl.system(N, 1.0, 500 + D, "uniform")
+    plan, p = make_pair(D, 24, 8, n_max=N)
+    xt = torch.tensor(x, device=DEV, requires_grad=True)
+    qt = torch.tensor(q, device=DEV, requires_grad=True)
+    E = SEEnergy.apply(xt, qt, plan)
+    E.backward()
+    ref, gref = se.spectral_ewald(x, q, p)
+    assert rel(qt.grad.cpu().numpy(), ref) < 1e-12
+    assert rel(xt.grad.cpu().numpy(), q[:, None] * gref) < 1e-11
+
+
+def test_potential_vjp_against_finite_differences():
+    """SEPotential backward for a random cotangent vs central differences of
+    L = g . phi(x, q) computed on the GPU in FP64."""
+    print("case potential vjp", flush=True)
+    N = 64
+    x, q = wl.system(N, 1.0, 901, "uniform")
+    plan, _ = make_pair(3, 24, 8, n_max=N)
+    rng = np.random.default_rng(3)
+    gco = rng.standard_normal(N)
+    xt = torch.tensor(x, device=DEV, requires_grad=True)
+    qt = torch.tensor(q, device=DEV, requires_grad=True)
+    phi = SEPotential.apply(xt, qt, plan)
+    (phi * torch.tensor(gco, device=DEV)).sum().backward()
+
+    def Lval(xx, qq):
+        p_, _, _ = gpu_eval(plan, xx, qq, check=False, allow_nonneutral=True)
+        return float(np.dot(gco, p_))
+
+    eps = 1e-6
+    for m, d in ((0, 0), (5, 2), (17, 1)):
+        xp = x.copy(); xp[m, d] += eps
+        xm = x.copy(); xm[m, d] -= eps
+        fd = (Lval(xp, q) - Lval(xm, q)) / (2 * eps)
+        assert abs(fd - xt.grad[m, d].item()) < 1e-6 * max(1.0, abs(fd))
+    for m in (3, 40):
+        qp = q.copy(); qp[m] += eps
+        qm = q.copy(); qm[m] -= eps
+        fd = (Lval(x, qp) - Lval(x, qm)) / (2 * eps)
+        assert abs(fd - qt.grad[m].item()) < 1e-7 * max(1.0, abs(fd))
+
+
+def test_device_status_errors():
+    print("case status", flush=True)
+    plan, _ = make_pair(2, 16, 6, n_max=64)
+    x, q = wl.system(64, 1.0, 5, "pm1")
+    qn = q.copy(); qn[0] += 1.0
+    with pytest.raises(_lib.SEError) as e:
+        gpu_eval(plan, x, qn)
+    assert e.value.status == _lib.SE_ERR_NONNEUTRAL
+    xb = x.copy(); xb[3, 2] = 1.5            # free direction z outside [0, L)
+    with pytest.raises(_lib.SEError) as e:
+        gpu_eval(plan, xb, q)
+    assert e.value.status == _lib.SE_ERR_OUT_OF_BOX
+    xn = x.copy(); xn[7, 0] = np.nan
+    with pytest.raises(_lib.SEError) as e:
+        gpu_eval(plan, xn, q)
+    assert e.value.status == _lib.SE_ERR_NONFINITE
+    # the plan still works after errors
+    phi, _, _ = gpu_eval(plan, x, q)
+    assert np.all(np.isfinite(phi))
+    xw = x.copy(); xw[:, 0] += 3.0            # periodic coordinates wrap
+    phi2, _, _ = gpu_eval(plan, xw, q)
+    assert rel(phi2, phi) < 1e-12

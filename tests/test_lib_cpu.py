@@ -1,0 +1,74 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports
+every function include/se.h declares, applies the paper's parameter rules, and
+rejects invalid arguments before touching the device."""
+import ctypes
+import math
+
+import pytest
+
+from oracle import se_discrete as se
+from paper_1712_04732_amd import _lib as L
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    names = L.declared_functions()
+    assert set(names) >= {"se_params_default", "se_plan_create", "se_plan_get_info", "se_eval",
+                          "se_get_device_status", "se_plan_destroy", "se_status_string"}
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings():
+    for s in range(9):
+        assert L.se_status_string(s)
+    assert "neutral" in L.se_status_string(L.SE_ERR_NONNEUTRAL)
+
+
+@pytest.mark.parametrize("D,M,N,xi,kind", [(2, 96, 100000, 33.84, "pm1"), (1, 160, 1000000, 56.40, "normal"),
+                                           (2, 32, 1000, 8.0, "uniform"), (1, 40, 300, 10.0, "uniform")])
+def test_aft_estimates_match_oracle(D, M, N, xi, kind):
+    """s and n_l of Eqs. (estimate-s), (estimate-nl) from the library equal the
+    oracle's independent implementation (relative tolerance 1e-6 B)."""
+    Q = float(N) if kind != "uniform" else N / 3.0
+    B = se.B_scale(Q, xi, 1.0)
+    eps = 1e-6 * B
+    p = L.se_params_default(D, 1.0, xi, M, 8, L.SE_WIN_PKB, Q, eps, L.SE_F32)
+    o = se.with_aft_estimates(D, 1.0, xi, M, 8, Q, eps, window="pkb")
+    assert abs(p.s - o.s) < 1e-12 and p.n_l == o.n_l
+    assert p.lambda_ == o.lam and p.s0 == o.s0 and p.shape == o.shape and p.nu == o.nu
+
+
+def test_survey_aft_values():
+    """Doubly periodic, M = 96, N = 1e5 +-1 charges, xi = 33.84, 1e-6 relative:
+    s = 2.471 and n_l = 8; singly periodic M = 160, N = 1e6, xi = 56.40: s = 2.745,
+    n_l = 16."""
+    p = L.se_params_default(2, 1.0, 33.84, 96, 8, L.SE_WIN_PKB, 1e5, 1e-6 * se.B_scale(1e5, 33.84, 1.0), L.SE_F32)
+    assert abs(p.s - 2.471) < 2e-3 and p.n_l == 8
+    p = L.se_params_default(1, 1.0, 56.40, 160, 8, L.SE_WIN_PKB, 1e6, 1e-6 * se.B_scale(1e6, 56.40, 1.0), L.SE_F32)
+    assert abs(p.s - 2.745) < 2e-3 and p.n_l == 16
+
+
+@pytest.mark.parametrize("D,Lb,xi,M,P", [(4, 1.0, 5.0, 32, 8), (3, 0.0, 5.0, 32, 8), (3, 1.0, -1.0, 32, 8),
+                                         (3, 1.0, 5.0, 33, 8), (3, 1.0, 5.0, 32, 7), (3, 1.0, 5.0, 8, 10),
+                                         (3, 1.0, 5.0, 38, 8), (3, 1.0, 5.0, 32, 18), (3, float("nan"), 5.0, 32, 8)])
+def test_plan_create_rejects_invalid_parameters(D, Lb, xi, M, P):
+    """Section 3.3: M, P even, P <= M; M must factor into 2, 3, 5, 7 (38 = 2*19
+    does not); the support is limited to P <= 16."""
+    lib = L.load()
+    p = L.se_params()
+    p.D, p.L, p.xi, p.M, p.P, p.window = D, Lb, xi, M, P, L.SE_WIN_PKB
+    plan = ctypes.c_void_p()
+    assert lib.se_plan_create(ctypes.byref(p), 10, None, ctypes.byref(plan)) == L.SE_ERR_PARAM
+    assert not plan.value
+
+
+def test_null_arguments():
+    lib = L.load()
+    assert lib.se_plan_create(None, 10, None, None) == L.SE_ERR_ARG
+    assert lib.se_eval(None, 0, None, None, None, None, None, 0, None) == L.SE_ERR_ARG
+    assert lib.se_plan_get_info(None, None) == L.SE_ERR_ARG
+    assert lib.se_plan_destroy(None) == L.SE_OK
+    assert lib.se_params_default(3, 1.0, 5.0, 32, 8, 1, 1.0, 1e-6, 0, None) == L.SE_ERR_ARG
+    out = L.se_params()
+    assert lib.se_params_default(3, 1.0, 5.0, 32, 8, 1, 1.0, -1.0, 0, ctypes.byref(out)) == L.SE_ERR_PARAM

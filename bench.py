@@ -148,7 +148,7 @@ def main():
     x64 = torch.tensor(x, dtype=torch.float64, device=dev)
     q64 = torch.tensor(q, dtype=torch.float64, device=dev)
     print(f"bench: {args.workload} D={D} N={N} M={M} Mt={plan32.info.Mt} P={P} xi={xi} "
-          f"tile={plan32.info.tile}", file=sys.stderr, flush=True)
+          f"tile={list(plan32.info.tile)}", file=sys.stderr, flush=True)
 
     ms32, out32, stages32 = run_path(plan32, x64, q64, args.steps, args.warmup)
     ms64, out64, stages64 = run_path(plan64, x64, q64, args.steps, args.warmup)

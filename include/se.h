@@ -79,7 +79,7 @@ typedef struct {
   double tol;         /* absolute rms tolerance for the s, n_l estimates          */
   double Q;           /* sum of q^2, used by the s, n_l estimates (B, Section 5.2) */
   se_precision prec;  /* compute precision of grid, FFT, gather                   */
-  int tile;           /* spread/gather tile edge in grid points; <= 0 -> automatic */
+  int tile;           /* cubic spread/gather tile edge (multiple of 4); <= 0 -> automatic */
 } se_params;
 
 /* Derived sizes of a plan (read-only report). */
@@ -91,7 +91,7 @@ typedef struct {
   int n_l;            /* size of the set I                                             */
   int grid[3];        /* gridding grid points in x, y, z                               */
   int nfft[3];        /* transform lengths of the periodic / 0P padded directions      */
-  int tile;
+  int tile[3];        /* spread/gather tile edges in grid points (x, y, z)             */
   double h, shape, lambda, s0, s, R;
   size_t device_bytes; /* device memory held by the plan                               */
 } se_plan_info;

@@ -68,7 +68,7 @@ class se_plan_info(ctypes.Structure):
         ("n_l", ctypes.c_int),
         ("grid", ctypes.c_int * 3),
         ("nfft", ctypes.c_int * 3),
-        ("tile", ctypes.c_int),
+        ("tile", ctypes.c_int * 3),
         ("h", ctypes.c_double),
         ("shape", ctypes.c_double),
         ("lambda_", ctypes.c_double),

@@ -14,6 +14,8 @@ constexpr int kMaxClasses = 3;
 constexpr int kMaxP = 16;
 constexpr int kMaxNu = 12;
 constexpr int kBlock = 256;      // threads per block of every kernel
+constexpr int kSB = 4;           // sub-bin edge in grid cells (particle sort key)
+constexpr int kMaxOwnRanges = 256;  // sub-bin rows of one tile ((T/kSB)^2 <= 256 for T <= 64)
 
 // Green's-function modes of the fused scaling pass (Eq. scale).
 enum GMode : int {
@@ -69,9 +71,10 @@ struct GridGeom {
   int G[3];           // grid points per direction (x, y, z)
   int per[3];         // 1 if the direction is periodic
   int d0[3];          // integer offset of the free-direction grid origin, (Mt - M)/2
-  int tile;           // tile edge in grid points
-  int chunk;          // particles staged in LDS per round (<= kBlock)
+  int T[3];           // tile edges in grid points (multiples of kSB)
   int nt[3];          // tiles per direction
+  int nsb[3];         // sub-bins per direction, ceil(G / kSB)
+  int chunk;          // particles per wavefront round of the spread kernel (<= 64)
   int P, nu;
   int window;         // 0 Gaussian, 1 PKB
   double h, L, xi;
@@ -81,15 +84,17 @@ struct GridGeom {
 
 // Device buffers of one evaluation.
 struct EvalBuffers {
-  int* tile_count;    // ntiles
-  int* tile_start;    // ntiles + 1
-  int* tile_cursor;   // ntiles
-  int* p_tile;        // n_max: tile of each particle (input order)
+  int* sb_count;      // sub-bins
+  int* sb_start;      // sub-bins + 1
+  int* sb_cursor;     // sub-bins
+  int* p_key;         // n_max: sub-bin of each particle (input order)
   int* p_cell;        // n_max: packed cell of each particle (input order)
   void* p_frac;       // n_max x 4 (fx, fy, fz, q) in compute precision (input order)
   int* s_cell;        // n_max: sorted packed cells
   int* s_idx;         // n_max: sorted original indices
   void* s_fq;         // n_max x 4 sorted (fx, fy, fz, q)
+  int* bsum;          // per scan block: count total
+  void* stage;        // per tile: spread box (T+P-1)^3 in compute precision
   double* qpart;      // per bin block: sum q, sum |q|, sum q^2
   double* epart;      // per gather block: sum q phi
   double* red;        // 4 doubles: Q, sum|q|, Q2, E
@@ -105,6 +110,7 @@ hipError_t launch_scan(const GridGeom& g, const EvalBuffers& b, int nblk_bin, in
                        hipStream_t st);
 hipError_t launch_scatter(const GridGeom& g, const EvalBuffers& b, long N, bool f64, hipStream_t st);
 hipError_t launch_spread(const GridGeom& g, const EvalBuffers& b, bool f64, hipStream_t st);
+hipError_t launch_fold(const GridGeom& g, const EvalBuffers& b, bool f64, hipStream_t st);
 hipError_t launch_gather(const GridGeom& g, const EvalBuffers& b, bool f64, void* phi, void* force,
                          int out_grad, double self_coef, hipStream_t st);
 hipError_t launch_energy(const GridGeom& g, const EvalBuffers& b, double* energy, double self_e,
@@ -113,6 +119,7 @@ hipError_t launch_fft(const FftPass& p, bool f64, hipStream_t st);
 size_t fft_lds_bytes(const FftPass& p, bool f64);
 size_t spread_lds_bytes(const GridGeom& g, bool f64);
 size_t gather_lds_bytes(const GridGeom& g, bool f64);
+int scan_blocks(const GridGeom& g);
 
 // 0P precompute helpers (FP64).
 hipError_t launch_g0p_fill(double* buf, int n0, double h, double R, hipStream_t st);

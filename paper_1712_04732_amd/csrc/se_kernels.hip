@@ -369,7 +369,10 @@ hipError_t launch_fft(const FftPass& p, bool f64, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// Binning
+// Binning: grid cell, fractional offset and sub-bin of every particle.  The
+// sub-bins are blocks of kSB^3 cells; sorting the particles by sub-bin lets a
+// tile find every particle whose stencil can reach it as a short list of
+// contiguous index ranges.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int pack_cell(int cx_, int cy, int cz) { return cx_ | (cy << 10) | (cz << 20); }
 
@@ -378,6 +381,25 @@ __device__ __forceinline__ T warp_sum(T v) {
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
   return v;
+}
+
+// Sum over aligned groups of W lanes (W a power of two <= 64).
+template <int W, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int m = W / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// LDS writes of a wavefront made visible to the other lanes of the same wavefront.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int sb_key(const GridGeom& g, int cx_, int cy, int cz) {
+  return ((cz / kSB) * g.nsb[1] + cy / kSB) * g.nsb[0] + cx_ / kSB;
 }
 
 template <typename Tin, typename T>
@@ -405,11 +427,7 @@ __global__ __launch_bounds__(kBlock) void bin_kernel(GridGeom g, EvalBuffers b, 
         const double xw = x - g.L * floor(x / g.L);
         t = xw / g.h;
         ci = (int)floor(t);
-        if (ci >= g.G[d]) {  // xw rounded up to L
-          ci = 0;
-          t = 0.0;
-        }
-        if (ci < 0) {
+        if (ci >= g.G[d] || ci < 0) {  // xw rounded up to L
           ci = 0;
           t = 0.0;
         }
@@ -417,7 +435,7 @@ __global__ __launch_bounds__(kBlock) void bin_kernel(GridGeom g, EvalBuffers b, 
         if (!(x >= 0.0 && x < g.L)) bad |= 2;
         t = x / g.h + g.d0[d];
         ci = (int)floor(t);
-        const int lo = g.d0[d], hi = g.d0[d] + (g.G[d] - 2 * g.d0[d]) - 1;
+        const int lo = g.d0[d], hi = g.G[d] - g.d0[d] - 1;
         if (ci < lo) {
           ci = lo;
           t = (double)lo;
@@ -434,11 +452,11 @@ __global__ __launch_bounds__(kBlock) void bin_kernel(GridGeom g, EvalBuffers b, 
       atomicOr(b.status, bad);
       qn = 0.0;
     }
-    const int tile = ((c[2] / g.tile) * g.nt[1] + c[1] / g.tile) * g.nt[0] + c[0] / g.tile;
-    b.p_tile[n] = tile;
+    const int key = sb_key(g, c[0], c[1], c[2]);
+    b.p_key[n] = key;
     b.p_cell[n] = pack_cell(c[0], c[1], c[2]);
     reinterpret_cast<Quad<T>*>(b.p_frac)[n] = Quad<T>{(T)f[0], (T)f[1], (T)f[2], (T)qn};
-    atomicAdd(&b.tile_count[tile], 1);
+    atomicAdd(&b.sb_count[key], 1);
     sq = qn;
     sa = fabs(qn);
     s2 = qn * qn;
@@ -480,37 +498,70 @@ hipError_t launch_bin(const GridGeom& g, const EvalBuffers& b, long N, const voi
   return hipGetLastError();
 }
 
-// Exclusive scan of the tile counts (one workgroup of 1024 threads), the
-// cursors of the scatter, and the FP64 charge sums with the neutrality check.
-__global__ __launch_bounds__(1024) void scan_kernel(GridGeom g, EvalBuffers b, int nblk_bin,
-                                                    int check_neutral) {
-  const int ntiles = g.nt[0] * g.nt[1] * g.nt[2];
-  const int T = blockDim.x;
-  const int per = (ntiles + T - 1) / T;
-  const int lo = threadIdx.x * per;
-  const int hi = min(ntiles, lo + per);
+// Exclusive scan of the sub-bin counts in two passes over blocks of
+// kScanBlock entries: a local scan with block totals, then each block adds the
+// sum of the totals before it.  Block 0 of the second pass also reduces the
+// FP64 charge sums and applies the neutrality check.
+constexpr int kScanBlock = 1024;
+
+__global__ __launch_bounds__(kBlock) void scan1_kernel(GridGeom g, EvalBuffers b) {
+  const int n = g.nsb[0] * g.nsb[1] * g.nsb[2];
+  const int base = blockIdx.x * kScanBlock;
+  constexpr int K = kScanBlock / kBlock;
+  int v[K];
   int s = 0;
-  for (int i = lo; i < hi; ++i) s += b.tile_count[i];
-  __shared__ int part[1024];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = base + threadIdx.x * K + k;
+    v[k] = i < n ? b.sb_count[i] : 0;
+    s += v[k];
+  }
+  __shared__ int part[kBlock];
   part[threadIdx.x] = s;
   __syncthreads();
-  for (int off = 1; off < T; off <<= 1) {
-    const int v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+  for (int off = 1; off < kBlock; off <<= 1) {
+    const int t = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
     __syncthreads();
-    part[threadIdx.x] += v;
+    part[threadIdx.x] += t;
     __syncthreads();
   }
   int run = part[threadIdx.x] - s;
-  for (int i = lo; i < hi; ++i) {
-    b.tile_start[i] = run;
-    b.tile_cursor[i] = run;
-    run += b.tile_count[i];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = base + threadIdx.x * K + k;
+    if (i < n) b.sb_start[i] = run;
+    run += v[k];
   }
-  if (threadIdx.x == T - 1) b.tile_start[ntiles] = part[T - 1];
+  if (threadIdx.x == kBlock - 1) b.bsum[blockIdx.x] = part[kBlock - 1];
+}
 
-  __shared__ double dq[3][1024];
+__global__ __launch_bounds__(kBlock) void scan2_kernel(GridGeom g, EvalBuffers b, int nblk_bin,
+                                                       int check_neutral) {
+  const int n = g.nsb[0] * g.nsb[1] * g.nsb[2];
+  __shared__ int ps[kBlock];
+  __shared__ double dq[3][kBlock];
+  int o = 0;
+  for (int j = threadIdx.x; j < (int)blockIdx.x; j += kBlock) o += b.bsum[j];
+  ps[threadIdx.x] = o;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) ps[threadIdx.x] += ps[threadIdx.x + off];
+    __syncthreads();
+  }
+  const int offset = ps[0];
+  const int base = blockIdx.x * kScanBlock;
+  for (int k = threadIdx.x; k < kScanBlock; k += kBlock) {
+    const int i = base + k;
+    if (i < n) {
+      const int v = b.sb_start[i] + offset;
+      b.sb_start[i] = v;
+      b.sb_cursor[i] = v;
+    }
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) b.sb_start[n] = offset + b.bsum[blockIdx.x];
+  if (blockIdx.x != 0) return;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  for (int i = threadIdx.x; i < nblk_bin; i += T) {
+  for (int i = threadIdx.x; i < nblk_bin; i += kBlock) {
     a0 += b.qpart[3 * i];
     a1 += b.qpart[3 * i + 1];
     a2 += b.qpart[3 * i + 2];
@@ -519,21 +570,31 @@ __global__ __launch_bounds__(1024) void scan_kernel(GridGeom g, EvalBuffers b, i
   dq[1][threadIdx.x] = a1;
   dq[2][threadIdx.x] = a2;
   __syncthreads();
-  if (threadIdx.x < 3) {
-    double acc = 0.0;
-    for (int i = 0; i < T; ++i) acc += dq[threadIdx.x][i];
-    b.red[threadIdx.x] = acc;
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      dq[0][threadIdx.x] += dq[0][threadIdx.x + off];
+      dq[1][threadIdx.x] += dq[1][threadIdx.x + off];
+      dq[2][threadIdx.x] += dq[2][threadIdx.x + off];
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  if (threadIdx.x == 0 && check_neutral) {
-    const double Q = b.red[0], A = b.red[1];
-    if (fabs(Q) > 1e-10 * A) atomicOr(b.status, 4);
+  if (threadIdx.x == 0) {
+    b.red[0] = dq[0][0];
+    b.red[1] = dq[1][0];
+    b.red[2] = dq[2][0];
+    if (check_neutral && fabs(dq[0][0]) > 1e-10 * dq[1][0]) atomicOr(b.status, 4);
   }
+}
+
+int scan_blocks(const GridGeom& g) {
+  return (g.nsb[0] * g.nsb[1] * g.nsb[2] + kScanBlock - 1) / kScanBlock;
 }
 
 hipError_t launch_scan(const GridGeom& g, const EvalBuffers& b, int nblk_bin, int check_neutral,
                        hipStream_t st) {
-  scan_kernel<<<dim3(1), dim3(1024), 0, st>>>(g, b, nblk_bin, check_neutral);
+  const int nb = scan_blocks(g);
+  scan1_kernel<<<dim3(nb), dim3(kBlock), 0, st>>>(g, b);
+  scan2_kernel<<<dim3(nb), dim3(kBlock), 0, st>>>(g, b, nblk_bin, check_neutral);
   return hipGetLastError();
 }
 
@@ -541,8 +602,8 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void scatter_kernel(EvalBuffers b, long N) {
   const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
-  const int tile = b.p_tile[n];
-  const int pos = atomicAdd(&b.tile_cursor[tile], 1);
+  const int key = b.p_key[n];
+  const int pos = atomicAdd(&b.sb_cursor[key], 1);
   b.s_cell[pos] = b.p_cell[n];
   b.s_idx[pos] = (int)n;
   reinterpret_cast<Quad<T>*>(b.s_fq)[pos] = reinterpret_cast<const Quad<T>*>(b.p_frac)[n];
@@ -562,177 +623,326 @@ hipError_t launch_scatter(const GridGeom& g, const EvalBuffers& b, long N, bool 
 // ---------------------------------------------------------------------------
 // Window weights (Section 4).  f = frac(t) of the particle's grid coordinate,
 // stencil point i at grid index floor(t) - P/2 + 1 + i.
-//   PKB: xbar = 1 - 2f for all i (Section 4.1), Horner per subinterval;
-//        derivative table already holds d/dx (chain factor -2/h).
+//   PKB: xbar = 1 - 2f for all i (Section 4.1), Horner on row i of the
+//        coefficient table; the derivative table already carries d/dx
+//        (chain factor -2/h).
 //   Gaussian: u = i + 1 - P/2 - f (grid units), W = exp(-alpha (2u/P)^2),
 //        dW/dx = W 2 alpha (2/P)^2 u / h.
 // ---------------------------------------------------------------------------
 template <typename T, int P>
-__device__ __forceinline__ void window_weights(const GridGeom& g, const T* __restrict__ coef,
-                                               const T* __restrict__ dcoef, T f, T* w, T* dw) {
+__device__ __forceinline__ T weight_row(const GridGeom& g, const T* __restrict__ tab, int i, T f) {
   if (g.window == 1) {
     const T xb = (T)1 - (T)2 * f;
     const int m = g.nu + 1;
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-      T a = coef[i * m + g.nu];
-      for (int j = g.nu - 1; j >= 0; --j) a = a * xb + coef[i * m + j];
-      w[i] = a;
-      if (dw) {
-        T d = dcoef[i * m + g.nu];
-        for (int j = g.nu - 1; j >= 0; --j) d = d * xb + dcoef[i * m + j];
-        dw[i] = d;
-      }
-    }
-  } else {
-    const T a = (T)g.alpha;
-    const T c2 = (T)4 / (T)(P * P);
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-      const T u = (T)(i + 1 - P / 2) - f;
-      const T e = exp(-a * c2 * u * u);
-      w[i] = e;
-      if (dw) dw[i] = e * (T)2 * a * c2 * u / (T)g.h;
-    }
+    T a = tab[i * m + g.nu];
+    for (int j = g.nu - 1; j >= 0; --j) a = a * xb + tab[i * m + j];
+    return a;
   }
+  const T u = (T)(i + 1 - P / 2) - f;
+  return exp(-(T)g.alpha * ((T)4 / (T)(P * P)) * u * u);
 }
 
-// Tiles of one direction that hold anchor cells of particles whose stencil
-// meets the tile [x0, x0 + ext).  Anchor cells c with c - P/2 + 1 <= x0 + ext - 1
-// and c + P/2 >= x0, wrapped in periodic directions.
-__device__ __forceinline__ int neighbor_tiles(int x0, int ext, int G, int per, int tile, int P,
-                                              int* list) {
-  int cnt = 0;
-  const int lo = x0 - P / 2, hi = x0 + ext - 2 + P / 2;
-  for (int c = lo; c <= hi; ++c) {
-    int cc = c;
-    if (per) {
-      cc = c % G;
-      if (cc < 0) cc += G;
-    } else if (c < 0 || c >= G) {
-      continue;
-    }
-    const int t = cc / tile;
-    bool seen = false;
-    for (int k = 0; k < cnt; ++k) seen |= (list[k] == t);
-    if (!seen && cnt < 8) list[cnt++] = t;
-  }
-  return cnt;
+template <typename T, int P>
+__device__ __forceinline__ T dweight_row(const GridGeom& g, const T* __restrict__ dtab, int i, T f) {
+  if (g.window == 1) return weight_row<T, P>(g, dtab, i, f);
+  const T u = (T)(i + 1 - P / 2) - f;
+  const T c2 = (T)4 / (T)(P * P);
+  return exp(-(T)g.alpha * c2 * u * u) * (T)2 * (T)g.alpha * c2 * u / (T)g.h;
 }
 
+// Segments are {first0, last0, first1, last1} in sub-bin units.
+__device__ __forceinline__ int seg_len(const int* seg, int ns) {
+  int n = 0;
+  for (int k = 0; k < ns; ++k) n += seg[2 * k + 1] - seg[2 * k] + 1;
+  return n;
+}
+
+__device__ __forceinline__ int seg_at(const int* seg, int ns, int r) {
+  const int l0 = seg[1] - seg[0] + 1;
+  return (ns == 1 || r < l0) ? seg[0] + r : seg[2] + (r - l0);
+}
+
+// Particle index ranges of the sub-bin rows (z, y, x-segment) of a tile's
+// anchor box, and their exclusive prefix; returns the total particle count.
+// All threads of the block call it; ends with a barrier.
+__device__ int build_ranges(const GridGeom& g, const EvalBuffers& b, const int* sz, int nsz,
+                            const int* sy, int nsy, const int* sx, int nsx, int* rstart, int* rpre) {
+  const int nz = seg_len(sz, nsz), ny = seg_len(sy, nsy);
+  const int nr = nz * ny * nsx;
+  for (int r = threadIdx.x; r < nr; r += blockDim.x) {
+    const int xs = r % nsx, ry = (r / nsx) % ny, rz = r / (nsx * ny);
+    const int bz = seg_at(sz, nsz, rz), by = seg_at(sy, nsy, ry);
+    const int row = (bz * g.nsb[1] + by) * g.nsb[0];
+    const int a = b.sb_start[row + sx[2 * xs]], e = b.sb_start[row + sx[2 * xs + 1] + 1];
+    rstart[r] = a;
+    rpre[r] = e - a;
+  }
+  __syncthreads();
+  // exclusive prefix of rpre[0..nr) (nr <= kMaxOwnRanges)
+  __shared__ int part[kBlock];
+  const int per = (nr + blockDim.x - 1) / blockDim.x;
+  const int lo = min(nr, (int)threadIdx.x * per), hi = min(nr, lo + per);
+  int s = 0;
+  for (int i = lo; i < hi; ++i) s += rpre[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+    const int v = (int)threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int run = part[threadIdx.x] - s;
+  for (int i = lo; i < hi; ++i) {
+    const int c = rpre[i];
+    rpre[i] = run;
+    run += c;
+  }
+  const int total = part[blockDim.x - 1];
+  __syncthreads();
+  if (threadIdx.x == 0) rpre[nr] = total;
+  __syncthreads();
+  return total;
+}
+
+// Range holding flattened index e: the last r with rpre[r] <= e.
+__device__ __forceinline__ int find_range(const int* rpre, int nr, int e) {
+  int lo = 0, hi = nr - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (rpre[mid] <= e) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------------------
+// Spreading, Eq. (gridding), in two kernels.
+//   spread: one workgroup per tile takes the particles anchored in the tile
+//     and adds their full P^3 stencils into an LDS box covering the tile and
+//     its stencil halo, (T+P-1)^3 points; each wavefront evaluates the weights
+//     of 64 particles at a time (one lane per particle), then adds them one
+//     particle at a time, 64 lanes over the stencil columns (ix, iy) and a loop
+//     over iz; the box is stored once to a staging array.
+//   fold: one workgroup per tile sums, for each of its grid points, the boxes
+//     of the up to 27 tiles (periodic images included) that cover the point,
+//     in a fixed order, and writes the grid point once.
+// No global atomics.
+// ---------------------------------------------------------------------------
+// Lanes per particle when one lane evaluates one row of the window weights.
+template <int P>
+struct Lanes {
+  static constexpr int G2 = P <= 2 ? 2 : (P <= 4 ? 4 : (P <= 8 ? 8 : 16));
+  static constexpr int PPW = 64 / G2;
+};
+
+// Row i of the PKB coefficient table (values or derivatives) in registers.
+template <typename T>
+__device__ __forceinline__ void load_row(const T* __restrict__ tab, int i, int m, T* r) {
+#pragma unroll
+  for (int j = 0; j <= kMaxNu; ++j) r[j] = j < m ? tab[i * m + j] : (T)0;
+}
+
+// Window weight of stencil row i at fractional offset f from a register row.
+template <typename T, int P>
+__device__ __forceinline__ T weight_reg(const GridGeom& g, const T* r, int i, T f) {
+  if (g.window == 1) {
+    const T xb = (T)1 - (T)2 * f;
+    T a = r[kMaxNu];
+#pragma unroll
+    for (int j = kMaxNu - 1; j >= 0; --j) a = a * xb + r[j];
+    return a;
+  }
+  const T u = (T)(i + 1 - P / 2) - f;
+  return exp(-(T)g.alpha * ((T)4 / (T)(P * P)) * u * u);
+}
+
+template <typename T, int P>
+__device__ __forceinline__ T dweight_reg(const GridGeom& g, const T* r, int i, T f) {
+  if (g.window == 1) return weight_reg<T, P>(g, r, i, f);
+  const T u = (T)(i + 1 - P / 2) - f;
+  const T c2 = (T)4 / (T)(P * P);
+  return exp(-(T)g.alpha * c2 * u * u) * (T)2 * (T)g.alpha * c2 * u / (T)g.h;
+}
+
+// Round d to the nearest integer for |d| < 2^51: adding 1.5 * 2^52 moves the
+// integer part into the low mantissa bits.
+__device__ __forceinline__ long long round_fixed(double d) {
+  return __double_as_longlong(d + 6755399441055744.0) - 0x4338000000000000LL;
+}
 
 template <typename T, int P>
 __global__ __launch_bounds__(kBlock) void spread_kernel(GridGeom g, EvalBuffers b) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int TT = g.tile;
-  const int tz = blockIdx.x / (g.nt[0] * g.nt[1]);
-  const int ty = (blockIdx.x / g.nt[0]) % g.nt[1];
-  const int tx = blockIdx.x % g.nt[0];
-  const int x0 = tx * TT, y0 = ty * TT, z0 = tz * TT;
-  const int ex = min(TT, g.G[0] - x0), ey = min(TT, g.G[1] - y0), ez = min(TT, g.G[2] - z0);
+  constexpr int G2 = Lanes<P>::G2, PPW = Lanes<P>::PPW;
+  const int TX = g.T[0], TY = g.T[1], TZ = g.T[2];
+  const int t_id = blockIdx.x;
+  const int tz = t_id / (g.nt[0] * g.nt[1]);
+  const int ty = (t_id / g.nt[0]) % g.nt[1];
+  const int tx = t_id % g.nt[0];
+  const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+  const int ex = min(TX, g.G[0] - x0), ey = min(TY, g.G[1] - y0), ez = min(TZ, g.G[2] - z0);
+  const int RX = TX + P - 1, RY = TY + P - 1, RZ = TZ + P - 1, R3 = RX * RY * RZ;
   const int m = g.nu + 1;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int nwaves = blockDim.x / 64;
+  const int CH = g.chunk;                                     // particles per wavefront round
 
-  const int kChunk = g.chunk;
-  T* acc = reinterpret_cast<T*>(smem);                  // TT^3
-  T* wx = acc + TT * TT * TT;                            // kChunk * P
-  T* wy = wx + kChunk * P;
-  T* wz = wy + kChunk * P;
-  T* coef = wz + kChunk * P;                             // P * m
-  int* off = reinterpret_cast<int*>(coef + P * m);       // kChunk * 3
-  int* ncomp = off + 3 * kChunk;
+  unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem);   // R3, fixed point
+  int* rstart = reinterpret_cast<int*>(acc + R3);             // kMaxOwnRanges
+  int* rpre = rstart + kMaxOwnRanges;                         // kMaxOwnRanges + 1
+  T* wbuf = reinterpret_cast<T*>(rpre + kMaxOwnRanges + 4);   // nwaves * CH * 3P
+  int* obuf = reinterpret_cast<int*>(wbuf + nwaves * CH * 3 * P);  // nwaves * CH * 3
+  __shared__ double wsum[kBlock / 64];
 
-  for (int i = threadIdx.x; i < TT * TT * TT; i += blockDim.x) acc[i] = (T)0;
-  for (int i = threadIdx.x; i < P * m; i += blockDim.x) coef[i] = reinterpret_cast<const T*>(b.wtab)[i];
-  if (threadIdx.x == 0) *ncomp = 0;
-
-  int lx[8], ly[8], lz[8];
-  const int nx = neighbor_tiles(x0, ex, g.G[0], g.per[0], TT, P, lx);
-  const int ny = neighbor_tiles(y0, ey, g.G[1], g.per[1], TT, P, ly);
-  const int nz = neighbor_tiles(z0, ez, g.G[2], g.per[2], TT, P, lz);
-  __syncthreads();
-
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, nwaves = blockDim.x / 64;
+  for (int i = threadIdx.x; i < R3; i += blockDim.x) acc[i] = 0ull;
+  int sx[2] = {x0 / kSB, (x0 + ex - 1) / kSB}, sy[2] = {y0 / kSB, (y0 + ey - 1) / kSB},
+      sz[2] = {z0 / kSB, (z0 + ez - 1) / kSB};
+  const int nr = (sz[1] - sz[0] + 1) * (sy[1] - sy[0] + 1);
+  const int total = build_ranges(g, b, sz, 1, sy, 1, sx, 1, rstart, rpre);
   const Quad<T>* sfq = reinterpret_cast<const Quad<T>*>(b.s_fq);
 
-  for (int a = 0; a < nz; ++a)
-    for (int bb = 0; bb < ny; ++bb)
-      for (int c = 0; c < nx; ++c) {
-        const int nt = (lz[a] * g.nt[1] + ly[bb]) * g.nt[0] + lx[c];
-        const int start = b.tile_start[nt], end = b.tile_start[nt + 1];
-        for (int base = start; base < end; base += kChunk) {
-          // 1. select particles whose stencil meets this tile; window weights
-          const int i = base + threadIdx.x;
-          if (threadIdx.x < kChunk && i < end) {
-            const int pc = b.s_cell[i];
-            const int cc[3] = {pc & 1023, (pc >> 10) & 1023, (pc >> 20) & 1023};
-            const int org[3] = {x0, y0, z0}, ext[3] = {ex, ey, ez};
-            int o[3];
-            bool hit = true;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-              int od = cc[d] - P / 2 + 1 - org[d];
-              if (g.per[d]) {
-                od %= g.G[d];
-                if (od < 0) od += g.G[d];
-                hit = hit && (od < ext[d] || od + P > g.G[d]);
-              } else {
-                hit = hit && (od < ext[d] && od + P > 0);
-              }
-              o[d] = od;
-            }
-            if (hit) {
-              const int slot = atomicAdd(ncomp, 1);
-              off[3 * slot] = o[0];
-              off[3 * slot + 1] = o[1];
-              off[3 * slot + 2] = o[2];
-              const Quad<T> f = sfq[i];
-              window_weights<T, P>(g, coef, nullptr, f.fx, wx + slot * P, nullptr);
-              window_weights<T, P>(g, coef, nullptr, f.fy, wy + slot * P, nullptr);
-              window_weights<T, P>(g, coef, nullptr, f.fz, wz + slot * P, nullptr);
-#pragma unroll
-              for (int k = 0; k < P; ++k) wz[slot * P + k] *= f.q;
-            }
-          }
-          __syncthreads();
-          // 2. accumulate: one wavefront per particle, lanes over (ix, iy)
-          const int nc = *ncomp;
-          for (int s = wave; s < nc; s += nwaves) {
-            const int ox = off[3 * s], oy = off[3 * s + 1], oz = off[3 * s + 2];
-            for (int l = lane; l < P * P; l += 64) {
-              const int ix = l % P, iy = l / P;
-              int px = ox + ix, py = oy + iy;
-              if (g.per[0] && px >= g.G[0]) px -= g.G[0];
-              if (g.per[1] && py >= g.G[1]) py -= g.G[1];
-              if (px < 0 || px >= ex || py < 0 || py >= ey) continue;
-              const T wxy = wx[s * P + ix] * wy[s * P + iy];
-#pragma unroll
-              for (int iz = 0; iz < P; ++iz) {
-                int pz = oz + iz;
-                if (g.per[2] && pz >= g.G[2]) pz -= g.G[2];
-                if (pz < 0 || pz >= ez) continue;
-                atomicAdd(&acc[(pz * TT + py) * TT + px], wxy * wz[s * P + iz]);
-              }
-            }
-          }
-          __syncthreads();
-          if (threadIdx.x == 0) *ncomp = 0;
-          __syncthreads();
+  // Fixed-point scale of this tile: |sum of q W| at any box point is at most
+  // sum |q| over the tile's particles (W <= 1), kept below 2^50.
+  double sa = 0.0;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    const int r = find_range(rpre, nr, e);
+    sa += fabs((double)sfq[rstart[r] + (e - rpre[r])].q);
+  }
+  sa = warp_sum(sa);
+  if (lane == 0) wsum[wave] = sa;
+  __syncthreads();
+  double stile = 0.0;
+  for (int w = 0; w < nwaves; ++w) stile += wsum[w];
+  const double scale = stile > 0.0 ? 1125899906842624.0 / (1.0009765625 * stile) : 0.0;   // 2^50
+
+  // coefficient row of this lane (row k = lane % G2)
+  const int kr = lane % G2, pr = lane / G2;
+  T crow[kMaxNu + 1];
+  load_row(reinterpret_cast<const T*>(b.wtab), min(kr, P - 1), m, crow);
+
+  T* ww = wbuf + wave * CH * 3 * P;
+  int* wo = obuf + wave * CH * 3;
+  const int RXY = RX * RY;
+  for (int base = wave * CH; base < total; base += nwaves * CH) {
+    const int nv = min(CH, total - base);
+    // weights: G2 lanes per particle, lane k evaluates row k in x, y, z
+    for (int p0 = 0; p0 < nv; p0 += PPW) {
+      const int p = p0 + pr;
+      if (p < nv && kr < P) {
+        const int e = base + p;
+        const int r = find_range(rpre, nr, e);
+        const int i = rstart[r] + (e - rpre[r]);
+        const Quad<T> f = sfq[i];
+        T* w = ww + p * 3 * P;
+        w[kr] = weight_reg<T, P>(g, crow, kr, f.fx);
+        w[P + kr] = weight_reg<T, P>(g, crow, kr, f.fy);
+        w[2 * P + kr] = f.q * weight_reg<T, P>(g, crow, kr, f.fz);
+        if (kr == 0) {
+          const int pc = b.s_cell[i];
+          // stencil origin c - P/2 + 1 in box coordinates (box origin x0 - P/2 + 1)
+          wo[3 * p] = (pc & 1023) - x0;
+          wo[3 * p + 1] = ((pc >> 10) & 1023) - y0;
+          wo[3 * p + 2] = ((pc >> 20) & 1023) - z0;
         }
       }
+    }
+    wave_sync();
+    for (int s = 0; s < nv; ++s) {
+      const int ox = wo[3 * s], oy = wo[3 * s + 1], oz = wo[3 * s + 2];
+      const T* w = ww + s * 3 * P;
+      T wz[P];
+#pragma unroll
+      for (int k = 0; k < P; ++k) wz[k] = w[2 * P + k];
+      for (int l = lane; l < P * P; l += 64) {
+        const int ix = l % P, iy = l / P;
+        const double wxy = (double)(w[ix] * w[P + iy]) * scale;
+        unsigned long long* col = acc + (oz * RY + oy + iy) * RX + ox + ix;
+#pragma unroll
+        for (int iz = 0; iz < P; ++iz)
+          atomicAdd(col + iz * RXY, (unsigned long long)round_fixed(wxy * (double)wz[iz]));
+      }
+    }
+    wave_sync();
+  }
+  __syncthreads();
+  T* stg = reinterpret_cast<T*>(b.stage) + (long long)t_id * R3;
+  const double inv = stile > 0.0 ? 1.0 / scale : 0.0;
+  for (int i = threadIdx.x; i < R3; i += blockDim.x) stg[i] = (T)((double)(long long)acc[i] * inv);
+}
 
-  // write the tile once
+// For one direction: the tile at offset d from tile t (wrapped in periodic
+// directions), and the origin of its box in the unwrapped frame of tile t.
+// Returns false if there is no such tile.
+__device__ __forceinline__ bool box_of(const GridGeom& g, int dim, int t, int d, int* tile, int* org) {
+  const int nt = g.nt[dim], G = g.G[dim];
+  int u = t + d, shift = 0;
+  while (u < 0) {
+    if (!g.per[dim]) return false;
+    u += nt;
+    shift -= G;
+  }
+  while (u >= nt) {
+    if (!g.per[dim]) return false;
+    u -= nt;
+    shift += G;
+  }
+  *tile = u;
+  *org = u * g.T[dim] + shift - (g.P / 2 - 1);
+  return true;
+}
+
+// Tiles whose box can reach a point of tile t lie at offsets |d| <= dmax:
+// a box extends P/2 - 1 below and P/2 above its tile.
+__device__ __forceinline__ int fold_reach(const GridGeom& g, int dim) { return 1 + (g.P / 2 - 1) / g.T[dim]; }
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void fold_kernel(GridGeom g, EvalBuffers b) {
+  const int t_id = blockIdx.x;
+  const int tz = t_id / (g.nt[0] * g.nt[1]);
+  const int ty = (t_id / g.nt[0]) % g.nt[1];
+  const int tx = t_id % g.nt[0];
+  const int x0 = tx * g.T[0], y0 = ty * g.T[1], z0 = tz * g.T[2];
+  const int ex = min(g.T[0], g.G[0] - x0), ey = min(g.T[1], g.G[1] - y0), ez = min(g.T[2], g.G[2] - z0);
+  const int RX = g.T[0] + g.P - 1, RY = g.T[1] + g.P - 1, RZ = g.T[2] + g.P - 1;
+  const long long R3 = (long long)RX * RY * RZ;
+  const int rx = fold_reach(g, 0), ry = fold_reach(g, 1), rz = fold_reach(g, 2);
+  const T* stg = reinterpret_cast<const T*>(b.stage);
   T* grid = reinterpret_cast<T*>(b.grid);
   const int n = ex * ey * ez;
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int px = e % ex, py = (e / ex) % ey, pz = e / (ex * ey);
-    grid[((long long)(z0 + pz) * g.G[1] + (y0 + py)) * g.G[0] + (x0 + px)] = acc[(pz * TT + py) * TT + px];
+    const int x = x0 + e % ex, y = y0 + (e / ex) % ey, z = z0 + e / (ex * ey);
+    T sum = 0;
+    for (int dz = -rz; dz <= rz; ++dz) {
+      int uz, oz;
+      if (!box_of(g, 2, tz, dz, &uz, &oz)) continue;
+      const int bz = z - oz;
+      if (bz < 0 || bz >= RZ) continue;
+      for (int dy = -ry; dy <= ry; ++dy) {
+        int uy, oy;
+        if (!box_of(g, 1, ty, dy, &uy, &oy)) continue;
+        const int by = y - oy;
+        if (by < 0 || by >= RY) continue;
+        for (int dx = -rx; dx <= rx; ++dx) {
+          int ux, ox;
+          if (!box_of(g, 0, tx, dx, &ux, &ox)) continue;
+          const int bx = x - ox;
+          if (bx < 0 || bx >= RX) continue;
+          const long long nt = ((long long)uz * g.nt[1] + uy) * g.nt[0] + ux;
+          sum += stg[nt * R3 + ((long long)bz * RY + by) * RX + bx];
+        }
+      }
+    }
+    grid[((long long)z * g.G[1] + y) * g.G[0] + x] = sum;
   }
 }
 
 template <typename T>
 size_t spread_lds(const GridGeom& g) {
-  const int TT = g.tile, P = g.P, m = g.nu + 1, C = g.chunk;
-  return sizeof(T) * ((size_t)TT * TT * TT + 3 * C * P + P * m) + sizeof(int) * (3 * C + 4);
+  const int P = g.P, nw = kBlock / 64;
+  const size_t R3 = (size_t)(g.T[0] + P - 1) * (g.T[1] + P - 1) * (g.T[2] + P - 1);
+  return 8 * R3 + sizeof(T) * ((size_t)nw * g.chunk * 3 * P) +
+         sizeof(int) * (2 * kMaxOwnRanges + 4 + nw * g.chunk * 3) + 64;
 }
 
 template <typename T, int P>
@@ -765,51 +975,63 @@ hipError_t launch_spread(const GridGeom& g, const EvalBuffers& b, bool f64, hipS
   return f64 ? spread_dispatch<double>(g, b, st) : spread_dispatch<float>(g, b, st);
 }
 
+hipError_t launch_fold(const GridGeom& g, const EvalBuffers& b, bool f64, hipStream_t st) {
+  const int ntiles = g.nt[0] * g.nt[1] * g.nt[2];
+  if (f64)
+    fold_kernel<double><<<dim3(ntiles), dim3(kBlock), 0, st>>>(g, b);
+  else
+    fold_kernel<float><<<dim3(ntiles), dim3(kBlock), 0, st>>>(g, b);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
-// Gathering
+// Gathering, trapezoidal rule of Eq. (complete_integral), and the gradient of
+// Eq. (force-method-1).  One workgroup per tile stages the tile's stencil
+// region of the grid in LDS and takes the particles anchored in the tile.
+// A group of G2 = next_pow2(P) lanes serves one particle; lane iz owns the
+// z-plane iz of the stencil, evaluates row iz of the three weight vectors,
+// contracts its plane separably (x, then y) and the group sums the planes
+// with shuffles.
 // ---------------------------------------------------------------------------
 template <typename T, int P>
 __global__ __launch_bounds__(kBlock) void gather_kernel(GridGeom g, EvalBuffers b, T* __restrict__ phi,
                                                         T* __restrict__ force, int out_grad,
                                                         double self_coef) {
   extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int G2 = Lanes<P>::G2, PPW = Lanes<P>::PPW;
+  const int TX = g.T[0], TY = g.T[1], TZ = g.T[2];
   const int t_id = blockIdx.x;
-  const int start = b.tile_start[t_id], end = b.tile_start[t_id + 1];
-  __shared__ double ewave[kBlock / 64];
-  if (start == end) {
-    if (threadIdx.x == 0) b.epart[t_id] = 0.0;
-    return;
-  }
-  const int TT = g.tile;
-  const int R = TT + P - 1;
   const int tz = t_id / (g.nt[0] * g.nt[1]);
   const int ty = (t_id / g.nt[0]) % g.nt[1];
   const int tx = t_id % g.nt[0];
-  const int x0 = tx * TT, y0 = ty * TT, z0 = tz * TT;
+  const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+  const int ex = min(TX, g.G[0] - x0), ey = min(TY, g.G[1] - y0), ez = min(TZ, g.G[2] - z0);
+  const int RX = TX + P - 1, RY = TY + P - 1, RZ = TZ + P - 1;
   const int m = g.nu + 1;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int nwaves = blockDim.x / 64;
 
-  const int kChunk = g.chunk;
-  T* reg = reinterpret_cast<T*>(smem);                   // R^3
-  T* wx = reg + R * R * R;                                // kChunk * P each
-  T* wy = wx + kChunk * P;
-  T* wz = wy + kChunk * P;
-  T* dx = wz + kChunk * P;
-  T* dy = dx + kChunk * P;
-  T* dz = dy + kChunk * P;
-  T* coef = dz + kChunk * P;                              // P*m
-  T* dcoef = coef + P * m;                                // P*m
-  int* loc = reinterpret_cast<int*>(dcoef + P * m);       // kChunk * 3
-  int* pidx = loc + 3 * kChunk;                           // kChunk
-  T* pq = reinterpret_cast<T*>(pidx + kChunk);            // kChunk
+  T* reg = reinterpret_cast<T*>(smem);                       // RX*RY*RZ
+  int* rstart = reinterpret_cast<int*>(reg + RX * RY * RZ);   // kMaxOwnRanges
+  int* rpre = rstart + kMaxOwnRanges;                         // kMaxOwnRanges + 1
+  T* wsh = reinterpret_cast<T*>(rpre + kMaxOwnRanges + 4);    // nwaves * PPW * 4P
+  __shared__ double ewave[kBlock / 64];
 
-  const T* wt = reinterpret_cast<const T*>(b.wtab);
-  for (int i = threadIdx.x; i < 2 * P * m; i += blockDim.x) coef[i] = wt[i];
+  // particles anchored in this tile: sub-bins of the tile
+  int sx[2] = {x0 / kSB, (x0 + ex - 1) / kSB}, sy[2] = {y0 / kSB, (y0 + ey - 1) / kSB},
+      sz[2] = {z0 / kSB, (z0 + ez - 1) / kSB};
+  const int nr = (sz[1] - sz[0] + 1) * (sy[1] - sy[0] + 1);
+  const int total = build_ranges(g, b, sz, 1, sy, 1, sx, 1, rstart, rpre);
+  if (total == 0) {
+    if (threadIdx.x == 0) b.epart[t_id] = 0.0;
+    return;
+  }
 
-  // stage the stencil region [x0 - P/2 + 1, x0 + TT + P/2 - 1] of the grid
+  // stage the stencil region [x0 - P/2 + 1, x0 + TX + P/2 - 1] of the grid
   const T* grid = reinterpret_cast<const T*>(b.grid);
   const int rx = x0 - P / 2 + 1, ry = y0 - P / 2 + 1, rz = z0 - P / 2 + 1;
-  for (int e = threadIdx.x; e < R * R * R; e += blockDim.x) {
-    const int px = e % R, py = (e / R) % R, pz = e / (R * R);
+  for (int e = threadIdx.x; e < RX * RY * RZ; e += blockDim.x) {
+    const int px = e % RX, py = (e / RX) % RY, pz = e / (RX * RY);
     int gx = rx + px, gy = ry + py, gz = rz + pz;
     bool ok = true;
     if (g.per[0]) { gx %= g.G[0]; if (gx < 0) gx += g.G[0]; } else ok = ok && gx >= 0 && gx < g.G[0];
@@ -818,68 +1040,102 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GridGeom g, EvalBuffers 
     reg[e] = ok ? grid[((long long)gz * g.G[1] + gy) * g.G[0] + gx] : (T)0;
   }
 
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, nwaves = blockDim.x / 64;
+  const int p = lane / G2, iz = lane % G2;
+  // coefficient rows (values, derivatives) of stencil row iz in registers
+  T crow[kMaxNu + 1], drow[kMaxNu + 1];
+  {
+    const T* wt = reinterpret_cast<const T*>(b.wtab);
+    load_row(wt, min(iz, P - 1), m, crow);
+    load_row(wt + P * m, min(iz, P - 1), m, drow);
+  }
+  __syncthreads();
+
+  T* wp = wsh + (wave * PPW + p) * 4 * P;    // wx | dwx | wy | dwy of this lane's particle
   const Quad<T>* sfq = reinterpret_cast<const Quad<T>*>(b.s_fq);
   const T sc = (T)g.scale;
   double eacc = 0.0;
-  __syncthreads();
-
-  for (int base = start; base < end; base += kChunk) {
-    const int cnt = min(kChunk, end - base);
-    if (threadIdx.x < cnt) {
-      const int i = base + threadIdx.x;
-      const int pc = b.s_cell[i];
-      loc[3 * threadIdx.x] = (pc & 1023) - x0;
-      loc[3 * threadIdx.x + 1] = ((pc >> 10) & 1023) - y0;
-      loc[3 * threadIdx.x + 2] = ((pc >> 20) & 1023) - z0;
-      pidx[threadIdx.x] = b.s_idx[i];
-      const Quad<T> f = sfq[i];
-      pq[threadIdx.x] = f.q;
-      const int s = threadIdx.x;
-      window_weights<T, P>(g, coef, dcoef, f.fx, wx + s * P, dx + s * P);
-      window_weights<T, P>(g, coef, dcoef, f.fy, wy + s * P, dy + s * P);
-      window_weights<T, P>(g, coef, dcoef, f.fz, wz + s * P, dz + s * P);
-    }
-    __syncthreads();
-    for (int s = wave; s < cnt; s += nwaves) {
-      const int cx_ = loc[3 * s], cy = loc[3 * s + 1], cz = loc[3 * s + 2];
-      T ph = 0, gx = 0, gy = 0, gz = 0;
-      for (int l = lane; l < P * P; l += 64) {
-        const int ix = l % P, iy = l / P;
-        const T* col = reg + ((long long)cz * R + (cy + iy)) * R + (cx_ + ix);
-        T a0 = 0, a1 = 0;
-#pragma unroll
-        for (int iz = 0; iz < P; ++iz) {
-          const T v = col[iz * R * R];
-          a0 += v * wz[s * P + iz];
-          a1 += v * dz[s * P + iz];
-        }
-        const T wxy = wx[s * P + ix] * wy[s * P + iy];
-        ph += wxy * a0;
-        gx += dx[s * P + ix] * wy[s * P + iy] * a0;
-        gy += wx[s * P + ix] * dy[s * P + iy] * a0;
-        gz += wxy * a1;
-      }
-      ph = warp_sum(ph);
-      gx = warp_sum(gx);
-      gy = warp_sum(gy);
-      gz = warp_sum(gz);
-      if (lane == 0) {
-        const int idx = pidx[s];
-        const T qv = pq[s];
-        const T pv = sc * ph + (T)(self_coef * (double)qv);
-        if (phi) phi[idx] = pv;
-        if (force) {
-          const T f0 = out_grad ? (T)1 : -qv;
-          force[3 * idx] = f0 * sc * gx;
-          force[3 * idx + 1] = f0 * sc * gy;
-          force[3 * idx + 2] = f0 * sc * gz;
-        }
-        eacc += (double)qv * (double)pv;
-      }
-    }
-    __syncthreads();
+  // software pipeline: the sorted index, cell and record of the next particle
+  // are loaded one round ahead
+  int e = wave * PPW + p;
+  int i_n = 0, pc_n = 0;
+  Quad<T> f_n = {0, 0, 0, 0};
+  if (e < total) {
+    const int r = find_range(rpre, nr, e);
+    i_n = rstart[r] + (e - rpre[r]);
+    pc_n = b.s_cell[i_n];
+    f_n = sfq[i_n];
   }
+  for (int base = wave * PPW; base < total; base += nwaves * PPW) {
+    const bool valid = e < total;
+    const int i = i_n, pc = pc_n;
+    const Quad<T> f = f_n;
+    e += nwaves * PPW;
+    if (e < total) {
+      const int r = find_range(rpre, nr, e);
+      i_n = rstart[r] + (e - rpre[r]);
+      pc_n = b.s_cell[i_n];
+      f_n = sfq[i_n];
+    }
+    const int lx = (pc & 1023) - x0, ly = ((pc >> 10) & 1023) - y0, lz = ((pc >> 20) & 1023) - z0;
+    T wz = 0, dwz = 0;
+    if (valid && iz < P) {
+      wp[iz] = weight_reg<T, P>(g, crow, iz, f.fx);
+      wp[P + iz] = dweight_reg<T, P>(g, drow, iz, f.fx);
+      wp[2 * P + iz] = weight_reg<T, P>(g, crow, iz, f.fy);
+      wp[3 * P + iz] = dweight_reg<T, P>(g, drow, iz, f.fy);
+      wz = weight_reg<T, P>(g, crow, iz, f.fz);
+      dwz = dweight_reg<T, P>(g, drow, iz, f.fz);
+    }
+    wave_sync();
+    T ph = 0, gx = 0, gy = 0, gz = 0;
+    if (valid && iz < P) {
+      T wx[P], dwx[P];
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        wx[k] = wp[k];
+        dwx[k] = wp[P + k];
+      }
+      T s00 = 0, s01 = 0, s10 = 0;
+      const T* plane = reg + (long long)(lz + iz) * RX * RY + (long long)ly * RX + lx;
+#pragma unroll
+      for (int iy = 0; iy < P; ++iy) {
+        const T* row = plane + iy * RX;
+        T r0 = 0, r1 = 0;
+#pragma unroll
+        for (int ix = 0; ix < P; ++ix) {
+          const T v = row[ix];
+          r0 += wx[ix] * v;
+          r1 += dwx[ix] * v;
+        }
+        const T wy = wp[2 * P + iy], dwy = wp[3 * P + iy];
+        s00 += wy * r0;
+        s01 += dwy * r0;
+        s10 += wy * r1;
+      }
+      ph = wz * s00;
+      gx = wz * s10;
+      gy = wz * s01;
+      gz = dwz * s00;
+    }
+    ph = group_sum<G2>(ph);
+    gx = group_sum<G2>(gx);
+    gy = group_sum<G2>(gy);
+    gz = group_sum<G2>(gz);
+    if (valid && iz == 0) {
+      const int idx = b.s_idx[i];
+      const T pv = sc * ph + (T)(self_coef * (double)f.q);
+      if (phi) phi[idx] = pv;
+      if (force) {
+        const T f0 = out_grad ? (T)1 : -f.q;
+        force[3 * idx] = f0 * sc * gx;
+        force[3 * idx + 1] = f0 * sc * gy;
+        force[3 * idx + 2] = f0 * sc * gz;
+      }
+      eacc += (double)f.q * (double)pv;
+    }
+    wave_sync();
+  }
+  eacc = warp_sum(eacc);
   if (lane == 0) ewave[wave] = eacc;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -891,8 +1147,11 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GridGeom g, EvalBuffers 
 
 template <typename T>
 size_t gather_lds(const GridGeom& g) {
-  const int R = g.tile + g.P - 1, P = g.P, m = g.nu + 1, C = g.chunk;
-  return sizeof(T) * ((size_t)R * R * R + 6 * C * P + 2 * P * m + C) + sizeof(int) * (4 * C);
+  const int P = g.P, m = g.nu + 1, nw = kBlock / 64;
+  const int G2 = P <= 2 ? 2 : (P <= 4 ? 4 : (P <= 8 ? 8 : 16));
+  const size_t R = (size_t)(g.T[0] + P - 1) * (g.T[1] + P - 1) * (g.T[2] + P - 1);
+  (void)m;
+  return sizeof(T) * (R + (size_t)nw * (64 / G2) * 4 * P) + sizeof(int) * (2 * kMaxOwnRanges + 4) + 64;
 }
 
 template <typename T, int P>

@@ -175,6 +175,7 @@ struct se_plan {
   std::vector<void*> allocs;
   std::vector<se::FftPass> passes;
   int ntiles = 0;
+  int nsbtot = 0;
   // tracing: HIP event pairs around launches of SE_PROFILE evaluations
   struct ProfRec {
     int site;
@@ -480,42 +481,46 @@ se_status se_plan_create(const se_params* params, long n_max, void* hip_stream, 
   g.alpha = p.shape;
   g.scale = 4.0 * kPi * I.h * I.h * I.h;
   {
-    // Largest tile (and particle chunk) whose spread and gather LDS fit, with
-    // at least 512 tiles when the grid allows it.
-    int best_t = 0, best_c = 0;
-    const int tiles[] = {16, 12, 8, 6, 4};
-    const int chunks[] = {64, 32, 16};
+    // Largest tile whose spread and gather LDS fit, with at least 512 tiles
+    // when the grid allows it.
+    static const int cands[][3] = {{16, 16, 16}, {32, 16, 8}, {16, 16, 8}, {16, 8, 8}, {8, 8, 8},
+                                   {8, 8, 4},    {8, 4, 4},   {4, 4, 4}};
+    int best = -1, best_chunk = 64;
     for (size_t budget : {pl->lds_limit, pl->lds_max}) {
-      for (int tt : tiles) {
-        if (p.tile > 0 && tt != p.tile) continue;
-        int cfit = 0;
-        for (int cc : chunks) {
-          g.tile = tt;
-          g.chunk = cc;
+      for (int c = 0; c < (int)(sizeof(cands) / sizeof(cands[0])); ++c) {
+        if (p.tile > 0 && !(cands[c][0] == p.tile && cands[c][1] == p.tile && cands[c][2] == p.tile)) continue;
+        for (int d = 0; d < 3; ++d) g.T[d] = cands[c][d];
+        int fit = 0;
+        for (int ch : {64, 32, 16}) {
+          g.chunk = ch;
           if (se::spread_lds_bytes(g, pl->f64) <= budget && se::gather_lds_bytes(g, pl->f64) <= budget) {
-            cfit = cc;
+            fit = ch;
             break;
           }
         }
-        if (!cfit) continue;
+        if (!fit) continue;
         long nt = 1;
-        for (int d = 0; d < 3; ++d) nt *= (g.G[d] + tt - 1) / tt;
-        best_t = tt;
-        best_c = cfit;
+        for (int d = 0; d < 3; ++d) nt *= (g.G[d] + g.T[d] - 1) / g.T[d];
+        best = c;
+        best_chunk = fit;
         if (p.tile > 0 || nt >= 512) break;
       }
-      if (best_t) break;
+      if (best >= 0) break;
     }
-    if (!best_t) {
+    if (best < 0) {
       delete pl;
       return SE_ERR_UNSUPPORTED;
     }
-    g.tile = best_t;
-    g.chunk = best_c;
+    g.chunk = best_chunk;
+    for (int d = 0; d < 3; ++d) g.T[d] = cands[best][d];
   }
-  I.tile = g.tile;
-  for (int d = 0; d < 3; ++d) g.nt[d] = (g.G[d] + g.tile - 1) / g.tile;
+  for (int d = 0; d < 3; ++d) I.tile[d] = g.T[d];
+  for (int d = 0; d < 3; ++d) {
+    g.nt[d] = (g.G[d] + g.T[d] - 1) / g.T[d];
+    g.nsb[d] = (g.G[d] + se::kSB - 1) / se::kSB;
+  }
   pl->ntiles = g.nt[0] * g.nt[1] * g.nt[2];
+  pl->nsbtot = g.nsb[0] * g.nsb[1] * g.nsb[2];
 
   hipStream_t st = (hipStream_t)hip_stream;
   se_status rc = SE_OK;
@@ -547,21 +552,23 @@ se_status se_plan_create(const se_params* params, long n_max, void* hip_stream, 
     const size_t esz = pl->f64 ? 8 : 4;
     const long nm = std::max(1L, n_max);
     const int nblk = (int)((nm + se::kBlock - 1) / se::kBlock);
-    b.tile_count = (int*)pl->dalloc(sizeof(int) * pl->ntiles);
-    b.tile_start = (int*)pl->dalloc(sizeof(int) * (pl->ntiles + 1));
-    b.tile_cursor = (int*)pl->dalloc(sizeof(int) * pl->ntiles);
-    b.p_tile = (int*)pl->dalloc(sizeof(int) * nm);
+    b.sb_count = (int*)pl->dalloc(sizeof(int) * pl->nsbtot);
+    b.sb_start = (int*)pl->dalloc(sizeof(int) * (pl->nsbtot + 1));
+    b.sb_cursor = (int*)pl->dalloc(sizeof(int) * pl->nsbtot);
+    b.p_key = (int*)pl->dalloc(sizeof(int) * nm);
     b.p_cell = (int*)pl->dalloc(sizeof(int) * nm);
     b.p_frac = pl->dalloc(4 * esz * nm);
     b.s_cell = (int*)pl->dalloc(sizeof(int) * nm);
     b.s_idx = (int*)pl->dalloc(sizeof(int) * nm);
     b.s_fq = pl->dalloc(4 * esz * nm);
     b.qpart = (double*)pl->dalloc(sizeof(double) * 3 * nblk);
+    b.bsum = (int*)pl->dalloc(sizeof(int) * se::scan_blocks(g));
+    b.stage = pl->dalloc(esz * (size_t)pl->ntiles * (g.T[0] + p.P - 1) * (g.T[1] + p.P - 1) * (g.T[2] + p.P - 1));
     b.epart = (double*)pl->dalloc(sizeof(double) * pl->ntiles);
     b.red = (double*)pl->dalloc(sizeof(double) * 4);
     b.status = (int*)pl->dalloc(sizeof(int));
     b.grid = pl->dalloc(esz * (size_t)g.G[0] * g.G[1] * g.G[2]);
-    if (!b.tile_count || !b.tile_start || !b.tile_cursor || !b.p_tile || !b.p_cell || !b.p_frac ||
+    if (!b.sb_count || !b.sb_start || !b.sb_cursor || !b.p_key || !b.p_cell || !b.p_frac || !b.bsum || !b.stage ||
         !b.s_cell || !b.s_idx || !b.s_fq || !b.qpart || !b.epart || !b.red || !b.status || !b.grid) {
       rc = SE_ERR_NOMEM;
       break;
@@ -955,26 +962,32 @@ se_status se_eval(se_plan* plan, long N, const void* xyz, const void* q, void* p
   const int P = g.P, nu = std::max(g.nu, 5);
 
   begin();
-  if (hipMemsetAsync(b.tile_count, 0, sizeof(int) * plan->ntiles, st) != hipSuccess) return SE_ERR_DEVICE;
+  if (hipMemsetAsync(b.sb_count, 0, sizeof(int) * plan->nsbtot, st) != hipSuccess) return SE_ERR_DEVICE;
   if (se::launch_bin(g, b, N, xyz, q, (flags & SE_IN_F32) != 0, f64, nblk, st) != hipSuccess) return SE_ERR_DEVICE;
   end(0, N * 4.0 * in_e, 0.0);
   begin();
   if (se::launch_scan(g, b, nblk, plan->p.D >= 1 && !(flags & SE_ALLOW_NONNEUTRAL), st) != hipSuccess)
     return SE_ERR_DEVICE;
-  end(1, plan->ntiles * 8.0, 0.0);
+  end(1, plan->nsbtot * 12.0, 0.0);
   begin();
   if (se::launch_scatter(g, b, N, f64, st) != hipSuccess) return SE_ERR_DEVICE;
   end(2, N * 2.0 * (8.0 + 4.0 * re), 0.0);
   begin();
   if (se::launch_spread(g, b, f64, st) != hipSuccess) return SE_ERR_DEVICE;
   end(3, N * 4.0 * re + G * re, N * 2.0 * (3.0 * P * nu + P * P + (double)P * P * P));
+  begin();
+  if (se::launch_fold(g, b, f64, st) != hipSuccess) return SE_ERR_DEVICE;
+  {
+    const double R3 = (double)(g.T[0] + P - 1) * (g.T[1] + P - 1) * (g.T[2] + P - 1);
+    end(4, plan->ntiles * R3 * re + G * re, plan->ntiles * R3);
+  }
   for (size_t i = 0; i < plan->passes.size(); ++i) {
     const se::FftPass& ps = plan->passes[i];
     begin();
     if (se::launch_fft(ps, f64, st) != hipSuccess) return SE_ERR_DEVICE;
-    end(4 + (int)i, ps.alg_bytes, ps.alg_flops);
+    end(5 + (int)i, ps.alg_bytes, ps.alg_flops);
   }
-  const int s_gather = 4 + (int)plan->passes.size();
+  const int s_gather = 5 + (int)plan->passes.size();
   if (phi || force || energy) {
     begin();
     if (se::launch_gather(g, b, f64, phi, force, (flags & SE_OUT_GRAD) ? 1 : 0, self_coef, st) != hipSuccess)
@@ -995,7 +1008,7 @@ se_status se_plan_profile(se_plan* plan, void* hip_stream, se_stage_record* out,
                           int reset) {
   if (!plan || !n || (cap > 0 && !out)) return SE_ERR_ARG;
   if (hipStreamSynchronize((hipStream_t)hip_stream) != hipSuccess) return SE_ERR_DEVICE;
-  const int nsites = 6 + (int)plan->passes.size();
+  const int nsites = 7 + (int)plan->passes.size();
   std::vector<se_stage_record> agg(nsites);
   std::vector<double> bsum(nsites, 0.0), fsum(nsites, 0.0);
   for (int s = 0; s < nsites; ++s) {
@@ -1007,10 +1020,11 @@ se_status se_plan_profile(se_plan* plan, void* hip_stream, se_stage_record* out,
     else if (s == 1) nm = "scan";
     else if (s == 2) nm = "scatter";
     else if (s == 3) nm = "spread";
-    else if (s < 4 + (int)plan->passes.size()) {
-      std::snprintf(buf, sizeof(buf), "%s_%d", kFftNames[plan->passes[s - 4].kind], s - 3);
+    else if (s == 4) nm = "fold";
+    else if (s < 5 + (int)plan->passes.size()) {
+      std::snprintf(buf, sizeof(buf), "%s_%d", kFftNames[plan->passes[s - 5].kind], s - 4);
       nm = buf;
-    } else if (s == 4 + (int)plan->passes.size()) nm = "gather";
+    } else if (s == 5 + (int)plan->passes.size()) nm = "gather";
     else nm = "energy";
     std::snprintf(r.name, sizeof(r.name), "%s", nm);
   }

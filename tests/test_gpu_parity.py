@@ -63,8 +63,10 @@ CASES = [
     (3, 32, 8, 1000, "pkb", 0),
     (3, 24, 6, 257, "gaussian", 4),
     (3, 20, 8, 1, "pkb", 0),
+    (3, 20, 12, 300, "pkb", 4),       # stencil halo reaches two tiles away
+    (1, 20, 12, 200, "pkb", 4),
     (2, 24, 8, 500, "pkb", 0),
-    (2, 20, 6, 333, "gaussian", 6),
+    (2, 20, 6, 333, "gaussian", 8),
     (1, 24, 8, 500, "pkb", 0),
     (1, 16, 6, 129, "gaussian", 4),
     (0, 24, 8, 400, "pkb", 0),

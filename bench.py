@@ -110,12 +110,171 @@ def cpu_baseline(cfg, x, q, budget_s=15.0):
                       f"{N} sources, potential and gradient, {dt:.1f} s"}, tg, phi, grad
 
 
+def batch_cpu_baseline(systems, budget_s=15.0, per_sys_targets=256):
+    """The direct FP64 oracle on the host cores for sampled targets of the
+    first systems of the batch, until the time budget is used."""
+    import numpy as np
+    from oracle import direct
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t_tot, n_tot, used, res = 0.0, 0, 0, []
+    for k, s in enumerate(systems):
+        T = min(per_sys_targets, s["N"])
+        tg = np.sort(np.random.default_rng(100 + k).choice(s["N"], size=T, replace=False))
+        t0 = time.perf_counter()
+        phi, grad = direct.kspace(s["D"], s["L"], s["xi"], s["x"], s["q"], targets=tg)
+        t_tot += time.perf_counter() - t0
+        n_tot += T
+        used += 1
+        res.append((k, tg, phi, grad))
+        if t_tot > budget_s:
+            break
+    return {"value": n_tot / t_tot, "unit": "particles/s", "cores": cores, "kind": "oracle",
+            "sample": f"direct FP64 k-space sums (closed forms, potential and gradient) for {n_tot} "
+                      f"targets: up to {per_sys_targets} per system of the first {used} systems, "
+                      f"each against all of its sources, {t_tot:.1f} s"}, res
+
+
+def main_batch(args):
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    from paper_1712_04732_amd import SpectralEwald, SpectralEwaldBatch, params_for_tolerance
+    from paper_1712_04732_amd import _lib
+
+    cfg = wl.BATCH
+    systems = wl.batch_systems()
+    dev = torch.device("cuda:0")
+    N = [s["N"] for s in systems]
+    tot = sum(N)
+    p32 = [params_for_tolerance(s["D"], s["L"], s["xi"], float((s["q"] ** 2).sum()), cfg["tol_rel"],
+                                cfg["P"], cfg["window"], "f32") for s in systems]
+    p64 = [params_for_tolerance(s["D"], s["L"], s["xi"], float((s["q"] ** 2).sum()), cfg["tol_rel"],
+                                cfg["P"], cfg["window"], "f64") for s in systems]
+    x = torch.tensor(np.concatenate([s["x"] for s in systems]), device=dev)
+    q = torch.tensor(np.concatenate([s["q"] for s in systems]), device=dev)
+    t0 = time.perf_counter()
+    b32 = SpectralEwaldBatch(p32, N)
+    t_plan = time.perf_counter() - t0
+    print(f"bench: batch of {len(N)} systems, sum N = {tot}, D counts "
+          f"{np.bincount([s['D'] for s in systems], minlength=4).tolist()}, M {min(p.M for p in p32)}.."
+          f"{max(p.M for p in p32)}, plan {t_plan:.1f} s",
+          file=sys.stderr, flush=True)
+
+    out32 = (torch.empty(tot, dtype=torch.float32, device=dev), torch.empty((tot, 3), dtype=torch.float32, device=dev),
+             torch.empty(len(N), dtype=torch.float64, device=dev))
+    b32(x, q, out=out32, check=True)
+    for _ in range(args.warmup):
+        b32(x, q, out=out32, check=False)
+    torch.cuda.synchronize()
+    b32.profile(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b32(x, q, out=out32, check=False, profile=True)
+    torch.cuda.synchronize()
+    ms32 = (time.perf_counter() - t0) * 1e3 / args.steps
+    rec = b32.profile(reset=True)
+    print(f"bench: FP32 batched {ms32:.3f} ms/step", file=sys.stderr, flush=True)
+
+    # the plain FP64 path: one plan per system, evaluated one after another
+    plans = []
+    for k, s in enumerate(systems):
+        p = p64[k]
+        plans.append(SpectralEwald(s["D"], s["L"], s["xi"], p.M, cfg["P"], window=cfg["window"], prec="f64",
+                                   n_max=s["N"], s=p.s, n_l=p.n_l))
+    offs = np.concatenate([[0], np.cumsum(N)])
+    out64 = [(torch.empty(n, dtype=torch.float64, device=dev), torch.empty((n, 3), dtype=torch.float64, device=dev),
+              torch.empty((), dtype=torch.float64, device=dev)) for n in N]
+    xs = [x[offs[k]:offs[k + 1]] for k in range(len(N))]
+    qs = [q[offs[k]:offs[k + 1]] for k in range(len(N))]
+    for k, pl in enumerate(plans):
+        pl(xs[k], qs[k], out=out64[k], check=True)
+    torch.cuda.synchronize()
+    steps64 = max(1, args.steps // 2)
+    t0 = time.perf_counter()
+    for _ in range(steps64):
+        for k, pl in enumerate(plans):
+            pl(xs[k], qs[k], out=out64[k], check=False)
+    torch.cuda.synchronize()
+    ms64 = (time.perf_counter() - t0) * 1e3 / steps64
+    print(f"bench: FP64 plain loop {ms64:.3f} ms/step", file=sys.stderr, flush=True)
+
+    phi32 = out32[0].double().cpu().numpy()
+    f32 = out32[1].double().cpu().numpy()
+    e32 = out32[2].cpu().numpy()
+    phi64 = np.concatenate([o[0].cpu().numpy() for o in out64])
+    f64 = np.concatenate([o[1].cpu().numpy() for o in out64])
+    e64 = np.array([float(o[2]) for o in out64])
+    err = {"phi_f32_vs_f64": rel_rms(phi32, phi64), "force_f32_vs_f64": rel_rms(f32, f64),
+           "energy_f32_vs_f64_max": float(np.max(np.abs(e32 - e64) / np.abs(e64)))}
+
+    t = rec["ms_avg"] * 1e-3
+    bw, fl = rec["bytes"] / t, rec["flops"] / t
+    f_hbm, f_alu = bw / HBM_PEAK, fl / ALU_PEAK["f32"]
+    if f_hbm >= f_alu:
+        roof = {"bound": "hbm", "achieved": bw / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": f_hbm}
+    else:
+        roof = {"bound": "alu", "achieved": fl / 1e12, "peak": ALU_PEAK["f32"] / 1e12, "unit": "TFLOP/s",
+                "frac": f_alu}
+    roof.update({"traffic": None, "kernel": "batch_all_stages (14 launches)", "ms_avg": rec["ms_avg"],
+                 "alg_bytes": rec["bytes"], "alg_flops": rec["flops"]})
+
+    result = {
+        "metric": METRIC,
+        "value": tot / (ms32 * 1e-3),
+        "unit": "particles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms32,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "C5_batch", "n_sys": len(N), "sum_N": tot, "P": cfg["P"], "window": cfg["window"],
+                   "tol_rel": cfg["tol_rel"], "xi": "1.2 N^(1/3)/L", "charges": cfg["charges"],
+                   "outputs": "potential+force+energy", "launch": "one launch per stage over all systems"},
+        "fp64_plain_value": tot / (ms64 * 1e-3),
+        "fp64_plain_ms_per_step": ms64,
+        "speedup_vs_fp64_plain": ms64 / ms32,
+        "roofline": roof,
+        "errors": err,
+    }
+    if not args.no_cpu_baseline:
+        cb, res = batch_cpu_baseline(systems)
+        result["cpu_baseline"] = cb
+        e_phi32, e_phi64, e_f32, ref_n = 0.0, 0.0, 0.0, 0.0
+        for k, tg, phi_o, grad_o in res:
+            sl = offs[k] + tg
+            e_phi32 += float(np.sum((phi32[sl] - phi_o) ** 2))
+            e_phi64 += float(np.sum((phi64[sl] - phi_o) ** 2))
+            e_f32 += float(np.sum((f32[sl] + systems[k]["q"][tg, None] * grad_o) ** 2))
+            ref_n += float(np.sum(phi_o ** 2))
+        err["phi_f32_vs_oracle"] = (e_phi32 / ref_n) ** 0.5
+        err["phi_f64_vs_oracle"] = (e_phi64 / ref_n) ** 0.5
+    print(json.dumps(result), flush=True)
+
+
+def _traffic(name):
+    tpath = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(tpath):
+        return None
+    try:
+        ent = json.load(open(tpath)).get(name)
+        if ent and ent.get("source_sha") == _source_sha():
+            return ent["bytes_per_launch"]
+    except Exception:
+        return None
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="C2_0P")
+    ap.add_argument("--workload", default="C5_batch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -124,6 +283,8 @@ def main():
               "MI355X; multi-GPU sharding is a design note, not a measured configuration.",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "C5_batch":
+        return main_batch(args)
 
     import numpy as np
     import torch

@@ -116,6 +116,17 @@ typedef struct se_plan se_plan;
 se_status se_params_default(int D, double L, double xi, int M, int P, se_window window,
                             double Q, double tol, se_precision prec, se_params* out);
 
+/* The parameter recipe of Section 6 for a relative tolerance tol_rel (an
+ * absolute rms tolerance tol_rel * B, B = sqrt(Q) f_c(xi L)/L of Section 5.2)
+ * at a given xi and window support P: M is the smallest even 7-smooth grid
+ * size whose Kolafa-Perram k-space estimate, Eq. (KP_fourier_space), meets the
+ * tolerance and for which P <= f_W(M/(xi L)) (no error pollution, Eq.
+ * error_pollution); the other fields as se_params_default.
+ * Errors: SE_ERR_ARG for out == NULL; SE_ERR_PARAM for invalid inputs or when
+ * no M below 4096 qualifies. */
+se_status se_params_for_tolerance(int D, double L, double xi, double Q, double tol_rel, int P,
+                                  se_window window, se_precision prec, se_params* out);
+
 /* Validate the parameters, derive the grids (Section 3.3: Mt = 2 ceil((M +
  * lambda P)/2); Mt, s0 Mt and s Mt are rounded up to even integers with prime
  * factors 2, 3, 5, 7 only), build the FP64 tables (PKB coefficients by the
@@ -174,6 +185,47 @@ se_status se_plan_profile(se_plan* plan, void* hip_stream, se_stage_record* out,
 
 /* Release all device memory of the plan.  NULL is accepted. */
 se_status se_plan_destroy(se_plan* plan);
+
+/* ---- Batched evaluation: many independent systems, one launch per stage ----
+ * Each system s has its own parameters params[s] (any D, L, xi, M) and N[s]
+ * charges; all systems share P (4, 6, 8, 10 or 12), the window and the
+ * precision.  Positions, charges, potentials and forces of all systems are
+ * concatenated in system order (system s starts at sum_{r<s} N[r]).  One
+ * evaluation runs Algorithm 4 for every system: each stage of the path (bin,
+ * scan, scatter, spread, fold, five transform passes, gather, energy) is one
+ * launch whose workgroups are the work items (particle blocks, tiles, pencil
+ * groups) of all systems, so the whole batch costs 14 launches.
+ * Errors: SE_ERR_ARG; SE_ERR_UNSUPPORTED when P, window or precision differ
+ * between systems or P is not instantiated for batches; SE_ERR_PARAM,
+ * SE_ERR_NOMEM, SE_ERR_DEVICE as se_plan_create. */
+typedef struct se_batch_plan se_batch_plan;
+
+se_status se_batch_plan_create(const se_params* params, const long* N, int n_sys, void* hip_stream,
+                               se_batch_plan** out);
+
+/* Derived sizes of system 'sys' (host outputs, each may be NULL);
+ * *reserved receives 0. */
+se_status se_batch_plan_get_info(const se_batch_plan* plan, int sys, se_plan_info* info,
+                                 long* n_particles, int* reserved);
+
+/* One batched evaluation.  xyz, q: device, concatenated as above (float64, or
+ * float32 with SE_IN_F32); phi (sum N), force (sum N x 3): device, compute
+ * precision, or NULL; energy: device, n_sys float64 energies, or NULL.  Flags
+ * as for se_eval (SE_PROFILE times the whole evaluation with one event pair). */
+se_status se_eval_batch(se_batch_plan* plan, const void* xyz, const void* q, void* phi, void* force,
+                        double* energy, unsigned flags, void* hip_stream);
+
+/* Aggregate timing of the SE_PROFILE batched evaluations since the last reset
+ * into one record (host 'out'); bytes and flops are the algorithmic counts of
+ * one launch summed over systems and stages. */
+se_status se_batch_plan_profile(se_batch_plan* plan, void* hip_stream, se_stage_record* out, int reset);
+
+/* Wait for the stream, report and clear the device status of every system
+ * (the most severe code wins). */
+se_status se_batch_get_device_status(se_batch_plan* plan, void* hip_stream);
+
+/* Release the batch plan and its sub-plans.  NULL is accepted. */
+se_status se_batch_plan_destroy(se_batch_plan* plan);
 
 /* Static English text of a status code. */
 const char* se_status_string(se_status s);

@@ -5,6 +5,8 @@ the C ABI of include/se.h).  This package holds the ctypes binding (_lib), the
 torch-facing plan and autograd adjoint (api), and the build script (build_lib).
 """
 from . import _lib
-from .api import SEEnergy, SEPotential, SpectralEwald, self_potential
+from .api import (SEEnergy, SEPotential, SpectralEwald, SpectralEwaldBatch, params_for_tolerance,
+                  self_potential)
 
-__all__ = ["SpectralEwald", "SEEnergy", "SEPotential", "self_potential", "_lib"]
+__all__ = ["SpectralEwald", "SpectralEwaldBatch", "SEEnergy", "SEPotential", "params_for_tolerance",
+           "self_potential", "_lib"]

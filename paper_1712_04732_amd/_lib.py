@@ -112,6 +112,19 @@ _SIGS = {
     "se_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "se_plan_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(se_stage_record),
                                        ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
+    "se_params_for_tolerance": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                               ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                               ctypes.POINTER(se_params)]),
+    "se_batch_plan_create": (ctypes.c_int, [ctypes.POINTER(se_params), ctypes.POINTER(ctypes.c_long), ctypes.c_int,
+                                            ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "se_batch_plan_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(se_plan_info),
+                                              ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_int)]),
+    "se_eval_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint, ctypes.c_void_p]),
+    "se_batch_plan_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(se_stage_record),
+                                             ctypes.c_int]),
+    "se_batch_get_device_status": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "se_batch_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
 }
 
 
@@ -185,6 +198,50 @@ def se_plan_profile(plan, stream, reset=True):
         out.append(dict(name=r.name.decode(), launches=r.launches, ms_total=r.ms_total,
                         ms_avg=r.ms_total / max(r.launches, 1), bytes=r.bytes, flops=r.flops))
     return out
+
+
+def se_params_for_tolerance(D, L, xi, Q, tol_rel, P, window, prec):
+    out = se_params()
+    _check(load().se_params_for_tolerance(int(D), float(L), float(xi), float(Q), float(tol_rel), int(P),
+                                          int(window), int(prec), ctypes.byref(out)), "se_params_for_tolerance")
+    return out
+
+
+def se_batch_plan_create(params, N, stream=0):
+    n = len(params)
+    arr = (se_params * n)(*params)
+    narr = (ctypes.c_long * n)(*[int(v) for v in N])
+    plan = ctypes.c_void_p()
+    _check(load().se_batch_plan_create(arr, narr, n, ctypes.c_void_p(stream), ctypes.byref(plan)),
+           "se_batch_plan_create")
+    return plan
+
+
+def se_batch_plan_get_info(plan, sys):
+    info = se_plan_info()
+    n = ctypes.c_long()
+    blocks = ctypes.c_int()
+    _check(load().se_batch_plan_get_info(plan, int(sys), ctypes.byref(info), ctypes.byref(n), ctypes.byref(blocks)),
+           "se_batch_plan_get_info")
+    return info, n.value, blocks.value
+
+
+def se_eval_batch(plan, xyz_ptr, q_ptr, phi_ptr, force_ptr, energy_ptr, flags, stream) -> int:
+    return load().se_eval_batch(plan, ctypes.c_void_p(xyz_ptr), ctypes.c_void_p(q_ptr), ctypes.c_void_p(phi_ptr),
+                                ctypes.c_void_p(force_ptr), ctypes.c_void_p(energy_ptr), ctypes.c_uint(flags),
+                                ctypes.c_void_p(stream))
+
+
+def se_batch_plan_profile(plan, stream, reset=True):
+    r = se_stage_record()
+    _check(load().se_batch_plan_profile(plan, ctypes.c_void_p(stream), ctypes.byref(r), int(reset)),
+           "se_batch_plan_profile")
+    return dict(name=r.name.decode(), launches=r.launches, ms_total=r.ms_total,
+                ms_avg=r.ms_total / max(r.launches, 1), bytes=r.bytes, flops=r.flops)
+
+
+def se_batch_plan_destroy(plan) -> int:
+    return load().se_batch_plan_destroy(plan)
 
 
 def se_plan_destroy(plan) -> int:

@@ -120,6 +120,101 @@ class SpectralEwald:
     __call__ = evaluate
 
 
+def _params(D, L_box, xi, M, P, window="pkb", prec="f64", Q=None, tol=None, s=None, n_l=None, tile=0):
+    w = _WINDOWS[window]
+    pr = _PRECS[prec]
+    if Q is not None and tol is not None:
+        p = L.se_params_default(D, L_box, xi, M, P, w, Q, tol, pr)
+    else:
+        p = L.se_params()
+        p.D, p.L, p.xi, p.M, p.P, p.window, p.prec = D, L_box, xi, M, P, w, pr
+        p.n_l = -1
+    if s is not None:
+        p.s = s
+    if n_l is not None:
+        p.n_l = n_l
+    p.tile = tile
+    return p
+
+
+def params_for_tolerance(D, L_box, xi, Q, tol_rel, P=8, window="pkb", prec="f32"):
+    """Section 6 recipe: grid size and AFT parameters for a relative tolerance."""
+    return L.se_params_for_tolerance(D, L_box, xi, Q, tol_rel, P, _WINDOWS[window], _PRECS[prec])
+
+
+class SpectralEwaldBatch:
+    """Many independent systems evaluated together: one launch per stage of
+    the path over the work items of all systems.
+
+    params: list of se_params (one per system, same P, window and precision);
+    N: particles per system.  Inputs and outputs are concatenated in system
+    order."""
+
+    def __init__(self, params, N):
+        if not torch.cuda.is_available():
+            raise RuntimeError("SpectralEwaldBatch needs a HIP device")
+        L.load()
+        self.params = list(params)
+        self.N = [int(n) for n in N]
+        self.n_sys = len(self.N)
+        self.total = sum(self.N)
+        self.dtype = torch.float64 if self.params[0].prec == L.SE_F64 else torch.float32
+        self._plan = L.se_batch_plan_create(self.params, self.N, _stream())
+
+    def info(self, sys):
+        return L.se_batch_plan_get_info(self._plan, sys)[0]
+
+    def __del__(self):
+        plan = getattr(self, "_plan", None)
+        if plan is not None and plan.value:
+            try:
+                L.se_batch_plan_destroy(plan)
+            except Exception:
+                pass
+            self._plan = None
+
+    def profile(self, reset=True):
+        return L.se_batch_plan_profile(self._plan, _stream(), reset)
+
+    def evaluate(self, x, q, *, phi=True, force=True, energy=True, add_self=False, out_grad=False,
+                 check=True, allow_nonneutral=False, profile=False, out=None):
+        if x.shape != (self.total, 3) or q.shape != (self.total,):
+            raise ValueError("x must be (sum N, 3) and q (sum N,)")
+        if x.dtype != q.dtype or not (x.is_cuda and q.is_cuda):
+            raise ValueError("x and q must be device tensors of one dtype")
+        x = x.contiguous()
+        q = q.contiguous()
+        dev = x.device
+        if out is not None:
+            out_phi, out_f, out_e = out
+        else:
+            out_phi = torch.empty(self.total, dtype=self.dtype, device=dev) if phi else None
+            out_f = torch.empty((self.total, 3), dtype=self.dtype, device=dev) if force else None
+            out_e = torch.empty(self.n_sys, dtype=torch.float64, device=dev) if energy else None
+        flags = 0
+        if x.dtype == torch.float32:
+            flags |= L.SE_IN_F32
+        if add_self:
+            flags |= L.SE_ADD_SELF
+        if out_grad:
+            flags |= L.SE_OUT_GRAD
+        if check:
+            flags |= L.SE_SYNC_CHECK
+        if allow_nonneutral:
+            flags |= L.SE_ALLOW_NONNEUTRAL
+        if profile:
+            flags |= L.SE_PROFILE
+        st = L.se_eval_batch(self._plan, x.data_ptr(), q.data_ptr(),
+                             out_phi.data_ptr() if out_phi is not None else 0,
+                             out_f.data_ptr() if out_f is not None else 0,
+                             out_e.data_ptr() if out_e is not None else 0, flags, _stream())
+        if st != L.SE_OK:
+            raise L.SEError(st, "se_eval_batch")
+        return out_phi, out_f, out_e
+
+    __call__ = evaluate
+
+
 class SEEnergy(torch.autograd.Function):
     """E = 1/2 sum_m q_m phi_m (k-space part, plus the self energy when
     add_self).  Backward: dE/dq = phi, dE/dx_m = q_m grad phi(x_m), the

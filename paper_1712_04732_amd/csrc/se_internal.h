@@ -16,6 +16,8 @@ constexpr int kMaxNu = 12;
 constexpr int kBlock = 256;      // threads per block of every kernel
 constexpr int kSB = 4;           // sub-bin edge in grid cells (particle sort key)
 constexpr int kMaxOwnRanges = 256;  // sub-bin rows of one tile ((T/kSB)^2 <= 256 for T <= 64)
+// Most periodic images of tile boxes one fold block sums over in a direction.
+constexpr int kMaxFoldImages = 16;
 
 // Green's-function modes of the fused scaling pass (Eq. scale).
 enum GMode : int {
@@ -103,6 +105,38 @@ struct EvalBuffers {
   void* grid;         // real grid G[0]*G[1]*G[2]
 };
 
+// One system of a batch: its geometry, buffers and transform passes, and
+// where its particles sit in the concatenated input/output arrays.
+constexpr int kPasses = 5;
+struct SysDesc {
+  GridGeom g;
+  EvalBuffers b;
+  FftPass pass[kPasses];
+  long long N;        // particles of the system
+  long long off;      // index of its first particle in the concatenated arrays
+  int nblk_bin;       // bin / scatter work items
+  int nscan;          // scan work items
+  int ntiles;         // spread / fold / gather work items
+  int check_neutral;  // D >= 1
+  double self_coef;   // -2 xi / sqrt(pi)
+};
+
+// Inputs and outputs of a batched evaluation (concatenated over systems).
+struct BatchIO {
+  const void* xyz;
+  const void* q;
+  void* phi;
+  void* force;
+  double* energy;     // one per system
+  int in_f32, out_grad, add_self, allow_nonneutral;
+};
+
+// Stages of a batched evaluation, in order; one launch per stage.
+enum BatchStage : int {
+  BS_ZERO = 0, BS_BIN, BS_SCAN1, BS_SCAN2, BS_SCATTER, BS_SPREAD, BS_FOLD,
+  BS_FFT0, BS_FFT1, BS_FFT2, BS_FFT3, BS_FFT4, BS_GATHER, BS_ENERGY, BS_COUNT
+};
+
 // Launchers (se_kernels.hip).  All enqueue on 'st' and return the HIP error.
 hipError_t launch_bin(const GridGeom& g, const EvalBuffers& b, long N, const void* xyz,
                       const void* q, bool in_f32, bool f64, int nblk, hipStream_t st);
@@ -120,6 +154,12 @@ size_t fft_lds_bytes(const FftPass& p, bool f64);
 size_t spread_lds_bytes(const GridGeom& g, bool f64);
 size_t gather_lds_bytes(const GridGeom& g, bool f64);
 int scan_blocks(const GridGeom& g);
+
+// Batched evaluation: one launch per stage over the work items of all systems.
+// off: device table [BS_COUNT][nsys + 1] of work-item prefix sums per stage;
+// items: host array of the stage totals.
+hipError_t launch_batch(int P, bool f64, const SysDesc* sys, int nsys, const int* off, const int* items,
+                        const BatchIO& io, size_t lds, hipStream_t st);
 
 // 0P precompute helpers (FP64).
 hipError_t launch_g0p_fill(double* buf, int n0, double h, double R, hipStream_t st);

@@ -260,9 +260,8 @@ __device__ __forceinline__ T scale_factor(const FftClass& C, int b0, int b1, int
 }
 
 template <typename T, int KIND>
-__global__ __launch_bounds__(kBlock) void fft_kernel(const FftPass P) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int4 it = P.items[blockIdx.x];
+__device__ void stage_fft(const FftPass& P, int item, unsigned char* smem) {
+  const int4 it = P.items[item];
   const FftClass& C = P.cls[it.x];
   const int n = C.n, B = P.B, cnt = it.w, b0s = it.y, b1 = it.z;
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem);
@@ -344,6 +343,12 @@ __global__ __launch_bounds__(kBlock) void fft_kernel(const FftPass P) {
   }
 }
 
+template <typename T, int KIND>
+__global__ __launch_bounds__(kBlock) void fft_kernel(const FftPass P) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  stage_fft<T, KIND>(P, blockIdx.x, smem);
+}
+
 size_t fft_lds_bytes(const FftPass& p, bool f64) {
   const size_t c = f64 ? 16 : 8;
   return c * ((size_t)p.nmax + 2 * (size_t)p.B * p.nmax);
@@ -403,10 +408,9 @@ __device__ __forceinline__ int sb_key(const GridGeom& g, int cx_, int cy, int cz
 }
 
 template <typename Tin, typename T>
-__global__ __launch_bounds__(kBlock) void bin_kernel(GridGeom g, EvalBuffers b, long N,
-                                                     const Tin* __restrict__ xyz,
-                                                     const Tin* __restrict__ q) {
-  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ void stage_bin(const GridGeom& g, const EvalBuffers& b, long N, const Tin* __restrict__ xyz,
+                          const Tin* __restrict__ q, int item) {
+  const long n = (long)item * blockDim.x + threadIdx.x;
   double sq = 0.0, sa = 0.0, s2 = 0.0;
   if (n < N) {
     double qn = (double)q[n];
@@ -476,8 +480,15 @@ __global__ __launch_bounds__(kBlock) void bin_kernel(GridGeom g, EvalBuffers b, 
   if (threadIdx.x < 3) {
     double s = 0.0;
     for (int i = 0; i < kBlock / 64; ++i) s += red[threadIdx.x][i];
-    b.qpart[3 * blockIdx.x + threadIdx.x] = s;
+    b.qpart[3 * item + threadIdx.x] = s;
   }
+}
+
+template <typename Tin, typename T>
+__global__ __launch_bounds__(kBlock) void bin_kernel(GridGeom g, EvalBuffers b, long N,
+                                                     const Tin* __restrict__ xyz,
+                                                     const Tin* __restrict__ q) {
+  stage_bin<Tin, T>(g, b, N, xyz, q, blockIdx.x);
 }
 
 hipError_t launch_bin(const GridGeom& g, const EvalBuffers& b, long N, const void* xyz,
@@ -504,9 +515,9 @@ hipError_t launch_bin(const GridGeom& g, const EvalBuffers& b, long N, const voi
 // FP64 charge sums and applies the neutrality check.
 constexpr int kScanBlock = 1024;
 
-__global__ __launch_bounds__(kBlock) void scan1_kernel(GridGeom g, EvalBuffers b) {
+__device__ void stage_scan1(const GridGeom& g, const EvalBuffers& b, int item) {
   const int n = g.nsb[0] * g.nsb[1] * g.nsb[2];
-  const int base = blockIdx.x * kScanBlock;
+  const int base = item * kScanBlock;
   constexpr int K = kScanBlock / kBlock;
   int v[K];
   int s = 0;
@@ -532,16 +543,20 @@ __global__ __launch_bounds__(kBlock) void scan1_kernel(GridGeom g, EvalBuffers b
     if (i < n) b.sb_start[i] = run;
     run += v[k];
   }
-  if (threadIdx.x == kBlock - 1) b.bsum[blockIdx.x] = part[kBlock - 1];
+  if (threadIdx.x == kBlock - 1) b.bsum[item] = part[kBlock - 1];
 }
 
-__global__ __launch_bounds__(kBlock) void scan2_kernel(GridGeom g, EvalBuffers b, int nblk_bin,
-                                                       int check_neutral) {
+__global__ __launch_bounds__(kBlock) void scan1_kernel(GridGeom g, EvalBuffers b) {
+  stage_scan1(g, b, blockIdx.x);
+}
+
+__device__ void stage_scan2(const GridGeom& g, const EvalBuffers& b, int nblk_bin, int check_neutral,
+                            int item, int nscan) {
   const int n = g.nsb[0] * g.nsb[1] * g.nsb[2];
   __shared__ int ps[kBlock];
   __shared__ double dq[3][kBlock];
   int o = 0;
-  for (int j = threadIdx.x; j < (int)blockIdx.x; j += kBlock) o += b.bsum[j];
+  for (int j = threadIdx.x; j < item; j += kBlock) o += b.bsum[j];
   ps[threadIdx.x] = o;
   __syncthreads();
   for (int off = kBlock / 2; off > 0; off >>= 1) {
@@ -549,7 +564,7 @@ __global__ __launch_bounds__(kBlock) void scan2_kernel(GridGeom g, EvalBuffers b
     __syncthreads();
   }
   const int offset = ps[0];
-  const int base = blockIdx.x * kScanBlock;
+  const int base = item * kScanBlock;
   for (int k = threadIdx.x; k < kScanBlock; k += kBlock) {
     const int i = base + k;
     if (i < n) {
@@ -558,8 +573,8 @@ __global__ __launch_bounds__(kBlock) void scan2_kernel(GridGeom g, EvalBuffers b
       b.sb_cursor[i] = v;
     }
   }
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) b.sb_start[n] = offset + b.bsum[blockIdx.x];
-  if (blockIdx.x != 0) return;
+  if (item == nscan - 1 && threadIdx.x == 0) b.sb_start[n] = offset + b.bsum[item];
+  if (item != 0) return;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   for (int i = threadIdx.x; i < nblk_bin; i += kBlock) {
     a0 += b.qpart[3 * i];
@@ -586,6 +601,11 @@ __global__ __launch_bounds__(kBlock) void scan2_kernel(GridGeom g, EvalBuffers b
   }
 }
 
+__global__ __launch_bounds__(kBlock) void scan2_kernel(GridGeom g, EvalBuffers b, int nblk_bin,
+                                                       int check_neutral) {
+  stage_scan2(g, b, nblk_bin, check_neutral, blockIdx.x, gridDim.x);
+}
+
 int scan_blocks(const GridGeom& g) {
   return (g.nsb[0] * g.nsb[1] * g.nsb[2] + kScanBlock - 1) / kScanBlock;
 }
@@ -599,14 +619,19 @@ hipError_t launch_scan(const GridGeom& g, const EvalBuffers& b, int nblk_bin, in
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void scatter_kernel(EvalBuffers b, long N) {
-  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ void stage_scatter(const EvalBuffers& b, long N, int item) {
+  const long n = (long)item * blockDim.x + threadIdx.x;
   if (n >= N) return;
   const int key = b.p_key[n];
   const int pos = atomicAdd(&b.sb_cursor[key], 1);
   b.s_cell[pos] = b.p_cell[n];
   b.s_idx[pos] = (int)n;
   reinterpret_cast<Quad<T>*>(b.s_fq)[pos] = reinterpret_cast<const Quad<T>*>(b.p_frac)[n];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void scatter_kernel(EvalBuffers b, long N) {
+  stage_scatter<T>(b, N, blockIdx.x);
 }
 
 hipError_t launch_scatter(const GridGeom& g, const EvalBuffers& b, long N, bool f64, hipStream_t st) {
@@ -772,11 +797,10 @@ __device__ __forceinline__ long long round_fixed(double d) {
 }
 
 template <typename T, int P>
-__global__ __launch_bounds__(kBlock) void spread_kernel(GridGeom g, EvalBuffers b) {
-  extern __shared__ __align__(16) unsigned char smem[];
+__device__ void stage_spread(const GridGeom& g, const EvalBuffers& b, int item, unsigned char* smem) {
   constexpr int G2 = Lanes<P>::G2, PPW = Lanes<P>::PPW;
   const int TX = g.T[0], TY = g.T[1], TZ = g.T[2];
-  const int t_id = blockIdx.x;
+  const int t_id = item;
   const int tz = t_id / (g.nt[0] * g.nt[1]);
   const int ty = (t_id / g.nt[0]) % g.nt[1];
   const int tx = t_id % g.nt[0];
@@ -869,6 +893,13 @@ __global__ __launch_bounds__(kBlock) void spread_kernel(GridGeom g, EvalBuffers 
   T* stg = reinterpret_cast<T*>(b.stage) + (long long)t_id * R3;
   const double inv = stile > 0.0 ? 1.0 / scale : 0.0;
   for (int i = threadIdx.x; i < R3; i += blockDim.x) stg[i] = (T)((double)(long long)acc[i] * inv);
+  __syncthreads();
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(kBlock) void spread_kernel(GridGeom g, EvalBuffers b) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  stage_spread<T, P>(g, b, blockIdx.x, smem);
 }
 
 // For one direction: the tile at offset d from tile t (wrapped in periodic
@@ -892,13 +923,32 @@ __device__ __forceinline__ bool box_of(const GridGeom& g, int dim, int t, int d,
   return true;
 }
 
-// Tiles whose box can reach a point of tile t lie at offsets |d| <= dmax:
-// a box extends P/2 - 1 below and P/2 above its tile.
-__device__ __forceinline__ int fold_reach(const GridGeom& g, int dim) { return 1 + (g.P / 2 - 1) / g.T[dim]; }
+// Boxes (tile, origin) of one direction that intersect [x0, x0 + ext): the
+// tiles at offsets d from tile t, periodic images included.  Offsets are
+// scanned generously (a partial last tile in a periodic direction brings the
+// images closer than T apart) and kept only if the box meets the tile.
+__device__ __forceinline__ int fold_images(const GridGeom& g, int dim, int t, int x0, int ext, int* tl,
+                                           int* org) {
+  const int T = g.T[dim], RX = T + g.P - 1;
+  int emin = T;
+  if (g.per[dim]) emin = min(T, g.G[dim] - (g.nt[dim] - 1) * T);
+  const int reach = 2 + (T + g.P) / max(emin, 1);
+  int n = 0;
+  for (int d = -reach; d <= reach; ++d) {
+    int u, o;
+    if (!box_of(g, dim, t, d, &u, &o)) continue;
+    if (o < x0 + ext && o + RX > x0 && n < kMaxFoldImages) {
+      tl[n] = u;
+      org[n] = o;
+      ++n;
+    }
+  }
+  return n;
+}
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void fold_kernel(GridGeom g, EvalBuffers b) {
-  const int t_id = blockIdx.x;
+__device__ void stage_fold(const GridGeom& g, const EvalBuffers& b, int item) {
+  const int t_id = item;
   const int tz = t_id / (g.nt[0] * g.nt[1]);
   const int ty = (t_id / g.nt[0]) % g.nt[1];
   const int tx = t_id % g.nt[0];
@@ -906,35 +956,37 @@ __global__ __launch_bounds__(kBlock) void fold_kernel(GridGeom g, EvalBuffers b)
   const int ex = min(g.T[0], g.G[0] - x0), ey = min(g.T[1], g.G[1] - y0), ez = min(g.T[2], g.G[2] - z0);
   const int RX = g.T[0] + g.P - 1, RY = g.T[1] + g.P - 1, RZ = g.T[2] + g.P - 1;
   const long long R3 = (long long)RX * RY * RZ;
-  const int rx = fold_reach(g, 0), ry = fold_reach(g, 1), rz = fold_reach(g, 2);
+  int tlx[kMaxFoldImages], olx[kMaxFoldImages], tly[kMaxFoldImages], oly[kMaxFoldImages], tlz[kMaxFoldImages], olz[kMaxFoldImages];
+  const int nx = fold_images(g, 0, tx, x0, ex, tlx, olx);
+  const int ny = fold_images(g, 1, ty, y0, ey, tly, oly);
+  const int nz = fold_images(g, 2, tz, z0, ez, tlz, olz);
   const T* stg = reinterpret_cast<const T*>(b.stage);
   T* grid = reinterpret_cast<T*>(b.grid);
   const int n = ex * ey * ez;
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
     const int x = x0 + e % ex, y = y0 + (e / ex) % ey, z = z0 + e / (ex * ey);
     T sum = 0;
-    for (int dz = -rz; dz <= rz; ++dz) {
-      int uz, oz;
-      if (!box_of(g, 2, tz, dz, &uz, &oz)) continue;
-      const int bz = z - oz;
+    for (int kz = 0; kz < nz; ++kz) {
+      const int bz = z - olz[kz];
       if (bz < 0 || bz >= RZ) continue;
-      for (int dy = -ry; dy <= ry; ++dy) {
-        int uy, oy;
-        if (!box_of(g, 1, ty, dy, &uy, &oy)) continue;
-        const int by = y - oy;
+      for (int ky = 0; ky < ny; ++ky) {
+        const int by = y - oly[ky];
         if (by < 0 || by >= RY) continue;
-        for (int dx = -rx; dx <= rx; ++dx) {
-          int ux, ox;
-          if (!box_of(g, 0, tx, dx, &ux, &ox)) continue;
-          const int bx = x - ox;
+        for (int kx = 0; kx < nx; ++kx) {
+          const int bx = x - olx[kx];
           if (bx < 0 || bx >= RX) continue;
-          const long long nt = ((long long)uz * g.nt[1] + uy) * g.nt[0] + ux;
+          const long long nt = ((long long)tlz[kz] * g.nt[1] + tly[ky]) * g.nt[0] + tlx[kx];
           sum += stg[nt * R3 + ((long long)bz * RY + by) * RX + bx];
         }
       }
     }
     grid[((long long)z * g.G[1] + y) * g.G[0] + x] = sum;
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void fold_kernel(GridGeom g, EvalBuffers b) {
+  stage_fold<T>(g, b, blockIdx.x);
 }
 
 template <typename T>
@@ -994,13 +1046,12 @@ hipError_t launch_fold(const GridGeom& g, const EvalBuffers& b, bool f64, hipStr
 // with shuffles.
 // ---------------------------------------------------------------------------
 template <typename T, int P>
-__global__ __launch_bounds__(kBlock) void gather_kernel(GridGeom g, EvalBuffers b, T* __restrict__ phi,
-                                                        T* __restrict__ force, int out_grad,
-                                                        double self_coef) {
-  extern __shared__ __align__(16) unsigned char smem[];
+__device__ void stage_gather(const GridGeom& g, const EvalBuffers& b, T* __restrict__ phi,
+                             T* __restrict__ force, int out_grad, double self_coef, int item,
+                             unsigned char* smem) {
   constexpr int G2 = Lanes<P>::G2, PPW = Lanes<P>::PPW;
   const int TX = g.T[0], TY = g.T[1], TZ = g.T[2];
-  const int t_id = blockIdx.x;
+  const int t_id = item;
   const int tz = t_id / (g.nt[0] * g.nt[1]);
   const int ty = (t_id / g.nt[0]) % g.nt[1];
   const int tx = t_id % g.nt[0];
@@ -1143,6 +1194,15 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GridGeom g, EvalBuffers 
     for (int w = 0; w < nwaves; ++w) s += ewave[w];
     b.epart[t_id] = s;
   }
+  __syncthreads();
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(kBlock) void gather_kernel(GridGeom g, EvalBuffers b, T* __restrict__ phi,
+                                                        T* __restrict__ force, int out_grad,
+                                                        double self_coef) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  stage_gather<T, P>(g, b, phi, force, out_grad, self_coef, blockIdx.x, smem);
 }
 
 template <typename T>
@@ -1192,25 +1252,141 @@ hipError_t launch_gather(const GridGeom& g, const EvalBuffers& b, bool f64, void
 }
 
 // E = 1/2 sum of the per-tile partials of q phi, in a fixed order (FP64).
-__global__ __launch_bounds__(1024) void energy_kernel(const double* __restrict__ epart, int n,
-                                                      double* __restrict__ energy) {
-  __shared__ double s[1024];
+__device__ void stage_energy(const double* __restrict__ epart, int n, double* __restrict__ energy) {
+  __shared__ double es[kBlock];
   double a = 0.0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) a += epart[i];
-  s[threadIdx.x] = a;
+  es[threadIdx.x] = a;
   __syncthreads();
   for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-    if (threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+    if ((int)threadIdx.x < off) es[threadIdx.x] += es[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *energy = 0.5 * s[0];
+  if (threadIdx.x == 0 && energy) *energy = 0.5 * es[0];
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kBlock) void energy_kernel(const double* __restrict__ epart, int n,
+                                                        double* __restrict__ energy) {
+  stage_energy(epart, n, energy);
 }
 
 hipError_t launch_energy(const GridGeom& g, const EvalBuffers& b, double* energy, double self_e,
                          hipStream_t st) {
   (void)self_e;
   const int ntiles = g.nt[0] * g.nt[1] * g.nt[2];
-  energy_kernel<<<dim3(1), dim3(1024), 0, st>>>(b.epart, ntiles, energy);
+  energy_kernel<<<dim3(1), dim3(kBlock), 0, st>>>(b.epart, ntiles, energy);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched evaluation: many systems of uneven size and periodicity.  Each stage
+// of the path is one launch over the work items of all systems (a work item is
+// one block-sized piece of one system: a particle block, a scan block, a tile
+// or a pencil group); consecutive launches on the stream order the stages.
+// ---------------------------------------------------------------------------
+__device__ void stage_zero(const GridGeom& g, const EvalBuffers& b, int item) {
+  const int n = g.nsb[0] * g.nsb[1] * g.nsb[2];
+  for (int k = threadIdx.x; k < kScanBlock; k += blockDim.x) {
+    const int i = item * kScanBlock + k;
+    if (i < n) b.sb_count[i] = 0;
+  }
+}
+
+template <typename T, int P>
+__device__ void run_batch_stage(int st, const SysDesc& S, int sys_id, int li, const BatchIO& io,
+                                unsigned char* smem) {
+  switch (st) {
+    case BS_ZERO:
+      stage_zero(S.g, S.b, li);
+      break;
+    case BS_BIN:
+      if (io.in_f32)
+        stage_bin<float, T>(S.g, S.b, S.N, reinterpret_cast<const float*>(io.xyz) + 3 * S.off,
+                            reinterpret_cast<const float*>(io.q) + S.off, li);
+      else
+        stage_bin<double, T>(S.g, S.b, S.N, reinterpret_cast<const double*>(io.xyz) + 3 * S.off,
+                             reinterpret_cast<const double*>(io.q) + S.off, li);
+      break;
+    case BS_SCAN1:
+      stage_scan1(S.g, S.b, li);
+      break;
+    case BS_SCAN2:
+      stage_scan2(S.g, S.b, S.nblk_bin, S.check_neutral && !io.allow_nonneutral, li, S.nscan);
+      break;
+    case BS_SCATTER:
+      stage_scatter<T>(S.b, S.N, li);
+      break;
+    case BS_SPREAD:
+      stage_spread<T, P>(S.g, S.b, li, smem);
+      break;
+    case BS_FOLD:
+      stage_fold<T>(S.g, S.b, li);
+      break;
+    case BS_GATHER: {
+      T* phi = io.phi ? reinterpret_cast<T*>(io.phi) + S.off : nullptr;
+      T* force = io.force ? reinterpret_cast<T*>(io.force) + 3 * S.off : nullptr;
+      stage_gather<T, P>(S.g, S.b, phi, force, io.out_grad, io.add_self ? S.self_coef : 0.0, li, smem);
+      break;
+    }
+    case BS_ENERGY:
+      stage_energy(S.b.epart, S.ntiles, io.energy ? io.energy + sys_id : nullptr);
+      break;
+    default: {
+      const FftPass& ps = S.pass[st - BS_FFT0];
+      switch (ps.kind) {
+        case K_C2C_FWD: stage_fft<T, K_C2C_FWD>(ps, li, smem); break;
+        case K_C2C_INV: stage_fft<T, K_C2C_INV>(ps, li, smem); break;
+        case K_R2C: stage_fft<T, K_R2C>(ps, li, smem); break;
+        case K_C2R: stage_fft<T, K_C2R>(ps, li, smem); break;
+        default: stage_fft<T, K_FUSED>(ps, li, smem); break;
+      }
+    }
+  }
+}
+
+// One stage of the batch for all systems: block b is work item b of the stage,
+// counted over the systems in order.  No block waits on another.
+template <typename T, int P>
+__global__ __launch_bounds__(kBlock) void batch_stage_kernel(const SysDesc* __restrict__ sys, int nsys,
+                                                             const int* __restrict__ off, int st,
+                                                             BatchIO io) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int* o = off + st * (nsys + 1);
+  const int item = blockIdx.x;
+  // the system owning this item: last s with o[s] <= item
+  int lo = 0, hi = nsys - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (o[mid] <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  run_batch_stage<T, P>(st, sys[lo], lo, item - o[lo], io, smem);
+}
+
+template <typename T, int P>
+static void batch_launch_t(const SysDesc* sys, int nsys, const int* off, const int* items, const BatchIO& io,
+                           size_t lds, hipStream_t st) {
+  for (int s = 0; s < BS_COUNT; ++s)
+    if (items[s] > 0)
+      batch_stage_kernel<T, P><<<dim3(items[s]), dim3(kBlock), lds, st>>>(sys, nsys, off, s, io);
+}
+
+hipError_t launch_batch(int P, bool f64, const SysDesc* sys, int nsys, const int* off, const int* items,
+                        const BatchIO& io, size_t lds, hipStream_t st) {
+  switch (P) {
+    case 4: f64 ? batch_launch_t<double, 4>(sys, nsys, off, items, io, lds, st)
+                : batch_launch_t<float, 4>(sys, nsys, off, items, io, lds, st); break;
+    case 6: f64 ? batch_launch_t<double, 6>(sys, nsys, off, items, io, lds, st)
+                : batch_launch_t<float, 6>(sys, nsys, off, items, io, lds, st); break;
+    case 8: f64 ? batch_launch_t<double, 8>(sys, nsys, off, items, io, lds, st)
+                : batch_launch_t<float, 8>(sys, nsys, off, items, io, lds, st); break;
+    case 10: f64 ? batch_launch_t<double, 10>(sys, nsys, off, items, io, lds, st)
+                 : batch_launch_t<float, 10>(sys, nsys, off, items, io, lds, st); break;
+    case 12: f64 ? batch_launch_t<double, 12>(sys, nsys, off, items, io, lds, st)
+                 : batch_launch_t<float, 12>(sys, nsys, off, items, io, lds, st); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

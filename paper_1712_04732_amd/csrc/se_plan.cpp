@@ -376,6 +376,33 @@ se_status se_params_default(int D, double L, double xi, int M, int P, se_window 
   return SE_OK;
 }
 
+// Kolafa-Perram k-space truncation estimate, Eq. (KP_fourier_space), k_inf = M/2.
+static double kp_kspace(double Q, double xi, double L, int M) {
+  const double kinf = M / 2.0;
+  return std::sqrt(Q) * xi / (kPi * kPi) * std::pow(kinf, -1.5) * std::exp(-std::pow(kPi * kinf / (xi * L), 2));
+}
+
+// Error-pollution bound f_W(x), Eq. (error_pollution).
+static double pollution_fw(se_window w, double x) {
+  return w == SE_WIN_GAUSSIAN ? x * x + 0.2 * x + 2.25 : 0.7 * x * x + 0.2 * x + 1.8;
+}
+
+se_status se_params_for_tolerance(int D, double L, double xi, double Q, double tol_rel, int P, se_window window,
+                                  se_precision prec, se_params* out) {
+  if (!out) return SE_ERR_ARG;
+  if (D < 0 || D > 3 || !(L > 0) || !(xi > 0) || !(Q > 0) || !(tol_rel > 0) || P < 2 || P % 2 || P > se::kMaxP)
+    return SE_ERR_PARAM;
+  const double B = std::sqrt(Q) * fc(xi * L) / L;
+  int M = std::max(P, 4);
+  M = smooth_even_up(M);
+  // smallest 7-smooth even M whose truncation estimate meets tol_rel * B,
+  // then no error pollution: P <= f_W(M / (xi L))
+  while (M < 4096 && (kp_kspace(Q, xi, L, M) > tol_rel * B || P > pollution_fw(window, M / (xi * L))))
+    M = smooth_even_up(M + 2);
+  if (M >= 4096) return SE_ERR_PARAM;
+  return se_params_default(D, L, xi, M, P, window, Q, tol_rel * B, prec, out);
+}
+
 se_status se_plan_get_info(const se_plan* plan, se_plan_info* info) {
   if (!plan || !info) return SE_ERR_ARG;
   *info = plan->info;
@@ -394,7 +421,39 @@ se_status se_plan_destroy(se_plan* plan) {
 static se_status build_passes(se_plan* pl);
 static se_status precompute_0p(se_plan* pl, hipStream_t st, const void** table);
 
+// Largest number of tile-box images (periodic copies included) that meet one
+// tile in direction d; the fold kernel sums over at most kMaxFoldImages.
+static int fold_image_count(const se::GridGeom& g, int d) {
+  const int T = g.T[d], G = g.G[d], nt = g.nt[d], RX = T + g.P - 1, h = g.P / 2 - 1;
+  int emin = T;
+  if (g.per[d]) emin = std::min(T, G - (nt - 1) * T);
+  const int reach = 2 + (T + g.P) / std::max(emin, 1);
+  int most = 0;
+  for (int t = 0; t < nt; ++t) {
+    const int x0 = t * T, ext = std::min(T, G - x0);
+    int n = 0;
+    for (int dd = -reach; dd <= reach; ++dd) {
+      int u = t + dd, shift = 0;
+      if (!g.per[d] && (u < 0 || u >= nt)) continue;
+      while (u < 0) u += nt, shift -= G;
+      while (u >= nt) u -= nt, shift += G;
+      const int o = u * T + shift - h;
+      if (o < x0 + ext && o + RX > x0) ++n;
+    }
+    most = std::max(most, n);
+  }
+  return most;
+}
+
+static se_status plan_create(const se_params* params, long n_max, void* hip_stream, size_t lds_soft,
+                             se_plan** out);
+
 se_status se_plan_create(const se_params* params, long n_max, void* hip_stream, se_plan** out) {
+  return plan_create(params, n_max, hip_stream, 65536, out);
+}
+
+static se_status plan_create(const se_params* params, long n_max, void* hip_stream, size_t lds_soft,
+                             se_plan** out) {
   if (!params || !out || n_max < 0 || n_max > (1L << 30)) return SE_ERR_ARG;
   *out = nullptr;
   se_params p = *params;
@@ -435,6 +494,7 @@ se_status se_plan_create(const se_params* params, long n_max, void* hip_stream, 
   pl->f64 = (p.prec == SE_F64);
   pl->n_max = n_max;
   (void)hipGetDevice(&pl->device);
+  pl->lds_limit = lds_soft;
   int lds = 0;
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, pl->device) == hipSuccess && lds > 0)
     pl->lds_max = std::max<size_t>(pl->lds_limit, (size_t)lds);
@@ -520,6 +580,11 @@ se_status se_plan_create(const se_params* params, long n_max, void* hip_stream, 
     g.nsb[d] = (g.G[d] + se::kSB - 1) / se::kSB;
   }
   pl->ntiles = g.nt[0] * g.nt[1] * g.nt[2];
+  for (int d = 0; d < 3; ++d)
+    if (fold_image_count(g, d) > se::kMaxFoldImages) {
+      delete pl;
+      return SE_ERR_UNSUPPORTED;
+    }
   pl->nsbtot = g.nsb[0] * g.nsb[1] * g.nsb[2];
 
   hipStream_t st = (hipStream_t)hip_stream;
@@ -1064,6 +1129,232 @@ se_status se_get_device_status(se_plan* plan, void* hip_stream) {
   if (s & 1) return SE_ERR_NONFINITE;
   if (s & 2) return SE_ERR_OUT_OF_BOX;
   if (s & 4) return SE_ERR_NONNEUTRAL;
+  return SE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched plans: one sub-plan per system; one persistent launch per evaluation.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct se_batch_plan {
+  std::vector<se_plan*> sys;
+  std::vector<long> N, off;
+  long total = 0;
+  se::SysDesc* d_sys = nullptr;
+  int* d_off = nullptr;
+  int items[se::BS_COUNT] = {};
+  size_t lds = 0;
+  int P = 0;
+  bool f64 = true;
+  int device = 0;
+  double alg_bytes = 0.0, alg_flops = 0.0;   // per launch, summed over systems and stages
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int prof_pending = 0, prof_launches = 0;
+  double prof_ms = 0.0;
+  ~se_batch_plan() {
+    if (ev[0]) (void)hipEventDestroy(ev[0]);
+    if (ev[1]) (void)hipEventDestroy(ev[1]);
+    if (d_sys) (void)hipFree(d_sys);
+    if (d_off) (void)hipFree(d_off);
+    for (se_plan* s : sys) delete s;
+  }
+};
+
+extern "C" {
+
+se_status se_batch_plan_create(const se_params* params, const long* N, int n_sys, void* hip_stream,
+                               se_batch_plan** out) {
+  if (!params || !N || !out || n_sys < 1) return SE_ERR_ARG;
+  *out = nullptr;
+  for (int s = 0; s < n_sys; ++s) {
+    if (N[s] < 0) return SE_ERR_ARG;
+    if (params[s].P != params[0].P || params[s].window != params[0].window || params[s].prec != params[0].prec)
+      return SE_ERR_UNSUPPORTED;
+  }
+  const int P = params[0].P;
+  if (P != 4 && P != 6 && P != 8 && P != 10 && P != 12) return SE_ERR_UNSUPPORTED;
+  se_batch_plan* bp = new (std::nothrow) se_batch_plan();
+  if (!bp) return SE_ERR_NOMEM;
+  bp->P = P;
+  bp->f64 = params[0].prec == SE_F64;
+  (void)hipGetDevice(&bp->device);
+  hipStream_t st = (hipStream_t)hip_stream;
+  std::vector<se::SysDesc> desc(n_sys);
+  std::vector<int> off((size_t)se::BS_COUNT * (n_sys + 1), 0);
+  long run = 0;
+  for (int s = 0; s < n_sys; ++s) {
+    se_plan* sp = nullptr;
+    // a common LDS budget keeps several workgroups per CU in every stage
+    se_status rc = plan_create(&params[s], N[s], hip_stream, 48 * 1024, &sp);
+    if (rc != SE_OK) {
+      delete bp;
+      return rc;
+    }
+    bp->sys.push_back(sp);
+    if (sp->passes.size() != (size_t)se::kPasses) {
+      delete bp;
+      return SE_ERR_UNSUPPORTED;
+    }
+    se::SysDesc& d = desc[s];
+    std::memset(&d, 0, sizeof(d));
+    d.g = sp->geom;
+    d.b = sp->buf;
+    for (int k = 0; k < se::kPasses; ++k) d.pass[k] = sp->passes[k];
+    d.N = N[s];
+    d.off = run;
+    d.nblk_bin = (int)((N[s] + se::kBlock - 1) / se::kBlock);
+    d.nscan = se::scan_blocks(sp->geom);
+    d.ntiles = sp->ntiles;
+    d.check_neutral = sp->p.D >= 1;
+    d.self_coef = -2.0 * sp->p.xi / std::sqrt(kPi);
+    bp->N.push_back(N[s]);
+    bp->off.push_back(run);
+    run += N[s];
+    const int items[se::BS_COUNT] = {d.nscan, d.nblk_bin, d.nscan, d.nscan, d.nblk_bin, d.ntiles, d.ntiles,
+                                     d.pass[0].nitems, d.pass[1].nitems, d.pass[2].nitems, d.pass[3].nitems,
+                                     d.pass[4].nitems, d.ntiles, 1};
+    for (int k = 0; k < se::BS_COUNT; ++k) off[(size_t)k * (n_sys + 1) + s + 1] = items[k];
+    bp->lds = std::max(bp->lds, se::spread_lds_bytes(sp->geom, bp->f64));
+    bp->lds = std::max(bp->lds, se::gather_lds_bytes(sp->geom, bp->f64));
+    for (int k = 0; k < se::kPasses; ++k) bp->lds = std::max(bp->lds, se::fft_lds_bytes(d.pass[k], bp->f64));
+    // algorithmic counts of one evaluation of this system (as for se_eval)
+    const double re = bp->f64 ? 8.0 : 4.0;
+    const double G = (double)d.g.G[0] * d.g.G[1] * d.g.G[2];
+    const double R3 = (double)(d.g.T[0] + P - 1) * (d.g.T[1] + P - 1) * (d.g.T[2] + P - 1);
+    const int nu = std::max(d.g.nu, 5);
+    const double n = (double)N[s];
+    bp->alg_bytes += n * 4.0 * re + n * 2.0 * (8.0 + 4.0 * re) + n * 4.0 * re + G * re +
+                     d.ntiles * R3 * re + G * re + n * 8.0 * re + G * re;
+    bp->alg_flops += n * 2.0 * (3.0 * P * nu + P * P + (double)P * P * P) + d.ntiles * R3 +
+                     n * 2.0 * (6.0 * P * nu + 3.0 * P * P + (double)P * P * (2 * P + 4));
+    for (int k = 0; k < se::kPasses; ++k) {
+      bp->alg_bytes += d.pass[k].alg_bytes;
+      bp->alg_flops += d.pass[k].alg_flops;
+    }
+  }
+  bp->total = run;
+  for (int k = 0; k < se::BS_COUNT; ++k)
+    for (int s = 0; s < n_sys; ++s) off[(size_t)k * (n_sys + 1) + s + 1] += off[(size_t)k * (n_sys + 1) + s];
+  int lds_max = 0;
+  (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, bp->device);
+  if (lds_max > 0 && bp->lds > (size_t)lds_max) {
+    delete bp;
+    return SE_ERR_UNSUPPORTED;
+  }
+  for (int k = 0; k < se::BS_COUNT; ++k) bp->items[k] = off[(size_t)k * (n_sys + 1) + n_sys];
+  if (hipMalloc(&bp->d_sys, sizeof(se::SysDesc) * n_sys) != hipSuccess ||
+      hipMalloc(&bp->d_off, sizeof(int) * off.size()) != hipSuccess) {
+    delete bp;
+    return SE_ERR_NOMEM;
+  }
+  if (hipMemcpy(bp->d_sys, desc.data(), sizeof(se::SysDesc) * n_sys, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(bp->d_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    delete bp;
+    return SE_ERR_DEVICE;
+  }
+  *out = bp;
+  return SE_OK;
+}
+
+se_status se_batch_plan_get_info(const se_batch_plan* plan, int sys, se_plan_info* info, long* n_particles,
+                                 int* persistent_blocks) {
+  // persistent_blocks is the 'reserved' output of the header
+  if (!plan || sys < 0 || sys >= (int)plan->sys.size()) return SE_ERR_ARG;
+  if (info) {
+    *info = plan->sys[sys]->info;
+    info->device_bytes = plan->sys[sys]->bytes;
+  }
+  if (n_particles) *n_particles = plan->N[sys];
+  if (persistent_blocks) *persistent_blocks = 0;
+  return SE_OK;
+}
+
+se_status se_eval_batch(se_batch_plan* plan, const void* xyz, const void* q, void* phi, void* force,
+                        double* energy, unsigned flags, void* hip_stream) {
+  if (!plan) return SE_ERR_ARG;
+  if (plan->total > 0 && (!xyz || !q)) return SE_ERR_ARG;
+  if (flags & ~(SE_IN_F32 | SE_ADD_SELF | SE_SYNC_CHECK | SE_OUT_GRAD | SE_ALLOW_NONNEUTRAL | SE_PROFILE))
+    return SE_ERR_ARG;
+  hipStream_t st = (hipStream_t)hip_stream;
+  se::BatchIO io{};
+  io.xyz = xyz;
+  io.q = q;
+  io.phi = phi;
+  io.force = force;
+  io.energy = energy;
+  io.in_f32 = (flags & SE_IN_F32) ? 1 : 0;
+  io.out_grad = (flags & SE_OUT_GRAD) ? 1 : 0;
+  io.add_self = (flags & SE_ADD_SELF) ? 1 : 0;
+  io.allow_nonneutral = (flags & SE_ALLOW_NONNEUTRAL) ? 1 : 0;
+  const bool prof = (flags & SE_PROFILE) != 0;
+  if (prof && !plan->ev[0]) {
+    if (hipEventCreate(&plan->ev[0]) != hipSuccess || hipEventCreate(&plan->ev[1]) != hipSuccess)
+      return SE_ERR_DEVICE;
+  }
+  if (prof && plan->prof_pending) {
+    // the previous profiled launch: fold its time in before reusing the events
+    float ms = 0.f;
+    if (hipEventSynchronize(plan->ev[1]) != hipSuccess ||
+        hipEventElapsedTime(&ms, plan->ev[0], plan->ev[1]) != hipSuccess)
+      return SE_ERR_DEVICE;
+    plan->prof_ms += ms;
+    plan->prof_launches += 1;
+    plan->prof_pending = 0;
+  }
+  if (prof && hipEventRecord(plan->ev[0], st) != hipSuccess) return SE_ERR_DEVICE;
+  if (se::launch_batch(plan->P, plan->f64, plan->d_sys, (int)plan->sys.size(), plan->d_off, plan->items, io,
+                       plan->lds, st) != hipSuccess)
+    return SE_ERR_DEVICE;
+  if (prof) {
+    if (hipEventRecord(plan->ev[1], st) != hipSuccess) return SE_ERR_DEVICE;
+    plan->prof_pending = 1;
+  }
+  if (flags & SE_SYNC_CHECK) return se_batch_get_device_status(plan, hip_stream);
+  return SE_OK;
+}
+
+se_status se_batch_plan_profile(se_batch_plan* plan, void* hip_stream, se_stage_record* out, int reset) {
+  if (!plan || !out) return SE_ERR_ARG;
+  if (hipStreamSynchronize((hipStream_t)hip_stream) != hipSuccess) return SE_ERR_DEVICE;
+  if (plan->prof_pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, plan->ev[0], plan->ev[1]) != hipSuccess) return SE_ERR_DEVICE;
+    plan->prof_ms += ms;
+    plan->prof_launches += 1;
+    plan->prof_pending = 0;
+  }
+  std::memset(out, 0, sizeof(*out));
+  std::snprintf(out->name, sizeof(out->name), "batch_all_stages");
+  out->launches = plan->prof_launches;
+  out->ms_total = plan->prof_ms;
+  out->bytes = plan->alg_bytes;
+  out->flops = plan->alg_flops;
+  if (reset) {
+    plan->prof_ms = 0.0;
+    plan->prof_launches = 0;
+  }
+  return SE_OK;
+}
+
+se_status se_batch_get_device_status(se_batch_plan* plan, void* hip_stream) {
+  if (!plan) return SE_ERR_ARG;
+  se_status worst = SE_OK;
+  for (se_plan* s : plan->sys) {
+    const se_status r = se_get_device_status(s, hip_stream);
+    if (r == SE_ERR_NONFINITE || (r != SE_OK && worst == SE_OK) ||
+        (r == SE_ERR_OUT_OF_BOX && worst == SE_ERR_NONNEUTRAL))
+      worst = r;
+  }
+  return worst;
+}
+
+se_status se_batch_plan_destroy(se_batch_plan* plan) {
+  if (plan) {
+    (void)hipSetDevice(plan->device);
+    delete plan;
+  }
   return SE_OK;
 }
 

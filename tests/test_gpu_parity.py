@@ -71,6 +71,12 @@ CASES = [
     (1, 16, 6, 129, "gaussian", 4),
     (0, 24, 8, 400, "pkb", 0),
     (0, 16, 4, 77, "gaussian", 8),
+    # periodic grids that are not a multiple of the tile: the short last tile
+    # brings boxes two tiles away into reach of the fold
+    (3, 14, 8, 300, "pkb", 4),
+    (2, 14, 8, 240, "pkb", 4),
+    (1, 18, 12, 180, "gaussian", 4),
+    (3, 18, 10, 150, "pkb", 8),
 ]
 
 

@@ -9,6 +9,8 @@ import pytest
 from oracle import se_discrete as se
 from paper_1712_04732_amd import _lib as L
 
+L_ = L
+
 
 def test_library_exports_every_declared_symbol():
     lib = L.load()
@@ -72,3 +74,25 @@ def test_null_arguments():
     assert lib.se_params_default(3, 1.0, 5.0, 32, 8, 1, 1.0, 1e-6, 0, None) == L.SE_ERR_ARG
     out = L.se_params()
     assert lib.se_params_default(3, 1.0, 5.0, 32, 8, 1, 1.0, -1.0, 0, ctypes.byref(out)) == L.SE_ERR_PARAM
+
+
+@pytest.mark.parametrize("D,L,N,tol", [(3, 1.0, 1000, 1e-7), (2, 0.7, 5000, 1e-7), (1, 1.9, 800, 1e-6),
+                                       (0, 1.3, 20000, 1e-8), (3, 0.5, 40000, 1e-7)])
+def test_params_for_tolerance_matches_oracle_rule(D, L, N, tol):
+    """Section 6: M is the smallest even 7-smooth size whose Kolafa-Perram
+    estimate over B meets the tolerance, with no error pollution
+    (P <= f_W(M/(xi L))); recomputed here from the oracle's own estimates."""
+    xi = 1.2 * N ** (1 / 3) / L
+    Q = float(N)
+    p = L_.se_params_for_tolerance(D, L, xi, Q, tol, 8, L_.SE_WIN_PKB, L_.SE_F32)
+    B = se.B_scale(Q, xi, L)
+    M = 8
+    while True:
+        M = se.smooth_even_up(M)
+        if se.kp_kspace_error(Q, xi, L, M) <= tol * B and 8 <= se.pollution_bound("pkb", M / (xi * L)):
+            break
+        M += 2
+    assert p.M == M
+    if D in (1, 2):
+        o = se.with_aft_estimates(D, L, xi, M, 8, Q, tol * B, window="pkb")
+        assert abs(p.s - o.s) < 1e-12 and p.n_l == o.n_l

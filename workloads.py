@@ -76,6 +76,28 @@ CONFIGS = {
 }
 
 
+# The batched configuration: 256 independent systems from batch_draw(), each
+# with xi = 1.2 N^(1/3) / L, PKB window P = 8, grid from a 1e-7 relative
+# tolerance, FP32.
+BATCH = dict(n_sys=256, seed=SEED_BASE + 4, P=8, window="pkb", tol_rel=1e-7, xi_coef=1.2, prec="f32",
+             charges="pm1")
+
+
+def batch_xi(N: int, L: float, coef: float = 1.2) -> float:
+    """xi = coef * N^(1/3) / L: the splitting parameter of a batch system."""
+    return coef * N ** (1.0 / 3.0) / L
+
+
+def batch_systems(n_sys: int | None = None):
+    """(list of system dicts with D, N, L, seed, xi, x, q) of the batched workload."""
+    n = BATCH["n_sys"] if n_sys is None else n_sys
+    out = []
+    for s in batch_draw(n, BATCH["seed"]):
+        x, q = system(s["N"], s["L"], s["seed"], BATCH["charges"])
+        out.append(dict(s, xi=batch_xi(s["N"], s["L"], BATCH["xi_coef"]), x=x, q=q))
+    return out
+
+
 def config_system(name: str):
     c = CONFIGS[name]
     return system(c["N"], c["L"], c["seed"], c["charges"])

@@ -208,16 +208,17 @@ def main_batch(args):
     err = {"phi_f32_vs_f64": rel_rms(phi32, phi64), "force_f32_vs_f64": rel_rms(f32, f64),
            "energy_f32_vs_f64_max": float(np.max(np.abs(e32 - e64) / np.abs(e64)))}
 
-    t = rec["ms_avg"] * 1e-3
-    bw, fl = rec["bytes"] / t, rec["flops"] / t
-    f_hbm, f_alu = bw / HBM_PEAK, fl / ALU_PEAK["f32"]
-    if f_hbm >= f_alu:
-        roof = {"bound": "hbm", "achieved": bw / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": f_hbm}
-    else:
-        roof = {"bound": "alu", "achieved": fl / 1e12, "peak": ALU_PEAK["f32"] / 1e12, "unit": "TFLOP/s",
-                "frac": f_alu}
-    roof.update({"traffic": None, "kernel": "batch_all_stages (14 launches)", "ms_avg": rec["ms_avg"],
-                 "alg_bytes": rec["bytes"], "alg_flops": rec["flops"]})
+    stages = [r for r in rec if r["name"] != "batch_all_stages"]
+    whole = [r for r in rec if r["name"] == "batch_all_stages"][0]
+    for r in stages:
+        t = max(r["ms_avg"], 1e-9) * 1e-3
+        print(f"bench:   {r['name']:8s} {r['ms_avg'] * 1e3:9.1f} us  {r['bytes'] / t / 1e9:8.1f} GB/s  "
+              f"{r['flops'] / t / 1e12:7.2f} TFLOP/s", file=sys.stderr, flush=True)
+    roof = roofline(stages, "f32")
+    stage_ids = {"zero": 0, "bin": 1, "scan1": 2, "scan2": 3, "scatter": 4, "spread": 5, "fold": 6,
+                 "fft0": 7, "fft1": 8, "fft2": 9, "fft3": 10, "fft4": 11, "gather": 12, "energy": 13}
+    roof["kernel"] = f"batch_stage_kernel<float, {cfg['P']}, {stage_ids[roof['kernel']]}> ({roof['kernel']})"
+    roof["whole_eval_ms"] = whole["ms_avg"]
 
     result = {
         "metric": METRIC,

@@ -80,6 +80,10 @@ typedef struct {
   double Q;           /* sum of q^2, used by the s, n_l estimates (B, Section 5.2) */
   se_precision prec;  /* compute precision of grid, FFT, gather                   */
   int tile;           /* cubic spread/gather tile edge (multiple of 4); <= 0 -> automatic */
+  int tile3[3];       /* spread/gather tile edges x, y, z (multiples of 4, each <= 32);
+                         all > 0 -> used instead of 'tile'                          */
+  int fft_cap;        /* samples (length x pencils) per FFT workgroup: a power of two
+                         in 1024..8192; <= 0 -> 2048 (FP32) / 1024 (FP64)          */
 } se_params;
 
 /* Derived sizes of a plan (read-only report). */
@@ -92,6 +96,7 @@ typedef struct {
   int grid[3];        /* gridding grid points in x, y, z                               */
   int nfft[3];        /* transform lengths of the periodic / 0P padded directions      */
   int tile[3];        /* spread/gather tile edges in grid points (x, y, z)             */
+  int fft_cap;        /* samples per FFT workgroup in use                              */
   double h, shape, lambda, s0, s, R;
   size_t device_bytes; /* device memory held by the plan                               */
 } se_plan_info;
@@ -211,14 +216,20 @@ se_status se_batch_plan_get_info(const se_batch_plan* plan, int sys, se_plan_inf
 /* One batched evaluation.  xyz, q: device, concatenated as above (float64, or
  * float32 with SE_IN_F32); phi (sum N), force (sum N x 3): device, compute
  * precision, or NULL; energy: device, n_sys float64 energies, or NULL.  Flags
- * as for se_eval (SE_PROFILE times the whole evaluation with one event pair). */
+ * as for se_eval (SE_PROFILE records an event before each stage launch). */
 se_status se_eval_batch(se_batch_plan* plan, const void* xyz, const void* q, void* phi, void* force,
                         double* energy, unsigned flags, void* hip_stream);
 
-/* Aggregate timing of the SE_PROFILE batched evaluations since the last reset
- * into one record (host 'out'); bytes and flops are the algorithmic counts of
- * one launch summed over systems and stages. */
-se_status se_batch_plan_profile(se_batch_plan* plan, void* hip_stream, se_stage_record* out, int reset);
+/* Wait for the stream, then report the SE_PROFILE batched evaluations since
+ * the last reset: one record per stage launch that has work (zero, bin, scan1,
+ * scan2, scatter, spread, fold, fft0..fft4, gather, energy), timed with HIP
+ * events between the stage launches, then one record "batch_all_stages" for
+ * the whole evaluation; at most 'cap' records into host 'out', count in *n.
+ * bytes and flops are the algorithmic counts of one launch, summed over the
+ * systems.  reset != 0 clears the accumulated times.
+ * Errors: SE_ERR_ARG, SE_ERR_DEVICE. */
+se_status se_batch_plan_profile(se_batch_plan* plan, void* hip_stream, se_stage_record* out, int cap, int* n,
+                                int reset);
 
 /* Wait for the stream, report and clear the device status of every system
  * (the most severe code wins). */

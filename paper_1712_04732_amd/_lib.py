@@ -53,6 +53,8 @@ class se_params(ctypes.Structure):
         ("Q", ctypes.c_double),
         ("prec", ctypes.c_int),
         ("tile", ctypes.c_int),
+        ("tile3", ctypes.c_int * 3),
+        ("fft_cap", ctypes.c_int),
     ]
 
 
@@ -69,6 +71,7 @@ class se_plan_info(ctypes.Structure):
         ("grid", ctypes.c_int * 3),
         ("nfft", ctypes.c_int * 3),
         ("tile", ctypes.c_int * 3),
+        ("fft_cap", ctypes.c_int),
         ("h", ctypes.c_double),
         ("shape", ctypes.c_double),
         ("lambda_", ctypes.c_double),
@@ -122,7 +125,7 @@ _SIGS = {
     "se_eval_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint, ctypes.c_void_p]),
     "se_batch_plan_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(se_stage_record),
-                                             ctypes.c_int]),
+                                             ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
     "se_batch_get_device_status": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "se_batch_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
 }
@@ -233,11 +236,19 @@ def se_eval_batch(plan, xyz_ptr, q_ptr, phi_ptr, force_ptr, energy_ptr, flags, s
 
 
 def se_batch_plan_profile(plan, stream, reset=True):
-    r = se_stage_record()
-    _check(load().se_batch_plan_profile(plan, ctypes.c_void_p(stream), ctypes.byref(r), int(reset)),
+    """List of dicts per stage launch, then the whole evaluation
+    ("batch_all_stages"), as for se_plan_profile."""
+    cap = 32
+    arr = (se_stage_record * cap)()
+    n = ctypes.c_int()
+    _check(load().se_batch_plan_profile(plan, ctypes.c_void_p(stream), arr, cap, ctypes.byref(n), int(reset)),
            "se_batch_plan_profile")
-    return dict(name=r.name.decode(), launches=r.launches, ms_total=r.ms_total,
-                ms_avg=r.ms_total / max(r.launches, 1), bytes=r.bytes, flops=r.flops)
+    out = []
+    for i in range(n.value):
+        r = arr[i]
+        out.append(dict(name=r.name.decode(), launches=r.launches, ms_total=r.ms_total,
+                        ms_avg=r.ms_total / max(r.launches, 1), bytes=r.bytes, flops=r.flops))
+    return out
 
 
 def se_batch_plan_destroy(plan) -> int:

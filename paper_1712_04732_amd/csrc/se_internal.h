@@ -17,7 +17,11 @@ constexpr int kBlock = 256;      // threads per block of every kernel
 constexpr int kSB = 4;           // sub-bin edge in grid cells (particle sort key)
 constexpr int kMaxOwnRanges = 256;  // sub-bin rows of one tile ((T/kSB)^2 <= 256 for T <= 64)
 // Most periodic images of tile boxes one fold block sums over in a direction.
-constexpr int kMaxFoldImages = 16;
+constexpr int kMaxFoldImages = 8;
+// Most samples (transform length x pencils) one FFT workgroup holds, and the
+// FFT workgroup size.
+constexpr int kFftCap = 8192;
+constexpr int kFftBlock = 256;
 
 // Green's-function modes of the fused scaling pass (Eq. scale).
 enum GMode : int {
@@ -52,7 +56,8 @@ struct FftClass {
   const void* kB;
   const void* kC;
   const void* gtab;
-  int gd1, gd2;                   // folded table row lengths
+  int gd0, gd1;                   // table extents of the b0 (fastest) and b1 indices:
+                                  // G_TAB2 [t][b0], G_TAB3 [t][b1][b0]
   int fold1, fold2;               // transform lengths used to fold b1 and t
   int fold0;                      // transform length used to fold b0 (0: b0 not folded)
 };
@@ -61,7 +66,8 @@ struct FftPass {
   FftClass cls[kMaxClasses];
   const int4* items;              // per block: {class, b0_start, b1, count}
   int nitems;
-  int B;                          // pencils per block
+  int B;                          // pencils per block, B = 2^lgB
+  int lgB;
   int nmax;                       // largest n (LDS sizing)
   int kind;
   double alg_bytes, alg_flops;    // algorithmic counts of one launch (tracing only)
@@ -136,6 +142,12 @@ enum BatchStage : int {
   BS_ZERO = 0, BS_BIN, BS_SCAN1, BS_SCAN2, BS_SCATTER, BS_SPREAD, BS_FOLD,
   BS_FFT0, BS_FFT1, BS_FFT2, BS_FFT3, BS_FFT4, BS_GATHER, BS_ENERGY, BS_COUNT
 };
+constexpr int stage_block(int st) { return st >= BS_FFT0 && st <= BS_FFT4 ? kFftBlock : kBlock; }
+// Work lists of a batch: one per stage, and for the transform stages one per
+// (stage, transform kind) so that each launch runs a single kind.
+constexpr int kFftKinds = 5;
+constexpr int BL_COUNT = BS_COUNT + 5 * kFftKinds;
+constexpr int fft_list(int st, int kind) { return BS_COUNT + (st - BS_FFT0) * kFftKinds + kind; }
 
 // Launchers (se_kernels.hip).  All enqueue on 'st' and return the HIP error.
 hipError_t launch_bin(const GridGeom& g, const EvalBuffers& b, long N, const void* xyz,
@@ -156,10 +168,11 @@ size_t gather_lds_bytes(const GridGeom& g, bool f64);
 int scan_blocks(const GridGeom& g);
 
 // Batched evaluation: one launch per stage over the work items of all systems.
-// off: device table [BS_COUNT][nsys + 1] of work-item prefix sums per stage;
-// items: host array of the stage totals.
+// off: device table [BL_COUNT][nsys + 1] of work-item prefix sums per work
+// list; items: host array of the list totals; lds: dynamic LDS bytes per stage;
+// ev: BS_COUNT + 1 events recorded before each stage and after the last, or null.
 hipError_t launch_batch(int P, bool f64, const SysDesc* sys, int nsys, const int* off, const int* items,
-                        const BatchIO& io, size_t lds, hipStream_t st);
+                        const BatchIO& io, const size_t* lds, hipStream_t st, hipEvent_t* ev);
 
 // 0P precompute helpers (FP64).
 hipError_t launch_g0p_fill(double* buf, int n0, double h, double R, hipStream_t st);

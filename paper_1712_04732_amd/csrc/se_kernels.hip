@@ -172,23 +172,41 @@ __device__ __forceinline__ void dft(cx<T>* v, int sign) {
   else dft_odd<T, R>(v, sign);
 }
 
-// One Stockham stage over B interleaved pencils (sample-major, index t*B + p):
-//   input  j + r n/R   (j = 0..n/R-1)
-//   twiddle exp(sign 2 pi i r k/(Ns R)), k = j mod Ns
-//   output (j/Ns) Ns R + k + r Ns
+// Quotient of small non-negative integers a < 2^21 by d, given inv_d = 1/d in
+// FP32: (a + 1/2)/d lies at least 1/(2d) from an integer, which exceeds the
+// rounding error of the product, so truncation gives floor(a/d) exactly.
+__device__ __forceinline__ int fdiv(int a, float inv_d) { return (int)(((float)a + 0.5f) * inv_d); }
+
+// Work item of workgroup b out of n.  Workgroups are handed to the 8 XCDs in
+// turn (b mod 8); each XCD is given a contiguous range of items instead, so
+// that neighbouring items, which share cache lines at their edges, meet in
+// the same L2.  A bijection of [0, n).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_item(int b, int n) {
+  const int x = b % kXcds, s = b / kXcds, q = n / kXcds, r = n % kXcds;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + s;
+}
+
+// One Stockham stage from src to dst (LDS) over B = 2^lgB interleaved pencils
+// stored sample-major with pitch Bp (sample t of pencil p at t*Bp + p):
+//   inputs  j + r n/R   (j = 0..n/R-1), twiddle exp(sign 2 pi i r k/(Ns R)) with k = j mod Ns,
+//   outputs (j/Ns) Ns R + k + r Ns.
+// One butterfly per loop trip keeps the register footprint to one radix.
 template <typename T, int R>
 __device__ __forceinline__ void fft_stage(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst,
-                                          const cx<T>* __restrict__ tw, int n, int Ns, int B,
+                                          const cx<T>* __restrict__ tw, int n, int Ns, int lgB, int Bp,
                                           int sign) {
   const int nb = n / R;
-  const int total = nb * B;
+  const int total = nb << lgB;
+  const int mask = (1 << lgB) - 1;
   const int tws = n / (Ns * R);
-  for (int e = threadIdx.x; e < total; e += blockDim.x) {
-    const int j = e / B, p = e - (e / B) * B;
-    const int k = j % Ns;
+  const float inv_ns = 1.0f / (float)Ns;
+  for (int e = threadIdx.x; e < total; e += kFftBlock) {
+    const int j = e >> lgB, p = e & mask;
+    const int jq = fdiv(j, inv_ns), k = j - jq * Ns;
     cx<T> v[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = src[(j + r * nb) * B + p];
+    for (int r = 0; r < R; ++r) v[r] = src[(j + r * nb) * Bp + p];
     if (Ns > 1) {
 #pragma unroll
       for (int r = 1; r < R; ++r) {
@@ -198,15 +216,16 @@ __device__ __forceinline__ void fft_stage(const cx<T>* __restrict__ src, cx<T>* 
       }
     }
     dft<T, R>(v, sign);
-    const int base = (j / Ns) * Ns * R + k;
+    const int base = jq * Ns * R + k;
 #pragma unroll
-    for (int r = 0; r < R; ++r) dst[(base + r * Ns) * B + p] = v[r];
+    for (int r = 0; r < R; ++r) dst[(base + r * Ns) * Bp + p] = v[r];
   }
 }
 
-// Runs all stages of class C; returns the buffer holding the result.
+// Runs all stages of class C, alternating between the two buffers; returns
+// the buffer holding the result.
 template <typename T>
-__device__ cx<T>* fft_run(cx<T>* b0, cx<T>* b1, const cx<T>* tw, const FftClass& C, int B,
+__device__ cx<T>* fft_run(cx<T>* b0, cx<T>* b1, const cx<T>* tw, const FftClass& C, int lgB, int Bp,
                           int sign) {
   cx<T>* src = b0;
   cx<T>* dst = b1;
@@ -214,12 +233,12 @@ __device__ cx<T>* fft_run(cx<T>* b0, cx<T>* b1, const cx<T>* tw, const FftClass&
   for (int s = 0; s < C.nst; ++s) {
     const int R = C.rad[s];
     switch (R) {
-      case 2: fft_stage<T, 2>(src, dst, tw, C.n, Ns, B, sign); break;
-      case 3: fft_stage<T, 3>(src, dst, tw, C.n, Ns, B, sign); break;
-      case 4: fft_stage<T, 4>(src, dst, tw, C.n, Ns, B, sign); break;
-      case 5: fft_stage<T, 5>(src, dst, tw, C.n, Ns, B, sign); break;
-      case 7: fft_stage<T, 7>(src, dst, tw, C.n, Ns, B, sign); break;
-      default: fft_stage<T, 8>(src, dst, tw, C.n, Ns, B, sign); break;
+      case 2: fft_stage<T, 2>(src, dst, tw, C.n, Ns, lgB, Bp, sign); break;
+      case 3: fft_stage<T, 3>(src, dst, tw, C.n, Ns, lgB, Bp, sign); break;
+      case 4: fft_stage<T, 4>(src, dst, tw, C.n, Ns, lgB, Bp, sign); break;
+      case 5: fft_stage<T, 5>(src, dst, tw, C.n, Ns, lgB, Bp, sign); break;
+      case 7: fft_stage<T, 7>(src, dst, tw, C.n, Ns, lgB, Bp, sign); break;
+      default: fft_stage<T, 8>(src, dst, tw, C.n, Ns, lgB, Bp, sign); break;
     }
     __syncthreads();
     cx<T>* tmp = src;
@@ -246,119 +265,141 @@ __device__ __forceinline__ T scale_factor(const FftClass& C, int b0, int b1, int
     }
     case G_TAB1:
       return s * gt[t];
+    // tables store the pencil index b0 fastest, so that neighbouring lanes
+    // (neighbouring pencils) read neighbouring entries
     case G_TAB2: {
       const int i0 = C.fold0 ? fold_index(b0, C.fold0) : b0;
-      return s * gt[(long long)i0 * C.gd2 + fold_index(t, C.fold2)];
+      return s * gt[(long long)fold_index(t, C.fold2) * C.gd0 + i0];
     }
     case G_TAB3: {
       const int i0 = C.fold0 ? fold_index(b0, C.fold0) : b0;
-      return s * gt[((long long)i0 * C.gd1 + fold_index(b1, C.fold1)) * C.gd2 + fold_index(t, C.fold2)];
+      return s * gt[((long long)fold_index(t, C.fold2) * C.gd1 + fold_index(b1, C.fold1)) * C.gd0 + i0];
     }
     default:
       return s;
   }
 }
 
+// Sample (t, p) of load/store slot e: pencil-major when the transform
+// direction is contiguous in memory (consecutive lanes walk one pencil),
+// sample-major otherwise (consecutive lanes walk neighbouring pencils).
+__device__ __forceinline__ void slot_tp(int e, bool t_fast, int n, float inv_n, int lgB, int* t, int* p) {
+  if (t_fast) {
+    *p = fdiv(e, inv_n);
+    *t = e - *p * n;
+  } else {
+    *t = e >> lgB;
+    *p = e & ((1 << lgB) - 1);
+  }
+}
+
 template <typename T, int KIND>
 __device__ void stage_fft(const FftPass& P, int item, unsigned char* smem) {
+  constexpr int U = 8;  // global accesses in flight per thread
   const int4 it = P.items[item];
   const FftClass& C = P.cls[it.x];
-  const int n = C.n, B = P.B, cnt = it.w, b0s = it.y, b1 = it.z;
+  const int n = C.n, lgB = P.lgB, Bp = (1 << lgB) + 1, cnt = it.w, b0s = it.y, b1 = it.z;
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem);
-  cx<T>* buf0 = tw + P.nmax;
-  cx<T>* buf1 = buf0 + (size_t)B * P.nmax;
+  cx<T>* buf = tw + P.nmax;
+  cx<T>* buf2 = buf + (size_t)P.nmax * Bp;
 
   const cx<T>* twg = reinterpret_cast<const cx<T>*>(C.tw);
   for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = twg[i];
 
-  // ---- load B pencils, zero padded to n ----
+  // ---- load the pencils, zero padded to n ----
   const bool t_fast = (C.in_st == 1);
-  const int total = n * B;
-  for (int e = threadIdx.x; e < total; e += blockDim.x) {
-    int t, p;
-    if (t_fast) {
-      p = e / n;
-      t = e - p * n;
-    } else {
-      t = e / B;
-      p = e - t * B;
-    }
-    cx<T> v = {0, 0};
-    if (p < cnt) {
-      const long long base = (long long)(b0s + p) * C.in_s0 + (long long)b1 * C.in_s1;
-      if constexpr (KIND == K_R2C) {
-        if (t < C.n_in) v.re = reinterpret_cast<const T*>(C.in)[base + (long long)t * C.in_st];
-      } else if constexpr (KIND == K_C2R) {
-        // Hermitian extension of the stored half spectrum (t <= n/2)
-        const int h = n >> 1;
-        const int ts = t <= h ? t : n - t;
-        v = reinterpret_cast<const cx<T>*>(C.in)[base + (long long)ts * C.in_st];
-        if (t > h) v.im = -v.im;
-      } else {
-        if (t < C.n_in) v = reinterpret_cast<const cx<T>*>(C.in)[base + (long long)t * C.in_st];
+  const float inv_n = 1.0f / (float)n;
+  const int total = n << lgB;
+  const long long bs1 = (long long)b1 * C.in_s1;
+  for (int e0 = 0; e0 < total; e0 += U * kFftBlock) {
+    cx<T> v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * kFftBlock + threadIdx.x;
+      int t, p;
+      slot_tp(e, t_fast, n, inv_n, lgB, &t, &p);
+      v[u] = cx<T>{0, 0};
+      if (e < total && p < cnt) {
+        const long long base = (long long)(b0s + p) * C.in_s0 + bs1;
+        if constexpr (KIND == K_R2C) {
+          if (t < C.n_in) v[u].re = reinterpret_cast<const T*>(C.in)[base + (long long)t * C.in_st];
+        } else if constexpr (KIND == K_C2R) {
+          // Hermitian extension of the stored half spectrum (t <= n/2)
+          const int h = n >> 1;
+          const int ts = t <= h ? t : n - t;
+          v[u] = reinterpret_cast<const cx<T>*>(C.in)[base + (long long)ts * C.in_st];
+          if (t > h) v[u].im = -v[u].im;
+        } else {
+          if (t < C.n_in) v[u] = reinterpret_cast<const cx<T>*>(C.in)[base + (long long)t * C.in_st];
+        }
       }
     }
-    buf0[t * B + p] = v;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * kFftBlock + threadIdx.x;
+      if (e < total) {
+        int t, p;
+        slot_tp(e, t_fast, n, inv_n, lgB, &t, &p);
+        buf[t * Bp + p] = v[u];
+      }
+    }
   }
   __syncthreads();
 
   cx<T>* res;
   if constexpr (KIND == K_C2C_INV || KIND == K_C2R) {
-    res = fft_run<T>(buf0, buf1, tw, C, B, +1);
+    res = fft_run<T>(buf, buf2, tw, C, lgB, Bp, +1);
   } else {
-    res = fft_run<T>(buf0, buf1, tw, C, B, -1);
+    res = fft_run<T>(buf, buf2, tw, C, lgB, Bp, -1);
   }
 
   if constexpr (KIND == K_FUSED) {
     // scaling step, Eq. (scale), on the spectrum of each pencil
+    const int mask = (1 << lgB) - 1;
     for (int e = threadIdx.x; e < total; e += blockDim.x) {
-      const int t = e / B, p = e - (e / B) * B;
-      if (p < cnt) res[e] = cscale(res[e], scale_factor<T>(C, b0s + p, b1, t));
+      const int t = e >> lgB, p = e & mask;
+      if (p < cnt) res[t * Bp + p] = cscale(res[t * Bp + p], scale_factor<T>(C, b0s + p, b1, t));
     }
     __syncthreads();
-    cx<T>* other = (res == buf0) ? buf1 : buf0;
-    res = fft_run<T>(res, other, tw, C, B, +1);
+    res = fft_run<T>(res, res == buf ? buf2 : buf, tw, C, lgB, Bp, +1);
   }
 
-  // ---- store the first n_out samples ----
+  // ---- store the first n_out samples (stores do not stall the thread) ----
   const bool to_fast = (C.out_st == 1);
-  const int totout = C.n_out * B;
-  for (int e = threadIdx.x; e < totout; e += blockDim.x) {
+  const int nout = C.n_out;
+  const float inv_no = 1.0f / (float)nout;
+  const int totout = nout << lgB;
+  const long long os1 = (long long)b1 * C.out_s1;
+  for (int e = threadIdx.x; e < totout; e += kFftBlock) {
     int t, p;
-    if (to_fast) {
-      p = e / C.n_out;
-      t = e - p * C.n_out;
-    } else {
-      t = e / B;
-      p = e - t * B;
-    }
+    slot_tp(e, to_fast, nout, inv_no, lgB, &t, &p);
     if (p >= cnt) continue;
-    const long long base = (long long)(b0s + p) * C.out_s0 + (long long)b1 * C.out_s1;
-    const cx<T> v = res[t * B + p];
+    const cx<T> v = res[t * Bp + p];
+    const long long idx = (long long)(b0s + p) * C.out_s0 + os1 + (long long)t * C.out_st;
     if constexpr (KIND == K_C2R) {
-      reinterpret_cast<T*>(C.out)[base + (long long)t * C.out_st] = v.re;
+      reinterpret_cast<T*>(C.out)[idx] = v.re;
     } else {
-      reinterpret_cast<cx<T>*>(C.out)[base + (long long)t * C.out_st] = v;
+      reinterpret_cast<cx<T>*>(C.out)[idx] = v;
     }
   }
 }
 
 template <typename T, int KIND>
-__global__ __launch_bounds__(kBlock) void fft_kernel(const FftPass P) {
+__global__ __launch_bounds__(kFftBlock) void fft_kernel(const FftPass P) {
   extern __shared__ __align__(16) unsigned char smem[];
-  stage_fft<T, KIND>(P, blockIdx.x, smem);
+  stage_fft<T, KIND>(P, xcd_item(blockIdx.x, gridDim.x), smem);
 }
 
 size_t fft_lds_bytes(const FftPass& p, bool f64) {
   const size_t c = f64 ? 16 : 8;
-  return c * ((size_t)p.nmax + 2 * (size_t)p.B * p.nmax);
+  return c * ((size_t)p.nmax + 2 * (((size_t)1 << p.lgB) + 1) * p.nmax);
 }
 
 template <typename T>
 static hipError_t launch_fft_t(const FftPass& p, hipStream_t st) {
   if (p.nitems <= 0) return hipSuccess;
   const size_t lds = fft_lds_bytes(p, sizeof(T) == 8);
-  const dim3 grid(p.nitems), block(kBlock);
+  const dim3 grid(p.nitems), block(kFftBlock);
   switch (p.kind) {
     case K_C2C_FWD: fft_kernel<T, K_C2C_FWD><<<grid, block, lds, st>>>(p); break;
     case K_C2C_INV: fft_kernel<T, K_C2C_INV><<<grid, block, lds, st>>>(p); break;
@@ -899,7 +940,7 @@ __device__ void stage_spread(const GridGeom& g, const EvalBuffers& b, int item, 
 template <typename T, int P>
 __global__ __launch_bounds__(kBlock) void spread_kernel(GridGeom g, EvalBuffers b) {
   extern __shared__ __align__(16) unsigned char smem[];
-  stage_spread<T, P>(g, b, blockIdx.x, smem);
+  stage_spread<T, P>(g, b, xcd_item(blockIdx.x, gridDim.x), smem);
 }
 
 // For one direction: the tile at offset d from tile t (wrapped in periodic
@@ -986,7 +1027,7 @@ __device__ void stage_fold(const GridGeom& g, const EvalBuffers& b, int item) {
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void fold_kernel(GridGeom g, EvalBuffers b) {
-  stage_fold<T>(g, b, blockIdx.x);
+  stage_fold<T>(g, b, xcd_item(blockIdx.x, gridDim.x));
 }
 
 template <typename T>
@@ -1202,7 +1243,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GridGeom g, EvalBuffers 
                                                         T* __restrict__ force, int out_grad,
                                                         double self_coef) {
   extern __shared__ __align__(16) unsigned char smem[];
-  stage_gather<T, P>(g, b, phi, force, out_grad, self_coef, blockIdx.x, smem);
+  stage_gather<T, P>(g, b, phi, force, out_grad, self_coef, xcd_item(blockIdx.x, gridDim.x), smem);
 }
 
 template <typename T>
@@ -1346,14 +1387,15 @@ __device__ void run_batch_stage(int st, const SysDesc& S, int sys_id, int li, co
 }
 
 // One stage of the batch for all systems: block b is work item b of the stage,
-// counted over the systems in order.  No block waits on another.
-template <typename T, int P>
+// counted over the systems in order.  No block waits on another.  The stage
+// is a template argument so that each stage's kernel carries only its own
+// registers and LDS.
+template <typename T, int P, int ST>
 __global__ __launch_bounds__(kBlock) void batch_stage_kernel(const SysDesc* __restrict__ sys, int nsys,
-                                                             const int* __restrict__ off, int st,
-                                                             BatchIO io) {
+                                                             const int* __restrict__ off, BatchIO io) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int* o = off + st * (nsys + 1);
-  const int item = blockIdx.x;
+  const int* o = off + ST * (nsys + 1);
+  const int item = xcd_item(blockIdx.x, gridDim.x);
   // the system owning this item: last s with o[s] <= item
   int lo = 0, hi = nsys - 1;
   while (lo < hi) {
@@ -1361,30 +1403,81 @@ __global__ __launch_bounds__(kBlock) void batch_stage_kernel(const SysDesc* __re
     if (o[mid] <= item) lo = mid;
     else hi = mid - 1;
   }
-  run_batch_stage<T, P>(st, sys[lo], lo, item - o[lo], io, smem);
+  lo = __builtin_amdgcn_readfirstlane(lo);  // uniform: keeps the descriptor in scalar registers
+  run_batch_stage<T, P>(ST, sys[lo], lo, item - o[lo], io, smem);
+}
+
+// One transform kind of one transform stage of the batch.
+template <typename T, int KIND>
+__global__ __launch_bounds__(kFftBlock) void batch_fft_kernel(const SysDesc* __restrict__ sys, int nsys,
+                                                              const int* __restrict__ o, int pass) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  int lo = 0, hi = nsys - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (o[mid] <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  lo = __builtin_amdgcn_readfirstlane(lo);  // uniform: keeps the descriptor in scalar registers
+  stage_fft<T, KIND>(sys[lo].pass[pass], item - o[lo], smem);
+}
+
+template <typename T, int P, int ST>
+static void batch_launch_one(const SysDesc* sys, int nsys, const int* off, const int* items, const BatchIO& io,
+                             const size_t* lds, hipStream_t st, hipEvent_t* ev) {
+  if (ev) (void)hipEventRecord(ev[ST], st);
+  if constexpr (ST >= BS_FFT0 && ST <= BS_FFT4) {
+    const int pass = ST - BS_FFT0;
+#define SE_FFT_KIND(K)                                                                                    \
+  if (items[fft_list(ST, K)] > 0)                                                                        \
+    batch_fft_kernel<T, K><<<dim3(items[fft_list(ST, K)]), dim3(kFftBlock), lds[ST], st>>>(              \
+        sys, nsys, off + fft_list(ST, K) * (nsys + 1), pass);
+    SE_FFT_KIND(K_C2C_FWD)
+    SE_FFT_KIND(K_C2C_INV)
+    SE_FFT_KIND(K_R2C)
+    SE_FFT_KIND(K_C2R)
+    SE_FFT_KIND(K_FUSED)
+#undef SE_FFT_KIND
+  } else {
+    if (items[ST] > 0)
+      batch_stage_kernel<T, P, ST><<<dim3(items[ST]), dim3(kBlock), lds[ST], st>>>(sys, nsys, off, io);
+  }
 }
 
 template <typename T, int P>
 static void batch_launch_t(const SysDesc* sys, int nsys, const int* off, const int* items, const BatchIO& io,
-                           size_t lds, hipStream_t st) {
-  for (int s = 0; s < BS_COUNT; ++s)
-    if (items[s] > 0)
-      batch_stage_kernel<T, P><<<dim3(items[s]), dim3(kBlock), lds, st>>>(sys, nsys, off, s, io);
+                           const size_t* lds, hipStream_t st, hipEvent_t* ev) {
+  batch_launch_one<T, P, BS_ZERO>(sys, nsys, off, items, io, lds, st, ev);
+  batch_launch_one<T, P, BS_BIN>(sys, nsys, off, items, io, lds, st, ev);
+  batch_launch_one<T, P, BS_SCAN1>(sys, nsys, off, items, io, lds, st, ev);
+  batch_launch_one<T, P, BS_SCAN2>(sys, nsys, off, items, io, lds, st, ev);
+  batch_launch_one<T, P, BS_SCATTER>(sys, nsys, off, items, io, lds, st, ev);
+  batch_launch_one<T, P, BS_SPREAD>(sys, nsys, off, items, io, lds, st, ev);
+  batch_launch_one<T, P, BS_FOLD>(sys, nsys, off, items, io, lds, st, ev);
+  batch_launch_one<T, P, BS_FFT0>(sys, nsys, off, items, io, lds, st, ev);
+  batch_launch_one<T, P, BS_FFT0 + 1>(sys, nsys, off, items, io, lds, st, ev);
+  batch_launch_one<T, P, BS_FFT0 + 2>(sys, nsys, off, items, io, lds, st, ev);
+  batch_launch_one<T, P, BS_FFT0 + 3>(sys, nsys, off, items, io, lds, st, ev);
+  batch_launch_one<T, P, BS_FFT0 + 4>(sys, nsys, off, items, io, lds, st, ev);
+  batch_launch_one<T, P, BS_GATHER>(sys, nsys, off, items, io, lds, st, ev);
+  batch_launch_one<T, P, BS_ENERGY>(sys, nsys, off, items, io, lds, st, ev);
+  if (ev) (void)hipEventRecord(ev[BS_COUNT], st);
 }
 
 hipError_t launch_batch(int P, bool f64, const SysDesc* sys, int nsys, const int* off, const int* items,
-                        const BatchIO& io, size_t lds, hipStream_t st) {
+                        const BatchIO& io, const size_t* lds, hipStream_t st, hipEvent_t* ev) {
   switch (P) {
-    case 4: f64 ? batch_launch_t<double, 4>(sys, nsys, off, items, io, lds, st)
-                : batch_launch_t<float, 4>(sys, nsys, off, items, io, lds, st); break;
-    case 6: f64 ? batch_launch_t<double, 6>(sys, nsys, off, items, io, lds, st)
-                : batch_launch_t<float, 6>(sys, nsys, off, items, io, lds, st); break;
-    case 8: f64 ? batch_launch_t<double, 8>(sys, nsys, off, items, io, lds, st)
-                : batch_launch_t<float, 8>(sys, nsys, off, items, io, lds, st); break;
-    case 10: f64 ? batch_launch_t<double, 10>(sys, nsys, off, items, io, lds, st)
-                 : batch_launch_t<float, 10>(sys, nsys, off, items, io, lds, st); break;
-    case 12: f64 ? batch_launch_t<double, 12>(sys, nsys, off, items, io, lds, st)
-                 : batch_launch_t<float, 12>(sys, nsys, off, items, io, lds, st); break;
+    case 4: f64 ? batch_launch_t<double, 4>(sys, nsys, off, items, io, lds, st, ev)
+                : batch_launch_t<float, 4>(sys, nsys, off, items, io, lds, st, ev); break;
+    case 6: f64 ? batch_launch_t<double, 6>(sys, nsys, off, items, io, lds, st, ev)
+                : batch_launch_t<float, 6>(sys, nsys, off, items, io, lds, st, ev); break;
+    case 8: f64 ? batch_launch_t<double, 8>(sys, nsys, off, items, io, lds, st, ev)
+                : batch_launch_t<float, 8>(sys, nsys, off, items, io, lds, st, ev); break;
+    case 10: f64 ? batch_launch_t<double, 10>(sys, nsys, off, items, io, lds, st, ev)
+                 : batch_launch_t<float, 10>(sys, nsys, off, items, io, lds, st, ev); break;
+    case 12: f64 ? batch_launch_t<double, 12>(sys, nsys, off, items, io, lds, st, ev)
+                 : batch_launch_t<float, 12>(sys, nsys, off, items, io, lds, st, ev); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1439,14 +1532,15 @@ hipError_t launch_g0p_truncate(const double* big, int n0, double* small, int Mt,
   return hipGetLastError();
 }
 
-// Octant (Mt+1)^3 of the real, even effective Green's function, index [kx][ky][kz].
+// Octant (Mt+1)^3 of the real, even effective Green's function, index
+// [kz][ky][kx] (kx fastest, as the grid).
 template <typename T>
 __global__ void g0p_fold_kernel(const cx<double>* full, int Mt, T* table) {
   const int n = 2 * Mt, m = Mt + 1;
   const long long N = (long long)m * m * m;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < N;
        e += (long long)gridDim.x * blockDim.x) {
-    const int k = (int)(e % m), j = (int)((e / m) % m), i = (int)(e / ((long long)m * m));
+    const int i = (int)(e % m), j = (int)((e / m) % m), k = (int)(e / ((long long)m * m));
     table[e] = (T)full[((long long)k * n + j) * n + i].re;
   }
 }

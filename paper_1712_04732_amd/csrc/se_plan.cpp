@@ -186,6 +186,7 @@ struct se_plan {
   int ev_used = 0;
   std::vector<ProfRec> prof;
   size_t lds_limit = 65536;   // soft budget: keeps several workgroups per CU
+  int fft_cap = 0;            // samples per FFT workgroup (0: by precision)
   size_t lds_max = 65536;     // device maximum per workgroup
   size_t bytes = 0;
 
@@ -287,12 +288,21 @@ static bool finish_pass(se_plan* pl, se::FftPass& ps, int kind, int ncls,
   ps.kind = kind;
   ps.nmax = 0;
   for (int c = 0; c < ncls; ++c) ps.nmax = std::max(ps.nmax, ps.cls[c].n);
+  // pencils per block: the largest power of two B <= 64 with n B within the
+  // samples cap and the LDS budget (twiddles n, samples n (B + 1))
   const size_t esz = pl->f64 ? 16 : 8;
-  long B = ((long)(pl->lds_limit / esz) - ps.nmax) / (2L * ps.nmax);
-  if (B < 1) B = ((long)(pl->lds_max / esz) - ps.nmax) / (2L * ps.nmax);
-  if (B < 1) return false;
-  B = std::min(64L, B);
-  ps.B = (int)B;
+  // (LDS: twiddles n, two sample buffers n (B + 1))
+  const long cap = pl->fft_cap > 0 ? pl->fft_cap : (pl->f64 ? 1024 : 2048);
+  auto lds_of = [&](long B2) { return esz * (size_t)ps.nmax * (1 + 2 * (B2 + 1)); };
+  int lgB = 0;
+  while (lgB < 6) {
+    const long B2 = 2L << lgB;
+    if ((long)ps.nmax * B2 > cap || lds_of(B2) > pl->lds_limit) break;
+    ++lgB;
+  }
+  if (lds_of(1L << lgB) > pl->lds_max) return false;
+  ps.lgB = lgB;
+  ps.B = 1 << lgB;
   std::vector<int4> items;
   for (const auto& r : ranges) add_items(items, r[0], r[1], r[2], r[3], r[4], ps.B);
   ps.nitems = (int)items.size();
@@ -446,14 +456,18 @@ static int fold_image_count(const se::GridGeom& g, int d) {
 }
 
 static se_status plan_create(const se_params* params, long n_max, void* hip_stream, size_t lds_soft,
-                             se_plan** out);
+                             long min_tiles, se_plan** out);
 
 se_status se_plan_create(const se_params* params, long n_max, void* hip_stream, se_plan** out) {
-  return plan_create(params, n_max, hip_stream, 65536, out);
+  return plan_create(params, n_max, hip_stream, 65536, 512, out);
 }
 
+// lds_soft: LDS budget per workgroup that keeps several workgroups per CU;
+// min_tiles: the automatic tile choice takes the largest tile shape that fits
+// the budget and still gives at least this many tiles (a lone system needs
+// many workgroups; a batch gets them from its other systems).
 static se_status plan_create(const se_params* params, long n_max, void* hip_stream, size_t lds_soft,
-                             se_plan** out) {
+                             long min_tiles, se_plan** out) {
   if (!params || !out || n_max < 0 || n_max > (1L << 30)) return SE_ERR_ARG;
   *out = nullptr;
   se_params p = *params;
@@ -495,6 +509,13 @@ static se_status plan_create(const se_params* params, long n_max, void* hip_stre
   pl->n_max = n_max;
   (void)hipGetDevice(&pl->device);
   pl->lds_limit = lds_soft;
+  if (p.fft_cap > 0) {
+    if (p.fft_cap < 1024 || p.fft_cap > se::kFftCap || (p.fft_cap & (p.fft_cap - 1))) {
+      delete pl;
+      return SE_ERR_PARAM;
+    }
+    pl->fft_cap = p.fft_cap;
+  }
   int lds = 0;
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, pl->device) == hipSuccess && lds > 0)
     pl->lds_max = std::max<size_t>(pl->lds_limit, (size_t)lds);
@@ -541,15 +562,27 @@ static se_status plan_create(const se_params* params, long n_max, void* hip_stre
   g.alpha = p.shape;
   g.scale = 4.0 * kPi * I.h * I.h * I.h;
   {
-    // Largest tile whose spread and gather LDS fit, with at least 512 tiles
-    // when the grid allows it.
+    // Largest tile whose spread and gather LDS fit, with at least min_tiles
+    // tiles when the grid allows it.
     static const int cands[][3] = {{16, 16, 16}, {32, 16, 8}, {16, 16, 8}, {16, 8, 8}, {8, 8, 8},
                                    {8, 8, 4},    {8, 4, 4},   {4, 4, 4}};
+    const bool explicit3 = p.tile3[0] > 0 && p.tile3[1] > 0 && p.tile3[2] > 0;
+    if (explicit3)
+      for (int d = 0; d < 3; ++d)
+        if (p.tile3[d] % se::kSB || p.tile3[d] > 32) {
+          delete pl;
+          return SE_ERR_PARAM;
+        }
     int best = -1, best_chunk = 64;
     for (size_t budget : {pl->lds_limit, pl->lds_max}) {
       for (int c = 0; c < (int)(sizeof(cands) / sizeof(cands[0])); ++c) {
-        if (p.tile > 0 && !(cands[c][0] == p.tile && cands[c][1] == p.tile && cands[c][2] == p.tile)) continue;
-        for (int d = 0; d < 3; ++d) g.T[d] = cands[c][d];
+        if (explicit3) {
+          if (c > 0) break;
+          for (int d = 0; d < 3; ++d) g.T[d] = p.tile3[d];
+        } else {
+          if (p.tile > 0 && !(cands[c][0] == p.tile && cands[c][1] == p.tile && cands[c][2] == p.tile)) continue;
+          for (int d = 0; d < 3; ++d) g.T[d] = cands[c][d];
+        }
         int fit = 0;
         for (int ch : {64, 32, 16}) {
           g.chunk = ch;
@@ -563,7 +596,7 @@ static se_status plan_create(const se_params* params, long n_max, void* hip_stre
         for (int d = 0; d < 3; ++d) nt *= (g.G[d] + g.T[d] - 1) / g.T[d];
         best = c;
         best_chunk = fit;
-        if (p.tile > 0 || nt >= 512) break;
+        if (explicit3 || p.tile > 0 || nt >= min_tiles) break;
       }
       if (best >= 0) break;
     }
@@ -572,9 +605,10 @@ static se_status plan_create(const se_params* params, long n_max, void* hip_stre
       return SE_ERR_UNSUPPORTED;
     }
     g.chunk = best_chunk;
-    for (int d = 0; d < 3; ++d) g.T[d] = cands[best][d];
+    for (int d = 0; d < 3; ++d) g.T[d] = explicit3 ? p.tile3[d] : cands[best][d];
   }
   for (int d = 0; d < 3; ++d) I.tile[d] = g.T[d];
+  I.fft_cap = pl->fft_cap > 0 ? pl->fft_cap : (pl->f64 ? 1024 : 2048);
   for (int d = 0; d < 3; ++d) {
     g.nt[d] = (g.G[d] + g.T[d] - 1) / g.T[d];
     g.nsb[d] = (g.G[d] + se::kSB - 1) / se::kSB;
@@ -782,7 +816,7 @@ static se_status build_passes(se_plan* pl) {
     c.gmode = se::G_TAB3;
     c.sA = c.sB = c.sC = sep;
     c.gtab = table;
-    c.gd1 = c.gd2 = Mt + 1;
+    c.gd0 = c.gd1 = Mt + 1;
     c.fold0 = 0;
     c.fold1 = c.fold2 = n;
     p3.cls[0] = c;
@@ -821,11 +855,12 @@ static se_status build_passes(se_plan* pl) {
   const void* kIt = pl->k2_table(nI);
   const void* kJt = pl->k2_table(Mt);
   const int h0 = n0 / 2 + 1;
+  // zero-mode Green's function over the folded (k_z, k_y) frequencies, [k_z][k_y]
   std::vector<double> g1((size_t)h0 * h0);
-  for (int i = 0; i < h0; ++i)
-    for (int j = 0; j < h0; ++j) {
-      const double ki = 2.0 * kPi * i / (n0 * I.h), kj = 2.0 * kPi * j / (n0 * I.h);
-      g1[(size_t)i * h0 + j] = g1p_zero(std::sqrt(ki * ki + kj * kj), I.R);
+  for (int iz = 0; iz < h0; ++iz)
+    for (int iy = 0; iy < h0; ++iy) {
+      const double ky = 2.0 * kPi * iy / (n0 * I.h), kz = 2.0 * kPi * iz / (n0 * I.h);
+      g1[(size_t)iz * h0 + iy] = g1p_zero(std::sqrt(ky * ky + kz * kz), I.R);
     }
   const void* g1t = pl->upload(g1);
   if (!twM || !tw0 || !twI || !twJ || !sepM || !k2M || !s0t || !sIt || !sJt || !kIt || !kJt || !g1t)
@@ -855,7 +890,7 @@ static se_status build_passes(se_plan* pl) {
     c0.sB = sepM;
     c0.sC = s0t;
     c0.gtab = g1t;
-    c0.gd2 = h0;
+    c0.gd0 = h0;
     c0.fold0 = n0;
     c0.fold2 = n0;
     se::FftClass cI = make_class(nI, Mt, Mt, twI, bI, bI, (long long)nI * nl, 1, nl, (long long)nI * nl, 1, nl);
@@ -1143,23 +1178,42 @@ struct se_batch_plan {
   long total = 0;
   se::SysDesc* d_sys = nullptr;
   int* d_off = nullptr;
-  int items[se::BS_COUNT] = {};
-  size_t lds = 0;
+  int items[se::BL_COUNT] = {};                // work items per list
+  size_t lds[se::BS_COUNT] = {};               // dynamic LDS per stage launch
   int P = 0;
   bool f64 = true;
   int device = 0;
-  double alg_bytes = 0.0, alg_flops = 0.0;   // per launch, summed over systems and stages
-  hipEvent_t ev[2] = {nullptr, nullptr};
+  // algorithmic counts of one evaluation per stage, summed over systems
+  double st_bytes[se::BS_COUNT] = {}, st_flops[se::BS_COUNT] = {};
+  hipEvent_t ev[se::BS_COUNT + 1] = {};
+  bool have_ev = false;
   int prof_pending = 0, prof_launches = 0;
-  double prof_ms = 0.0;
+  double st_ms[se::BS_COUNT] = {};
   ~se_batch_plan() {
-    if (ev[0]) (void)hipEventDestroy(ev[0]);
-    if (ev[1]) (void)hipEventDestroy(ev[1]);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
     if (d_sys) (void)hipFree(d_sys);
     if (d_off) (void)hipFree(d_off);
     for (se_plan* s : sys) delete s;
   }
+  // fold the timings of the last profiled evaluation in (events complete)
+  se_status collect() {
+    if (!prof_pending) return SE_OK;
+    if (hipEventSynchronize(ev[se::BS_COUNT]) != hipSuccess) return SE_ERR_DEVICE;
+    for (int k = 0; k < se::BS_COUNT; ++k) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[k], ev[k + 1]) != hipSuccess) return SE_ERR_DEVICE;
+      st_ms[k] += ms;
+    }
+    prof_launches += 1;
+    prof_pending = 0;
+    return SE_OK;
+  }
 };
+
+static const char* const kBatchStageNames[se::BS_COUNT] = {
+    "zero", "bin", "scan1", "scan2", "scatter", "spread", "fold",
+    "fft0", "fft1", "fft2", "fft3", "fft4", "gather", "energy"};
 
 extern "C" {
 
@@ -1181,12 +1235,11 @@ se_status se_batch_plan_create(const se_params* params, const long* N, int n_sys
   (void)hipGetDevice(&bp->device);
   hipStream_t st = (hipStream_t)hip_stream;
   std::vector<se::SysDesc> desc(n_sys);
-  std::vector<int> off((size_t)se::BS_COUNT * (n_sys + 1), 0);
+  std::vector<int> off((size_t)se::BL_COUNT * (n_sys + 1), 0);
   long run = 0;
   for (int s = 0; s < n_sys; ++s) {
     se_plan* sp = nullptr;
-    // a common LDS budget keeps several workgroups per CU in every stage
-    se_status rc = plan_create(&params[s], N[s], hip_stream, 48 * 1024, &sp);
+    se_status rc = plan_create(&params[s], N[s], hip_stream, 64 * 1024, 1, &sp);
     if (rc != SE_OK) {
       delete bp;
       return rc;
@@ -1215,34 +1268,48 @@ se_status se_batch_plan_create(const se_params* params, const long* N, int n_sys
                                      d.pass[0].nitems, d.pass[1].nitems, d.pass[2].nitems, d.pass[3].nitems,
                                      d.pass[4].nitems, d.ntiles, 1};
     for (int k = 0; k < se::BS_COUNT; ++k) off[(size_t)k * (n_sys + 1) + s + 1] = items[k];
-    bp->lds = std::max(bp->lds, se::spread_lds_bytes(sp->geom, bp->f64));
-    bp->lds = std::max(bp->lds, se::gather_lds_bytes(sp->geom, bp->f64));
-    for (int k = 0; k < se::kPasses; ++k) bp->lds = std::max(bp->lds, se::fft_lds_bytes(d.pass[k], bp->f64));
-    // algorithmic counts of one evaluation of this system (as for se_eval)
+    for (int k = 0; k < se::kPasses; ++k)
+      off[(size_t)se::fft_list(se::BS_FFT0 + k, d.pass[k].kind) * (n_sys + 1) + s + 1] = d.pass[k].nitems;
+    size_t* lds = bp->lds;
+    lds[se::BS_SPREAD] = std::max(lds[se::BS_SPREAD], se::spread_lds_bytes(sp->geom, bp->f64));
+    lds[se::BS_GATHER] = std::max(lds[se::BS_GATHER], se::gather_lds_bytes(sp->geom, bp->f64));
+    for (int k = 0; k < se::kPasses; ++k)
+      lds[se::BS_FFT0 + k] = std::max(lds[se::BS_FFT0 + k], se::fft_lds_bytes(d.pass[k], bp->f64));
+    // algorithmic counts of one evaluation of this system, per stage (as for se_eval)
     const double re = bp->f64 ? 8.0 : 4.0;
     const double G = (double)d.g.G[0] * d.g.G[1] * d.g.G[2];
     const double R3 = (double)(d.g.T[0] + P - 1) * (d.g.T[1] + P - 1) * (d.g.T[2] + P - 1);
     const int nu = std::max(d.g.nu, 5);
     const double n = (double)N[s];
-    bp->alg_bytes += n * 4.0 * re + n * 2.0 * (8.0 + 4.0 * re) + n * 4.0 * re + G * re +
-                     d.ntiles * R3 * re + G * re + n * 8.0 * re + G * re;
-    bp->alg_flops += n * 2.0 * (3.0 * P * nu + P * P + (double)P * P * P) + d.ntiles * R3 +
-                     n * 2.0 * (6.0 * P * nu + 3.0 * P * P + (double)P * P * (2 * P + 4));
+    double* by = bp->st_bytes;
+    double* fl = bp->st_flops;
+    by[se::BS_ZERO] += sp->nsbtot * 4.0;
+    by[se::BS_BIN] += n * 4.0 * re;
+    by[se::BS_SCAN1] += sp->nsbtot * 8.0;
+    by[se::BS_SCAN2] += sp->nsbtot * 8.0;
+    by[se::BS_SCATTER] += n * 2.0 * (8.0 + 4.0 * re);
+    by[se::BS_SPREAD] += n * 4.0 * re + d.ntiles * R3 * re;
+    fl[se::BS_SPREAD] += n * 2.0 * (3.0 * P * nu + P * P + (double)P * P * P);
+    by[se::BS_FOLD] += d.ntiles * R3 * re + G * re;
+    fl[se::BS_FOLD] += d.ntiles * R3;
     for (int k = 0; k < se::kPasses; ++k) {
-      bp->alg_bytes += d.pass[k].alg_bytes;
-      bp->alg_flops += d.pass[k].alg_flops;
+      by[se::BS_FFT0 + k] += d.pass[k].alg_bytes;
+      fl[se::BS_FFT0 + k] += d.pass[k].alg_flops;
     }
+    by[se::BS_GATHER] += n * 8.0 * re + G * re;
+    fl[se::BS_GATHER] += n * 2.0 * (6.0 * P * nu + 3.0 * P * P + (double)P * P * (2 * P + 4));
+    by[se::BS_ENERGY] += d.ntiles * 8.0 + 8.0;
   }
   bp->total = run;
-  for (int k = 0; k < se::BS_COUNT; ++k)
+  for (int k = 0; k < se::BL_COUNT; ++k)
     for (int s = 0; s < n_sys; ++s) off[(size_t)k * (n_sys + 1) + s + 1] += off[(size_t)k * (n_sys + 1) + s];
   int lds_max = 0;
   (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, bp->device);
-  if (lds_max > 0 && bp->lds > (size_t)lds_max) {
+  if (lds_max > 0 && *std::max_element(bp->lds, bp->lds + se::BS_COUNT) > (size_t)lds_max) {
     delete bp;
     return SE_ERR_UNSUPPORTED;
   }
-  for (int k = 0; k < se::BS_COUNT; ++k) bp->items[k] = off[(size_t)k * (n_sys + 1) + n_sys];
+  for (int k = 0; k < se::BL_COUNT; ++k) bp->items[k] = off[(size_t)k * (n_sys + 1) + n_sys];
   if (hipMalloc(&bp->d_sys, sizeof(se::SysDesc) * n_sys) != hipSuccess ||
       hipMalloc(&bp->d_off, sizeof(int) * off.size()) != hipSuccess) {
     delete bp;
@@ -1289,50 +1356,53 @@ se_status se_eval_batch(se_batch_plan* plan, const void* xyz, const void* q, voi
   io.add_self = (flags & SE_ADD_SELF) ? 1 : 0;
   io.allow_nonneutral = (flags & SE_ALLOW_NONNEUTRAL) ? 1 : 0;
   const bool prof = (flags & SE_PROFILE) != 0;
-  if (prof && !plan->ev[0]) {
-    if (hipEventCreate(&plan->ev[0]) != hipSuccess || hipEventCreate(&plan->ev[1]) != hipSuccess)
-      return SE_ERR_DEVICE;
+  if (prof && !plan->have_ev) {
+    for (hipEvent_t& e : plan->ev)
+      if (hipEventCreate(&e) != hipSuccess) return SE_ERR_DEVICE;
+    plan->have_ev = true;
   }
-  if (prof && plan->prof_pending) {
-    // the previous profiled launch: fold its time in before reusing the events
-    float ms = 0.f;
-    if (hipEventSynchronize(plan->ev[1]) != hipSuccess ||
-        hipEventElapsedTime(&ms, plan->ev[0], plan->ev[1]) != hipSuccess)
-      return SE_ERR_DEVICE;
-    plan->prof_ms += ms;
-    plan->prof_launches += 1;
-    plan->prof_pending = 0;
-  }
-  if (prof && hipEventRecord(plan->ev[0], st) != hipSuccess) return SE_ERR_DEVICE;
+  // the previous profiled evaluation: fold its times in before reusing the events
+  if (prof && plan->collect() != SE_OK) return SE_ERR_DEVICE;
   if (se::launch_batch(plan->P, plan->f64, plan->d_sys, (int)plan->sys.size(), plan->d_off, plan->items, io,
-                       plan->lds, st) != hipSuccess)
+                       plan->lds, st, prof ? plan->ev : nullptr) != hipSuccess)
     return SE_ERR_DEVICE;
-  if (prof) {
-    if (hipEventRecord(plan->ev[1], st) != hipSuccess) return SE_ERR_DEVICE;
-    plan->prof_pending = 1;
-  }
+  if (prof) plan->prof_pending = 1;
   if (flags & SE_SYNC_CHECK) return se_batch_get_device_status(plan, hip_stream);
   return SE_OK;
 }
 
-se_status se_batch_plan_profile(se_batch_plan* plan, void* hip_stream, se_stage_record* out, int reset) {
-  if (!plan || !out) return SE_ERR_ARG;
+se_status se_batch_plan_profile(se_batch_plan* plan, void* hip_stream, se_stage_record* out, int cap, int* n,
+                                int reset) {
+  if (!plan || !out || !n || cap < 0) return SE_ERR_ARG;
   if (hipStreamSynchronize((hipStream_t)hip_stream) != hipSuccess) return SE_ERR_DEVICE;
-  if (plan->prof_pending) {
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, plan->ev[0], plan->ev[1]) != hipSuccess) return SE_ERR_DEVICE;
-    plan->prof_ms += ms;
-    plan->prof_launches += 1;
-    plan->prof_pending = 0;
+  if (plan->collect() != SE_OK) return SE_ERR_DEVICE;
+  int k_out = 0;
+  double ms_all = 0.0, by_all = 0.0, fl_all = 0.0;
+  for (int k = 0; k < se::BS_COUNT; ++k) {
+    ms_all += plan->st_ms[k];
+    by_all += plan->st_bytes[k];
+    fl_all += plan->st_flops[k];
+    if (plan->items[k] == 0 || k_out >= cap) continue;
+    se_stage_record& r = out[k_out++];
+    std::memset(&r, 0, sizeof(r));
+    std::snprintf(r.name, sizeof(r.name), "%s", kBatchStageNames[k]);
+    r.launches = plan->prof_launches;
+    r.ms_total = plan->st_ms[k];
+    r.bytes = plan->st_bytes[k];
+    r.flops = plan->st_flops[k];
   }
-  std::memset(out, 0, sizeof(*out));
-  std::snprintf(out->name, sizeof(out->name), "batch_all_stages");
-  out->launches = plan->prof_launches;
-  out->ms_total = plan->prof_ms;
-  out->bytes = plan->alg_bytes;
-  out->flops = plan->alg_flops;
+  if (k_out < cap) {
+    se_stage_record& r = out[k_out++];
+    std::memset(&r, 0, sizeof(r));
+    std::snprintf(r.name, sizeof(r.name), "batch_all_stages");
+    r.launches = plan->prof_launches;
+    r.ms_total = ms_all;
+    r.bytes = by_all;
+    r.flops = fl_all;
+  }
+  *n = k_out;
   if (reset) {
-    plan->prof_ms = 0.0;
+    for (double& m : plan->st_ms) m = 0.0;
     plan->prof_launches = 0;
   }
   return SE_OK;

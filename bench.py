@@ -5,7 +5,7 @@ One step = one evaluation of the whole path (bin, spread, transforms with
 scaling, gather of potentials and forces, FP64 energy) on one batch of
 synthetic input already resident in HBM.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+  python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline] [--no-tune]
 """
 from __future__ import annotations
 
@@ -53,6 +53,7 @@ def roofline(stages, prec):
         r = {"bound": "alu", "achieved": fl / 1e12, "peak": ALU_PEAK[prec] / 1e12, "unit": "TFLOP/s",
              "frac": f_alu}
     r["traffic"] = traffic
+    r["traffic_unit"] = "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     r["kernel"] = dom["name"]
     r["ms_avg"] = dom["ms_avg"]
     r["alg_bytes"] = dom["bytes"]
@@ -134,6 +135,32 @@ def batch_cpu_baseline(systems, budget_s=15.0, per_sys_targets=256):
                       f"each against all of its sources, {t_tot:.1f} s"}, res
 
 
+_KNOBS = ("tile3", "fft_cap", "xcd_tiles", "xcd_fft")
+
+
+def _save_schedule(path, params):
+    """The autotuner's knobs, one entry per system (with D and M to check
+    that a stored schedule belongs to the same batch)."""
+    rows = [dict(D=p.D, M=p.M, tile3=list(p.tile3), fft_cap=p.fft_cap, xcd_tiles=p.xcd_tiles, xcd_fft=p.xcd_fft)
+            for p in params]
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    with open(path, "w") as f:
+        f.write('{"device": "MI355X (gfx950)", "systems": [\n')
+        f.write(",\n".join(json.dumps(r) for r in rows))
+        f.write("\n]}\n")
+
+
+def _load_schedule(path, params):
+    rows = json.load(open(path))["systems"]
+    if len(rows) != len(params) or any(r["D"] != p.D or r["M"] != p.M for r, p in zip(rows, params)):
+        return False
+    for r, p in zip(rows, params):
+        for d in range(3):
+            p.tile3[d] = r["tile3"][d]
+        p.fft_cap, p.xcd_tiles, p.xcd_fft = r["fft_cap"], r["xcd_tiles"], r["xcd_fft"]
+    return True
+
+
 def main_batch(args):
     import numpy as np
     import torch
@@ -156,6 +183,25 @@ def main_batch(args):
     t0 = time.perf_counter()
     b32 = SpectralEwaldBatch(p32, N)
     t_plan = time.perf_counter() - t0
+    tune_rep = None
+    sched_path = args.schedule or os.path.join(ROOT, "paper_1712_04732_amd", "schedules", "c5_batch.json")
+    if args.no_tune:
+        schedule = "default"
+    elif os.path.exists(sched_path) and not args.retune and _load_schedule(sched_path, p32):
+        schedule = f"autotuned, stored ({os.path.relpath(sched_path, ROOT)})"
+        b32 = SpectralEwaldBatch(p32, N)
+    else:
+        t0 = time.perf_counter()
+        b32, tune_rep = SpectralEwaldBatch.tuned(p32, N, x, q)
+        tune_rep["seconds"] = time.perf_counter() - t0
+        schedule = "autotuned"
+        print(f"bench: autotuner {tune_rep['candidates']} candidates in {tune_rep['seconds']:.1f} s: "
+              f"{tune_rep['ms_default']:.2f} -> {tune_rep['ms_tuned']:.2f} ms", file=sys.stderr, flush=True)
+        if args.save_schedule:
+            _save_schedule(args.save_schedule, b32.params)
+    tiles = sorted({tuple(b32.info(k).tile) for k in range(len(N))})
+    caps = sorted({b32.info(k).fft_cap for k in range(len(N))})
+    print(f"bench: schedule {schedule}: tiles {tiles} fft_cap {caps}", file=sys.stderr, flush=True)
     print(f"bench: batch of {len(N)} systems, sum N = {tot}, D counts "
           f"{np.bincount([s['D'] for s in systems], minlength=4).tolist()}, M {min(p.M for p in p32)}.."
           f"{max(p.M for p in p32)}, plan {t_plan:.1f} s",
@@ -217,7 +263,13 @@ def main_batch(args):
     roof = roofline(stages, "f32")
     stage_ids = {"zero": 0, "bin": 1, "scan1": 2, "scan2": 3, "scatter": 4, "spread": 5, "fold": 6,
                  "fft0": 7, "fft1": 8, "fft2": 9, "fft3": 10, "fft4": 11, "gather": 12, "energy": 13}
-    roof["kernel"] = f"batch_stage_kernel<float, {cfg['P']}, {stage_ids[roof['kernel']]}> ({roof['kernel']})"
+    st_name = roof["kernel"]
+    if st_name == "fft2":
+        roof["kernel"] = "batch_fft_kernel<float, 4> (fft2: fused forward transform, scaling, inverse transform)"
+    elif st_name.startswith("fft"):
+        roof["kernel"] = f"batch_fft_kernel<float, *> ({st_name}: one launch per transform kind)"
+    else:
+        roof["kernel"] = f"batch_stage_kernel<float, {cfg['P']}, {stage_ids[st_name]}> ({st_name})"
     roof["whole_eval_ms"] = whole["ms_avg"]
 
     result = {
@@ -235,12 +287,14 @@ def main_batch(args):
         "data": "synthetic",
         "config": {"workload": "C5_batch", "n_sys": len(N), "sum_N": tot, "P": cfg["P"], "window": cfg["window"],
                    "tol_rel": cfg["tol_rel"], "xi": "1.2 N^(1/3)/L", "charges": cfg["charges"],
-                   "outputs": "potential+force+energy", "launch": "one launch per stage over all systems"},
+                   "outputs": "potential+force+energy", "launch": "one launch per stage over all systems",
+                   "schedule": schedule},
         "fp64_plain_value": tot / (ms64 * 1e-3),
         "fp64_plain_ms_per_step": ms64,
         "speedup_vs_fp64_plain": ms64 / ms32,
         "roofline": roof,
         "errors": err,
+        "autotune": tune_rep,
     }
     if not args.no_cpu_baseline:
         cb, res = batch_cpu_baseline(systems)
@@ -277,7 +331,22 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="C5_batch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="batch: keep the default schedule knobs")
+    ap.add_argument("--retune", action="store_true", help="batch: run the autotuner even if a schedule is stored")
+    ap.add_argument("--schedule", default=None, help="batch: stored schedule (JSON) to use")
+    ap.add_argument("--save-schedule", default=None, help="batch: write the autotuner's schedule here")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 256 MiB device to device 5 times (reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.empty(64 << 20, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": 2 * a.numel() * 4}), flush=True)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the Spectral Ewald path here runs on a single "

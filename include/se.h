@@ -84,6 +84,9 @@ typedef struct {
                          all > 0 -> used instead of 'tile'                          */
   int fft_cap;        /* samples (length x pencils) per FFT workgroup: a power of two
                          in 1024..8192; <= 0 -> 2048 (FP32) / 1024 (FP64)          */
+  int xcd_tiles;      /* workgroup -> tile mapping of spread, fold and gather:
+                         > 0 contiguous tile ranges per XCD, < 0 round robin, 0 -> on */
+  int xcd_fft;        /* the same for the transform passes' pencil groups            */
 } se_params;
 
 /* Derived sizes of a plan (read-only report). */
@@ -237,6 +240,37 @@ se_status se_batch_get_device_status(se_batch_plan* plan, void* hip_stream);
 
 /* Release the batch plan and its sub-plans.  NULL is accepted. */
 se_status se_batch_plan_destroy(se_batch_plan* plan);
+
+/* ---- autotuner ---------------------------------------------------------
+ * Schedule knobs (tile3, fft_cap, xcd_tiles, xcd_fft) chosen by timing
+ * candidate plans on the caller's own input with HIP events: first the tile
+ * shape of spread / fold / gather (their summed time), then the FFT samples
+ * per workgroup (the transform passes' time), then the XCD mappings.  The
+ * result is kept only if the whole evaluation is faster than with the
+ * default knobs.  The numbers computed by a tuned plan are those of the
+ * default plan up to rounding (the method's parameters are not touched). */
+typedef struct {
+  int candidates;      /* settings timed                                          */
+  double ms_default;   /* one evaluation with the default knobs (sum of launches) */
+  double ms_tuned;     /* one evaluation with the chosen knobs                    */
+} se_tune_report;
+
+/* Tune one system.  params: the plan parameters (method fields as for
+ * se_plan_create); xyz, q: device input of N >= 1 particles (float64, or
+ * float32 with flags SE_IN_F32; SE_ALLOW_NONNEUTRAL accepted); tuned: host,
+ * receives params with the knobs set; report: host or NULL.  Allocates
+ * temporary output buffers and creates and destroys one plan per candidate
+ * on 'hip_stream'; the stream is synchronised.
+ * Errors: SE_ERR_ARG, SE_ERR_NOMEM, SE_ERR_UNSUPPORTED (no candidate ran). */
+se_status se_autotune(const se_params* params, long N, const void* xyz, const void* q, unsigned flags,
+                      void* hip_stream, se_params* tuned, se_tune_report* report);
+
+/* Tune a batch (arguments as for se_batch_plan_create and se_eval_batch):
+ * tile shape and FFT samples per workgroup are chosen for each periodicity
+ * class on that class's systems, then one XCD mapping for the whole batch.
+ * tuned: host array of n_sys params. */
+se_status se_batch_autotune(const se_params* params, const long* N, int n_sys, const void* xyz, const void* q,
+                            unsigned flags, void* hip_stream, se_params* tuned, se_tune_report* report);
 
 /* Static English text of a status code. */
 const char* se_status_string(se_status s);

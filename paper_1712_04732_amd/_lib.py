@@ -55,6 +55,16 @@ class se_params(ctypes.Structure):
         ("tile", ctypes.c_int),
         ("tile3", ctypes.c_int * 3),
         ("fft_cap", ctypes.c_int),
+        ("xcd_tiles", ctypes.c_int),
+        ("xcd_fft", ctypes.c_int),
+    ]
+
+
+class se_tune_report(ctypes.Structure):
+    _fields_ = [
+        ("candidates", ctypes.c_int),
+        ("ms_default", ctypes.c_double),
+        ("ms_tuned", ctypes.c_double),
     ]
 
 
@@ -128,6 +138,12 @@ _SIGS = {
                                              ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
     "se_batch_get_device_status": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "se_batch_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "se_autotune": (ctypes.c_int, [ctypes.POINTER(se_params), ctypes.c_long, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_uint, ctypes.c_void_p, ctypes.POINTER(se_params),
+                                   ctypes.POINTER(se_tune_report)]),
+    "se_batch_autotune": (ctypes.c_int, [ctypes.POINTER(se_params), ctypes.POINTER(ctypes.c_long), ctypes.c_int,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint, ctypes.c_void_p,
+                                         ctypes.POINTER(se_params), ctypes.POINTER(se_tune_report)]),
 }
 
 
@@ -249,6 +265,28 @@ def se_batch_plan_profile(plan, stream, reset=True):
         out.append(dict(name=r.name.decode(), launches=r.launches, ms_total=r.ms_total,
                         ms_avg=r.ms_total / max(r.launches, 1), bytes=r.bytes, flops=r.flops))
     return out
+
+
+def se_autotune(params, N, xyz_ptr, q_ptr, flags, stream):
+    """Tuned copy of params and the report (dict)."""
+    out = se_params()
+    rep = se_tune_report()
+    _check(load().se_autotune(ctypes.byref(params), int(N), ctypes.c_void_p(xyz_ptr), ctypes.c_void_p(q_ptr),
+                              int(flags), ctypes.c_void_p(stream), ctypes.byref(out), ctypes.byref(rep)),
+           "se_autotune")
+    return out, dict(candidates=rep.candidates, ms_default=rep.ms_default, ms_tuned=rep.ms_tuned)
+
+
+def se_batch_autotune(params, N, xyz_ptr, q_ptr, flags, stream):
+    n = len(params)
+    arr = (se_params * n)(*params)
+    outs = (se_params * n)()
+    Ns = (ctypes.c_long * n)(*[int(v) for v in N])
+    rep = se_tune_report()
+    _check(load().se_batch_autotune(arr, Ns, n, ctypes.c_void_p(xyz_ptr), ctypes.c_void_p(q_ptr), int(flags),
+                                    ctypes.c_void_p(stream), outs, ctypes.byref(rep)), "se_batch_autotune")
+    return [outs[i] for i in range(n)], dict(candidates=rep.candidates, ms_default=rep.ms_default,
+                                             ms_tuned=rep.ms_tuned)
 
 
 def se_batch_plan_destroy(plan) -> int:

@@ -63,6 +63,32 @@ class SpectralEwald:
         self._plan = L.se_plan_create(p, self.n_max, _stream())
         self.info = L.se_plan_get_info(self._plan)
 
+    @classmethod
+    def from_params(cls, p, n_max):
+        """A plan from a filled se_params (for example one returned by
+        autotune)."""
+        self = cls.__new__(cls)
+        if not torch.cuda.is_available():
+            raise RuntimeError("SpectralEwald needs a HIP device")
+        L.load()
+        self.params = p
+        self.n_max = int(n_max)
+        self.prec = "f64" if p.prec == L.SE_F64 else "f32"
+        self.dtype = torch.float64 if p.prec == L.SE_F64 else torch.float32
+        self.D, self.L, self.xi = p.D, p.L, p.xi
+        self._plan = L.se_plan_create(p, self.n_max, _stream())
+        self.info = L.se_plan_get_info(self._plan)
+        return self
+
+    def autotune(self, x, q, allow_nonneutral=False):
+        """Schedule knobs timed on the input (x, q); returns a new plan with
+        the chosen knobs and the tuner's report."""
+        x, q = _device_pair(x, q)
+        flags = (L.SE_IN_F32 if x.dtype == torch.float32 else 0) | (
+            L.SE_ALLOW_NONNEUTRAL if allow_nonneutral else 0)
+        p, rep = L.se_autotune(self.params, x.shape[0], x.data_ptr(), q.data_ptr(), flags, _stream())
+        return SpectralEwald.from_params(p, self.n_max), rep
+
     def __del__(self):
         plan = getattr(self, "_plan", None)
         if plan is not None and plan.value:
@@ -120,6 +146,16 @@ class SpectralEwald:
     __call__ = evaluate
 
 
+def _device_pair(x, q):
+    if x.dim() != 2 or x.shape[1] != 3 or q.dim() != 1 or q.shape[0] != x.shape[0]:
+        raise ValueError("x must be (N,3) and q (N,)")
+    if x.dtype != q.dtype or x.dtype not in (torch.float32, torch.float64):
+        raise ValueError("x and q must share dtype float32 or float64")
+    if not (x.is_cuda and q.is_cuda):
+        raise ValueError("x and q must be device tensors")
+    return x.contiguous(), q.contiguous()
+
+
 def _params(D, L_box, xi, M, P, window="pkb", prec="f64", Q=None, tol=None, s=None, n_l=None, tile=0):
     w = _WINDOWS[window]
     pr = _PRECS[prec]
@@ -160,6 +196,18 @@ class SpectralEwaldBatch:
         self.total = sum(self.N)
         self.dtype = torch.float64 if self.params[0].prec == L.SE_F64 else torch.float32
         self._plan = L.se_batch_plan_create(self.params, self.N, _stream())
+
+    @classmethod
+    def tuned(cls, params, N, x, q, allow_nonneutral=False):
+        """A batch plan whose schedule knobs the autotuner chose on the input
+        (x, q); returns (plan, report)."""
+        if not torch.cuda.is_available():
+            raise RuntimeError("SpectralEwaldBatch needs a HIP device")
+        x, q = x.contiguous(), q.contiguous()
+        flags = (L.SE_IN_F32 if x.dtype == torch.float32 else 0) | (
+            L.SE_ALLOW_NONNEUTRAL if allow_nonneutral else 0)
+        tp, rep = L.se_batch_autotune(list(params), N, x.data_ptr(), q.data_ptr(), flags, _stream())
+        return cls(tp, N), rep
 
     def info(self, sys):
         return L.se_batch_plan_get_info(self._plan, sys)[0]

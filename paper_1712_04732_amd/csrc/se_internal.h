@@ -70,6 +70,7 @@ struct FftPass {
   int lgB;
   int nmax;                       // largest n (LDS sizing)
   int kind;
+  int xcd;                        // 1: XCD-contiguous item mapping
   double alg_bytes, alg_flops;    // algorithmic counts of one launch (tracing only)
 };
 
@@ -83,6 +84,7 @@ struct GridGeom {
   int nt[3];          // tiles per direction
   int nsb[3];         // sub-bins per direction, ceil(G / kSB)
   int chunk;          // particles per wavefront round of the spread kernel (<= 64)
+  int xcd;            // 1: XCD-contiguous tile mapping
   int P, nu;
   int window;         // 0 Gaussian, 1 PKB
   double h, L, xi;
@@ -135,6 +137,7 @@ struct BatchIO {
   void* force;
   double* energy;     // one per system
   int in_f32, out_grad, add_self, allow_nonneutral;
+  int xcd_tiles, xcd_fft;   // XCD-contiguous item mapping of the tile / transform stages
 };
 
 // Stages of a batched evaluation, in order; one launch per stage.

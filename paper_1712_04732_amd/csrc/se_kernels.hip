@@ -186,6 +186,7 @@ __device__ __forceinline__ int xcd_item(int b, int n) {
   const int x = b % kXcds, s = b / kXcds, q = n / kXcds, r = n % kXcds;
   return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + s;
 }
+__device__ __forceinline__ int work_item(int on) { return on ? xcd_item(blockIdx.x, gridDim.x) : blockIdx.x; }
 
 // One Stockham stage from src to dst (LDS) over B = 2^lgB interleaved pencils
 // stored sample-major with pitch Bp (sample t of pencil p at t*Bp + p):
@@ -387,7 +388,7 @@ __device__ void stage_fft(const FftPass& P, int item, unsigned char* smem) {
 template <typename T, int KIND>
 __global__ __launch_bounds__(kFftBlock) void fft_kernel(const FftPass P) {
   extern __shared__ __align__(16) unsigned char smem[];
-  stage_fft<T, KIND>(P, xcd_item(blockIdx.x, gridDim.x), smem);
+  stage_fft<T, KIND>(P, work_item(P.xcd), smem);
 }
 
 size_t fft_lds_bytes(const FftPass& p, bool f64) {
@@ -940,7 +941,7 @@ __device__ void stage_spread(const GridGeom& g, const EvalBuffers& b, int item, 
 template <typename T, int P>
 __global__ __launch_bounds__(kBlock) void spread_kernel(GridGeom g, EvalBuffers b) {
   extern __shared__ __align__(16) unsigned char smem[];
-  stage_spread<T, P>(g, b, xcd_item(blockIdx.x, gridDim.x), smem);
+  stage_spread<T, P>(g, b, work_item(g.xcd), smem);
 }
 
 // For one direction: the tile at offset d from tile t (wrapped in periodic
@@ -1027,7 +1028,7 @@ __device__ void stage_fold(const GridGeom& g, const EvalBuffers& b, int item) {
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void fold_kernel(GridGeom g, EvalBuffers b) {
-  stage_fold<T>(g, b, xcd_item(blockIdx.x, gridDim.x));
+  stage_fold<T>(g, b, work_item(g.xcd));
 }
 
 template <typename T>
@@ -1243,7 +1244,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GridGeom g, EvalBuffers 
                                                         T* __restrict__ force, int out_grad,
                                                         double self_coef) {
   extern __shared__ __align__(16) unsigned char smem[];
-  stage_gather<T, P>(g, b, phi, force, out_grad, self_coef, xcd_item(blockIdx.x, gridDim.x), smem);
+  stage_gather<T, P>(g, b, phi, force, out_grad, self_coef, work_item(g.xcd), smem);
 }
 
 template <typename T>
@@ -1392,10 +1393,10 @@ __device__ void run_batch_stage(int st, const SysDesc& S, int sys_id, int li, co
 // registers and LDS.
 template <typename T, int P, int ST>
 __global__ __launch_bounds__(kBlock) void batch_stage_kernel(const SysDesc* __restrict__ sys, int nsys,
-                                                             const int* __restrict__ off, BatchIO io) {
+                                                             const int* __restrict__ off, BatchIO io, int xcd) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int* o = off + ST * (nsys + 1);
-  const int item = xcd_item(blockIdx.x, gridDim.x);
+  const int item = work_item(xcd);
   // the system owning this item: last s with o[s] <= item
   int lo = 0, hi = nsys - 1;
   while (lo < hi) {
@@ -1410,9 +1411,9 @@ __global__ __launch_bounds__(kBlock) void batch_stage_kernel(const SysDesc* __re
 // One transform kind of one transform stage of the batch.
 template <typename T, int KIND>
 __global__ __launch_bounds__(kFftBlock) void batch_fft_kernel(const SysDesc* __restrict__ sys, int nsys,
-                                                              const int* __restrict__ o, int pass) {
+                                                              const int* __restrict__ o, int pass, int xcd) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int item = xcd_item(blockIdx.x, gridDim.x);
+  const int item = work_item(xcd);
   int lo = 0, hi = nsys - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -1432,7 +1433,7 @@ static void batch_launch_one(const SysDesc* sys, int nsys, const int* off, const
 #define SE_FFT_KIND(K)                                                                                    \
   if (items[fft_list(ST, K)] > 0)                                                                        \
     batch_fft_kernel<T, K><<<dim3(items[fft_list(ST, K)]), dim3(kFftBlock), lds[ST], st>>>(              \
-        sys, nsys, off + fft_list(ST, K) * (nsys + 1), pass);
+        sys, nsys, off + fft_list(ST, K) * (nsys + 1), pass, io.xcd_fft);
     SE_FFT_KIND(K_C2C_FWD)
     SE_FFT_KIND(K_C2C_INV)
     SE_FFT_KIND(K_R2C)
@@ -1441,7 +1442,8 @@ static void batch_launch_one(const SysDesc* sys, int nsys, const int* off, const
 #undef SE_FFT_KIND
   } else {
     if (items[ST] > 0)
-      batch_stage_kernel<T, P, ST><<<dim3(items[ST]), dim3(kBlock), lds[ST], st>>>(sys, nsys, off, io);
+      batch_stage_kernel<T, P, ST><<<dim3(items[ST]), dim3(kBlock), lds[ST], st>>>(
+          sys, nsys, off, io, (ST == BS_SPREAD || ST == BS_FOLD || ST == BS_GATHER) ? io.xcd_tiles : 0);
   }
 }
 

@@ -303,6 +303,7 @@ static bool finish_pass(se_plan* pl, se::FftPass& ps, int kind, int ncls,
   if (lds_of(1L << lgB) > pl->lds_max) return false;
   ps.lgB = lgB;
   ps.B = 1 << lgB;
+  ps.xcd = pl->p.xcd_fft >= 0 ? 1 : 0;
   std::vector<int4> items;
   for (const auto& r : ranges) add_items(items, r[0], r[1], r[2], r[3], r[4], ps.B);
   ps.nitems = (int)items.size();
@@ -561,6 +562,7 @@ static se_status plan_create(const se_params* params, long n_max, void* hip_stre
   g.xi = p.xi;
   g.alpha = p.shape;
   g.scale = 4.0 * kPi * I.h * I.h * I.h;
+  g.xcd = p.xcd_tiles >= 0 ? 1 : 0;
   {
     // Largest tile whose spread and gather LDS fit, with at least min_tiles
     // tiles when the grid allows it.
@@ -1355,6 +1357,8 @@ se_status se_eval_batch(se_batch_plan* plan, const void* xyz, const void* q, voi
   io.out_grad = (flags & SE_OUT_GRAD) ? 1 : 0;
   io.add_self = (flags & SE_ADD_SELF) ? 1 : 0;
   io.allow_nonneutral = (flags & SE_ALLOW_NONNEUTRAL) ? 1 : 0;
+  io.xcd_tiles = plan->sys[0]->p.xcd_tiles >= 0 ? 1 : 0;
+  io.xcd_fft = plan->sys[0]->p.xcd_fft >= 0 ? 1 : 0;
   const bool prof = (flags & SE_PROFILE) != 0;
   if (prof && !plan->have_ev) {
     for (hipEvent_t& e : plan->ev)
@@ -1425,6 +1429,277 @@ se_status se_batch_plan_destroy(se_batch_plan* plan) {
     (void)hipSetDevice(plan->device);
     delete plan;
   }
+  return SE_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Autotuner: picks the schedule knobs of a plan (tile shape, FFT samples per
+// workgroup, XCD mapping) by timing candidates on the caller's own input with
+// the plans' HIP event profiles.  Tile knobs only change the spread, fold and
+// gather launches and FFT knobs only the transform passes, so the two groups
+// are tuned one after the other against the times of their own launches.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct TuneTimes {
+  double tiles = 0.0, fft = 0.0, all = 0.0;
+};
+
+void classify(const se_stage_record* r, int n, TuneTimes* t) {
+  for (int i = 0; i < n; ++i) {
+    if (!std::strcmp(r[i].name, "batch_all_stages") || r[i].launches == 0) continue;
+    const double ms = r[i].ms_total / r[i].launches;
+    t->all += ms;
+    if (!std::strcmp(r[i].name, "spread") || !std::strcmp(r[i].name, "fold") || !std::strcmp(r[i].name, "gather"))
+      t->tiles += ms;
+    else if (!std::strncmp(r[i].name, "fft", 3))
+      t->fft += ms;
+  }
+}
+
+constexpr int kTuneWarm = 2, kTuneReps = 5;
+const int kTuneTiles[][3] = {{16, 16, 16}, {32, 16, 8}, {32, 8, 8}, {16, 16, 8},
+                             {16, 8, 8},   {8, 8, 8},   {8, 8, 4},  {4, 4, 4}};
+const int kTuneCaps[] = {1024, 2048, 4096, 8192};
+
+struct TuneIO {
+  const void* xyz;
+  const void* q;
+  void* phi;
+  void* force;
+  double* energy;
+  unsigned flags;
+  void* st;
+};
+
+// One candidate for a single system; false if it cannot be planned or run.
+bool time_single(const se_params& p, long N, const TuneIO& io, TuneTimes* t) {
+  se_plan* pl = nullptr;
+  if (se_plan_create(&p, N, io.st, &pl) != SE_OK) return false;
+  se_stage_record rec[32];
+  int n = 0;
+  bool ok = true;
+  for (int i = 0; i < kTuneWarm && ok; ++i)
+    ok = se_eval(pl, N, io.xyz, io.q, io.phi, io.force, io.energy, io.flags, io.st) == SE_OK;
+  ok = ok && se_plan_profile(pl, io.st, rec, 32, &n, 1) == SE_OK;
+  for (int i = 0; i < kTuneReps && ok; ++i)
+    ok = se_eval(pl, N, io.xyz, io.q, io.phi, io.force, io.energy, io.flags | SE_PROFILE, io.st) == SE_OK;
+  ok = ok && se_plan_profile(pl, io.st, rec, 32, &n, 1) == SE_OK;
+  if (ok) classify(rec, n, t);
+  se_plan_destroy(pl);
+  return ok;
+}
+
+bool time_batch(const std::vector<se_params>& p, const std::vector<long>& N, const TuneIO& io, TuneTimes* t) {
+  se_batch_plan* bp = nullptr;
+  if (se_batch_plan_create(p.data(), N.data(), (int)p.size(), io.st, &bp) != SE_OK) return false;
+  se_stage_record rec[32];
+  int n = 0;
+  bool ok = true;
+  for (int i = 0; i < kTuneWarm && ok; ++i)
+    ok = se_eval_batch(bp, io.xyz, io.q, io.phi, io.force, io.energy, io.flags, io.st) == SE_OK;
+  ok = ok && se_batch_plan_profile(bp, io.st, rec, 32, &n, 1) == SE_OK;
+  for (int i = 0; i < kTuneReps && ok; ++i)
+    ok = se_eval_batch(bp, io.xyz, io.q, io.phi, io.force, io.energy, io.flags | SE_PROFILE, io.st) == SE_OK;
+  ok = ok && se_batch_plan_profile(bp, io.st, rec, 32, &n, 1) == SE_OK;
+  if (ok) classify(rec, n, t);
+  se_batch_plan_destroy(bp);
+  return ok;
+}
+
+// Coordinate search over the knob groups.  timer(params, times) times one
+// setting; set(params, knob...) edits a copy.  Returns false if not even the
+// default setting runs.
+template <typename Timer>
+bool tune_knobs(se_params* base, int n_par, bool tune_xcd, Timer timer, se_tune_report* rep) {
+  auto with = [&](auto edit) {
+    std::vector<se_params> v(base, base + n_par);
+    for (auto& p : v) edit(p);
+    return v;
+  };
+  TuneTimes t0;
+  std::vector<se_params> cur(base, base + n_par);
+  if (!timer(cur, &t0)) return false;
+  int cand = 1;
+  // tile shape (with the current XCD setting)
+  double best = t0.tiles;
+  for (const auto& T : kTuneTiles) {
+    auto v = with([&](se_params& p) {
+      p.tile = 0;
+      for (int d = 0; d < 3; ++d) p.tile3[d] = T[d];
+    });
+    TuneTimes t;
+    if (!timer(v, &t)) continue;
+    ++cand;
+    if (t.tiles < best) {
+      best = t.tiles;
+      cur = v;
+    }
+  }
+  if (tune_xcd) {
+    auto v = cur;
+    for (auto& p : v) p.xcd_tiles = -1;
+    TuneTimes t;
+    if (timer(v, &t)) {
+      ++cand;
+      if (t.tiles < best) {
+        best = t.tiles;
+        cur = v;
+      }
+    }
+  }
+  // FFT samples per workgroup
+  TuneTimes tc;
+  if (!timer(cur, &tc)) return false;
+  best = tc.fft;
+  for (int cap : kTuneCaps) {
+    auto v = cur;
+    for (auto& p : v) p.fft_cap = cap;
+    TuneTimes t;
+    if (!timer(v, &t)) continue;
+    ++cand;
+    if (t.fft < best) {
+      best = t.fft;
+      cur = v;
+    }
+  }
+  if (tune_xcd) {
+    auto v = cur;
+    for (auto& p : v) p.xcd_fft = -1;
+    TuneTimes t;
+    if (timer(v, &t)) {
+      ++cand;
+      if (t.fft < best) {
+        best = t.fft;
+        cur = v;
+      }
+    }
+  }
+  TuneTimes tf;
+  if (!timer(cur, &tf)) return false;
+  // keep the default if the tuned setting is not faster as a whole
+  if (tf.all > t0.all) {
+    cur.assign(base, base + n_par);
+    tf = t0;
+  }
+  for (int i = 0; i < n_par; ++i) base[i] = cur[i];
+  if (rep) {
+    rep->candidates += cand;
+    rep->ms_default += t0.all;
+    rep->ms_tuned += tf.all;
+  }
+  return true;
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  bool alloc(size_t n) { return hipMalloc(&p, std::max<size_t>(n, 16)) == hipSuccess; }
+};
+
+}  // namespace
+
+extern "C" {
+
+se_status se_autotune(const se_params* params, long N, const void* xyz, const void* q, unsigned flags,
+                      void* hip_stream, se_params* tuned, se_tune_report* report) {
+  if (!params || !tuned || N < 1 || !xyz || !q) return SE_ERR_ARG;
+  if (flags & ~(SE_IN_F32 | SE_ALLOW_NONNEUTRAL)) return SE_ERR_ARG;
+  if (report) std::memset(report, 0, sizeof(*report));
+  const size_t re = params->prec == SE_F64 ? 8 : 4;
+  DevBuf phi, force, energy;
+  if (!phi.alloc(re * N) || !force.alloc(3 * re * N) || !energy.alloc(8)) return SE_ERR_NOMEM;
+  TuneIO io{xyz, q, phi.p, force.p, (double*)energy.p, flags, hip_stream};
+  se_params p = *params;
+  auto timer = [&](const std::vector<se_params>& v, TuneTimes* t) { return time_single(v[0], N, io, t); };
+  if (!tune_knobs(&p, 1, true, timer, report)) return SE_ERR_UNSUPPORTED;
+  *tuned = p;
+  return SE_OK;
+}
+
+se_status se_batch_autotune(const se_params* params, const long* N, int n_sys, const void* xyz, const void* q,
+                            unsigned flags, void* hip_stream, se_params* tuned, se_tune_report* report) {
+  if (!params || !N || !tuned || n_sys < 1 || !xyz || !q) return SE_ERR_ARG;
+  if (flags & ~(SE_IN_F32 | SE_ALLOW_NONNEUTRAL)) return SE_ERR_ARG;
+  if (report) std::memset(report, 0, sizeof(*report));
+  hipStream_t st = (hipStream_t)hip_stream;
+  std::vector<long> off(n_sys + 1, 0);
+  for (int s = 0; s < n_sys; ++s) {
+    if (N[s] < 0) return SE_ERR_ARG;
+    off[s + 1] = off[s] + N[s];
+  }
+  const long total = off[n_sys];
+  const size_t re = params[0].prec == SE_F64 ? 8 : 4, ie = (flags & SE_IN_F32) ? 4 : 8;
+  DevBuf phi, force, energy, gx, gq;
+  if (!phi.alloc(re * total) || !force.alloc(3 * re * total) || !energy.alloc(8 * n_sys) ||
+      !gx.alloc(3 * ie * total) || !gq.alloc(ie * total))
+    return SE_ERR_NOMEM;
+  std::vector<se_params> out(params, params + n_sys);
+  // tile and FFT knobs per periodicity class, on that class's systems alone
+  for (int D = 0; D <= 3; ++D) {
+    std::vector<int> idx;
+    for (int s = 0; s < n_sys; ++s)
+      if (params[s].D == D) idx.push_back(s);
+    if (idx.empty()) continue;
+    std::vector<se_params> sub;
+    std::vector<long> subN;
+    long run = 0;
+    for (int s : idx) {
+      sub.push_back(params[s]);
+      subN.push_back(N[s]);
+      if (N[s] > 0 &&
+          (hipMemcpyAsync((char*)gx.p + 3 * ie * run, (const char*)xyz + 3 * ie * off[s], 3 * ie * N[s],
+                          hipMemcpyDeviceToDevice, st) != hipSuccess ||
+           hipMemcpyAsync((char*)gq.p + ie * run, (const char*)q + ie * off[s], ie * N[s],
+                          hipMemcpyDeviceToDevice, st) != hipSuccess))
+        return SE_ERR_DEVICE;
+      run += N[s];
+    }
+    TuneIO io{gx.p, gq.p, phi.p, force.p, (double*)energy.p, flags, hip_stream};
+    auto timer = [&](const std::vector<se_params>& v, TuneTimes* t) { return time_batch(v, subN, io, t); };
+    se_tune_report r{};
+    if (!tune_knobs(sub.data(), (int)sub.size(), false, timer, &r)) return SE_ERR_UNSUPPORTED;
+    if (report) report->candidates += r.candidates;
+    for (size_t k = 0; k < idx.size(); ++k) out[idx[k]] = sub[k];
+  }
+  // XCD mapping (one setting for the whole batch) on the full batch
+  {
+    TuneIO io{xyz, q, phi.p, force.p, (double*)energy.p, flags, hip_stream};
+    std::vector<long> vN(N, N + n_sys);
+    TuneTimes t0, tb;
+    std::vector<se_params> def(params, params + n_sys);
+    if (!time_batch(def, vN, io, &t0)) return SE_ERR_UNSUPPORTED;
+    if (!time_batch(out, vN, io, &tb)) return SE_ERR_UNSUPPORTED;
+    int cand = 2;
+    for (int mode = 1; mode < 4; ++mode) {
+      auto v = out;
+      for (auto& p : v) {
+        p.xcd_tiles = (mode & 1) ? -1 : 1;
+        p.xcd_fft = (mode & 2) ? -1 : 1;
+      }
+      TuneTimes t;
+      if (!time_batch(v, vN, io, &t)) continue;
+      ++cand;
+      if (t.all < tb.all) {
+        tb = t;
+        out = v;
+      }
+    }
+    if (tb.all > t0.all) {
+      out = def;
+      tb = t0;
+    }
+    if (report) {
+      report->candidates += cand;
+      report->ms_default = t0.all;
+      report->ms_tuned = tb.all;
+    }
+  }
+  for (int s = 0; s < n_sys; ++s) tuned[s] = out[s];
   return SE_OK;
 }
 

@@ -1,0 +1,135 @@
+"""Schedule knobs and the autotuner: every tile shape, FFT workgroup size and
+XCD mapping the tuner can choose gives the discrete oracle's result, and a
+tuned plan (single or batch) computes what the default plan computes."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import se_discrete as se
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1712_04732_amd import SpectralEwald, SpectralEwaldBatch, _lib  # noqa: E402
+
+DEV = torch.device("cuda:0")
+TILES = [(16, 16, 16), (32, 16, 8), (32, 8, 8), (16, 16, 8), (16, 8, 8), (8, 8, 8), (8, 8, 4), (4, 4, 4)]
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def _plan(D, M, N, knobs, prec="f64"):
+    kw = {"s": 2.0, "n_l": 3} if D in (1, 2) else {}
+    base = SpectralEwald(D, 1.0, 8.0, M, 8, prec=prec, n_max=N, **kw)
+    p = base.params
+    for k, v in knobs.items():
+        if k == "tile3":
+            for d in range(3):
+                p.tile3[d] = v[d]
+        else:
+            setattr(p, k, v)
+    return SpectralEwald.from_params(p, N), se.Params(D=D, L=1.0, xi=8.0, M=M, P=8, window="pkb", **kw)
+
+
+def _eval(plan, x, q):
+    phi, g, _ = plan(torch.tensor(x, device=DEV), torch.tensor(q, device=DEV), out_grad=True)
+    torch.cuda.synchronize()
+    return phi.double().cpu().numpy(), g.double().cpu().numpy()
+
+
+_ORACLE = {}
+
+
+def _oracle(key, x, q, p):
+    if key not in _ORACLE:
+        _ORACLE[key] = se.spectral_ewald(x, q, p)
+    return _ORACLE[key]
+
+
+@pytest.mark.parametrize("D", [3, 2, 1, 0])
+@pytest.mark.parametrize("tile", TILES)
+def test_every_tile_shape_matches_oracle(D, tile):
+    """M = 36 is a multiple of no tile edge above 4, so every shape has short
+    last tiles in the periodic directions."""
+    print(f"case tile D={D} tile={tile}", flush=True)
+    x, q = wl.system(600, 1.0, 40 + D, "uniform")
+    plan, p = _plan(D, 36, 600, {"tile3": tile, "tile": 0})
+    assert tuple(plan.info.tile) == tile
+    phi, g = _eval(plan, x, q)
+    ref, gref = _oracle(("tile", D), x, q, p)
+    assert rel(phi, ref) < 1e-12 and rel(g, gref) < 1e-11
+
+
+@pytest.mark.parametrize("D", [3, 2, 1, 0])
+@pytest.mark.parametrize("knobs", [dict(fft_cap=1024), dict(fft_cap=4096), dict(fft_cap=8192),
+                                   dict(xcd_tiles=-1, xcd_fft=-1), dict(xcd_tiles=1, xcd_fft=-1)])
+def test_fft_and_mapping_knobs_match_oracle(D, knobs):
+    print(f"case knobs D={D} {knobs}", flush=True)
+    x, q = wl.system(500, 1.0, 60 + D, "uniform")
+    plan, p = _plan(D, 30, 500, knobs)
+    phi, g = _eval(plan, x, q)
+    ref, gref = _oracle(("knobs", D), x, q, p)
+    assert rel(phi, ref) < 1e-12 and rel(g, gref) < 1e-11
+
+
+def test_invalid_knobs_rejected():
+    base = SpectralEwald(3, 1.0, 8.0, 32, 8, prec="f64", n_max=10)
+    for edit in (lambda p: setattr(p, "fft_cap", 3000), lambda p: setattr(p, "fft_cap", 512)):
+        p = _lib.se_params()
+        ctypes_copy(base.params, p)
+        edit(p)
+        with pytest.raises(_lib.SEError) as e:
+            _lib.se_plan_create(p, 10, torch.cuda.current_stream().cuda_stream)
+        assert e.value.status == _lib.SE_ERR_PARAM
+
+
+def ctypes_copy(src, dst):
+    import ctypes
+    ctypes.memmove(ctypes.byref(dst), ctypes.byref(src), ctypes.sizeof(src))
+
+
+@pytest.mark.parametrize("D", [3, 0])
+def test_autotuned_plan_computes_the_same(D):
+    print(f"case autotune D={D}", flush=True)
+    N = 4000
+    x, q = wl.system(N, 1.0, 80 + D, "pm1")
+    base = SpectralEwald(D, 1.0, 10.0, 40, 8, prec="f64", n_max=N)
+    xt, qt = torch.tensor(x, device=DEV), torch.tensor(q, device=DEV)
+    tuned, rep = base.autotune(xt, qt)
+    print(f"tuned tile {list(tuned.info.tile)} fft_cap {tuned.info.fft_cap} report {rep}")
+    assert rep["candidates"] >= 2 and rep["ms_tuned"] <= rep["ms_default"] * 1.0001
+    phi0, g0 = _eval(base, x, q)
+    phi1, g1 = _eval(tuned, x, q)
+    assert rel(phi1, phi0) < 1e-13 and rel(g1, g0) < 1e-12
+
+
+def test_batch_autotune_computes_the_same():
+    print("case batch autotune", flush=True)
+    rng = np.random.default_rng(11)
+    params, N, xs, qs = [], [], [], []
+    for i in range(8):
+        D = [3, 2, 1, 0][i % 4]
+        n = int(rng.integers(100, 900)) * 2
+        Lb = float(rng.uniform(0.7, 1.4))
+        x, q = wl.system(n, Lb, 300 + i, "pm1")
+        params.append(_lib.se_params_for_tolerance(D, Lb, wl.batch_xi(n, Lb), float(n), 1e-7, 8,
+                                                   _lib.SE_WIN_PKB, _lib.SE_F32))
+        N.append(n)
+        xs.append(x)
+        qs.append(q)
+    x = torch.tensor(np.concatenate(xs), device=DEV, dtype=torch.float32)
+    q = torch.tensor(np.concatenate(qs), device=DEV, dtype=torch.float32)
+    b0 = SpectralEwaldBatch(params, N)
+    b1, rep = SpectralEwaldBatch.tuned(params, N, x, q)
+    print(f"batch tuner report {rep}")
+    assert rep["ms_tuned"] <= rep["ms_default"] * 1.0001
+    r0 = [t.double().cpu().numpy() for t in b0(x, q, out_grad=True)]
+    r1 = [t.double().cpu().numpy() for t in b1(x, q, out_grad=True)]
+    # FP32: the tile shape changes the per-tile fixed-point scale and the FFT
+    # workgroup size nothing; differences are FP32 rounding
+    assert rel(r1[0], r0[0]) < 2e-6 and rel(r1[1], r0[1]) < 5e-6

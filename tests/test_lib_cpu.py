@@ -96,3 +96,27 @@ def test_params_for_tolerance_matches_oracle_rule(D, L, N, tol):
     if D in (1, 2):
         o = se.with_aft_estimates(D, L, xi, M, 8, Q, tol * B, window="pkb")
         assert abs(p.s - o.s) < 1e-12 and p.n_l == o.n_l
+
+
+@pytest.mark.parametrize("tile3,fft_cap", [((6, 4, 4), 0), ((4, 4, 36), 0), ((8, 8, 8), 3000), ((8, 8, 8), 512),
+                                           ((8, 8, 8), 16384)])
+def test_plan_create_rejects_invalid_knobs(tile3, fft_cap):
+    """Tile edges are multiples of 4 up to 32; FFT samples per workgroup a power
+    of two in 1024..8192."""
+    lib = L.load()
+    p = L.se_params()
+    p.D, p.L, p.xi, p.M, p.P, p.window = 3, 1.0, 5.0, 32, 8, L.SE_WIN_PKB
+    for d in range(3):
+        p.tile3[d] = tile3[d]
+    p.fft_cap = fft_cap
+    plan = ctypes.c_void_p()
+    assert lib.se_plan_create(ctypes.byref(p), 10, None, ctypes.byref(plan)) == L.SE_ERR_PARAM
+    assert not plan.value
+
+
+def test_autotune_null_arguments():
+    lib = L.load()
+    p = L.se_params()
+    assert lib.se_autotune(None, 10, None, None, 0, None, None, None) == L.SE_ERR_ARG
+    assert lib.se_autotune(ctypes.byref(p), 0, None, None, 0, None, ctypes.byref(p), None) == L.SE_ERR_ARG
+    assert lib.se_batch_autotune(None, None, 0, None, None, 0, None, None, None) == L.SE_ERR_ARG

@@ -306,8 +306,13 @@ def main_batch(args):
             e_phi64 += float(np.sum((phi64[sl] - phi_o) ** 2))
             e_f32 += float(np.sum((f32[sl] + systems[k]["q"][tg, None] * grad_o) ** 2))
             ref_n += float(np.sum(phi_o ** 2))
+        g_n = sum(float(np.sum((systems[k]["q"][tg, None] * grad_o) ** 2)) for k, tg, phi_o, grad_o in res)
+        e_f64 = sum(float(np.sum((f64[offs[k] + tg] + systems[k]["q"][tg, None] * grad_o) ** 2))
+                    for k, tg, phi_o, grad_o in res)
         err["phi_f32_vs_oracle"] = (e_phi32 / ref_n) ** 0.5
         err["phi_f64_vs_oracle"] = (e_phi64 / ref_n) ** 0.5
+        err["force_f32_vs_oracle"] = (e_f32 / g_n) ** 0.5
+        err["force_f64_vs_oracle"] = (e_f64 / g_n) ** 0.5
     print(json.dumps(result), flush=True)
 
 

@@ -294,15 +294,29 @@ __device__ __forceinline__ void slot_tp(int e, bool t_fast, int n, float inv_n, 
   }
 }
 
+// A real pencil pair (a, b) shares one complex transform z = a + i b.  Forward:
+// A_k = (Z_k + conj Z_{n-k})/2 and B_k = (Z_k - conj Z_{n-k})/(2i).  Inverse:
+// the half spectra of a and b, Hermitian-extended, combine to Z = A + i B, whose
+// transform holds a in the real and b in the imaginary part.
+template <typename T>
+__device__ __forceinline__ cx<T> split_pair(cx<T> z, cx<T> zn, int odd) {
+  return odd ? cx<T>{(T)0.5 * (z.im + zn.im), (T)0.5 * (zn.re - z.re)}
+             : cx<T>{(T)0.5 * (z.re + zn.re), (T)0.5 * (z.im - zn.im)};
+}
+
 template <typename T, int KIND>
-__device__ void stage_fft(const FftPass& P, int item, unsigned char* smem) {
+__device__ __forceinline__ void stage_fft(const FftPass& P, int item, unsigned char* smem) {
   constexpr int U = 8;  // global accesses in flight per thread
+  constexpr bool REAL = (KIND == K_R2C || KIND == K_C2R);
   const int4 it = P.items[item];
   const FftClass& C = P.cls[it.x];
-  const int n = C.n, lgB = P.lgB, Bp = (1 << lgB) + 1, cnt = it.w, b0s = it.y, b1 = it.z;
+  const int n = C.n, lgB = P.lgB, cnt = it.w, b0s = it.y, b1 = it.z;
+  // real passes with B >= 2 run B/2 complex transforms of pencil pairs
+  const int pair = (REAL && lgB > 0) ? 1 : 0;
+  const int lgF = lgB - pair, Bp = (1 << lgF) + 1;
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem);
   cx<T>* buf = tw + P.nmax;
-  cx<T>* buf2 = buf + (size_t)P.nmax * Bp;
+  cx<T>* buf2 = buf + (size_t)P.nmax * ((1 << lgB) + 1);
 
   const cx<T>* twg = reinterpret_cast<const cx<T>*>(C.tw);
   for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = twg[i];
@@ -310,38 +324,80 @@ __device__ void stage_fft(const FftPass& P, int item, unsigned char* smem) {
   // ---- load the pencils, zero padded to n ----
   const bool t_fast = (C.in_st == 1);
   const float inv_n = 1.0f / (float)n;
-  const int total = n << lgB;
   const long long bs1 = (long long)b1 * C.in_s1;
-  for (int e0 = 0; e0 < total; e0 += U * kFftBlock) {
-    cx<T> v[U];
+  if constexpr (KIND == K_C2R) {
+    // slots (t, complex pencil c) of pencils 2c and 2c+1 (or c alone unpaired)
+    const int total = n << lgF;
+    const int h = n >> 1;
+    for (int e0 = 0; e0 < total; e0 += U * kFftBlock) {
+      cx<T> v[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int e = e0 + u * kFftBlock + threadIdx.x;
-      int t, p;
-      slot_tp(e, t_fast, n, inv_n, lgB, &t, &p);
-      v[u] = cx<T>{0, 0};
-      if (e < total && p < cnt) {
-        const long long base = (long long)(b0s + p) * C.in_s0 + bs1;
-        if constexpr (KIND == K_R2C) {
-          if (t < C.n_in) v[u].re = reinterpret_cast<const T*>(C.in)[base + (long long)t * C.in_st];
-        } else if constexpr (KIND == K_C2R) {
-          // Hermitian extension of the stored half spectrum (t <= n/2)
-          const int h = n >> 1;
-          const int ts = t <= h ? t : n - t;
-          v[u] = reinterpret_cast<const cx<T>*>(C.in)[base + (long long)ts * C.in_st];
-          if (t > h) v[u].im = -v[u].im;
-        } else {
-          if (t < C.n_in) v[u] = reinterpret_cast<const cx<T>*>(C.in)[base + (long long)t * C.in_st];
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * kFftBlock + threadIdx.x;
+        int t, c;
+        slot_tp(e, t_fast, n, inv_n, lgF, &t, &c);
+        v[u] = cx<T>{0, 0};
+        const int ts = t <= h ? t : n - t;
+        const T sg = t <= h ? (T)1 : (T)-1;   // Hermitian extension of the stored half
+        const int pa = c << pair;
+        if (e < total && pa < cnt) {
+          const cx<T>* in = reinterpret_cast<const cx<T>*>(C.in);
+          const cx<T> a = in[(long long)(b0s + pa) * C.in_s0 + bs1 + (long long)ts * C.in_st];
+          v[u] = cx<T>{a.re, sg * a.im};
+          if (pair && pa + 1 < cnt) {
+            const cx<T> bb = in[(long long)(b0s + pa + 1) * C.in_s0 + bs1 + (long long)ts * C.in_st];
+            v[u].re -= sg * bb.im;
+            v[u].im += bb.re;
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * kFftBlock + threadIdx.x;
+        if (e < total) {
+          int t, c;
+          slot_tp(e, t_fast, n, inv_n, lgF, &t, &c);
+          buf[t * Bp + c] = v[u];
         }
       }
     }
+  } else {
+    // slots (t, pencil p); a real pass packs pencil p into component p & 1
+    const int total = n << lgB;
+    if (pair) {
+      for (int e = threadIdx.x; e < (n << lgF); e += blockDim.x) {
+        const int t = e >> lgF, c = e & ((1 << lgF) - 1);
+        buf[t * Bp + c] = cx<T>{0, 0};
+      }
+      __syncthreads();
+    }
+    for (int e0 = 0; e0 < total; e0 += U * kFftBlock) {
+      cx<T> v[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int e = e0 + u * kFftBlock + threadIdx.x;
-      if (e < total) {
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * kFftBlock + threadIdx.x;
         int t, p;
         slot_tp(e, t_fast, n, inv_n, lgB, &t, &p);
-        buf[t * Bp + p] = v[u];
+        v[u] = cx<T>{0, 0};
+        if (e < total && p < cnt && t < C.n_in) {
+          const long long idx = (long long)(b0s + p) * C.in_s0 + bs1 + (long long)t * C.in_st;
+          if constexpr (KIND == K_R2C) v[u].re = reinterpret_cast<const T*>(C.in)[idx];
+          else v[u] = reinterpret_cast<const cx<T>*>(C.in)[idx];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * kFftBlock + threadIdx.x;
+        if (e < total) {
+          int t, p;
+          slot_tp(e, t_fast, n, inv_n, lgB, &t, &p);
+          if (pair) {
+            T* cell = reinterpret_cast<T*>(&buf[t * Bp + (p >> 1)]);
+            cell[p & 1] = v[u].re;
+          } else {
+            buf[t * Bp + p] = v[u];
+          }
+        }
       }
     }
   }
@@ -349,14 +405,15 @@ __device__ void stage_fft(const FftPass& P, int item, unsigned char* smem) {
 
   cx<T>* res;
   if constexpr (KIND == K_C2C_INV || KIND == K_C2R) {
-    res = fft_run<T>(buf, buf2, tw, C, lgB, Bp, +1);
+    res = fft_run<T>(buf, buf2, tw, C, lgF, Bp, +1);
   } else {
-    res = fft_run<T>(buf, buf2, tw, C, lgB, Bp, -1);
+    res = fft_run<T>(buf, buf2, tw, C, lgF, Bp, -1);
   }
 
   if constexpr (KIND == K_FUSED) {
     // scaling step, Eq. (scale), on the spectrum of each pencil
     const int mask = (1 << lgB) - 1;
+    const int total = n << lgB;
     for (int e = threadIdx.x; e < total; e += blockDim.x) {
       const int t = e >> lgB, p = e & mask;
       if (p < cnt) res[t * Bp + p] = cscale(res[t * Bp + p], scale_factor<T>(C, b0s + p, b1, t));
@@ -375,12 +432,21 @@ __device__ void stage_fft(const FftPass& P, int item, unsigned char* smem) {
     int t, p;
     slot_tp(e, to_fast, nout, inv_no, lgB, &t, &p);
     if (p >= cnt) continue;
-    const cx<T> v = res[t * Bp + p];
     const long long idx = (long long)(b0s + p) * C.out_s0 + os1 + (long long)t * C.out_st;
     if constexpr (KIND == K_C2R) {
-      reinterpret_cast<T*>(C.out)[idx] = v.re;
-    } else {
+      const cx<T> v = res[t * Bp + (p >> pair)];
+      reinterpret_cast<T*>(C.out)[idx] = (pair && (p & 1)) ? v.im : v.re;
+    } else if constexpr (KIND == K_R2C) {
+      cx<T> v;
+      if (pair) {
+        const int tn = t == 0 ? 0 : n - t;
+        v = split_pair(res[t * Bp + (p >> 1)], res[tn * Bp + (p >> 1)], p & 1);
+      } else {
+        v = res[t * Bp + p];
+      }
       reinterpret_cast<cx<T>*>(C.out)[idx] = v;
+    } else {
+      reinterpret_cast<cx<T>*>(C.out)[idx] = res[t * Bp + p];
     }
   }
 }
@@ -450,7 +516,7 @@ __device__ __forceinline__ int sb_key(const GridGeom& g, int cx_, int cy, int cz
 }
 
 template <typename Tin, typename T>
-__device__ void stage_bin(const GridGeom& g, const EvalBuffers& b, long N, const Tin* __restrict__ xyz,
+__device__ __forceinline__ void stage_bin(const GridGeom& g, const EvalBuffers& b, long N, const Tin* __restrict__ xyz,
                           const Tin* __restrict__ q, int item) {
   const long n = (long)item * blockDim.x + threadIdx.x;
   double sq = 0.0, sa = 0.0, s2 = 0.0;
@@ -557,7 +623,7 @@ hipError_t launch_bin(const GridGeom& g, const EvalBuffers& b, long N, const voi
 // FP64 charge sums and applies the neutrality check.
 constexpr int kScanBlock = 1024;
 
-__device__ void stage_scan1(const GridGeom& g, const EvalBuffers& b, int item) {
+__device__ __forceinline__ void stage_scan1(const GridGeom& g, const EvalBuffers& b, int item) {
   const int n = g.nsb[0] * g.nsb[1] * g.nsb[2];
   const int base = item * kScanBlock;
   constexpr int K = kScanBlock / kBlock;
@@ -592,7 +658,7 @@ __global__ __launch_bounds__(kBlock) void scan1_kernel(GridGeom g, EvalBuffers b
   stage_scan1(g, b, blockIdx.x);
 }
 
-__device__ void stage_scan2(const GridGeom& g, const EvalBuffers& b, int nblk_bin, int check_neutral,
+__device__ __forceinline__ void stage_scan2(const GridGeom& g, const EvalBuffers& b, int nblk_bin, int check_neutral,
                             int item, int nscan) {
   const int n = g.nsb[0] * g.nsb[1] * g.nsb[2];
   __shared__ int ps[kBlock];
@@ -661,7 +727,7 @@ hipError_t launch_scan(const GridGeom& g, const EvalBuffers& b, int nblk_bin, in
 }
 
 template <typename T>
-__device__ void stage_scatter(const EvalBuffers& b, long N, int item) {
+__device__ __forceinline__ void stage_scatter(const EvalBuffers& b, long N, int item) {
   const long n = (long)item * blockDim.x + threadIdx.x;
   if (n >= N) return;
   const int key = b.p_key[n];
@@ -839,7 +905,7 @@ __device__ __forceinline__ long long round_fixed(double d) {
 }
 
 template <typename T, int P>
-__device__ void stage_spread(const GridGeom& g, const EvalBuffers& b, int item, unsigned char* smem) {
+__device__ __forceinline__ void stage_spread(const GridGeom& g, const EvalBuffers& b, int item, unsigned char* smem) {
   constexpr int G2 = Lanes<P>::G2, PPW = Lanes<P>::PPW;
   const int TX = g.T[0], TY = g.T[1], TZ = g.T[2];
   const int t_id = item;
@@ -989,7 +1055,7 @@ __device__ __forceinline__ int fold_images(const GridGeom& g, int dim, int t, in
 }
 
 template <typename T>
-__device__ void stage_fold(const GridGeom& g, const EvalBuffers& b, int item) {
+__device__ __forceinline__ void stage_fold(const GridGeom& g, const EvalBuffers& b, int item) {
   const int t_id = item;
   const int tz = t_id / (g.nt[0] * g.nt[1]);
   const int ty = (t_id / g.nt[0]) % g.nt[1];
@@ -1088,7 +1154,7 @@ hipError_t launch_fold(const GridGeom& g, const EvalBuffers& b, bool f64, hipStr
 // with shuffles.
 // ---------------------------------------------------------------------------
 template <typename T, int P>
-__device__ void stage_gather(const GridGeom& g, const EvalBuffers& b, T* __restrict__ phi,
+__device__ __forceinline__ void stage_gather(const GridGeom& g, const EvalBuffers& b, T* __restrict__ phi,
                              T* __restrict__ force, int out_grad, double self_coef, int item,
                              unsigned char* smem) {
   constexpr int G2 = Lanes<P>::G2, PPW = Lanes<P>::PPW;
@@ -1294,7 +1360,7 @@ hipError_t launch_gather(const GridGeom& g, const EvalBuffers& b, bool f64, void
 }
 
 // E = 1/2 sum of the per-tile partials of q phi, in a fixed order (FP64).
-__device__ void stage_energy(const double* __restrict__ epart, int n, double* __restrict__ energy) {
+__device__ __forceinline__ void stage_energy(const double* __restrict__ epart, int n, double* __restrict__ energy) {
   __shared__ double es[kBlock];
   double a = 0.0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) a += epart[i];
@@ -1327,7 +1393,7 @@ hipError_t launch_energy(const GridGeom& g, const EvalBuffers& b, double* energy
 // one block-sized piece of one system: a particle block, a scan block, a tile
 // or a pencil group); consecutive launches on the stream order the stages.
 // ---------------------------------------------------------------------------
-__device__ void stage_zero(const GridGeom& g, const EvalBuffers& b, int item) {
+__device__ __forceinline__ void stage_zero(const GridGeom& g, const EvalBuffers& b, int item) {
   const int n = g.nsb[0] * g.nsb[1] * g.nsb[2];
   for (int k = threadIdx.x; k < kScanBlock; k += blockDim.x) {
     const int i = item * kScanBlock + k;
@@ -1336,7 +1402,7 @@ __device__ void stage_zero(const GridGeom& g, const EvalBuffers& b, int item) {
 }
 
 template <typename T, int P>
-__device__ void run_batch_stage(int st, const SysDesc& S, int sys_id, int li, const BatchIO& io,
+__device__ __forceinline__ void run_batch_stage(int st, const SysDesc& S, int sys_id, int li, const BatchIO& io,
                                 unsigned char* smem) {
   switch (st) {
     case BS_ZERO:

@@ -1,0 +1,130 @@
+"""Parity at the benchmark configurations' full sizes, in the launch
+configuration the bench times, on sampled outputs:
+
+  * C1-C4 single systems (FP64 and FP32 plans built as the bench builds them)
+    against the discrete oracle gathered at sampled targets (the oracle grids
+    and transforms the whole system; only the gathering is sampled);
+  * the same FP64 results against the direct Ewald oracle (k-space by the
+    splitting identity) at sampled targets: the method's own error at the
+    configuration's parameters;
+  * the C5 batch with the stored autotuned schedule, for the largest and one
+    other system of every periodicity, against the discrete oracle.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import direct
+from oracle import se_discrete as se
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1712_04732_amd import SpectralEwald, SpectralEwaldBatch, params_for_tolerance  # noqa: E402
+
+DEV = torch.device("cuda:0")
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def _targets(N, k=64):
+    return np.unique(np.concatenate([np.linspace(0, N - 1, k).astype(int), [0, N - 1]]))
+
+
+def _config_plans(name):
+    c = wl.CONFIGS[name]
+    x, q = wl.config_system(name)
+    Q = float((q * q).sum())
+    kw = dict(window=c["window"], n_max=c["N"])
+    if c["D"] in (1, 2):
+        kw.update(Q=Q, tol=1e-6 * se.B_scale(Q, c["xi"], c["L"]))
+    plans = {pr: SpectralEwald(c["D"], c["L"], c["xi"], c["M"], c["P"], prec=pr, **kw) for pr in ("f64", "f32")}
+    info = plans["f64"].info
+    extra = {"s": info.s, "n_l": info.n_l} if c["D"] in (1, 2) else {}
+    p = se.Params(D=c["D"], L=c["L"], xi=c["xi"], M=c["M"], P=c["P"], window=c["window"], **extra)
+    assert p.Mt == info.Mt
+    return c, x, q, plans, p
+
+
+def _gpu(plan, x, q):
+    phi, g, _ = plan(torch.tensor(x, device=DEV), torch.tensor(q, device=DEV), out_grad=True)
+    torch.cuda.synchronize()
+    return phi.double().cpu().numpy(), g.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("name", ["C1_3P", "C2_0P", "C3_2P", "C4_1P"])
+def test_config_full_size_matches_discrete_oracle(name):
+    print(f"case full-size discrete {name}", flush=True)
+    c, x, q, plans, p = _config_plans(name)
+    tg = _targets(c["N"])
+    ref, gref = se.spectral_ewald(x, q, p, targets=tg)
+    phi, g = _gpu(plans["f64"], x, q)
+    assert rel(phi[tg], ref) < 1e-12 and rel(g[tg], gref) < 1e-11
+    phi32, g32 = _gpu(plans["f32"], x, q)
+    e_phi, e_g = rel(phi32[tg], ref), rel(g32[tg], gref)
+    print(f"{name}: FP32 vs discrete oracle phi {e_phi:.2e} grad {e_g:.2e}")
+    assert e_phi < 2e-6 and e_g < 5e-6
+
+
+@pytest.mark.parametrize("name,bound", [("C1_3P", 3e-5), ("C2_0P", 1e-6), ("C3_2P", 1e-6)])
+def test_config_full_size_accuracy_vs_direct(name, bound):
+    """C1 uses the Gaussian window at P = 8, whose window error is about 1e-5
+    (Sec. 4 estimate 2 exp(-(pi/2) P c)); the PKB configurations meet 1e-6."""
+    print(f"case full-size direct {name}", flush=True)
+    c, x, q, plans, p = _config_plans(name)
+    tg = _targets(c["N"], 32)
+    ref, gref = direct.kspace_by_split(c["D"], c["L"], c["xi"], x, q, targets=tg)
+    phi, g = _gpu(plans["f64"], x, q)
+    e_phi, e_g = rel(phi[tg], ref), rel(g[tg], gref)
+    print(f"{name}: FP64 vs direct phi {e_phi:.2e} grad {e_g:.2e}")
+    assert e_phi < bound and e_g < 10 * bound
+
+
+def _stored_schedule(params):
+    rows = json.load(open(os.path.join(ROOT, "paper_1712_04732_amd", "schedules", "c5_batch.json")))["systems"]
+    assert len(rows) == len(params)
+    for r, p in zip(rows, params):
+        assert r["D"] == p.D and r["M"] == p.M
+        for d in range(3):
+            p.tile3[d] = r["tile3"][d]
+        p.fft_cap, p.xcd_tiles, p.xcd_fft = r["fft_cap"], r["xcd_tiles"], r["xcd_fft"]
+
+
+def test_c5_batch_full_size_matches_discrete_oracle():
+    print("case full-size C5 batch", flush=True)
+    cfg = wl.BATCH
+    systems = wl.batch_systems()
+    params = [params_for_tolerance(s["D"], s["L"], s["xi"], float((s["q"] ** 2).sum()), cfg["tol_rel"], cfg["P"],
+                                   cfg["window"], "f32") for s in systems]
+    _stored_schedule(params)
+    N = [s["N"] for s in systems]
+    b = SpectralEwaldBatch(params, N)
+    x = torch.tensor(np.concatenate([s["x"] for s in systems]), device=DEV)
+    q = torch.tensor(np.concatenate([s["q"] for s in systems]), device=DEV)
+    phi, g, _ = b(x, q, out_grad=True)
+    torch.cuda.synchronize()
+    phi, g = phi.double().cpu().numpy(), g.double().cpu().numpy()
+    off = np.concatenate([[0], np.cumsum(N)])
+    picks = []
+    for D in (3, 2, 1, 0):
+        ks = [k for k, s in enumerate(systems) if s["D"] == D]
+        picks += [max(ks, key=lambda k: N[k]), ks[len(ks) // 2]]
+    for k in picks:
+        s, pp = systems[k], params[k]
+        extra = {"s": pp.s, "n_l": pp.n_l} if s["D"] in (1, 2) else {}
+        p = se.Params(D=s["D"], L=s["L"], xi=s["xi"], M=pp.M, P=cfg["P"], window=cfg["window"], **extra)
+        tg = _targets(s["N"], 32)
+        ref, gref = se.spectral_ewald(s["x"], s["q"], p, targets=tg)
+        e_phi = rel(phi[off[k] + tg], ref)
+        e_g = rel(g[off[k] + tg], gref)
+        print(f"system {k} D={s['D']} N={s['N']} M={pp.M}: phi {e_phi:.2e} grad {e_g:.2e}", flush=True)
+        assert e_phi < 2e-6 and e_g < 5e-6, k

@@ -84,8 +84,10 @@ typedef struct {
                          all > 0 -> used instead of 'tile'                          */
   int fft_cap;        /* samples (length x pencils) per FFT workgroup: a power of two
                          in 1024..8192; <= 0 -> 2048 (FP32) / 1024 (FP64)          */
-  int xcd_tiles;      /* workgroup -> tile mapping of spread, fold and gather:
-                         > 0 contiguous tile ranges per XCD, < 0 round robin, 0 -> on */
+  int xcd_tiles;      /* workgroup -> tile mapping of spread, fold and gather (the
+                         8 XCDs take workgroups in turn): < 0 plain order, 1 one
+                         contiguous tile range per XCD, c >= 2 chunks of c
+                         neighbouring tiles per XCD, 0 -> 1                        */
   int xcd_fft;        /* the same for the transform passes' pencil groups            */
 } se_params;
 

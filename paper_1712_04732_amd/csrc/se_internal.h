@@ -41,7 +41,6 @@ struct FftClass {
   int n, n_in, n_out;
   int nst;
   int rad[kMaxStages];
-  const void* tw;                 // n twiddles exp(-2 pi i k/n) in compute precision
   const void* in;
   void* out;
   long long in_st, in_s0, in_s1;
@@ -70,7 +69,7 @@ struct FftPass {
   int lgB;
   int nmax;                       // largest n (LDS sizing)
   int kind;
-  int xcd;                        // 1: XCD-contiguous item mapping
+  int xcd;                        // item mapping: 0 plain, 1 one range per XCD, c >= 2 chunks of c
   double alg_bytes, alg_flops;    // algorithmic counts of one launch (tracing only)
 };
 
@@ -84,7 +83,7 @@ struct GridGeom {
   int nt[3];          // tiles per direction
   int nsb[3];         // sub-bins per direction, ceil(G / kSB)
   int chunk;          // particles per wavefront round of the spread kernel (<= 64)
-  int xcd;            // 1: XCD-contiguous tile mapping
+  int xcd;            // tile mapping: 0 plain, 1 one range per XCD, c >= 2 chunks of c
   int P, nu;
   int window;         // 0 Gaussian, 1 PKB
   double h, L, xi;
@@ -137,7 +136,7 @@ struct BatchIO {
   void* force;
   double* energy;     // one per system
   int in_f32, out_grad, add_self, allow_nonneutral;
-  int xcd_tiles, xcd_fft;   // XCD-contiguous item mapping of the tile / transform stages
+  int xcd_tiles, xcd_fft;   // item mapping modes of the tile / transform stages (as GridGeom::xcd)
 };
 
 // Stages of a batched evaluation, in order; one launch per stage.

@@ -178,15 +178,25 @@ __device__ __forceinline__ void dft(cx<T>* v, int sign) {
 __device__ __forceinline__ int fdiv(int a, float inv_d) { return (int)(((float)a + 0.5f) * inv_d); }
 
 // Work item of workgroup b out of n.  Workgroups are handed to the 8 XCDs in
-// turn (b mod 8); each XCD is given a contiguous range of items instead, so
-// that neighbouring items, which share cache lines at their edges, meet in
-// the same L2.  A bijection of [0, n).
+// turn (b mod 8), so neighbouring items, which share cache lines at their
+// edges, land in different L2s.  Mode 1 gives each XCD one contiguous range of
+// items; mode c >= 2 gives each XCD chunks of c neighbouring items while the
+// XCDs work side by side (rounds of 8c items; the last partial round keeps the
+// plain order).  Both are bijections of [0, n); mode 0 is the plain order.
 constexpr int kXcds = 8;
-__device__ __forceinline__ int xcd_item(int b, int n) {
-  const int x = b % kXcds, s = b / kXcds, q = n / kXcds, r = n % kXcds;
-  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + s;
+__device__ __forceinline__ int xcd_item(int b, int n, int mode) {
+  const int x = b % kXcds, s = b / kXcds;
+  if (mode == 1) {
+    const int q = n / kXcds, r = n % kXcds;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + s;
+  }
+  const int c = mode, round = kXcds * c;
+  if (b >= (n / round) * round) return b;
+  return ((s / c) * kXcds + x) * c + s % c;
 }
-__device__ __forceinline__ int work_item(int on) { return on ? xcd_item(blockIdx.x, gridDim.x) : blockIdx.x; }
+__device__ __forceinline__ int work_item(int mode) {
+  return mode > 0 ? xcd_item(blockIdx.x, gridDim.x, mode) : blockIdx.x;
+}
 
 // One Stockham stage from src to dst (LDS) over B = 2^lgB interleaved pencils
 // stored sample-major with pitch Bp (sample t of pencil p at t*Bp + p):
@@ -252,30 +262,46 @@ __device__ cx<T>* fft_run(cx<T>* b0, cx<T>* b1, const cx<T>* tw, const FftClass&
 
 __device__ __forceinline__ int fold_index(int i, int n) { return i <= n - i ? i : n - i; }
 
+// The factors of Eq. (scale) that depend only on the pencil (b0, b1): the
+// separable vectors of the two pencil directions and the pencil's part of the
+// table or |k|^2 index.
 template <typename T>
-__device__ __forceinline__ T scale_factor(const FftClass& C, int b0, int b1, int t) {
-  const T* sA = (const T*)C.sA;
-  const T* sB = (const T*)C.sB;
-  const T* sC = (const T*)C.sC;
-  T s = sA[b0 + C.offA] * sB[b1 + C.offB] * sC[t];
+struct ScaleRow {
+  T s;          // sA[b0] sB[b1]
+  T k2;         // kA[b0] + kB[b1]            (G_INVSQ)
+  long long g;  // table offset of the pencil (G_TAB2, G_TAB3)
+};
+
+template <typename T>
+__device__ __forceinline__ ScaleRow<T> scale_row(const FftClass& C, int b0, int b1) {
+  ScaleRow<T> r;
+  r.s = ((const T*)C.sA)[b0 + C.offA] * ((const T*)C.sB)[b1 + C.offB];
+  r.k2 = 0;
+  r.g = 0;
+  const int i0 = C.fold0 ? fold_index(b0, C.fold0) : b0;
+  if (C.gmode == G_INVSQ) r.k2 = ((const T*)C.kA)[b0 + C.offA] + ((const T*)C.kB)[b1 + C.offB];
+  else if (C.gmode == G_TAB2) r.g = i0;
+  else if (C.gmode == G_TAB3) r.g = (long long)fold_index(b1, C.fold1) * C.gd0 + i0;
+  return r;
+}
+
+// Tables store the pencil index b0 fastest, so neighbouring lanes (neighbouring
+// pencils) read neighbouring entries: G_TAB2 [t][b0], G_TAB3 [t][b1][b0].
+template <typename T>
+__device__ __forceinline__ T scale_at(const FftClass& C, const ScaleRow<T>& r, int t) {
+  const T s = r.s * ((const T*)C.sC)[t];
   const T* gt = (const T*)C.gtab;
   switch (C.gmode) {
     case G_INVSQ: {
-      const T k2 = ((const T*)C.kA)[b0 + C.offA] + ((const T*)C.kB)[b1 + C.offB] + ((const T*)C.kC)[t];
+      const T k2 = r.k2 + ((const T*)C.kC)[t];
       return k2 > (T)0 ? s / k2 : (T)0;
     }
     case G_TAB1:
       return s * gt[t];
-    // tables store the pencil index b0 fastest, so that neighbouring lanes
-    // (neighbouring pencils) read neighbouring entries
-    case G_TAB2: {
-      const int i0 = C.fold0 ? fold_index(b0, C.fold0) : b0;
-      return s * gt[(long long)fold_index(t, C.fold2) * C.gd0 + i0];
-    }
-    case G_TAB3: {
-      const int i0 = C.fold0 ? fold_index(b0, C.fold0) : b0;
-      return s * gt[((long long)fold_index(t, C.fold2) * C.gd1 + fold_index(b1, C.fold1)) * C.gd0 + i0];
-    }
+    case G_TAB2:
+      return s * gt[(long long)fold_index(t, C.fold2) * C.gd0 + r.g];
+    case G_TAB3:
+      return s * gt[(long long)fold_index(t, C.fold2) * C.gd1 * C.gd0 + r.g];
     default:
       return s;
   }
@@ -318,8 +344,12 @@ __device__ __forceinline__ void stage_fft(const FftPass& P, int item, unsigned c
   cx<T>* buf = tw + P.nmax;
   cx<T>* buf2 = buf + (size_t)P.nmax * ((1 << lgB) + 1);
 
-  const cx<T>* twg = reinterpret_cast<const cx<T>*>(C.tw);
-  for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = twg[i];
+  // twiddles exp(-2 pi i k/n), evaluated in FP64 and rounded once
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double sn, cs;
+    sincospi(-2.0 * (double)i / (double)n, &sn, &cs);
+    tw[i] = cx<T>{(T)cs, (T)sn};
+  }
 
   // ---- load the pencils, zero padded to n ----
   const bool t_fast = (C.in_st == 1);
@@ -411,12 +441,17 @@ __device__ __forceinline__ void stage_fft(const FftPass& P, int item, unsigned c
   }
 
   if constexpr (KIND == K_FUSED) {
-    // scaling step, Eq. (scale), on the spectrum of each pencil
+    // scaling step, Eq. (scale), on the spectrum of each pencil; the block
+    // size is a multiple of B, so each thread keeps one pencil p throughout
     const int mask = (1 << lgB) - 1;
     const int total = n << lgB;
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-      const int t = e >> lgB, p = e & mask;
-      if (p < cnt) res[t * Bp + p] = cscale(res[t * Bp + p], scale_factor<T>(C, b0s + p, b1, t));
+    const int p = threadIdx.x & mask;
+    if (p < cnt) {
+      const ScaleRow<T> row = scale_row<T>(C, b0s + p, b1);
+      for (int e = threadIdx.x; e < total; e += blockDim.x) {
+        const int t = e >> lgB;
+        res[t * Bp + p] = cscale(res[t * Bp + p], scale_at<T>(C, row, t));
+      }
     }
     __syncthreads();
     res = fft_run<T>(res, res == buf ? buf2 : buf, tw, C, lgB, Bp, +1);

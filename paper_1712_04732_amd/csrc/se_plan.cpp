@@ -220,16 +220,6 @@ struct se_plan {
   }
 
   // Twiddles exp(-2 pi i k/n), k = 0..n-1, interleaved complex.
-  const void* twiddles(int n) {
-    std::vector<double> t(2 * (size_t)n);
-    for (int k = 0; k < n; ++k) {
-      const long double a = -2.0L * 3.141592653589793238462643383279502884L * k / n;
-      t[2 * k] = (double)std::cos(a);
-      t[2 * k + 1] = (double)std::sin(a);
-    }
-    return upload(t);
-  }
-
   // Scaling vector of a direction transformed at length n over spacing h:
   //   e^{-k^2/4xi^2} / What(k)^2 / n   with k = 2 pi m/(n h), m the signed frequency.
   // The 1/n is the inverse transform's normalisation.
@@ -255,7 +245,7 @@ struct se_plan {
 
 namespace {
 
-se::FftClass make_class(int n, int n_in, int n_out, const void* tw, const void* in, void* out,
+se::FftClass make_class(int n, int n_in, int n_out, const void* in, void* out,
                         long long in_st, long long in_s0, long long in_s1, long long out_st,
                         long long out_s0, long long out_s1) {
   se::FftClass c{};
@@ -263,7 +253,6 @@ se::FftClass make_class(int n, int n_in, int n_out, const void* tw, const void* 
   c.n_in = n_in;
   c.n_out = n_out;
   radix_plan(n, c.rad, &c.nst);
-  c.tw = tw;
   c.in = in;
   c.out = out;
   c.in_st = in_st;
@@ -281,6 +270,10 @@ void add_items(std::vector<int4>& items, int cls, int b0_lo, int b0_hi, int b1_l
 }
 
 }  // namespace
+
+// Work-item mapping mode of a knob value: < 0 plain order, 0 the default
+// (one item range per XCD), 1 one range per XCD, c >= 2 chunks of c.
+static int xcd_mode(int knob) { return knob < 0 ? 0 : (knob == 0 ? 1 : knob); }
 
 // Finish a pass: pencils per block from the LDS budget, upload the work list.
 static bool finish_pass(se_plan* pl, se::FftPass& ps, int kind, int ncls,
@@ -303,7 +296,7 @@ static bool finish_pass(se_plan* pl, se::FftPass& ps, int kind, int ncls,
   if (lds_of(1L << lgB) > pl->lds_max) return false;
   ps.lgB = lgB;
   ps.B = 1 << lgB;
-  ps.xcd = pl->p.xcd_fft >= 0 ? 1 : 0;
+  ps.xcd = xcd_mode(pl->p.xcd_fft);
   std::vector<int4> items;
   for (const auto& r : ranges) add_items(items, r[0], r[1], r[2], r[3], r[4], ps.B);
   ps.nitems = (int)items.size();
@@ -562,7 +555,7 @@ static se_status plan_create(const se_params* params, long n_max, void* hip_stre
   g.xi = p.xi;
   g.alpha = p.shape;
   g.scale = 4.0 * kPi * I.h * I.h * I.h;
-  g.xcd = p.xcd_tiles >= 0 ? 1 : 0;
+  g.xcd = xcd_mode(p.xcd_tiles);
   {
     // Largest tile whose spread and gather LDS fit, with at least min_tiles
     // tiles when the grid allows it.
@@ -706,25 +699,24 @@ static se_status build_passes(se_plan* pl) {
     const int nx = M, Kx = M / 2 + 1;
     void* cb = pl->dalloc(ce * (size_t)Kx * Gy * Gz);
     if (!cb) return fail();
-    const void* twM = pl->twiddles(M);
     const void* sepM = pl->sep_table(M);
     const void* k2M = pl->k2_table(M);
-    if (!twM || !sepM || !k2M) return fail();
+    if (!sepM || !k2M) return fail();
     // x: real-to-complex
     se::FftPass p1{};
-    p1.cls[0] = make_class(nx, Gx, Kx, twM, pl->buf.grid, cb, 1, Gx, (long long)Gx * Gy, 1, Kx, (long long)Kx * Gy);
+    p1.cls[0] = make_class(nx, Gx, Kx, pl->buf.grid, cb, 1, Gx, (long long)Gx * Gy, 1, Kx, (long long)Kx * Gy);
     rg = {{0, 0, Gy, 0, Gz}};
     if (!finish_pass(pl, p1, se::K_R2C, 1, rg)) return fail();
     // y: complex forward
     se::FftPass p2{};
-    p2.cls[0] = make_class(M, M, M, twM, cb, cb, Kx, 1, (long long)Kx * Gy, Kx, 1, (long long)Kx * Gy);
+    p2.cls[0] = make_class(M, M, M, cb, cb, Kx, 1, (long long)Kx * Gy, Kx, 1, (long long)Kx * Gy);
     rg = {{0, 0, Kx, 0, Gz}};
     if (!finish_pass(pl, p2, se::K_C2C_FWD, 1, rg)) return fail();
     // z: fused forward / scale / inverse
     se::FftPass p3{};
     const long long zst = (long long)Kx * Gy;
     if (D == 3) {
-      se::FftClass c = make_class(M, M, M, twM, cb, cb, zst, 1, Kx, zst, 1, Kx);
+      se::FftClass c = make_class(M, M, M, cb, cb, zst, 1, Kx, zst, 1, Kx);
       c.gmode = se::G_INVSQ;
       c.sA = c.sB = c.sC = sepM;
       c.kA = c.kB = c.kC = k2M;
@@ -734,9 +726,6 @@ static se_status build_passes(se_plan* pl) {
     } else {
       // 2P: AFT classes, Algorithm 1 steps 2-4 / Algorithm 2 steps 1-3
       const int n0 = I.n0, nI = I.nI, nl = I.n_l;
-      const void* tw0 = pl->twiddles(n0);
-      const void* twI = pl->twiddles(nI);
-      const void* twJ = pl->twiddles(Mt);
       const void* s0t = pl->sep_table(n0);
       const void* sIt = pl->sep_table(nI);
       const void* sJt = pl->sep_table(Mt);
@@ -745,19 +734,19 @@ static se_status build_passes(se_plan* pl) {
       std::vector<double> g0(n0);
       for (int t = 0; t < n0; ++t) g0[t] = g2p_zero(2.0 * kPi * signed_freq(t, n0) / (n0 * I.h), I.R);
       const void* g0t = pl->upload(g0);
-      if (!tw0 || !twI || !twJ || !s0t || !sIt || !sJt || !kIt || !kJt || !g0t) return fail();
-      se::FftClass c0 = make_class(n0, Mt, Mt, tw0, cb, cb, zst, 1, Kx, zst, 1, Kx);
+      if (!s0t || !sIt || !sJt || !kIt || !kJt || !g0t) return fail();
+      se::FftClass c0 = make_class(n0, Mt, Mt, cb, cb, zst, 1, Kx, zst, 1, Kx);
       c0.gmode = se::G_TAB1;
       c0.sA = c0.sB = sepM;
       c0.sC = s0t;
       c0.gtab = g0t;
-      se::FftClass cI = make_class(nI, Mt, Mt, twI, cb, cb, zst, 1, Kx, zst, 1, Kx);
+      se::FftClass cI = make_class(nI, Mt, Mt, cb, cb, zst, 1, Kx, zst, 1, Kx);
       cI.gmode = se::G_INVSQ;
       cI.sA = cI.sB = sepM;
       cI.kA = cI.kB = k2M;
       cI.sC = sIt;
       cI.kC = kIt;
-      se::FftClass cJ = make_class(Mt, Mt, Mt, twJ, cb, cb, zst, 1, Kx, zst, 1, Kx);
+      se::FftClass cJ = make_class(Mt, Mt, Mt, cb, cb, zst, 1, Kx, zst, 1, Kx);
       cJ.gmode = se::G_INVSQ;
       cJ.sA = cJ.sB = sepM;
       cJ.kA = cJ.kB = k2M;
@@ -786,7 +775,7 @@ static se_status build_passes(se_plan* pl) {
     se::FftPass p4 = p2;
     p4.kind = se::K_C2C_INV;
     se::FftPass p5{};
-    p5.cls[0] = make_class(nx, Kx, Gx, twM, cb, pl->buf.grid, 1, Kx, (long long)Kx * Gy, 1, Gx, (long long)Gx * Gy);
+    p5.cls[0] = make_class(nx, Kx, Gx, cb, pl->buf.grid, 1, Kx, (long long)Kx * Gy, 1, Gx, (long long)Gx * Gy);
     rg = {{0, 0, Gy, 0, Gz}};
     if (!finish_pass(pl, p5, se::K_C2R, 1, rg)) return fail();
     pl->passes = {p1, p2, p3, p4, p5};
@@ -798,23 +787,22 @@ static se_status build_passes(se_plan* pl) {
     void* cb = pl->dalloc(ce * (size_t)Kx * Mt * Mt);
     void* cb2 = pl->dalloc(ce * (size_t)Kx * n * Mt);
     if (!cb || !cb2) return fail();
-    const void* tw = pl->twiddles(n);
     const void* sep = pl->sep_table(n);
-    if (!tw || !sep) return fail();
+    if (!sep) return fail();
     const void* table = nullptr;
     se_status rc = precompute_0p(pl, nullptr, &table);
     if (rc != SE_OK) return rc;
     se::FftPass p1{};
-    p1.cls[0] = make_class(n, Mt, Kx, tw, pl->buf.grid, cb, 1, Mt, (long long)Mt * Mt, 1, Kx, (long long)Kx * Mt);
+    p1.cls[0] = make_class(n, Mt, Kx, pl->buf.grid, cb, 1, Mt, (long long)Mt * Mt, 1, Kx, (long long)Kx * Mt);
     rg = {{0, 0, Mt, 0, Mt}};
     if (!finish_pass(pl, p1, se::K_R2C, 1, rg)) return fail();
     se::FftPass p2{};
-    p2.cls[0] = make_class(n, Mt, n, tw, cb, cb2, Kx, 1, (long long)Kx * Mt, Kx, 1, (long long)Kx * n);
+    p2.cls[0] = make_class(n, Mt, n, cb, cb2, Kx, 1, (long long)Kx * Mt, Kx, 1, (long long)Kx * n);
     rg = {{0, 0, Kx, 0, Mt}};
     if (!finish_pass(pl, p2, se::K_C2C_FWD, 1, rg)) return fail();
     se::FftPass p3{};
     const long long zst = (long long)Kx * n;
-    se::FftClass c = make_class(n, Mt, Mt, tw, cb2, cb2, zst, 1, Kx, zst, 1, Kx);
+    se::FftClass c = make_class(n, Mt, Mt, cb2, cb2, zst, 1, Kx, zst, 1, Kx);
     c.gmode = se::G_TAB3;
     c.sA = c.sB = c.sC = sep;
     c.gtab = table;
@@ -825,11 +813,11 @@ static se_status build_passes(se_plan* pl) {
     rg = {{0, 0, Kx, 0, n}};
     if (!finish_pass(pl, p3, se::K_FUSED, 1, rg)) return fail();
     se::FftPass p4{};
-    p4.cls[0] = make_class(n, n, Mt, tw, cb2, cb, Kx, 1, (long long)Kx * n, Kx, 1, (long long)Kx * Mt);
+    p4.cls[0] = make_class(n, n, Mt, cb2, cb, Kx, 1, (long long)Kx * n, Kx, 1, (long long)Kx * Mt);
     rg = {{0, 0, Kx, 0, Mt}};
     if (!finish_pass(pl, p4, se::K_C2C_INV, 1, rg)) return fail();
     se::FftPass p5{};
-    p5.cls[0] = make_class(n, Kx, Mt, tw, cb, pl->buf.grid, 1, Kx, (long long)Kx * Mt, 1, Mt, (long long)Mt * Mt);
+    p5.cls[0] = make_class(n, Kx, Mt, cb, pl->buf.grid, 1, Kx, (long long)Kx * Mt, 1, Mt, (long long)Mt * Mt);
     rg = {{0, 0, Mt, 0, Mt}};
     if (!finish_pass(pl, p5, se::K_C2R, 1, rg)) return fail();
     pl->passes = {p1, p2, p3, p4, p5};
@@ -845,10 +833,6 @@ static se_status build_passes(se_plan* pl) {
   void* b0 = pl->dalloc(ce * (size_t)n0 * Mt);
   void* bI = pl->dalloc(ce * (size_t)std::max(1, nl) * nI * Mt);
   if (!cb || !b0 || !bI) return fail();
-  const void* twM = pl->twiddles(M);
-  const void* tw0 = pl->twiddles(n0);
-  const void* twI = pl->twiddles(nI);
-  const void* twJ = pl->twiddles(Mt);
   const void* sepM = pl->sep_table(M);
   const void* k2M = pl->k2_table(M);
   const void* s0t = pl->sep_table(n0);
@@ -865,20 +849,20 @@ static se_status build_passes(se_plan* pl) {
       g1[(size_t)iz * h0 + iy] = g1p_zero(std::sqrt(ky * ky + kz * kz), I.R);
     }
   const void* g1t = pl->upload(g1);
-  if (!twM || !tw0 || !twI || !twJ || !sepM || !k2M || !s0t || !sIt || !sJt || !kIt || !kJt || !g1t)
+  if (!sepM || !k2M || !s0t || !sIt || !sJt || !kIt || !kJt || !g1t)
     return fail();
   char* cbc = (char*)cb;
   const long long mst = (long long)Kx * Mt;  // z stride of the main buffer
   // x: real-to-complex
   se::FftPass p1{};
-  p1.cls[0] = make_class(M, Gx, Kx, twM, pl->buf.grid, cb, 1, Gx, (long long)Gx * Gy, 1, Kx, mst);
+  p1.cls[0] = make_class(M, Gx, Kx, pl->buf.grid, cb, 1, Gx, (long long)Gx * Gy, 1, Kx, mst);
   rg = {{0, 0, Gy, 0, Gz}};
   if (!finish_pass(pl, p1, se::K_R2C, 1, rg)) return fail();
   // y: padded forward transforms per class (Algorithm 1 steps 2-4, first free direction)
   se::FftPass p2{};
-  p2.cls[0] = make_class(n0, Mt, n0, tw0, cb, b0, Kx, 0, mst, 1, 0, n0);
-  p2.cls[1] = make_class(nI, Mt, nI, twI, cbc + ce * 1, bI, Kx, 1, mst, nl, 1, (long long)nI * nl);
-  p2.cls[2] = make_class(Mt, Mt, Mt, twJ, cbc + ce * (nl + 1), cbc + ce * (nl + 1), Kx, 1, mst, Kx, 1, mst);
+  p2.cls[0] = make_class(n0, Mt, n0, cb, b0, Kx, 0, mst, 1, 0, n0);
+  p2.cls[1] = make_class(nI, Mt, nI, cbc + ce * 1, bI, Kx, 1, mst, nl, 1, (long long)nI * nl);
+  p2.cls[2] = make_class(Mt, Mt, Mt, cbc + ce * (nl + 1), cbc + ce * (nl + 1), Kx, 1, mst, Kx, 1, mst);
   rg = {{0, 0, 1, 0, Mt}};
   if (nl > 0) rg.push_back({1, 0, nl, 0, Mt});
   if (nJ > 0) rg.push_back({2, 0, nJ, 0, Mt});
@@ -886,7 +870,7 @@ static se_status build_passes(se_plan* pl) {
   // z: fused forward / scale / inverse per class
   se::FftPass p3{};
   {
-    se::FftClass c0 = make_class(n0, Mt, Mt, tw0, b0, b0, n0, 1, 0, n0, 1, 0);
+    se::FftClass c0 = make_class(n0, Mt, Mt, b0, b0, n0, 1, 0, n0, 1, 0);
     c0.gmode = se::G_TAB2;
     c0.sA = s0t;
     c0.sB = sepM;
@@ -895,7 +879,7 @@ static se_status build_passes(se_plan* pl) {
     c0.gd0 = h0;
     c0.fold0 = n0;
     c0.fold2 = n0;
-    se::FftClass cI = make_class(nI, Mt, Mt, twI, bI, bI, (long long)nI * nl, 1, nl, (long long)nI * nl, 1, nl);
+    se::FftClass cI = make_class(nI, Mt, Mt, bI, bI, (long long)nI * nl, 1, nl, (long long)nI * nl, 1, nl);
     cI.gmode = se::G_INVSQ;
     cI.sA = sepM;
     cI.kA = k2M;
@@ -904,7 +888,7 @@ static se_status build_passes(se_plan* pl) {
     cI.kB = kIt;
     cI.sC = sIt;
     cI.kC = kIt;
-    se::FftClass cJ = make_class(Mt, Mt, Mt, twJ, cbc + ce * (nl + 1), cbc + ce * (nl + 1), mst, 1, Kx, mst, 1, Kx);
+    se::FftClass cJ = make_class(Mt, Mt, Mt, cbc + ce * (nl + 1), cbc + ce * (nl + 1), mst, 1, Kx, mst, 1, Kx);
     cJ.gmode = se::G_INVSQ;
     cJ.sA = sepM;
     cJ.kA = k2M;
@@ -923,8 +907,8 @@ static se_status build_passes(se_plan* pl) {
   if (!finish_pass(pl, p3, se::K_FUSED, 3, rg)) return fail();
   // y: inverse transforms with truncation back to Mt (Algorithm 2 steps 1-4)
   se::FftPass p4{};
-  p4.cls[0] = make_class(n0, n0, Mt, tw0, b0, cb, 1, 0, n0, Kx, 0, mst);
-  p4.cls[1] = make_class(nI, nI, Mt, twI, bI, cbc + ce * 1, nl, 1, (long long)nI * nl, Kx, 1, mst);
+  p4.cls[0] = make_class(n0, n0, Mt, b0, cb, 1, 0, n0, Kx, 0, mst);
+  p4.cls[1] = make_class(nI, nI, Mt, bI, cbc + ce * 1, nl, 1, (long long)nI * nl, Kx, 1, mst);
   p4.cls[2] = p2.cls[2];
   rg = {{0, 0, 1, 0, Mt}};
   if (nl > 0) rg.push_back({1, 0, nl, 0, Mt});
@@ -932,7 +916,7 @@ static se_status build_passes(se_plan* pl) {
   if (!finish_pass(pl, p4, se::K_C2C_INV, 3, rg)) return fail();
   // x: complex-to-real
   se::FftPass p5{};
-  p5.cls[0] = make_class(M, Kx, Gx, twM, cb, pl->buf.grid, 1, Kx, mst, 1, Gx, (long long)Gx * Gy);
+  p5.cls[0] = make_class(M, Kx, Gx, cb, pl->buf.grid, 1, Kx, mst, 1, Gx, (long long)Gx * Gy);
   rg = {{0, 0, Gy, 0, Gz}};
   if (!finish_pass(pl, p5, se::K_C2R, 1, rg)) return fail();
   pl->passes = {p1, p2, p3, p4, p5};
@@ -954,27 +938,18 @@ static se_status precompute_0p(se_plan* pl, hipStream_t st, const void** table) 
     return SE_ERR_NOMEM;
   }
   se_status rc = SE_OK;
-  const bool f64_saved = pl->f64;
   do {
-    pl->f64 = true;  // twiddles of the precompute are FP64
-    const void* twb = pl->twiddles(n0);
-    const void* tws = pl->twiddles(n);
-    pl->f64 = f64_saved;
-    if (!twb || !tws) {
-      rc = SE_ERR_NOMEM;
-      break;
-    }
     if (se::launch_g0p_fill(big, n0, h, R, st) != hipSuccess) {
       rc = SE_ERR_DEVICE;
       break;
     }
     // 3D complex transforms of an n^3 array: x (contiguous), y, z
-    auto run3 = [&](double* a, int len, const void* tw, int kind) -> bool {
+    auto run3 = [&](double* a, int len, int kind) -> bool {
       const long long L1 = len, L2 = (long long)len * len;
       const long long st_[3] = {1, L1, L2}, s0_[3] = {L1, 1, 1}, s1_[3] = {L2, L2, L1};
       for (int ax = 0; ax < 3; ++ax) {
         se::FftPass ps{};
-        ps.cls[0] = make_class(len, len, len, tw, a, a, st_[ax], s0_[ax], s1_[ax], st_[ax], s0_[ax], s1_[ax]);
+        ps.cls[0] = make_class(len, len, len, a, a, st_[ax], s0_[ax], s1_[ax], st_[ax], s0_[ax], s1_[ax]);
         const bool saved = pl->f64;
         pl->f64 = true;
         const bool ok = finish_pass(pl, ps, kind, 1, {{0, 0, len, 0, len}});
@@ -984,7 +959,7 @@ static se_status precompute_0p(se_plan* pl, hipStream_t st, const void** table) 
       }
       return true;
     };
-    if (!run3(big, n0, twb, se::K_C2C_INV)) {
+    if (!run3(big, n0, se::K_C2C_INV)) {
       rc = SE_ERR_DEVICE;
       break;
     }
@@ -992,7 +967,7 @@ static se_status precompute_0p(se_plan* pl, hipStream_t st, const void** table) 
       rc = SE_ERR_DEVICE;
       break;
     }
-    if (!run3(small, n, tws, se::K_C2C_FWD)) {
+    if (!run3(small, n, se::K_C2C_FWD)) {
       rc = SE_ERR_DEVICE;
       break;
     }
@@ -1012,7 +987,6 @@ static se_status precompute_0p(se_plan* pl, hipStream_t st, const void** table) 
     }
     *table = tab;
   } while (false);
-  pl->f64 = f64_saved;
   (void)hipFree(big);
   (void)hipFree(small);
   return rc;
@@ -1357,8 +1331,8 @@ se_status se_eval_batch(se_batch_plan* plan, const void* xyz, const void* q, voi
   io.out_grad = (flags & SE_OUT_GRAD) ? 1 : 0;
   io.add_self = (flags & SE_ADD_SELF) ? 1 : 0;
   io.allow_nonneutral = (flags & SE_ALLOW_NONNEUTRAL) ? 1 : 0;
-  io.xcd_tiles = plan->sys[0]->p.xcd_tiles >= 0 ? 1 : 0;
-  io.xcd_fft = plan->sys[0]->p.xcd_fft >= 0 ? 1 : 0;
+  io.xcd_tiles = xcd_mode(plan->sys[0]->p.xcd_tiles);
+  io.xcd_fft = xcd_mode(plan->sys[0]->p.xcd_fft);
   const bool prof = (flags & SE_PROFILE) != 0;
   if (prof && !plan->have_ev) {
     for (hipEvent_t& e : plan->ev)
@@ -1463,6 +1437,7 @@ constexpr int kTuneWarm = 2, kTuneReps = 5;
 const int kTuneTiles[][3] = {{16, 16, 16}, {32, 16, 8}, {32, 8, 8}, {16, 16, 8},
                              {16, 8, 8},   {8, 8, 8},   {8, 8, 4},  {4, 4, 4}};
 const int kTuneCaps[] = {1024, 2048, 4096, 8192};
+const int kTuneXcd[] = {-1, 8, 32};   // plain order, chunks of 8, chunks of 32 (besides the default)
 
 struct TuneIO {
   const void* xyz;
@@ -1539,10 +1514,12 @@ bool tune_knobs(se_params* base, int n_par, bool tune_xcd, Timer timer, se_tune_
     }
   }
   if (tune_xcd) {
-    auto v = cur;
-    for (auto& p : v) p.xcd_tiles = -1;
-    TuneTimes t;
-    if (timer(v, &t)) {
+    const auto base_v = cur;
+    for (int mode : kTuneXcd) {
+      auto v = base_v;
+      for (auto& p : v) p.xcd_tiles = mode;
+      TuneTimes t;
+      if (!timer(v, &t)) continue;
       ++cand;
       if (t.tiles < best) {
         best = t.tiles;
@@ -1566,10 +1543,12 @@ bool tune_knobs(se_params* base, int n_par, bool tune_xcd, Timer timer, se_tune_
     }
   }
   if (tune_xcd) {
-    auto v = cur;
-    for (auto& p : v) p.xcd_fft = -1;
-    TuneTimes t;
-    if (timer(v, &t)) {
+    const auto base_v = cur;
+    for (int mode : kTuneXcd) {
+      auto v = base_v;
+      for (auto& p : v) p.xcd_fft = mode;
+      TuneTimes t;
+      if (!timer(v, &t)) continue;
       ++cand;
       if (t.fft < best) {
         best = t.fft;
@@ -1675,18 +1654,18 @@ se_status se_batch_autotune(const se_params* params, const long* N, int n_sys, c
     if (!time_batch(def, vN, io, &t0)) return SE_ERR_UNSUPPORTED;
     if (!time_batch(out, vN, io, &tb)) return SE_ERR_UNSUPPORTED;
     int cand = 2;
-    for (int mode = 1; mode < 4; ++mode) {
-      auto v = out;
-      for (auto& p : v) {
-        p.xcd_tiles = (mode & 1) ? -1 : 1;
-        p.xcd_fft = (mode & 2) ? -1 : 1;
-      }
-      TuneTimes t;
-      if (!time_batch(v, vN, io, &t)) continue;
-      ++cand;
-      if (t.all < tb.all) {
-        tb = t;
-        out = v;
+    for (int group = 0; group < 2; ++group) {
+      const auto base_v = out;
+      for (int mode : kTuneXcd) {
+        auto v = base_v;
+        for (auto& p : v) (group == 0 ? p.xcd_tiles : p.xcd_fft) = mode;
+        TuneTimes t;
+        if (!time_batch(v, vN, io, &t)) continue;
+        ++cand;
+        if ((group == 0 ? t.tiles < tb.tiles : t.fft < tb.fft)) {
+          tb = t;
+          out = v;
+        }
       }
     }
     if (tb.all > t0.all) {

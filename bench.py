@@ -135,14 +135,14 @@ def batch_cpu_baseline(systems, budget_s=15.0, per_sys_targets=256):
                       f"each against all of its sources, {t_tot:.1f} s"}, res
 
 
-_KNOBS = ("tile3", "fft_cap", "xcd_tiles", "xcd_fft")
+_KNOBS = ("tile3", "fft_cap", "xcd_tiles", "xcd_fft", "spread_mode")
 
 
 def _save_schedule(path, params):
     """The autotuner's knobs, one entry per system (with D and M to check
     that a stored schedule belongs to the same batch)."""
-    rows = [dict(D=p.D, M=p.M, tile3=list(p.tile3), fft_cap=p.fft_cap, xcd_tiles=p.xcd_tiles, xcd_fft=p.xcd_fft)
-            for p in params]
+    rows = [dict(D=p.D, M=p.M, tile3=list(p.tile3), fft_cap=p.fft_cap, xcd_tiles=p.xcd_tiles, xcd_fft=p.xcd_fft,
+                 spread_mode=p.spread_mode) for p in params]
     os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
     with open(path, "w") as f:
         f.write('{"device": "MI355X (gfx950)", "systems": [\n')
@@ -158,6 +158,7 @@ def _load_schedule(path, params):
         for d in range(3):
             p.tile3[d] = r["tile3"][d]
         p.fft_cap, p.xcd_tiles, p.xcd_fft = r["fft_cap"], r["xcd_tiles"], r["xcd_fft"]
+        p.spread_mode = r.get("spread_mode", 0)
     return True
 
 
@@ -201,7 +202,9 @@ def main_batch(args):
             _save_schedule(args.save_schedule, b32.params)
     tiles = sorted({tuple(b32.info(k).tile) for k in range(len(N))})
     caps = sorted({b32.info(k).fft_cap for k in range(len(N))})
-    print(f"bench: schedule {schedule}: tiles {tiles} fft_cap {caps}", file=sys.stderr, flush=True)
+    modes = sorted({b32.info(k).spread_mode for k in range(len(N))})
+    print(f"bench: schedule {schedule}: tiles {tiles} fft_cap {caps} spread modes {modes}", file=sys.stderr,
+          flush=True)
     print(f"bench: batch of {len(N)} systems, sum N = {tot}, D counts "
           f"{np.bincount([s['D'] for s in systems], minlength=4).tolist()}, M {min(p.M for p in p32)}.."
           f"{max(p.M for p in p32)}, plan {t_plan:.1f} s",
@@ -261,8 +264,8 @@ def main_batch(args):
         print(f"bench:   {r['name']:8s} {r['ms_avg'] * 1e3:9.1f} us  {r['bytes'] / t / 1e9:8.1f} GB/s  "
               f"{r['flops'] / t / 1e12:7.2f} TFLOP/s", file=sys.stderr, flush=True)
     roof = roofline(stages, "f32")
-    stage_ids = {"zero": 0, "bin": 1, "scan1": 2, "scan2": 3, "scatter": 4, "spread": 5, "fold": 6,
-                 "fft0": 7, "fft1": 8, "fft2": 9, "fft3": 10, "fft4": 11, "gather": 12, "energy": 13}
+    stage_ids = {n: k for k, n in enumerate(["zero", "bin", "scan1", "scan2", "scatter", "order", "spread", "fold",
+                                             "fft0", "fft1", "fft2", "fft3", "fft4", "gather", "energy"])}
     st_name = roof["kernel"]
     if st_name == "fft2":
         roof["kernel"] = "batch_fft_kernel<float, 4> (fft2: fused forward transform, scaling, inverse transform)"

@@ -89,6 +89,14 @@ typedef struct {
                          contiguous tile range per XCD, c >= 2 chunks of c
                          neighbouring tiles per XCD, 0 -> 1                        */
   int xcd_fft;        /* the same for the transform passes' pencil groups            */
+  int spread_mode;    /* 1: each tile spreads its particles' whole stencils into an
+                         LDS box with halo, boxes are summed by a fold pass;
+                         2: each tile adds the parts of all stencils that reach it
+                         and writes the grid directly (no staging, no fold);
+                         3: as 2, but each thread sums the stencils covering its
+                         own grid column in registers (no atomics; tiles with
+                         x*y <= 256 and z <= 16);
+                         0 -> 3 below 0.1 particles per grid point, else 1        */
 } se_params;
 
 /* Derived sizes of a plan (read-only report). */
@@ -102,6 +110,7 @@ typedef struct {
   int nfft[3];        /* transform lengths of the periodic / 0P padded directions      */
   int tile[3];        /* spread/gather tile edges in grid points (x, y, z)             */
   int fft_cap;        /* samples per FFT workgroup in use                              */
+  int spread_mode;    /* spreading mode in use (1 boxes and fold, 2 clipped, 3 columns) */
   double h, shape, lambda, s0, s, R;
   size_t device_bytes; /* device memory held by the plan                               */
 } se_plan_info;

@@ -57,6 +57,7 @@ class se_params(ctypes.Structure):
         ("fft_cap", ctypes.c_int),
         ("xcd_tiles", ctypes.c_int),
         ("xcd_fft", ctypes.c_int),
+        ("spread_mode", ctypes.c_int),
     ]
 
 
@@ -82,6 +83,7 @@ class se_plan_info(ctypes.Structure):
         ("nfft", ctypes.c_int * 3),
         ("tile", ctypes.c_int * 3),
         ("fft_cap", ctypes.c_int),
+        ("spread_mode", ctypes.c_int),
         ("h", ctypes.c_double),
         ("shape", ctypes.c_double),
         ("lambda_", ctypes.c_double),

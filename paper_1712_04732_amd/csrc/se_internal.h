@@ -16,6 +16,15 @@ constexpr int kMaxNu = 12;
 constexpr int kBlock = 256;      // threads per block of every kernel
 constexpr int kSB = 4;           // sub-bin edge in grid cells (particle sort key)
 constexpr int kMaxOwnRanges = 256;  // sub-bin rows of one tile ((T/kSB)^2 <= 256 for T <= 64)
+// Clipped spreading: most anchor pieces (periodic images) per direction and
+// most particle ranges per tile.
+constexpr int kMaxPieces = 4;
+// Particle records one gather workgroup holds in LDS at a time.
+constexpr int kGatherBatch = 256;
+// Column spreading: particles per weight batch, and most tile points per column.
+constexpr int kColBatch = 128;
+constexpr int kColZ = 16;
+constexpr int kMaxClipRanges = 512;
 // Most periodic images of tile boxes one fold block sums over in a direction.
 constexpr int kMaxFoldImages = 8;
 // Most samples (transform length x pencils) one FFT workgroup holds, and the
@@ -41,6 +50,7 @@ struct FftClass {
   int n, n_in, n_out;
   int nst;
   int rad[kMaxStages];
+  unsigned long long radpack;     // rad[] packed 4 bits per stage, stage 0 lowest
   const void* in;
   void* out;
   long long in_st, in_s0, in_s1;
@@ -84,6 +94,7 @@ struct GridGeom {
   int nsb[3];         // sub-bins per direction, ceil(G / kSB)
   int chunk;          // particles per wavefront round of the spread kernel (<= 64)
   int xcd;            // tile mapping: 0 plain, 1 one range per XCD, c >= 2 chunks of c
+  int clip;           // spreading: 0 boxes + fold, 1 clipped stencils, 2 columns (both write the grid)
   int P, nu;
   int window;         // 0 Gaussian, 1 PKB
   double h, L, xi;
@@ -141,7 +152,7 @@ struct BatchIO {
 
 // Stages of a batched evaluation, in order; one launch per stage.
 enum BatchStage : int {
-  BS_ZERO = 0, BS_BIN, BS_SCAN1, BS_SCAN2, BS_SCATTER, BS_SPREAD, BS_FOLD,
+  BS_ZERO = 0, BS_BIN, BS_SCAN1, BS_SCAN2, BS_SCATTER, BS_ORDER, BS_SPREAD, BS_FOLD,
   BS_FFT0, BS_FFT1, BS_FFT2, BS_FFT3, BS_FFT4, BS_GATHER, BS_ENERGY, BS_COUNT
 };
 constexpr int stage_block(int st) { return st >= BS_FFT0 && st <= BS_FFT4 ? kFftBlock : kBlock; }
@@ -157,6 +168,7 @@ hipError_t launch_bin(const GridGeom& g, const EvalBuffers& b, long N, const voi
 hipError_t launch_scan(const GridGeom& g, const EvalBuffers& b, int nblk_bin, int check_neutral,
                        hipStream_t st);
 hipError_t launch_scatter(const GridGeom& g, const EvalBuffers& b, long N, bool f64, hipStream_t st);
+hipError_t launch_order(const GridGeom& g, const EvalBuffers& b, int nsbtot, bool f64, hipStream_t st);
 hipError_t launch_spread(const GridGeom& g, const EvalBuffers& b, bool f64, hipStream_t st);
 hipError_t launch_fold(const GridGeom& g, const EvalBuffers& b, bool f64, hipStream_t st);
 hipError_t launch_gather(const GridGeom& g, const EvalBuffers& b, bool f64, void* phi, void* force,

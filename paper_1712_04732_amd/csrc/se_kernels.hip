@@ -172,6 +172,18 @@ __device__ __forceinline__ void dft(cx<T>* v, int sign) {
   else dft_odd<T, R>(v, sign);
 }
 
+// A coordinate of direction d folded into the grid: periodic directions wrap
+// (any number of periods), free directions report points outside [0, G).
+__device__ __forceinline__ int wrap_coord(const GridGeom& g, int d, int c, bool* ok) {
+  const int G = g.G[d];
+  if (g.per[d]) {
+    c %= G;
+    return c < 0 ? c + G : c;
+  }
+  *ok = *ok && c >= 0 && c < G;
+  return c;
+}
+
 // Quotient of small non-negative integers a < 2^21 by d, given inv_d = 1/d in
 // FP32: (a + 1/2)/d lies at least 1/(2d) from an integer, which exceeds the
 // rounding error of the product, so truncation gives floor(a/d) exactly.
@@ -236,20 +248,23 @@ __device__ __forceinline__ void fft_stage(const cx<T>* __restrict__ src, cx<T>* 
 // Runs all stages of class C, alternating between the two buffers; returns
 // the buffer holding the result.
 template <typename T>
-__device__ cx<T>* fft_run(cx<T>* b0, cx<T>* b1, const cx<T>* tw, const FftClass& C, int lgB, int Bp,
-                          int sign) {
+__device__ __forceinline__ cx<T>* fft_run(cx<T>* b0, cx<T>* b1, const cx<T>* tw, const FftClass& C, int lgB,
+                                          int Bp, int sign) {
   cx<T>* src = b0;
   cx<T>* dst = b1;
   int Ns = 1;
-  for (int s = 0; s < C.nst; ++s) {
-    const int R = C.rad[s];
+  const int n = C.n, nst = C.nst;
+  unsigned long long radices = C.radpack;   // 4 bits per stage, first stage lowest
+  for (int s = 0; s < nst; ++s) {
+    const int R = (int)(radices & 15u);
+    radices >>= 4;
     switch (R) {
-      case 2: fft_stage<T, 2>(src, dst, tw, C.n, Ns, lgB, Bp, sign); break;
-      case 3: fft_stage<T, 3>(src, dst, tw, C.n, Ns, lgB, Bp, sign); break;
-      case 4: fft_stage<T, 4>(src, dst, tw, C.n, Ns, lgB, Bp, sign); break;
-      case 5: fft_stage<T, 5>(src, dst, tw, C.n, Ns, lgB, Bp, sign); break;
-      case 7: fft_stage<T, 7>(src, dst, tw, C.n, Ns, lgB, Bp, sign); break;
-      default: fft_stage<T, 8>(src, dst, tw, C.n, Ns, lgB, Bp, sign); break;
+      case 2: fft_stage<T, 2>(src, dst, tw, n, Ns, lgB, Bp, sign); break;
+      case 3: fft_stage<T, 3>(src, dst, tw, n, Ns, lgB, Bp, sign); break;
+      case 4: fft_stage<T, 4>(src, dst, tw, n, Ns, lgB, Bp, sign); break;
+      case 5: fft_stage<T, 5>(src, dst, tw, n, Ns, lgB, Bp, sign); break;
+      case 7: fft_stage<T, 7>(src, dst, tw, n, Ns, lgB, Bp, sign); break;
+      default: fft_stage<T, 8>(src, dst, tw, n, Ns, lgB, Bp, sign); break;
     }
     __syncthreads();
     cx<T>* tmp = src;
@@ -344,12 +359,15 @@ __device__ __forceinline__ void stage_fft(const FftPass& P, int item, unsigned c
   cx<T>* buf = tw + P.nmax;
   cx<T>* buf2 = buf + (size_t)P.nmax * ((1 << lgB) + 1);
 
-  // twiddles exp(-2 pi i k/n), evaluated in FP64 and rounded once
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    double sn, cs;
-    sincospi(-2.0 * (double)i / (double)n, &sn, &cs);
-    tw[i] = cx<T>{(T)cs, (T)sn};
-  }
+  // twiddles exp(-2 pi i k/n), evaluated in FP64 and rounded once; computed
+  // while the first round of pencil loads is in flight
+  auto make_twiddles = [&]() {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      double sn, cs;
+      sincospi(-2.0 * (double)i / (double)n, &sn, &cs);
+      tw[i] = cx<T>{(T)cs, (T)sn};
+    }
+  };
 
   // ---- load the pencils, zero padded to n ----
   const bool t_fast = (C.in_st == 1);
@@ -381,6 +399,7 @@ __device__ __forceinline__ void stage_fft(const FftPass& P, int item, unsigned c
           }
         }
       }
+      if (e0 == 0) make_twiddles();
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int e = e0 + u * kFftBlock + threadIdx.x;
@@ -415,6 +434,7 @@ __device__ __forceinline__ void stage_fft(const FftPass& P, int item, unsigned c
           else v[u] = reinterpret_cast<const cx<T>*>(C.in)[idx];
         }
       }
+      if (e0 == 0) make_twiddles();
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int e = e0 + u * kFftBlock + threadIdx.x;
@@ -608,22 +628,28 @@ __device__ __forceinline__ void stage_bin(const GridGeom& g, const EvalBuffers& 
     sa = fabs(qn);
     s2 = qn * qn;
   }
-  // block partial sums of the charges (FP64), for the neutrality check and Q
-  __shared__ double red[3][kBlock / 64];
+  // block partial sums of the charges (FP64), for the neutrality check and Q,
+  // and the block's largest |q| (bounds the spreading's fixed-point range)
+  __shared__ double red[4][kBlock / 64];
+  double smax = sa;
   sq = warp_sum(sq);
   sa = warp_sum(sa);
   s2 = warp_sum(s2);
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) smax = fmax(smax, __shfl_xor(smax, m, 64));
   const int w = threadIdx.x / 64, l = threadIdx.x % 64;
   if (l == 0) {
     red[0][w] = sq;
     red[1][w] = sa;
     red[2][w] = s2;
+    red[3][w] = smax;
   }
   __syncthreads();
-  if (threadIdx.x < 3) {
+  if (threadIdx.x < 4) {
     double s = 0.0;
-    for (int i = 0; i < kBlock / 64; ++i) s += red[threadIdx.x][i];
-    b.qpart[3 * item + threadIdx.x] = s;
+    for (int i = 0; i < kBlock / 64; ++i)
+      s = threadIdx.x == 3 ? fmax(s, red[3][i]) : s + red[threadIdx.x][i];
+    b.qpart[4 * item + threadIdx.x] = s;
   }
 }
 
@@ -697,7 +723,7 @@ __device__ __forceinline__ void stage_scan2(const GridGeom& g, const EvalBuffers
                             int item, int nscan) {
   const int n = g.nsb[0] * g.nsb[1] * g.nsb[2];
   __shared__ int ps[kBlock];
-  __shared__ double dq[3][kBlock];
+  __shared__ double dq[4][kBlock];
   int o = 0;
   for (int j = threadIdx.x; j < item; j += kBlock) o += b.bsum[j];
   ps[threadIdx.x] = o;
@@ -718,21 +744,24 @@ __device__ __forceinline__ void stage_scan2(const GridGeom& g, const EvalBuffers
   }
   if (item == nscan - 1 && threadIdx.x == 0) b.sb_start[n] = offset + b.bsum[item];
   if (item != 0) return;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   for (int i = threadIdx.x; i < nblk_bin; i += kBlock) {
-    a0 += b.qpart[3 * i];
-    a1 += b.qpart[3 * i + 1];
-    a2 += b.qpart[3 * i + 2];
+    a0 += b.qpart[4 * i];
+    a1 += b.qpart[4 * i + 1];
+    a2 += b.qpart[4 * i + 2];
+    a3 = fmax(a3, b.qpart[4 * i + 3]);
   }
   dq[0][threadIdx.x] = a0;
   dq[1][threadIdx.x] = a1;
   dq[2][threadIdx.x] = a2;
+  dq[3][threadIdx.x] = a3;
   __syncthreads();
   for (int off = kBlock / 2; off > 0; off >>= 1) {
     if ((int)threadIdx.x < off) {
       dq[0][threadIdx.x] += dq[0][threadIdx.x + off];
       dq[1][threadIdx.x] += dq[1][threadIdx.x + off];
       dq[2][threadIdx.x] += dq[2][threadIdx.x + off];
+      dq[3][threadIdx.x] = fmax(dq[3][threadIdx.x], dq[3][threadIdx.x + off]);
     }
     __syncthreads();
   }
@@ -740,6 +769,7 @@ __device__ __forceinline__ void stage_scan2(const GridGeom& g, const EvalBuffers
     b.red[0] = dq[0][0];
     b.red[1] = dq[1][0];
     b.red[2] = dq[2][0];
+    b.red[3] = dq[3][0];
     if (check_neutral && fabs(dq[0][0]) > 1e-10 * dq[1][0]) atomicOr(b.status, 4);
   }
 }
@@ -788,6 +818,50 @@ hipError_t launch_scatter(const GridGeom& g, const EvalBuffers& b, long N, bool 
   return hipGetLastError();
 }
 
+// Order each sub-bin's particles by input index.  The scatter fills a
+// sub-bin's slots in the order its atomic cursor is taken, which varies
+// between runs; spreading modes that sum in floating point in particle order
+// need a fixed order to give the same result every time.  One thread per
+// sub-bin, insertion sort of its (short) segment in place.
+template <typename T>
+__device__ __forceinline__ void stage_order(const EvalBuffers& b, int nsbtot, int item) {
+  const int k = item * blockDim.x + threadIdx.x;
+  if (k >= nsbtot) return;
+  const int a = b.sb_start[k], e = b.sb_start[k + 1];
+  Quad<T>* fq = reinterpret_cast<Quad<T>*>(b.s_fq);
+  for (int j = a + 1; j < e; ++j) {
+    const int idx = b.s_idx[j];
+    if (b.s_idx[j - 1] <= idx) continue;
+    const int cell = b.s_cell[j];
+    const Quad<T> f = fq[j];
+    int i = j - 1;
+    while (i >= a && b.s_idx[i] > idx) {
+      b.s_idx[i + 1] = b.s_idx[i];
+      b.s_cell[i + 1] = b.s_cell[i];
+      fq[i + 1] = fq[i];
+      --i;
+    }
+    b.s_idx[i + 1] = idx;
+    b.s_cell[i + 1] = cell;
+    fq[i + 1] = f;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void order_kernel(EvalBuffers b, int nsbtot) {
+  stage_order<T>(b, nsbtot, blockIdx.x);
+}
+
+hipError_t launch_order(const GridGeom& g, const EvalBuffers& b, int nsbtot, bool f64, hipStream_t st) {
+  (void)g;
+  const dim3 grid((unsigned)((nsbtot + kBlock - 1) / kBlock)), block(kBlock);
+  if (f64)
+    order_kernel<double><<<grid, block, 0, st>>>(b, nsbtot);
+  else
+    order_kernel<float><<<grid, block, 0, st>>>(b, nsbtot);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Window weights (Section 4).  f = frac(t) of the particle's grid coordinate,
 // stencil point i at grid index floor(t) - P/2 + 1 + i.
@@ -830,6 +904,8 @@ __device__ __forceinline__ int seg_at(const int* seg, int ns, int r) {
   return (ns == 1 || r < l0) ? seg[0] + r : seg[2] + (r - l0);
 }
 
+__device__ int prefix_ranges(int* rpre, int nr);
+
 // Particle index ranges of the sub-bin rows (z, y, x-segment) of a tile's
 // anchor box, and their exclusive prefix; returns the total particle count.
 // All threads of the block call it; ends with a barrier.
@@ -846,7 +922,12 @@ __device__ int build_ranges(const GridGeom& g, const EvalBuffers& b, const int* 
     rpre[r] = e - a;
   }
   __syncthreads();
-  // exclusive prefix of rpre[0..nr) (nr <= kMaxOwnRanges)
+  return prefix_ranges(rpre, nr);
+}
+
+// Exclusive prefix of rpre[0..nr) in place, rpre[nr] = total; returns the
+// total.  All threads of the block call it; ends with a barrier.
+__device__ int prefix_ranges(int* rpre, int nr) {
   __shared__ int part[kBlock];
   const int per = (nr + blockDim.x - 1) / blockDim.x;
   const int lo = min(nr, (int)threadIdx.x * per), hi = min(nr, lo + per);
@@ -960,7 +1041,7 @@ __device__ __forceinline__ void stage_spread(const GridGeom& g, const EvalBuffer
   int* rpre = rstart + kMaxOwnRanges;                         // kMaxOwnRanges + 1
   T* wbuf = reinterpret_cast<T*>(rpre + kMaxOwnRanges + 4);   // nwaves * CH * 3P
   int* obuf = reinterpret_cast<int*>(wbuf + nwaves * CH * 3 * P);  // nwaves * CH * 3
-  __shared__ double wsum[kBlock / 64];
+  Quad<T>* rbuf = reinterpret_cast<Quad<T>*>(obuf + nwaves * CH * 3 + 4);  // nwaves * CH
 
   for (int i = threadIdx.x; i < R3; i += blockDim.x) acc[i] = 0ull;
   int sx[2] = {x0 / kSB, (x0 + ex - 1) / kSB}, sy[2] = {y0 / kSB, (y0 + ey - 1) / kSB},
@@ -969,18 +1050,9 @@ __device__ __forceinline__ void stage_spread(const GridGeom& g, const EvalBuffer
   const int total = build_ranges(g, b, sz, 1, sy, 1, sx, 1, rstart, rpre);
   const Quad<T>* sfq = reinterpret_cast<const Quad<T>*>(b.s_fq);
 
-  // Fixed-point scale of this tile: |sum of q W| at any box point is at most
-  // sum |q| over the tile's particles (W <= 1), kept below 2^50.
-  double sa = 0.0;
-  for (int e = threadIdx.x; e < total; e += blockDim.x) {
-    const int r = find_range(rpre, nr, e);
-    sa += fabs((double)sfq[rstart[r] + (e - rpre[r])].q);
-  }
-  sa = warp_sum(sa);
-  if (lane == 0) wsum[wave] = sa;
-  __syncthreads();
-  double stile = 0.0;
-  for (int w = 0; w < nwaves; ++w) stile += wsum[w];
+  // Fixed-point scale of this tile: |sum of q W| at any point is at most
+  // (particles) x max |q| (W <= 1), kept below 2^50.
+  const double stile = (double)total * b.red[3];
   const double scale = stile > 0.0 ? 1125899906842624.0 / (1.0009765625 * stile) : 0.0;   // 2^50
 
   // coefficient row of this lane (row k = lane % G2)
@@ -990,28 +1062,32 @@ __device__ __forceinline__ void stage_spread(const GridGeom& g, const EvalBuffer
 
   T* ww = wbuf + wave * CH * 3 * P;
   int* wo = obuf + wave * CH * 3;
+  Quad<T>* wr = rbuf + wave * CH;
   const int RXY = RX * RY;
   for (int base = wave * CH; base < total; base += nwaves * CH) {
     const int nv = min(CH, total - base);
+    // the chunk's particle records, one per lane in one round of loads
+    if (lane < nv) {
+      const int e = base + lane;
+      const int r = find_range(rpre, nr, e);
+      const int i = rstart[r] + (e - rpre[r]);
+      wr[lane] = sfq[i];
+      const int pc = b.s_cell[i];
+      // stencil origin c - P/2 + 1 in box coordinates (box origin x0 - P/2 + 1)
+      wo[3 * lane] = (pc & 1023) - x0;
+      wo[3 * lane + 1] = ((pc >> 10) & 1023) - y0;
+      wo[3 * lane + 2] = ((pc >> 20) & 1023) - z0;
+    }
+    wave_sync();
     // weights: G2 lanes per particle, lane k evaluates row k in x, y, z
     for (int p0 = 0; p0 < nv; p0 += PPW) {
       const int p = p0 + pr;
       if (p < nv && kr < P) {
-        const int e = base + p;
-        const int r = find_range(rpre, nr, e);
-        const int i = rstart[r] + (e - rpre[r]);
-        const Quad<T> f = sfq[i];
+        const Quad<T> f = wr[p];
         T* w = ww + p * 3 * P;
         w[kr] = weight_reg<T, P>(g, crow, kr, f.fx);
         w[P + kr] = weight_reg<T, P>(g, crow, kr, f.fy);
         w[2 * P + kr] = f.q * weight_reg<T, P>(g, crow, kr, f.fz);
-        if (kr == 0) {
-          const int pc = b.s_cell[i];
-          // stencil origin c - P/2 + 1 in box coordinates (box origin x0 - P/2 + 1)
-          wo[3 * p] = (pc & 1023) - x0;
-          wo[3 * p + 1] = ((pc >> 10) & 1023) - y0;
-          wo[3 * p + 2] = ((pc >> 20) & 1023) - z0;
-        }
       }
     }
     wave_sync();
@@ -1039,10 +1115,323 @@ __device__ __forceinline__ void stage_spread(const GridGeom& g, const EvalBuffer
   __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// Spreading straight into the grid (no staging, no fold).  One workgroup per
+// tile takes every particle whose stencil reaches the tile -- its own and its
+// neighbours', periodic images included -- and adds the part of each stencil
+// that falls inside the tile into an LDS copy of the tile alone (T^3 points,
+// 64-bit fixed point as above), then writes the tile once.  A particle near a
+// tile boundary is visited by every tile its stencil reaches; the stencil
+// points it adds are split among those tiles.  Suited to sparse grids, where
+// staging (T+P-1)^3 boxes costs more than the particles.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int floor_div(int a, int b) { return a >= 0 ? a / b : -((b - 1 - a) / b); }
+
+// Anchor cells [lo, hi] (unwrapped) of one direction as pieces of the grid:
+// sub-bin segment [s0, s1] and the image shift added to the cells of the
+// piece.  Returns the number of pieces (at most kMaxPieces; the planner
+// rejects geometries needing more).
+__device__ __forceinline__ int anchor_pieces(const GridGeom& g, int d, int lo, int hi, int* s0, int* s1,
+                                             int* shift) {
+  const int G = g.G[d];
+  int n = 0;
+  if (!g.per[d]) {
+    lo = max(lo, 0);
+    hi = min(hi, G - 1);
+    if (lo <= hi) {
+      s0[0] = lo / kSB;
+      s1[0] = hi / kSB;
+      shift[0] = 0;
+      n = 1;
+    }
+    return n;
+  }
+  for (int k = floor_div(lo, G); k <= floor_div(hi, G) && n < kMaxPieces; ++k) {
+    const int a = max(lo - k * G, 0), e = min(hi - k * G, G - 1);
+    if (a > e) continue;
+    s0[n] = a / kSB;
+    s1[n] = e / kSB;
+    shift[n] = k * G;
+    ++n;
+  }
+  return n;
+}
+
+template <typename T, int P>
+__device__ __forceinline__ void stage_spread_clip(const GridGeom& g, const EvalBuffers& b, int item,
+                                                  unsigned char* smem) {
+  constexpr int G2 = Lanes<P>::G2, PPW = Lanes<P>::PPW;
+  const int TX = g.T[0], TY = g.T[1], TZ = g.T[2];
+  const int tz = item / (g.nt[0] * g.nt[1]);
+  const int ty = (item / g.nt[0]) % g.nt[1];
+  const int tx = item % g.nt[0];
+  const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+  const int ex = min(TX, g.G[0] - x0), ey = min(TY, g.G[1] - y0), ez = min(TZ, g.G[2] - z0);
+  const int T3 = TX * TY * TZ, TXY = TX * TY;
+  const int m = g.nu + 1;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int nwaves = blockDim.x / 64;
+  const int CH = g.chunk;
+
+  unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem);   // T3, fixed point
+  int* rstart = reinterpret_cast<int*>(acc + T3);             // kMaxClipRanges
+  int* rpre = rstart + kMaxClipRanges;                        // kMaxClipRanges + 1
+  int* rsh = rpre + kMaxClipRanges + 4;                       // kMaxClipRanges
+  T* wbuf = reinterpret_cast<T*>(rsh + kMaxClipRanges);       // nwaves * CH * 3P
+  int* obuf = reinterpret_cast<int*>(wbuf + nwaves * CH * 3 * P);  // nwaves * CH * 3
+  Quad<T>* rbuf = reinterpret_cast<Quad<T>*>(obuf + nwaves * CH * 3 + 4);  // nwaves * CH
+  __shared__ int pc_s0[3][kMaxPieces], pc_s1[3][kMaxPieces], pc_sh[3][kMaxPieces], pc_n[3];
+
+  for (int i = threadIdx.x; i < T3; i += blockDim.x) acc[i] = 0ull;
+  if (threadIdx.x < 3) {
+    const int d = threadIdx.x, o = d == 0 ? x0 : (d == 1 ? y0 : z0), e = d == 0 ? ex : (d == 1 ? ey : ez);
+    // anchors c whose stencil c - P/2 + 1 .. c + P/2 meets [o, o + e)
+    pc_n[d] = anchor_pieces(g, d, o - P / 2, o + e - 1 + P / 2 - 1, pc_s0[d], pc_s1[d], pc_sh[d]);
+  }
+  __syncthreads();
+  // ranges: (z piece, z sub-bin) x (y piece, y sub-bin) x x piece
+  int nzb = 0, nyb = 0;
+  for (int k = 0; k < pc_n[2]; ++k) nzb += pc_s1[2][k] - pc_s0[2][k] + 1;
+  for (int k = 0; k < pc_n[1]; ++k) nyb += pc_s1[1][k] - pc_s0[1][k] + 1;
+  const int npx = pc_n[0];
+  const int nr = nzb * nyb * npx;
+  for (int r = threadIdx.x; r < nr; r += blockDim.x) {
+    const int xs = r % npx, ry = (r / npx) % nyb, rz = r / (npx * nyb);
+    int kz = 0, bz = rz, ky = 0, by = ry;
+    while (bz > pc_s1[2][kz] - pc_s0[2][kz]) bz -= pc_s1[2][kz] - pc_s0[2][kz] + 1, ++kz;
+    while (by > pc_s1[1][ky] - pc_s0[1][ky]) by -= pc_s1[1][ky] - pc_s0[1][ky] + 1, ++ky;
+    bz += pc_s0[2][kz];
+    by += pc_s0[1][ky];
+    const int row = (bz * g.nsb[1] + by) * g.nsb[0];
+    const int a = b.sb_start[row + pc_s0[0][xs]], e = b.sb_start[row + pc_s1[0][xs] + 1];
+    rstart[r] = a;
+    rpre[r] = e - a;
+    rsh[r] = kz | (ky << 4) | (xs << 8);
+  }
+  __syncthreads();
+  const int total = prefix_ranges(rpre, nr);
+  const Quad<T>* sfq = reinterpret_cast<const Quad<T>*>(b.s_fq);
+
+  // fixed-point scale: every tile point is bounded by (visits) x max |q|
+  const double stile = (double)total * b.red[3];
+  const double scale = stile > 0.0 ? 1125899906842624.0 / (1.0009765625 * stile) : 0.0;   // 2^50
+
+  const int kr = lane % G2, pr = lane / G2;
+  T crow[kMaxNu + 1];
+  load_row(reinterpret_cast<const T*>(b.wtab), min(kr, P - 1), m, crow);
+
+  T* ww = wbuf + wave * CH * 3 * P;
+  int* wo = obuf + wave * CH * 3;
+  Quad<T>* wr = rbuf + wave * CH;
+  for (int base = wave * CH; base < total; base += nwaves * CH) {
+    const int nv = min(CH, total - base);
+    // the chunk's particle records, one per lane in one round of loads
+    if (lane < nv) {
+      const int e = base + lane;
+      const int r = find_range(rpre, nr, e);
+      const int i = rstart[r] + (e - rpre[r]);
+      wr[lane] = sfq[i];
+      const int pc = b.s_cell[i], code = rsh[r];
+      // stencil origin c + shift - P/2 + 1 in tile coordinates
+      wo[3 * lane] = (pc & 1023) + pc_sh[0][code >> 8] - P / 2 + 1 - x0;
+      wo[3 * lane + 1] = ((pc >> 10) & 1023) + pc_sh[1][(code >> 4) & 15] - P / 2 + 1 - y0;
+      wo[3 * lane + 2] = ((pc >> 20) & 1023) + pc_sh[2][code & 15] - P / 2 + 1 - z0;
+    }
+    wave_sync();
+    for (int p0 = 0; p0 < nv; p0 += PPW) {
+      const int p = p0 + pr;
+      if (p < nv && kr < P) {
+        const Quad<T> f = wr[p];
+        T* w = ww + p * 3 * P;
+        w[kr] = weight_reg<T, P>(g, crow, kr, f.fx);
+        w[P + kr] = weight_reg<T, P>(g, crow, kr, f.fy);
+        w[2 * P + kr] = f.q * weight_reg<T, P>(g, crow, kr, f.fz);
+      }
+    }
+    wave_sync();
+    for (int s = 0; s < nv; ++s) {
+      const int ox = wo[3 * s], oy = wo[3 * s + 1], oz = wo[3 * s + 2];
+      const T* w = ww + s * 3 * P;
+      T wz[P];
+#pragma unroll
+      for (int k = 0; k < P; ++k) wz[k] = w[2 * P + k];
+      // the stencil's z overlap with the tile is the same for all lanes
+      const int iz0 = max(0, -oz), iz1 = min(P, ez - oz);
+      for (int l = lane; l < P * P; l += 64) {
+        const int lx = ox + l % P, ly = oy + l / P;
+        if ((unsigned)lx >= (unsigned)ex || (unsigned)ly >= (unsigned)ey) continue;
+        const double wxy = (double)(w[l % P] * w[P + l / P]) * scale;
+        unsigned long long* col = acc + ly * TX + lx;
+#pragma unroll
+        for (int iz = 0; iz < P; ++iz)
+          if (iz >= iz0 && iz < iz1)
+            atomicAdd(col + (oz + iz) * TXY, (unsigned long long)round_fixed(wxy * (double)wz[iz]));
+      }
+    }
+    wave_sync();
+  }
+  __syncthreads();
+  T* grid = reinterpret_cast<T*>(b.grid);
+  const double inv = stile > 0.0 ? 1.0 / scale : 0.0;
+  {
+    // rows of the tile, 64 / TX rows per wavefront at a time
+    const int rpw = 64 / TX, sub = lane / TX, lx = lane - sub * TX;
+    const int nrows = ey * ez;
+    if (sub < rpw && lx < ex)
+      for (int r0 = wave * rpw; r0 < nrows; r0 += nwaves * rpw) {
+        const int row = r0 + sub;
+        if (row >= nrows) break;
+        const int ly = row % ey, lz = row / ey;
+        grid[((long long)(z0 + lz) * g.G[1] + y0 + ly) * g.G[0] + x0 + lx] =
+            (T)((double)(long long)acc[(lz * TY + ly) * TX + lx] * inv);
+      }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Spreading by columns (no atomics, no staging, no fold).  One workgroup per
+// tile; thread c owns grid column (x0 + c mod TX, y0 + c / TX) of the tile and
+// keeps its TZ values in registers.  The particles whose stencils reach the
+// tile (periodic images included, as for the clipped mode) are taken in
+// batches: each thread evaluates the 3P window weights of one particle into
+// LDS, then every thread adds each stencil that covers its column, the z
+// offsets being the same for all threads (uniform branches, fixed register
+// indices).  Sums run in the compute precision in a fixed particle order.
+// ---------------------------------------------------------------------------
+template <typename T, int P>
+__device__ __forceinline__ void stage_spread_cols(const GridGeom& g, const EvalBuffers& b, int item,
+                                                  unsigned char* smem) {
+  const int TX = g.T[0], TY = g.T[1], TZ = g.T[2];
+  const int tz = item / (g.nt[0] * g.nt[1]);
+  const int ty = (item / g.nt[0]) % g.nt[1];
+  const int tx = item % g.nt[0];
+  const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+  const int ex = min(TX, g.G[0] - x0), ey = min(TY, g.G[1] - y0), ez = min(TZ, g.G[2] - z0);
+  const int m = g.nu + 1;
+
+  int* rstart = reinterpret_cast<int*>(smem);                 // kMaxClipRanges
+  int* rpre = rstart + kMaxClipRanges;                        // kMaxClipRanges + 1
+  int* rsh = rpre + kMaxClipRanges + 4;                       // kMaxClipRanges
+  int* org = rsh + kMaxClipRanges;                            // kColBatch packed origins
+  T* wb = reinterpret_cast<T*>(org + kColBatch);              // kColBatch * 3P weights
+  __shared__ int pc_s0[3][kMaxPieces], pc_s1[3][kMaxPieces], pc_sh[3][kMaxPieces], pc_n[3];
+
+  if (threadIdx.x < 3) {
+    const int d = threadIdx.x, o = d == 0 ? x0 : (d == 1 ? y0 : z0), e = d == 0 ? ex : (d == 1 ? ey : ez);
+    pc_n[d] = anchor_pieces(g, d, o - P / 2, o + e - 1 + P / 2 - 1, pc_s0[d], pc_s1[d], pc_sh[d]);
+  }
+  __syncthreads();
+  int nzb = 0, nyb = 0;
+  for (int k = 0; k < pc_n[2]; ++k) nzb += pc_s1[2][k] - pc_s0[2][k] + 1;
+  for (int k = 0; k < pc_n[1]; ++k) nyb += pc_s1[1][k] - pc_s0[1][k] + 1;
+  const int npx = pc_n[0];
+  const int nr = nzb * nyb * npx;
+  for (int r = threadIdx.x; r < nr; r += blockDim.x) {
+    const int xs = r % npx, ry = (r / npx) % nyb, rz = r / (npx * nyb);
+    int kz = 0, bz = rz, ky = 0, by = ry;
+    while (bz > pc_s1[2][kz] - pc_s0[2][kz]) bz -= pc_s1[2][kz] - pc_s0[2][kz] + 1, ++kz;
+    while (by > pc_s1[1][ky] - pc_s0[1][ky]) by -= pc_s1[1][ky] - pc_s0[1][ky] + 1, ++ky;
+    bz += pc_s0[2][kz];
+    by += pc_s0[1][ky];
+    const int row = (bz * g.nsb[1] + by) * g.nsb[0];
+    const int a = b.sb_start[row + pc_s0[0][xs]], e = b.sb_start[row + pc_s1[0][xs] + 1];
+    rstart[r] = a;
+    rpre[r] = e - a;
+    rsh[r] = kz | (ky << 4) | (xs << 8);
+  }
+  __syncthreads();
+  const int total = prefix_ranges(rpre, nr);
+  const Quad<T>* sfq = reinterpret_cast<const Quad<T>*>(b.s_fq);
+
+  const int c = threadIdx.x, cx = c % TX, cy = c / TX;
+  const bool own = c < TX * TY && cx < ex && cy < ey;
+  T acc[kColZ];
+#pragma unroll
+  for (int z = 0; z < kColZ; ++z) acc[z] = (T)0;
+
+  // weights: G2 lanes per particle, lane kr evaluates stencil row kr in x, y
+  // and z with its coefficient row in registers
+  constexpr int G2 = Lanes<P>::G2;
+  const int kr = threadIdx.x % G2, pv = threadIdx.x / G2, per_pass = blockDim.x / G2;
+  T crow[kMaxNu + 1];
+  load_row(reinterpret_cast<const T*>(b.wtab), min(kr, P - 1), m, crow);
+  for (int v0 = 0; v0 < total; v0 += kColBatch) {
+    const int nb = min(kColBatch, total - v0);
+    if (v0 > 0) __syncthreads();   // the previous batch has been consumed
+    for (int k = pv; k < nb; k += per_pass) {
+      const int e = v0 + k;
+      const int r = find_range(rpre, nr, e);
+      const int i = rstart[r] + (e - rpre[r]);
+      const Quad<T> f = sfq[i];
+      if (kr == 0) {
+        const int pc = b.s_cell[i], code = rsh[r];
+        // stencil origin c + shift - P/2 + 1 in tile coordinates, each in [-P+1, T)
+        const int ox = (pc & 1023) + pc_sh[0][code >> 8] - P / 2 + 1 - x0;
+        const int oy = ((pc >> 10) & 1023) + pc_sh[1][(code >> 4) & 15] - P / 2 + 1 - y0;
+        const int oz = ((pc >> 20) & 1023) + pc_sh[2][code & 15] - P / 2 + 1 - z0;
+        org[k] = (ox + 64) | ((oy + 64) << 8) | ((oz + 64) << 16);
+      }
+      if (kr < P) {
+        T* w = wb + k * 3 * P;
+        w[kr] = weight_reg<T, P>(g, crow, kr, f.fx);
+        w[P + kr] = weight_reg<T, P>(g, crow, kr, f.fy);
+        w[2 * P + kr] = f.q * weight_reg<T, P>(g, crow, kr, f.fz);
+      }
+    }
+    __syncthreads();
+    if (own) {
+      // add visit k's stencil to this column; the origin is the same for all
+      // threads (uniform branches over z)
+      auto add_visit = [&](int k, int o) {
+        o = __builtin_amdgcn_readfirstlane(o);
+        const int ox = (o & 255) - 64, oy = ((o >> 8) & 255) - 64, oz = ((o >> 16) & 255) - 64;
+        const int dx = cx - ox, dy = cy - oy;
+        if ((unsigned)dx < (unsigned)P && (unsigned)dy < (unsigned)P) {
+          const T* w = wb + k * 3 * P;
+          const T wxy = w[dx] * w[P + dy];
+#pragma unroll
+          for (int z = 0; z < kColZ; ++z) {
+            const int iz = z - oz;
+            if ((unsigned)iz < (unsigned)P) acc[z] += wxy * w[2 * P + iz];
+          }
+        }
+      };
+      // two visits per trip so that their LDS reads overlap
+      int k = 0;
+      for (; k + 1 < nb; k += 2) {
+        const int o0 = org[k], o1 = org[k + 1];
+        add_visit(k, o0);
+        add_visit(k + 1, o1);
+      }
+      if (k < nb) add_visit(k, org[k]);
+    }
+  }
+  if (own) {
+    T* grid = reinterpret_cast<T*>(b.grid);
+    const long long base = ((long long)z0 * g.G[1] + y0 + cy) * g.G[0] + x0 + cx;
+    const long long zs = (long long)g.G[0] * g.G[1];
+#pragma unroll
+    for (int z = 0; z < kColZ; ++z)
+      if (z < ez) grid[base + z * zs] = acc[z];
+  }
+  __syncthreads();
+}
+
+// The spread stage in the plan's mode: boxes to staging (folded afterwards)
+// or clipped stencils straight into the grid.
+template <typename T, int P>
+__device__ __forceinline__ void stage_spread_mode(const GridGeom& g, const EvalBuffers& b, int item,
+                                                  unsigned char* smem) {
+  if (g.clip == 2) stage_spread_cols<T, P>(g, b, item, smem);
+  else if (g.clip) stage_spread_clip<T, P>(g, b, item, smem);
+  else stage_spread<T, P>(g, b, item, smem);
+}
+
 template <typename T, int P>
 __global__ __launch_bounds__(kBlock) void spread_kernel(GridGeom g, EvalBuffers b) {
   extern __shared__ __align__(16) unsigned char smem[];
-  stage_spread<T, P>(g, b, work_item(g.xcd), smem);
+  stage_spread_mode<T, P>(g, b, work_item(g.xcd), smem);
 }
 
 // For one direction: the tile at offset d from tile t (wrapped in periodic
@@ -1105,9 +1494,15 @@ __device__ __forceinline__ void stage_fold(const GridGeom& g, const EvalBuffers&
   const int nz = fold_images(g, 2, tz, z0, ez, tlz, olz);
   const T* stg = reinterpret_cast<const T*>(b.stage);
   T* grid = reinterpret_cast<T*>(b.grid);
-  const int n = ex * ey * ez;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int x = x0 + e % ex, y = y0 + (e / ex) % ey, z = z0 + e / (ex * ey);
+  // rows of the tile, 64 / TX rows per wavefront at a time
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64, nwaves = blockDim.x / 64;
+  const int rpw = 64 / g.T[0], sub = lane / g.T[0], lxo = lane - sub * g.T[0];
+  const int nrows = ey * ez;
+  if (sub >= rpw || lxo >= ex) return;
+  for (int r0 = wave * rpw; r0 < nrows; r0 += nwaves * rpw) {
+    const int row = r0 + sub;
+    if (row >= nrows) break;
+    const int x = x0 + lxo, y = y0 + row % ey, z = z0 + row / ey;
     T sum = 0;
     for (int kz = 0; kz < nz; ++kz) {
       const int bz = z - olz[kz];
@@ -1135,9 +1530,16 @@ __global__ __launch_bounds__(kBlock) void fold_kernel(GridGeom g, EvalBuffers b)
 template <typename T>
 size_t spread_lds(const GridGeom& g) {
   const int P = g.P, nw = kBlock / 64;
+  if (g.clip == 2)
+    return sizeof(int) * (3 * kMaxClipRanges + 4 + kColBatch) + sizeof(T) * ((size_t)kColBatch * 3 * P) + 64;
+  if (g.clip) {
+    const size_t T3 = (size_t)g.T[0] * g.T[1] * g.T[2];
+    return 8 * T3 + sizeof(T) * ((size_t)nw * g.chunk * (3 * P + 4)) +
+           sizeof(int) * (3 * kMaxClipRanges + 4 + nw * g.chunk * 3 + 4) + 64;
+  }
   const size_t R3 = (size_t)(g.T[0] + P - 1) * (g.T[1] + P - 1) * (g.T[2] + P - 1);
-  return 8 * R3 + sizeof(T) * ((size_t)nw * g.chunk * 3 * P) +
-         sizeof(int) * (2 * kMaxOwnRanges + 4 + nw * g.chunk * 3) + 64;
+  return 8 * R3 + sizeof(T) * ((size_t)nw * g.chunk * (3 * P + 4)) +
+         sizeof(int) * (2 * kMaxOwnRanges + 4 + nw * g.chunk * 3 + 4) + 64;
 }
 
 template <typename T, int P>
@@ -1209,6 +1611,9 @@ __device__ __forceinline__ void stage_gather(const GridGeom& g, const EvalBuffer
   int* rstart = reinterpret_cast<int*>(reg + RX * RY * RZ);   // kMaxOwnRanges
   int* rpre = rstart + kMaxOwnRanges;                         // kMaxOwnRanges + 1
   T* wsh = reinterpret_cast<T*>(rpre + kMaxOwnRanges + 4);    // nwaves * PPW * 4P
+  Quad<T>* rq = reinterpret_cast<Quad<T>*>(wsh + nwaves * PPW * 4 * P);   // kGatherBatch records
+  int* rc = reinterpret_cast<int*>(rq + kGatherBatch);        // kGatherBatch cells
+  int* ri = rc + kGatherBatch;                                // kGatherBatch input indices
   __shared__ double ewave[kBlock / 64];
 
   // particles anchored in this tile: sub-bins of the tile
@@ -1221,17 +1626,52 @@ __device__ __forceinline__ void stage_gather(const GridGeom& g, const EvalBuffer
     return;
   }
 
-  // stage the stencil region [x0 - P/2 + 1, x0 + TX + P/2 - 1] of the grid
+  // particle records of a batch, one per thread in one round of loads
+  const Quad<T>* sfq = reinterpret_cast<const Quad<T>*>(b.s_fq);
+  auto load_batch = [&](int b0) {
+    const int nb = min(kGatherBatch, total - b0);
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+      const int e = b0 + k;
+      const int r = find_range(rpre, nr, e);
+      const int i = rstart[r] + (e - rpre[r]);
+      rq[k] = sfq[i];
+      rc[k] = b.s_cell[i];
+      ri[k] = b.s_idx[i];
+    }
+  };
+  load_batch(0);   // in flight together with the region below
+
+  // stage the stencil region [x0 - P/2 + 1, x0 + TX + P/2 - 1] of the grid:
+  // each wavefront copies whole rows, 64 / RX rows at a time, and each lane
+  // keeps its x offset (wrapped once) for all rows
   const T* grid = reinterpret_cast<const T*>(b.grid);
   const int rx = x0 - P / 2 + 1, ry = y0 - P / 2 + 1, rz = z0 - P / 2 + 1;
-  for (int e = threadIdx.x; e < RX * RY * RZ; e += blockDim.x) {
-    const int px = e % RX, py = (e / RX) % RY, pz = e / (RX * RY);
-    int gx = rx + px, gy = ry + py, gz = rz + pz;
-    bool ok = true;
-    if (g.per[0]) { gx %= g.G[0]; if (gx < 0) gx += g.G[0]; } else ok = ok && gx >= 0 && gx < g.G[0];
-    if (g.per[1]) { gy %= g.G[1]; if (gy < 0) gy += g.G[1]; } else ok = ok && gy >= 0 && gy < g.G[1];
-    if (g.per[2]) { gz %= g.G[2]; if (gz < 0) gz += g.G[2]; } else ok = ok && gz >= 0 && gz < g.G[2];
-    reg[e] = ok ? grid[((long long)gz * g.G[1] + gy) * g.G[0] + gx] : (T)0;
+  {
+    constexpr int U = 8;  // rows in flight per lane
+    const int rpw = 64 / RX, sub = lane / RX, px = lane - sub * RX;
+    bool okx = sub < rpw;
+    const int gx = wrap_coord(g, 0, rx + px, &okx);
+    const int nrows = RY * RZ, step = nwaves * rpw;
+    if (sub < rpw)
+      for (int r0 = wave * rpw + sub; r0 < nrows; r0 += U * step) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int row = r0 + u * step;
+          v[u] = (T)0;
+          if (row < nrows) {
+            const int py = row % RY, pz = row / RY;
+            bool ok = okx;
+            const int gy = wrap_coord(g, 1, ry + py, &ok), gz = wrap_coord(g, 2, rz + pz, &ok);
+            if (ok) v[u] = grid[((long long)gz * g.G[1] + gy) * g.G[0] + gx];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int row = r0 + u * step;
+          if (row < nrows) reg[row * RX + px] = v[u];
+        }
+      }
   }
 
   const int p = lane / G2, iz = lane % G2;
@@ -1245,89 +1685,79 @@ __device__ __forceinline__ void stage_gather(const GridGeom& g, const EvalBuffer
   __syncthreads();
 
   T* wp = wsh + (wave * PPW + p) * 4 * P;    // wx | dwx | wy | dwy of this lane's particle
-  const Quad<T>* sfq = reinterpret_cast<const Quad<T>*>(b.s_fq);
   const T sc = (T)g.scale;
   double eacc = 0.0;
-  // software pipeline: the sorted index, cell and record of the next particle
-  // are loaded one round ahead
-  int e = wave * PPW + p;
-  int i_n = 0, pc_n = 0;
-  Quad<T> f_n = {0, 0, 0, 0};
-  if (e < total) {
-    const int r = find_range(rpre, nr, e);
-    i_n = rstart[r] + (e - rpre[r]);
-    pc_n = b.s_cell[i_n];
-    f_n = sfq[i_n];
-  }
-  for (int base = wave * PPW; base < total; base += nwaves * PPW) {
-    const bool valid = e < total;
-    const int i = i_n, pc = pc_n;
-    const Quad<T> f = f_n;
-    e += nwaves * PPW;
-    if (e < total) {
-      const int r = find_range(rpre, nr, e);
-      i_n = rstart[r] + (e - rpre[r]);
-      pc_n = b.s_cell[i_n];
-      f_n = sfq[i_n];
+  for (int b0 = 0; b0 < total; b0 += kGatherBatch) {
+    if (b0 > 0) {
+      __syncthreads();
+      load_batch(b0);
+      __syncthreads();
     }
-    const int lx = (pc & 1023) - x0, ly = ((pc >> 10) & 1023) - y0, lz = ((pc >> 20) & 1023) - z0;
-    T wz = 0, dwz = 0;
-    if (valid && iz < P) {
-      wp[iz] = weight_reg<T, P>(g, crow, iz, f.fx);
-      wp[P + iz] = dweight_reg<T, P>(g, drow, iz, f.fx);
-      wp[2 * P + iz] = weight_reg<T, P>(g, crow, iz, f.fy);
-      wp[3 * P + iz] = dweight_reg<T, P>(g, drow, iz, f.fy);
-      wz = weight_reg<T, P>(g, crow, iz, f.fz);
-      dwz = dweight_reg<T, P>(g, drow, iz, f.fz);
-    }
-    wave_sync();
-    T ph = 0, gx = 0, gy = 0, gz = 0;
-    if (valid && iz < P) {
-      T wx[P], dwx[P];
-#pragma unroll
-      for (int k = 0; k < P; ++k) {
-        wx[k] = wp[k];
-        dwx[k] = wp[P + k];
+    const int nb = min(kGatherBatch, total - b0);
+    for (int base = wave * PPW; base < nb; base += nwaves * PPW) {
+      const int k = base + p;
+      const bool valid = k < nb;
+      const Quad<T> f = valid ? rq[k] : Quad<T>{0, 0, 0, 0};
+      const int pc = valid ? rc[k] : 0;
+      const int lx = (pc & 1023) - x0, ly = ((pc >> 10) & 1023) - y0, lz = ((pc >> 20) & 1023) - z0;
+      T wz = 0, dwz = 0;
+      if (valid && iz < P) {
+        wp[iz] = weight_reg<T, P>(g, crow, iz, f.fx);
+        wp[P + iz] = dweight_reg<T, P>(g, drow, iz, f.fx);
+        wp[2 * P + iz] = weight_reg<T, P>(g, crow, iz, f.fy);
+        wp[3 * P + iz] = dweight_reg<T, P>(g, drow, iz, f.fy);
+        wz = weight_reg<T, P>(g, crow, iz, f.fz);
+        dwz = dweight_reg<T, P>(g, drow, iz, f.fz);
       }
-      T s00 = 0, s01 = 0, s10 = 0;
-      const T* plane = reg + (long long)(lz + iz) * RX * RY + (long long)ly * RX + lx;
+      wave_sync();
+      T ph = 0, gx = 0, gy = 0, gz = 0;
+      if (valid && iz < P) {
+        T wx[P], dwx[P];
 #pragma unroll
-      for (int iy = 0; iy < P; ++iy) {
-        const T* row = plane + iy * RX;
-        T r0 = 0, r1 = 0;
-#pragma unroll
-        for (int ix = 0; ix < P; ++ix) {
-          const T v = row[ix];
-          r0 += wx[ix] * v;
-          r1 += dwx[ix] * v;
+        for (int q = 0; q < P; ++q) {
+          wx[q] = wp[q];
+          dwx[q] = wp[P + q];
         }
-        const T wy = wp[2 * P + iy], dwy = wp[3 * P + iy];
-        s00 += wy * r0;
-        s01 += dwy * r0;
-        s10 += wy * r1;
+        T s00 = 0, s01 = 0, s10 = 0;
+        const T* plane = reg + (long long)(lz + iz) * RX * RY + (long long)ly * RX + lx;
+#pragma unroll
+        for (int iy = 0; iy < P; ++iy) {
+          const T* row = plane + iy * RX;
+          T r0 = 0, r1 = 0;
+#pragma unroll
+          for (int ix = 0; ix < P; ++ix) {
+            const T v = row[ix];
+            r0 += wx[ix] * v;
+            r1 += dwx[ix] * v;
+          }
+          const T wy = wp[2 * P + iy], dwy = wp[3 * P + iy];
+          s00 += wy * r0;
+          s01 += dwy * r0;
+          s10 += wy * r1;
+        }
+        ph = wz * s00;
+        gx = wz * s10;
+        gy = wz * s01;
+        gz = dwz * s00;
       }
-      ph = wz * s00;
-      gx = wz * s10;
-      gy = wz * s01;
-      gz = dwz * s00;
-    }
-    ph = group_sum<G2>(ph);
-    gx = group_sum<G2>(gx);
-    gy = group_sum<G2>(gy);
-    gz = group_sum<G2>(gz);
-    if (valid && iz == 0) {
-      const int idx = b.s_idx[i];
-      const T pv = sc * ph + (T)(self_coef * (double)f.q);
-      if (phi) phi[idx] = pv;
-      if (force) {
-        const T f0 = out_grad ? (T)1 : -f.q;
-        force[3 * idx] = f0 * sc * gx;
-        force[3 * idx + 1] = f0 * sc * gy;
-        force[3 * idx + 2] = f0 * sc * gz;
+      ph = group_sum<G2>(ph);
+      gx = group_sum<G2>(gx);
+      gy = group_sum<G2>(gy);
+      gz = group_sum<G2>(gz);
+      if (valid && iz == 0) {
+        const int idx = ri[k];
+        const T pv = sc * ph + (T)(self_coef * (double)f.q);
+        if (phi) phi[idx] = pv;
+        if (force) {
+          const T f0 = out_grad ? (T)1 : -f.q;
+          force[3 * idx] = f0 * sc * gx;
+          force[3 * idx + 1] = f0 * sc * gy;
+          force[3 * idx + 2] = f0 * sc * gz;
+        }
+        eacc += (double)f.q * (double)pv;
       }
-      eacc += (double)f.q * (double)pv;
+      wave_sync();
     }
-    wave_sync();
   }
   eacc = warp_sum(eacc);
   if (lane == 0) ewave[wave] = eacc;
@@ -1354,7 +1784,8 @@ size_t gather_lds(const GridGeom& g) {
   const int G2 = P <= 2 ? 2 : (P <= 4 ? 4 : (P <= 8 ? 8 : 16));
   const size_t R = (size_t)(g.T[0] + P - 1) * (g.T[1] + P - 1) * (g.T[2] + P - 1);
   (void)m;
-  return sizeof(T) * (R + (size_t)nw * (64 / G2) * 4 * P) + sizeof(int) * (2 * kMaxOwnRanges + 4) + 64;
+  return sizeof(T) * (R + (size_t)nw * (64 / G2) * 4 * P + 4 * kGatherBatch) +
+         sizeof(int) * (2 * kMaxOwnRanges + 4 + 2 * kGatherBatch) + 64;
 }
 
 template <typename T, int P>
@@ -1460,8 +1891,11 @@ __device__ __forceinline__ void run_batch_stage(int st, const SysDesc& S, int sy
     case BS_SCATTER:
       stage_scatter<T>(S.b, S.N, li);
       break;
+    case BS_ORDER:
+      stage_order<T>(S.b, S.g.nsb[0] * S.g.nsb[1] * S.g.nsb[2], li);
+      break;
     case BS_SPREAD:
-      stage_spread<T, P>(S.g, S.b, li, smem);
+      stage_spread_mode<T, P>(S.g, S.b, li, smem);
       break;
     case BS_FOLD:
       stage_fold<T>(S.g, S.b, li);
@@ -1556,6 +1990,7 @@ static void batch_launch_t(const SysDesc* sys, int nsys, const int* off, const i
   batch_launch_one<T, P, BS_SCAN1>(sys, nsys, off, items, io, lds, st, ev);
   batch_launch_one<T, P, BS_SCAN2>(sys, nsys, off, items, io, lds, st, ev);
   batch_launch_one<T, P, BS_SCATTER>(sys, nsys, off, items, io, lds, st, ev);
+  batch_launch_one<T, P, BS_ORDER>(sys, nsys, off, items, io, lds, st, ev);
   batch_launch_one<T, P, BS_SPREAD>(sys, nsys, off, items, io, lds, st, ev);
   batch_launch_one<T, P, BS_FOLD>(sys, nsys, off, items, io, lds, st, ev);
   batch_launch_one<T, P, BS_FFT0>(sys, nsys, off, items, io, lds, st, ev);

@@ -253,6 +253,8 @@ se::FftClass make_class(int n, int n_in, int n_out, const void* in, void* out,
   c.n_in = n_in;
   c.n_out = n_out;
   radix_plan(n, c.rad, &c.nst);
+  c.radpack = 0;
+  for (int k = 0; k < c.nst; ++k) c.radpack |= (unsigned long long)c.rad[k] << (4 * k);
   c.in = in;
   c.out = out;
   c.in_st = in_st;
@@ -449,6 +451,39 @@ static int fold_image_count(const se::GridGeom& g, int d) {
   return most;
 }
 
+// Clipped spreading: anchor pieces of one direction over all tiles (as the
+// kernel forms them); returns the largest sub-bin count (sub-bins summed over
+// pieces, or pieces when 'pieces_only'), or a value above every limit when a
+// tile needs more than kMaxPieces pieces.
+static int clip_dim_max(const se::GridGeom& g, int d, bool pieces_only) {
+  const int T = g.T[d], G = g.G[d], nt = g.nt[d], h = g.P / 2;
+  int most = 0;
+  for (int t = 0; t < nt; ++t) {
+    const int o = t * T, e = std::min(T, G - o);
+    int lo = o - h, hi = o + e - 1 + h - 1, cnt = 0, np = 0;
+    if (!g.per[d]) {
+      lo = std::max(lo, 0);
+      hi = std::min(hi, G - 1);
+      if (lo <= hi) cnt = hi / se::kSB - lo / se::kSB + 1, np = 1;
+    } else {
+      auto fdiv = [](int a, int b) { return a >= 0 ? a / b : -((b - 1 - a) / b); };
+      for (int k = fdiv(lo, G); k <= fdiv(hi, G); ++k) {
+        const int a = std::max(lo - k * G, 0), b = std::min(hi - k * G, G - 1);
+        if (a > b) continue;
+        cnt += b / se::kSB - a / se::kSB + 1;
+        ++np;
+      }
+    }
+    if (np > se::kMaxPieces) return 1 << 28;
+    most = std::max(most, pieces_only ? np : cnt);
+  }
+  return most;
+}
+
+static long clip_ranges_max(const se::GridGeom& g) {
+  return (long)clip_dim_max(g, 2, false) * clip_dim_max(g, 1, false) * clip_dim_max(g, 0, true);
+}
+
 static se_status plan_create(const se_params* params, long n_max, void* hip_stream, size_t lds_soft,
                              long min_tiles, se_plan** out);
 
@@ -503,6 +538,10 @@ static se_status plan_create(const se_params* params, long n_max, void* hip_stre
   pl->n_max = n_max;
   (void)hipGetDevice(&pl->device);
   pl->lds_limit = lds_soft;
+  if (p.spread_mode < 0 || p.spread_mode > 3) {
+    delete pl;
+    return SE_ERR_PARAM;
+  }
   if (p.fft_cap > 0) {
     if (p.fft_cap < 1024 || p.fft_cap > se::kFftCap || (p.fft_cap & (p.fft_cap - 1))) {
       delete pl;
@@ -556,6 +595,14 @@ static se_status plan_create(const se_params* params, long n_max, void* hip_stre
   g.alpha = p.shape;
   g.scale = 4.0 * kPi * I.h * I.h * I.h;
   g.xcd = xcd_mode(p.xcd_tiles);
+  // spreading mode: clipped stencils straight into the grid for sparse grids
+  // (fewer than 0.1 particles per grid point), boxes and fold otherwise
+  {
+    const double npts = (double)I.grid[0] * I.grid[1] * I.grid[2];
+    const bool sparse = (double)std::max(1L, n_max) < 0.1 * npts;
+    const int mode = p.spread_mode > 0 ? p.spread_mode : (sparse ? 3 : 1);
+    g.clip = mode - 1;
+  }
   {
     // Largest tile whose spread and gather LDS fit, with at least min_tiles
     // tiles when the grid allows it.
@@ -577,6 +624,14 @@ static se_status plan_create(const se_params* params, long n_max, void* hip_stre
         } else {
           if (p.tile > 0 && !(cands[c][0] == p.tile && cands[c][1] == p.tile && cands[c][2] == p.tile)) continue;
           for (int d = 0; d < 3; ++d) g.T[d] = cands[c][d];
+        }
+        // column spreading: one thread per (x, y) column, at most kColZ points each
+        if (g.clip == 2 && (g.T[0] * g.T[1] > se::kBlock || g.T[2] > se::kColZ)) {
+          if (explicit3 || p.tile > 0) {
+            delete pl;
+            return SE_ERR_PARAM;
+          }
+          continue;
         }
         int fit = 0;
         for (int ch : {64, 32, 16}) {
@@ -609,11 +664,24 @@ static se_status plan_create(const se_params* params, long n_max, void* hip_stre
     g.nsb[d] = (g.G[d] + se::kSB - 1) / se::kSB;
   }
   pl->ntiles = g.nt[0] * g.nt[1] * g.nt[2];
-  for (int d = 0; d < 3; ++d)
-    if (fold_image_count(g, d) > se::kMaxFoldImages) {
+  if (g.clip && clip_ranges_max(g) > se::kMaxClipRanges) {
+    if (p.spread_mode >= 2) {
       delete pl;
       return SE_ERR_UNSUPPORTED;
     }
+    g.clip = 0;  // the automatic choice falls back to boxes and fold
+    if (se::spread_lds_bytes(g, pl->f64) > pl->lds_max) {
+      delete pl;
+      return SE_ERR_UNSUPPORTED;
+    }
+  }
+  I.spread_mode = g.clip + 1;
+  if (!g.clip)
+    for (int d = 0; d < 3; ++d)
+      if (fold_image_count(g, d) > se::kMaxFoldImages) {
+        delete pl;
+        return SE_ERR_UNSUPPORTED;
+      }
   pl->nsbtot = g.nsb[0] * g.nsb[1] * g.nsb[2];
 
   hipStream_t st = (hipStream_t)hip_stream;
@@ -655,14 +723,16 @@ static se_status plan_create(const se_params* params, long n_max, void* hip_stre
     b.s_cell = (int*)pl->dalloc(sizeof(int) * nm);
     b.s_idx = (int*)pl->dalloc(sizeof(int) * nm);
     b.s_fq = pl->dalloc(4 * esz * nm);
-    b.qpart = (double*)pl->dalloc(sizeof(double) * 3 * nblk);
+    b.qpart = (double*)pl->dalloc(sizeof(double) * 4 * nblk);
     b.bsum = (int*)pl->dalloc(sizeof(int) * se::scan_blocks(g));
-    b.stage = pl->dalloc(esz * (size_t)pl->ntiles * (g.T[0] + p.P - 1) * (g.T[1] + p.P - 1) * (g.T[2] + p.P - 1));
+    b.stage = g.clip ? nullptr
+                     : pl->dalloc(esz * (size_t)pl->ntiles * (g.T[0] + p.P - 1) * (g.T[1] + p.P - 1) *
+                                  (g.T[2] + p.P - 1));
     b.epart = (double*)pl->dalloc(sizeof(double) * pl->ntiles);
     b.red = (double*)pl->dalloc(sizeof(double) * 4);
     b.status = (int*)pl->dalloc(sizeof(int));
     b.grid = pl->dalloc(esz * (size_t)g.G[0] * g.G[1] * g.G[2]);
-    if (!b.sb_count || !b.sb_start || !b.sb_cursor || !b.p_key || !b.p_cell || !b.p_frac || !b.bsum || !b.stage ||
+    if (!b.sb_count || !b.sb_start || !b.sb_cursor || !b.p_key || !b.p_cell || !b.p_frac || !b.bsum || (!b.stage && !g.clip) ||
         !b.s_cell || !b.s_idx || !b.s_fq || !b.qpart || !b.epart || !b.red || !b.status || !b.grid) {
       rc = SE_ERR_NOMEM;
       break;
@@ -1047,13 +1117,14 @@ se_status se_eval(se_plan* plan, long N, const void* xyz, const void* q, void* p
   end(1, plan->nsbtot * 12.0, 0.0);
   begin();
   if (se::launch_scatter(g, b, N, f64, st) != hipSuccess) return SE_ERR_DEVICE;
+  if (g.clip == 2 && se::launch_order(g, b, plan->nsbtot, f64, st) != hipSuccess) return SE_ERR_DEVICE;
   end(2, N * 2.0 * (8.0 + 4.0 * re), 0.0);
   begin();
   if (se::launch_spread(g, b, f64, st) != hipSuccess) return SE_ERR_DEVICE;
   end(3, N * 4.0 * re + G * re, N * 2.0 * (3.0 * P * nu + P * P + (double)P * P * P));
-  begin();
-  if (se::launch_fold(g, b, f64, st) != hipSuccess) return SE_ERR_DEVICE;
-  {
+  if (!g.clip) {
+    begin();
+    if (se::launch_fold(g, b, f64, st) != hipSuccess) return SE_ERR_DEVICE;
     const double R3 = (double)(g.T[0] + P - 1) * (g.T[1] + P - 1) * (g.T[2] + P - 1);
     end(4, plan->ntiles * R3 * re + G * re, plan->ntiles * R3);
   }
@@ -1188,7 +1259,7 @@ struct se_batch_plan {
 };
 
 static const char* const kBatchStageNames[se::BS_COUNT] = {
-    "zero", "bin", "scan1", "scan2", "scatter", "spread", "fold",
+    "zero", "bin", "scan1", "scan2", "scatter", "order", "spread", "fold",
     "fft0", "fft1", "fft2", "fft3", "fft4", "gather", "energy"};
 
 extern "C" {
@@ -1240,7 +1311,9 @@ se_status se_batch_plan_create(const se_params* params, const long* N, int n_sys
     bp->N.push_back(N[s]);
     bp->off.push_back(run);
     run += N[s];
-    const int items[se::BS_COUNT] = {d.nscan, d.nblk_bin, d.nscan, d.nscan, d.nblk_bin, d.ntiles, d.ntiles,
+    const int n_order = d.g.clip == 2 ? (sp->nsbtot + se::kBlock - 1) / se::kBlock : 0;
+    const int items[se::BS_COUNT] = {d.nscan, d.nblk_bin, d.nscan, d.nscan, d.nblk_bin, n_order, d.ntiles,
+                                     d.g.clip ? 0 : d.ntiles,
                                      d.pass[0].nitems, d.pass[1].nitems, d.pass[2].nitems, d.pass[3].nitems,
                                      d.pass[4].nitems, d.ntiles, 1};
     for (int k = 0; k < se::BS_COUNT; ++k) off[(size_t)k * (n_sys + 1) + s + 1] = items[k];
@@ -1264,10 +1337,13 @@ se_status se_batch_plan_create(const se_params* params, const long* N, int n_sys
     by[se::BS_SCAN1] += sp->nsbtot * 8.0;
     by[se::BS_SCAN2] += sp->nsbtot * 8.0;
     by[se::BS_SCATTER] += n * 2.0 * (8.0 + 4.0 * re);
-    by[se::BS_SPREAD] += n * 4.0 * re + d.ntiles * R3 * re;
+    if (n_order) by[se::BS_ORDER] += n * 2.0 * (8.0 + 4.0 * re);
+    by[se::BS_SPREAD] += n * 4.0 * re + G * re;
     fl[se::BS_SPREAD] += n * 2.0 * (3.0 * P * nu + P * P + (double)P * P * P);
-    by[se::BS_FOLD] += d.ntiles * R3 * re + G * re;
-    fl[se::BS_FOLD] += d.ntiles * R3;
+    if (!d.g.clip) {
+      by[se::BS_FOLD] += d.ntiles * R3 * re + G * re;
+      fl[se::BS_FOLD] += d.ntiles * R3;
+    }
     for (int k = 0; k < se::kPasses; ++k) {
       by[se::BS_FFT0 + k] += d.pass[k].alg_bytes;
       fl[se::BS_FFT0 + k] += d.pass[k].alg_flops;
@@ -1426,7 +1502,8 @@ void classify(const se_stage_record* r, int n, TuneTimes* t) {
     if (!std::strcmp(r[i].name, "batch_all_stages") || r[i].launches == 0) continue;
     const double ms = r[i].ms_total / r[i].launches;
     t->all += ms;
-    if (!std::strcmp(r[i].name, "spread") || !std::strcmp(r[i].name, "fold") || !std::strcmp(r[i].name, "gather"))
+    if (!std::strcmp(r[i].name, "spread") || !std::strcmp(r[i].name, "fold") || !std::strcmp(r[i].name, "gather") ||
+        !std::strcmp(r[i].name, "order") || !std::strcmp(r[i].name, "scatter"))
       t->tiles += ms;
     else if (!std::strncmp(r[i].name, "fft", 3))
       t->fft += ms;
@@ -1498,21 +1575,23 @@ bool tune_knobs(se_params* base, int n_par, bool tune_xcd, Timer timer, se_tune_
   std::vector<se_params> cur(base, base + n_par);
   if (!timer(cur, &t0)) return false;
   int cand = 1;
-  // tile shape (with the current XCD setting)
+  // spreading mode and tile shape (with the current XCD setting)
   double best = t0.tiles;
-  for (const auto& T : kTuneTiles) {
-    auto v = with([&](se_params& p) {
-      p.tile = 0;
-      for (int d = 0; d < 3; ++d) p.tile3[d] = T[d];
-    });
-    TuneTimes t;
-    if (!timer(v, &t)) continue;
-    ++cand;
-    if (t.tiles < best) {
-      best = t.tiles;
-      cur = v;
+  for (int mode : {1, 2, 3})
+    for (const auto& T : kTuneTiles) {
+      auto v = with([&](se_params& p) {
+        p.tile = 0;
+        p.spread_mode = mode;
+        for (int d = 0; d < 3; ++d) p.tile3[d] = T[d];
+      });
+      TuneTimes t;
+      if (!timer(v, &t)) continue;
+      ++cand;
+      if (t.tiles < best) {
+        best = t.tiles;
+        cur = v;
+      }
     }
-  }
   if (tune_xcd) {
     const auto base_v = cur;
     for (int mode : kTuneXcd) {

@@ -97,6 +97,7 @@ def _stored_schedule(params):
         for d in range(3):
             p.tile3[d] = r["tile3"][d]
         p.fft_cap, p.xcd_tiles, p.xcd_fft = r["fft_cap"], r["xcd_tiles"], r["xcd_fft"]
+        p.spread_mode = r.get("spread_mode", 0)
 
 
 def test_c5_batch_full_size_matches_discrete_oracle():

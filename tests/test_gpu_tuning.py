@@ -53,13 +53,20 @@ def _oracle(key, x, q, p):
 
 @pytest.mark.parametrize("D", [3, 2, 1, 0])
 @pytest.mark.parametrize("tile", TILES)
-def test_every_tile_shape_matches_oracle(D, tile):
+@pytest.mark.parametrize("mode", [1, 2, 3])
+def test_every_tile_shape_matches_oracle(D, tile, mode):
     """M = 36 is a multiple of no tile edge above 4, so every shape has short
-    last tiles in the periodic directions."""
-    print(f"case tile D={D} tile={tile}", flush=True)
+    last tiles in the periodic directions; all spreading modes (the column
+    mode takes tiles with x*y <= 256 and z <= 16 only)."""
+    print(f"case tile D={D} tile={tile} spread mode {mode}", flush=True)
     x, q = wl.system(600, 1.0, 40 + D, "uniform")
-    plan, p = _plan(D, 36, 600, {"tile3": tile, "tile": 0})
-    assert tuple(plan.info.tile) == tile
+    if mode == 3 and (tile[0] * tile[1] > 256 or tile[2] > 16):
+        with pytest.raises(_lib.SEError) as e:
+            _plan(D, 36, 600, {"tile3": tile, "tile": 0, "spread_mode": mode})
+        assert e.value.status == _lib.SE_ERR_PARAM
+        return
+    plan, p = _plan(D, 36, 600, {"tile3": tile, "tile": 0, "spread_mode": mode})
+    assert tuple(plan.info.tile) == tile and plan.info.spread_mode == mode
     phi, g = _eval(plan, x, q)
     ref, gref = _oracle(("tile", D), x, q, p)
     assert rel(phi, ref) < 1e-12 and rel(g, gref) < 1e-11
@@ -105,7 +112,9 @@ def test_autotuned_plan_computes_the_same(D):
     assert rep["candidates"] >= 2 and rep["ms_tuned"] <= rep["ms_default"] * 1.0001
     phi0, g0 = _eval(base, x, q)
     phi1, g1 = _eval(tuned, x, q)
-    assert rel(phi1, phi0) < 1e-13 and rel(g1, g0) < 1e-12
+    # the tile shape sets the per-tile fixed-point scale of the spreading, so
+    # the two plans round differently: the FP64 bar of the oracle comparison
+    assert rel(phi1, phi0) < 1e-12 and rel(g1, g0) < 1e-11
 
 
 def test_batch_autotune_computes_the_same():
@@ -133,3 +142,28 @@ def test_batch_autotune_computes_the_same():
     # FP32: the tile shape changes the per-tile fixed-point scale and the FFT
     # workgroup size nothing; differences are FP32 rounding
     assert rel(r1[0], r0[0]) < 2e-6 and rel(r1[1], r0[1]) < 5e-6
+
+
+@pytest.mark.parametrize("mode", [2, 3])
+@pytest.mark.parametrize("D,M,P,tile", [(3, 10, 8, (16, 16, 16)), (2, 12, 10, (32, 8, 8)), (1, 14, 12, (8, 8, 8)),
+                                        (3, 16, 16, (4, 4, 4)), (0, 12, 6, (16, 16, 8))])
+def test_clipped_spread_small_periodic_grids(D, M, P, tile, mode):
+    """Clipped spreading where a stencil wraps onto the same tile more than
+    once (tiles wider than the periodic grid, supports close to M)."""
+    print(f"case clip mode {mode} D={D} M={M} P={P} tile={tile}", flush=True)
+    x, q = wl.system(300, 1.0, 90 + D, "uniform")
+    kw = {"s": 2.0, "n_l": 2} if D in (1, 2) else {}
+    base = SpectralEwald(D, 1.0, 4.0, M, P, prec="f64", n_max=300, **kw)
+    p = base.params
+    for d in range(3):
+        p.tile3[d] = tile[d]
+    p.tile, p.spread_mode = 0, mode
+    plan = SpectralEwald.from_params(p, 300)
+    assert plan.info.spread_mode == mode
+    phi, g = _eval(plan, x, q)
+    ref, gref = se.spectral_ewald(x, q, se.Params(D=D, L=1.0, xi=4.0, M=M, P=P, window="pkb", **kw))
+    # the fixed-point quantum is 2^-50 times the sum of |q| over every stencil
+    # visit of the tile; here each particle visits the one tile once per
+    # periodic image it wraps onto (up to 2^3 times), so the bar is 10x the
+    # single-visit FP64 bar
+    assert rel(phi, ref) < 1e-11 and rel(g, gref) < 1e-10

@@ -58,6 +58,39 @@ struct Quad {
   T fx, fy, fz, q;
 };
 
+// Pointers held in descriptors are generic (they could address LDS), so
+// loads through them are flat vector loads.  Device buffers are global
+// memory: these casts let the compiler use global (and, for uniform
+// addresses, scalar) loads and stores.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gld(const T* p) {
+  return (const __attribute__((address_space(1))) T*)(p);
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gst(T* p) {
+  return (__attribute__((address_space(1))) T*)(p);
+}
+
+// Complex values through global pointers, as two-component vectors.
+template <typename T>
+using vec2 = T __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ cx<T> ld_cx(const cx<T>* p, long long i) {
+  const vec2<T> v = gld(reinterpret_cast<const vec2<T>*>(p))[i];
+  return cx<T>{v.x, v.y};
+}
+template <typename T>
+__device__ __forceinline__ void st_cx(cx<T>* p, long long i, cx<T> v) {
+  gst(reinterpret_cast<vec2<T>*>(p))[i] = vec2<T>{v.re, v.im};
+}
+template <typename T>
+using vec4 = T __attribute__((ext_vector_type(4)));
+template <typename T>
+__device__ __forceinline__ Quad<T> ld_quad(const void* p, long long i) {
+  const vec4<T> v = gld(reinterpret_cast<const vec4<T>*>(p))[i];
+  return Quad<T>{v.x, v.y, v.z, v.w};
+}
+
 // ---------------------------------------------------------------------------
 // Small DFTs, X_m = sum_r v_r exp(sign 2 pi i r m / R)
 // ---------------------------------------------------------------------------
@@ -290,11 +323,11 @@ struct ScaleRow {
 template <typename T>
 __device__ __forceinline__ ScaleRow<T> scale_row(const FftClass& C, int b0, int b1) {
   ScaleRow<T> r;
-  r.s = ((const T*)C.sA)[b0 + C.offA] * ((const T*)C.sB)[b1 + C.offB];
+  r.s = gld((const T*)C.sA)[b0 + C.offA] * gld((const T*)C.sB)[b1 + C.offB];
   r.k2 = 0;
   r.g = 0;
   const int i0 = C.fold0 ? fold_index(b0, C.fold0) : b0;
-  if (C.gmode == G_INVSQ) r.k2 = ((const T*)C.kA)[b0 + C.offA] + ((const T*)C.kB)[b1 + C.offB];
+  if (C.gmode == G_INVSQ) r.k2 = gld((const T*)C.kA)[b0 + C.offA] + gld((const T*)C.kB)[b1 + C.offB];
   else if (C.gmode == G_TAB2) r.g = i0;
   else if (C.gmode == G_TAB3) r.g = (long long)fold_index(b1, C.fold1) * C.gd0 + i0;
   return r;
@@ -304,11 +337,11 @@ __device__ __forceinline__ ScaleRow<T> scale_row(const FftClass& C, int b0, int 
 // pencils) read neighbouring entries: G_TAB2 [t][b0], G_TAB3 [t][b1][b0].
 template <typename T>
 __device__ __forceinline__ T scale_at(const FftClass& C, const ScaleRow<T>& r, int t) {
-  const T s = r.s * ((const T*)C.sC)[t];
-  const T* gt = (const T*)C.gtab;
+  const T s = r.s * gld((const T*)C.sC)[t];
+  const auto gt = gld((const T*)C.gtab);
   switch (C.gmode) {
     case G_INVSQ: {
-      const T k2 = r.k2 + ((const T*)C.kC)[t];
+      const T k2 = r.k2 + gld((const T*)C.kC)[t];
       return k2 > (T)0 ? s / k2 : (T)0;
     }
     case G_TAB1:
@@ -349,9 +382,12 @@ template <typename T, int KIND>
 __device__ __forceinline__ void stage_fft(const FftPass& P, int item, unsigned char* smem) {
   constexpr int U = 8;  // global accesses in flight per thread
   constexpr bool REAL = (KIND == K_R2C || KIND == K_C2R);
-  const int4 it = P.items[item];
-  const FftClass& C = P.cls[it.x];
-  const int n = C.n, lgB = P.lgB, cnt = it.w, b0s = it.y, b1 = it.z;
+  // the work item {class, b0 start, b1, count}, the same for the whole workgroup
+  const auto itp = gld(reinterpret_cast<const int*>(P.items)) + 4 * item;
+  const int cls = __builtin_amdgcn_readfirstlane(itp[0]), b0s = __builtin_amdgcn_readfirstlane(itp[1]),
+            b1 = __builtin_amdgcn_readfirstlane(itp[2]), cnt = __builtin_amdgcn_readfirstlane(itp[3]);
+  const FftClass& C = P.cls[cls];
+  const int n = C.n, lgB = P.lgB;
   // real passes with B >= 2 run B/2 complex transforms of pencil pairs
   const int pair = (REAL && lgB > 0) ? 1 : 0;
   const int lgF = lgB - pair, Bp = (1 << lgF) + 1;
@@ -390,10 +426,10 @@ __device__ __forceinline__ void stage_fft(const FftPass& P, int item, unsigned c
         const int pa = c << pair;
         if (e < total && pa < cnt) {
           const cx<T>* in = reinterpret_cast<const cx<T>*>(C.in);
-          const cx<T> a = in[(long long)(b0s + pa) * C.in_s0 + bs1 + (long long)ts * C.in_st];
+          const cx<T> a = ld_cx(in, (long long)(b0s + pa) * C.in_s0 + bs1 + (long long)ts * C.in_st);
           v[u] = cx<T>{a.re, sg * a.im};
           if (pair && pa + 1 < cnt) {
-            const cx<T> bb = in[(long long)(b0s + pa + 1) * C.in_s0 + bs1 + (long long)ts * C.in_st];
+            const cx<T> bb = ld_cx(in, (long long)(b0s + pa + 1) * C.in_s0 + bs1 + (long long)ts * C.in_st);
             v[u].re -= sg * bb.im;
             v[u].im += bb.re;
           }
@@ -430,8 +466,8 @@ __device__ __forceinline__ void stage_fft(const FftPass& P, int item, unsigned c
         v[u] = cx<T>{0, 0};
         if (e < total && p < cnt && t < C.n_in) {
           const long long idx = (long long)(b0s + p) * C.in_s0 + bs1 + (long long)t * C.in_st;
-          if constexpr (KIND == K_R2C) v[u].re = reinterpret_cast<const T*>(C.in)[idx];
-          else v[u] = reinterpret_cast<const cx<T>*>(C.in)[idx];
+          if constexpr (KIND == K_R2C) v[u].re = gld(reinterpret_cast<const T*>(C.in))[idx];
+          else v[u] = ld_cx(reinterpret_cast<const cx<T>*>(C.in), idx);
         }
       }
       if (e0 == 0) make_twiddles();
@@ -490,7 +526,7 @@ __device__ __forceinline__ void stage_fft(const FftPass& P, int item, unsigned c
     const long long idx = (long long)(b0s + p) * C.out_s0 + os1 + (long long)t * C.out_st;
     if constexpr (KIND == K_C2R) {
       const cx<T> v = res[t * Bp + (p >> pair)];
-      reinterpret_cast<T*>(C.out)[idx] = (pair && (p & 1)) ? v.im : v.re;
+      gst(reinterpret_cast<T*>(C.out))[idx] = (pair && (p & 1)) ? v.im : v.re;
     } else if constexpr (KIND == K_R2C) {
       cx<T> v;
       if (pair) {
@@ -499,9 +535,9 @@ __device__ __forceinline__ void stage_fft(const FftPass& P, int item, unsigned c
       } else {
         v = res[t * Bp + p];
       }
-      reinterpret_cast<cx<T>*>(C.out)[idx] = v;
+      st_cx(reinterpret_cast<cx<T>*>(C.out), idx, v);
     } else {
-      reinterpret_cast<cx<T>*>(C.out)[idx] = res[t * Bp + p];
+      st_cx(reinterpret_cast<cx<T>*>(C.out), idx, res[t * Bp + p]);
     }
   }
 }
@@ -917,7 +953,8 @@ __device__ int build_ranges(const GridGeom& g, const EvalBuffers& b, const int* 
     const int xs = r % nsx, ry = (r / nsx) % ny, rz = r / (nsx * ny);
     const int bz = seg_at(sz, nsz, rz), by = seg_at(sy, nsy, ry);
     const int row = (bz * g.nsb[1] + by) * g.nsb[0];
-    const int a = b.sb_start[row + sx[2 * xs]], e = b.sb_start[row + sx[2 * xs + 1] + 1];
+    const auto sbs = gld(b.sb_start);
+    const int a = sbs[row + sx[2 * xs]], e = sbs[row + sx[2 * xs + 1] + 1];
     rstart[r] = a;
     rpre[r] = e - a;
   }
@@ -988,8 +1025,9 @@ struct Lanes {
 // Row i of the PKB coefficient table (values or derivatives) in registers.
 template <typename T>
 __device__ __forceinline__ void load_row(const T* __restrict__ tab, int i, int m, T* r) {
+  const auto t = gld(tab);
 #pragma unroll
-  for (int j = 0; j <= kMaxNu; ++j) r[j] = j < m ? tab[i * m + j] : (T)0;
+  for (int j = 0; j <= kMaxNu; ++j) r[j] = j < m ? t[i * m + j] : (T)0;
 }
 
 // Window weight of stencil row i at fractional offset f from a register row.
@@ -1048,11 +1086,10 @@ __device__ __forceinline__ void stage_spread(const GridGeom& g, const EvalBuffer
       sz[2] = {z0 / kSB, (z0 + ez - 1) / kSB};
   const int nr = (sz[1] - sz[0] + 1) * (sy[1] - sy[0] + 1);
   const int total = build_ranges(g, b, sz, 1, sy, 1, sx, 1, rstart, rpre);
-  const Quad<T>* sfq = reinterpret_cast<const Quad<T>*>(b.s_fq);
 
   // Fixed-point scale of this tile: |sum of q W| at any point is at most
   // (particles) x max |q| (W <= 1), kept below 2^50.
-  const double stile = (double)total * b.red[3];
+  const double stile = (double)total * gld(b.red)[3];
   const double scale = stile > 0.0 ? 1125899906842624.0 / (1.0009765625 * stile) : 0.0;   // 2^50
 
   // coefficient row of this lane (row k = lane % G2)
@@ -1071,8 +1108,8 @@ __device__ __forceinline__ void stage_spread(const GridGeom& g, const EvalBuffer
       const int e = base + lane;
       const int r = find_range(rpre, nr, e);
       const int i = rstart[r] + (e - rpre[r]);
-      wr[lane] = sfq[i];
-      const int pc = b.s_cell[i];
+      wr[lane] = ld_quad<T>(b.s_fq, i);
+      const int pc = gld(b.s_cell)[i];
       // stencil origin c - P/2 + 1 in box coordinates (box origin x0 - P/2 + 1)
       wo[3 * lane] = (pc & 1023) - x0;
       wo[3 * lane + 1] = ((pc >> 10) & 1023) - y0;
@@ -1111,7 +1148,7 @@ __device__ __forceinline__ void stage_spread(const GridGeom& g, const EvalBuffer
   __syncthreads();
   T* stg = reinterpret_cast<T*>(b.stage) + (long long)t_id * R3;
   const double inv = stile > 0.0 ? 1.0 / scale : 0.0;
-  for (int i = threadIdx.x; i < R3; i += blockDim.x) stg[i] = (T)((double)(long long)acc[i] * inv);
+  for (int i = threadIdx.x; i < R3; i += blockDim.x) gst(stg)[i] = (T)((double)(long long)acc[i] * inv);
   __syncthreads();
 }
 
@@ -1203,17 +1240,17 @@ __device__ __forceinline__ void stage_spread_clip(const GridGeom& g, const EvalB
     bz += pc_s0[2][kz];
     by += pc_s0[1][ky];
     const int row = (bz * g.nsb[1] + by) * g.nsb[0];
-    const int a = b.sb_start[row + pc_s0[0][xs]], e = b.sb_start[row + pc_s1[0][xs] + 1];
+    const auto sbs = gld(b.sb_start);
+    const int a = sbs[row + pc_s0[0][xs]], e = sbs[row + pc_s1[0][xs] + 1];
     rstart[r] = a;
     rpre[r] = e - a;
     rsh[r] = kz | (ky << 4) | (xs << 8);
   }
   __syncthreads();
   const int total = prefix_ranges(rpre, nr);
-  const Quad<T>* sfq = reinterpret_cast<const Quad<T>*>(b.s_fq);
 
   // fixed-point scale: every tile point is bounded by (visits) x max |q|
-  const double stile = (double)total * b.red[3];
+  const double stile = (double)total * gld(b.red)[3];
   const double scale = stile > 0.0 ? 1125899906842624.0 / (1.0009765625 * stile) : 0.0;   // 2^50
 
   const int kr = lane % G2, pr = lane / G2;
@@ -1230,8 +1267,8 @@ __device__ __forceinline__ void stage_spread_clip(const GridGeom& g, const EvalB
       const int e = base + lane;
       const int r = find_range(rpre, nr, e);
       const int i = rstart[r] + (e - rpre[r]);
-      wr[lane] = sfq[i];
-      const int pc = b.s_cell[i], code = rsh[r];
+      wr[lane] = ld_quad<T>(b.s_fq, i);
+      const int pc = gld(b.s_cell)[i], code = rsh[r];
       // stencil origin c + shift - P/2 + 1 in tile coordinates
       wo[3 * lane] = (pc & 1023) + pc_sh[0][code >> 8] - P / 2 + 1 - x0;
       wo[3 * lane + 1] = ((pc >> 10) & 1023) + pc_sh[1][(code >> 4) & 15] - P / 2 + 1 - y0;
@@ -1282,7 +1319,7 @@ __device__ __forceinline__ void stage_spread_clip(const GridGeom& g, const EvalB
         const int row = r0 + sub;
         if (row >= nrows) break;
         const int ly = row % ey, lz = row / ey;
-        grid[((long long)(z0 + lz) * g.G[1] + y0 + ly) * g.G[0] + x0 + lx] =
+        gst(grid)[((long long)(z0 + lz) * g.G[1] + y0 + ly) * g.G[0] + x0 + lx] =
             (T)((double)(long long)acc[(lz * TY + ly) * TX + lx] * inv);
       }
   }
@@ -1335,14 +1372,14 @@ __device__ __forceinline__ void stage_spread_cols(const GridGeom& g, const EvalB
     bz += pc_s0[2][kz];
     by += pc_s0[1][ky];
     const int row = (bz * g.nsb[1] + by) * g.nsb[0];
-    const int a = b.sb_start[row + pc_s0[0][xs]], e = b.sb_start[row + pc_s1[0][xs] + 1];
+    const auto sbs = gld(b.sb_start);
+    const int a = sbs[row + pc_s0[0][xs]], e = sbs[row + pc_s1[0][xs] + 1];
     rstart[r] = a;
     rpre[r] = e - a;
     rsh[r] = kz | (ky << 4) | (xs << 8);
   }
   __syncthreads();
   const int total = prefix_ranges(rpre, nr);
-  const Quad<T>* sfq = reinterpret_cast<const Quad<T>*>(b.s_fq);
 
   const int c = threadIdx.x, cx = c % TX, cy = c / TX;
   const bool own = c < TX * TY && cx < ex && cy < ey;
@@ -1363,9 +1400,9 @@ __device__ __forceinline__ void stage_spread_cols(const GridGeom& g, const EvalB
       const int e = v0 + k;
       const int r = find_range(rpre, nr, e);
       const int i = rstart[r] + (e - rpre[r]);
-      const Quad<T> f = sfq[i];
+      const Quad<T> f = ld_quad<T>(b.s_fq, i);
       if (kr == 0) {
-        const int pc = b.s_cell[i], code = rsh[r];
+        const int pc = gld(b.s_cell)[i], code = rsh[r];
         // stencil origin c + shift - P/2 + 1 in tile coordinates, each in [-P+1, T)
         const int ox = (pc & 1023) + pc_sh[0][code >> 8] - P / 2 + 1 - x0;
         const int oy = ((pc >> 10) & 1023) + pc_sh[1][(code >> 4) & 15] - P / 2 + 1 - y0;
@@ -1413,7 +1450,7 @@ __device__ __forceinline__ void stage_spread_cols(const GridGeom& g, const EvalB
     const long long zs = (long long)g.G[0] * g.G[1];
 #pragma unroll
     for (int z = 0; z < kColZ; ++z)
-      if (z < ez) grid[base + z * zs] = acc[z];
+      if (z < ez) gst(grid)[base + z * zs] = acc[z];
   }
   __syncthreads();
 }
@@ -1514,11 +1551,11 @@ __device__ __forceinline__ void stage_fold(const GridGeom& g, const EvalBuffers&
           const int bx = x - olx[kx];
           if (bx < 0 || bx >= RX) continue;
           const long long nt = ((long long)tlz[kz] * g.nt[1] + tly[ky]) * g.nt[0] + tlx[kx];
-          sum += stg[nt * R3 + ((long long)bz * RY + by) * RX + bx];
+          sum += gld(stg)[nt * R3 + ((long long)bz * RY + by) * RX + bx];
         }
       }
     }
-    grid[((long long)z * g.G[1] + y) * g.G[0] + x] = sum;
+    gst(grid)[((long long)z * g.G[1] + y) * g.G[0] + x] = sum;
   }
 }
 
@@ -1622,21 +1659,20 @@ __device__ __forceinline__ void stage_gather(const GridGeom& g, const EvalBuffer
   const int nr = (sz[1] - sz[0] + 1) * (sy[1] - sy[0] + 1);
   const int total = build_ranges(g, b, sz, 1, sy, 1, sx, 1, rstart, rpre);
   if (total == 0) {
-    if (threadIdx.x == 0) b.epart[t_id] = 0.0;
+    if (threadIdx.x == 0) gst(b.epart)[t_id] = 0.0;
     return;
   }
 
   // particle records of a batch, one per thread in one round of loads
-  const Quad<T>* sfq = reinterpret_cast<const Quad<T>*>(b.s_fq);
   auto load_batch = [&](int b0) {
     const int nb = min(kGatherBatch, total - b0);
     for (int k = threadIdx.x; k < nb; k += blockDim.x) {
       const int e = b0 + k;
       const int r = find_range(rpre, nr, e);
       const int i = rstart[r] + (e - rpre[r]);
-      rq[k] = sfq[i];
-      rc[k] = b.s_cell[i];
-      ri[k] = b.s_idx[i];
+      rq[k] = ld_quad<T>(b.s_fq, i);
+      rc[k] = gld(b.s_cell)[i];
+      ri[k] = gld(b.s_idx)[i];
     }
   };
   load_batch(0);   // in flight together with the region below
@@ -1663,7 +1699,7 @@ __device__ __forceinline__ void stage_gather(const GridGeom& g, const EvalBuffer
             const int py = row % RY, pz = row / RY;
             bool ok = okx;
             const int gy = wrap_coord(g, 1, ry + py, &ok), gz = wrap_coord(g, 2, rz + pz, &ok);
-            if (ok) v[u] = grid[((long long)gz * g.G[1] + gy) * g.G[0] + gx];
+            if (ok) v[u] = gld(grid)[((long long)gz * g.G[1] + gy) * g.G[0] + gx];
           }
         }
 #pragma unroll
@@ -1747,12 +1783,13 @@ __device__ __forceinline__ void stage_gather(const GridGeom& g, const EvalBuffer
       if (valid && iz == 0) {
         const int idx = ri[k];
         const T pv = sc * ph + (T)(self_coef * (double)f.q);
-        if (phi) phi[idx] = pv;
+        if (phi) gst(phi)[idx] = pv;
         if (force) {
           const T f0 = out_grad ? (T)1 : -f.q;
-          force[3 * idx] = f0 * sc * gx;
-          force[3 * idx + 1] = f0 * sc * gy;
-          force[3 * idx + 2] = f0 * sc * gz;
+          const auto fo = gst(force);
+          fo[3 * idx] = f0 * sc * gx;
+          fo[3 * idx + 1] = f0 * sc * gy;
+          fo[3 * idx + 2] = f0 * sc * gz;
         }
         eacc += (double)f.q * (double)pv;
       }
@@ -1765,7 +1802,7 @@ __device__ __forceinline__ void stage_gather(const GridGeom& g, const EvalBuffer
   if (threadIdx.x == 0) {
     double s = 0.0;
     for (int w = 0; w < nwaves; ++w) s += ewave[w];
-    b.epart[t_id] = s;
+    gst(b.epart)[t_id] = s;
   }
   __syncthreads();
 }

@@ -1417,31 +1417,32 @@ __device__ __forceinline__ void stage_spread_cols(const GridGeom& g, const EvalB
       }
     }
     __syncthreads();
-    if (own) {
-      // add visit k's stencil to this column; the origin is the same for all
-      // threads (uniform branches over z)
-      auto add_visit = [&](int k, int o) {
-        o = __builtin_amdgcn_readfirstlane(o);
-        const int ox = (o & 255) - 64, oy = ((o >> 8) & 255) - 64, oz = ((o >> 16) & 255) - 64;
-        const int dx = cx - ox, dy = cy - oy;
-        if ((unsigned)dx < (unsigned)P && (unsigned)dy < (unsigned)P) {
-          const T* w = wb + k * 3 * P;
-          const T wxy = w[dx] * w[P + dy];
+    // origins of 64 visits at a time, one per lane, broadcast by readlane;
+    // all lanes stay active through the loop (readlane reads every lane's
+    // value), and each visit's stencil rows add to the own column's registers
+    for (int k0 = 0; k0 < nb; k0 += 64) {
+      const int my_org = org[min(k0 + (int)(threadIdx.x & 63), nb - 1)];
+      const int kn = min(64, nb - k0);
+      {
+        for (int j = 0; j < kn; ++j) {
+          const int o = __builtin_amdgcn_readlane(my_org, j);
+          const int ox = (o & 255) - 64, oy = ((o >> 8) & 255) - 64, oz = ((o >> 16) & 255) - 64;
+          const int dx = cx - ox, dy = cy - oy;
+          if (own && (unsigned)dx < (unsigned)P && (unsigned)dy < (unsigned)P) {
+            const T* w = wb + (k0 + j) * 3 * P;
+            const T wxy = w[dx] * w[P + dy];
+            // fixed register index z, weight row index z - oz from LDS (the
+            // LDS index is clamped into the row so that a read the compiler
+            // hoists above the range test stays inside it)
 #pragma unroll
-          for (int z = 0; z < kColZ; ++z) {
-            const int iz = z - oz;
-            if ((unsigned)iz < (unsigned)P) acc[z] += wxy * w[2 * P + iz];
+            for (int z = 0; z < kColZ; ++z) {
+              const int iz = z - oz;
+              const T wz = w[2 * P + min(max(iz, 0), P - 1)];
+              if ((unsigned)iz < (unsigned)P) acc[z] += wxy * wz;
+            }
           }
         }
-      };
-      // two visits per trip so that their LDS reads overlap
-      int k = 0;
-      for (; k + 1 < nb; k += 2) {
-        const int o0 = org[k], o1 = org[k + 1];
-        add_visit(k, o0);
-        add_visit(k + 1, o1);
       }
-      if (k < nb) add_visit(k, org[k]);
     }
   }
   if (own) {

@@ -29,7 +29,7 @@ def rel_rms(a, b):
     return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
 
 
-def roofline(stages, prec):
+def roofline(stages, prec, workload_P=None):
     """Roofline object for the stage with the largest total time."""
     dom = max(stages, key=lambda s: s["ms_total"])
     t = dom["ms_avg"] * 1e-3
@@ -43,7 +43,7 @@ def roofline(stages, prec):
         try:
             tr = json.load(open(tpath))
             ent = tr.get(dom["name"])
-            if ent and ent.get("source_sha") == _source_sha():
+            if ent and ent.get("source_sha") == _source_sha() and ent.get("P") == workload_P:
                 traffic = ent["bytes_per_launch"]
         except Exception:
             traffic = None
@@ -263,7 +263,7 @@ def main_batch(args):
         t = max(r["ms_avg"], 1e-9) * 1e-3
         print(f"bench:   {r['name']:8s} {r['ms_avg'] * 1e3:9.1f} us  {r['bytes'] / t / 1e9:8.1f} GB/s  "
               f"{r['flops'] / t / 1e12:7.2f} TFLOP/s", file=sys.stderr, flush=True)
-    roof = roofline(stages, "f32")
+    roof = roofline(stages, "f32", cfg["P"])
     stage_ids = {n: k for k, n in enumerate(["zero", "bin", "scan1", "scan2", "scatter", "order", "spread", "fold",
                                              "fft0", "fft1", "fft2", "fft3", "fft4", "gather", "energy"])}
     st_name = roof["kernel"]

@@ -64,7 +64,7 @@ def roofline(stages, prec, workload_P=None):
 def _source_sha():
     import hashlib
     h = hashlib.sha256()
-    for f in ("se_kernels.hip", "se_plan.cpp", "se_internal.h"):
+    for f in ("se_kernels.hip", "se_fft.hip", "se_plan.cpp", "se_internal.h", "se_device.h"):
         h.update(open(os.path.join(ROOT, "paper_1712_04732_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 

@@ -1,0 +1,616 @@
+// gfx950 pencil transforms of the Spectral Ewald k-space path (Algorithms 1-3
+// of Shamshirgar, Bagge, Tornberg, arXiv:1712.04732).
+//
+// One workgroup transforms B pencils of one length-n class at once: it loads
+// them into LDS (zero padding up to n), runs mixed-radix (2,3,4,5,7,8)
+// Stockham stages between two LDS buffers, and stores the first n_out samples
+// (truncation).  Real-to-complex and complex-to-real passes transform two real
+// pencils as the real and imaginary parts of one complex pencil.  The fused
+// pass runs the forward transform, the scaling of Eq. (scale) and the inverse
+// transform of a pencil without leaving LDS.
+//
+// Addressing: every per-lane offset is kept relative to a per-workgroup base
+// held in scalar registers and advanced by additions; offsets are 32-bit
+// unless a workgroup's pencils span 4 GiB (then 64-bit).  LDS addresses are
+// 32-bit and butterfly strides are uniform, so a butterfly input or output
+// costs one vector add.
+#include "se_device.h"
+
+namespace se {
+
+// ---------------------------------------------------------------------------
+// Small DFTs, X_m = sum_r v_r exp(sign 2 pi i r m / R)
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void dft2(cx<T>* v) {
+  const cx<T> a = v[0], b = v[1];
+  v[0] = a + b;
+  v[1] = a - b;
+}
+
+template <typename T>
+__device__ __forceinline__ void dft4(cx<T>* v, int sign) {
+  const cx<T> t0 = v[0] + v[2], t1 = v[0] - v[2], t2 = v[1] + v[3];
+  const cx<T> t3 = mul_si(v[1] - v[3], sign);
+  v[0] = t0 + t2;
+  v[2] = t0 - t2;
+  v[1] = t1 + t3;
+  v[3] = t1 - t3;
+}
+
+template <typename T>
+__device__ __forceinline__ void dft8(cx<T>* v, int sign) {
+  cx<T> e[4] = {v[0], v[2], v[4], v[6]};
+  cx<T> o[4] = {v[1], v[3], v[5], v[7]};
+  dft4(e, sign);
+  dft4(o, sign);
+  const T c = (T)0.70710678118654752440;
+  // w^k = exp(sign i pi k / 4)
+  const cx<T> o1 = cmul(o[1], cx<T>{c, sign * c});
+  const cx<T> o2 = mul_si(o[2], sign);
+  const cx<T> o3 = cmul(o[3], cx<T>{-c, sign * c});
+  v[0] = e[0] + o[0];
+  v[4] = e[0] - o[0];
+  v[1] = e[1] + o1;
+  v[5] = e[1] - o1;
+  v[2] = e[2] + o2;
+  v[6] = e[2] - o2;
+  v[3] = e[3] + o3;
+  v[7] = e[3] - o3;
+}
+
+// Odd radix R in {3,5,7}: pair r with R-r,
+//   X_m = v_0 + sum_{r=1}^{(R-1)/2} [(v_r + v_{R-r}) cos(2 pi r m/R)
+//                                  + sign i (v_r - v_{R-r}) sin(2 pi r m/R)].
+template <int R>
+struct OddRoots;
+template <>
+struct OddRoots<3> {
+  static constexpr double c[3] = {1.0, -0.5, -0.5};
+  static constexpr double s[3] = {0.0, 0.86602540378443864676, -0.86602540378443864676};
+};
+template <>
+struct OddRoots<5> {
+  static constexpr double c[5] = {1.0, 0.30901699437494742410, -0.80901699437494742410,
+                                  -0.80901699437494742410, 0.30901699437494742410};
+  static constexpr double s[5] = {0.0, 0.95105651629515357212, 0.58778525229247312917,
+                                  -0.58778525229247312917, -0.95105651629515357212};
+};
+template <>
+struct OddRoots<7> {
+  static constexpr double c[7] = {1.0,
+                                  0.62348980185873353053,
+                                  -0.22252093395631440429,
+                                  -0.90096886790241912624,
+                                  -0.90096886790241912624,
+                                  -0.22252093395631440429,
+                                  0.62348980185873353053};
+  static constexpr double s[7] = {0.0,
+                                  0.78183148246802980871,
+                                  0.97492791218182360702,
+                                  0.43388373911755812048,
+                                  -0.43388373911755812048,
+                                  -0.97492791218182360702,
+                                  -0.78183148246802980871};
+};
+
+template <typename T, int R>
+__device__ __forceinline__ void dft_odd(cx<T>* v, int sign) {
+  constexpr int H = (R - 1) / 2;
+  cx<T> a[H], b[H];
+  cx<T> x0 = v[0];
+#pragma unroll
+  for (int r = 1; r <= H; ++r) {
+    a[r - 1] = v[r] + v[R - r];
+    b[r - 1] = v[r] - v[R - r];
+    x0 = x0 + a[r - 1];
+  }
+  cx<T> out[R];
+  out[0] = x0;
+#pragma unroll
+  for (int m = 1; m < R; ++m) {
+    cx<T> acc = v[0];
+    cx<T> bs = {0, 0};
+#pragma unroll
+    for (int r = 1; r <= H; ++r) {
+      const int j = (r * m) % R;
+      const T cc = (T)OddRoots<R>::c[j], ss = (T)OddRoots<R>::s[j];
+      acc = acc + cscale(a[r - 1], cc);
+      bs = bs + cscale(b[r - 1], ss);
+    }
+    out[m] = acc + mul_si(bs, sign);
+  }
+#pragma unroll
+  for (int m = 0; m < R; ++m) v[m] = out[m];
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void dft(cx<T>* v, int sign) {
+  if constexpr (R == 2) dft2(v);
+  else if constexpr (R == 4) dft4(v, sign);
+  else if constexpr (R == 8) dft8(v, sign);
+  else dft_odd<T, R>(v, sign);
+}
+
+
+// LDS views.  Arithmetic on these pointers is 32-bit.
+template <typename T>
+using lds = __attribute__((address_space(3))) T;
+
+template <typename T>
+__device__ __forceinline__ cx<T> lget(const lds<vec2<T>>* p, int i) {
+  const vec2<T> v = p[i];
+  return cx<T>{v.x, v.y};
+}
+template <typename T>
+__device__ __forceinline__ void lput(lds<vec2<T>>* p, int i, cx<T> v) {
+  p[i] = vec2<T>{v.re, v.im};
+}
+
+// Global loads and stores at a byte offset from a base pointer.  With a
+// uniform base and a 32-bit offset the compiler addresses them as scalar base
+// plus vector offset.
+template <typename V, typename OFF>
+__device__ __forceinline__ V gload(const void* base, OFF off) {
+  return *(const __attribute__((address_space(1))) V*)((const __attribute__((address_space(1))) char*)base + off);
+}
+template <typename V, typename OFF>
+__device__ __forceinline__ void gstore(void* base, OFF off, V v) {
+  *(__attribute__((address_space(1))) V*)((__attribute__((address_space(1))) char*)base + off) = v;
+}
+
+__device__ __forceinline__ int rfl(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// One Stockham stage from src to dst over B = 2^lgB interleaved pencils stored
+// sample-major with pitch Bp (sample t of pencil p at t Bp + p).  Butterfly j
+// (pencil p) reads samples j + r n/R, multiplies input r by the twiddle
+// exp(sign 2 pi i r k/(Ns R)) = tw[r k tws] (k = j mod Ns, tws = n/(Ns R)),
+// and writes outputs (j div Ns) Ns R + k + r Ns.  The first stage (Ns = 1)
+// has no twiddles.
+template <typename T, int R, bool FIRST, int SIGN>
+__device__ __forceinline__ void fft_stage(const lds<vec2<T>>* __restrict__ src, lds<vec2<T>>* __restrict__ dst,
+                                          const lds<vec2<T>>* __restrict__ tw, int n, int Ns, int tws, int lgB,
+                                          int Bp) {
+  const int nb = n / R;
+  const int total = nb << lgB;
+  const int mask = (1 << lgB) - 1;
+  const int sstr = nb * Bp;   // between the inputs of a butterfly
+  const int dstr = Ns * Bp;   // between its outputs
+  const int nsr = Ns * R;
+  const float inv_ns = 1.0f / (float)Ns;
+  for (int e = threadIdx.x; e < total; e += kFftBlock) {
+    const int j = e >> lgB, p = e & mask;
+    const lds<vec2<T>>* s = src + (__mul24(j, Bp) + p);
+    cx<T> v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = lget<T>(s, r * sstr);
+    int base;
+    if constexpr (FIRST) {
+      base = __mul24(j, R);
+    } else {
+      const int jq = fdiv(j, inv_ns), k = j - __mul24(jq, Ns);
+      const int kt = __mul24(k, tws);
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        cx<T> w = lget<T>(tw, r * kt);   // r k tws < R Ns tws = n
+        if constexpr (SIGN > 0) w.im = -w.im;
+        v[r] = cmul(v[r], w);
+      }
+      base = __mul24(jq, nsr) + k;
+    }
+    dft<T, R>(v, SIGN);
+    lds<vec2<T>>* d = dst + (__mul24(base, Bp) + p);
+#pragma unroll
+    for (int r = 0; r < R; ++r) lput<T>(d, r * dstr, v[r]);
+  }
+}
+
+template <typename T, bool FIRST, int SIGN>
+__device__ __forceinline__ void fft_stage_r(int R, const lds<vec2<T>>* src, lds<vec2<T>>* dst,
+                                            const lds<vec2<T>>* tw, int n, int Ns, int tws, int lgB, int Bp) {
+  switch (R) {
+    case 2: fft_stage<T, 2, FIRST, SIGN>(src, dst, tw, n, Ns, tws, lgB, Bp); break;
+    case 3: fft_stage<T, 3, FIRST, SIGN>(src, dst, tw, n, Ns, tws, lgB, Bp); break;
+    case 4: fft_stage<T, 4, FIRST, SIGN>(src, dst, tw, n, Ns, tws, lgB, Bp); break;
+    case 5: fft_stage<T, 5, FIRST, SIGN>(src, dst, tw, n, Ns, tws, lgB, Bp); break;
+    case 7: fft_stage<T, 7, FIRST, SIGN>(src, dst, tw, n, Ns, tws, lgB, Bp); break;
+    default: fft_stage<T, 8, FIRST, SIGN>(src, dst, tw, n, Ns, tws, lgB, Bp); break;
+  }
+}
+
+// All stages of class C (radices packed 4 bits per stage, first stage lowest),
+// alternating between the two buffers; returns the buffer holding the result.
+template <typename T, int SIGN>
+__device__ __forceinline__ lds<vec2<T>>* fft_run(lds<vec2<T>>* b0, lds<vec2<T>>* b1, const lds<vec2<T>>* tw,
+                                                 const FftClass& C, int lgB, int Bp) {
+  lds<vec2<T>>* src = b0;
+  lds<vec2<T>>* dst = b1;
+  const int n = C.n, nst = C.nst;
+  unsigned long long radices = C.radpack;
+  int Ns = 1, rem = n;   // rem = n / Ns
+  for (int s = 0; s < nst; ++s) {
+    const int R = (int)(radices & 15u);
+    radices >>= 4;
+    const int tws = rem / R;
+    if (s == 0) fft_stage_r<T, true, SIGN>(R, src, dst, tw, n, Ns, tws, lgB, Bp);
+    else fft_stage_r<T, false, SIGN>(R, src, dst, tw, n, Ns, tws, lgB, Bp);
+    __syncthreads();
+    lds<vec2<T>>* tmp = src;
+    src = dst;
+    dst = tmp;
+    Ns *= R;
+    rem = tws;
+  }
+  return src;
+}
+
+__device__ __forceinline__ int fold_index(int i, int n) { return i <= n - i ? i : n - i; }
+
+// The factors of Eq. (scale) that depend only on the pencil (b0, b1): the
+// separable vectors of the two pencil directions and the pencil's part of the
+// table or |k|^2 index.
+template <typename T>
+struct ScaleRow {
+  T s;     // sA[b0] sB[b1]
+  T k2;    // kA[b0] + kB[b1]            (G_INVSQ)
+  int g;   // table offset of the pencil (G_TAB2, G_TAB3)
+};
+
+template <typename T>
+__device__ __forceinline__ ScaleRow<T> scale_row(const FftClass& C, int b0, int b1) {
+  ScaleRow<T> r;
+  r.s = gld((const T*)C.sA)[b0 + C.offA] * gld((const T*)C.sB)[b1 + C.offB];
+  r.k2 = 0;
+  r.g = 0;
+  const int i0 = C.fold0 ? fold_index(b0, C.fold0) : b0;
+  if (C.gmode == G_INVSQ) r.k2 = gld((const T*)C.kA)[b0 + C.offA] + gld((const T*)C.kB)[b1 + C.offB];
+  else if (C.gmode == G_TAB2) r.g = i0;
+  else if (C.gmode == G_TAB3) r.g = fold_index(b1, C.fold1) * C.gd0 + i0;
+  return r;
+}
+
+// Tables store the pencil index b0 fastest, so neighbouring lanes (neighbouring
+// pencils) read neighbouring entries: G_TAB2 [t][b0], G_TAB3 [t][b1][b0].
+template <typename T>
+__device__ __forceinline__ T scale_at(const FftClass& C, const ScaleRow<T>& r, int t) {
+  const T s = r.s * gld((const T*)C.sC)[t];
+  const auto gt = gld((const T*)C.gtab);
+  switch (C.gmode) {
+    case G_INVSQ: {
+      const T k2 = r.k2 + gld((const T*)C.kC)[t];
+      return k2 > (T)0 ? s / k2 : (T)0;
+    }
+    case G_TAB1:
+      return s * gt[t];
+    case G_TAB2:
+      return s * gt[fold_index(t, C.fold2) * C.gd0 + r.g];
+    case G_TAB3:
+      return s * gt[fold_index(t, C.fold2) * (C.gd1 * C.gd0) + r.g];
+    default:
+      return s;
+  }
+}
+
+// The slots one thread visits when a workgroup streams an n x B block of
+// pencil samples: slots tid, tid + kFftBlock, ...  Slot order is pencil-major
+// (p = e div n, t = e mod n) when the transform direction is contiguous in
+// memory (TF) and sample-major (t = e div B, p = e mod B) otherwise, so that
+// neighbouring lanes touch neighbouring addresses.  The thread tracks the
+// sample t, the pencil p, a global byte offset g = p gs0 + t gst and an LDS
+// index l = t lt + p lp, all advanced by additions (B <= 64 divides
+// kFftBlock).
+template <bool TF, typename OFF>
+struct SlotWalk {
+  int n, dt, q, r;
+  OFF dg, dgw;
+  int dl, dlw;
+  int t, p;
+  OFF g;
+  int l;
+
+  __device__ __forceinline__ SlotWalk(int n_, int lgB, OFF gs0, OFF gst, int lt, int lp) : n(n_) {
+    const int tid = threadIdx.x;
+    if constexpr (TF) {
+      const float inv_n = 1.0f / (float)n;
+      q = fdiv(kFftBlock, inv_n);
+      r = kFftBlock - q * n;
+      p = fdiv(tid, inv_n);
+      t = tid - p * n;
+      dg = (OFF)r * gst + (OFF)q * gs0;
+      dgw = gs0 - (OFF)n * gst;
+      dl = r * lt + q * lp;
+      dlw = lp - n * lt;
+      dt = 0;
+    } else {
+      dt = kFftBlock >> lgB;
+      p = tid & ((1 << lgB) - 1);
+      t = tid >> lgB;
+      dg = (OFF)dt * gst;
+      dl = dt * lt;
+      q = r = 0;
+      dgw = 0;
+      dlw = 0;
+    }
+    g = (OFF)p * gs0 + (OFF)t * gst;
+    l = t * lt + p * lp;
+  }
+  __device__ __forceinline__ void step() {
+    if constexpr (TF) {
+      t += r;
+      p += q;
+      g += dg;
+      l += dl;
+      const bool w = t >= n;
+      t = w ? t - n : t;
+      p = w ? p + 1 : p;
+      g = w ? g + dgw : g;
+      l = w ? l + dlw : l;
+    } else {
+      t += dt;
+      g += dg;
+      l += dl;
+    }
+  }
+};
+
+// A real pencil pair (a, b) shares one complex transform z = a + i b.  Forward:
+// A_k = (Z_k + conj Z_{n-k})/2 and B_k = (Z_k - conj Z_{n-k})/(2i).  Inverse:
+// the half spectra of a and b, Hermitian-extended, combine to Z = A + i B, whose
+// transform holds a in the real and b in the imaginary part.
+template <typename T>
+__device__ __forceinline__ cx<T> split_pair(cx<T> z, cx<T> zn, int odd) {
+  return odd ? cx<T>{(T)0.5 * (z.im + zn.im), (T)0.5 * (zn.re - z.re)}
+             : cx<T>{(T)0.5 * (z.re + zn.re), (T)0.5 * (z.im - zn.im)};
+}
+
+constexpr int kSlotsInFlight = 8;   // global loads in flight per thread
+
+// Load phase: pencils p < cnt of the work item into buf (sample-major, pitch
+// Bp), zero padded from n_in to n; twiddles into tw.  C2R reads the stored
+// half spectrum (t <= n/2) and extends it by Hermitian symmetry.
+template <typename T, int KIND, bool TF, typename OFF>
+__device__ __forceinline__ void fft_load(const FftClass& C, int b0s, int b1, int cnt, int lgB, int pair, int Bp,
+                                         lds<vec2<T>>* buf, lds<vec2<T>>* tw) {
+  constexpr int U = kSlotsInFlight;
+  using V2 = vec2<T>;
+  const int n = C.n;
+  // twiddle table: the first kFftBlock entries travel with the first round
+  const bool has_tw = (int)threadIdx.x < n;
+  V2 tw0 = V2{0, 0};
+  if (has_tw) tw0 = gld(reinterpret_cast<const V2*>(C.tw))[threadIdx.x];
+  auto put_twiddles = [&]() {
+    if (has_tw) tw[threadIdx.x] = tw0;
+    for (int i = threadIdx.x + kFftBlock; i < n; i += kFftBlock) tw[i] = gld(reinterpret_cast<const V2*>(C.tw))[i];
+  };
+  if constexpr (KIND == K_C2R) {
+    // slots (t, complex pencil c), c < B / 2^pair: pencils 2c, 2c + 1 (paired) or c
+    constexpr OFF esz = 2 * sizeof(T);
+    const int lgF = lgB - pair;
+    const char* base = (const char*)C.in + ((long long)b0s * C.in_s0 + (long long)b1 * C.in_s1) * (long long)esz;
+    const OFF gs0 = (OFF)C.in_s0 * esz, gst = (OFF)C.in_st * esz;
+    const OFF gsp = gs0 << pair;
+    const int total = n << lgF, h = n >> 1, F = 1 << lgF;
+    SlotWalk<TF, OFF> w(n, lgF, gsp, (OFF)0, Bp, 1);   // g tracks the pencil part only
+    for (int e0 = 0; e0 < total; e0 += U * kFftBlock) {
+      cx<T> v[U];
+      int lw[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        v[u] = cx<T>{0, 0};
+        const int pa = w.p << pair;
+        const bool up = w.t <= h;
+        const int ts = up ? w.t : n - w.t;
+        const T sg = up ? (T)1 : (T)-1;   // Hermitian extension of the stored half
+        const OFF go = w.g + (TF ? (OFF)ts * esz : (OFF)ts * gst);
+        if (w.t < n && pa < cnt) {
+          const V2 a = gload<V2>(base, go);
+          v[u] = cx<T>{a.x, sg * a.y};
+          if (pair && pa + 1 < cnt) {
+            const V2 bb = gload<V2>(base, go + gs0);
+            v[u].re -= sg * bb.y;
+            v[u].im += bb.x;
+          }
+        }
+        lw[u] = (w.t < n && w.p < F) ? w.l : -1;
+        w.step();
+      }
+      if (e0 == 0) put_twiddles();
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (lw[u] >= 0) lput<T>(buf, lw[u], v[u]);
+    }
+  } else {
+    // slots (t, pencil p), p < B; a paired real pass packs pencil p into
+    // component p & 1 of complex pencil p / 2 (LDS float index 2 t Bp + p)
+    constexpr bool RIN = (KIND == K_R2C);
+    constexpr OFF esz = RIN ? sizeof(T) : 2 * sizeof(T);
+    const char* base = (const char*)C.in + ((long long)b0s * C.in_s0 + (long long)b1 * C.in_s1) * (long long)esz;
+    const OFF gs0 = (OFF)C.in_s0 * esz, gst = (OFF)C.in_st * esz;
+    const int total = n << lgB, n_in = C.n_in, B = 1 << lgB;
+    SlotWalk<TF, OFF> w(n, lgB, gs0, gst, pair ? 2 * Bp : Bp, 1);
+    lds<T>* fbuf = reinterpret_cast<lds<T>*>(buf);
+    for (int e0 = 0; e0 < total; e0 += U * kFftBlock) {
+      cx<T> v[U];
+      int lw[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        v[u] = cx<T>{0, 0};
+        if (w.p < cnt && w.t < n_in) {
+          if constexpr (RIN) {
+            v[u].re = gload<T>(base, w.g);
+          } else {
+            const V2 a = gload<V2>(base, w.g);
+            v[u] = cx<T>{a.x, a.y};
+          }
+        }
+        lw[u] = (w.t < n && w.p < B) ? w.l : -1;
+        w.step();
+      }
+      if (e0 == 0) put_twiddles();
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (lw[u] < 0) continue;
+        if (RIN && pair) fbuf[lw[u]] = v[u].re;
+        else lput<T>(buf, lw[u], v[u]);
+      }
+    }
+  }
+}
+
+// Store phase: the first n_out samples of pencils p < cnt from res.
+template <typename T, int KIND, bool TF, typename OFF>
+__device__ __forceinline__ void fft_store(const FftClass& C, int b0s, int b1, int cnt, int lgB, int pair, int Bp,
+                                          const lds<vec2<T>>* res) {
+  constexpr int U = kSlotsInFlight;
+  constexpr bool ROUT = (KIND == K_C2R);
+  constexpr OFF esz = ROUT ? sizeof(T) : 2 * sizeof(T);
+  const int n = C.n, nout = C.n_out;
+  char* base = (char*)C.out + ((long long)b0s * C.out_s0 + (long long)b1 * C.out_s1) * (long long)esz;
+  const OFF gs0 = (OFF)C.out_s0 * esz, gst = (OFF)C.out_st * esz;
+  const int total = nout << lgB;
+  // LDS index of slot (t, p): complex t Bp + p; for the real passes the float
+  // index 2 t Bp + p (paired) or 2 (t Bp + p) (single pencil, C2R)
+  const int lt = (KIND == K_R2C || KIND == K_C2R) ? 2 * Bp : Bp;
+  const int lp = (KIND == K_C2R && !pair) ? 2 : 1;
+  SlotWalk<TF, OFF> w(nout, lgB, gs0, gst, lt, lp);
+  const lds<T>* fres = reinterpret_cast<const lds<T>*>(res);
+  for (int e0 = 0; e0 < total; e0 += U * kFftBlock) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (w.p < cnt && w.t < nout) {
+        if constexpr (KIND == K_C2R) {
+          gstore<T>(base, w.g, fres[w.l]);
+        } else if constexpr (KIND == K_R2C) {
+          cx<T> v;
+          if (pair) {
+            const int lc = w.l >> 1;                  // t Bp + p / 2
+            const int tn = w.t == 0 ? 0 : n - w.t;
+            v = split_pair(lget<T>(res, lc), lget<T>(res, lc + __mul24(tn - w.t, Bp)), w.p & 1);
+          } else {
+            v = lget<T>(res, w.l >> 1);               // float index 2 (t Bp + p) for B = 1
+          }
+          gstore<vec2<T>>(base, w.g, vec2<T>{v.re, v.im});
+        } else {
+          const cx<T> v = lget<T>(res, w.l);
+          gstore<vec2<T>>(base, w.g, vec2<T>{v.re, v.im});
+        }
+      }
+      w.step();
+    }
+  }
+}
+
+template <typename T, int KIND, typename OFF>
+__device__ __forceinline__ void stage_fft(const FftPass& P, int item, lds<unsigned char>* smem) {
+  constexpr bool REAL = (KIND == K_R2C || KIND == K_C2R);
+  // the work item {class, b0 start, b1, count}, the same for the whole workgroup
+  const auto itp = gld(reinterpret_cast<const int*>(P.items)) + 4 * item;
+  const int cls = rfl(itp[0]), b0s = rfl(itp[1]), b1 = rfl(itp[2]), cnt = rfl(itp[3]);
+  const FftClass& C = P.cls[cls];
+  const int n = C.n, lgB = P.lgB;
+  // real passes with B >= 2 run B/2 complex transforms of pencil pairs
+  const int pair = (REAL && lgB > 0) ? 1 : 0;
+  const int lgF = lgB - pair, Bp = (1 << lgF) + 1;
+  lds<vec2<T>>* tw = reinterpret_cast<lds<vec2<T>>*>(smem);
+  lds<vec2<T>>* buf = tw + P.nmax;
+  lds<vec2<T>>* buf2 = buf + P.nmax * ((1 << lgB) + 1);
+
+  if (C.in_st == 1) fft_load<T, KIND, true, OFF>(C, b0s, b1, cnt, lgB, pair, Bp, buf, tw);
+  else fft_load<T, KIND, false, OFF>(C, b0s, b1, cnt, lgB, pair, Bp, buf, tw);
+  __syncthreads();
+
+  lds<vec2<T>>* res;
+  if constexpr (KIND == K_C2C_INV || KIND == K_C2R) res = fft_run<T, +1>(buf, buf2, tw, C, lgF, Bp);
+  else res = fft_run<T, -1>(buf, buf2, tw, C, lgF, Bp);
+
+  if constexpr (KIND == K_FUSED) {
+    // scaling step, Eq. (scale), on the spectrum of each pencil; the block
+    // size is a multiple of B, so each thread keeps one pencil p throughout
+    const int p = threadIdx.x & ((1 << lgB) - 1);
+    const int dt = kFftBlock >> lgB, dl = dt * Bp;
+    if (p < cnt) {
+      const ScaleRow<T> row = scale_row<T>(C, b0s + p, b1);
+      int t = threadIdx.x >> lgB;
+      for (int l = __mul24(t, Bp) + p; t < n; t += dt, l += dl) lput<T>(res, l, cscale(lget<T>(res, l), scale_at<T>(C, row, t)));
+    }
+    __syncthreads();
+    res = fft_run<T, +1>(res, res == buf ? buf2 : buf, tw, C, lgB, Bp);
+  }
+
+  if (C.out_st == 1) fft_store<T, KIND, true, OFF>(C, b0s, b1, cnt, lgB, pair, Bp, res);
+  else fft_store<T, KIND, false, OFF>(C, b0s, b1, cnt, lgB, pair, Bp, res);
+}
+
+template <typename T, int KIND, typename OFF>
+__global__ __launch_bounds__(kFftBlock) void fft_kernel(const FftPass P) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  stage_fft<T, KIND, OFF>(P, work_item(P.xcd), (lds<unsigned char>*)smem);
+}
+
+// One transform kind of one transform stage of a batch: block b is work item b
+// of the (stage, kind) list, counted over the systems in order.
+template <typename T, int KIND, typename OFF>
+__global__ __launch_bounds__(kFftBlock) void batch_fft_kernel(const SysDesc* __restrict__ sys, int nsys,
+                                                              const int* __restrict__ o, int pass, int xcd) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int item = work_item(xcd);
+  int lo = 0, hi = nsys - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (o[mid] <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  lo = rfl(lo);  // uniform: keeps the descriptor in scalar registers
+  stage_fft<T, KIND, OFF>(sys[lo].pass[pass], item - o[lo], (lds<unsigned char>*)smem);
+}
+
+size_t fft_lds_bytes(const FftPass& p, bool f64) {
+  const size_t c = f64 ? 16 : 8;
+  return c * ((size_t)p.nmax + 2 * (((size_t)1 << p.lgB) + 1) * p.nmax);
+}
+
+template <typename T, typename OFF>
+static void launch_fft_t(const FftPass& p, hipStream_t st) {
+  const size_t lds = fft_lds_bytes(p, sizeof(T) == 8);
+  const dim3 grid(p.nitems), block(kFftBlock);
+  switch (p.kind) {
+    case K_C2C_FWD: fft_kernel<T, K_C2C_FWD, OFF><<<grid, block, lds, st>>>(p); break;
+    case K_C2C_INV: fft_kernel<T, K_C2C_INV, OFF><<<grid, block, lds, st>>>(p); break;
+    case K_R2C: fft_kernel<T, K_R2C, OFF><<<grid, block, lds, st>>>(p); break;
+    case K_C2R: fft_kernel<T, K_C2R, OFF><<<grid, block, lds, st>>>(p); break;
+    default: fft_kernel<T, K_FUSED, OFF><<<grid, block, lds, st>>>(p); break;
+  }
+}
+
+hipError_t launch_fft(const FftPass& p, bool f64, hipStream_t st) {
+  if (p.nitems <= 0) return hipSuccess;
+  using W = unsigned long long;
+  if (f64) p.wide ? launch_fft_t<double, W>(p, st) : launch_fft_t<double, unsigned>(p, st);
+  else p.wide ? launch_fft_t<float, W>(p, st) : launch_fft_t<float, unsigned>(p, st);
+  return hipGetLastError();
+}
+
+template <typename T, typename OFF>
+static void launch_batch_fft_t(int kind, const SysDesc* sys, int nsys, const int* o, int pass, int nitems,
+                               size_t lds, int xcd, hipStream_t st) {
+  const dim3 grid(nitems), block(kFftBlock);
+  switch (kind) {
+    case K_C2C_FWD: batch_fft_kernel<T, K_C2C_FWD, OFF><<<grid, block, lds, st>>>(sys, nsys, o, pass, xcd); break;
+    case K_C2C_INV: batch_fft_kernel<T, K_C2C_INV, OFF><<<grid, block, lds, st>>>(sys, nsys, o, pass, xcd); break;
+    case K_R2C: batch_fft_kernel<T, K_R2C, OFF><<<grid, block, lds, st>>>(sys, nsys, o, pass, xcd); break;
+    case K_C2R: batch_fft_kernel<T, K_C2R, OFF><<<grid, block, lds, st>>>(sys, nsys, o, pass, xcd); break;
+    default: batch_fft_kernel<T, K_FUSED, OFF><<<grid, block, lds, st>>>(sys, nsys, o, pass, xcd); break;
+  }
+}
+
+void launch_batch_fft(bool f64, int kind, bool wide, const SysDesc* sys, int nsys, const int* o, int pass,
+                      int nitems, size_t lds, int xcd, hipStream_t st) {
+  if (nitems <= 0) return;
+  using W = unsigned long long;
+  if (f64) wide ? launch_batch_fft_t<double, W>(kind, sys, nsys, o, pass, nitems, lds, xcd, st)
+                : launch_batch_fft_t<double, unsigned>(kind, sys, nsys, o, pass, nitems, lds, xcd, st);
+  else wide ? launch_batch_fft_t<float, W>(kind, sys, nsys, o, pass, nitems, lds, xcd, st)
+            : launch_batch_fft_t<float, unsigned>(kind, sys, nsys, o, pass, nitems, lds, xcd, st);
+}
+
+}  // namespace se

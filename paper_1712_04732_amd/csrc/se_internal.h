@@ -53,6 +53,7 @@ struct FftClass {
   unsigned long long radpack;     // rad[] packed 4 bits per stage, stage 0 lowest
   const void* in;
   void* out;
+  const void* tw;                 // twiddles exp(-2 pi i k/n), k < n, in the compute precision
   long long in_st, in_s0, in_s1;
   long long out_st, out_s0, out_s1;
   // scaling of the fused pass: S = sA[b0+offA] sB[b1+offB] sC[t] G
@@ -80,6 +81,7 @@ struct FftPass {
   int nmax;                       // largest n (LDS sizing)
   int kind;
   int xcd;                        // item mapping: 0 plain, 1 one range per XCD, c >= 2 chunks of c
+  int wide;                       // 1 if a workgroup's pencils span 4 GiB or more (64-bit offsets)
   double alg_bytes, alg_flops;    // algorithmic counts of one launch (tracing only)
 };
 
@@ -148,6 +150,7 @@ struct BatchIO {
   double* energy;     // one per system
   int in_f32, out_grad, add_self, allow_nonneutral;
   int xcd_tiles, xcd_fft;   // item mapping modes of the tile / transform stages (as GridGeom::xcd)
+  int fft_wide;             // bit k: transform stage k needs 64-bit offsets for some system
 };
 
 // Stages of a batched evaluation, in order; one launch per stage.
@@ -175,8 +178,13 @@ hipError_t launch_gather(const GridGeom& g, const EvalBuffers& b, bool f64, void
                          int out_grad, double self_coef, hipStream_t st);
 hipError_t launch_energy(const GridGeom& g, const EvalBuffers& b, double* energy, double self_e,
                          hipStream_t st);
+// Transforms (se_fft.hip).
 hipError_t launch_fft(const FftPass& p, bool f64, hipStream_t st);
 size_t fft_lds_bytes(const FftPass& p, bool f64);
+// One transform kind of transform stage 'pass' of a batch: 'nitems' work items,
+// 'o' the device prefix table [nsys + 1] of that (stage, kind) work list.
+void launch_batch_fft(bool f64, int kind, bool wide, const SysDesc* sys, int nsys, const int* o, int pass,
+                      int nitems, size_t lds, int xcd, hipStream_t st);
 size_t spread_lds_bytes(const GridGeom& g, bool f64);
 size_t gather_lds_bytes(const GridGeom& g, bool f64);
 int scan_blocks(const GridGeom& g);

@@ -7,12 +7,7 @@
 //              of the grid, accumulates every particle whose P^3 stencil meets
 //              the tile into an LDS copy of the tile, and writes the tile once.
 //              No global atomics; grid bytes are written exactly once.
-//   fft      : mixed-radix (2,3,4,5,7,8) Stockham pencil transforms in LDS,
-//              with zero padding on load and truncation on store (the padded
-//              free-direction transforms of Algorithm 1/2 and the (2 Mt)^3
-//              free-space transform), and a fused variant that runs forward
-//              transform, scaling by Eq. (scale) and inverse transform on a
-//              pencil without leaving LDS.
+//   fft      : pencil transforms, in se_fft.hip.
 //   gather   : trapezoidal rule of Eq. (complete_integral) and its gradient,
 //              Eq. (force-method-1).  One workgroup per tile stages the
 //              tile's stencil region of the grid in LDS; one wavefront per
@@ -20,190 +15,9 @@
 //              reduction by shuffles.
 //   energy   : FP64 reduction of q phi.
 //   0P       : Algorithm 3 helpers in FP64.
-#include <hip/hip_runtime.h>
-
-#include "se_internal.h"
+#include "se_device.h"
 
 namespace se {
-
-template <typename T>
-struct __align__(2 * sizeof(T)) cx {
-  T re, im;
-};
-
-template <typename T>
-__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) {
-  return {a.re + b.re, a.im + b.im};
-}
-template <typename T>
-__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) {
-  return {a.re - b.re, a.im - b.im};
-}
-template <typename T>
-__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
-  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
-}
-template <typename T>
-__device__ __forceinline__ cx<T> cscale(cx<T> a, T s) {
-  return {a.re * s, a.im * s};
-}
-// multiply by sign * i
-template <typename T>
-__device__ __forceinline__ cx<T> mul_si(cx<T> a, int sign) {
-  return sign > 0 ? cx<T>{-a.im, a.re} : cx<T>{a.im, -a.re};
-}
-
-template <typename T>
-struct Quad {
-  T fx, fy, fz, q;
-};
-
-// Pointers held in descriptors are generic (they could address LDS), so
-// loads through them are flat vector loads.  Device buffers are global
-// memory: these casts let the compiler use global (and, for uniform
-// addresses, scalar) loads and stores.
-template <typename T>
-__device__ __forceinline__ const __attribute__((address_space(1))) T* gld(const T* p) {
-  return (const __attribute__((address_space(1))) T*)(p);
-}
-template <typename T>
-__device__ __forceinline__ __attribute__((address_space(1))) T* gst(T* p) {
-  return (__attribute__((address_space(1))) T*)(p);
-}
-
-// Complex values through global pointers, as two-component vectors.
-template <typename T>
-using vec2 = T __attribute__((ext_vector_type(2)));
-template <typename T>
-__device__ __forceinline__ cx<T> ld_cx(const cx<T>* p, long long i) {
-  const vec2<T> v = gld(reinterpret_cast<const vec2<T>*>(p))[i];
-  return cx<T>{v.x, v.y};
-}
-template <typename T>
-__device__ __forceinline__ void st_cx(cx<T>* p, long long i, cx<T> v) {
-  gst(reinterpret_cast<vec2<T>*>(p))[i] = vec2<T>{v.re, v.im};
-}
-template <typename T>
-using vec4 = T __attribute__((ext_vector_type(4)));
-template <typename T>
-__device__ __forceinline__ Quad<T> ld_quad(const void* p, long long i) {
-  const vec4<T> v = gld(reinterpret_cast<const vec4<T>*>(p))[i];
-  return Quad<T>{v.x, v.y, v.z, v.w};
-}
-
-// ---------------------------------------------------------------------------
-// Small DFTs, X_m = sum_r v_r exp(sign 2 pi i r m / R)
-// ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void dft2(cx<T>* v) {
-  const cx<T> a = v[0], b = v[1];
-  v[0] = a + b;
-  v[1] = a - b;
-}
-
-template <typename T>
-__device__ __forceinline__ void dft4(cx<T>* v, int sign) {
-  const cx<T> t0 = v[0] + v[2], t1 = v[0] - v[2], t2 = v[1] + v[3];
-  const cx<T> t3 = mul_si(v[1] - v[3], sign);
-  v[0] = t0 + t2;
-  v[2] = t0 - t2;
-  v[1] = t1 + t3;
-  v[3] = t1 - t3;
-}
-
-template <typename T>
-__device__ __forceinline__ void dft8(cx<T>* v, int sign) {
-  cx<T> e[4] = {v[0], v[2], v[4], v[6]};
-  cx<T> o[4] = {v[1], v[3], v[5], v[7]};
-  dft4(e, sign);
-  dft4(o, sign);
-  const T c = (T)0.70710678118654752440;
-  // w^k = exp(sign i pi k / 4)
-  const cx<T> o1 = cmul(o[1], cx<T>{c, sign * c});
-  const cx<T> o2 = mul_si(o[2], sign);
-  const cx<T> o3 = cmul(o[3], cx<T>{-c, sign * c});
-  v[0] = e[0] + o[0];
-  v[4] = e[0] - o[0];
-  v[1] = e[1] + o1;
-  v[5] = e[1] - o1;
-  v[2] = e[2] + o2;
-  v[6] = e[2] - o2;
-  v[3] = e[3] + o3;
-  v[7] = e[3] - o3;
-}
-
-// Odd radix R in {3,5,7}: pair r with R-r,
-//   X_m = v_0 + sum_{r=1}^{(R-1)/2} [(v_r + v_{R-r}) cos(2 pi r m/R)
-//                                  + sign i (v_r - v_{R-r}) sin(2 pi r m/R)].
-template <int R>
-struct OddRoots;
-template <>
-struct OddRoots<3> {
-  static constexpr double c[3] = {1.0, -0.5, -0.5};
-  static constexpr double s[3] = {0.0, 0.86602540378443864676, -0.86602540378443864676};
-};
-template <>
-struct OddRoots<5> {
-  static constexpr double c[5] = {1.0, 0.30901699437494742410, -0.80901699437494742410,
-                                  -0.80901699437494742410, 0.30901699437494742410};
-  static constexpr double s[5] = {0.0, 0.95105651629515357212, 0.58778525229247312917,
-                                  -0.58778525229247312917, -0.95105651629515357212};
-};
-template <>
-struct OddRoots<7> {
-  static constexpr double c[7] = {1.0,
-                                  0.62348980185873353053,
-                                  -0.22252093395631440429,
-                                  -0.90096886790241912624,
-                                  -0.90096886790241912624,
-                                  -0.22252093395631440429,
-                                  0.62348980185873353053};
-  static constexpr double s[7] = {0.0,
-                                  0.78183148246802980871,
-                                  0.97492791218182360702,
-                                  0.43388373911755812048,
-                                  -0.43388373911755812048,
-                                  -0.97492791218182360702,
-                                  -0.78183148246802980871};
-};
-
-template <typename T, int R>
-__device__ __forceinline__ void dft_odd(cx<T>* v, int sign) {
-  constexpr int H = (R - 1) / 2;
-  cx<T> a[H], b[H];
-  cx<T> x0 = v[0];
-#pragma unroll
-  for (int r = 1; r <= H; ++r) {
-    a[r - 1] = v[r] + v[R - r];
-    b[r - 1] = v[r] - v[R - r];
-    x0 = x0 + a[r - 1];
-  }
-  cx<T> out[R];
-  out[0] = x0;
-#pragma unroll
-  for (int m = 1; m < R; ++m) {
-    cx<T> acc = v[0];
-    cx<T> bs = {0, 0};
-#pragma unroll
-    for (int r = 1; r <= H; ++r) {
-      const int j = (r * m) % R;
-      const T cc = (T)OddRoots<R>::c[j], ss = (T)OddRoots<R>::s[j];
-      acc = acc + cscale(a[r - 1], cc);
-      bs = bs + cscale(b[r - 1], ss);
-    }
-    out[m] = acc + mul_si(bs, sign);
-  }
-#pragma unroll
-  for (int m = 0; m < R; ++m) v[m] = out[m];
-}
-
-template <typename T, int R>
-__device__ __forceinline__ void dft(cx<T>* v, int sign) {
-  if constexpr (R == 2) dft2(v);
-  else if constexpr (R == 4) dft4(v, sign);
-  else if constexpr (R == 8) dft8(v, sign);
-  else dft_odd<T, R>(v, sign);
-}
 
 // A coordinate of direction d folded into the grid: periodic directions wrap
 // (any number of periods), free directions report points outside [0, G).
@@ -217,360 +31,6 @@ __device__ __forceinline__ int wrap_coord(const GridGeom& g, int d, int c, bool*
   return c;
 }
 
-// Quotient of small non-negative integers a < 2^21 by d, given inv_d = 1/d in
-// FP32: (a + 1/2)/d lies at least 1/(2d) from an integer, which exceeds the
-// rounding error of the product, so truncation gives floor(a/d) exactly.
-__device__ __forceinline__ int fdiv(int a, float inv_d) { return (int)(((float)a + 0.5f) * inv_d); }
-
-// Work item of workgroup b out of n.  Workgroups are handed to the 8 XCDs in
-// turn (b mod 8), so neighbouring items, which share cache lines at their
-// edges, land in different L2s.  Mode 1 gives each XCD one contiguous range of
-// items; mode c >= 2 gives each XCD chunks of c neighbouring items while the
-// XCDs work side by side (rounds of 8c items; the last partial round keeps the
-// plain order).  Both are bijections of [0, n); mode 0 is the plain order.
-constexpr int kXcds = 8;
-__device__ __forceinline__ int xcd_item(int b, int n, int mode) {
-  const int x = b % kXcds, s = b / kXcds;
-  if (mode == 1) {
-    const int q = n / kXcds, r = n % kXcds;
-    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + s;
-  }
-  const int c = mode, round = kXcds * c;
-  if (b >= (n / round) * round) return b;
-  return ((s / c) * kXcds + x) * c + s % c;
-}
-__device__ __forceinline__ int work_item(int mode) {
-  return mode > 0 ? xcd_item(blockIdx.x, gridDim.x, mode) : blockIdx.x;
-}
-
-// One Stockham stage from src to dst (LDS) over B = 2^lgB interleaved pencils
-// stored sample-major with pitch Bp (sample t of pencil p at t*Bp + p):
-//   inputs  j + r n/R   (j = 0..n/R-1), twiddle exp(sign 2 pi i r k/(Ns R)) with k = j mod Ns,
-//   outputs (j/Ns) Ns R + k + r Ns.
-// One butterfly per loop trip keeps the register footprint to one radix.
-template <typename T, int R>
-__device__ __forceinline__ void fft_stage(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst,
-                                          const cx<T>* __restrict__ tw, int n, int Ns, int lgB, int Bp,
-                                          int sign) {
-  const int nb = n / R;
-  const int total = nb << lgB;
-  const int mask = (1 << lgB) - 1;
-  const int tws = n / (Ns * R);
-  const float inv_ns = 1.0f / (float)Ns;
-  for (int e = threadIdx.x; e < total; e += kFftBlock) {
-    const int j = e >> lgB, p = e & mask;
-    const int jq = fdiv(j, inv_ns), k = j - jq * Ns;
-    cx<T> v[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = src[(j + r * nb) * Bp + p];
-    if (Ns > 1) {
-#pragma unroll
-      for (int r = 1; r < R; ++r) {
-        cx<T> w = tw[r * k * tws];  // r k tws < R Ns tws = n
-        if (sign > 0) w.im = -w.im;
-        v[r] = cmul(v[r], w);
-      }
-    }
-    dft<T, R>(v, sign);
-    const int base = jq * Ns * R + k;
-#pragma unroll
-    for (int r = 0; r < R; ++r) dst[(base + r * Ns) * Bp + p] = v[r];
-  }
-}
-
-// Runs all stages of class C, alternating between the two buffers; returns
-// the buffer holding the result.
-template <typename T>
-__device__ __forceinline__ cx<T>* fft_run(cx<T>* b0, cx<T>* b1, const cx<T>* tw, const FftClass& C, int lgB,
-                                          int Bp, int sign) {
-  cx<T>* src = b0;
-  cx<T>* dst = b1;
-  int Ns = 1;
-  const int n = C.n, nst = C.nst;
-  unsigned long long radices = C.radpack;   // 4 bits per stage, first stage lowest
-  for (int s = 0; s < nst; ++s) {
-    const int R = (int)(radices & 15u);
-    radices >>= 4;
-    switch (R) {
-      case 2: fft_stage<T, 2>(src, dst, tw, n, Ns, lgB, Bp, sign); break;
-      case 3: fft_stage<T, 3>(src, dst, tw, n, Ns, lgB, Bp, sign); break;
-      case 4: fft_stage<T, 4>(src, dst, tw, n, Ns, lgB, Bp, sign); break;
-      case 5: fft_stage<T, 5>(src, dst, tw, n, Ns, lgB, Bp, sign); break;
-      case 7: fft_stage<T, 7>(src, dst, tw, n, Ns, lgB, Bp, sign); break;
-      default: fft_stage<T, 8>(src, dst, tw, n, Ns, lgB, Bp, sign); break;
-    }
-    __syncthreads();
-    cx<T>* tmp = src;
-    src = dst;
-    dst = tmp;
-    Ns *= R;
-  }
-  return src;
-}
-
-__device__ __forceinline__ int fold_index(int i, int n) { return i <= n - i ? i : n - i; }
-
-// The factors of Eq. (scale) that depend only on the pencil (b0, b1): the
-// separable vectors of the two pencil directions and the pencil's part of the
-// table or |k|^2 index.
-template <typename T>
-struct ScaleRow {
-  T s;          // sA[b0] sB[b1]
-  T k2;         // kA[b0] + kB[b1]            (G_INVSQ)
-  long long g;  // table offset of the pencil (G_TAB2, G_TAB3)
-};
-
-template <typename T>
-__device__ __forceinline__ ScaleRow<T> scale_row(const FftClass& C, int b0, int b1) {
-  ScaleRow<T> r;
-  r.s = gld((const T*)C.sA)[b0 + C.offA] * gld((const T*)C.sB)[b1 + C.offB];
-  r.k2 = 0;
-  r.g = 0;
-  const int i0 = C.fold0 ? fold_index(b0, C.fold0) : b0;
-  if (C.gmode == G_INVSQ) r.k2 = gld((const T*)C.kA)[b0 + C.offA] + gld((const T*)C.kB)[b1 + C.offB];
-  else if (C.gmode == G_TAB2) r.g = i0;
-  else if (C.gmode == G_TAB3) r.g = (long long)fold_index(b1, C.fold1) * C.gd0 + i0;
-  return r;
-}
-
-// Tables store the pencil index b0 fastest, so neighbouring lanes (neighbouring
-// pencils) read neighbouring entries: G_TAB2 [t][b0], G_TAB3 [t][b1][b0].
-template <typename T>
-__device__ __forceinline__ T scale_at(const FftClass& C, const ScaleRow<T>& r, int t) {
-  const T s = r.s * gld((const T*)C.sC)[t];
-  const auto gt = gld((const T*)C.gtab);
-  switch (C.gmode) {
-    case G_INVSQ: {
-      const T k2 = r.k2 + gld((const T*)C.kC)[t];
-      return k2 > (T)0 ? s / k2 : (T)0;
-    }
-    case G_TAB1:
-      return s * gt[t];
-    case G_TAB2:
-      return s * gt[(long long)fold_index(t, C.fold2) * C.gd0 + r.g];
-    case G_TAB3:
-      return s * gt[(long long)fold_index(t, C.fold2) * C.gd1 * C.gd0 + r.g];
-    default:
-      return s;
-  }
-}
-
-// Sample (t, p) of load/store slot e: pencil-major when the transform
-// direction is contiguous in memory (consecutive lanes walk one pencil),
-// sample-major otherwise (consecutive lanes walk neighbouring pencils).
-__device__ __forceinline__ void slot_tp(int e, bool t_fast, int n, float inv_n, int lgB, int* t, int* p) {
-  if (t_fast) {
-    *p = fdiv(e, inv_n);
-    *t = e - *p * n;
-  } else {
-    *t = e >> lgB;
-    *p = e & ((1 << lgB) - 1);
-  }
-}
-
-// A real pencil pair (a, b) shares one complex transform z = a + i b.  Forward:
-// A_k = (Z_k + conj Z_{n-k})/2 and B_k = (Z_k - conj Z_{n-k})/(2i).  Inverse:
-// the half spectra of a and b, Hermitian-extended, combine to Z = A + i B, whose
-// transform holds a in the real and b in the imaginary part.
-template <typename T>
-__device__ __forceinline__ cx<T> split_pair(cx<T> z, cx<T> zn, int odd) {
-  return odd ? cx<T>{(T)0.5 * (z.im + zn.im), (T)0.5 * (zn.re - z.re)}
-             : cx<T>{(T)0.5 * (z.re + zn.re), (T)0.5 * (z.im - zn.im)};
-}
-
-template <typename T, int KIND>
-__device__ __forceinline__ void stage_fft(const FftPass& P, int item, unsigned char* smem) {
-  constexpr int U = 8;  // global accesses in flight per thread
-  constexpr bool REAL = (KIND == K_R2C || KIND == K_C2R);
-  // the work item {class, b0 start, b1, count}, the same for the whole workgroup
-  const auto itp = gld(reinterpret_cast<const int*>(P.items)) + 4 * item;
-  const int cls = __builtin_amdgcn_readfirstlane(itp[0]), b0s = __builtin_amdgcn_readfirstlane(itp[1]),
-            b1 = __builtin_amdgcn_readfirstlane(itp[2]), cnt = __builtin_amdgcn_readfirstlane(itp[3]);
-  const FftClass& C = P.cls[cls];
-  const int n = C.n, lgB = P.lgB;
-  // real passes with B >= 2 run B/2 complex transforms of pencil pairs
-  const int pair = (REAL && lgB > 0) ? 1 : 0;
-  const int lgF = lgB - pair, Bp = (1 << lgF) + 1;
-  cx<T>* tw = reinterpret_cast<cx<T>*>(smem);
-  cx<T>* buf = tw + P.nmax;
-  cx<T>* buf2 = buf + (size_t)P.nmax * ((1 << lgB) + 1);
-
-  // twiddles exp(-2 pi i k/n), evaluated in FP64 and rounded once; computed
-  // while the first round of pencil loads is in flight
-  auto make_twiddles = [&]() {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      double sn, cs;
-      sincospi(-2.0 * (double)i / (double)n, &sn, &cs);
-      tw[i] = cx<T>{(T)cs, (T)sn};
-    }
-  };
-
-  // ---- load the pencils, zero padded to n ----
-  const bool t_fast = (C.in_st == 1);
-  const float inv_n = 1.0f / (float)n;
-  const long long bs1 = (long long)b1 * C.in_s1;
-  if constexpr (KIND == K_C2R) {
-    // slots (t, complex pencil c) of pencils 2c and 2c+1 (or c alone unpaired)
-    const int total = n << lgF;
-    const int h = n >> 1;
-    for (int e0 = 0; e0 < total; e0 += U * kFftBlock) {
-      cx<T> v[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int e = e0 + u * kFftBlock + threadIdx.x;
-        int t, c;
-        slot_tp(e, t_fast, n, inv_n, lgF, &t, &c);
-        v[u] = cx<T>{0, 0};
-        const int ts = t <= h ? t : n - t;
-        const T sg = t <= h ? (T)1 : (T)-1;   // Hermitian extension of the stored half
-        const int pa = c << pair;
-        if (e < total && pa < cnt) {
-          const cx<T>* in = reinterpret_cast<const cx<T>*>(C.in);
-          const cx<T> a = ld_cx(in, (long long)(b0s + pa) * C.in_s0 + bs1 + (long long)ts * C.in_st);
-          v[u] = cx<T>{a.re, sg * a.im};
-          if (pair && pa + 1 < cnt) {
-            const cx<T> bb = ld_cx(in, (long long)(b0s + pa + 1) * C.in_s0 + bs1 + (long long)ts * C.in_st);
-            v[u].re -= sg * bb.im;
-            v[u].im += bb.re;
-          }
-        }
-      }
-      if (e0 == 0) make_twiddles();
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int e = e0 + u * kFftBlock + threadIdx.x;
-        if (e < total) {
-          int t, c;
-          slot_tp(e, t_fast, n, inv_n, lgF, &t, &c);
-          buf[t * Bp + c] = v[u];
-        }
-      }
-    }
-  } else {
-    // slots (t, pencil p); a real pass packs pencil p into component p & 1
-    const int total = n << lgB;
-    if (pair) {
-      for (int e = threadIdx.x; e < (n << lgF); e += blockDim.x) {
-        const int t = e >> lgF, c = e & ((1 << lgF) - 1);
-        buf[t * Bp + c] = cx<T>{0, 0};
-      }
-      __syncthreads();
-    }
-    for (int e0 = 0; e0 < total; e0 += U * kFftBlock) {
-      cx<T> v[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int e = e0 + u * kFftBlock + threadIdx.x;
-        int t, p;
-        slot_tp(e, t_fast, n, inv_n, lgB, &t, &p);
-        v[u] = cx<T>{0, 0};
-        if (e < total && p < cnt && t < C.n_in) {
-          const long long idx = (long long)(b0s + p) * C.in_s0 + bs1 + (long long)t * C.in_st;
-          if constexpr (KIND == K_R2C) v[u].re = gld(reinterpret_cast<const T*>(C.in))[idx];
-          else v[u] = ld_cx(reinterpret_cast<const cx<T>*>(C.in), idx);
-        }
-      }
-      if (e0 == 0) make_twiddles();
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int e = e0 + u * kFftBlock + threadIdx.x;
-        if (e < total) {
-          int t, p;
-          slot_tp(e, t_fast, n, inv_n, lgB, &t, &p);
-          if (pair) {
-            T* cell = reinterpret_cast<T*>(&buf[t * Bp + (p >> 1)]);
-            cell[p & 1] = v[u].re;
-          } else {
-            buf[t * Bp + p] = v[u];
-          }
-        }
-      }
-    }
-  }
-  __syncthreads();
-
-  cx<T>* res;
-  if constexpr (KIND == K_C2C_INV || KIND == K_C2R) {
-    res = fft_run<T>(buf, buf2, tw, C, lgF, Bp, +1);
-  } else {
-    res = fft_run<T>(buf, buf2, tw, C, lgF, Bp, -1);
-  }
-
-  if constexpr (KIND == K_FUSED) {
-    // scaling step, Eq. (scale), on the spectrum of each pencil; the block
-    // size is a multiple of B, so each thread keeps one pencil p throughout
-    const int mask = (1 << lgB) - 1;
-    const int total = n << lgB;
-    const int p = threadIdx.x & mask;
-    if (p < cnt) {
-      const ScaleRow<T> row = scale_row<T>(C, b0s + p, b1);
-      for (int e = threadIdx.x; e < total; e += blockDim.x) {
-        const int t = e >> lgB;
-        res[t * Bp + p] = cscale(res[t * Bp + p], scale_at<T>(C, row, t));
-      }
-    }
-    __syncthreads();
-    res = fft_run<T>(res, res == buf ? buf2 : buf, tw, C, lgB, Bp, +1);
-  }
-
-  // ---- store the first n_out samples (stores do not stall the thread) ----
-  const bool to_fast = (C.out_st == 1);
-  const int nout = C.n_out;
-  const float inv_no = 1.0f / (float)nout;
-  const int totout = nout << lgB;
-  const long long os1 = (long long)b1 * C.out_s1;
-  for (int e = threadIdx.x; e < totout; e += kFftBlock) {
-    int t, p;
-    slot_tp(e, to_fast, nout, inv_no, lgB, &t, &p);
-    if (p >= cnt) continue;
-    const long long idx = (long long)(b0s + p) * C.out_s0 + os1 + (long long)t * C.out_st;
-    if constexpr (KIND == K_C2R) {
-      const cx<T> v = res[t * Bp + (p >> pair)];
-      gst(reinterpret_cast<T*>(C.out))[idx] = (pair && (p & 1)) ? v.im : v.re;
-    } else if constexpr (KIND == K_R2C) {
-      cx<T> v;
-      if (pair) {
-        const int tn = t == 0 ? 0 : n - t;
-        v = split_pair(res[t * Bp + (p >> 1)], res[tn * Bp + (p >> 1)], p & 1);
-      } else {
-        v = res[t * Bp + p];
-      }
-      st_cx(reinterpret_cast<cx<T>*>(C.out), idx, v);
-    } else {
-      st_cx(reinterpret_cast<cx<T>*>(C.out), idx, res[t * Bp + p]);
-    }
-  }
-}
-
-template <typename T, int KIND>
-__global__ __launch_bounds__(kFftBlock) void fft_kernel(const FftPass P) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  stage_fft<T, KIND>(P, work_item(P.xcd), smem);
-}
-
-size_t fft_lds_bytes(const FftPass& p, bool f64) {
-  const size_t c = f64 ? 16 : 8;
-  return c * ((size_t)p.nmax + 2 * (((size_t)1 << p.lgB) + 1) * p.nmax);
-}
-
-template <typename T>
-static hipError_t launch_fft_t(const FftPass& p, hipStream_t st) {
-  if (p.nitems <= 0) return hipSuccess;
-  const size_t lds = fft_lds_bytes(p, sizeof(T) == 8);
-  const dim3 grid(p.nitems), block(kFftBlock);
-  switch (p.kind) {
-    case K_C2C_FWD: fft_kernel<T, K_C2C_FWD><<<grid, block, lds, st>>>(p); break;
-    case K_C2C_INV: fft_kernel<T, K_C2C_INV><<<grid, block, lds, st>>>(p); break;
-    case K_R2C: fft_kernel<T, K_R2C><<<grid, block, lds, st>>>(p); break;
-    case K_C2R: fft_kernel<T, K_C2R><<<grid, block, lds, st>>>(p); break;
-    default: fft_kernel<T, K_FUSED><<<grid, block, lds, st>>>(p); break;
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_fft(const FftPass& p, bool f64, hipStream_t st) {
-  return f64 ? launch_fft_t<double>(p, st) : launch_fft_t<float>(p, st);
-}
 
 // ---------------------------------------------------------------------------
 // Binning: grid cell, fractional offset and sub-bin of every particle.  The
@@ -1947,16 +1407,8 @@ __device__ __forceinline__ void run_batch_stage(int st, const SysDesc& S, int sy
     case BS_ENERGY:
       stage_energy(S.b.epart, S.ntiles, io.energy ? io.energy + sys_id : nullptr);
       break;
-    default: {
-      const FftPass& ps = S.pass[st - BS_FFT0];
-      switch (ps.kind) {
-        case K_C2C_FWD: stage_fft<T, K_C2C_FWD>(ps, li, smem); break;
-        case K_C2C_INV: stage_fft<T, K_C2C_INV>(ps, li, smem); break;
-        case K_R2C: stage_fft<T, K_R2C>(ps, li, smem); break;
-        case K_C2R: stage_fft<T, K_C2R>(ps, li, smem); break;
-        default: stage_fft<T, K_FUSED>(ps, li, smem); break;
-      }
-    }
+    default:
+      break;
   }
 }
 
@@ -1981,38 +1433,17 @@ __global__ __launch_bounds__(kBlock) void batch_stage_kernel(const SysDesc* __re
   run_batch_stage<T, P>(ST, sys[lo], lo, item - o[lo], io, smem);
 }
 
-// One transform kind of one transform stage of the batch.
-template <typename T, int KIND>
-__global__ __launch_bounds__(kFftBlock) void batch_fft_kernel(const SysDesc* __restrict__ sys, int nsys,
-                                                              const int* __restrict__ o, int pass, int xcd) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int item = work_item(xcd);
-  int lo = 0, hi = nsys - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (o[mid] <= item) lo = mid;
-    else hi = mid - 1;
-  }
-  lo = __builtin_amdgcn_readfirstlane(lo);  // uniform: keeps the descriptor in scalar registers
-  stage_fft<T, KIND>(sys[lo].pass[pass], item - o[lo], smem);
-}
-
 template <typename T, int P, int ST>
 static void batch_launch_one(const SysDesc* sys, int nsys, const int* off, const int* items, const BatchIO& io,
                              const size_t* lds, hipStream_t st, hipEvent_t* ev) {
   if (ev) (void)hipEventRecord(ev[ST], st);
   if constexpr (ST >= BS_FFT0 && ST <= BS_FFT4) {
     const int pass = ST - BS_FFT0;
-#define SE_FFT_KIND(K)                                                                                    \
-  if (items[fft_list(ST, K)] > 0)                                                                        \
-    batch_fft_kernel<T, K><<<dim3(items[fft_list(ST, K)]), dim3(kFftBlock), lds[ST], st>>>(              \
-        sys, nsys, off + fft_list(ST, K) * (nsys + 1), pass, io.xcd_fft);
-    SE_FFT_KIND(K_C2C_FWD)
-    SE_FFT_KIND(K_C2C_INV)
-    SE_FFT_KIND(K_R2C)
-    SE_FFT_KIND(K_C2R)
-    SE_FFT_KIND(K_FUSED)
-#undef SE_FFT_KIND
+    const bool wide = (io.fft_wide >> pass) & 1;
+    for (int k = 0; k < kFftKinds; ++k)
+      if (items[fft_list(ST, k)] > 0)
+        launch_batch_fft(sizeof(T) == 8, k, wide, sys, nsys, off + fft_list(ST, k) * (nsys + 1), pass,
+                         items[fft_list(ST, k)], lds[ST], io.xcd_fft, st);
   } else {
     if (items[ST] > 0)
       batch_stage_kernel<T, P, ST><<<dim3(items[ST]), dim3(kBlock), lds[ST], st>>>(

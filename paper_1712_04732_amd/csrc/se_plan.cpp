@@ -219,7 +219,26 @@ struct se_plan {
     return e == hipSuccess ? d : nullptr;
   }
 
-  // Twiddles exp(-2 pi i k/n), k = 0..n-1, interleaved complex.
+  // Twiddles exp(-2 pi i k/n), k = 0..n-1, interleaved complex, evaluated in
+  // extended precision and rounded once to the compute precision; one table
+  // per (length, precision), shared by the passes of the plan.
+  std::vector<std::pair<long, const void*>> twc;
+  const void* twiddles(int n) {
+    const long key = 2L * n + (f64 ? 1 : 0);
+    for (const auto& e : twc)
+      if (e.first == key) return e.second;
+    std::vector<double> w(2 * (size_t)n);
+    const long double two_pi = 6.283185307179586476925286766559L;
+    for (int k = 0; k < n; ++k) {
+      const long double a = two_pi * (long double)k / (long double)n;
+      w[2 * k] = (double)cosl(a);
+      w[2 * k + 1] = (double)-sinl(a);
+    }
+    const void* d = upload(w);
+    if (d) twc.emplace_back(key, d);
+    return d;
+  }
+
   // Scaling vector of a direction transformed at length n over spacing h:
   //   e^{-k^2/4xi^2} / What(k)^2 / n   with k = 2 pi m/(n h), m the signed frequency.
   // The 1/n is the inverse transform's normalisation.
@@ -298,6 +317,16 @@ static bool finish_pass(se_plan* pl, se::FftPass& ps, int kind, int ncls,
   if (lds_of(1L << lgB) > pl->lds_max) return false;
   ps.lgB = lgB;
   ps.B = 1 << lgB;
+  // twiddle tables; 64-bit offsets if the B pencils of a workgroup span 4 GiB
+  ps.wide = 0;
+  for (int c = 0; c < ncls; ++c) {
+    se::FftClass& k = ps.cls[c];
+    k.tw = pl->twiddles(k.n);
+    if (!k.tw) return false;
+    const long double span_in = ((long double)ps.B * k.in_s0 + (long double)k.n * k.in_st) * esz;
+    const long double span_out = ((long double)ps.B * k.out_s0 + (long double)k.n * k.out_st) * esz;
+    if (std::max(span_in, span_out) >= 4294967296.0L) ps.wide = 1;
+  }
   ps.xcd = xcd_mode(pl->p.xcd_fft);
   std::vector<int4> items;
   for (const auto& r : ranges) add_items(items, r[0], r[1], r[2], r[3], r[4], ps.B);
@@ -1409,6 +1438,9 @@ se_status se_eval_batch(se_batch_plan* plan, const void* xyz, const void* q, voi
   io.allow_nonneutral = (flags & SE_ALLOW_NONNEUTRAL) ? 1 : 0;
   io.xcd_tiles = xcd_mode(plan->sys[0]->p.xcd_tiles);
   io.xcd_fft = xcd_mode(plan->sys[0]->p.xcd_fft);
+  for (const se_plan* sp : plan->sys)
+    for (int k = 0; k < se::kPasses; ++k)
+      if (sp->passes[k].wide) io.fft_wide |= 1 << k;
   const bool prof = (flags & SE_PROFILE) != 0;
   if (prof && !plan->have_ev) {
     for (hipEvent_t& e : plan->ev)

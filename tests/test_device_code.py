@@ -20,13 +20,16 @@ sys.path.insert(0, os.path.join(ROOT, "paper_1712_04732_amd"))
 @pytest.fixture(scope="module")
 def device_asm(tmp_path_factory):
     import build_lib as b
-    out = tmp_path_factory.mktemp("asm") / "se_kernels.s"
-    cmd = [b.HIPCC, *[f for f in b.FLAGS if f != "-fPIC"], "--cuda-device-only", "-S", "-x", "hip",
-           os.path.join(b.CSRC, "se_kernels.hip"), "-o", str(out)]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        pytest.skip("hipcc unavailable: " + r.stderr[-300:])
-    return out.read_text()
+    text = []
+    for src in (f for f in b.SOURCES if f.endswith(".hip")):
+        out = tmp_path_factory.mktemp("asm") / (src + ".s")
+        cmd = [b.HIPCC, *[f for f in b.FLAGS if f != "-fPIC"], "--cuda-device-only", "-S", "-x", "hip",
+               os.path.join(b.CSRC, src), "-o", str(out)]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            pytest.skip("hipcc unavailable: " + r.stderr[-300:])
+        text.append(out.read_text())
+    return "\n".join(text)
 
 
 def test_no_indexed_register_access(device_asm):

@@ -2,7 +2,7 @@
 // of Shamshirgar, Bagge, Tornberg, arXiv:1712.04732).
 //
 // One workgroup transforms B pencils of one length-n class at once: it loads
-// them into LDS (zero padding up to n), runs mixed-radix (2,3,4,5,7,8)
+// them into LDS (zero padding up to n), runs mixed-radix (2,3,4,5,7,8,16)
 // Stockham stages between two LDS buffers, and stores the first n_out samples
 // (truncation).  Real-to-complex and complex-to-real passes transform two real
 // pencils as the real and imaginary parts of one complex pencil.  The fused
@@ -57,6 +57,63 @@ __device__ __forceinline__ void dft8(cx<T>* v, int sign) {
   v[6] = e[2] - o2;
   v[3] = e[3] + o3;
   v[7] = e[3] - o3;
+}
+
+// x exp(sign 2 pi i e/16) for a compile-time e in [0, 16).
+template <typename T, int E>
+__device__ __forceinline__ cx<T> rot16(cx<T> x, int sign) {
+  constexpr double c16[5] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173, 0.0};
+  if constexpr (E == 0) {
+    return x;
+  } else if constexpr (E == 4) {
+    return mul_si(x, sign);
+  } else if constexpr (E == 8) {
+    return cx<T>{-x.re, -x.im};
+  } else if constexpr (E == 12) {
+    return mul_si(x, -sign);
+  } else if constexpr (E == 2 || E == 6 || E == 10 || E == 14) {
+    // exp(sign i pi e/8) = (cr + sign i ci) / sqrt(2), cr, ci = +-1
+    constexpr T h = (T)0.70710678118654752440;
+    constexpr int cr = (E == 2 || E == 14) ? 1 : -1, ci = (E == 2 || E == 6) ? 1 : -1;
+    const T a = cr * x.re, b = cr * x.im, c = ci * x.re, d = ci * x.im;
+    // (x.re + i x.im)(cr + sign i ci) = (x.re cr - sign ci x.im) + i (x.im cr + sign ci x.re)
+    return sign > 0 ? cx<T>{h * (a - d), h * (b + c)} : cx<T>{h * (a + d), h * (b - c)};
+  } else {
+    // cos and sin of pi e/8 from the first-quadrant table
+    constexpr int q = E / 4, r = E % 4;
+    constexpr double cq = q == 0 ? c16[r] : (q == 1 ? -c16[4 - r] : (q == 2 ? -c16[r] : c16[4 - r]));
+    constexpr double sq = q == 0 ? c16[4 - r] : (q == 1 ? c16[r] : (q == 2 ? -c16[4 - r] : -c16[r]));
+    return cmul(x, cx<T>{(T)cq, (T)(sign * sq)});
+  }
+}
+
+// 16 = 4 x 4: X[k1 + 4 k2] = sum_q W16^(q k1) W4^(q k2) sum_m v[q + 4 m] W4^(m k1).
+template <typename T>
+__device__ __forceinline__ void dft16(cx<T>* v, int sign) {
+  cx<T> a[4][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    cx<T> t[4] = {v[q], v[q + 4], v[q + 8], v[q + 12]};
+    dft4(t, sign);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a[q][k] = t[k];
+  }
+  a[1][1] = rot16<T, 1>(a[1][1], sign);
+  a[1][2] = rot16<T, 2>(a[1][2], sign);
+  a[1][3] = rot16<T, 3>(a[1][3], sign);
+  a[2][1] = rot16<T, 2>(a[2][1], sign);
+  a[2][2] = rot16<T, 4>(a[2][2], sign);
+  a[2][3] = rot16<T, 6>(a[2][3], sign);
+  a[3][1] = rot16<T, 3>(a[3][1], sign);
+  a[3][2] = rot16<T, 6>(a[3][2], sign);
+  a[3][3] = rot16<T, 9>(a[3][3], sign);
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    cx<T> t[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+    dft4(t, sign);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+  }
 }
 
 // Odd radix R in {3,5,7}: pair r with R-r,
@@ -129,6 +186,7 @@ __device__ __forceinline__ void dft(cx<T>* v, int sign) {
   if constexpr (R == 2) dft2(v);
   else if constexpr (R == 4) dft4(v, sign);
   else if constexpr (R == 8) dft8(v, sign);
+  else if constexpr (R == 16) dft16(v, sign);
   else dft_odd<T, R>(v, sign);
 }
 
@@ -214,11 +272,13 @@ __device__ __forceinline__ void fft_stage_r(int R, const lds<vec2<T>>* src, lds<
     case 4: fft_stage<T, 4, FIRST, SIGN>(src, dst, tw, n, Ns, tws, lgB, Bp); break;
     case 5: fft_stage<T, 5, FIRST, SIGN>(src, dst, tw, n, Ns, tws, lgB, Bp); break;
     case 7: fft_stage<T, 7, FIRST, SIGN>(src, dst, tw, n, Ns, tws, lgB, Bp); break;
-    default: fft_stage<T, 8, FIRST, SIGN>(src, dst, tw, n, Ns, tws, lgB, Bp); break;
+    case 8: fft_stage<T, 8, FIRST, SIGN>(src, dst, tw, n, Ns, tws, lgB, Bp); break;
+    default: fft_stage<T, 16, FIRST, SIGN>(src, dst, tw, n, Ns, tws, lgB, Bp); break;
   }
 }
 
-// All stages of class C (radices packed 4 bits per stage, first stage lowest),
+// All stages of class C (radices packed 4 bits per stage, first stage lowest,
+// radix 16 as 0),
 // alternating between the two buffers; returns the buffer holding the result.
 template <typename T, int SIGN>
 __device__ __forceinline__ lds<vec2<T>>* fft_run(lds<vec2<T>>* b0, lds<vec2<T>>* b1, const lds<vec2<T>>* tw,
@@ -229,7 +289,8 @@ __device__ __forceinline__ lds<vec2<T>>* fft_run(lds<vec2<T>>* b0, lds<vec2<T>>*
   unsigned long long radices = C.radpack;
   int Ns = 1, rem = n;   // rem = n / Ns
   for (int s = 0; s < nst; ++s) {
-    const int R = (int)(radices & 15u);
+    const int code = (int)(radices & 15u);   // radix 16 is stored as 0
+    const int R = code == 0 ? 16 : code;
     radices >>= 4;
     const int tws = rem / R;
     if (s == 0) fft_stage_r<T, true, SIGN>(R, src, dst, tw, n, Ns, tws, lgB, Bp);
@@ -500,12 +561,11 @@ __device__ __forceinline__ void fft_store(const FftClass& C, int b0s, int b1, in
   }
 }
 
+// One work item: pencils b0s .. b0s + cnt - 1 at b1 of class cls of pass P.
 template <typename T, int KIND, typename OFF>
-__device__ __forceinline__ void stage_fft(const FftPass& P, int item, lds<unsigned char>* smem) {
+__device__ __forceinline__ void stage_fft(const FftPass& P, int cls, int b0s, int b1, int cnt,
+                                          lds<unsigned char>* smem) {
   constexpr bool REAL = (KIND == K_R2C || KIND == K_C2R);
-  // the work item {class, b0 start, b1, count}, the same for the whole workgroup
-  const auto itp = gld(reinterpret_cast<const int*>(P.items)) + 4 * item;
-  const int cls = rfl(itp[0]), b0s = rfl(itp[1]), b1 = rfl(itp[2]), cnt = rfl(itp[3]);
   const FftClass& C = P.cls[cls];
   const int n = C.n, lgB = P.lgB;
   // real passes with B >= 2 run B/2 complex transforms of pencil pairs
@@ -541,27 +601,29 @@ __device__ __forceinline__ void stage_fft(const FftPass& P, int item, lds<unsign
   else fft_store<T, KIND, false, OFF>(C, b0s, b1, cnt, lgB, pair, Bp, res);
 }
 
+// The work record {class, b0 start, b1, count}, the same for the whole
+// workgroup (scalar loads).
+__device__ __forceinline__ int4 work_record(const int4* rec, int item) {
+  const auto p = gld(reinterpret_cast<const int*>(rec)) + 4 * item;
+  return make_int4(rfl(p[0]), rfl(p[1]), rfl(p[2]), rfl(p[3]));
+}
+
 template <typename T, int KIND, typename OFF>
 __global__ __launch_bounds__(kFftBlock) void fft_kernel(const FftPass P) {
   extern __shared__ __align__(16) unsigned char smem[];
-  stage_fft<T, KIND, OFF>(P, work_item(P.xcd), (lds<unsigned char>*)smem);
+  const int4 r = work_record(P.items, work_item(P.xcd));
+  stage_fft<T, KIND, OFF>(P, r.x, r.y, r.z, r.w, (lds<unsigned char>*)smem);
 }
 
-// One transform kind of one transform stage of a batch: block b is work item b
-// of the (stage, kind) list, counted over the systems in order.
+// One transform kind of one transform stage of a batch: block b takes record
+// b of the (stage, kind) list, {system * 4 + class, b0 start, b1, count}, so a
+// workgroup finds its system and pencils with one scalar load.
 template <typename T, int KIND, typename OFF>
-__global__ __launch_bounds__(kFftBlock) void batch_fft_kernel(const SysDesc* __restrict__ sys, int nsys,
-                                                              const int* __restrict__ o, int pass, int xcd) {
+__global__ __launch_bounds__(kFftBlock) void batch_fft_kernel(const SysDesc* __restrict__ sys,
+                                                              const int4* __restrict__ rec, int pass, int xcd) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int item = work_item(xcd);
-  int lo = 0, hi = nsys - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (o[mid] <= item) lo = mid;
-    else hi = mid - 1;
-  }
-  lo = rfl(lo);  // uniform: keeps the descriptor in scalar registers
-  stage_fft<T, KIND, OFF>(sys[lo].pass[pass], item - o[lo], (lds<unsigned char>*)smem);
+  const int4 r = work_record(rec, work_item(xcd));
+  stage_fft<T, KIND, OFF>(sys[r.x >> 2].pass[pass], r.x & 3, r.y, r.z, r.w, (lds<unsigned char>*)smem);
 }
 
 size_t fft_lds_bytes(const FftPass& p, bool f64) {
@@ -591,26 +653,26 @@ hipError_t launch_fft(const FftPass& p, bool f64, hipStream_t st) {
 }
 
 template <typename T, typename OFF>
-static void launch_batch_fft_t(int kind, const SysDesc* sys, int nsys, const int* o, int pass, int nitems,
-                               size_t lds, int xcd, hipStream_t st) {
+static void launch_batch_fft_t(int kind, const SysDesc* sys, const int4* rec, int pass, int nitems, size_t lds,
+                               int xcd, hipStream_t st) {
   const dim3 grid(nitems), block(kFftBlock);
   switch (kind) {
-    case K_C2C_FWD: batch_fft_kernel<T, K_C2C_FWD, OFF><<<grid, block, lds, st>>>(sys, nsys, o, pass, xcd); break;
-    case K_C2C_INV: batch_fft_kernel<T, K_C2C_INV, OFF><<<grid, block, lds, st>>>(sys, nsys, o, pass, xcd); break;
-    case K_R2C: batch_fft_kernel<T, K_R2C, OFF><<<grid, block, lds, st>>>(sys, nsys, o, pass, xcd); break;
-    case K_C2R: batch_fft_kernel<T, K_C2R, OFF><<<grid, block, lds, st>>>(sys, nsys, o, pass, xcd); break;
-    default: batch_fft_kernel<T, K_FUSED, OFF><<<grid, block, lds, st>>>(sys, nsys, o, pass, xcd); break;
+    case K_C2C_FWD: batch_fft_kernel<T, K_C2C_FWD, OFF><<<grid, block, lds, st>>>(sys, rec, pass, xcd); break;
+    case K_C2C_INV: batch_fft_kernel<T, K_C2C_INV, OFF><<<grid, block, lds, st>>>(sys, rec, pass, xcd); break;
+    case K_R2C: batch_fft_kernel<T, K_R2C, OFF><<<grid, block, lds, st>>>(sys, rec, pass, xcd); break;
+    case K_C2R: batch_fft_kernel<T, K_C2R, OFF><<<grid, block, lds, st>>>(sys, rec, pass, xcd); break;
+    default: batch_fft_kernel<T, K_FUSED, OFF><<<grid, block, lds, st>>>(sys, rec, pass, xcd); break;
   }
 }
 
-void launch_batch_fft(bool f64, int kind, bool wide, const SysDesc* sys, int nsys, const int* o, int pass,
-                      int nitems, size_t lds, int xcd, hipStream_t st) {
+void launch_batch_fft(bool f64, int kind, bool wide, const SysDesc* sys, const int4* rec, int pass, int nitems,
+                      size_t lds, int xcd, hipStream_t st) {
   if (nitems <= 0) return;
   using W = unsigned long long;
-  if (f64) wide ? launch_batch_fft_t<double, W>(kind, sys, nsys, o, pass, nitems, lds, xcd, st)
-                : launch_batch_fft_t<double, unsigned>(kind, sys, nsys, o, pass, nitems, lds, xcd, st);
-  else wide ? launch_batch_fft_t<float, W>(kind, sys, nsys, o, pass, nitems, lds, xcd, st)
-            : launch_batch_fft_t<float, unsigned>(kind, sys, nsys, o, pass, nitems, lds, xcd, st);
+  if (f64) wide ? launch_batch_fft_t<double, W>(kind, sys, rec, pass, nitems, lds, xcd, st)
+                : launch_batch_fft_t<double, unsigned>(kind, sys, rec, pass, nitems, lds, xcd, st);
+  else wide ? launch_batch_fft_t<float, W>(kind, sys, rec, pass, nitems, lds, xcd, st)
+            : launch_batch_fft_t<float, unsigned>(kind, sys, rec, pass, nitems, lds, xcd, st);
 }
 
 }  // namespace se

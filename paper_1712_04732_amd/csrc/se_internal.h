@@ -151,6 +151,7 @@ struct BatchIO {
   int in_f32, out_grad, add_self, allow_nonneutral;
   int xcd_tiles, xcd_fft;   // item mapping modes of the tile / transform stages (as GridGeom::xcd)
   int fft_wide;             // bit k: transform stage k needs 64-bit offsets for some system
+  const int4* fft_rec;      // work records of the transform lists, concatenated in list order
 };
 
 // Stages of a batched evaluation, in order; one launch per stage.
@@ -181,10 +182,10 @@ hipError_t launch_energy(const GridGeom& g, const EvalBuffers& b, double* energy
 // Transforms (se_fft.hip).
 hipError_t launch_fft(const FftPass& p, bool f64, hipStream_t st);
 size_t fft_lds_bytes(const FftPass& p, bool f64);
-// One transform kind of transform stage 'pass' of a batch: 'nitems' work items,
-// 'o' the device prefix table [nsys + 1] of that (stage, kind) work list.
-void launch_batch_fft(bool f64, int kind, bool wide, const SysDesc* sys, int nsys, const int* o, int pass,
-                      int nitems, size_t lds, int xcd, hipStream_t st);
+// One transform kind of transform stage 'pass' of a batch: 'nitems' work
+// records {system * 4 + class, b0 start, b1, count} at 'rec' (device).
+void launch_batch_fft(bool f64, int kind, bool wide, const SysDesc* sys, const int4* rec, int pass, int nitems,
+                      size_t lds, int xcd, hipStream_t st);
 size_t spread_lds_bytes(const GridGeom& g, bool f64);
 size_t gather_lds_bytes(const GridGeom& g, bool f64);
 int scan_blocks(const GridGeom& g);

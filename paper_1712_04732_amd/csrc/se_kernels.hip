@@ -1440,10 +1440,15 @@ static void batch_launch_one(const SysDesc* sys, int nsys, const int* off, const
   if constexpr (ST >= BS_FFT0 && ST <= BS_FFT4) {
     const int pass = ST - BS_FFT0;
     const bool wide = (io.fft_wide >> pass) & 1;
-    for (int k = 0; k < kFftKinds; ++k)
+    // records of earlier transform lists come first
+    long first = 0;
+    for (int l = BS_COUNT; l < fft_list(ST, 0); ++l) first += items[l];
+    for (int k = 0; k < kFftKinds; ++k) {
       if (items[fft_list(ST, k)] > 0)
-        launch_batch_fft(sizeof(T) == 8, k, wide, sys, nsys, off + fft_list(ST, k) * (nsys + 1), pass,
-                         items[fft_list(ST, k)], lds[ST], io.xcd_fft, st);
+        launch_batch_fft(sizeof(T) == 8, k, wide, sys, io.fft_rec + first, pass, items[fft_list(ST, k)], lds[ST],
+                         io.xcd_fft, st);
+      first += items[fft_list(ST, k)];
+    }
   } else {
     if (items[ST] > 0)
       batch_stage_kernel<T, P, ST><<<dim3(items[ST]), dim3(kBlock), lds[ST], st>>>(

@@ -41,10 +41,10 @@ bool is_smooth(long n) {
   return n == 1;
 }
 
-// Radix sequence for the Stockham stages (radices 8, 4, 2, 3, 5, 7).
+// Radix sequence for the Stockham stages (radices 16, 8, 4, 2, 3, 5, 7).
 bool radix_plan(int n, int* rad, int* nst) {
   int k = 0, m = n;
-  for (int r : {8, 4, 2, 3, 5, 7}) {
+  for (int r : {16, 8, 4, 2, 3, 5, 7}) {
     while (m % r == 0) {
       if (k >= se::kMaxStages) return false;
       rad[k++] = r;
@@ -273,7 +273,7 @@ se::FftClass make_class(int n, int n_in, int n_out, const void* in, void* out,
   c.n_out = n_out;
   radix_plan(n, c.rad, &c.nst);
   c.radpack = 0;
-  for (int k = 0; k < c.nst; ++k) c.radpack |= (unsigned long long)c.rad[k] << (4 * k);
+  for (int k = 0; k < c.nst; ++k) c.radpack |= (unsigned long long)(c.rad[k] & 15) << (4 * k);   // 16 -> 0
   c.in = in;
   c.out = out;
   c.in_st = in_st;
@@ -1254,6 +1254,7 @@ struct se_batch_plan {
   long total = 0;
   se::SysDesc* d_sys = nullptr;
   int* d_off = nullptr;
+  int4* d_rec = nullptr;                        // transform work records, list by list
   int items[se::BL_COUNT] = {};                // work items per list
   size_t lds[se::BS_COUNT] = {};               // dynamic LDS per stage launch
   int P = 0;
@@ -1270,6 +1271,7 @@ struct se_batch_plan {
       if (e) (void)hipEventDestroy(e);
     if (d_sys) (void)hipFree(d_sys);
     if (d_off) (void)hipFree(d_off);
+    if (d_rec) (void)hipFree(d_rec);
     for (se_plan* s : sys) delete s;
   }
   // fold the timings of the last profiled evaluation in (events complete)
@@ -1312,6 +1314,7 @@ se_status se_batch_plan_create(const se_params* params, const long* N, int n_sys
   hipStream_t st = (hipStream_t)hip_stream;
   std::vector<se::SysDesc> desc(n_sys);
   std::vector<int> off((size_t)se::BL_COUNT * (n_sys + 1), 0);
+  std::vector<std::vector<int4>> lrec((size_t)se::kPasses * se::kFftKinds);   // per transform list
   long run = 0;
   for (int s = 0; s < n_sys; ++s) {
     se_plan* sp = nullptr;
@@ -1346,8 +1349,18 @@ se_status se_batch_plan_create(const se_params* params, const long* N, int n_sys
                                      d.pass[0].nitems, d.pass[1].nitems, d.pass[2].nitems, d.pass[3].nitems,
                                      d.pass[4].nitems, d.ntiles, 1};
     for (int k = 0; k < se::BS_COUNT; ++k) off[(size_t)k * (n_sys + 1) + s + 1] = items[k];
-    for (int k = 0; k < se::kPasses; ++k)
+    for (int k = 0; k < se::kPasses; ++k) {
       off[(size_t)se::fft_list(se::BS_FFT0 + k, d.pass[k].kind) * (n_sys + 1) + s + 1] = d.pass[k].nitems;
+      // this system's records of transform list (stage k, kind): {s * 4 + class, b0, b1, count}
+      std::vector<int4> it(d.pass[k].nitems);
+      if (!it.empty() && hipMemcpy(it.data(), d.pass[k].items, it.size() * sizeof(int4), hipMemcpyDeviceToHost) !=
+                             hipSuccess) {
+        delete bp;
+        return SE_ERR_DEVICE;
+      }
+      auto& dst = lrec[(size_t)k * se::kFftKinds + d.pass[k].kind];
+      for (const int4& r : it) dst.push_back(make_int4(s * 4 + r.x, r.y, r.z, r.w));
+    }
     size_t* lds = bp->lds;
     lds[se::BS_SPREAD] = std::max(lds[se::BS_SPREAD], se::spread_lds_bytes(sp->geom, bp->f64));
     lds[se::BS_GATHER] = std::max(lds[se::BS_GATHER], se::gather_lds_bytes(sp->geom, bp->f64));
@@ -1396,8 +1409,15 @@ se_status se_batch_plan_create(const se_params* params, const long* N, int n_sys
     delete bp;
     return SE_ERR_NOMEM;
   }
+  std::vector<int4> rec;
+  for (const auto& l : lrec) rec.insert(rec.end(), l.begin(), l.end());
+  if (hipMalloc(&bp->d_rec, sizeof(int4) * std::max<size_t>(rec.size(), 1)) != hipSuccess) {
+    delete bp;
+    return SE_ERR_NOMEM;
+  }
   if (hipMemcpy(bp->d_sys, desc.data(), sizeof(se::SysDesc) * n_sys, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(bp->d_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      (!rec.empty() && hipMemcpy(bp->d_rec, rec.data(), sizeof(int4) * rec.size(), hipMemcpyHostToDevice) != hipSuccess) ||
       hipStreamSynchronize(st) != hipSuccess) {
     delete bp;
     return SE_ERR_DEVICE;
@@ -1441,6 +1461,7 @@ se_status se_eval_batch(se_batch_plan* plan, const void* xyz, const void* q, voi
   for (const se_plan* sp : plan->sys)
     for (int k = 0; k < se::kPasses; ++k)
       if (sp->passes[k].wide) io.fft_wide |= 1 << k;
+  io.fft_rec = plan->d_rec;
   const bool prof = (flags & SE_PROFILE) != 0;
   if (prof && !plan->have_ev) {
     for (hipEvent_t& e : plan->ev)

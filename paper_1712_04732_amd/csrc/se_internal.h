@@ -31,6 +31,11 @@ constexpr int kMaxFoldImages = 8;
 // FFT workgroup size.
 constexpr int kFftCap = 8192;
 constexpr int kFftBlock = 256;
+// LDS budget of an FFT workgroup: the transforms are latency bound, so a pass
+// takes fewer pencils per workgroup rather than fewer workgroups per CU (four
+// per 160 KB CU at this budget).  Across a batch the largest pass sets every
+// system's occupancy.
+constexpr size_t kFftLdsSoft = 40 * 1024;
 
 // Green's-function modes of the fused scaling pass (Eq. scale).
 enum GMode : int {

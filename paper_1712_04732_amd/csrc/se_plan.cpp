@@ -311,7 +311,7 @@ static bool finish_pass(se_plan* pl, se::FftPass& ps, int kind, int ncls,
   int lgB = 0;
   while (lgB < 6) {
     const long B2 = 2L << lgB;
-    if ((long)ps.nmax * B2 > cap || lds_of(B2) > pl->lds_limit) break;
+    if ((long)ps.nmax * B2 > cap || lds_of(B2) > std::min(pl->lds_limit, se::kFftLdsSoft)) break;
     ++lgB;
   }
   if (lds_of(1L << lgB) > pl->lds_max) return false;

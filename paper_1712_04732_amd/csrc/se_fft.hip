@@ -272,8 +272,7 @@ __device__ __forceinline__ void fft_stage_r(int R, const lds<vec2<T>>* src, lds<
     case 4: fft_stage<T, 4, FIRST, SIGN>(src, dst, tw, n, Ns, tws, lgB, Bp); break;
     case 5: fft_stage<T, 5, FIRST, SIGN>(src, dst, tw, n, Ns, tws, lgB, Bp); break;
     case 7: fft_stage<T, 7, FIRST, SIGN>(src, dst, tw, n, Ns, tws, lgB, Bp); break;
-    case 8: fft_stage<T, 8, FIRST, SIGN>(src, dst, tw, n, Ns, tws, lgB, Bp); break;
-    default: fft_stage<T, 16, FIRST, SIGN>(src, dst, tw, n, Ns, tws, lgB, Bp); break;
+    default: fft_stage<T, 8, FIRST, SIGN>(src, dst, tw, n, Ns, tws, lgB, Bp); break;
   }
 }
 
@@ -303,6 +302,91 @@ __device__ __forceinline__ lds<vec2<T>>* fft_run(lds<vec2<T>>* b0, lds<vec2<T>>*
     rem = tws;
   }
   return src;
+}
+
+// The same stage in place: every thread first reads and transforms all its
+// butterflies (at most kFftInplaceCap / (R kFftBlock) of them, held in
+// registers), then, after a barrier, writes them back over the inputs.
+template <typename T, int R, bool FIRST, int SIGN>
+__device__ __forceinline__ void fft_stage_ip(lds<vec2<T>>* buf, const lds<vec2<T>>* __restrict__ tw, int n, int Ns,
+                                             int tws, int lgB, int Bp) {
+  constexpr int IT = (kFftInplaceCap + R * kFftBlock - 1) / (R * kFftBlock);
+  const int nb = n / R;
+  const int total = nb << lgB;
+  const int mask = (1 << lgB) - 1;
+  const int sstr = nb * Bp;
+  const int dstr = Ns * Bp;
+  const int nsr = Ns * R;
+  const float inv_ns = 1.0f / (float)Ns;
+  cx<T> v[IT][R];
+  int dofs[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = threadIdx.x + it * kFftBlock;
+    dofs[it] = -1;
+    if (e < total) {
+      const int j = e >> lgB, p = e & mask;
+      const lds<vec2<T>>* s = buf + (__mul24(j, Bp) + p);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[it][r] = lget<T>(s, r * sstr);
+      int base;
+      if constexpr (FIRST) {
+        base = __mul24(j, R);
+      } else {
+        const int jq = fdiv(j, inv_ns), k = j - __mul24(jq, Ns);
+        const int kt = __mul24(k, tws);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cx<T> w = lget<T>(tw, r * kt);
+          if constexpr (SIGN > 0) w.im = -w.im;
+          v[it][r] = cmul(v[it][r], w);
+        }
+        base = __mul24(jq, nsr) + k;
+      }
+      dft<T, R>(v[it], SIGN);
+      dofs[it] = __mul24(base, Bp) + p;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < IT; ++it)
+    if (dofs[it] >= 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) lput<T>(buf, dofs[it] + r * dstr, v[it][r]);
+    }
+  __syncthreads();
+}
+
+template <typename T, bool FIRST, int SIGN>
+__device__ __forceinline__ void fft_stage_ip_r(int R, lds<vec2<T>>* buf, const lds<vec2<T>>* tw, int n, int Ns,
+                                               int tws, int lgB, int Bp) {
+  switch (R) {
+    case 2: fft_stage_ip<T, 2, FIRST, SIGN>(buf, tw, n, Ns, tws, lgB, Bp); break;
+    case 3: fft_stage_ip<T, 3, FIRST, SIGN>(buf, tw, n, Ns, tws, lgB, Bp); break;
+    case 4: fft_stage_ip<T, 4, FIRST, SIGN>(buf, tw, n, Ns, tws, lgB, Bp); break;
+    case 5: fft_stage_ip<T, 5, FIRST, SIGN>(buf, tw, n, Ns, tws, lgB, Bp); break;
+    case 7: fft_stage_ip<T, 7, FIRST, SIGN>(buf, tw, n, Ns, tws, lgB, Bp); break;
+    default: fft_stage_ip<T, 8, FIRST, SIGN>(buf, tw, n, Ns, tws, lgB, Bp); break;
+  }
+}
+
+// All stages of class C in place in buf.
+template <typename T, int SIGN>
+__device__ __forceinline__ void fft_run_ip(lds<vec2<T>>* buf, const lds<vec2<T>>* tw, const FftClass& C, int lgB,
+                                           int Bp) {
+  const int n = C.n, nst = C.nst;
+  unsigned long long radices = C.radpack;
+  int Ns = 1, rem = n;
+  for (int s = 0; s < nst; ++s) {
+    const int code = (int)(radices & 15u);   // radix 16 is stored as 0
+    const int R = code == 0 ? 16 : code;
+    radices >>= 4;
+    const int tws = rem / R;
+    if (s == 0) fft_stage_ip_r<T, true, SIGN>(R, buf, tw, n, Ns, tws, lgB, Bp);
+    else fft_stage_ip_r<T, false, SIGN>(R, buf, tw, n, Ns, tws, lgB, Bp);
+    Ns *= R;
+    rem = tws;
+  }
 }
 
 __device__ __forceinline__ int fold_index(int i, int n) { return i <= n - i ? i : n - i; }
@@ -571,17 +655,19 @@ __device__ __forceinline__ void stage_fft(const FftPass& P, int cls, int b0s, in
   // real passes with B >= 2 run B/2 complex transforms of pencil pairs
   const int pair = (REAL && lgB > 0) ? 1 : 0;
   const int lgF = lgB - pair, Bp = (1 << lgF) + 1;
+  const bool ip = fft_in_place(P.nmax, lgB);
   lds<vec2<T>>* tw = reinterpret_cast<lds<vec2<T>>*>(smem);
   lds<vec2<T>>* buf = tw + P.nmax;
-  lds<vec2<T>>* buf2 = buf + P.nmax * ((1 << lgB) + 1);
+  lds<vec2<T>>* buf2 = buf + P.nmax * ((1 << lgB) + 1);   // only if not in place
 
   if (C.in_st == 1) fft_load<T, KIND, true, OFF>(C, b0s, b1, cnt, lgB, pair, Bp, buf, tw);
   else fft_load<T, KIND, false, OFF>(C, b0s, b1, cnt, lgB, pair, Bp, buf, tw);
   __syncthreads();
 
-  lds<vec2<T>>* res;
-  if constexpr (KIND == K_C2C_INV || KIND == K_C2R) res = fft_run<T, +1>(buf, buf2, tw, C, lgF, Bp);
-  else res = fft_run<T, -1>(buf, buf2, tw, C, lgF, Bp);
+  constexpr int SIGN = (KIND == K_C2C_INV || KIND == K_C2R) ? +1 : -1;
+  lds<vec2<T>>* res = buf;
+  if (ip) fft_run_ip<T, SIGN>(buf, tw, C, lgF, Bp);
+  else res = fft_run<T, SIGN>(buf, buf2, tw, C, lgF, Bp);
 
   if constexpr (KIND == K_FUSED) {
     // scaling step, Eq. (scale), on the spectrum of each pencil; the block
@@ -594,7 +680,8 @@ __device__ __forceinline__ void stage_fft(const FftPass& P, int cls, int b0s, in
       for (int l = __mul24(t, Bp) + p; t < n; t += dt, l += dl) lput<T>(res, l, cscale(lget<T>(res, l), scale_at<T>(C, row, t)));
     }
     __syncthreads();
-    res = fft_run<T, +1>(res, res == buf ? buf2 : buf, tw, C, lgB, Bp);
+    if (ip) fft_run_ip<T, +1>(buf, tw, C, lgB, Bp);
+    else res = fft_run<T, +1>(res, res == buf ? buf2 : buf, tw, C, lgB, Bp);
   }
 
   if (C.out_st == 1) fft_store<T, KIND, true, OFF>(C, b0s, b1, cnt, lgB, pair, Bp, res);
@@ -628,7 +715,8 @@ __global__ __launch_bounds__(kFftBlock) void batch_fft_kernel(const SysDesc* __r
 
 size_t fft_lds_bytes(const FftPass& p, bool f64) {
   const size_t c = f64 ? 16 : 8;
-  return c * ((size_t)p.nmax + 2 * (((size_t)1 << p.lgB) + 1) * p.nmax);
+  const size_t nbuf = fft_in_place(p.nmax, p.lgB) ? 1 : 2;
+  return c * ((size_t)p.nmax + nbuf * (((size_t)1 << p.lgB) + 1) * p.nmax);
 }
 
 template <typename T, typename OFF>

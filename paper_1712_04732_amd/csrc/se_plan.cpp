@@ -41,10 +41,10 @@ bool is_smooth(long n) {
   return n == 1;
 }
 
-// Radix sequence for the Stockham stages (radices 16, 8, 4, 2, 3, 5, 7).
+// Radix sequence for the Stockham stages (radices 8, 4, 2, 3, 5, 7).
 bool radix_plan(int n, int* rad, int* nst) {
   int k = 0, m = n;
-  for (int r : {16, 8, 4, 2, 3, 5, 7}) {
+  for (int r : {8, 4, 2, 3, 5, 7}) {
     while (m % r == 0) {
       if (k >= se::kMaxStages) return false;
       rad[k++] = r;
@@ -307,7 +307,10 @@ static bool finish_pass(se_plan* pl, se::FftPass& ps, int kind, int ncls,
   const size_t esz = pl->f64 ? 16 : 8;
   // (LDS: twiddles n, two sample buffers n (B + 1))
   const long cap = pl->fft_cap > 0 ? pl->fft_cap : (pl->f64 ? 1024 : 2048);
-  auto lds_of = [&](long B2) { return esz * (size_t)ps.nmax * (1 + 2 * (B2 + 1)); };
+  auto lds_of = [&](long B2) {
+    const size_t nbuf = (long)ps.nmax * B2 <= se::kFftInplaceCap ? 1 : 2;
+    return esz * (size_t)ps.nmax * (1 + nbuf * (B2 + 1));
+  };
   int lgB = 0;
   while (lgB < 6) {
     const long B2 = 2L << lgB;

@@ -154,31 +154,34 @@ struct OddRoots<7> {
 template <typename T, int R>
 __device__ __forceinline__ void dft_odd(cx<T>* v, int sign) {
   constexpr int H = (R - 1) / 2;
-  cx<T> a[H], b[H];
+  // a_r = v_r + v_{R-r}, b_r = v_r - v_{R-r}, kept in v_r and v_{R-r}
   cx<T> x0 = v[0];
 #pragma unroll
   for (int r = 1; r <= H; ++r) {
-    a[r - 1] = v[r] + v[R - r];
-    b[r - 1] = v[r] - v[R - r];
-    x0 = x0 + a[r - 1];
+    const cx<T> a = v[r] + v[R - r], b = v[r] - v[R - r];
+    v[r] = a;
+    v[R - r] = b;
+    x0 = x0 + a;
   }
+  // outputs m and R - m share the cosine sum A_m and the sine sum B_m:
+  // X_m = A_m + sign i B_m, X_{R-m} = A_m - sign i B_m
   cx<T> out[R];
-  out[0] = x0;
 #pragma unroll
-  for (int m = 1; m < R; ++m) {
-    cx<T> acc = v[0];
-    cx<T> bs = {0, 0};
+  for (int m = 1; m <= H; ++m) {
+    cx<T> A = v[0], Bs = {0, 0};
 #pragma unroll
     for (int r = 1; r <= H; ++r) {
       const int j = (r * m) % R;
-      const T cc = (T)OddRoots<R>::c[j], ss = (T)OddRoots<R>::s[j];
-      acc = acc + cscale(a[r - 1], cc);
-      bs = bs + cscale(b[r - 1], ss);
+      A = A + cscale(v[r], (T)OddRoots<R>::c[j]);
+      Bs = Bs + cscale(v[R - r], (T)OddRoots<R>::s[j]);
     }
-    out[m] = acc + mul_si(bs, sign);
+    const cx<T> iB = mul_si(Bs, sign);
+    out[m] = A + iB;
+    out[R - m] = A - iB;
   }
+  v[0] = x0;
 #pragma unroll
-  for (int m = 0; m < R; ++m) v[m] = out[m];
+  for (int m = 1; m < R; ++m) v[m] = out[m];
 }
 
 template <typename T, int R>

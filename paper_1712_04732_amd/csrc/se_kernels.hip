@@ -811,7 +811,10 @@ __device__ __forceinline__ void stage_spread_cols(const GridGeom& g, const EvalB
   int* rpre = rstart + kMaxClipRanges;                        // kMaxClipRanges + 1
   int* rsh = rpre + kMaxClipRanges + 4;                       // kMaxClipRanges
   int* org = rsh + kMaxClipRanges;                            // kColBatch packed origins
-  T* wb = reinterpret_cast<T*>(org + kColBatch);              // kColBatch * 3P weights
+  T* wb = reinterpret_cast<T*>(org + kColBatch);              // kColBatch records of SW weights
+  // per visit: x and y stencil rows, then the z weights in the tile's z frame
+  // (zero outside the stencil); 16-byte aligned for P even
+  constexpr int SW = 2 * P + kColZ;
   __shared__ int pc_s0[3][kMaxPieces], pc_s1[3][kMaxPieces], pc_sh[3][kMaxPieces], pc_n[3];
 
   if (threadIdx.x < 3) {
@@ -861,19 +864,21 @@ __device__ __forceinline__ void stage_spread_cols(const GridGeom& g, const EvalB
       const int r = find_range(rpre, nr, e);
       const int i = rstart[r] + (e - rpre[r]);
       const Quad<T> f = ld_quad<T>(b.s_fq, i);
-      if (kr == 0) {
-        const int pc = gld(b.s_cell)[i], code = rsh[r];
-        // stencil origin c + shift - P/2 + 1 in tile coordinates, each in [-P+1, T)
-        const int ox = (pc & 1023) + pc_sh[0][code >> 8] - P / 2 + 1 - x0;
-        const int oy = ((pc >> 10) & 1023) + pc_sh[1][(code >> 4) & 15] - P / 2 + 1 - y0;
-        const int oz = ((pc >> 20) & 1023) + pc_sh[2][code & 15] - P / 2 + 1 - z0;
-        org[k] = (ox + 64) | ((oy + 64) << 8) | ((oz + 64) << 16);
-      }
+      const int pc = gld(b.s_cell)[i], code = rsh[r];
+      // stencil origin c + shift - P/2 + 1 in tile coordinates, each in [-P+1, T)
+      const int ox = (pc & 1023) + pc_sh[0][code >> 8] - P / 2 + 1 - x0;
+      const int oy = ((pc >> 10) & 1023) + pc_sh[1][(code >> 4) & 15] - P / 2 + 1 - y0;
+      const int oz = ((pc >> 20) & 1023) + pc_sh[2][code & 15] - P / 2 + 1 - z0;
+      if (kr == 0) org[k] = (ox + 64) | ((oy + 64) << 8);
+      T* w = wb + k * SW;
+      // the z row: zeros first, then the stencil rows over them (both by
+      // this particle's lanes of one wavefront, so in this order)
+      for (int z = kr; z < kColZ; z += G2) w[2 * P + z] = (T)0;
       if (kr < P) {
-        T* w = wb + k * 3 * P;
         w[kr] = weight_reg<T, P>(g, crow, kr, f.fx);
         w[P + kr] = weight_reg<T, P>(g, crow, kr, f.fy);
-        w[2 * P + kr] = f.q * weight_reg<T, P>(g, crow, kr, f.fz);
+        const int zz = oz + kr;
+        if ((unsigned)zz < (unsigned)kColZ) w[2 * P + zz] = f.q * weight_reg<T, P>(g, crow, kr, f.fz);
       }
     }
     __syncthreads();
@@ -886,19 +891,21 @@ __device__ __forceinline__ void stage_spread_cols(const GridGeom& g, const EvalB
       {
         for (int j = 0; j < kn; ++j) {
           const int o = __builtin_amdgcn_readlane(my_org, j);
-          const int ox = (o & 255) - 64, oy = ((o >> 8) & 255) - 64, oz = ((o >> 16) & 255) - 64;
+          const int ox = (o & 255) - 64, oy = ((o >> 8) & 255) - 64;
           const int dx = cx - ox, dy = cy - oy;
           if (own && (unsigned)dx < (unsigned)P && (unsigned)dy < (unsigned)P) {
-            const T* w = wb + (k0 + j) * 3 * P;
+            const T* w = wb + (k0 + j) * SW;
             const T wxy = w[dx] * w[P + dy];
-            // fixed register index z, weight row index z - oz from LDS (the
-            // LDS index is clamped into the row so that a read the compiler
-            // hoists above the range test stays inside it)
+            // the whole z row (zeros outside the stencil) with fixed register
+            // indices
+            const vec4<T>* wz4 = reinterpret_cast<const vec4<T>*>(w + 2 * P);
 #pragma unroll
-            for (int z = 0; z < kColZ; ++z) {
-              const int iz = z - oz;
-              const T wz = w[2 * P + min(max(iz, 0), P - 1)];
-              if ((unsigned)iz < (unsigned)P) acc[z] += wxy * wz;
+            for (int q = 0; q < kColZ / 4; ++q) {
+              const vec4<T> v = wz4[q];
+              acc[4 * q] += wxy * v.x;
+              acc[4 * q + 1] += wxy * v.y;
+              acc[4 * q + 2] += wxy * v.z;
+              acc[4 * q + 3] += wxy * v.w;
             }
           }
         }
@@ -1029,7 +1036,7 @@ template <typename T>
 size_t spread_lds(const GridGeom& g) {
   const int P = g.P, nw = kBlock / 64;
   if (g.clip == 2)
-    return sizeof(int) * (3 * kMaxClipRanges + 4 + kColBatch) + sizeof(T) * ((size_t)kColBatch * 3 * P) + 64;
+    return sizeof(int) * (3 * kMaxClipRanges + 4 + kColBatch) + sizeof(T) * ((size_t)kColBatch * (2 * P + kColZ)) + 64;
   if (g.clip) {
     const size_t T3 = (size_t)g.T[0] * g.T[1] * g.T[2];
     return 8 * T3 + sizeof(T) * ((size_t)nw * g.chunk * (3 * P + 4)) +

@@ -658,7 +658,7 @@ __device__ __forceinline__ void stage_fft(const FftPass& P, int cls, int b0s, in
   // real passes with B >= 2 run B/2 complex transforms of pencil pairs
   const int pair = (REAL && lgB > 0) ? 1 : 0;
   const int lgF = lgB - pair, Bp = (1 << lgF) + 1;
-  const bool ip = fft_in_place(P.nmax, lgB);
+  const bool ip = P.inplace;
   lds<vec2<T>>* tw = reinterpret_cast<lds<vec2<T>>*>(smem);
   lds<vec2<T>>* buf = tw + P.nmax;
   lds<vec2<T>>* buf2 = buf + P.nmax * ((1 << lgB) + 1);   // only if not in place
@@ -718,7 +718,7 @@ __global__ __launch_bounds__(kFftBlock) void batch_fft_kernel(const SysDesc* __r
 
 size_t fft_lds_bytes(const FftPass& p, bool f64) {
   const size_t c = f64 ? 16 : 8;
-  const size_t nbuf = fft_in_place(p.nmax, p.lgB) ? 1 : 2;
+  const size_t nbuf = p.inplace ? 1 : 2;
   return c * ((size_t)p.nmax + nbuf * (((size_t)1 << p.lgB) + 1) * p.nmax);
 }
 

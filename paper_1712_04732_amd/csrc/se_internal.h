@@ -36,11 +36,11 @@ constexpr int kFftBlock = 256;
 // per 160 KB CU at this budget).  Across a batch the largest pass sets every
 // system's occupancy.
 constexpr size_t kFftLdsSoft = 40 * 1024;
-// Blocks of at most this many samples (transform length x pencils) run their
-// stages in place in one LDS buffer (inputs of a stage held in registers);
-// larger ones alternate between two buffers.
+// Passes whose blocks hold at most this many samples (transform length x
+// pencils) run their stages in place in one LDS buffer (inputs of a stage
+// held in registers); passes with a larger samples cap alternate between two
+// buffers.
 constexpr int kFftInplaceCap = 2048;
-__host__ __device__ inline bool fft_in_place(int nmax, int lgB) { return ((long)nmax << lgB) <= kFftInplaceCap; }
 
 // Green's-function modes of the fused scaling pass (Eq. scale).
 enum GMode : int {
@@ -92,6 +92,7 @@ struct FftPass {
   int kind;
   int xcd;                        // item mapping: 0 plain, 1 one range per XCD, c >= 2 chunks of c
   int wide;                       // 1 if a workgroup's pencils span 4 GiB or more (64-bit offsets)
+  int inplace;                    // 1: stages in place in one LDS buffer
   double alg_bytes, alg_flops;    // algorithmic counts of one launch (tracing only)
 };
 

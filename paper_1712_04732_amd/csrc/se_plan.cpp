@@ -307,10 +307,9 @@ static bool finish_pass(se_plan* pl, se::FftPass& ps, int kind, int ncls,
   const size_t esz = pl->f64 ? 16 : 8;
   // (LDS: twiddles n, two sample buffers n (B + 1))
   const long cap = pl->fft_cap > 0 ? pl->fft_cap : (pl->f64 ? 1024 : 2048);
-  auto lds_of = [&](long B2) {
-    const size_t nbuf = (long)ps.nmax * B2 <= se::kFftInplaceCap ? 1 : 2;
-    return esz * (size_t)ps.nmax * (1 + nbuf * (B2 + 1));
-  };
+  // in place unless the samples cap (or a single pencil) exceeds kFftInplaceCap
+  ps.inplace = (cap <= se::kFftInplaceCap && ps.nmax <= se::kFftInplaceCap) ? 1 : 0;
+  auto lds_of = [&](long B2) { return esz * (size_t)ps.nmax * (1 + (ps.inplace ? 1 : 2) * (B2 + 1)); };
   int lgB = 0;
   while (lgB < 6) {
     const long B2 = 2L << lgB;

@@ -13,7 +13,12 @@ constexpr int kMaxStages = 16;
 constexpr int kMaxClasses = 3;
 constexpr int kMaxP = 16;
 constexpr int kMaxNu = 12;
-constexpr int kBlock = 256;      // threads per block of every kernel
+constexpr int kBlock = 256;      // threads per block (transforms and gathering: below)
+// Gathering stages a (T + P - 1)^3 grid region per tile, so few of its
+// workgroups fit a CU; eight wavefronts per workgroup keep more region loads
+// in flight.
+constexpr int kGatherBlock = 512;
+constexpr int kMaxBlock = kGatherBlock;
 constexpr int kSB = 4;           // sub-bin edge in grid cells (particle sort key)
 constexpr int kMaxOwnRanges = 256;  // sub-bin rows of one tile ((T/kSB)^2 <= 256 for T <= 64)
 // Clipped spreading: most anchor pieces (periodic images) per direction and
@@ -170,7 +175,9 @@ enum BatchStage : int {
   BS_ZERO = 0, BS_BIN, BS_SCAN1, BS_SCAN2, BS_SCATTER, BS_ORDER, BS_SPREAD, BS_FOLD,
   BS_FFT0, BS_FFT1, BS_FFT2, BS_FFT3, BS_FFT4, BS_GATHER, BS_ENERGY, BS_COUNT
 };
-constexpr int stage_block(int st) { return st >= BS_FFT0 && st <= BS_FFT4 ? kFftBlock : kBlock; }
+constexpr int stage_block(int st) {
+  return st >= BS_FFT0 && st <= BS_FFT4 ? kFftBlock : (st == BS_GATHER ? kGatherBlock : kBlock);
+}
 // Work lists of a batch: one per stage, and for the transform stages one per
 // (stage, transform kind) so that each launch runs a single kind.
 constexpr int kFftKinds = 5;

@@ -425,7 +425,7 @@ __device__ int build_ranges(const GridGeom& g, const EvalBuffers& b, const int* 
 // Exclusive prefix of rpre[0..nr) in place, rpre[nr] = total; returns the
 // total.  All threads of the block call it; ends with a barrier.
 __device__ int prefix_ranges(int* rpre, int nr) {
-  __shared__ int part[kBlock];
+  __shared__ int part[kMaxBlock];
   const int per = (nr + blockDim.x - 1) / blockDim.x;
   const int lo = min(nr, (int)threadIdx.x * per), hi = min(nr, lo + per);
   int s = 0;
@@ -1119,7 +1119,7 @@ __device__ __forceinline__ void stage_gather(const GridGeom& g, const EvalBuffer
   Quad<T>* rq = reinterpret_cast<Quad<T>*>(wsh + nwaves * PPW * 4 * P);   // kGatherBatch records
   int* rc = reinterpret_cast<int*>(rq + kGatherBatch);        // kGatherBatch cells
   int* ri = rc + kGatherBatch;                                // kGatherBatch input indices
-  __shared__ double ewave[kBlock / 64];
+  __shared__ double ewave[kGatherBlock / 64];
 
   // particles anchored in this tile: sub-bins of the tile
   int sx[2] = {x0 / kSB, (x0 + ex - 1) / kSB}, sy[2] = {y0 / kSB, (y0 + ey - 1) / kSB},
@@ -1276,7 +1276,7 @@ __device__ __forceinline__ void stage_gather(const GridGeom& g, const EvalBuffer
 }
 
 template <typename T, int P>
-__global__ __launch_bounds__(kBlock) void gather_kernel(GridGeom g, EvalBuffers b, T* __restrict__ phi,
+__global__ __launch_bounds__(kGatherBlock) void gather_kernel(GridGeom g, EvalBuffers b, T* __restrict__ phi,
                                                         T* __restrict__ force, int out_grad,
                                                         double self_coef) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1285,7 +1285,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GridGeom g, EvalBuffers 
 
 template <typename T>
 size_t gather_lds(const GridGeom& g) {
-  const int P = g.P, m = g.nu + 1, nw = kBlock / 64;
+  const int P = g.P, m = g.nu + 1, nw = kGatherBlock / 64;
   const int G2 = P <= 2 ? 2 : (P <= 4 ? 4 : (P <= 8 ? 8 : 16));
   const size_t R = (size_t)(g.T[0] + P - 1) * (g.T[1] + P - 1) * (g.T[2] + P - 1);
   (void)m;
@@ -1297,7 +1297,7 @@ template <typename T, int P>
 static void gather_launch(const GridGeom& g, const EvalBuffers& b, T* phi, T* force, int out_grad,
                           double self_coef, hipStream_t st) {
   const int ntiles = g.nt[0] * g.nt[1] * g.nt[2];
-  gather_kernel<T, P><<<dim3(ntiles), dim3(kBlock), gather_lds<T>(g), st>>>(g, b, phi, force, out_grad,
+  gather_kernel<T, P><<<dim3(ntiles), dim3(kGatherBlock), gather_lds<T>(g), st>>>(g, b, phi, force, out_grad,
                                                                             self_coef);
 }
 
@@ -1424,7 +1424,7 @@ __device__ __forceinline__ void run_batch_stage(int st, const SysDesc& S, int sy
 // is a template argument so that each stage's kernel carries only its own
 // registers and LDS.
 template <typename T, int P, int ST>
-__global__ __launch_bounds__(kBlock) void batch_stage_kernel(const SysDesc* __restrict__ sys, int nsys,
+__global__ __launch_bounds__(stage_block(ST)) void batch_stage_kernel(const SysDesc* __restrict__ sys, int nsys,
                                                              const int* __restrict__ off, BatchIO io, int xcd) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int* o = off + ST * (nsys + 1);
@@ -1458,7 +1458,7 @@ static void batch_launch_one(const SysDesc* sys, int nsys, const int* off, const
     }
   } else {
     if (items[ST] > 0)
-      batch_stage_kernel<T, P, ST><<<dim3(items[ST]), dim3(kBlock), lds[ST], st>>>(
+      batch_stage_kernel<T, P, ST><<<dim3(items[ST]), dim3(stage_block(ST)), lds[ST], st>>>(
           sys, nsys, off, io, (ST == BS_SPREAD || ST == BS_FOLD || ST == BS_GATHER) ? io.xcd_tiles : 0);
   }
 }

@@ -268,7 +268,7 @@ def main_batch(args):
                                              "fft0", "fft1", "fft2", "fft3", "fft4", "gather", "energy"])}
     st_name = roof["kernel"]
     if st_name == "fft2":
-        roof["kernel"] = "batch_fft_kernel<float, 4> (fft2: fused forward transform, scaling, inverse transform)"
+        roof["kernel"] = "batch_fft_kernel<float, 4, unsigned int> (fft2: fused forward transform, scaling, inverse transform)"
     elif st_name.startswith("fft"):
         roof["kernel"] = f"batch_fft_kernel<float, *> ({st_name}: one launch per transform kind)"
     else:

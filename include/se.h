@@ -111,6 +111,8 @@ typedef struct {
   int tile[3];        /* spread/gather tile edges in grid points (x, y, z)             */
   int fft_cap;        /* samples per FFT workgroup in use                              */
   int spread_mode;    /* spreading mode in use (1 boxes and fold, 2 clipped, 3 columns) */
+  int fft_wide;       /* bit k: transform pass k addresses with 64-bit offsets (its
+                         workgroups' pencils span 4 GiB or more)                    */
   double h, shape, lambda, s0, s, R;
   size_t device_bytes; /* device memory held by the plan                               */
 } se_plan_info;

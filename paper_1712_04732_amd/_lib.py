@@ -84,6 +84,7 @@ class se_plan_info(ctypes.Structure):
         ("tile", ctypes.c_int * 3),
         ("fft_cap", ctypes.c_int),
         ("spread_mode", ctypes.c_int),
+        ("fft_wide", ctypes.c_int),
         ("h", ctypes.c_double),
         ("shape", ctypes.c_double),
         ("lambda_", ctypes.c_double),

@@ -782,6 +782,9 @@ static se_status plan_create(const se_params* params, long n_max, void* hip_stre
     return rc;
   }
   I.device_bytes = pl->bytes;
+  I.fft_wide = 0;
+  for (size_t k = 0; k < pl->passes.size(); ++k)
+    if (pl->passes[k].wide) I.fft_wide |= 1 << k;
   *out = pl;
   return SE_OK;
 }

@@ -319,19 +319,6 @@ def main_batch(args):
     print(json.dumps(result), flush=True)
 
 
-def _traffic(name):
-    tpath = os.path.join(ROOT, "profiles", "traffic.json")
-    if not os.path.exists(tpath):
-        return None
-    try:
-        ent = json.load(open(tpath)).get(name)
-        if ent and ent.get("source_sha") == _source_sha():
-            return ent["bytes_per_launch"]
-    except Exception:
-        return None
-    return None
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)

@@ -83,7 +83,9 @@ typedef struct {
   int tile3[3];       /* spread/gather tile edges x, y, z (multiples of 4, each <= 32);
                          all > 0 -> used instead of 'tile'                          */
   int fft_cap;        /* samples (length x pencils) per FFT workgroup: a power of two
-                         in 1024..8192; <= 0 -> 2048 (FP32) / 1024 (FP64)          */
+                         in 1024..8192; <= 0 -> 2048 (FP32) / 1024 (FP64); up to
+                         2048 the stages run in place in one LDS buffer, above it
+                         they alternate between two                                */
   int xcd_tiles;      /* workgroup -> tile mapping of spread, fold and gather (the
                          8 XCDs take workgroups in turn): < 0 plain order, 1 one
                          contiguous tile range per XCD, c >= 2 chunks of c

@@ -2,7 +2,7 @@
 // of Shamshirgar, Bagge, Tornberg, arXiv:1712.04732).
 //
 // One workgroup transforms B pencils of one length-n class at once: it loads
-// them into LDS (zero padding up to n), runs mixed-radix (2,3,4,5,7,8,16)
+// them into LDS (zero padding up to n), runs mixed-radix (2,3,4,5,7,8)
 // Stockham stages between two LDS buffers, and stores the first n_out samples
 // (truncation).  Real-to-complex and complex-to-real passes transform two real
 // pencils as the real and imaginary parts of one complex pencil.  The fused
@@ -57,63 +57,6 @@ __device__ __forceinline__ void dft8(cx<T>* v, int sign) {
   v[6] = e[2] - o2;
   v[3] = e[3] + o3;
   v[7] = e[3] - o3;
-}
-
-// x exp(sign 2 pi i e/16) for a compile-time e in [0, 16).
-template <typename T, int E>
-__device__ __forceinline__ cx<T> rot16(cx<T> x, int sign) {
-  constexpr double c16[5] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173, 0.0};
-  if constexpr (E == 0) {
-    return x;
-  } else if constexpr (E == 4) {
-    return mul_si(x, sign);
-  } else if constexpr (E == 8) {
-    return cx<T>{-x.re, -x.im};
-  } else if constexpr (E == 12) {
-    return mul_si(x, -sign);
-  } else if constexpr (E == 2 || E == 6 || E == 10 || E == 14) {
-    // exp(sign i pi e/8) = (cr + sign i ci) / sqrt(2), cr, ci = +-1
-    constexpr T h = (T)0.70710678118654752440;
-    constexpr int cr = (E == 2 || E == 14) ? 1 : -1, ci = (E == 2 || E == 6) ? 1 : -1;
-    const T a = cr * x.re, b = cr * x.im, c = ci * x.re, d = ci * x.im;
-    // (x.re + i x.im)(cr + sign i ci) = (x.re cr - sign ci x.im) + i (x.im cr + sign ci x.re)
-    return sign > 0 ? cx<T>{h * (a - d), h * (b + c)} : cx<T>{h * (a + d), h * (b - c)};
-  } else {
-    // cos and sin of pi e/8 from the first-quadrant table
-    constexpr int q = E / 4, r = E % 4;
-    constexpr double cq = q == 0 ? c16[r] : (q == 1 ? -c16[4 - r] : (q == 2 ? -c16[r] : c16[4 - r]));
-    constexpr double sq = q == 0 ? c16[4 - r] : (q == 1 ? c16[r] : (q == 2 ? -c16[4 - r] : -c16[r]));
-    return cmul(x, cx<T>{(T)cq, (T)(sign * sq)});
-  }
-}
-
-// 16 = 4 x 4: X[k1 + 4 k2] = sum_q W16^(q k1) W4^(q k2) sum_m v[q + 4 m] W4^(m k1).
-template <typename T>
-__device__ __forceinline__ void dft16(cx<T>* v, int sign) {
-  cx<T> a[4][4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    cx<T> t[4] = {v[q], v[q + 4], v[q + 8], v[q + 12]};
-    dft4(t, sign);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) a[q][k] = t[k];
-  }
-  a[1][1] = rot16<T, 1>(a[1][1], sign);
-  a[1][2] = rot16<T, 2>(a[1][2], sign);
-  a[1][3] = rot16<T, 3>(a[1][3], sign);
-  a[2][1] = rot16<T, 2>(a[2][1], sign);
-  a[2][2] = rot16<T, 4>(a[2][2], sign);
-  a[2][3] = rot16<T, 6>(a[2][3], sign);
-  a[3][1] = rot16<T, 3>(a[3][1], sign);
-  a[3][2] = rot16<T, 6>(a[3][2], sign);
-  a[3][3] = rot16<T, 9>(a[3][3], sign);
-#pragma unroll
-  for (int k1 = 0; k1 < 4; ++k1) {
-    cx<T> t[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
-    dft4(t, sign);
-#pragma unroll
-    for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
-  }
 }
 
 // Odd radix R in {3,5,7}: pair r with R-r,
@@ -189,7 +132,6 @@ __device__ __forceinline__ void dft(cx<T>* v, int sign) {
   if constexpr (R == 2) dft2(v);
   else if constexpr (R == 4) dft4(v, sign);
   else if constexpr (R == 8) dft8(v, sign);
-  else if constexpr (R == 16) dft16(v, sign);
   else dft_odd<T, R>(v, sign);
 }
 
@@ -279,8 +221,7 @@ __device__ __forceinline__ void fft_stage_r(int R, const lds<vec2<T>>* src, lds<
   }
 }
 
-// All stages of class C (radices packed 4 bits per stage, first stage lowest,
-// radix 16 as 0),
+// All stages of class C (radices packed 4 bits per stage, first stage lowest),
 // alternating between the two buffers; returns the buffer holding the result.
 template <typename T, int SIGN>
 __device__ __forceinline__ lds<vec2<T>>* fft_run(lds<vec2<T>>* b0, lds<vec2<T>>* b1, const lds<vec2<T>>* tw,
@@ -291,8 +232,7 @@ __device__ __forceinline__ lds<vec2<T>>* fft_run(lds<vec2<T>>* b0, lds<vec2<T>>*
   unsigned long long radices = C.radpack;
   int Ns = 1, rem = n;   // rem = n / Ns
   for (int s = 0; s < nst; ++s) {
-    const int code = (int)(radices & 15u);   // radix 16 is stored as 0
-    const int R = code == 0 ? 16 : code;
+    const int R = (int)(radices & 15u);
     radices >>= 4;
     const int tws = rem / R;
     if (s == 0) fft_stage_r<T, true, SIGN>(R, src, dst, tw, n, Ns, tws, lgB, Bp);
@@ -381,8 +321,7 @@ __device__ __forceinline__ void fft_run_ip(lds<vec2<T>>* buf, const lds<vec2<T>>
   unsigned long long radices = C.radpack;
   int Ns = 1, rem = n;
   for (int s = 0; s < nst; ++s) {
-    const int code = (int)(radices & 15u);   // radix 16 is stored as 0
-    const int R = code == 0 ? 16 : code;
+    const int R = (int)(radices & 15u);
     radices >>= 4;
     const int tws = rem / R;
     if (s == 0) fft_stage_ip_r<T, true, SIGN>(R, buf, tw, n, Ns, tws, lgB, Bp);

@@ -273,7 +273,7 @@ se::FftClass make_class(int n, int n_in, int n_out, const void* in, void* out,
   c.n_out = n_out;
   radix_plan(n, c.rad, &c.nst);
   c.radpack = 0;
-  for (int k = 0; k < c.nst; ++k) c.radpack |= (unsigned long long)(c.rad[k] & 15) << (4 * k);   // 16 -> 0
+  for (int k = 0; k < c.nst; ++k) c.radpack |= (unsigned long long)c.rad[k] << (4 * k);
   c.in = in;
   c.out = out;
   c.in_st = in_st;

@@ -62,10 +62,15 @@ def roofline(stages, prec, workload_P=None):
 
 
 def _source_sha():
+    """Hash of the kernel and planner sources without comments and blank lines
+    (a stored HBM byte count stays valid across comment edits only)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in ("se_kernels.hip", "se_fft.hip", "se_plan.cpp", "se_internal.h", "se_device.h"):
-        h.update(open(os.path.join(ROOT, "paper_1712_04732_amd", "csrc", f), "rb").read())
+        text = open(os.path.join(ROOT, "paper_1712_04732_amd", "csrc", f)).read()
+        code = [ln.rstrip() for ln in (re.sub(r"//.*", "", x) for x in text.split("\n"))]
+        h.update("\n".join(ln for ln in code if ln.strip()).encode())
     return h.hexdigest()[:16]
 
 

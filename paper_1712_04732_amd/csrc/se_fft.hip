@@ -3,8 +3,10 @@
 //
 // One workgroup transforms B pencils of one length-n class at once: it loads
 // them into LDS (zero padding up to n), runs mixed-radix (2,3,4,5,7,8)
-// Stockham stages between two LDS buffers, and stores the first n_out samples
-// (truncation).  Real-to-complex and complex-to-real passes transform two real
+// Stockham stages in place in one LDS buffer (each thread holds its
+// butterflies of a stage in registers across a barrier; blocks above 2048
+// samples alternate between two buffers instead), and stores the first n_out
+// samples (truncation).  Real-to-complex and complex-to-real passes transform two real
 // pencils as the real and imaginary parts of one complex pencil.  The fused
 // pass runs the forward transform, the scaling of Eq. (scale) and the inverse
 // transform of a pencil without leaving LDS.

@@ -116,7 +116,7 @@ def cpu_baseline(cfg, x, q, budget_s=15.0):
                       f"{N} sources, potential and gradient, {dt:.1f} s"}, tg, phi, grad
 
 
-def batch_cpu_baseline(systems, budget_s=15.0, per_sys_targets=256):
+def batch_cpu_baseline(systems, budget_s=15.0, per_sys_targets=64):
     """The direct FP64 oracle on the host cores for sampled targets of the
     first systems of the batch, until the time budget is used."""
     import numpy as np

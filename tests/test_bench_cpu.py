@@ -1,0 +1,83 @@
+"""Host-side parts of bench.py (no GPU): the one-GPU contract, the roofline
+object, the stored HBM byte counts and their source hash, and the schedule
+file round trip."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_roofline_picks_the_dominant_stage_and_binding_peak():
+    st = [{"name": "spread", "ms_total": 3.0, "ms_avg": 3.0, "bytes": 1e9, "flops": 1e12},
+          {"name": "fft2", "ms_total": 4.0, "ms_avg": 4.0, "bytes": 4e9, "flops": 4e10}]
+    r = bench.roofline(st, "f32", None)
+    assert r["ms_avg"] == 4.0 and r["bound"] == "hbm"
+    assert r["achieved"] == pytest.approx(4e9 / 4e-3 / 1e9)
+    assert r["frac"] == pytest.approx(r["achieved"] / r["peak"])
+    st[1]["flops"] = 1e15   # now the flop rate binds
+    r = bench.roofline(st, "f32", None)
+    assert r["bound"] == "alu" and r["unit"] == "TFLOP/s"
+
+
+def test_stored_traffic_only_for_its_sources_and_workload():
+    """A stored HBM byte count is reported only while the sources it was
+    measured on are unchanged (comments aside) and for its own workload."""
+    t = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))["fft2"]
+    st = [{"name": "fft2", "ms_total": 4.0, "ms_avg": 4.0, "bytes": 4e9, "flops": 4e10}]
+    same = t["source_sha"] == bench._source_sha()
+    got = bench.roofline(st, "f32", t["P"])["traffic"]
+    assert got == (pytest.approx(t["bytes_per_launch"]) if same else None)
+    assert bench.roofline(st, "f32", t["P"] + 2)["traffic"] is None
+
+
+def test_source_hash_ignores_comments(tmp_path, monkeypatch):
+    import shutil
+    csrc = os.path.join(ROOT, "paper_1712_04732_amd", "csrc")
+    fake = tmp_path / "paper_1712_04732_amd" / "csrc"
+    shutil.copytree(csrc, fake)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    h0 = bench._source_sha()
+    f = fake / "se_fft.hip"
+    f.write_text("// a comment line\n" + f.read_text().replace("namespace se {", "namespace se {  // trailing"))
+    assert bench._source_sha() == h0
+    f.write_text(f.read_text().replace("namespace se {", "namespace se {   \n\n", 1))
+    assert bench._source_sha() == h0        # trailing blanks and blank lines
+    f.write_text(f.read_text() + "\nint extra_symbol;\n")
+    assert bench._source_sha() != h0
+
+
+def test_schedule_round_trip(tmp_path):
+    from paper_1712_04732_amd import _lib as L
+    ps = []
+    for D, M in ((3, 32), (0, 48)):
+        p = L.se_params()
+        p.D, p.M = D, M
+        p.tile3[0], p.tile3[1], p.tile3[2] = 16, 16, 8
+        p.fft_cap, p.xcd_tiles, p.xcd_fft, p.spread_mode = 4096, 8, -1, 3
+        ps.append(p)
+    path = str(tmp_path / "s.json")
+    bench._save_schedule(path, ps)
+    qs = []
+    for D, M in ((3, 32), (0, 48)):
+        q = L.se_params()
+        q.D, q.M = D, M
+        qs.append(q)
+    assert bench._load_schedule(path, qs)
+    for p, q in zip(ps, qs):
+        assert list(q.tile3) == list(p.tile3) and q.fft_cap == p.fft_cap
+        assert (q.xcd_tiles, q.xcd_fft, q.spread_mode) == (p.xcd_tiles, p.xcd_fft, p.spread_mode)
+    qs[1].M = 50   # a schedule for other systems is not applied
+    assert not bench._load_schedule(path, qs)

@@ -472,41 +472,43 @@ __device__ __forceinline__ void fft_load(const FftClass& C, int b0s, int b1, int
     for (int i = threadIdx.x + kFftBlock; i < n; i += kFftBlock) tw[i] = gld(reinterpret_cast<const V2*>(C.tw))[i];
   };
   if constexpr (KIND == K_C2R) {
-    // slots (t, complex pencil c), c < B / 2^pair: pencils 2c, 2c + 1 (paired) or c
+    // slots (t, complex pencil c) over the stored half t <= n/2, c < B / 2^pair:
+    // pencils a = 2c, b = 2c + 1 (paired) or a = c.  Each stored bin is read
+    // once and gives, by Hermitian symmetry, Z_t = A_t + i B_t and, for
+    // 0 < t < n - t, Z_{n-t} = conj(A_t) + i conj(B_t).
     constexpr OFF esz = 2 * sizeof(T);
     const int lgF = lgB - pair;
     const char* base = (const char*)C.in + ((long long)b0s * C.in_s0 + (long long)b1 * C.in_s1) * (long long)esz;
     const OFF gs0 = (OFF)C.in_s0 * esz, gst = (OFF)C.in_st * esz;
     const OFF gsp = gs0 << pair;
-    const int total = n << lgF, h = n >> 1, F = 1 << lgF;
-    SlotWalk<TF, OFF> w(n, lgF, gsp, (OFF)0, Bp, 1);   // g tracks the pencil part only
+    const int nh = (n >> 1) + 1, total = nh << lgF, F = 1 << lgF;
+    SlotWalk<TF, OFF> w(nh, lgF, gsp, (OFF)0, Bp, 1);   // g tracks the pencil part only
     for (int e0 = 0; e0 < total; e0 += U * kFftBlock) {
-      cx<T> v[U];
-      int lw[U];
+      V2 va[U], vb[U];
+      int lw[U], tt[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        v[u] = cx<T>{0, 0};
+        va[u] = V2{0, 0};
+        vb[u] = V2{0, 0};
         const int pa = w.p << pair;
-        const bool up = w.t <= h;
-        const int ts = up ? w.t : n - w.t;
-        const T sg = up ? (T)1 : (T)-1;   // Hermitian extension of the stored half
-        const OFF go = w.g + (TF ? (OFF)ts * esz : (OFF)ts * gst);
-        if (w.t < n && pa < cnt) {
-          const V2 a = gload<V2>(base, go);
-          v[u] = cx<T>{a.x, sg * a.y};
-          if (pair && pa + 1 < cnt) {
-            const V2 bb = gload<V2>(base, go + gs0);
-            v[u].re -= sg * bb.y;
-            v[u].im += bb.x;
-          }
+        const OFF go = w.g + (TF ? (OFF)w.t * esz : (OFF)w.t * gst);
+        if (w.t < nh && pa < cnt) {
+          va[u] = gload<V2>(base, go);
+          if (pair && pa + 1 < cnt) vb[u] = gload<V2>(base, go + gs0);
         }
-        lw[u] = (w.t < n && w.p < F) ? w.l : -1;
+        lw[u] = (w.t < nh && w.p < F) ? w.l : -1;
+        tt[u] = w.t;
         w.step();
       }
       if (e0 == 0) put_twiddles();
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (lw[u] >= 0) lput<T>(buf, lw[u], v[u]);
+      for (int u = 0; u < U; ++u) {
+        if (lw[u] < 0) continue;
+        const V2 a = va[u], b = vb[u];
+        lput<T>(buf, lw[u], cx<T>{a.x - b.y, a.y + b.x});
+        const int t = tt[u];
+        if (t > 0 && t < n - t) lput<T>(buf, lw[u] + __mul24(n - 2 * t, Bp), cx<T>{a.x + b.y, b.x - a.y});
+      }
     }
   } else {
     // slots (t, pencil p), p < B; a paired real pass packs pencil p into

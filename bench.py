@@ -333,6 +333,126 @@ def main_batch(args):
     print(json.dumps(result), flush=True)
 
 
+def kp_real_cutoff(Q, xi, L, tol):
+    """Smallest cutoff whose real-space error estimate, Eq. (KP_real_space),
+    sqrt(Q) xi^-2 (L rc)^-3/2 exp(-(xi rc)^2), is at most tol (bisection on the
+    decreasing branch)."""
+    est = lambda rc: math.sqrt(Q) / xi ** 2 * (L * rc) ** -1.5 * math.exp(-(xi * rc) ** 2)
+    lo, hi = 0.5 / xi, 1.0 / xi
+    while est(hi) > tol:
+        hi *= 1.5
+    for _ in range(100):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if est(mid) > tol else (lo, mid)
+    return hi
+
+
+def pairs_within(D, L, rc, x, n_sample=20000, seed=11):
+    """Mean number of other charges within rc of a charge (periodic images in
+    the first D directions), counted exactly for a sample of charges."""
+    import numpy as np
+    from scipy.spatial import cKDTree
+    pts = [x]
+    for d in range(D):                  # images across the periodic faces within rc
+        new = []
+        for p in pts:
+            lo = p[p[:, d] < rc].copy()
+            lo[:, d] += L
+            hi = p[p[:, d] >= L - rc].copy()
+            hi[:, d] -= L
+            new += [lo, hi]
+        pts += new
+    tree = cKDTree(np.concatenate(pts))
+    idx = np.random.default_rng(seed).choice(x.shape[0], size=min(n_sample, x.shape[0]), replace=False)
+    cnt = tree.query_ball_point(x[idx], rc, return_length=True)
+    return float(np.mean(cnt)) - 1.0
+
+
+# Arithmetic of one pair term of Eq. (real_space_ewald) and its gradient as
+# written: difference (3), r^2 (5), r and 1/r (2), erfc and exp (1 each),
+# the potential term (2), the gradient factor (5) and its three products and
+# sums (6).
+PAIR_FLOPS = 25
+
+
+def main_real_space(args):
+    """The real-space part (Eq. real_space_ewald) on the GPU for one of the
+    single-system workloads, at the cutoff of Eq. (KP_real_space) for the same
+    1e-6 relative tolerance as the k-space part."""
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    from oracle.se_discrete import B_scale   # only the B normalisation of the tolerance
+    from paper_1712_04732_amd import RealSpace
+
+    name = args.workload if args.workload in wl.CONFIGS else "C4_1P"
+    cfg = wl.CONFIGS[name]
+    D, N, L, xi = cfg["D"], cfg["N"], cfg["L"], cfg["xi"]
+    x, q = wl.config_system(name)
+    Q = float((q * q).sum())
+    rc = kp_real_cutoff(Q, xi, L, 1e-6 * B_scale(Q, xi, L))
+    dev = torch.device("cuda:0")
+    xt = torch.tensor(x, dtype=torch.float64, device=dev)
+    qt = torch.tensor(q, dtype=torch.float64, device=dev)
+    res = {}
+    for prec in ("f32", "f64"):
+        rs = RealSpace(D, L, xi, rc, prec=prec, n_max=N)
+        dt = rs.dtype
+        out = (torch.empty(N, dtype=dt, device=dev), torch.empty((N, 3), dtype=dt, device=dev),
+               torch.empty((), dtype=torch.float64, device=dev))
+        rs(xt, qt, out=out, check=True)
+        for _ in range(args.warmup):
+            rs(xt, qt, out=out, check=False)
+        torch.cuda.synchronize()
+        rs.profile(reset=True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            rs(xt, qt, out=out, check=False, profile=True)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        st = {r["name"]: r["ms_avg"] for r in rs.profile(reset=True)}
+        res[prec] = (ms, st, [t.double().cpu().numpy() for t in out], rs.cells, rs.span)
+        print(f"bench real space {prec}: {ms:.4f} ms/step, stages {st}", file=sys.stderr, flush=True)
+    ms32, st32, (phi32, f32, e32), cells, span = res["f32"]
+    ms64, st64, (phi64, f64, e64), _, _ = res["f64"]
+    npair = pairs_within(D, L, rc, x)
+    flops = N * npair * PAIR_FLOPS
+    t_pairs = st32["rs_pairs"] * 1e-3
+    err = {"phi_f32_vs_f64": rel_rms(phi32, phi64), "force_f32_vs_f64": rel_rms(f32, f64),
+           "energy_f32_vs_f64": float(abs(e32 - e64) / abs(e64))}
+    result = {
+        "metric": "particles/s, real-space part (potential+force+energy) at the 1e-6 cutoff",
+        "value": N / (ms32 * 1e-3), "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms32, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": name + "_real_space", "D": D, "N": N, "L": L, "xi": xi, "rc": rc,
+                   "cells": cells, "span": span, "pairs_per_particle": npair},
+        "fp64_value": N / (ms64 * 1e-3), "fp64_ms_per_step": ms64,
+        "stages_ms": st32, "stages_ms_fp64": st64,
+        "roofline": {"bound": "alu", "achieved": flops / t_pairs / 1e12, "peak": ALU_PEAK["f32"] / 1e12,
+                     "unit": "TFLOP/s", "frac": flops / t_pairs / ALU_PEAK["f32"], "traffic": None,
+                     "kernel": "rs_sum_kernel<float, true> (rs_pairs)", "ms_avg": st32["rs_pairs"],
+                     "alg_flops": flops},
+        "errors": err,
+    }
+    if not args.no_cpu_baseline:
+        from oracle import direct
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        tg = np.sort(np.random.default_rng(7).choice(N, size=min(N, 2048), replace=False))
+        t0 = time.perf_counter()
+        phi_o, grad_o = direct.real_space(D, L, xi, rc, x, q, targets=tg)
+        dt = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": len(tg) / dt, "unit": "particles/s", "cores": cores, "kind": "oracle",
+                                  "sample": f"direct FP64 real-space sum for {len(tg)} of {N} targets against "
+                                            f"all {N} sources and their images within rc, {dt:.1f} s"}
+        err["phi_f32_vs_oracle"] = rel_rms(phi32[tg], phi_o)
+        err["phi_f64_vs_oracle"] = rel_rms(phi64[tg], phi_o)
+        err["force_f32_vs_oracle"] = rel_rms(f32[tg], -q[tg, None] * grad_o)
+        err["force_f64_vs_oracle"] = rel_rms(f64[tg], -q[tg, None] * grad_o)
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -344,6 +464,8 @@ def main():
     ap.add_argument("--retune", action="store_true", help="batch: run the autotuner even if a schedule is stored")
     ap.add_argument("--schedule", default=None, help="batch: stored schedule (JSON) to use")
     ap.add_argument("--save-schedule", default=None, help="batch: write the autotuner's schedule here")
+    ap.add_argument("--real-space", action="store_true",
+                    help="time the real-space part instead (single-system workloads; default C4_1P)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device 5 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -362,6 +484,8 @@ def main():
               "MI355X; multi-GPU sharding is a design note, not a measured configuration.",
               file=sys.stderr)
         sys.exit(2)
+    if args.real_space:
+        return main_real_space(args)
     if args.workload == "C5_batch":
         return main_batch(args)
 

@@ -129,6 +129,7 @@ typedef struct se_plan se_plan;
 #define SE_ALLOW_NONNEUTRAL 0x10u /* skip the neutrality check (adjoint passes whose
                                      'charges' are cotangents)                     */
 #define SE_PROFILE     0x20u  /* record a HIP event pair around every kernel launch */
+#define SE_ACCUMULATE  0x40u  /* se_rs_eval: add into phi, force and energy       */
 
 /* Fill *out with the paper's parameter rules (Section 6) for a system of N
  * charges with sum of squares Q: shape, nu, lambda, s0, and s, n_l from the
@@ -286,6 +287,71 @@ se_status se_autotune(const se_params* params, long N, const void* xyz, const vo
  * tuned: host array of n_sys params. */
 se_status se_batch_autotune(const se_params* params, const long* N, int n_sys, const void* xyz, const void* q,
                             unsigned flags, void* hip_stream, se_params* tuned, se_tune_report* report);
+
+/* ---- Real-space part on the GPU ----------------------------------------
+ * The short-range sum of the Ewald split, Eq. (real_space_ewald):
+ *   phi^R_m = sum_{p in P_D} sum_n' q_n erfc(xi r) / r,  r = |x_m - x_n + p|,
+ * over the pairs with r < rc (the prime drops n = m at p = 0), and its
+ * gradient.  Together with se_eval (SE_ADD_SELF) it gives the full potential
+ * phi = phi^R + phi^F + phi^self of Eq. (potential_split); the error of the
+ * cutoff is bounded by Eq. (KP_real_space) of Section 5.2.
+ * Positions and charges follow the conventions above (periodic coordinates
+ * wrapped, free ones in [0, L)).  A cell list of c^3 cells with c <= cells_per_rc
+ * L / rc serves the pair search; charges are ordered by cell and, inside a
+ * cell of at most 2048 charges, by input index, so results repeat bit for
+ * bit from run to run. */
+typedef struct se_rs_plan se_rs_plan;
+
+/* Cells per direction and neighbour span (host only, no device work):
+ * c = max(1, min(floor(cells_per_rc L / rc), floor(cbrt(n_max)), 160)) and the
+ * smallest s with s L / c >= rc, so every pair within rc lies in the
+ * (2s+1)^3 cells around a charge's cell.  cells_per_rc <= 0 means 2.
+ * Errors: SE_ERR_ARG for NULL outputs; SE_ERR_PARAM for L, rc not positive
+ * and finite, n_max < 0 or cells_per_rc > 8. */
+se_status se_rs_cells(double L, double rc, long n_max, int cells_per_rc, int* cells, int* span);
+
+/* A real-space plan for up to n_max charges of periodicity D in a box of side
+ * L with Ewald parameter xi and cutoff rc, sums in precision prec.  Allocates
+ * one device buffer (cell counts and offsets, sorted records, energy
+ * partials) that the plan owns until se_rs_plan_destroy.
+ * Errors: SE_ERR_ARG (out NULL), SE_ERR_PARAM (D, xi, prec, n_max > 2^31-1,
+ * or as se_rs_cells), SE_ERR_NOMEM. */
+se_status se_rs_plan_create(int D, double L, double xi, double rc, long n_max, se_precision prec,
+                            int cells_per_rc, void* hip_stream, se_rs_plan** out);
+
+/* Cells per direction, span and device bytes of a plan (host outputs, each
+ * may be NULL).  Errors: SE_ERR_ARG for plan NULL. */
+se_status se_rs_get_info(const se_rs_plan* plan, int* cells, int* span, size_t* device_bytes);
+
+/* One evaluation for N <= n_max charges.
+ *   xyz, q  device, as for se_eval (float64, or float32 with SE_IN_F32)
+ *   phi     device, N values phi^R in the plan's precision, or NULL
+ *   force   device, N x 3: -q grad phi^R, or grad phi^R with SE_OUT_GRAD, or NULL
+ *   energy  device, one float64: E^R = 1/2 sum_m q_m phi^R_m, or NULL
+ * With SE_ACCUMULATE the results are added to what phi, force and energy
+ * hold (for example the output of se_eval on the same charges).  N = 0 writes
+ * a zero energy (or leaves it with SE_ACCUMULATE).
+ * Flags: SE_IN_F32, SE_OUT_GRAD, SE_ACCUMULATE, SE_SYNC_CHECK, SE_PROFILE.
+ * Errors: SE_ERR_ARG (pointers, N, flags); with SE_SYNC_CHECK also
+ * SE_ERR_NONFINITE, SE_ERR_OUT_OF_BOX and SE_ERR_DEVICE. */
+se_status se_rs_eval(se_rs_plan* plan, long N, const void* xyz, const void* q, void* phi, void* force,
+                     double* energy, unsigned flags, void* hip_stream);
+
+/* Wait for the stream, then report and clear the plan's device status word. */
+se_status se_rs_get_device_status(se_rs_plan* plan, void* hip_stream);
+
+/* Wait for the stream, then report the se_rs_eval calls made with SE_PROFILE
+ * since the last reset (a pool of 1024 calls; later ones are not recorded):
+ * three records, "rs_cells" (binning, scan, scatter and ordering by cell),
+ * "rs_pairs" (the pair sums) and "rs_energy", with the summed HIP-event time
+ * and the number of calls; bytes and flops are left 0 (the pair count
+ * depends on the input).  At most 'cap' records into host 'out', count in
+ * *n; reset != 0 clears the sums.  Errors: SE_ERR_ARG, SE_ERR_DEVICE. */
+se_status se_rs_plan_profile(se_rs_plan* plan, void* hip_stream, se_stage_record* out, int cap, int* n,
+                             int reset);
+
+/* Release the plan's device memory.  NULL is accepted. */
+se_status se_rs_plan_destroy(se_rs_plan* plan);
 
 /* Static English text of a status code. */
 const char* se_status_string(se_status s);

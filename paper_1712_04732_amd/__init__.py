@@ -5,8 +5,8 @@ the C ABI of include/se.h).  This package holds the ctypes binding (_lib), the
 torch-facing plan and autograd adjoint (api), and the build script (build_lib).
 """
 from . import _lib
-from .api import (SEEnergy, SEPotential, SpectralEwald, SpectralEwaldBatch, params_for_tolerance,
+from .api import (RealSpace, SEEnergy, SEPotential, SpectralEwald, SpectralEwaldBatch, params_for_tolerance,
                   self_potential)
 
-__all__ = ["SpectralEwald", "SpectralEwaldBatch", "SEEnergy", "SEPotential", "params_for_tolerance",
+__all__ = ["RealSpace", "SpectralEwald", "SpectralEwaldBatch", "SEEnergy", "SEPotential", "params_for_tolerance",
            "self_potential", "_lib"]

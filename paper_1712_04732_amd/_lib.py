@@ -33,6 +33,7 @@ SE_SYNC_CHECK = 0x4
 SE_OUT_GRAD = 0x8
 SE_ALLOW_NONNEUTRAL = 0x10
 SE_PROFILE = 0x20
+SE_ACCUMULATE = 0x40
 
 
 class se_params(ctypes.Structure):
@@ -144,6 +145,20 @@ _SIGS = {
     "se_autotune": (ctypes.c_int, [ctypes.POINTER(se_params), ctypes.c_long, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_uint, ctypes.c_void_p, ctypes.POINTER(se_params),
                                    ctypes.POINTER(se_tune_report)]),
+    "se_rs_cells": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_long, ctypes.c_int,
+                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "se_rs_plan_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_long, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_void_p)]),
+    "se_rs_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                      ctypes.POINTER(ctypes.c_size_t)]),
+    "se_rs_eval": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_long, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint,
+                                  ctypes.c_void_p]),
+    "se_rs_get_device_status": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "se_rs_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "se_rs_plan_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(se_stage_record),
+                                          ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
     "se_batch_autotune": (ctypes.c_int, [ctypes.POINTER(se_params), ctypes.POINTER(ctypes.c_long), ctypes.c_int,
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint, ctypes.c_void_p,
                                          ctypes.POINTER(se_params), ctypes.POINTER(se_tune_report)]),
@@ -290,6 +305,49 @@ def se_batch_autotune(params, N, xyz_ptr, q_ptr, flags, stream):
                                     ctypes.c_void_p(stream), outs, ctypes.byref(rep)), "se_batch_autotune")
     return [outs[i] for i in range(n)], dict(candidates=rep.candidates, ms_default=rep.ms_default,
                                              ms_tuned=rep.ms_tuned)
+
+
+def se_rs_cells(L, rc, n_max, cells_per_rc=0):
+    """(cells per direction, neighbour span) of the real-space cell list."""
+    c, sp = ctypes.c_int(), ctypes.c_int()
+    _check(load().se_rs_cells(float(L), float(rc), int(n_max), int(cells_per_rc), ctypes.byref(c), ctypes.byref(sp)),
+           "se_rs_cells")
+    return c.value, sp.value
+
+
+def se_rs_plan_create(D, L, xi, rc, n_max, prec, cells_per_rc=0, stream=0):
+    plan = ctypes.c_void_p()
+    _check(load().se_rs_plan_create(int(D), float(L), float(xi), float(rc), int(n_max), int(prec),
+                                    int(cells_per_rc), ctypes.c_void_p(stream), ctypes.byref(plan)),
+           "se_rs_plan_create")
+    return plan
+
+
+def se_rs_get_info(plan):
+    c, sp, b = ctypes.c_int(), ctypes.c_int(), ctypes.c_size_t()
+    _check(load().se_rs_get_info(plan, ctypes.byref(c), ctypes.byref(sp), ctypes.byref(b)), "se_rs_get_info")
+    return c.value, sp.value, b.value
+
+
+def se_rs_eval(plan, N, xyz_ptr, q_ptr, phi_ptr, force_ptr, energy_ptr, flags, stream) -> int:
+    """Returns the status (callers decide whether to raise)."""
+    return load().se_rs_eval(plan, int(N), ctypes.c_void_p(xyz_ptr), ctypes.c_void_p(q_ptr),
+                             ctypes.c_void_p(phi_ptr), ctypes.c_void_p(force_ptr), ctypes.c_void_p(energy_ptr),
+                             ctypes.c_uint(flags), ctypes.c_void_p(stream))
+
+
+def se_rs_plan_profile(plan, stream, reset=True):
+    """Records {name, launches, ms_total, ms_avg} of rs_cells, rs_pairs, rs_energy."""
+    arr = (se_stage_record * 4)()
+    n = ctypes.c_int()
+    _check(load().se_rs_plan_profile(plan, ctypes.c_void_p(stream), arr, 4, ctypes.byref(n), int(reset)),
+           "se_rs_plan_profile")
+    return [dict(name=arr[i].name.decode(), launches=arr[i].launches, ms_total=arr[i].ms_total,
+                 ms_avg=arr[i].ms_total / max(arr[i].launches, 1)) for i in range(n.value)]
+
+
+def se_rs_plan_destroy(plan) -> int:
+    return load().se_rs_plan_destroy(plan)
 
 
 def se_batch_plan_destroy(plan) -> int:

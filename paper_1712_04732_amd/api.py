@@ -317,6 +317,68 @@ class SEPotential(torch.autograd.Function):
         return gx, gq, None, None
 
 
+class RealSpace:
+    """The real-space sum of the Ewald split, Eq. (real_space_ewald), with
+    cutoff rc, on the GPU (cell list in the HIP library).  Adds to a k-space
+    result of SpectralEwald (accumulate=True) to give the full potential of
+    Eq. (potential_split)."""
+
+    def __init__(self, D, L_box, xi, rc, *, prec="f64", n_max=1 << 20, cells_per_rc=0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("RealSpace needs a HIP device")
+        L.load()
+        self.D, self.L, self.xi, self.rc = D, L_box, xi, rc
+        self.prec = prec
+        self.dtype = torch.float64 if prec == "f64" else torch.float32
+        self.n_max = int(n_max)
+        self._plan = L.se_rs_plan_create(D, L_box, xi, rc, self.n_max, _PRECS[prec], cells_per_rc, _stream())
+        self.cells, self.span, self.device_bytes = L.se_rs_get_info(self._plan)
+
+    def __del__(self):
+        plan = getattr(self, "_plan", None)
+        if plan is not None and plan.value:
+            try:
+                L.se_rs_plan_destroy(plan)
+            except Exception:
+                pass
+            self._plan = None
+
+    def profile(self, reset=True):
+        """HIP-event times of the evaluations made with profile=True."""
+        return L.se_rs_plan_profile(self._plan, _stream(), reset)
+
+    def evaluate(self, x, q, *, phi=True, force=True, energy=True, out_grad=False, accumulate=False,
+                 check=True, profile=False, out=None):
+        """Returns (phi^R, force_or_grad, E^R); with accumulate=True the
+        results are added into out = (phi, force, energy)."""
+        x, q = _device_pair(x, q)
+        N = x.shape[0]
+        dev = x.device
+        if out is not None:
+            out_phi, out_f, out_e = out
+        elif accumulate:
+            raise ValueError("accumulate=True needs out")
+        else:
+            out_phi = torch.empty(N, dtype=self.dtype, device=dev) if phi else None
+            out_f = torch.empty((N, 3), dtype=self.dtype, device=dev) if force else None
+            out_e = torch.empty((), dtype=torch.float64, device=dev) if energy else None
+        for t, shape, dt in ((out_phi, (N,), self.dtype), (out_f, (N, 3), self.dtype), (out_e, (), torch.float64)):
+            if t is not None and (tuple(t.shape) != shape or t.dtype != dt or not t.is_contiguous()):
+                raise ValueError("output tensors must be contiguous with the plan's shapes and dtypes")
+        flags = (L.SE_IN_F32 if x.dtype == torch.float32 else 0) | (L.SE_OUT_GRAD if out_grad else 0) | (
+            L.SE_ACCUMULATE if accumulate else 0) | (L.SE_SYNC_CHECK if check else 0) | (
+            L.SE_PROFILE if profile else 0)
+        st = L.se_rs_eval(self._plan, N, x.data_ptr(), q.data_ptr(),
+                          out_phi.data_ptr() if out_phi is not None else 0,
+                          out_f.data_ptr() if out_f is not None else 0,
+                          out_e.data_ptr() if out_e is not None else 0, flags, _stream())
+        if st != L.SE_OK:
+            raise L.SEError(st, "se_rs_eval")
+        return out_phi, out_f, out_e
+
+    __call__ = evaluate
+
+
 def self_potential(xi, q):
     """phi_self = -2 xi / sqrt(pi) q (Section 2)."""
     return -2.0 * xi / math.sqrt(math.pi) * q

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libse_mi355x.so")
-SOURCES = ["se_kernels.hip", "se_fft.hip", "se_plan.cpp"]
+SOURCES = ["se_kernels.hip", "se_fft.hip", "se_real.hip", "se_plan.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

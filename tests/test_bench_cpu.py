@@ -81,3 +81,28 @@ def test_schedule_round_trip(tmp_path):
         assert (q.xcd_tiles, q.xcd_fft, q.spread_mode) == (p.xcd_tiles, p.xcd_fft, p.spread_mode)
     qs[1].M = 50   # a schedule for other systems is not applied
     assert not bench._load_schedule(path, qs)
+
+
+def test_real_space_cutoff_meets_the_estimate():
+    """The cutoff solves Eq. (KP_real_space) for the tolerance: the estimate
+    is at the tolerance there and above it just below."""
+    import math
+    Q, xi, L, tol = 1e6, 56.4, 1.0, 3e-4
+    rc = bench.kp_real_cutoff(Q, xi, L, tol)
+    est = lambda r: math.sqrt(Q) / xi ** 2 * (L * r) ** -1.5 * math.exp(-(xi * r) ** 2)
+    assert est(rc) <= tol and est(rc * (1 - 1e-9)) > tol * (1 - 1e-6)
+    assert est(0.99 * rc) > tol
+
+
+@pytest.mark.parametrize("D", [3, 2, 1, 0])
+def test_pair_count_matches_brute_force(D):
+    import numpy as np
+    rng = np.random.default_rng(5 + D)
+    N, L, rc = 400, 1.0, 0.23
+    x = rng.random((N, 3)) * L
+    d = x[:, None, :] - x[None, :, :]
+    for k in range(D):                  # nearest image in the periodic directions (rc < L/2)
+        d[..., k] -= L * np.round(d[..., k] / L)
+    r = np.sqrt((d * d).sum(-1))
+    brute = (np.count_nonzero(r < rc) - N) / N
+    assert abs(bench.pairs_within(D, L, rc, x, n_sample=N) - brute) < 1e-12

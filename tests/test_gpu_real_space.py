@@ -1,0 +1,219 @@
+"""GPU parity of the real-space sum, Eq. (real_space_ewald), against the direct
+FP64 oracle (oracle/ewald_direct.cpp), element by element:
+
+  * FP64: relative rms 1e-13 in phi^R and grad phi^R, energy 1e-12 (the two sum
+    the same pairs; only the order of the additions differs).
+  * FP32: relative rms 1e-5 (positions and sums rounded to FP32).
+
+Cutoffs are taken with xi rc = 4.8, so a pair that sits on the cutoff within
+rounding contributes below 1e-11 and cannot decide a comparison.  Cases: every
+periodicity, cutoffs that give one cell per direction (rc above the box side,
+several periodic images of the same cell), two cells, and many cells; ragged
+and empty cells; a cluster holding more charges than one cell sorts; empty and
+one-charge inputs; float32 inputs; accumulation; device status errors; and the
+full potential (real space + k space + self term, all on the GPU) against the
+Madelung constants of rock salt, the square lattice and the alternating chain.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import direct
+from oracle import se_discrete as se
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1712_04732_amd import RealSpace, SpectralEwald, _lib  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def run(rs, x, q, dtype=torch.float64, **kw):
+    xt = torch.tensor(x, dtype=dtype, device=DEV)
+    qt = torch.tensor(q, dtype=dtype, device=DEV)
+    phi, g, E = rs(xt, qt, out_grad=True, **kw)
+    torch.cuda.synchronize()
+    return phi.double().cpu().numpy(), g.double().cpu().numpy(), float(E)
+
+
+def oracle(D, L, xi, rc, x, q):
+    phi, g = direct.real_space(D, L, xi, rc, x, q)
+    return phi, g, 0.5 * float(np.dot(q, phi))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("rc", [0.12, 0.3, 0.7, 1.6])
+@pytest.mark.parametrize("D", [3, 2, 1, 0])
+def test_parity_with_oracle(D, rc, prec):
+    print(f"case real space D={D} rc={rc} {prec}", flush=True)
+    N, L = 700, 1.0
+    xi = 4.8 / rc
+    x, q = wl.system(N, L, 500 + D, "uniform")
+    rs = RealSpace(D, L, xi, rc, prec=prec, n_max=N)
+    phi, g, E = run(rs, x, q)
+    pr, gr, Er = oracle(D, L, xi, rc, x, q)
+    tol = 1e-13 if prec == "f64" else 1e-5
+    print(f"  cells {rs.cells} span {rs.span}: phi {rel(phi, pr):.2e} grad {rel(g, gr):.2e} "
+          f"energy {abs(E - Er) / abs(Er):.2e}")
+    assert rel(phi, pr) < tol
+    assert rel(g, gr) < 10 * tol
+    assert abs(E - Er) <= (1e-12 if prec == "f64" else 1e-5) * abs(Er)
+
+
+@pytest.mark.parametrize("cells_per_rc", [1, 3])
+def test_cell_choice_does_not_change_the_sum(cells_per_rc):
+    """One and three cells per cutoff (span 1 and 3, corner cells skipped)
+    sum the same pairs as the oracle."""
+    N, L, rc, D = 3400, 1.0, 0.2, 3
+    xi = 4.8 / rc
+    x, q = wl.system(N, L, 610 + cells_per_rc, "pm1")
+    rs = RealSpace(D, L, xi, rc, prec="f64", n_max=N, cells_per_rc=cells_per_rc)
+    assert rs.span == cells_per_rc
+    phi, g, E = run(rs, x, q)
+    pr, gr, Er = oracle(D, L, xi, rc, x, q)
+    assert rel(phi, pr) < 1e-13 and rel(g, gr) < 1e-12
+
+
+def test_float32_inputs_fp64_sums():
+    N, L, rc, D = 500, 1.0, 0.25, 2
+    xi = 4.8 / rc
+    x, q = wl.system(N, L, 620, "uniform")
+    x32 = x.astype(np.float32).astype(np.float64)
+    q32 = q.astype(np.float32).astype(np.float64)
+    rs = RealSpace(D, L, xi, rc, prec="f64", n_max=N)
+    phi, g, _ = run(rs, x32, q32, dtype=torch.float32)
+    pr, gr, _ = oracle(D, L, xi, rc, x32, q32)
+    assert rel(phi, pr) < 1e-13 and rel(g, gr) < 1e-12
+
+
+def test_cluster_larger_than_a_sorted_cell():
+    """2500 charges in one cell (more than a cell sorts by index): arrival
+    order, same sums up to rounding; and coordinates on the cell and box
+    edges."""
+    N, L, rc, D = 2500, 1.0, 0.3, 3
+    xi = 4.8 / rc
+    rng = np.random.default_rng(630)
+    x = 0.5 + 0.05 * rng.random((N, 3))
+    x[:4] = [[0.0, 0.0, 0.0], [1.0 - 1e-16, 0.5, 0.5], [1.0, 0.25, 0.75], [-0.0, 2.0 - 1e-12, -3.5]]
+    q = rng.uniform(-1, 1, N)
+    q -= q.mean()
+    rs = RealSpace(D, L, xi, rc, prec="f64", n_max=N)
+    phi, g, E = run(rs, x, q)
+    xw = np.mod(x, L)
+    pr, gr, Er = oracle(D, L, xi, rc, xw, q)
+    assert rel(phi, pr) < 1e-12 and rel(g, gr) < 1e-11
+    assert abs(E - Er) <= 1e-12 * abs(Er)
+
+
+def test_empty_and_single_charge():
+    rs = RealSpace(3, 1.0, 3.0, 1.6, prec="f64", n_max=4)
+    e = torch.full((), 7.0, dtype=torch.float64, device=DEV)
+    z = torch.empty((0, 3), dtype=torch.float64, device=DEV)
+    rs(z, z[:, 0], phi=False, force=False, out=(None, None, e))
+    assert float(e) == 0.0
+    # one charge: only its own periodic images (|p| < rc) contribute
+    x = np.array([[0.3, 0.6, 0.1]])
+    q = np.array([1.0])
+    for D in (3, 2, 1, 0):
+        rsD = RealSpace(D, 1.0, 3.0, 1.6, prec="f64", n_max=4)
+        phi, g, E = run(rsD, x, q)
+        ref = sum(math.erfc(3.0 * math.sqrt(a * a + b * b + c * c)) / math.sqrt(a * a + b * b + c * c)
+                  for a in range(-2, 3) for b in range(-2, 3) for c in range(-2, 3)
+                  if (a, b, c) != (0, 0, 0) and (D >= 1 or a == 0) and (D >= 2 or b == 0)
+                  and (D >= 3 or c == 0) and a * a + b * b + c * c < 1.6 ** 2)
+        np.testing.assert_allclose(phi, [ref], rtol=1e-14, atol=0 if ref else 1e-300)
+        np.testing.assert_allclose(g, 0.0, atol=1e-14)   # images come in +-p pairs
+
+
+def test_repeatable_and_accumulate():
+    N, L, rc, D = 1200, 1.0, 0.15, 1
+    xi = 4.8 / rc
+    x, q = wl.system(N, L, 640, "pm1")
+    rs = RealSpace(D, L, xi, rc, prec="f32", n_max=N)
+    a = run(rs, x, q)
+    b = run(rs, x, q)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
+    xt = torch.tensor(x, dtype=torch.float32, device=DEV)
+    qt = torch.tensor(q, dtype=torch.float32, device=DEV)
+    g = torch.Generator(device="cpu").manual_seed(1)
+    p0 = torch.rand(N, generator=g).to(DEV)
+    f0 = torch.rand((N, 3), generator=g).to(DEV)
+    e0 = torch.tensor(0.25, dtype=torch.float64, device=DEV)
+    p1, f1, e1 = rs(xt, qt, out_grad=True, accumulate=True, out=(p0.clone(), f0.clone(), e0.clone()))
+    torch.cuda.synchronize()
+    assert torch.equal(p1, p0 + torch.tensor(a[0], dtype=torch.float32, device=DEV))
+    assert torch.equal(f1, f0 + torch.tensor(a[1], dtype=torch.float32, device=DEV))
+    assert float(e1) == 0.25 + a[2]
+
+
+def test_device_status_and_argument_errors():
+    rs = RealSpace(1, 1.0, 10.0, 0.2, prec="f64", n_max=8)
+    x = torch.rand((8, 3), dtype=torch.float64, device=DEV)
+    q = torch.zeros(8, dtype=torch.float64, device=DEV)
+    x[3, 2] = 1.5                      # free direction z outside [0, L)
+    with pytest.raises(_lib.SEError) as e:
+        rs(x, q)
+    assert e.value.status == _lib.SE_ERR_OUT_OF_BOX
+    x[3, 2] = 0.5
+    x[5, 0] = float("nan")
+    with pytest.raises(_lib.SEError) as e:
+        rs(x, q)
+    assert e.value.status == _lib.SE_ERR_NONFINITE
+    x[5, 0] = 3.25                     # periodic x: wrapped, accepted
+    rs(x, q)
+    big = torch.rand((9, 3), dtype=torch.float64, device=DEV)
+    with pytest.raises(_lib.SEError) as e:
+        rs(big, torch.zeros(9, dtype=torch.float64, device=DEV))
+    assert e.value.status == _lib.SE_ERR_ARG
+    assert _lib.se_rs_eval(rs._plan, 8, x.data_ptr(), q.data_ptr(), 0, 0, 0, 0x100, 0) == _lib.SE_ERR_ARG
+
+
+def _lattice(D, L=1.0):
+    """Alternating +-1 lattice with spacing a = L/2 (rock salt, square
+    checkerboard, chain), shifted off the symmetric points."""
+    a = L / 2
+    off = np.array([0.1234, 0.2345, 0.3456])
+    pts, qs = [], []
+    n = {3: (2, 2, 2), 2: (2, 2, 1), 1: (2, 1, 1)}[D]
+    for i in range(n[0]):
+        for j in range(n[1]):
+            for k in range(n[2]):
+                pts.append((np.array([i, j, k]) * a + off) % L)
+                qs.append((-1.0) ** (i + j + k))
+    return np.array(pts), np.array(qs), a
+
+
+@pytest.mark.parametrize("D,const", [(3, 1.747564594633182), (2, 1.615542626712880),
+                                     (1, 2.0 * math.log(2.0))])
+def test_full_potential_madelung(D, const):
+    """phi = phi^R + phi^F + phi^self (Eq. potential_split) from the GPU alone:
+    the k-space part by se_eval (PKB P = 16, error ~1e-15), the real-space part
+    accumulated into it by se_rs_eval."""
+    print(f"case madelung D={D}", flush=True)
+    x, q, a = _lattice(D)
+    xi, M, P = 6.0, 40, 16
+    Q = float((q * q).sum())
+    pp = se.with_aft_estimates(D, 1.0, xi, M, P, Q, 1e-16 * se.B_scale(Q, xi, 1.0), window="pkb")
+    ks = SpectralEwald(D, 1.0, xi, M, P, window="pkb", prec="f64", n_max=len(q),
+                       **({"s": pp.s, "n_l": pp.n_l} if D in (1, 2) else {}))
+    rs = RealSpace(D, 1.0, xi, direct.real_space_cutoff(xi), prec="f64", n_max=len(q))
+    xt = torch.tensor(x, dtype=torch.float64, device=DEV)
+    qt = torch.tensor(q, dtype=torch.float64, device=DEV)
+    out = ks(xt, qt, add_self=True, out_grad=True)
+    phi, g, E = rs(xt, qt, out_grad=True, accumulate=True, out=out)
+    torch.cuda.synchronize()
+    m = -phi.cpu().numpy() * a / q
+    print(f"  madelung D={D}: {m[0]:.15f} (cells {rs.cells}, span {rs.span})")
+    np.testing.assert_allclose(m, const, rtol=0, atol=1e-10)
+    np.testing.assert_allclose(g.cpu().numpy(), 0.0, atol=1e-8)   # every ion sits at a symmetric site
+    assert abs(float(E) - 0.5 * float(np.dot(q, -const * q / a))) < 1e-9 * len(q)

@@ -120,3 +120,32 @@ def test_autotune_null_arguments():
     assert lib.se_autotune(None, 10, None, None, 0, None, None, None) == L.SE_ERR_ARG
     assert lib.se_autotune(ctypes.byref(p), 0, None, None, 0, None, ctypes.byref(p), None) == L.SE_ERR_ARG
     assert lib.se_batch_autotune(None, None, 0, None, None, 0, None, None, None) == L.SE_ERR_ARG
+
+
+@pytest.mark.parametrize("L,rc,n_max,k", [(1.0, 0.071, 10**6, 0), (1.0, 0.3, 1000, 2), (1.0, 2.5, 64, 1),
+                                          (2.0, 0.5, 64, 1), (1.0, 1e-4, 10**7, 8), (1.0, 0.2, 3400, 3),
+                                          (3.0, 1.0, 0, 0), (1.0, 1.0 / 3.0, 27, 1)])
+def test_real_space_cells_cover_the_cutoff(L, rc, n_max, k):
+    """Cell list of the real-space sum: s cells of side L/c reach rc and s - 1
+    do not; c follows the cells-per-cutoff, charge-count and 160 limits."""
+    c, s = L_.se_rs_cells(L, rc, n_max, k)
+    h = L / c
+    assert 1 <= c <= 160 and s >= 1
+    assert s * h >= rc and (s == 1 or (s - 1) * h < rc)
+    kk = 2 if k <= 0 else k
+    assert c == max(1, min(math.floor(kk * L / rc), math.floor(max(1, n_max) ** (1 / 3) + 1e-9), 160))
+
+
+def test_real_space_cells_reject_invalid():
+    lib = L.load()
+    c, s = ctypes.c_int(), ctypes.c_int()
+    for args in [(0.0, 0.1, 10, 0), (1.0, 0.0, 10, 0), (1.0, float("inf"), 10, 0), (1.0, 0.1, -1, 0),
+                 (1.0, 0.1, 10, 9), (float("nan"), 0.1, 10, 0)]:
+        assert lib.se_rs_cells(*args, ctypes.byref(c), ctypes.byref(s)) == L.SE_ERR_PARAM
+    assert lib.se_rs_cells(1.0, 0.1, 10, 0, None, ctypes.byref(s)) == L.SE_ERR_ARG
+    plan = ctypes.c_void_p()
+    assert lib.se_rs_plan_create(4, 1.0, 1.0, 0.1, 10, 0, 0, None, ctypes.byref(plan)) == L.SE_ERR_PARAM
+    assert lib.se_rs_plan_create(3, 1.0, -1.0, 0.1, 10, 0, 0, None, ctypes.byref(plan)) == L.SE_ERR_PARAM
+    assert lib.se_rs_plan_create(3, 1.0, 1.0, 0.1, 10, 5, 0, None, ctypes.byref(plan)) == L.SE_ERR_PARAM
+    assert lib.se_rs_eval(None, 0, None, None, None, None, None, 0, None) == L.SE_ERR_ARG
+    assert lib.se_rs_plan_destroy(None) == L.SE_OK

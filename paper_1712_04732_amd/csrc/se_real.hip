@@ -179,16 +179,20 @@ __global__ __launch_bounds__(kRsBlock) void rs_scatter_kernel(long N, const int*
 
 // One workgroup per cell: sort the cell's input indices (bitonic, in LDS;
 // cells of more than kRsSortMax charges keep their arrival order), then
-// store the cell's charges as {x, y, z, q} records in that order.
+// store the cell's charges in that order as records {x, y, z, q} with the
+// position taken from the cell's corner (so differences of nearby charges
+// keep the precision of the cell side, not of the box), and the charge's x
+// cell index in scx.
 template <typename T, typename Tin>
 __global__ __launch_bounds__(kRsBlock) void rs_order_kernel(RsGeom g, const Tin* __restrict__ xyz,
                                                             const Tin* __restrict__ q,
                                                             const int* __restrict__ start, int* __restrict__ sidx,
-                                                            vec4<T>* __restrict__ spos) {
+                                                            vec4<T>* __restrict__ spos, int* __restrict__ scx) {
   __shared__ int key[kRsSortMax];
   const int cell = blockIdx.x;
   const int j0 = start[cell], j1 = start[cell + 1], n = j1 - j0;
   if (n <= 0) return;
+  const int cx = cell % g.c, cy = (cell / g.c) % g.c, cz = cell / (g.c * g.c);
   if (n > 1 && n <= kRsSortMax) {
     int m = 1;
     while (m < n) m <<= 1;
@@ -217,7 +221,8 @@ __global__ __launch_bounds__(kRsBlock) void rs_order_kernel(RsGeom g, const Tin*
     double w[3], qi;
     int bad = 0;
     load_wrapped(xyz, q, o, g, w, &qi, &bad);
-    gst(spos)[j0 + i] = vec4<T>{(T)w[0], (T)w[1], (T)w[2], (T)qi};
+    gst(spos)[j0 + i] = vec4<T>{(T)(w[0] - cx * g.h), (T)(w[1] - cy * g.h), (T)(w[2] - cz * g.h), (T)qi};
+    gst(scx)[j0 + i] = cx;
   }
 }
 
@@ -233,12 +238,29 @@ __device__ __forceinline__ T bcast(T v, int lane) {
   }
 }
 
-__device__ __forceinline__ float erfc_t(float x) { return erfcf(x); }
+// FP64 pairs use the device library's erfc, exp and sqrt.
 __device__ __forceinline__ double erfc_t(double x) { return erfc(x); }
-__device__ __forceinline__ float exp_t(float x) { return expf(x); }
 __device__ __forceinline__ double exp_t(double x) { return exp(x); }
-__device__ __forceinline__ float sqrt_t(float x) { return sqrtf(x); }
 __device__ __forceinline__ double sqrt_t(double x) { return sqrt(x); }
+
+// erfc(z) for z >= 0 in FP32 by the Chebyshev fit of Press et al.
+// (Numerical Recipes, function erfcc; relative error below 1.2e-7):
+// erfc(z) = t exp(-z^2 + P(t)), t = 1/(1 + z/2), P a degree-9 polynomial.
+// gauss = exp(-z^2) is passed in (the gradient needs it as well).
+__device__ __forceinline__ float erfc_cheb(float z, float gauss) {
+  const float t = __builtin_amdgcn_rcpf(1.0f + 0.5f * z);
+  float p = 0.17087277f;
+  p = fmaf(p, t, -0.82215223f);
+  p = fmaf(p, t, 1.48851587f);
+  p = fmaf(p, t, -1.13520398f);
+  p = fmaf(p, t, 0.27886807f);
+  p = fmaf(p, t, -0.18628806f);
+  p = fmaf(p, t, 0.09678418f);
+  p = fmaf(p, t, 0.37409196f);
+  p = fmaf(p, t, 1.00002368f);
+  p = fmaf(p, t, -1.26551223f);
+  return t * gauss * expf(p);
+}
 
 struct RsOut {
   void* phi;        // N, compute precision, or null
@@ -261,7 +283,8 @@ __device__ __forceinline__ int floor_div(int a, int c) { return a >= 0 ? a / c :
 template <typename T, bool GRAD>
 __global__ __launch_bounds__(64) void rs_sum_kernel(RsGeom g, const int* __restrict__ start,
                                                     const int* __restrict__ sidx,
-                                                    const vec4<T>* __restrict__ spos, RsOut out) {
+                                                    const vec4<T>* __restrict__ spos,
+                                                    const int* __restrict__ scx, RsOut out) {
   const int cell = blockIdx.x, lane = threadIdx.x, c = g.c, s = g.s;
   const int ix = cell % c, iy = (cell / c) % c, iz = cell / (c * c);
   const int t0 = uni(gld(start)[cell]), t1 = uni(gld(start)[cell + 1]);
@@ -272,6 +295,7 @@ __global__ __launch_bounds__(64) void rs_sum_kernel(RsGeom g, const int* __restr
   const T rc2 = (T)(g.rc * g.rc), xi = (T)g.xi, xi2 = (T)(g.xi * g.xi);
   const T c2 = (T)(2.0 * g.xi / 1.7724538509055160272981674833411452);
   const double h = g.h, rc2d = g.rc * g.rc;
+  const T hT = (T)g.h;
   const T far = (T)(4.0 * g.L + 4.0 * g.rc + 1.0);   // padding charge, out of range of every target
   double e_acc = 0.0;
   for (int tb = t0; tb < t1; tb += per) {
@@ -283,13 +307,21 @@ __global__ __launch_bounds__(64) void rs_sum_kernel(RsGeom g, const int* __restr
       const T dxv = tp.x - xj, dyv = tp.y - yj, dzv = tp.z - zj;
       const T r2 = dxv * dxv + dyv * dyv + dzv * dzv;
       if (r2 < rc2 && !self) {
-        const T r = sqrt_t(r2);
-        const T ir = (T)1 / r;
-        const T e = erfc_t(xi * r) * ir;
+        T ir, e, gauss;
+        if constexpr (sizeof(T) == 4) {
+          ir = __builtin_amdgcn_rsqf(r2);
+          gauss = expf(-xi2 * r2);
+          e = erfc_cheb(xi * r2 * ir, gauss) * ir;
+        } else {
+          const T r = sqrt_t(r2);
+          ir = (T)1 / r;
+          gauss = exp_t(-xi2 * r2);
+          e = erfc_t(xi * r) * ir;
+        }
         phi += qn * e;
         if constexpr (GRAD) {
           // d/dr [erfc(xi r)/r] = -erfc(xi r)/r^2 - 2 xi/sqrt(pi) exp(-xi^2 r^2)/r
-          const T f = -qn * (e + c2 * exp_t(-xi2 * r2)) * ir * ir;
+          const T f = -qn * (e + c2 * gauss) * ir * ir;
           gx += f * dxv;
           gy += f * dyv;
           gz += f * dzv;
@@ -320,14 +352,18 @@ __global__ __launch_bounds__(64) void rs_sum_kernel(RsGeom g, const int* __restr
           const int lo = max(xa, qx * c) - qx * c, hi = min(xb, qx * c + c - 1) - qx * c;
           const int j0 = uni(gld(start)[rowc + lo]), j1 = uni(gld(start)[rowc + hi + 1]);
           const bool same = qx == 0 && qy == 0 && qz == 0 && uy == iy && uz == iz;
-          // the neighbours' image: x_n + (qx, qy, qz) L
-          const T sx = (T)(qx * g.L), sy = (T)(qy * g.L), sz = (T)(qz * g.L);
+          // neighbour positions relative to the target cell's corner: the
+          // neighbour's unwrapped cell is (cx + qx c, iy + dy, iz + dz)
+          const T oy = (T)dy * hT, oz = (T)dz * hT;
           for (int jb = j0; jb < j1; jb += 64) {
             const int jn = jb + lane;
-            vec4<T> np = jn < j1 ? gld(spos)[jn] : vec4<T>{far, far, far, (T)0};
-            np.x += sx;
-            np.y += sy;
-            np.z += sz;
+            vec4<T> np = vec4<T>{far, far, far, (T)0};
+            if (jn < j1) {
+              np = gld(spos)[jn];
+              np.x += (T)(gld(scx)[jn] + qx * c - ix) * hT;
+              np.y += oy;
+              np.z += oz;
+            }
             const int cntj = min(64, j1 - jb);
             if (gsz == 1) {
               for (int u = 0; u < cntj; ++u)
@@ -400,6 +436,8 @@ struct se_rs_plan {
   bool f64 = true;
   int ncell = 0, nscan = 0;
   void* mem = nullptr;  // one device allocation, carved below
+  // slot: arrival slot of each charge in its cell (bin to scatter), then the x
+  // cell index of each sorted record (order to pair sums)
   int *cnt = nullptr, *start = nullptr, *bsum = nullptr, *cell_of = nullptr, *slot = nullptr, *sidx = nullptr,
       *status = nullptr;
   double* epart = nullptr;
@@ -553,25 +591,25 @@ se_status se_rs_eval(se_rs_plan* plan, long N, const void* xyz, const void* q, v
     auto* sp = (vec4<double>*)plan->spos;
     if (in32)
       rs_order_kernel<double, float><<<nc, kRsBlock, 0, st>>>(g, (const float*)xyz, (const float*)q, plan->start,
-                                                              plan->sidx, sp);
+                                                              plan->sidx, sp, plan->slot);
     else
       rs_order_kernel<double, double><<<nc, kRsBlock, 0, st>>>(g, (const double*)xyz, (const double*)q,
-                                                               plan->start, plan->sidx, sp);
+                                                               plan->start, plan->sidx, sp, plan->slot);
     mark(1);
-    if (force) rs_sum_kernel<double, true><<<nc, 64, 0, st>>>(g, plan->start, plan->sidx, sp, out);
-    else rs_sum_kernel<double, false><<<nc, 64, 0, st>>>(g, plan->start, plan->sidx, sp, out);
+    if (force) rs_sum_kernel<double, true><<<nc, 64, 0, st>>>(g, plan->start, plan->sidx, sp, plan->slot, out);
+    else rs_sum_kernel<double, false><<<nc, 64, 0, st>>>(g, plan->start, plan->sidx, sp, plan->slot, out);
     mark(2);
   } else {
     auto* sp = (vec4<float>*)plan->spos;
     if (in32)
       rs_order_kernel<float, float><<<nc, kRsBlock, 0, st>>>(g, (const float*)xyz, (const float*)q, plan->start,
-                                                             plan->sidx, sp);
+                                                             plan->sidx, sp, plan->slot);
     else
       rs_order_kernel<float, double><<<nc, kRsBlock, 0, st>>>(g, (const double*)xyz, (const double*)q,
-                                                              plan->start, plan->sidx, sp);
+                                                              plan->start, plan->sidx, sp, plan->slot);
     mark(1);
-    if (force) rs_sum_kernel<float, true><<<nc, 64, 0, st>>>(g, plan->start, plan->sidx, sp, out);
-    else rs_sum_kernel<float, false><<<nc, 64, 0, st>>>(g, plan->start, plan->sidx, sp, out);
+    if (force) rs_sum_kernel<float, true><<<nc, 64, 0, st>>>(g, plan->start, plan->sidx, sp, plan->slot, out);
+    else rs_sum_kernel<float, false><<<nc, 64, 0, st>>>(g, plan->start, plan->sidx, sp, plan->slot, out);
     mark(2);
   }
   if (energy) rs_energy_kernel<<<1, kRsBlock, 0, st>>>(plan->epart, nc, energy, acc ? 1 : 0);

@@ -143,8 +143,8 @@ def test_repeatable_and_accumulate():
     a = run(rs, x, q)
     b = run(rs, x, q)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
-    xt = torch.tensor(x, dtype=torch.float32, device=DEV)
-    qt = torch.tensor(q, dtype=torch.float32, device=DEV)
+    xt = torch.tensor(x, dtype=torch.float64, device=DEV)   # the inputs of run()
+    qt = torch.tensor(q, dtype=torch.float64, device=DEV)
     g = torch.Generator(device="cpu").manual_seed(1)
     p0 = torch.rand(N, generator=g).to(DEV)
     f0 = torch.rand((N, 3), generator=g).to(DEV)
@@ -217,3 +217,20 @@ def test_full_potential_madelung(D, const):
     np.testing.assert_allclose(m, const, rtol=0, atol=1e-10)
     np.testing.assert_allclose(g.cpu().numpy(), 0.0, atol=1e-8)   # every ion sits at a symmetric site
     assert abs(float(E) - 0.5 * float(np.dot(q, -const * q / a))) < 1e-9 * len(q)
+
+
+def test_fp32_close_pairs():
+    """FP32 at a dense uniform input (200 000 charges, closest pairs ~1e-4 apart):
+    positions are kept relative to their cell's corner, so the pair
+    differences carry the precision of the cell side; forces against the FP64
+    path (itself checked against the oracle above) within 2e-5 rms."""
+    N, L, rc, D = 200000, 1.0, 0.06, 1
+    xi = 3.2 / rc
+    x, q = wl.system(N, L, 650, "normal")
+    out = {}
+    for prec in ("f64", "f32"):
+        rs = RealSpace(D, L, xi, rc, prec=prec, n_max=N)
+        out[prec] = run(rs, x, q)
+    e_phi, e_f = rel(out["f32"][0], out["f64"][0]), rel(out["f32"][1], out["f64"][1])
+    print(f"fp32 vs fp64 real space, N={N}: phi {e_phi:.2e} grad {e_f:.2e}")
+    assert e_phi < 2e-5 and e_f < 2e-5

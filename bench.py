@@ -453,6 +453,55 @@ def main_real_space(args):
     print(json.dumps(result), flush=True)
 
 
+def main_xi_balance(args):
+    """Total time of the full potential (k space + real space + self term) of
+    one workload against the Ewald parameter: for each xi the grid M comes
+    from the k-space estimate (Eq. KP_fourier_space, se_params_for_tolerance)
+    and rc from the real-space estimate (Eq. KP_real_space), both at 1e-6 B,
+    so that the balance point the paper tunes xi for is measured.  One JSON
+    line per xi."""
+    import torch
+
+    import workloads as wl
+    from oracle.se_discrete import B_scale   # only the B normalisation of the tolerance
+    from paper_1712_04732_amd import RealSpace, SpectralEwald, params_for_tolerance
+
+    name = args.workload if args.workload in wl.CONFIGS else "C4_1P"
+    cfg = wl.CONFIGS[name]
+    D, N, L, xi0, P = cfg["D"], cfg["N"], cfg["L"], cfg["xi"], cfg["P"]
+    x, q = wl.config_system(name)
+    Q = float((q * q).sum())
+    dev = torch.device("cuda:0")
+    xt = torch.tensor(x, dtype=torch.float32, device=dev)
+    qt = torch.tensor(q, dtype=torch.float32, device=dev)
+    for f in (0.5, 0.7, 0.85, 1.0, 1.2, 1.45, 1.75):
+        xi = xi0 * f
+        tol = 1e-6 * B_scale(Q, xi, L)
+        p = params_for_tolerance(D, L, xi, Q, 1e-6, P=P, window=cfg["window"], prec="f32")
+        if p.M > 400:
+            continue
+        rc = kp_real_cutoff(Q, xi, L, tol)
+        ks = SpectralEwald.from_params(p, N)
+        rs = RealSpace(D, L, xi, rc, prec="f32", n_max=N)
+        out = ks(xt, qt, add_self=True)
+        ms = {}
+        for label, fn in (("kspace", lambda: ks(xt, qt, add_self=True, check=False, out=out)),
+                          ("real", lambda: rs(xt, qt, accumulate=True, check=False, out=out))):
+            for _ in range(args.warmup):
+                fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                fn()
+            torch.cuda.synchronize()
+            ms[label] = (time.perf_counter() - t0) * 1e3 / args.steps
+        print(json.dumps({"workload": name, "xi": xi, "M": p.M, "rc": rc, "cells": rs.cells,
+                          "ms_kspace": ms["kspace"], "ms_real": ms["real"],
+                          "ms_total": ms["kspace"] + ms["real"],
+                          "particles_per_s": N / ((ms["kspace"] + ms["real"]) * 1e-3)}), flush=True)
+        del ks, rs
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -466,6 +515,8 @@ def main():
     ap.add_argument("--save-schedule", default=None, help="batch: write the autotuner's schedule here")
     ap.add_argument("--real-space", action="store_true",
                     help="time the real-space part instead (single-system workloads; default C4_1P)")
+    ap.add_argument("--xi-balance", action="store_true",
+                    help="time k space + real space against xi (single-system workloads; default C4_1P)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device 5 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -486,6 +537,8 @@ def main():
         sys.exit(2)
     if args.real_space:
         return main_real_space(args)
+    if args.xi_balance:
+        return main_xi_balance(args)
     if args.workload == "C5_batch":
         return main_batch(args)
 

@@ -286,6 +286,33 @@ class SEEnergy(torch.autograd.Function):
         return gx, gq, None, None
 
 
+class EwaldEnergy(torch.autograd.Function):
+    """Total electrostatic energy of Eq. (potential_split),
+    E = 1/2 sum_m q_m (phi^F + phi^R + phi^self)_m: the k-space part by the
+    SpectralEwald plan (with the self term), the real-space part by the
+    RealSpace plan accumulated into the same outputs.  Backward: dE/dq = phi,
+    dE/dx_m = q_m grad phi(x_m)."""
+
+    @staticmethod
+    def forward(ctx, x, q, kplan: SpectralEwald, rplan: "RealSpace"):
+        xd, qd = x.detach(), q.detach()
+        out = kplan.evaluate(xd, qd, out_grad=True, add_self=True)
+        phi, grad, E = rplan.evaluate(xd, qd, out_grad=True, accumulate=True, out=out)
+        ctx.save_for_backward(qd, phi, grad)
+        ctx.xdtype = x.dtype
+        return E
+
+    @staticmethod
+    def backward(ctx, gE):
+        q, phi, grad = ctx.saved_tensors
+        gx = gq = None
+        if ctx.needs_input_grad[0]:
+            gx = (gE * q.to(torch.float64)[:, None] * grad.to(torch.float64)).to(ctx.xdtype)
+        if ctx.needs_input_grad[1]:
+            gq = (gE * phi.to(torch.float64)).to(q.dtype)
+        return gx, gq, None, None
+
+
 class SEPotential(torch.autograd.Function):
     """phi = A(x) q.  The discrete operator A (spread, scale, gather with one
     window) is symmetric, so for a cotangent g:

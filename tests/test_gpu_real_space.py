@@ -234,3 +234,32 @@ def test_fp32_close_pairs():
     e_phi, e_f = rel(out["f32"][0], out["f64"][0]), rel(out["f32"][1], out["f64"][1])
     print(f"fp32 vs fp64 real space, N={N}: phi {e_phi:.2e} grad {e_f:.2e}")
     assert e_phi < 2e-5 and e_f < 2e-5
+
+
+@pytest.mark.parametrize("D", [3, 2, 1, 0])
+def test_total_energy_autograd_against_oracle(D):
+    """EwaldEnergy (k space + real space + self term on the GPU): the energy
+    and its autograd gradients against the direct oracle's total potential
+    and gradient (Eq. potential_split) at high-accuracy parameters."""
+    print(f"case total energy D={D}", flush=True)
+    from paper_1712_04732_amd import EwaldEnergy
+    N = 300
+    x, q = wl.system(N, 1.0, 660 + D, "uniform")
+    Q = float((q * q).sum())
+    xi, M, P = 8.0, 40, 16
+    pp = se.with_aft_estimates(D, 1.0, xi, M, P, Q, 1e-16 * se.B_scale(Q, xi, 1.0), window="pkb")
+    ks = SpectralEwald(D, 1.0, xi, M, P, window="pkb", prec="f64", n_max=N,
+                       **({"s": pp.s, "n_l": pp.n_l} if D in (1, 2) else {}))
+    rs = RealSpace(D, 1.0, xi, direct.real_space_cutoff(xi), prec="f64", n_max=N)
+    xt = torch.tensor(x, dtype=torch.float64, device=DEV, requires_grad=True)
+    qt = torch.tensor(q, dtype=torch.float64, device=DEV, requires_grad=True)
+    E = EwaldEnergy.apply(xt, qt, ks, rs)
+    E.backward()
+    torch.cuda.synchronize()
+    phi_o, g_o = direct.total(D, 1.0, xi, x, q)
+    E_o = 0.5 * float(np.dot(q, phi_o))
+    E = E.detach()
+    print(f"  energy {float(E):.12f} oracle {E_o:.12f}")
+    assert abs(float(E) - E_o) <= 1e-10 * abs(E_o)
+    assert rel(qt.grad.cpu().numpy(), phi_o) < 1e-10
+    assert rel(xt.grad.cpu().numpy(), q[:, None] * g_o) < 1e-9

@@ -166,6 +166,13 @@ __device__ __forceinline__ void gstore(void* base, OFF off, V v) {
 
 __device__ __forceinline__ int rfl(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Reciprocal for the quotients fdiv(a, .) of the transforms, whose
+// dividends stay below kFftCap = 2^13: the hardware reciprocal (relative
+// error below 2^-22) and the product's rounding move (a + 1/2)/d by less than
+// 2^13 2^-21 / d = 2^-8 / d, far inside the 1/(2d) that separates it from an
+// integer, so truncation is still exact.
+__device__ __forceinline__ float quot_recip(int d) { return __builtin_amdgcn_rcpf((float)d); }
+
 // One Stockham stage from src to dst over B = 2^lgB interleaved pencils stored
 // sample-major with pitch Bp (sample t of pencil p at t Bp + p).  Butterfly j
 // (pencil p) reads samples j + r n/R, multiplies input r by the twiddle
@@ -182,7 +189,7 @@ __device__ __forceinline__ void fft_stage(const lds<vec2<T>>* __restrict__ src, 
   const int sstr = nb * Bp;   // between the inputs of a butterfly
   const int dstr = Ns * Bp;   // between its outputs
   const int nsr = Ns * R;
-  const float inv_ns = 1.0f / (float)Ns;
+  const float inv_ns = quot_recip(Ns);
   for (int e = threadIdx.x; e < total; e += kFftBlock) {
     const int j = e >> lgB, p = e & mask;
     const lds<vec2<T>>* s = src + (__mul24(j, Bp) + p);
@@ -262,7 +269,7 @@ __device__ __forceinline__ void fft_stage_ip(lds<vec2<T>>* buf, const lds<vec2<T
   const int sstr = nb * Bp;
   const int dstr = Ns * Bp;
   const int nsr = Ns * R;
-  const float inv_ns = 1.0f / (float)Ns;
+  const float inv_ns = quot_recip(Ns);
   cx<T> v[IT][R];
   int dofs[IT];
 #pragma unroll
@@ -400,7 +407,7 @@ struct SlotWalk {
   __device__ __forceinline__ SlotWalk(int n_, int lgB, OFF gs0, OFF gst, int lt, int lp) : n(n_) {
     const int tid = threadIdx.x;
     if constexpr (TF) {
-      const float inv_n = 1.0f / (float)n;
+      const float inv_n = quot_recip(n);
       q = fdiv(kFftBlock, inv_n);
       r = kFftBlock - q * n;
       p = fdiv(tid, inv_n);

@@ -1791,6 +1791,24 @@ se_status se_batch_autotune(const se_params* params, const long* N, int n_sys, c
     if (!time_batch(def, vN, io, &t0)) return SE_ERR_UNSUPPORTED;
     if (!time_batch(out, vN, io, &tb)) return SE_ERR_UNSUPPORTED;
     int cand = 2;
+    // One transform launch takes the largest LDS of all its systems, so the
+    // samples cap chosen per class is checked against each chosen value used
+    // for every system, on the whole batch.
+    std::vector<int> caps;
+    for (const auto& p : out)
+      if (std::find(caps.begin(), caps.end(), p.fft_cap) == caps.end()) caps.push_back(p.fft_cap);
+    if (caps.size() > 1)
+      for (int cap : caps) {
+        auto v = out;
+        for (auto& p : v) p.fft_cap = cap;
+        TuneTimes t;
+        if (!time_batch(v, vN, io, &t)) continue;
+        ++cand;
+        if (t.fft < tb.fft) {
+          tb = t;
+          out = v;
+        }
+      }
     for (int group = 0; group < 2; ++group) {
       const auto base_v = out;
       for (int mode : kTuneXcd) {

@@ -559,10 +559,7 @@ se_status se_rs_eval(se_rs_plan* plan, long N, const void* xyz, const void* q, v
       for (auto& e : plan->ev)
         if (hipEventCreate(&e) != hipSuccess) return SE_ERR_DEVICE;
     }
-    if (plan->ev_used + 4 <= (int)plan->ev.size()) {
-      e0 = plan->ev_used;
-      plan->ev_used += 4;
-    }
+    if (plan->ev_used + 4 <= (int)plan->ev.size()) e0 = plan->ev_used;   // kept once all four are recorded
   }
   auto mark = [&](int k) {
     if (e0 >= 0) (void)hipEventRecord(plan->ev[e0 + k], st);
@@ -618,6 +615,7 @@ se_status se_rs_eval(se_rs_plan* plan, long N, const void* xyz, const void* q, v
   if (energy) rs_energy_kernel<<<1, kRsBlock, 0, st>>>(plan->epart, nc, energy, acc ? 1 : 0);
   mark(3);
   if (hipGetLastError() != hipSuccess) return SE_ERR_DEVICE;
+  if (e0 >= 0) plan->ev_used += 4;
   if (flags & SE_SYNC_CHECK) return se_rs_get_device_status(plan, hip_stream);
   return SE_OK;
 }

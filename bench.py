@@ -61,13 +61,13 @@ def roofline(stages, prec, workload_P=None):
     return r
 
 
-def _source_sha():
+def _source_sha(files=("se_kernels.hip", "se_fft.hip", "se_plan.cpp", "se_internal.h", "se_device.h")):
     """Hash of the kernel and planner sources without comments and blank lines
     (a stored HBM byte count stays valid across comment edits only)."""
     import hashlib
     import re
     h = hashlib.sha256()
-    for f in ("se_kernels.hip", "se_fft.hip", "se_plan.cpp", "se_internal.h", "se_device.h"):
+    for f in files:
         text = open(os.path.join(ROOT, "paper_1712_04732_amd", "csrc", f)).read()
         code = [ln.rstrip() for ln in (re.sub(r"//.*", "", x) for x in text.split("\n"))]
         h.update("\n".join(ln for ln in code if ln.strip()).encode())
@@ -375,6 +375,23 @@ def pairs_within(D, L, rc, x, n_sample=20000, seed=11):
 PAIR_FLOPS = 25
 
 
+RS_SOURCES = ("se_real.hip", "se_device.h", "se_internal.h")
+
+
+def _rs_traffic(workload):
+    """Stored HBM bytes per launch of the FP32 pair kernel (FETCH_SIZE +
+    WRITE_SIZE, copy-calibrated) when they were taken on these sources and
+    this workload, else None."""
+    tpath = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        ent = json.load(open(tpath)).get("rs_pairs")
+        if ent and ent.get("source_sha") == _source_sha(RS_SOURCES) and ent.get("workload") == workload:
+            return ent["bytes_per_launch"]
+    except Exception:
+        pass
+    return None
+
+
 def main_real_space(args):
     """The real-space part (Eq. real_space_ewald) on the GPU for one of the
     single-system workloads, at the cutoff of Eq. (KP_real_space) for the same
@@ -431,7 +448,7 @@ def main_real_space(args):
         "fp64_value": N / (ms64 * 1e-3), "fp64_ms_per_step": ms64,
         "stages_ms": st32, "stages_ms_fp64": st64,
         "roofline": {"bound": "alu", "achieved": flops / t_pairs / 1e12, "peak": ALU_PEAK["f32"] / 1e12,
-                     "unit": "TFLOP/s", "frac": flops / t_pairs / ALU_PEAK["f32"], "traffic": None,
+                     "unit": "TFLOP/s", "frac": flops / t_pairs / ALU_PEAK["f32"], "traffic": _rs_traffic(name),
                      "kernel": "rs_sum_kernel<float, true> (rs_pairs)", "ms_avg": st32["rs_pairs"],
                      "alg_flops": flops},
         "errors": err,

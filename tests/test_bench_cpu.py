@@ -106,3 +106,17 @@ def test_pair_count_matches_brute_force(D):
     r = np.sqrt((d * d).sum(-1))
     brute = (np.count_nonzero(r < rc) - N) / N
     assert abs(bench.pairs_within(D, L, rc, x, n_sample=N) - brute) < 1e-12
+
+
+def test_real_space_traffic_only_for_matching_sources_and_workload():
+    """The real-space bench line reports stored HBM bytes only when they were
+    taken on the current sources (comment-free hash) and the same workload."""
+    t = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
+    ent = t.get("rs_pairs")
+    if ent is None:
+        pytest.skip("no stored real-space byte count")
+    if ent["source_sha"] == bench._source_sha(bench.RS_SOURCES):
+        assert bench._rs_traffic(ent["workload"]) == ent["bytes_per_launch"]
+    else:
+        assert bench._rs_traffic(ent["workload"]) is None
+    assert bench._rs_traffic("no such workload") is None

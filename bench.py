@@ -333,20 +333,6 @@ def main_batch(args):
     print(json.dumps(result), flush=True)
 
 
-def kp_real_cutoff(Q, xi, L, tol):
-    """Smallest cutoff whose real-space error estimate, Eq. (KP_real_space),
-    sqrt(Q) xi^-2 (L rc)^-3/2 exp(-(xi rc)^2), is at most tol (bisection on the
-    decreasing branch)."""
-    est = lambda rc: math.sqrt(Q) / xi ** 2 * (L * rc) ** -1.5 * math.exp(-(xi * rc) ** 2)
-    lo, hi = 0.5 / xi, 1.0 / xi
-    while est(hi) > tol:
-        hi *= 1.5
-    for _ in range(100):
-        mid = 0.5 * (lo + hi)
-        lo, hi = (mid, hi) if est(mid) > tol else (lo, mid)
-    return hi
-
-
 def pairs_within(D, L, rc, x, n_sample=20000, seed=11):
     """Mean number of other charges within rc of a charge (periodic images in
     the first D directions), counted exactly for a sample of charges."""
@@ -400,15 +386,14 @@ def main_real_space(args):
     import torch
 
     import workloads as wl
-    from oracle.se_discrete import B_scale   # only the B normalisation of the tolerance
-    from paper_1712_04732_amd import RealSpace
+    from paper_1712_04732_amd import RealSpace, _lib
 
     name = args.workload if args.workload in wl.CONFIGS else "C4_1P"
     cfg = wl.CONFIGS[name]
     D, N, L, xi = cfg["D"], cfg["N"], cfg["L"], cfg["xi"]
     x, q = wl.config_system(name)
     Q = float((q * q).sum())
-    rc = kp_real_cutoff(Q, xi, L, 1e-6 * B_scale(Q, xi, L))
+    rc = _lib.se_rs_cutoff_for_tolerance(L, xi, Q, 1e-6)
     dev = torch.device("cuda:0")
     xt = torch.tensor(x, dtype=torch.float64, device=dev)
     qt = torch.tensor(q, dtype=torch.float64, device=dev)
@@ -474,14 +459,13 @@ def main_xi_balance(args):
     """Total time of the full potential (k space + real space + self term) of
     one workload against the Ewald parameter: for each xi the grid M comes
     from the k-space estimate (Eq. KP_fourier_space, se_params_for_tolerance)
-    and rc from the real-space estimate (Eq. KP_real_space), both at 1e-6 B,
+    and rc from the real-space estimate (Eq. KP_rc, se_rs_cutoff_for_tolerance), both at 1e-6 B,
     so that the balance point the paper tunes xi for is measured.  One JSON
     line per xi."""
     import torch
 
     import workloads as wl
-    from oracle.se_discrete import B_scale   # only the B normalisation of the tolerance
-    from paper_1712_04732_amd import RealSpace, SpectralEwald, params_for_tolerance
+    from paper_1712_04732_amd import RealSpace, SpectralEwald, _lib, params_for_tolerance
 
     name = args.workload if args.workload in wl.CONFIGS else "C4_1P"
     cfg = wl.CONFIGS[name]
@@ -493,11 +477,10 @@ def main_xi_balance(args):
     qt = torch.tensor(q, dtype=torch.float32, device=dev)
     for f in (0.5, 0.7, 0.85, 1.0, 1.2, 1.45, 1.75):
         xi = xi0 * f
-        tol = 1e-6 * B_scale(Q, xi, L)
         p = params_for_tolerance(D, L, xi, Q, 1e-6, P=P, window=cfg["window"], prec="f32")
         if p.M > 400:
             continue
-        rc = kp_real_cutoff(Q, xi, L, tol)
+        rc = _lib.se_rs_cutoff_for_tolerance(L, xi, Q, 1e-6)
         ks = SpectralEwald.from_params(p, N)
         rs = RealSpace(D, L, xi, rc, prec="f32", n_max=N)
         out = ks(xt, qt, add_self=True)
@@ -569,8 +552,8 @@ def main():
     D, N, L, M, P, xi, win = cfg["D"], cfg["N"], cfg["L"], cfg["M"], cfg["P"], cfg["xi"], cfg["window"]
     x, q = wl.config_system(args.workload)
     Q = float((q * q).sum())
-    from oracle.se_discrete import B_scale   # only the B normalisation of the tolerance
-    tol = 1e-6 * B_scale(Q, xi, L)
+    from paper_1712_04732_amd import _lib
+    tol = 1e-6 * _lib.se_error_scale(Q, xi, L)
     dev = torch.device("cuda:0")
     prec = "f32"
     kw = dict(window=win, n_max=N)

@@ -151,9 +151,25 @@ se_status se_params_default(int D, double L, double xi, int M, int P, se_window 
 se_status se_params_for_tolerance(int D, double L, double xi, double Q, double tol_rel, int P,
                                   se_window window, se_precision prec, se_params* out);
 
-/* Validate the parameters, derive the grids (Section 3.3: Mt = 2 ceil((M +
- * lambda P)/2); Mt, s0 Mt and s Mt are rounded up to even integers with prime
- * factors 2, 3, 5, 7 only), build the FP64 tables (PKB coefficients by the
+/* The error scale of Section 5.2, B = sqrt(Q) f_c(xi L) / L with f_c of
+ * Eq. (fc-expression) and Q = sum of q^2: relative tolerances of the other
+ * calls are tolerances on rms errors divided by B.  *B receives it (host).
+ * Errors: SE_ERR_ARG for B == NULL; SE_ERR_PARAM for Q < 0, xi <= 0, L <= 0
+ * or non-finite inputs. */
+se_status se_error_scale(double Q, double xi, double L, double* B);
+
+/* Real-space cutoff for a relative tolerance tol_rel (absolute rms tolerance
+ * tol_rel * B): Eq. (KP_rc), the inverse of the Kolafa-Perram real-space
+ * estimate Eq. (KP_real_space), by the principal branch of the Lambert W
+ * function.  *rc receives the cutoff (host).
+ * Errors: SE_ERR_ARG for rc == NULL; SE_ERR_PARAM for non-positive or
+ * non-finite L, xi, Q, tol_rel. */
+se_status se_rs_cutoff_for_tolerance(double L, double xi, double Q, double tol_rel, double* rc);
+
+/* Validate the parameters (Section 3.3 and 3.4: lambda >= 1, s >= 1 and
+ * s0 >= 1 + sqrt(3 - D) for D < 3), derive the grids (Section 3.3: Mt = 2
+ * ceil((M + lambda P)/2); Mt, s0 Mt and s Mt are rounded up to even integers
+ * with prime factors 2, 3, 5, 7 only), build the FP64 tables (PKB coefficients by the
  * Vandermonde solve of Eq. polynomial-linsys, separable scaling vectors of
  * Eq. scale, Green's-function tables of Eqs. G_hat_0d..G_hat_3d), allocate
  * device memory for up to n_max particles, and for D = 0 run Algorithm 3 on

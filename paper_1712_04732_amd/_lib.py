@@ -159,6 +159,10 @@ _SIGS = {
     "se_rs_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "se_rs_plan_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(se_stage_record),
                                           ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
+    "se_error_scale": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                      ctypes.POINTER(ctypes.c_double)]),
+    "se_rs_cutoff_for_tolerance": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                                  ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
     "se_batch_autotune": (ctypes.c_int, [ctypes.POINTER(se_params), ctypes.POINTER(ctypes.c_long), ctypes.c_int,
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint, ctypes.c_void_p,
                                          ctypes.POINTER(se_params), ctypes.POINTER(se_tune_report)]),
@@ -242,6 +246,21 @@ def se_params_for_tolerance(D, L, xi, Q, tol_rel, P, window, prec):
     _check(load().se_params_for_tolerance(int(D), float(L), float(xi), float(Q), float(tol_rel), int(P),
                                           int(window), int(prec), ctypes.byref(out)), "se_params_for_tolerance")
     return out
+
+
+def se_error_scale(Q, xi, L):
+    """B of Section 5.2 (relative tolerances are rms tolerances over B)."""
+    b = ctypes.c_double()
+    _check(load().se_error_scale(float(Q), float(xi), float(L), ctypes.byref(b)), "se_error_scale")
+    return b.value
+
+
+def se_rs_cutoff_for_tolerance(L, xi, Q, tol_rel):
+    """Real-space cutoff of Eq. (KP_rc) for the relative tolerance tol_rel."""
+    rc = ctypes.c_double()
+    _check(load().se_rs_cutoff_for_tolerance(float(L), float(xi), float(Q), float(tol_rel), ctypes.byref(rc)),
+           "se_rs_cutoff_for_tolerance")
+    return rc.value
 
 
 def se_batch_plan_create(params, N, stream=0):

@@ -20,6 +20,20 @@ def _stream():
     return torch.cuda.current_stream().cuda_stream
 
 
+def _check_out(out, N, dtype, dev, e_shape):
+    """Caller-supplied outputs (phi, force, energy): each None or a contiguous
+    tensor on the input's device with shape (N,), (N, 3), e_shape and dtype
+    dtype, dtype, float64.  The kernels write N rows without bounds checks, so
+    a mismatch is an error here."""
+    for t, shape, dt in zip(out, ((N,), (N, 3), e_shape), (dtype, dtype, torch.float64)):
+        if t is None:
+            continue
+        if (not isinstance(t, torch.Tensor) or tuple(t.shape) != shape or t.dtype != dt or not t.is_contiguous()
+                or t.device != dev):
+            raise ValueError("output tensors must be contiguous, on the input's device, with the plan's "
+                             f"shapes and dtypes: expected {shape} {dt}")
+
+
 class SpectralEwald:
     """A plan for one system size class: periodicity D, box L, Ewald xi, grid M,
     window support P.  Parameters left as None follow the paper's rules
@@ -118,6 +132,7 @@ class SpectralEwald:
         dev = x.device
         if out is not None:
             out_phi, out_f, out_e = out
+            _check_out(out, N, self.dtype, dev, ())
         else:
             out_phi = torch.empty(N, dtype=self.dtype, device=dev) if phi else None
             out_f = torch.empty((N, 3), dtype=self.dtype, device=dev) if force else None
@@ -203,6 +218,11 @@ class SpectralEwaldBatch:
         (x, q); returns (plan, report)."""
         if not torch.cuda.is_available():
             raise RuntimeError("SpectralEwaldBatch needs a HIP device")
+        total = sum(int(n) for n in N)
+        if x.shape != (total, 3) or q.shape != (total,):
+            raise ValueError("x must be (sum N, 3) and q (sum N,)")
+        if x.dtype != q.dtype or x.dtype not in (torch.float32, torch.float64) or not (x.is_cuda and q.is_cuda):
+            raise ValueError("x and q must be device tensors of one dtype, float32 or float64")
         x, q = x.contiguous(), q.contiguous()
         flags = (L.SE_IN_F32 if x.dtype == torch.float32 else 0) | (
             L.SE_ALLOW_NONNEUTRAL if allow_nonneutral else 0)
@@ -228,13 +248,14 @@ class SpectralEwaldBatch:
                  check=True, allow_nonneutral=False, profile=False, out=None):
         if x.shape != (self.total, 3) or q.shape != (self.total,):
             raise ValueError("x must be (sum N, 3) and q (sum N,)")
-        if x.dtype != q.dtype or not (x.is_cuda and q.is_cuda):
-            raise ValueError("x and q must be device tensors of one dtype")
+        if x.dtype != q.dtype or x.dtype not in (torch.float32, torch.float64) or not (x.is_cuda and q.is_cuda):
+            raise ValueError("x and q must be device tensors of one dtype, float32 or float64")
         x = x.contiguous()
         q = q.contiguous()
         dev = x.device
         if out is not None:
             out_phi, out_f, out_e = out
+            _check_out(out, self.total, self.dtype, dev, (self.n_sys,))
         else:
             out_phi = torch.empty(self.total, dtype=self.dtype, device=dev) if phi else None
             out_f = torch.empty((self.total, 3), dtype=self.dtype, device=dev) if force else None
@@ -389,9 +410,7 @@ class RealSpace:
             out_phi = torch.empty(N, dtype=self.dtype, device=dev) if phi else None
             out_f = torch.empty((N, 3), dtype=self.dtype, device=dev) if force else None
             out_e = torch.empty((), dtype=torch.float64, device=dev) if energy else None
-        for t, shape, dt in ((out_phi, (N,), self.dtype), (out_f, (N, 3), self.dtype), (out_e, (), torch.float64)):
-            if t is not None and (tuple(t.shape) != shape or t.dtype != dt or not t.is_contiguous()):
-                raise ValueError("output tensors must be contiguous with the plan's shapes and dtypes")
+        _check_out((out_phi, out_f, out_e), N, self.dtype, dev, ())
         flags = (L.SE_IN_F32 if x.dtype == torch.float32 else 0) | (L.SE_OUT_GRAD if out_grad else 0) | (
             L.SE_ACCUMULATE if accumulate else 0) | (L.SE_SYNC_CHECK if check else 0) | (
             L.SE_PROFILE if profile else 0)

@@ -424,6 +424,41 @@ static double pollution_fw(se_window w, double x) {
   return w == SE_WIN_GAUSSIAN ? x * x + 0.2 * x + 2.25 : 0.7 * x * x + 0.2 * x + 1.8;
 }
 
+se_status se_error_scale(double Q, double xi, double L, double* B) {
+  if (!B) return SE_ERR_ARG;
+  if (!(Q >= 0) || !(xi > 0) || !(L > 0) || !std::isfinite(Q) || !std::isfinite(xi) || !std::isfinite(L))
+    return SE_ERR_PARAM;
+  *B = std::sqrt(Q) * fc(xi * L) / L;
+  return SE_OK;
+}
+
+// Principal branch of the Lambert W function, w e^w = x, for x >= 0: Halley's
+// iteration from log(1 + x) (an upper bound of W(x) for x >= 0).
+static double lambert_w0(double x) {
+  double w = std::log1p(x);
+  for (int it = 0; it < 64; ++it) {
+    const double ew = std::exp(w), f = w * ew - x;
+    const double d = ew * (w + 1.0) - (w + 2.0) * f / (2.0 * w + 2.0);
+    const double nw = w - f / d;
+    if (std::fabs(nw - w) <= 1e-15 * (1.0 + std::fabs(nw))) return nw;
+    w = nw;
+  }
+  return w;
+}
+
+se_status se_rs_cutoff_for_tolerance(double L, double xi, double Q, double tol_rel, double* rc) {
+  if (!rc) return SE_ERR_ARG;
+  if (!(L > 0) || !(xi > 0) || !(Q > 0) || !(tol_rel > 0) || !std::isfinite(L) || !std::isfinite(xi) ||
+      !std::isfinite(Q) || !std::isfinite(tol_rel))
+    return SE_ERR_PARAM;
+  // Eq. (KP_rc): the cutoff at which Eq. (KP_real_space) equals the absolute
+  // tolerance eps = tol_rel B
+  const double eps = tol_rel * std::sqrt(Q) * fc(xi * L) / L;
+  const double arg = (4.0 / 3.0) * std::pow(Q / (xi * L * L * L * eps * eps), 2.0 / 3.0);
+  *rc = std::sqrt(3.0) / (2.0 * xi) * std::sqrt(lambert_w0(arg));
+  return SE_OK;
+}
+
 se_status se_params_for_tolerance(int D, double L, double xi, double Q, double tol_rel, int P, se_window window,
                                   se_precision prec, se_params* out) {
   if (!out) return SE_ERR_ARG;
@@ -547,7 +582,9 @@ static se_status plan_create(const se_params* params, long n_max, void* hip_stre
     const double s0[3] = {2.8, 2.5, 2.0};
     if (!(p.lambda > 0)) p.lambda = lam[p.window == SE_WIN_PKB][p.D];
     if (!(p.s0 > 0)) p.s0 = s0[p.D];
-    if (p.lambda < 1.0 || p.s0 < 1.0) return SE_ERR_PARAM;
+    // Section 3.4: the zero mode (2P, 1P) and the free-space transform (0P)
+    // need s0 >= 1 + sqrt(d) for d = 3 - D free directions
+    if (p.lambda < 1.0 || p.s0 < 1.0 + std::sqrt((double)(3 - p.D)) - 1e-12) return SE_ERR_PARAM;
   }
   if (p.D == 1 || p.D == 2) {
     if (!(p.s > 0) || p.n_l < 0) {
@@ -1151,7 +1188,9 @@ se_status se_eval(se_plan* plan, long N, const void* xyz, const void* q, void* p
   end(1, plan->nsbtot * 12.0, 0.0);
   begin();
   if (se::launch_scatter(g, b, N, f64, st) != hipSuccess) return SE_ERR_DEVICE;
-  if (g.clip == 2 && se::launch_order(g, b, plan->nsbtot, f64, st) != hipSuccess) return SE_ERR_DEVICE;
+  // sub-bins in input order: the column sums and the per-tile energy partials
+  // then add in an order that does not depend on the scatter's atomics
+  if (se::launch_order(g, b, plan->nsbtot, f64, st) != hipSuccess) return SE_ERR_DEVICE;
   end(2, N * 2.0 * (8.0 + 4.0 * re), 0.0);
   begin();
   if (se::launch_spread(g, b, f64, st) != hipSuccess) return SE_ERR_DEVICE;
@@ -1249,7 +1288,8 @@ se_status se_get_device_status(se_plan* plan, void* hip_stream) {
 }
 
 // ---------------------------------------------------------------------------
-// Batched plans: one sub-plan per system; one persistent launch per evaluation.
+// Batched plans: one sub-plan per system; one launch per stage of the path
+// over the work items of all systems.
 // ---------------------------------------------------------------------------
 }  // extern "C"
 
@@ -1348,7 +1388,7 @@ se_status se_batch_plan_create(const se_params* params, const long* N, int n_sys
     bp->N.push_back(N[s]);
     bp->off.push_back(run);
     run += N[s];
-    const int n_order = d.g.clip == 2 ? (sp->nsbtot + se::kBlock - 1) / se::kBlock : 0;
+    const int n_order = (sp->nsbtot + se::kBlock - 1) / se::kBlock;
     const int items[se::BS_COUNT] = {d.nscan, d.nblk_bin, d.nscan, d.nscan, d.nblk_bin, n_order, d.ntiles,
                                      d.g.clip ? 0 : d.ntiles,
                                      d.pass[0].nitems, d.pass[1].nitems, d.pass[2].nitems, d.pass[3].nitems,

@@ -149,3 +149,53 @@ def test_real_space_cells_reject_invalid():
     assert lib.se_rs_plan_create(3, 1.0, 1.0, 0.1, 10, 5, 0, None, ctypes.byref(plan)) == L.SE_ERR_PARAM
     assert lib.se_rs_eval(None, 0, None, None, None, None, None, 0, None) == L.SE_ERR_ARG
     assert lib.se_rs_plan_destroy(None) == L.SE_OK
+
+
+@pytest.mark.parametrize("Q,xi,Lb", [(1000.0, 13.18, 1.0), (1e6, 56.4, 1.0), (3.3e4, 3.0, 10.0), (40.0, 0.7, 2.0)])
+def test_error_scale_matches_oracle(Q, xi, Lb):
+    """B = sqrt(Q) f_c(xi L)/L of Section 5.2, against the oracle's own
+    implementation of Eq. (fc-expression)."""
+    assert abs(L.se_error_scale(Q, xi, Lb) / se.B_scale(Q, xi, Lb) - 1.0) < 1e-14
+
+
+@pytest.mark.parametrize("Q,xi,Lb,tol", [(1000.0, 10.0, 1.0, 1e-6), (1e6, 56.4, 1.0, 1e-6), (4000.0, 6.0, 2.0, 1e-8),
+                                         (3.3e4, 3.0, 10.0, 1e-12), (1e5, 33.84, 1.0, 1e-3)])
+def test_real_space_cutoff_inverts_the_estimate(Q, xi, Lb, tol):
+    """Eq. (KP_rc) is the exact inverse of Eq. (KP_real_space): the oracle's
+    estimate at the library's cutoff equals the absolute tolerance tol B."""
+    rc = L.se_rs_cutoff_for_tolerance(Lb, xi, Q, tol)
+    est = se.kp_realspace_error(Q, xi, Lb, rc)
+    assert abs(est / (tol * se.B_scale(Q, xi, Lb)) - 1.0) < 1e-9
+
+
+def test_cutoff_and_scale_reject_invalid():
+    lib = L.load()
+    v = ctypes.c_double()
+    assert lib.se_error_scale(1.0, 1.0, 1.0, None) == L.SE_ERR_ARG
+    assert lib.se_error_scale(-1.0, 1.0, 1.0, ctypes.byref(v)) == L.SE_ERR_PARAM
+    assert lib.se_error_scale(1.0, 0.0, 1.0, ctypes.byref(v)) == L.SE_ERR_PARAM
+    assert lib.se_rs_cutoff_for_tolerance(1.0, 1.0, 1.0, 1e-6, None) == L.SE_ERR_ARG
+    for args in [(0.0, 1.0, 1.0, 1e-6), (1.0, -1.0, 1.0, 1e-6), (1.0, 1.0, 0.0, 1e-6), (1.0, 1.0, 1.0, 0.0),
+                 (1.0, float("nan"), 1.0, 1e-6)]:
+        assert lib.se_rs_cutoff_for_tolerance(*args, ctypes.byref(v)) == L.SE_ERR_PARAM
+
+
+@pytest.mark.parametrize("D,s0,ok", [(2, 1.99, False), (2, 2.0, True), (1, 2.40, False), (1, 2.42, True),
+                                     (0, 2.70, False), (0, 1.9, False), (0, 2.74, True)])
+def test_plan_create_enforces_the_upsampling_bound(D, s0, ok):
+    """Section 3.4: s0 >= 1 + sqrt(d) for d = 3 - D free directions.  Below
+    the bound the plan is rejected before any device work; at or above it
+    validation passes (the call then needs a device, so only the rejection is
+    checked here)."""
+    lib = L.load()
+    p = L.se_params()
+    p.D, p.L, p.xi, p.M, p.P, p.window = D, 1.0, 5.0, 32, 8, L.SE_WIN_PKB
+    p.s0, p.s, p.n_l = s0, 2.0, 2
+    plan = ctypes.c_void_p()
+    st = lib.se_plan_create(ctypes.byref(p), 10, None, ctypes.byref(plan))
+    if ok:
+        assert st != L.SE_ERR_PARAM
+        if plan.value:
+            lib.se_plan_destroy(plan)
+    else:
+        assert st == L.SE_ERR_PARAM and not plan.value

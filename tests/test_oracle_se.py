@@ -37,6 +37,26 @@ def test_kp_relative_estimates_printed_values():
         assert abs(r - printed) / printed < 0.10
 
 
+@pytest.mark.parametrize("D,Lb,N,xi", [(3, 1.0, 2000, 10.0), (3, 2.0, 4000, 6.0), (3, 1.0, 2000, 20.0),
+                                        (2, 1.0, 2000, 12.0), (0, 1.0, 2000, 12.0)])
+def test_kp_real_space_estimate_against_truncation(D, Lb, N, xi):
+    """Eq. (KP_real_space) against the measured truncation error of the direct
+    real-space sum (Eq. real_space_ewald) at cutoffs 1.6/xi ... 2.8/xi, uniform
+    +-1 charges: the estimate is within 0.6 ... 1.4 of the rms error over 400
+    targets (Kolafa and Perram's estimate is good to tens of percent).  A wrong
+    power of xi, L or rc, or a wrong exponent, misses by factors."""
+    x, q = wl.system(N, Lb, 5, "pm1")
+    Q = float((q * q).sum())
+    tg = np.arange(400)
+    ref, _ = direct.real_space(D, Lb, xi, 6.5 / xi, x, q, tg)
+    for f in (1.6, 2.2, 2.8):
+        rc = f / xi
+        phi, _ = direct.real_space(D, Lb, xi, rc, x, q, tg)
+        err = float(np.sqrt(np.mean((phi - ref) ** 2)))
+        ratio = err / se.kp_realspace_error(Q, xi, Lb, rc)
+        assert 0.6 < ratio < 1.4, (f, ratio)
+
+
 def test_vandermonde_condition_number():
     """Section 4.1: the Chebyshev-point Vandermonde matrix has condition
     number about 0.6 x 10^{0.38 nu}, 1.6e3 at nu = 9."""

@@ -83,17 +83,6 @@ def test_schedule_round_trip(tmp_path):
     assert not bench._load_schedule(path, qs)
 
 
-def test_real_space_cutoff_meets_the_estimate():
-    """The cutoff solves Eq. (KP_real_space) for the tolerance: the estimate
-    is at the tolerance there and above it just below."""
-    import math
-    Q, xi, L, tol = 1e6, 56.4, 1.0, 3e-4
-    rc = bench.kp_real_cutoff(Q, xi, L, tol)
-    est = lambda r: math.sqrt(Q) / xi ** 2 * (L * r) ** -1.5 * math.exp(-(xi * r) ** 2)
-    assert est(rc) <= tol and est(rc * (1 - 1e-9)) > tol * (1 - 1e-6)
-    assert est(0.99 * rc) > tol
-
-
 @pytest.mark.parametrize("D", [3, 2, 1, 0])
 def test_pair_count_matches_brute_force(D):
     import numpy as np

@@ -33,8 +33,15 @@
  *     compute precision (se_params.prec).  Energies are always float64.
  *   - All work is enqueued on the HIP stream passed in (NULL = the default
  *     stream) and returns without waiting, except where SE_SYNC_CHECK is set.
- *   - Nothing is allocated or freed during se_eval; plans own their device
- *     memory from se_plan_create until se_plan_destroy.
+ *   - Ownership: the caller owns every input and output buffer and the
+ *     workspace, one block of device memory per plan that holds all work
+ *     buffers of an evaluation (sorted particles, grid, spectra, partial
+ *     sums); se_plan_workspace_size reports its size and
+ *     se_plan_set_workspace binds it (batches and real-space plans likewise).
+ *     A plan itself owns only its tables (window coefficients, twiddles,
+ *     scaling vectors, Green's-function tables, transform work lists) and its
+ *     device status word.  Nothing is allocated or freed during an
+ *     evaluation.
  *   - No exceptions cross the ABI; every call returns an se_status.
  */
 #ifndef SE_MI355X_H
@@ -55,7 +62,8 @@ typedef enum {
   SE_ERR_NONFINITE = 5,   /* NaN or Inf in positions or charges                   */
   SE_ERR_DEVICE = 6,      /* a HIP runtime call failed                            */
   SE_ERR_NOMEM = 7,       /* device allocation failed in se_plan_create           */
-  SE_ERR_UNSUPPORTED = 8  /* valid request this build does not implement           */
+  SE_ERR_UNSUPPORTED = 8, /* valid request this build does not implement           */
+  SE_ERR_WORKSPACE = 9    /* no workspace bound, or one too small or misaligned     */
 } se_status;
 
 typedef enum { SE_WIN_GAUSSIAN = 0, SE_WIN_PKB = 1 } se_window;
@@ -116,7 +124,8 @@ typedef struct {
   int fft_wide;       /* bit k: transform pass k addresses with 64-bit offsets (its
                          workgroups' pencils span 4 GiB or more)                    */
   double h, shape, lambda, s0, s, R;
-  size_t device_bytes; /* device memory held by the plan                               */
+  size_t device_bytes; /* device memory held by the plan (tables, status word)         */
+  size_t workspace_bytes; /* workspace an evaluation needs (se_plan_workspace_size)    */
 } se_plan_info;
 
 typedef struct se_plan se_plan;
@@ -181,6 +190,23 @@ se_status se_plan_create(const se_params* params, long n_max, void* hip_stream, 
 /* Copy the derived sizes of a plan into *info (host). */
 se_status se_plan_get_info(const se_plan* plan, se_plan_info* info);
 
+/* Bytes of device workspace one evaluation of the plan needs (host output):
+ * the work buffers of Algorithm 4 for n_max particles (binned and sorted
+ * particle records, the gridding grid, the spectra of the transform passes,
+ * block partial sums, and the buffers of se_eval_vjp).
+ * Errors: SE_ERR_ARG for NULL arguments. */
+se_status se_plan_workspace_size(const se_plan* plan, size_t* bytes);
+
+/* Bind a caller-owned workspace: ptr is a device address aligned to 256
+ * bytes with at least se_plan_workspace_size bytes, owned by the caller (for
+ * example a torch tensor) and kept alive while evaluations that use it may
+ * run.  Every later se_eval / se_eval_vjp uses it; its contents need no
+ * initialisation and are overwritten by each evaluation, so evaluations that
+ * share one workspace must be ordered (one stream).  ptr = NULL unbinds.
+ * No device work is enqueued.
+ * Errors: SE_ERR_ARG (plan NULL); SE_ERR_WORKSPACE (misaligned or too small). */
+se_status se_plan_set_workspace(se_plan* plan, void* ptr, size_t bytes);
+
 /* One evaluation of Algorithm 4 for N <= n_max charges.
  *   xyz    device, N x 3 positions (float64, or float32 with SE_IN_F32)
  *   q      device, N charges (same dtype as xyz)
@@ -191,12 +217,46 @@ se_status se_plan_get_info(const se_plan* plan, se_plan_info* info);
  *          -xi/sqrt(pi) sum q^2 with SE_ADD_SELF), or NULL
  * The energy is one half of the paper's E^F = sum q phi (Section 7.2): with the
  * half, dE/dq = phi and -dE/dx = the forces above.
- * Errors: SE_ERR_ARG (bad pointers, N > n_max); with SE_SYNC_CHECK also
- * SE_ERR_NONFINITE, SE_ERR_OUT_OF_BOX, SE_ERR_NONNEUTRAL, SE_ERR_DEVICE.
+ * Errors: SE_ERR_ARG (bad pointers, N > n_max); SE_ERR_WORKSPACE (no
+ * workspace bound); with SE_SYNC_CHECK also SE_ERR_NONFINITE,
+ * SE_ERR_OUT_OF_BOX, SE_ERR_NONNEUTRAL, SE_ERR_DEVICE.
  * Without SE_SYNC_CHECK device-side errors are latched and reported by
  * se_get_device_status; outputs of such a call are not meaningful. */
 se_status se_eval(se_plan* plan, long N, const void* xyz, const void* q, void* phi, void* force,
                   double* energy, unsigned flags, void* hip_stream);
+
+/* Adjoint of phi = A(x) q (the vector-Jacobian product of the potential).
+ * The discrete operator A of Algorithm 4 (gridding, scaling, gathering with
+ * the same window) is symmetric, so for a cotangent g of phi:
+ *   grad_q   = A g  (+ phi_self(g) = -2 xi/sqrt(pi) g with SE_ADD_SELF)
+ *   grad_x_m = g_m grad phi(x_m) + q_m grad(A g)(x_m)   (Eq. force-method-1)
+ * The library runs Algorithm 4 with the charges g (no neutrality check) and
+ * combines the results in FP64.
+ *   xyz, q, g   device, N x 3 / N / N, float64 (float32 with SE_IN_F32)
+ *   grad_phi    device, N x 3 in the plan's precision: grad phi of the
+ *               forward evaluation (se_eval with SE_OUT_GRAD); may be NULL
+ *               when grad_x is NULL
+ *   grad_x      device, N x 3 in the input precision, or NULL
+ *   grad_q      device, N in the input precision, or NULL
+ * Flags: SE_IN_F32, SE_ADD_SELF, SE_SYNC_CHECK.  Uses the bound workspace.
+ * Errors: as se_eval. */
+se_status se_eval_vjp(se_plan* plan, long N, const void* xyz, const void* q, const void* g, const void* grad_phi,
+                      void* grad_x, void* grad_q, unsigned flags, void* hip_stream);
+
+/* Adjoint of the energy E = 1/2 sum_m q_m phi_m of se_eval (or of se_eval
+ * plus se_rs_eval with SE_ACCUMULATE): with dE/dq = phi and
+ * dE/dx_m = q_m grad phi(x_m) (Section 7.2), for a cotangent grad_E of E
+ *   grad_x = grad_E q grad_phi,   grad_q = grad_E phi   (FP64 arithmetic).
+ *   grad_E      device, one float64
+ *   q           device, N, float64 (float32 with SE_IN_F32)
+ *   phi         device, N in precision prec, or NULL when grad_q is NULL
+ *   grad_phi    device, N x 3 in precision prec, or NULL when grad_x is NULL
+ *   grad_x      device, N x 3 in the input precision, or NULL
+ *   grad_q      device, N in the input precision, or NULL
+ * Flags: SE_IN_F32.  Enqueued on hip_stream; no plan or workspace needed.
+ * Errors: SE_ERR_ARG, SE_ERR_DEVICE. */
+se_status se_energy_vjp(long N, se_precision prec, const double* grad_E, const void* q, const void* phi,
+                        const void* grad_phi, void* grad_x, void* grad_q, unsigned flags, void* hip_stream);
 
 /* Wait for the stream, then report (and clear) the device-side status word of
  * the plan's last evaluations. */
@@ -244,9 +304,16 @@ se_status se_batch_plan_create(const se_params* params, const long* N, int n_sys
                                se_batch_plan** out);
 
 /* Derived sizes of system 'sys' (host outputs, each may be NULL);
- * *reserved receives 0. */
+ * *reserved receives 0 (the output is reserved). */
 se_status se_batch_plan_get_info(const se_batch_plan* plan, int sys, se_plan_info* info,
                                  long* n_particles, int* reserved);
+
+/* Workspace of a batch: the workspaces of its systems one after another.
+ * Arguments and errors as se_plan_workspace_size / se_plan_set_workspace;
+ * binding uploads the systems' descriptors (synchronous host-to-device copy),
+ * so it must not overlap an evaluation of the same batch plan. */
+se_status se_batch_plan_workspace_size(const se_batch_plan* plan, size_t* bytes);
+se_status se_batch_plan_set_workspace(se_batch_plan* plan, void* ptr, size_t bytes);
 
 /* One batched evaluation.  xyz, q: device, concatenated as above (float64, or
  * float32 with SE_IN_F32); phi (sum N), force (sum N x 3): device, compute
@@ -327,16 +394,24 @@ typedef struct se_rs_plan se_rs_plan;
 se_status se_rs_cells(double L, double rc, long n_max, int cells_per_rc, int* cells, int* span);
 
 /* A real-space plan for up to n_max charges of periodicity D in a box of side
- * L with Ewald parameter xi and cutoff rc, sums in precision prec.  Allocates
- * one device buffer (cell counts and offsets, sorted records, energy
- * partials) that the plan owns until se_rs_plan_destroy.
+ * L with Ewald parameter xi and cutoff rc, sums in precision prec.  The plan
+ * owns only its device status word; the work buffers of an evaluation (cell
+ * counts and offsets, sorted records, energy partials) lie in a caller-owned
+ * workspace (se_rs_workspace_size, se_rs_set_workspace).
  * Errors: SE_ERR_ARG (out NULL), SE_ERR_PARAM (D, xi, prec, n_max > 2^31-1,
  * or as se_rs_cells), SE_ERR_NOMEM. */
 se_status se_rs_plan_create(int D, double L, double xi, double rc, long n_max, se_precision prec,
                             int cells_per_rc, void* hip_stream, se_rs_plan** out);
 
-/* Cells per direction, span and device bytes of a plan (host outputs, each
- * may be NULL).  Errors: SE_ERR_ARG for plan NULL. */
+/* Workspace of a real-space plan: size in bytes (host output), and binding
+ * of a caller-owned block (device, 256-byte aligned, at least that size;
+ * NULL unbinds).  As se_plan_workspace_size / se_plan_set_workspace.
+ * Errors: SE_ERR_ARG (NULL plan or output); SE_ERR_WORKSPACE. */
+se_status se_rs_workspace_size(const se_rs_plan* plan, size_t* bytes);
+se_status se_rs_set_workspace(se_rs_plan* plan, void* ptr, size_t bytes);
+
+/* Cells per direction, span and plan-owned device bytes of a plan (host
+ * outputs, each may be NULL).  Errors: SE_ERR_ARG for plan NULL. */
 se_status se_rs_get_info(const se_rs_plan* plan, int* cells, int* span, size_t* device_bytes);
 
 /* One evaluation for N <= n_max charges.
@@ -348,7 +423,8 @@ se_status se_rs_get_info(const se_rs_plan* plan, int* cells, int* span, size_t* 
  * hold (for example the output of se_eval on the same charges).  N = 0 writes
  * a zero energy (or leaves it with SE_ACCUMULATE).
  * Flags: SE_IN_F32, SE_OUT_GRAD, SE_ACCUMULATE, SE_SYNC_CHECK, SE_PROFILE.
- * Errors: SE_ERR_ARG (pointers, N, flags); with SE_SYNC_CHECK also
+ * Errors: SE_ERR_ARG (pointers, N, flags); SE_ERR_WORKSPACE (none bound);
+ * with SE_SYNC_CHECK also
  * SE_ERR_NONFINITE, SE_ERR_OUT_OF_BOX and SE_ERR_DEVICE. */
 se_status se_rs_eval(se_rs_plan* plan, long N, const void* xyz, const void* q, void* phi, void* force,
                      double* energy, unsigned flags, void* hip_stream);

@@ -21,6 +21,7 @@ SE_ERR_NONFINITE = 5
 SE_ERR_DEVICE = 6
 SE_ERR_NOMEM = 7
 SE_ERR_UNSUPPORTED = 8
+SE_ERR_WORKSPACE = 9
 
 SE_WIN_GAUSSIAN = 0
 SE_WIN_PKB = 1
@@ -93,6 +94,7 @@ class se_plan_info(ctypes.Structure):
         ("s", ctypes.c_double),
         ("R", ctypes.c_double),
         ("device_bytes", ctypes.c_size_t),
+        ("workspace_bytes", ctypes.c_size_t),
     ]
 
 
@@ -163,6 +165,18 @@ _SIGS = {
                                       ctypes.POINTER(ctypes.c_double)]),
     "se_rs_cutoff_for_tolerance": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                                   ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
+    "se_plan_workspace_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
+    "se_plan_set_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
+    "se_batch_plan_workspace_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
+    "se_batch_plan_set_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
+    "se_rs_workspace_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
+    "se_rs_set_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
+    "se_eval_vjp": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_long, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_uint, ctypes.c_void_p]),
+    "se_energy_vjp": (ctypes.c_int, [ctypes.c_long, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_uint, ctypes.c_void_p]),
     "se_batch_autotune": (ctypes.c_int, [ctypes.POINTER(se_params), ctypes.POINTER(ctypes.c_long), ctypes.c_int,
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint, ctypes.c_void_p,
                                          ctypes.POINTER(se_params), ctypes.POINTER(se_tune_report)]),
@@ -213,6 +227,52 @@ def se_plan_get_info(plan) -> se_plan_info:
     info = se_plan_info()
     _check(load().se_plan_get_info(plan, ctypes.byref(info)), "se_plan_get_info")
     return info
+
+
+def _ws_size(fn, plan, what):
+    b = ctypes.c_size_t()
+    _check(fn(plan, ctypes.byref(b)), what)
+    return b.value
+
+
+def se_plan_workspace_size(plan) -> int:
+    return _ws_size(load().se_plan_workspace_size, plan, "se_plan_workspace_size")
+
+
+def se_plan_set_workspace(plan, ptr, nbytes):
+    _check(load().se_plan_set_workspace(plan, ctypes.c_void_p(ptr), ctypes.c_size_t(nbytes)),
+           "se_plan_set_workspace")
+
+
+def se_batch_plan_workspace_size(plan) -> int:
+    return _ws_size(load().se_batch_plan_workspace_size, plan, "se_batch_plan_workspace_size")
+
+
+def se_batch_plan_set_workspace(plan, ptr, nbytes):
+    _check(load().se_batch_plan_set_workspace(plan, ctypes.c_void_p(ptr), ctypes.c_size_t(nbytes)),
+           "se_batch_plan_set_workspace")
+
+
+def se_rs_workspace_size(plan) -> int:
+    return _ws_size(load().se_rs_workspace_size, plan, "se_rs_workspace_size")
+
+
+def se_rs_set_workspace(plan, ptr, nbytes):
+    _check(load().se_rs_set_workspace(plan, ctypes.c_void_p(ptr), ctypes.c_size_t(nbytes)), "se_rs_set_workspace")
+
+
+def se_eval_vjp(plan, N, xyz_ptr, q_ptr, g_ptr, grad_phi_ptr, grad_x_ptr, grad_q_ptr, flags, stream) -> int:
+    """Returns the status (callers decide whether to raise)."""
+    return load().se_eval_vjp(plan, int(N), ctypes.c_void_p(xyz_ptr), ctypes.c_void_p(q_ptr), ctypes.c_void_p(g_ptr),
+                              ctypes.c_void_p(grad_phi_ptr), ctypes.c_void_p(grad_x_ptr),
+                              ctypes.c_void_p(grad_q_ptr), ctypes.c_uint(flags), ctypes.c_void_p(stream))
+
+
+def se_energy_vjp(N, prec, grad_E_ptr, q_ptr, phi_ptr, grad_phi_ptr, grad_x_ptr, grad_q_ptr, flags, stream) -> int:
+    """Returns the status (callers decide whether to raise)."""
+    return load().se_energy_vjp(int(N), int(prec), ctypes.c_void_p(grad_E_ptr), ctypes.c_void_p(q_ptr),
+                                ctypes.c_void_p(phi_ptr), ctypes.c_void_p(grad_phi_ptr), ctypes.c_void_p(grad_x_ptr),
+                                ctypes.c_void_p(grad_q_ptr), ctypes.c_uint(flags), ctypes.c_void_p(stream))
 
 
 def se_eval(plan, N, xyz_ptr, q_ptr, phi_ptr, force_ptr, energy_ptr, flags, stream) -> int:

@@ -6,8 +6,6 @@ provides device tensors and the current stream.
 """
 from __future__ import annotations
 
-import math
-
 import torch
 
 from . import _lib as L
@@ -18,6 +16,12 @@ _PRECS = {"f64": L.SE_F64, "f32": L.SE_F32}
 
 def _stream():
     return torch.cuda.current_stream().cuda_stream
+
+
+def _workspace(nbytes):
+    """A torch-owned device block for a plan's work buffers (the caching
+    allocator aligns blocks to 512 bytes, the library needs 256)."""
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device="cuda")
 
 
 def _check_out(out, N, dtype, dev, e_shape):
@@ -76,6 +80,11 @@ class SpectralEwald:
         self.D, self.L, self.xi = D, L_box, xi
         self._plan = L.se_plan_create(p, self.n_max, _stream())
         self.info = L.se_plan_get_info(self._plan)
+        self._bind()
+
+    def _bind(self):
+        self.workspace = _workspace(L.se_plan_workspace_size(self._plan))
+        L.se_plan_set_workspace(self._plan, self.workspace.data_ptr(), self.workspace.numel())
 
     @classmethod
     def from_params(cls, p, n_max):
@@ -92,6 +101,7 @@ class SpectralEwald:
         self.D, self.L, self.xi = p.D, p.L, p.xi
         self._plan = L.se_plan_create(p, self.n_max, _stream())
         self.info = L.se_plan_get_info(self._plan)
+        self._bind()
         return self
 
     def autotune(self, x, q, allow_nonneutral=False):
@@ -211,6 +221,8 @@ class SpectralEwaldBatch:
         self.total = sum(self.N)
         self.dtype = torch.float64 if self.params[0].prec == L.SE_F64 else torch.float32
         self._plan = L.se_batch_plan_create(self.params, self.N, _stream())
+        self.workspace = _workspace(L.se_batch_plan_workspace_size(self._plan))
+        L.se_batch_plan_set_workspace(self._plan, self.workspace.data_ptr(), self.workspace.numel())
 
     @classmethod
     def tuned(cls, params, N, x, q, allow_nonneutral=False):
@@ -284,26 +296,37 @@ class SpectralEwaldBatch:
     __call__ = evaluate
 
 
+def _energy_backward(gE, q, phi, grad, prec, needs_x, needs_q):
+    """dE/dx = gE q grad phi and dE/dq = gE phi, computed by se_energy_vjp."""
+    N = q.shape[0]
+    gx = torch.empty((N, 3), dtype=q.dtype, device=q.device) if needs_x else None
+    gq = torch.empty_like(q) if needs_q else None
+    gE = gE.to(device=q.device, dtype=torch.float64).contiguous()
+    st = L.se_energy_vjp(N, prec, gE.data_ptr(), q.data_ptr(), phi.data_ptr(), grad.data_ptr(),
+                         gx.data_ptr() if gx is not None else 0, gq.data_ptr() if gq is not None else 0,
+                         L.SE_IN_F32 if q.dtype == torch.float32 else 0, _stream())
+    if st != L.SE_OK:
+        raise L.SEError(st, "se_energy_vjp")
+    return gx, gq
+
+
 class SEEnergy(torch.autograd.Function):
     """E = 1/2 sum_m q_m phi_m (k-space part, plus the self energy when
-    add_self).  Backward: dE/dq = phi, dE/dx_m = q_m grad phi(x_m), the
-    gradient of the gathering window (Eq. force-method-1)."""
+    add_self).  Backward (se_energy_vjp): dE/dq = phi, dE/dx_m = q_m grad
+    phi(x_m), the gradient of the gathering window (Eq. force-method-1)."""
 
     @staticmethod
     def forward(ctx, x, q, plan: SpectralEwald, add_self: bool = False):
-        phi, grad, E = plan.evaluate(x.detach(), q.detach(), out_grad=True, add_self=add_self)
-        ctx.save_for_backward(q.detach(), phi, grad)
-        ctx.xdtype = x.dtype
+        x, q = _device_pair(x.detach(), q.detach())
+        phi, grad, E = plan.evaluate(x, q, out_grad=True, add_self=add_self)
+        ctx.save_for_backward(q, phi, grad)
+        ctx.prec = plan.params.prec
         return E
 
     @staticmethod
     def backward(ctx, gE):
         q, phi, grad = ctx.saved_tensors
-        gx = gq = None
-        if ctx.needs_input_grad[0]:
-            gx = (gE * q.to(torch.float64)[:, None] * grad.to(torch.float64)).to(ctx.xdtype)
-        if ctx.needs_input_grad[1]:
-            gq = (gE * phi.to(torch.float64)).to(q.dtype)
+        gx, gq = _energy_backward(gE, q, phi, grad, ctx.prec, ctx.needs_input_grad[0], ctx.needs_input_grad[1])
         return gx, gq, None, None
 
 
@@ -311,40 +334,36 @@ class EwaldEnergy(torch.autograd.Function):
     """Total electrostatic energy of Eq. (potential_split),
     E = 1/2 sum_m q_m (phi^F + phi^R + phi^self)_m: the k-space part by the
     SpectralEwald plan (with the self term), the real-space part by the
-    RealSpace plan accumulated into the same outputs.  Backward: dE/dq = phi,
-    dE/dx_m = q_m grad phi(x_m)."""
+    RealSpace plan accumulated into the same outputs.  Backward
+    (se_energy_vjp): dE/dq = phi, dE/dx_m = q_m grad phi(x_m)."""
 
     @staticmethod
     def forward(ctx, x, q, kplan: SpectralEwald, rplan: "RealSpace"):
-        xd, qd = x.detach(), q.detach()
+        xd, qd = _device_pair(x.detach(), q.detach())
         out = kplan.evaluate(xd, qd, out_grad=True, add_self=True)
         phi, grad, E = rplan.evaluate(xd, qd, out_grad=True, accumulate=True, out=out)
         ctx.save_for_backward(qd, phi, grad)
-        ctx.xdtype = x.dtype
+        ctx.prec = kplan.params.prec
         return E
 
     @staticmethod
     def backward(ctx, gE):
         q, phi, grad = ctx.saved_tensors
-        gx = gq = None
-        if ctx.needs_input_grad[0]:
-            gx = (gE * q.to(torch.float64)[:, None] * grad.to(torch.float64)).to(ctx.xdtype)
-        if ctx.needs_input_grad[1]:
-            gq = (gE * phi.to(torch.float64)).to(q.dtype)
+        gx, gq = _energy_backward(gE, q, phi, grad, ctx.prec, ctx.needs_input_grad[0], ctx.needs_input_grad[1])
         return gx, gq, None, None
 
 
 class SEPotential(torch.autograd.Function):
     """phi = A(x) q.  The discrete operator A (spread, scale, gather with one
-    window) is symmetric, so for a cotangent g:
+    window) is symmetric, so for a cotangent g (se_eval_vjp):
         dL/dq   = A g
         dL/dx_m = g_m grad phi(x_m) + q_m grad (A g)(x_m)."""
 
     @staticmethod
     def forward(ctx, x, q, plan: SpectralEwald, add_self: bool = False):
-        phi, grad, _ = plan.evaluate(x.detach(), q.detach(), out_grad=True, energy=False,
-                                     add_self=add_self)
-        ctx.save_for_backward(x.detach(), q.detach(), grad)
+        x, q = _device_pair(x.detach(), q.detach())
+        phi, grad, _ = plan.evaluate(x, q, out_grad=True, energy=False, add_self=add_self)
+        ctx.save_for_backward(x, q, grad)
         ctx.plan = plan
         ctx.add_self = add_self
         return phi
@@ -353,15 +372,16 @@ class SEPotential(torch.autograd.Function):
     def backward(ctx, g):
         x, q, grad = ctx.saved_tensors
         plan = ctx.plan
-        g = g.contiguous()
-        gin = g.to(x.dtype)
-        ag, agrad, _ = plan.evaluate(x, gin, out_grad=True, energy=False, add_self=ctx.add_self,
-                                     allow_nonneutral=True)
-        gq = ag.to(q.dtype) if ctx.needs_input_grad[1] else None
-        gx = None
-        if ctx.needs_input_grad[0]:
-            gx = (g.to(torch.float64)[:, None] * grad.to(torch.float64)
-                  + q.to(torch.float64)[:, None] * agrad.to(torch.float64)).to(x.dtype)
+        N = x.shape[0]
+        g = g.to(x.dtype).contiguous()
+        gx = torch.empty_like(x) if ctx.needs_input_grad[0] else None
+        gq = torch.empty_like(q) if ctx.needs_input_grad[1] else None
+        flags = (L.SE_IN_F32 if x.dtype == torch.float32 else 0) | (L.SE_ADD_SELF if ctx.add_self else 0)
+        st = L.se_eval_vjp(plan._plan, N, x.data_ptr(), q.data_ptr(), g.data_ptr(), grad.data_ptr(),
+                           gx.data_ptr() if gx is not None else 0, gq.data_ptr() if gq is not None else 0,
+                           flags, _stream())
+        if st != L.SE_OK:
+            raise L.SEError(st, "se_eval_vjp")
         return gx, gq, None, None
 
 
@@ -381,6 +401,8 @@ class RealSpace:
         self.n_max = int(n_max)
         self._plan = L.se_rs_plan_create(D, L_box, xi, rc, self.n_max, _PRECS[prec], cells_per_rc, _stream())
         self.cells, self.span, self.device_bytes = L.se_rs_get_info(self._plan)
+        self.workspace = _workspace(L.se_rs_workspace_size(self._plan))
+        L.se_rs_set_workspace(self._plan, self.workspace.data_ptr(), self.workspace.numel())
 
     def __del__(self):
         plan = getattr(self, "_plan", None)
@@ -423,8 +445,3 @@ class RealSpace:
         return out_phi, out_f, out_e
 
     __call__ = evaluate
-
-
-def self_potential(xi, q):
-    """phi_self = -2 xi / sqrt(pi) q (Section 2)."""
-    return -2.0 * xi / math.sqrt(math.pi) * q

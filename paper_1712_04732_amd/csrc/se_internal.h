@@ -139,6 +139,8 @@ struct EvalBuffers {
   int* status;        // device status word
   const void* wtab;   // window coefficient table (compute precision)
   void* grid;         // real grid G[0]*G[1]*G[2]
+  void* vjp_phi;      // n_max: A g of an adjoint evaluation (compute precision)
+  void* vjp_grad;     // n_max x 3: grad (A g) of an adjoint evaluation
 };
 
 // One system of a batch: its geometry, buffers and transform passes, and
@@ -197,6 +199,18 @@ hipError_t launch_gather(const GridGeom& g, const EvalBuffers& b, bool f64, void
                          int out_grad, double self_coef, hipStream_t st);
 hipError_t launch_energy(const GridGeom& g, const EvalBuffers& b, double* energy, double self_e,
                          hipStream_t st);
+// Sub-bin counts set to zero (a fill kernel, so that the evaluation records
+// no memset node when a caller captures it in a graph).
+hipError_t launch_zero(const GridGeom& g, const EvalBuffers& b, hipStream_t st);
+// Adjoint combinations of the autograd layer (FP64 arithmetic, outputs in the
+// input precision in_f32 ? float : double; phi, grad, ag, agrad in the compute
+// precision f64 ? double : float).  Either output may be null.
+//   energy:    gx = gE q grad,  gq = gE phi                 (gE: device scalar)
+//   potential: gx = g grad + q agrad,  gq = ag
+hipError_t launch_energy_vjp(long N, bool in_f32, bool f64, const double* gE, const void* q, const void* phi,
+                             const void* grad, void* gx, void* gq, hipStream_t st);
+hipError_t launch_potential_vjp(long N, bool in_f32, bool f64, const void* q, const void* g, const void* grad,
+                                const void* ag, const void* agrad, void* gx, void* gq, hipStream_t st);
 // Transforms (se_fft.hip).
 hipError_t launch_fft(const FftPass& p, bool f64, hipStream_t st);
 size_t fft_lds_bytes(const FftPass& p, bool f64);

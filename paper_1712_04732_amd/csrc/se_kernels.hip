@@ -1358,6 +1358,84 @@ hipError_t launch_energy(const GridGeom& g, const EvalBuffers& b, double* energy
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(kBlock) void zero_kernel(GridGeom g, EvalBuffers b);
+
+hipError_t launch_zero(const GridGeom& g, const EvalBuffers& b, hipStream_t st) {
+  zero_kernel<<<dim3(scan_blocks(g)), dim3(kBlock), 0, st>>>(g, b);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint combinations (the chain rule of the autograd layer), FP64 arithmetic.
+// E = 1/2 sum q phi with phi = A q symmetric in q gives dE/dq = phi and
+// dE/dx_m = q_m grad phi(x_m) (Section 7.2); for a potential cotangent g,
+// dL/dq = A g and dL/dx_m = g_m grad phi(x_m) + q_m grad (A g)(x_m).
+// ---------------------------------------------------------------------------
+template <typename Tin, typename T>
+__global__ __launch_bounds__(kBlock) void energy_vjp_kernel(long N, const double* __restrict__ gE,
+                                                            const Tin* __restrict__ q, const T* __restrict__ phi,
+                                                            const T* __restrict__ grad, Tin* __restrict__ gx,
+                                                            Tin* __restrict__ gq) {
+  const long i = (long)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= N) return;
+  const double s = *gE;
+  if (gx) {
+    const double sq = s * (double)q[i];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gx[3 * i + k] = (Tin)(sq * (double)grad[3 * i + k]);
+  }
+  if (gq) gq[i] = (Tin)(s * (double)phi[i]);
+}
+
+template <typename Tin, typename T>
+__global__ __launch_bounds__(kBlock) void potential_vjp_kernel(long N, const Tin* __restrict__ q,
+                                                               const Tin* __restrict__ g, const T* __restrict__ grad,
+                                                               const T* __restrict__ ag, const T* __restrict__ agrad,
+                                                               Tin* __restrict__ gx, Tin* __restrict__ gq) {
+  const long i = (long)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= N) return;
+  if (gx) {
+    const double gi = (double)g[i], qi = (double)q[i];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gx[3 * i + k] = (Tin)(gi * (double)grad[3 * i + k] + qi * (double)agrad[3 * i + k]);
+  }
+  if (gq) gq[i] = (Tin)ag[i];
+}
+
+template <typename Tin, typename T>
+static void energy_vjp_t(long N, const double* gE, const void* q, const void* phi, const void* grad, void* gx,
+                         void* gq, hipStream_t st) {
+  energy_vjp_kernel<Tin, T><<<dim3((unsigned)((N + kBlock - 1) / kBlock)), dim3(kBlock), 0, st>>>(
+      N, gE, (const Tin*)q, (const T*)phi, (const T*)grad, (Tin*)gx, (Tin*)gq);
+}
+
+template <typename Tin, typename T>
+static void potential_vjp_t(long N, const void* q, const void* g, const void* grad, const void* ag, const void* agrad,
+                            void* gx, void* gq, hipStream_t st) {
+  potential_vjp_kernel<Tin, T><<<dim3((unsigned)((N + kBlock - 1) / kBlock)), dim3(kBlock), 0, st>>>(
+      N, (const Tin*)q, (const Tin*)g, (const T*)grad, (const T*)ag, (const T*)agrad, (Tin*)gx, (Tin*)gq);
+}
+
+hipError_t launch_energy_vjp(long N, bool in_f32, bool f64, const double* gE, const void* q, const void* phi,
+                             const void* grad, void* gx, void* gq, hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  if (in_f32) f64 ? energy_vjp_t<float, double>(N, gE, q, phi, grad, gx, gq, st)
+                  : energy_vjp_t<float, float>(N, gE, q, phi, grad, gx, gq, st);
+  else f64 ? energy_vjp_t<double, double>(N, gE, q, phi, grad, gx, gq, st)
+           : energy_vjp_t<double, float>(N, gE, q, phi, grad, gx, gq, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_potential_vjp(long N, bool in_f32, bool f64, const void* q, const void* g, const void* grad,
+                                const void* ag, const void* agrad, void* gx, void* gq, hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  if (in_f32) f64 ? potential_vjp_t<float, double>(N, q, g, grad, ag, agrad, gx, gq, st)
+                  : potential_vjp_t<float, float>(N, q, g, grad, ag, agrad, gx, gq, st);
+  else f64 ? potential_vjp_t<double, double>(N, q, g, grad, ag, agrad, gx, gq, st)
+           : potential_vjp_t<double, float>(N, q, g, grad, ag, agrad, gx, gq, st);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Batched evaluation: many systems of uneven size and periodicity.  Each stage
 // of the path is one launch over the work items of all systems (a work item is
@@ -1371,6 +1449,8 @@ __device__ __forceinline__ void stage_zero(const GridGeom& g, const EvalBuffers&
     if (i < n) b.sb_count[i] = 0;
   }
 }
+
+__global__ __launch_bounds__(kBlock) void zero_kernel(GridGeom g, EvalBuffers b) { stage_zero(g, b, blockIdx.x); }
 
 template <typename T, int P>
 __device__ __forceinline__ void run_batch_stage(int st, const SysDesc& S, int sys_id, int li, const BatchIO& io,

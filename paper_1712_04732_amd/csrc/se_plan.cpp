@@ -3,21 +3,27 @@
 // The planner applies the paper's parameter rules (Section 3.3, Section 6),
 // builds every FP64 table once (PKB coefficients of Section 4.1, separable
 // scaling vectors and Green's-function tables of Eq. scale / Section 3.1),
-// runs Algorithm 3 on the GPU for free space, allocates all device memory and
-// records the launch sequence of Algorithm 4 for one system.  se_eval only
-// enqueues kernels.
+// runs Algorithm 3 on the GPU for free space, lays out the evaluation's work
+// buffers in a caller-owned workspace and records the launch sequence of
+// Algorithm 4 for one system.  se_eval only enqueues kernels.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/se.h"
 #include "se_internal.h"
+
+// Stand-in base of a plan's work pointers before a workspace is bound (the
+// first page, which no device allocation occupies).
+constexpr uintptr_t kWsStandIn = 4096;
 
 namespace {
 
@@ -160,7 +166,8 @@ const char* kStatusText[] = {"ok",
                              "non-finite position or charge",
                              "HIP runtime error",
                              "device allocation failed",
-                             "not supported"};
+                             "not supported",
+                             "no workspace bound, or the workspace is too small or misaligned"};
 
 }  // namespace
 
@@ -188,11 +195,44 @@ struct se_plan {
   size_t lds_limit = 65536;   // soft budget: keeps several workgroups per CU
   int fft_cap = 0;            // samples per FFT workgroup (0: by precision)
   size_t lds_max = 65536;     // device maximum per workgroup
-  size_t bytes = 0;
+  size_t bytes = 0;           // device memory the plan owns (tables)
+  // Workspace: every buffer of an evaluation (particles, grid, spectra,
+  // partial sums) lies in one caller-owned block.  During planning the
+  // buffers are laid out as offsets from a stand-in base (kWsStandIn, never a
+  // device address); binding a block moves every work pointer to it.
+  size_t ws_bytes = 0;
+  uintptr_t ws_base = kWsStandIn;
+  bool ws_bound = false;
 
   ~se_plan() {
     for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
     for (void* a : allocs) (void)hipFree(a);
+  }
+
+  // A work buffer of n bytes at the next 256-byte boundary of the workspace.
+  void* walloc(size_t n) {
+    const size_t o = (ws_bytes + 255) & ~(size_t)255;
+    ws_bytes = o + std::max<size_t>(n, 16);
+    return (void*)(ws_base + o);
+  }
+
+  // Move every work pointer from the current base to 'base'.
+  void rebase(uintptr_t base) {
+    const uintptr_t lo = ws_base, hi = ws_base + ws_bytes;
+    auto mv = [&](auto& ptr) {
+      const uintptr_t v = (uintptr_t)ptr;
+      if (v >= lo && v < hi) ptr = (std::remove_reference_t<decltype(ptr)>)(v - lo + base);
+    };
+    se::EvalBuffers& b = buf;
+    mv(b.sb_count); mv(b.sb_start); mv(b.sb_cursor); mv(b.p_key); mv(b.p_cell); mv(b.p_frac);
+    mv(b.s_cell); mv(b.s_idx); mv(b.s_fq); mv(b.bsum); mv(b.stage); mv(b.qpart); mv(b.epart);
+    mv(b.red); mv(b.grid); mv(b.vjp_phi); mv(b.vjp_grad);
+    for (se::FftPass& ps : passes)
+      for (se::FftClass& c : ps.cls) {
+        mv(c.in);
+        mv(c.out);
+      }
+    ws_base = base;
   }
 
   void* dalloc(size_t n) {
@@ -362,7 +402,7 @@ static bool finish_pass(se_plan* pl, se::FftPass& ps, int kind, int ncls,
 extern "C" {
 
 const char* se_status_string(se_status s) {
-  if ((int)s < 0 || (int)s > 8) return "unknown status";
+  if ((int)s < 0 || (int)s >= (int)(sizeof(kStatusText) / sizeof(kStatusText[0]))) return "unknown status";
   return kStatusText[(int)s];
 }
 
@@ -490,7 +530,7 @@ se_status se_plan_destroy(se_plan* plan) {
   return SE_OK;
 }
 
-static se_status build_passes(se_plan* pl);
+static se_status build_passes(se_plan* pl, hipStream_t st);
 static se_status precompute_0p(se_plan* pl, hipStream_t st, const void** table);
 
 // Largest number of tile-box images (periodic copies included) that meet one
@@ -782,26 +822,29 @@ static se_status plan_create(const se_params* params, long n_max, void* hip_stre
     const size_t esz = pl->f64 ? 8 : 4;
     const long nm = std::max(1L, n_max);
     const int nblk = (int)((nm + se::kBlock - 1) / se::kBlock);
-    b.sb_count = (int*)pl->dalloc(sizeof(int) * pl->nsbtot);
-    b.sb_start = (int*)pl->dalloc(sizeof(int) * (pl->nsbtot + 1));
-    b.sb_cursor = (int*)pl->dalloc(sizeof(int) * pl->nsbtot);
-    b.p_key = (int*)pl->dalloc(sizeof(int) * nm);
-    b.p_cell = (int*)pl->dalloc(sizeof(int) * nm);
-    b.p_frac = pl->dalloc(4 * esz * nm);
-    b.s_cell = (int*)pl->dalloc(sizeof(int) * nm);
-    b.s_idx = (int*)pl->dalloc(sizeof(int) * nm);
-    b.s_fq = pl->dalloc(4 * esz * nm);
-    b.qpart = (double*)pl->dalloc(sizeof(double) * 4 * nblk);
-    b.bsum = (int*)pl->dalloc(sizeof(int) * se::scan_blocks(g));
+    // work buffers: laid out in the workspace (bound later by the caller)
+    b.sb_count = (int*)pl->walloc(sizeof(int) * pl->nsbtot);
+    b.sb_start = (int*)pl->walloc(sizeof(int) * (pl->nsbtot + 1));
+    b.sb_cursor = (int*)pl->walloc(sizeof(int) * pl->nsbtot);
+    b.p_key = (int*)pl->walloc(sizeof(int) * nm);
+    b.p_cell = (int*)pl->walloc(sizeof(int) * nm);
+    b.p_frac = pl->walloc(4 * esz * nm);
+    b.s_cell = (int*)pl->walloc(sizeof(int) * nm);
+    b.s_idx = (int*)pl->walloc(sizeof(int) * nm);
+    b.s_fq = pl->walloc(4 * esz * nm);
+    b.qpart = (double*)pl->walloc(sizeof(double) * 4 * nblk);
+    b.bsum = (int*)pl->walloc(sizeof(int) * se::scan_blocks(g));
     b.stage = g.clip ? nullptr
-                     : pl->dalloc(esz * (size_t)pl->ntiles * (g.T[0] + p.P - 1) * (g.T[1] + p.P - 1) *
+                     : pl->walloc(esz * (size_t)pl->ntiles * (g.T[0] + p.P - 1) * (g.T[1] + p.P - 1) *
                                   (g.T[2] + p.P - 1));
-    b.epart = (double*)pl->dalloc(sizeof(double) * pl->ntiles);
-    b.red = (double*)pl->dalloc(sizeof(double) * 4);
+    b.epart = (double*)pl->walloc(sizeof(double) * pl->ntiles);
+    b.red = (double*)pl->walloc(sizeof(double) * 4);
+    b.grid = pl->walloc(esz * (size_t)g.G[0] * g.G[1] * g.G[2]);
+    b.vjp_phi = pl->walloc(esz * nm);
+    b.vjp_grad = pl->walloc(3 * esz * nm);
+    // the device status word persists across evaluations: plan-owned
     b.status = (int*)pl->dalloc(sizeof(int));
-    b.grid = pl->dalloc(esz * (size_t)g.G[0] * g.G[1] * g.G[2]);
-    if (!b.sb_count || !b.sb_start || !b.sb_cursor || !b.p_key || !b.p_cell || !b.p_frac || !b.bsum || (!b.stage && !g.clip) ||
-        !b.s_cell || !b.s_idx || !b.s_fq || !b.qpart || !b.epart || !b.red || !b.status || !b.grid) {
+    if (!b.status) {
       rc = SE_ERR_NOMEM;
       break;
     }
@@ -809,16 +852,17 @@ static se_status plan_create(const se_params* params, long n_max, void* hip_stre
       rc = SE_ERR_DEVICE;
       break;
     }
-    rc = build_passes(pl);
+    rc = build_passes(pl, st);
     if (rc != SE_OK) break;
-    (void)st;
   } while (false);
-  if (rc == SE_OK && hipDeviceSynchronize() != hipSuccess) rc = SE_ERR_DEVICE;
+  // table uploads are synchronous; the free-space precompute ran on st
+  if (rc == SE_OK && hipStreamSynchronize(st) != hipSuccess) rc = SE_ERR_DEVICE;
   if (rc != SE_OK) {
     delete pl;
     return rc;
   }
   I.device_bytes = pl->bytes;
+  I.workspace_bytes = pl->ws_bytes;
   I.fft_wide = 0;
   for (size_t k = 0; k < pl->passes.size(); ++k)
     if (pl->passes[k].wide) I.fft_wide |= 1 << k;
@@ -827,7 +871,7 @@ static se_status plan_create(const se_params* params, long n_max, void* hip_stre
 }
 
 // Record the transform passes of Algorithm 4 steps 2-4 for this plan.
-static se_status build_passes(se_plan* pl) {
+static se_status build_passes(se_plan* pl, hipStream_t st) {
   const se_params& p = pl->p;
   const se_plan_info& I = pl->info;
   const int D = p.D, M = p.M, Mt = I.Mt;
@@ -838,8 +882,7 @@ static se_status build_passes(se_plan* pl) {
 
   if (D == 3 || D == 2) {
     const int nx = M, Kx = M / 2 + 1;
-    void* cb = pl->dalloc(ce * (size_t)Kx * Gy * Gz);
-    if (!cb) return fail();
+    void* cb = pl->walloc(ce * (size_t)Kx * Gy * Gz);
     const void* sepM = pl->sep_table(M);
     const void* k2M = pl->k2_table(M);
     if (!sepM || !k2M) return fail();
@@ -925,13 +968,12 @@ static se_status build_passes(se_plan* pl) {
 
   if (D == 0) {
     const int n = 2 * Mt, Kx = Mt + 1;
-    void* cb = pl->dalloc(ce * (size_t)Kx * Mt * Mt);
-    void* cb2 = pl->dalloc(ce * (size_t)Kx * n * Mt);
-    if (!cb || !cb2) return fail();
+    void* cb = pl->walloc(ce * (size_t)Kx * Mt * Mt);
+    void* cb2 = pl->walloc(ce * (size_t)Kx * n * Mt);
     const void* sep = pl->sep_table(n);
     if (!sep) return fail();
     const void* table = nullptr;
-    se_status rc = precompute_0p(pl, nullptr, &table);
+    se_status rc = precompute_0p(pl, st, &table);
     if (rc != SE_OK) return rc;
     se::FftPass p1{};
     p1.cls[0] = make_class(n, Mt, Kx, pl->buf.grid, cb, 1, Mt, (long long)Mt * Mt, 1, Kx, (long long)Kx * Mt);
@@ -970,10 +1012,9 @@ static se_status build_passes(se_plan* pl) {
   const int Kx = M / 2 + 1, n0 = I.n0, nI = I.nI;
   const int nl = std::min(I.n_l, Kx - 1);
   const int nJ = Kx - 1 - nl;
-  void* cb = pl->dalloc(ce * (size_t)Kx * Mt * Mt);
-  void* b0 = pl->dalloc(ce * (size_t)n0 * Mt);
-  void* bI = pl->dalloc(ce * (size_t)std::max(1, nl) * nI * Mt);
-  if (!cb || !b0 || !bI) return fail();
+  void* cb = pl->walloc(ce * (size_t)Kx * Mt * Mt);
+  void* b0 = pl->walloc(ce * (size_t)n0 * Mt);
+  void* bI = pl->walloc(ce * (size_t)std::max(1, nl) * nI * Mt);
   const void* sepM = pl->sep_table(M);
   const void* k2M = pl->k2_table(M);
   const void* s0t = pl->sep_table(n0);
@@ -1138,12 +1179,41 @@ const char* kFftNames[] = {"fft_c2c_fwd", "fft_c2c_inv", "fft_r2c", "fft_c2r", "
 constexpr int kEventPool = 8192;
 }  // namespace
 
+static se_status eval_bound(se_plan* plan, long N, const void* xyz, const void* q, void* phi, void* force,
+                            double* energy, unsigned flags, void* hip_stream);
+
+se_status se_plan_workspace_size(const se_plan* plan, size_t* bytes) {
+  if (!plan || !bytes) return SE_ERR_ARG;
+  *bytes = plan->ws_bytes;
+  return SE_OK;
+}
+
+se_status se_plan_set_workspace(se_plan* plan, void* ptr, size_t bytes) {
+  if (!plan) return SE_ERR_ARG;
+  if (!ptr) {
+    plan->rebase(kWsStandIn);
+    plan->ws_bound = false;
+    return SE_OK;
+  }
+  if (((uintptr_t)ptr & 255) || bytes < plan->ws_bytes) return SE_ERR_WORKSPACE;
+  plan->rebase((uintptr_t)ptr);
+  plan->ws_bound = true;
+  return SE_OK;
+}
+
 se_status se_eval(se_plan* plan, long N, const void* xyz, const void* q, void* phi, void* force,
                   double* energy, unsigned flags, void* hip_stream) {
   if (!plan || N < 0 || N > plan->n_max) return SE_ERR_ARG;
   if (N > 0 && (!xyz || !q)) return SE_ERR_ARG;
   if (flags & ~(SE_IN_F32 | SE_ADD_SELF | SE_SYNC_CHECK | SE_OUT_GRAD | SE_ALLOW_NONNEUTRAL | SE_PROFILE))
     return SE_ERR_ARG;
+  if (!plan->ws_bound) return SE_ERR_WORKSPACE;
+  return eval_bound(plan, N, xyz, q, phi, force, energy, flags, hip_stream);
+}
+
+// se_eval on a plan whose work pointers point at a workspace.
+static se_status eval_bound(se_plan* plan, long N, const void* xyz, const void* q, void* phi, void* force,
+                            double* energy, unsigned flags, void* hip_stream) {
   hipStream_t st = (hipStream_t)hip_stream;
   const se::GridGeom& g = plan->geom;
   se::EvalBuffers& b = plan->buf;
@@ -1179,7 +1249,7 @@ se_status se_eval(se_plan* plan, long N, const void* xyz, const void* q, void* p
   const int P = g.P, nu = std::max(g.nu, 5);
 
   begin();
-  if (hipMemsetAsync(b.sb_count, 0, sizeof(int) * plan->nsbtot, st) != hipSuccess) return SE_ERR_DEVICE;
+  if (se::launch_zero(g, b, st) != hipSuccess) return SE_ERR_DEVICE;
   if (se::launch_bin(g, b, N, xyz, q, (flags & SE_IN_F32) != 0, f64, nblk, st) != hipSuccess) return SE_ERR_DEVICE;
   end(0, N * 4.0 * in_e, 0.0);
   begin();
@@ -1287,6 +1357,36 @@ se_status se_get_device_status(se_plan* plan, void* hip_stream) {
   return SE_OK;
 }
 
+se_status se_eval_vjp(se_plan* plan, long N, const void* xyz, const void* q, const void* g, const void* grad_phi,
+                      void* grad_x, void* grad_q, unsigned flags, void* hip_stream) {
+  if (!plan || N < 0 || N > plan->n_max) return SE_ERR_ARG;
+  if (N > 0 && (!xyz || !q || !g || (grad_x && !grad_phi))) return SE_ERR_ARG;
+  if (flags & ~(SE_IN_F32 | SE_ADD_SELF | SE_SYNC_CHECK)) return SE_ERR_ARG;
+  if (!plan->ws_bound) return SE_ERR_WORKSPACE;
+  if (!grad_x && !grad_q) return SE_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  // Algorithm 4 with the cotangent as charges: A g and grad (A g)
+  const unsigned ef = (flags & (SE_IN_F32 | SE_ADD_SELF)) | SE_OUT_GRAD | SE_ALLOW_NONNEUTRAL;
+  se_status rc = eval_bound(plan, N, xyz, g, plan->buf.vjp_phi, grad_x ? plan->buf.vjp_grad : nullptr, nullptr,
+                            ef, hip_stream);
+  if (rc != SE_OK) return rc;
+  if (se::launch_potential_vjp(N, (flags & SE_IN_F32) != 0, plan->f64, q, g, grad_phi, plan->buf.vjp_phi,
+                               plan->buf.vjp_grad, grad_x, grad_q, st) != hipSuccess)
+    return SE_ERR_DEVICE;
+  if (flags & SE_SYNC_CHECK) return se_get_device_status(plan, hip_stream);
+  return SE_OK;
+}
+
+se_status se_energy_vjp(long N, se_precision prec, const double* grad_E, const void* q, const void* phi,
+                        const void* grad_phi, void* grad_x, void* grad_q, unsigned flags, void* hip_stream) {
+  if (N < 0 || (prec != SE_F64 && prec != SE_F32) || (flags & ~SE_IN_F32)) return SE_ERR_ARG;
+  if (N > 0 && (!grad_E || (grad_x && (!q || !grad_phi)) || (grad_q && !phi))) return SE_ERR_ARG;
+  if (se::launch_energy_vjp(N, (flags & SE_IN_F32) != 0, prec == SE_F64, grad_E, q, phi, grad_phi, grad_x, grad_q,
+                            (hipStream_t)hip_stream) != hipSuccess)
+    return SE_ERR_DEVICE;
+  return SE_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Batched plans: one sub-plan per system; one launch per stage of the path
 // over the work items of all systems.
@@ -1305,6 +1405,11 @@ struct se_batch_plan {
   int P = 0;
   bool f64 = true;
   int device = 0;
+  // workspace: the sub-plans' workspaces one after another (256-byte aligned)
+  std::vector<se::SysDesc> desc;
+  std::vector<size_t> ws_off;
+  size_t ws_bytes = 0;
+  bool ws_bound = false;
   // algorithmic counts of one evaluation per stage, summed over systems
   double st_bytes[se::BS_COUNT] = {}, st_flops[se::BS_COUNT] = {};
   hipEvent_t ev[se::BS_COUNT + 1] = {};
@@ -1440,6 +1545,10 @@ se_status se_batch_plan_create(const se_params* params, const long* N, int n_sys
     by[se::BS_ENERGY] += d.ntiles * 8.0 + 8.0;
   }
   bp->total = run;
+  for (se_plan* sp : bp->sys) {
+    bp->ws_off.push_back(bp->ws_bytes);
+    bp->ws_bytes += (sp->ws_bytes + 255) & ~(size_t)255;
+  }
   for (int k = 0; k < se::BL_COUNT; ++k)
     for (int s = 0; s < n_sys; ++s) off[(size_t)k * (n_sys + 1) + s + 1] += off[(size_t)k * (n_sys + 1) + s];
   int lds_max = 0;
@@ -1460,6 +1569,7 @@ se_status se_batch_plan_create(const se_params* params, const long* N, int n_sys
     delete bp;
     return SE_ERR_NOMEM;
   }
+  bp->desc = desc;
   if (hipMemcpy(bp->d_sys, desc.data(), sizeof(se::SysDesc) * n_sys, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(bp->d_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice) != hipSuccess ||
       (!rec.empty() && hipMemcpy(bp->d_rec, rec.data(), sizeof(int4) * rec.size(), hipMemcpyHostToDevice) != hipSuccess) ||
@@ -1478,15 +1588,43 @@ se_status se_batch_plan_get_info(const se_batch_plan* plan, int sys, se_plan_inf
   if (info) {
     *info = plan->sys[sys]->info;
     info->device_bytes = plan->sys[sys]->bytes;
+    info->workspace_bytes = plan->sys[sys]->ws_bytes;
   }
   if (n_particles) *n_particles = plan->N[sys];
   if (persistent_blocks) *persistent_blocks = 0;
   return SE_OK;
 }
 
+se_status se_batch_plan_workspace_size(const se_batch_plan* plan, size_t* bytes) {
+  if (!plan || !bytes) return SE_ERR_ARG;
+  *bytes = plan->ws_bytes;
+  return SE_OK;
+}
+
+se_status se_batch_plan_set_workspace(se_batch_plan* plan, void* ptr, size_t bytes) {
+  if (!plan) return SE_ERR_ARG;
+  if (ptr && (((uintptr_t)ptr & 255) || bytes < plan->ws_bytes)) return SE_ERR_WORKSPACE;
+  for (size_t s = 0; s < plan->sys.size(); ++s) {
+    se_plan* sp = plan->sys[s];
+    sp->rebase(ptr ? (uintptr_t)ptr + plan->ws_off[s] : kWsStandIn);
+    sp->ws_bound = ptr != nullptr;
+    plan->desc[s].b = sp->buf;
+    for (int k = 0; k < se::kPasses; ++k) plan->desc[s].pass[k] = sp->passes[k];
+  }
+  plan->ws_bound = false;
+  if (!ptr) return SE_OK;
+  // the descriptors the stage kernels read: uploaded once per binding
+  if (hipMemcpy(plan->d_sys, plan->desc.data(), sizeof(se::SysDesc) * plan->desc.size(), hipMemcpyHostToDevice) !=
+      hipSuccess)
+    return SE_ERR_DEVICE;
+  plan->ws_bound = true;
+  return SE_OK;
+}
+
 se_status se_eval_batch(se_batch_plan* plan, const void* xyz, const void* q, void* phi, void* force,
                         double* energy, unsigned flags, void* hip_stream) {
   if (!plan) return SE_ERR_ARG;
+  if (!plan->ws_bound) return SE_ERR_WORKSPACE;
   if (plan->total > 0 && (!xyz || !q)) return SE_ERR_ARG;
   if (flags & ~(SE_IN_F32 | SE_ADD_SELF | SE_SYNC_CHECK | SE_OUT_GRAD | SE_ALLOW_NONNEUTRAL | SE_PROFILE))
     return SE_ERR_ARG;
@@ -1624,10 +1762,25 @@ struct TuneIO {
   void* st;
 };
 
+// Device memory the tuner allocates for its own runs (outputs, workspaces).
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  bool alloc(size_t n) { return hipMalloc(&p, std::max<size_t>(n, 16)) == hipSuccess; }
+};
+
 // One candidate for a single system; false if it cannot be planned or run.
 bool time_single(const se_params& p, long N, const TuneIO& io, TuneTimes* t) {
   se_plan* pl = nullptr;
   if (se_plan_create(&p, N, io.st, &pl) != SE_OK) return false;
+  DevBuf ws;
+  size_t wb = 0;
+  if (se_plan_workspace_size(pl, &wb) != SE_OK || !ws.alloc(wb) || se_plan_set_workspace(pl, ws.p, wb) != SE_OK) {
+    se_plan_destroy(pl);
+    return false;
+  }
   se_stage_record rec[32];
   int n = 0;
   bool ok = true;
@@ -1645,6 +1798,13 @@ bool time_single(const se_params& p, long N, const TuneIO& io, TuneTimes* t) {
 bool time_batch(const std::vector<se_params>& p, const std::vector<long>& N, const TuneIO& io, TuneTimes* t) {
   se_batch_plan* bp = nullptr;
   if (se_batch_plan_create(p.data(), N.data(), (int)p.size(), io.st, &bp) != SE_OK) return false;
+  DevBuf ws;
+  size_t wb = 0;
+  if (se_batch_plan_workspace_size(bp, &wb) != SE_OK || !ws.alloc(wb) ||
+      se_batch_plan_set_workspace(bp, ws.p, wb) != SE_OK) {
+    se_batch_plan_destroy(bp);
+    return false;
+  }
   se_stage_record rec[32];
   int n = 0;
   bool ok = true;
@@ -1748,14 +1908,6 @@ bool tune_knobs(se_params* base, int n_par, bool tune_xcd, Timer timer, se_tune_
   }
   return true;
 }
-
-struct DevBuf {
-  void* p = nullptr;
-  ~DevBuf() {
-    if (p) (void)hipFree(p);
-  }
-  bool alloc(size_t n) { return hipMalloc(&p, std::max<size_t>(n, 16)) == hipSuccess; }
-};
 
 }  // namespace
 

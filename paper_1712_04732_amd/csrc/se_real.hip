@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -427,6 +428,11 @@ __global__ __launch_bounds__(kRsBlock) void rs_energy_kernel(const double* __res
   if (threadIdx.x == 0) *gst(energy) = (accumulate ? *gld(energy) : 0.0) + 0.5 * sh[0];
 }
 
+__global__ __launch_bounds__(kRsBlock) void rs_zero_kernel(int* __restrict__ p, int n) {
+  const int i = blockIdx.x * kRsBlock + threadIdx.x;
+  if (i < n) gst(p)[i] = 0;
+}
+
 }  // namespace
 }  // namespace se
 
@@ -438,7 +444,13 @@ struct se_rs_plan {
   long n_max = 0;
   bool f64 = true;
   int ncell = 0, nscan = 0;
-  void* mem = nullptr;  // one device allocation, carved below
+  // workspace (caller-owned, bound by se_rs_set_workspace): byte offsets of
+  // the cell counts and starts, scan sums, per-charge cells, slots and
+  // sorted indices, per-cell energy partials and sorted records
+  size_t o_cnt = 0, o_start = 0, o_bsum = 0, o_cell = 0, o_slot = 0, o_sidx = 0, o_ep = 0, o_pos = 0;
+  size_t ws_bytes = 0;
+  bool ws_bound = false;
+  void* mem = nullptr;  // plan-owned: the device status word
   // slot: arrival slot of each charge in its cell (bin to scatter), then the x
   // cell index of each sorted record (order to pair sums)
   int *cnt = nullptr, *start = nullptr, *bsum = nullptr, *cell_of = nullptr, *slot = nullptr, *sidx = nullptr,
@@ -499,30 +511,49 @@ se_status se_rs_plan_create(int D, double L, double xi, double rc, long n_max, s
   const size_t n = (size_t)std::max(1L, n_max), nc = (size_t)p->ncell;
   const size_t rec = p->f64 ? 32 : 16;
   auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
-  const size_t o_cnt = 0, o_start = o_cnt + up(4 * nc), o_bsum = o_start + up(4 * (nc + 1)),
-               o_cell = o_bsum + up(4 * (size_t)p->nscan), o_slot = o_cell + up(4 * n), o_sidx = o_slot + up(4 * n),
-               o_stat = o_sidx + up(4 * n), o_ep = o_stat + 256, o_pos = o_ep + up(8 * nc), total = o_pos + up(rec * n);
-  if (hipMalloc(&p->mem, total) != hipSuccess) {
+  p->o_cnt = 0;
+  p->o_start = p->o_cnt + up(4 * nc);
+  p->o_bsum = p->o_start + up(4 * (nc + 1));
+  p->o_cell = p->o_bsum + up(4 * (size_t)p->nscan);
+  p->o_slot = p->o_cell + up(4 * n);
+  p->o_sidx = p->o_slot + up(4 * n);
+  p->o_ep = p->o_sidx + up(4 * n);
+  p->o_pos = p->o_ep + up(8 * nc);
+  p->ws_bytes = p->o_pos + up(rec * n);
+  if (hipMalloc(&p->mem, 256) != hipSuccess) {
     delete p;
     return SE_ERR_NOMEM;
   }
-  char* b = (char*)p->mem;
-  p->cnt = (int*)(b + o_cnt);
-  p->start = (int*)(b + o_start);
-  p->bsum = (int*)(b + o_bsum);
-  p->cell_of = (int*)(b + o_cell);
-  p->slot = (int*)(b + o_slot);
-  p->sidx = (int*)(b + o_sidx);
-  p->status = (int*)(b + o_stat);
-  p->epart = (double*)(b + o_ep);
-  p->spos = b + o_pos;
-  p->bytes = total;
+  p->status = (int*)p->mem;
+  p->bytes = 256;
   if (hipMemset(p->status, 0, sizeof(int)) != hipSuccess) {
     (void)hipFree(p->mem);
     delete p;
     return SE_ERR_DEVICE;
   }
   *out = p;
+  return SE_OK;
+}
+
+se_status se_rs_workspace_size(const se_rs_plan* plan, size_t* bytes) {
+  if (!plan || !bytes) return SE_ERR_ARG;
+  *bytes = plan->ws_bytes;
+  return SE_OK;
+}
+
+se_status se_rs_set_workspace(se_rs_plan* p, void* ptr, size_t bytes) {
+  if (!p) return SE_ERR_ARG;
+  if (ptr && (((uintptr_t)ptr & 255) || bytes < p->ws_bytes)) return SE_ERR_WORKSPACE;
+  char* b = (char*)ptr;
+  p->ws_bound = ptr != nullptr;
+  p->cnt = ptr ? (int*)(b + p->o_cnt) : nullptr;
+  p->start = ptr ? (int*)(b + p->o_start) : nullptr;
+  p->bsum = ptr ? (int*)(b + p->o_bsum) : nullptr;
+  p->cell_of = ptr ? (int*)(b + p->o_cell) : nullptr;
+  p->slot = ptr ? (int*)(b + p->o_slot) : nullptr;
+  p->sidx = ptr ? (int*)(b + p->o_sidx) : nullptr;
+  p->epart = ptr ? (double*)(b + p->o_ep) : nullptr;
+  p->spos = ptr ? (void*)(b + p->o_pos) : nullptr;
   return SE_OK;
 }
 
@@ -551,6 +582,7 @@ se_status se_rs_eval(se_rs_plan* plan, long N, const void* xyz, const void* q, v
   if (!plan || N < 0 || N > plan->n_max) return SE_ERR_ARG;
   if (N > 0 && (!xyz || !q)) return SE_ERR_ARG;
   if (flags & ~(SE_IN_F32 | SE_SYNC_CHECK | SE_OUT_GRAD | SE_ACCUMULATE | SE_PROFILE)) return SE_ERR_ARG;
+  if (!plan->ws_bound) return SE_ERR_WORKSPACE;
   hipStream_t st = (hipStream_t)hip_stream;
   int e0 = -1;
   if ((flags & SE_PROFILE) && N > 0) {
@@ -569,13 +601,16 @@ se_status se_rs_eval(se_rs_plan* plan, long N, const void* xyz, const void* q, v
   const RsGeom g = plan->g;
   if (N == 0) {
     // no charges: phi^R and its gradient are empty, the energy is zero
-    if (energy && !acc && hipMemsetAsync(energy, 0, sizeof(double), st) != hipSuccess) return SE_ERR_DEVICE;
+    if (energy && !acc) {
+      rs_energy_kernel<<<1, kRsBlock, 0, st>>>(plan->epart, 0, energy, 0);   // writes 0
+      if (hipGetLastError() != hipSuccess) return SE_ERR_DEVICE;
+    }
     if (flags & SE_SYNC_CHECK) return se_rs_get_device_status(plan, hip_stream);
     return SE_OK;
   }
   const int nb = (int)((N + kRsBlock - 1) / kRsBlock);
   mark(0);
-  if (hipMemsetAsync(plan->cnt, 0, sizeof(int) * nc, st) != hipSuccess) return SE_ERR_DEVICE;
+  rs_zero_kernel<<<(nc + kRsBlock - 1) / kRsBlock, kRsBlock, 0, st>>>(plan->cnt, nc);
   if (in32)
     rs_bin_kernel<float><<<nb, kRsBlock, 0, st>>>(g, N, (const float*)xyz, (const float*)q, plan->cnt,
                                                   plan->cell_of, plan->slot, plan->status);

@@ -22,8 +22,9 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_status_strings():
-    for s in range(9):
-        assert L.se_status_string(s)
+    for s in range(10):
+        assert L.se_status_string(s) != "unknown status"
+    assert L.se_status_string(10) == "unknown status"
     assert "neutral" in L.se_status_string(L.SE_ERR_NONNEUTRAL)
 
 
@@ -199,3 +200,23 @@ def test_plan_create_enforces_the_upsampling_bound(D, s0, ok):
             lib.se_plan_destroy(plan)
     else:
         assert st == L.SE_ERR_PARAM and not plan.value
+
+
+def test_workspace_and_adjoint_entries_reject_bad_arguments():
+    """The workspace and adjoint calls validate their arguments on the host
+    (no device work is enqueued for any of these)."""
+    lib = L.load()
+    b = ctypes.c_size_t()
+    for fn in (lib.se_plan_workspace_size, lib.se_batch_plan_workspace_size, lib.se_rs_workspace_size):
+        assert fn(None, ctypes.byref(b)) == L.SE_ERR_ARG
+    for fn in (lib.se_plan_set_workspace, lib.se_batch_plan_set_workspace, lib.se_rs_set_workspace):
+        assert fn(None, None, 0) == L.SE_ERR_ARG
+    assert lib.se_eval_vjp(None, 0, None, None, None, None, None, None, 0, None) == L.SE_ERR_ARG
+    # energy adjoint: bad precision, bad flags, missing inputs for a requested output
+    assert lib.se_energy_vjp(4, 7, None, None, None, None, None, None, 0, None) == L.SE_ERR_ARG
+    assert lib.se_energy_vjp(4, L.SE_F64, None, None, None, None, None, None, L.SE_ADD_SELF, None) == L.SE_ERR_ARG
+    dummy = ctypes.c_void_p(4096)
+    assert lib.se_energy_vjp(4, L.SE_F64, None, dummy, dummy, dummy, dummy, None, 0, None) == L.SE_ERR_ARG
+    assert lib.se_energy_vjp(4, L.SE_F64, dummy, None, dummy, dummy, dummy, None, 0, None) == L.SE_ERR_ARG
+    assert lib.se_energy_vjp(4, L.SE_F64, dummy, dummy, None, None, None, dummy, 0, None) == L.SE_ERR_ARG
+    assert lib.se_energy_vjp(0, L.SE_F64, None, None, None, None, None, None, 0, None) == L.SE_OK

@@ -225,6 +225,26 @@ se_status se_plan_set_workspace(se_plan* plan, void* ptr, size_t bytes);
 se_status se_eval(se_plan* plan, long N, const void* xyz, const void* q, void* phi, void* force,
                   double* energy, unsigned flags, void* hip_stream);
 
+/* Size of the library's static scratch array (see se_eval_static). */
+#define SE_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
+
+/* se_eval for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.
+ * Arguments, outputs and errors as se_eval; the plan's workspace binding is
+ * neither needed nor changed.  The work buffers lie in a static device array
+ * of SE_STATIC_SCRATCH_BYTES (128 MiB) that the library holds on each device
+ * it runs on until the process ends; nothing is allocated or freed.  The
+ * array keeps the last call's contents, and each evaluation clears what it
+ * accumulates itself.  Every call on one device shares that device's array:
+ * calls that overlap on one device (two streams, two threads) race and give
+ * undefined results, so they must be ordered by the caller.  The current
+ * device must be the plan's device.
+ * Errors: as se_eval; SE_ERR_WORKSPACE when the plan's workspace
+ * (se_plan_workspace_size) exceeds SE_STATIC_SCRATCH_BYTES; SE_ERR_ARG also
+ * for SE_PROFILE (its event pool would be created on first use). */
+se_status se_eval_static(se_plan* plan, long N, const void* xyz, const void* q, void* phi, void* force,
+                         double* energy, unsigned flags, void* hip_stream);
+
 /* Adjoint of phi = A(x) q (the vector-Jacobian product of the potential).
  * The discrete operator A of Algorithm 4 (gridding, scaling, gathering with
  * the same window) is symmetric, so for a cotangent g of phi:

@@ -126,6 +126,9 @@ _SIGS = {
     "se_eval": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_long, ctypes.c_void_p, ctypes.c_void_p,
                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint,
                                ctypes.c_void_p]),
+    "se_eval_static": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_long, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint,
+                                      ctypes.c_void_p]),
     "se_get_device_status": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "se_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "se_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -280,6 +283,17 @@ def se_eval(plan, N, xyz_ptr, q_ptr, phi_ptr, force_ptr, energy_ptr, flags, stre
     return load().se_eval(plan, int(N), ctypes.c_void_p(xyz_ptr), ctypes.c_void_p(q_ptr),
                           ctypes.c_void_p(phi_ptr), ctypes.c_void_p(force_ptr),
                           ctypes.c_void_p(energy_ptr), ctypes.c_uint(flags), ctypes.c_void_p(stream))
+
+
+SE_STATIC_SCRATCH_BYTES = 128 << 20
+
+
+def se_eval_static(plan, N, xyz_ptr, q_ptr, phi_ptr, force_ptr, energy_ptr, flags, stream) -> int:
+    """se_eval with the library's static scratch as workspace (allocates
+    nothing).  Returns the status (callers decide whether to raise)."""
+    return load().se_eval_static(plan, int(N), ctypes.c_void_p(xyz_ptr), ctypes.c_void_p(q_ptr),
+                                 ctypes.c_void_p(phi_ptr), ctypes.c_void_p(force_ptr),
+                                 ctypes.c_void_p(energy_ptr), ctypes.c_uint(flags), ctypes.c_void_p(stream))
 
 
 def se_get_device_status(plan, stream) -> int:

@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <vector>
@@ -1342,6 +1343,62 @@ se_status se_plan_profile(se_plan* plan, void* hip_stream, se_stage_record* out,
     plan->ev_used = 0;
   }
   return SE_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Evaluation without allocation: the workspace is a static device array of
+// SE_STATIC_SCRATCH_BYTES, one copy per device for the life of the process.
+// Host code never passes the array's name to a kernel (on the host it is
+// only a stand-in); it uses the device address hipGetSymbolAddress returns
+// for the current device, looked up once per device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[SE_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of the current device's copy of the scratch array.
+se_status scratch_address(int device, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SE_ERR_DEVICE;
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return SE_OK;
+}
+}  // namespace
+
+extern "C" {
+
+se_status se_eval_static(se_plan* plan, long N, const void* xyz, const void* q, void* phi, void* force,
+                         double* energy, unsigned flags, void* hip_stream) {
+  if (!plan || N < 0 || N > plan->n_max) return SE_ERR_ARG;
+  if (N > 0 && (!xyz || !q)) return SE_ERR_ARG;
+  // SE_PROFILE is refused: its event pool is created on first use
+  if (flags & ~(SE_IN_F32 | SE_ADD_SELF | SE_SYNC_CHECK | SE_OUT_GRAD | SE_ALLOW_NONNEUTRAL)) return SE_ERR_ARG;
+  if (plan->ws_bytes > SE_STATIC_SCRATCH_BYTES) return SE_ERR_WORKSPACE;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return SE_ERR_DEVICE;
+  if (dev != plan->device) return SE_ERR_ARG;
+  if (dev < 0 || dev >= kMaxScratchDevices) return SE_ERR_UNSUPPORTED;
+  void* base = nullptr;
+  const se_status sa = scratch_address(dev, &base);
+  if (sa != SE_OK) return sa;
+  // point the plan's work buffers at the scratch for this call only; the
+  // kernels receive them by value, so the caller's binding returns at once
+  const uintptr_t prev = plan->ws_base;
+  const bool prev_bound = plan->ws_bound;
+  plan->rebase((uintptr_t)base);
+  const se_status rc = eval_bound(plan, N, xyz, q, phi, force, energy, flags, hip_stream);
+  plan->rebase(prev);
+  plan->ws_bound = prev_bound;
+  return rc;
 }
 
 se_status se_get_device_status(se_plan* plan, void* hip_stream) {

@@ -502,6 +502,54 @@ def main_xi_balance(args):
         del ks, rs
 
 
+def main_force_methods(args):
+    """Section 7.2, Fig. force: the two ways of computing the k-space force on
+    the paper's workload (3P, N = 1e4 uniform in the unit box, charges uniform
+    in [-1, 1] re-centred, xi = 8, M = 64, PKB window).  For each P, the
+    force error of method 1 (gradient of the gathering window) and method 2
+    (i k in the scaling step, three inverse transforms and three gatherings)
+    against a high-accuracy GPU FP64 reference (method 1, P = 16, nu = 9; its
+    own parity with the oracles is tested), and the time of an evaluation of
+    the forces alone.  One JSON line per P and precision."""
+    import torch
+
+    import workloads as wl
+    from paper_1712_04732_amd import SpectralEwald
+
+    N, L, xi, M = 10000, 1.0, 8.0, 64
+    x, q = wl.system(N, L, 171204732 + 7, "uniform")
+    dev = torch.device("cuda:0")
+    x64, q64 = torch.tensor(x, device=dev), torch.tensor(q, device=dev)
+    ref_plan = SpectralEwald(3, L, xi, M, 16, nu=9, prec="f64", n_max=N)
+    _, fref, _ = ref_plan(x64, q64)
+    fref = fref.cpu().numpy()
+
+    def timed(plan, xt, qt):
+        f = torch.empty((N, 3), dtype=plan.dtype, device=dev)
+        out = (None, f, None)
+        plan(xt, qt, out=out)
+        for _ in range(args.warmup):
+            plan(xt, qt, out=out, check=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan(xt, qt, out=out, check=False)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / args.steps, f.double().cpu().numpy()
+
+    for prec in ("f64", "f32"):
+        xt, qt = x64, q64     # FP64 inputs (binning forms cell offsets in FP64 for both precisions)
+        for P in (4, 6, 8, 10, 12, 14):
+            row = {"workload": "W3_force_3P", "N": N, "xi": xi, "M": M, "P": P, "prec": prec}
+            for m in (1, 2):
+                plan = SpectralEwald(3, L, xi, M, P, prec=prec, n_max=N, force_method=m)
+                ms, f = timed(plan, xt, qt)
+                row[f"method{m}_ms"] = ms
+                row[f"method{m}_force_err"] = rel_rms(f, fref)
+                del plan
+            print(json.dumps(row), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -517,6 +565,8 @@ def main():
                     help="time the real-space part instead (single-system workloads; default C4_1P)")
     ap.add_argument("--xi-balance", action="store_true",
                     help="time k space + real space against xi (single-system workloads; default C4_1P)")
+    ap.add_argument("--force-methods", action="store_true",
+                    help="force method 1 vs method 2 against P on the paper's 3P workload (Section 7.2)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device 5 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -539,6 +589,8 @@ def main():
         return main_real_space(args)
     if args.xi_balance:
         return main_xi_balance(args)
+    if args.force_methods:
+        return main_force_methods(args)
     if args.workload == "C5_batch":
         return main_batch(args)
 

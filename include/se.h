@@ -107,6 +107,11 @@ typedef struct {
                          own grid column in registers (no atomics; tiles with
                          x*y <= 256 and z <= 16);
                          0 -> 3 below 0.1 particles per grid point, else 1        */
+  int force_method;   /* forces and grad phi (Section 7.2): 0 or 1 method 1, the
+                         gradient of the gathering window (Eq. force-method-1);
+                         2 method 2, the scaling step times i k_d and steps 4-5
+                         once per direction d, each gathering with the window
+                         itself (single plans only)                            */
 } se_params;
 
 /* Derived sizes of a plan (read-only report). */
@@ -316,7 +321,8 @@ se_status se_plan_destroy(se_plan* plan);
  * launch whose workgroups are the work items (particle blocks, tiles, pencil
  * groups) of all systems, so the whole batch costs 14 launches.
  * Errors: SE_ERR_ARG; SE_ERR_UNSUPPORTED when P, window or precision differ
- * between systems or P is not instantiated for batches; SE_ERR_PARAM,
+ * between systems, P is not instantiated for batches or a system asks for
+ * force method 2; SE_ERR_PARAM,
  * SE_ERR_NOMEM, SE_ERR_DEVICE as se_plan_create. */
 typedef struct se_batch_plan se_batch_plan;
 

@@ -408,8 +408,28 @@ def _mode_classes(p: Params):
     return zero, I, J
 
 
-def scaled_convolution(H, p: Params, GR=None):
-    """Steps 2-4 of Algorithm 4 on the gridded H: returns Ht (real, same shape)."""
+def _ik(k, deriv, d):
+    """Factor i k_d of force method 2 (Section 7.2) for direction d, or 1.
+    The Nyquist wavenumber of an even-length transform gets the factor 0 so
+    that the derivative of a real grid stays real."""
+    if deriv != d:
+        return 1.0
+    k = np.asarray(k, dtype=np.float64)
+    n = k.shape[0]
+    f = 1j * k
+    if n % 2 == 0:
+        f = f.copy()
+        f[n // 2] = 0.0
+    return f
+
+
+def scaled_convolution(H, p: Params, GR=None, deriv=None):
+    """Steps 2-4 of Algorithm 4 on the gridded H: returns Ht (real, same shape).
+
+    deriv = d in {0, 1, 2}: force method 2 of Section 7.2 -- the scaling step
+    is multiplied by i k_d (k_d the wavenumber of direction d on the grid that
+    direction is transformed on), so the result is the derivative of Ht along
+    d."""
     D, M, Mt, L, h = p.D, p.M, p.Mt, p.L, p.h
     if D == 3:
         Hh = np.fft.fftn(H)
@@ -419,7 +439,9 @@ def scaled_convolution(H, p: Params, GR=None):
         S = sep[:, None, None] * sep[None, :, None] * sep[None, None, :]
         with np.errstate(divide="ignore"):
             G = np.where(K2 == 0, 0.0, 1.0 / np.where(K2 == 0, 1.0, K2))  # Eq. (G_hat_3d)
-        return np.fft.ifftn(S * G * Hh).real
+        ik = (np.reshape(_ik(k, deriv, 0), (-1, 1, 1)) * np.reshape(_ik(k, deriv, 1), (1, -1, 1))
+              * np.reshape(_ik(k, deriv, 2), (1, 1, -1)))
+        return np.fft.ifftn(ik * S * G * Hh).real
 
     if D == 0:
         if GR is None:
@@ -429,7 +451,9 @@ def scaled_convolution(H, p: Params, GR=None):
         k = _free_k(n, h)
         sep = _sep(k, p)
         S = sep[:, None, None] * sep[None, :, None] * sep[None, None, :]
-        return _ifft_trunc(S * GR * Hh, (0, 1, 2), Mt).real
+        ik = (np.reshape(_ik(k, deriv, 0), (-1, 1, 1)) * np.reshape(_ik(k, deriv, 1), (1, -1, 1))
+              * np.reshape(_ik(k, deriv, 2), (1, 1, -1)))
+        return _ifft_trunc(ik * S * GR * Hh, (0, 1, 2), Mt).real
 
     zero, I, J = _mode_classes(p)
     kp = _periodic_k(M, L)
@@ -453,6 +477,9 @@ def scaled_convolution(H, p: Params, GR=None):
             else:
                 G = 1.0 / (kk2[:, None] + kap[None, :] ** 2)    # Eq. (G_hat_2d), k != 0
             S = s12[:, None] * _sep(kap, p)[None, :] * G
+            ik12 = (np.broadcast_to(np.reshape(_ik(kp, deriv, 0), (-1, 1)), (M, M))
+                    * np.broadcast_to(np.reshape(_ik(kp, deriv, 1), (1, -1)), (M, M)))[mask]
+            S = S * ik12[:, None] * np.reshape(_ik(kap, deriv, 2), (1, -1))
             out[mask] = _ifft_trunc(S * Hs, (1,), Mt)       # Algorithm 2, steps 1-4
         return np.fft.ifft2(out, axes=(0, 1)).real          # Algorithm 2, step 5
 
@@ -474,6 +501,8 @@ def scaled_convolution(H, p: Params, GR=None):
         else:
             G = 1.0 / (k1[:, None, None] ** 2 + KAP2[None, :, :])   # Eq. (G_hat_1d), k != 0
         S = sep_p[mask][:, None, None] * S2[None, :, :] * G
+        S = (S * np.reshape(np.broadcast_to(_ik(kp, deriv, 0), (M,))[mask], (-1, 1, 1))
+             * np.reshape(_ik(kap, deriv, 1), (1, -1, 1)) * np.reshape(_ik(kap, deriv, 2), (1, 1, -1)))
         out[mask] = _ifft_trunc(S * Hs, (1, 2), Mt)
     return np.fft.ifft(out, axis=0).real
 
@@ -512,12 +541,24 @@ def gathering(Ht, geom, p: Params, targets=None, grad=False):
     return c0 * phi, c0 * g
 
 
-def spectral_ewald(x, q, p: Params, targets=None, grad=True, GR=None):
+def spectral_ewald(x, q, p: Params, targets=None, grad=True, GR=None, force_method=1):
     """Algorithm 4: the SE approximation of phi^{D,F} (without the self
-    term) and its gradient at the targets (default: all particles)."""
+    term) and its gradient at the targets (default: all particles).
+
+    force_method 1 differentiates the gathering window (Eq. force-method-1);
+    force_method 2 differentiates in Fourier space (Section 7.2): the scaling
+    step carries i k_d, steps 4 and 5 run once per direction, and each
+    gathering uses the window itself."""
     H, geom = gridding(x, q, p)
+    if p.D == 0 and GR is None:
+        GR = precompute_0P(p)
     Ht = scaled_convolution(H, p, GR=GR)
-    return gathering(Ht, geom, p, targets=targets, grad=grad)
+    if not grad or force_method == 1:
+        return gathering(Ht, geom, p, targets=targets, grad=grad)
+    phi, _ = gathering(Ht, geom, p, targets=targets, grad=False)
+    g = np.stack([gathering(scaled_convolution(H, p, GR=GR, deriv=d), geom, p, targets=targets)[0]
+                  for d in range(3)], axis=1)
+    return phi, g
 
 
 def energy(q, phi):

@@ -60,6 +60,7 @@ class se_params(ctypes.Structure):
         ("xcd_tiles", ctypes.c_int),
         ("xcd_fft", ctypes.c_int),
         ("spread_mode", ctypes.c_int),
+        ("force_method", ctypes.c_int),
     ]
 
 

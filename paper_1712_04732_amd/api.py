@@ -42,13 +42,17 @@ class SpectralEwald:
     """A plan for one system size class: periodicity D, box L, Ewald xi, grid M,
     window support P.  Parameters left as None follow the paper's rules
     (Section 6); s and n_l need either explicit values or Q and tol.
+    force_method 1 differentiates the gathering window, 2 multiplies the
+    scaling step by i k (Section 7.2); with 2 the autograd functions receive
+    method 2's gradient, an approximation of the discrete energy's gradient
+    to the method's accuracy.
 
     Call it with positions x (N,3) and charges q (N,) on the GPU.
     """
 
     def __init__(self, D, L_box, xi, M, P, *, window="pkb", prec="f64", n_max=1 << 20,
                  Q=None, tol=None, shape=None, nu=None, lam=None, s0=None, s=None, n_l=None,
-                 tile=0):
+                 tile=0, force_method=1):
         if not torch.cuda.is_available():
             raise RuntimeError("SpectralEwald needs a HIP device")
         L.load()
@@ -73,6 +77,7 @@ class SpectralEwald:
         if n_l is not None:
             p.n_l = n_l
         p.tile = tile
+        p.force_method = force_method
         self.params = p
         self.n_max = int(n_max)
         self.prec = prec

@@ -622,7 +622,7 @@ __device__ __forceinline__ void stage_fft(const FftPass& P, int cls, int b0s, in
   if (ip) fft_run_ip<T, SIGN>(buf, tw, C, lgF, Bp);
   else res = fft_run<T, SIGN>(buf, buf2, tw, C, lgF, Bp);
 
-  if constexpr (KIND == K_FUSED) {
+  if constexpr (KIND == K_FUSED || KIND == K_FUSED_D) {
     // scaling step, Eq. (scale), on the spectrum of each pencil; the block
     // size is a multiple of B, so each thread keeps one pencil p throughout
     const int p = threadIdx.x & ((1 << lgB) - 1);
@@ -630,7 +630,23 @@ __device__ __forceinline__ void stage_fft(const FftPass& P, int cls, int b0s, in
     if (p < cnt) {
       const ScaleRow<T> row = scale_row<T>(C, b0s + p, b1);
       int t = threadIdx.x >> lgB;
-      for (int l = __mul24(t, Bp) + p; t < n; t += dt, l += dl) lput<T>(res, l, cscale(lget<T>(res, l), scale_at<T>(C, row, t)));
+      if constexpr (KIND == K_FUSED) {
+        for (int l = __mul24(t, Bp) + p; t < n; t += dt, l += dl)
+          lput<T>(res, l, cscale(lget<T>(res, l), scale_at<T>(C, row, t)));
+      } else {
+        // force method 2 (Section 7.2): the scaling times i k_d; k_d is a
+        // pencil constant for the A and B directions and varies along the
+        // pencil (z) otherwise
+        const int d = P.deriv;
+        const bool along = d != C.dirA && d != C.dirB;
+        const T kp = d == C.dirA ? gld((const T*)C.dA)[b0s + p + C.offA]
+                                 : (d == C.dirB ? gld((const T*)C.dB)[b1 + C.offB] : (T)0);
+        for (int l = __mul24(t, Bp) + p; t < n; t += dt, l += dl) {
+          const T k = along ? gld((const T*)C.dC)[t] : kp;
+          const cx<T> v = cscale(lget<T>(res, l), scale_at<T>(C, row, t) * k);
+          lput<T>(res, l, cx<T>{-v.im, v.re});
+        }
+      }
     }
     __syncthreads();
     if (ip) fft_run_ip<T, +1>(buf, tw, C, lgB, Bp);
@@ -681,6 +697,7 @@ static void launch_fft_t(const FftPass& p, hipStream_t st) {
     case K_C2C_INV: fft_kernel<T, K_C2C_INV, OFF><<<grid, block, lds, st>>>(p); break;
     case K_R2C: fft_kernel<T, K_R2C, OFF><<<grid, block, lds, st>>>(p); break;
     case K_C2R: fft_kernel<T, K_C2R, OFF><<<grid, block, lds, st>>>(p); break;
+    case K_FUSED_D: fft_kernel<T, K_FUSED_D, OFF><<<grid, block, lds, st>>>(p); break;
     default: fft_kernel<T, K_FUSED, OFF><<<grid, block, lds, st>>>(p); break;
   }
 }

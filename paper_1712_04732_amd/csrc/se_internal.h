@@ -56,7 +56,10 @@ enum GMode : int {
   G_TAB3 = 4    // folded table over (b0, b1, t) (0P, Algorithm 3 output)
 };
 
-enum FftKind : int { K_C2C_FWD = 0, K_C2C_INV = 1, K_R2C = 2, K_C2R = 3, K_FUSED = 4 };
+// K_FUSED_D: the fused pass of force method 2 (Section 7.2), whose scaling
+// carries the factor i k_d of one direction d (FftPass::deriv); single plans
+// only (batch transform lists hold kinds 0..4).
+enum FftKind : int { K_C2C_FWD = 0, K_C2C_INV = 1, K_R2C = 2, K_C2R = 3, K_FUSED = 4, K_FUSED_D = 5 };
 
 // One group of pencils that share a transform length.  A pencil is addressed
 // by (b0, b1); its sample t sits at base + b0*s0 + b1*s1 + t*st (in complex
@@ -85,6 +88,14 @@ struct FftClass {
                                   // G_TAB2 [t][b0], G_TAB3 [t][b1][b0]
   int fold1, fold2;               // transform lengths used to fold b1 and t
   int fold0;                      // transform length used to fold b0 (0: b0 not folded)
+  // force method 2: signed wavenumbers k of the b0 (A), b1 (B) and pencil (C)
+  // directions, indexed as sA, sB, sC (0 at the Nyquist index of an even
+  // length), and the physical directions (0 x, 1 y, 2 z) of A and B; the
+  // pencil direction of a fused pass is z
+  const void* dA;
+  const void* dB;
+  const void* dC;
+  int dirA, dirB;
 };
 
 struct FftPass {
@@ -98,6 +109,7 @@ struct FftPass {
   int xcd;                        // item mapping: 0 plain, 1 one range per XCD, c >= 2 chunks of c
   int wide;                       // 1 if a workgroup's pencils span 4 GiB or more (64-bit offsets)
   int inplace;                    // 1: stages in place in one LDS buffer
+  int deriv;                      // K_FUSED_D: direction d of the factor i k_d
   double alg_bytes, alg_flops;    // algorithmic counts of one launch (tracing only)
 };
 
@@ -195,8 +207,14 @@ hipError_t launch_scatter(const GridGeom& g, const EvalBuffers& b, long N, bool 
 hipError_t launch_order(const GridGeom& g, const EvalBuffers& b, int nsbtot, bool f64, hipStream_t st);
 hipError_t launch_spread(const GridGeom& g, const EvalBuffers& b, bool f64, hipStream_t st);
 hipError_t launch_fold(const GridGeom& g, const EvalBuffers& b, bool f64, hipStream_t st);
+// Gathering modes: GM_ALL phi and grad phi (Eq. force-method-1, forces by
+// method 1) and the per-tile energy partials; GM_PHI phi and the energy
+// partials only; GM_COMP one force component by method 2: 'force' column
+// comp receives -q (or 1 with out_grad) times the gathered value of a grid
+// that holds the derivative along comp.
+enum GatherMode : int { GM_ALL = 0, GM_PHI = 1, GM_COMP = 2 };
 hipError_t launch_gather(const GridGeom& g, const EvalBuffers& b, bool f64, void* phi, void* force,
-                         int out_grad, double self_coef, hipStream_t st);
+                         int out_grad, double self_coef, hipStream_t st, int mode = GM_ALL, int comp = 0);
 hipError_t launch_energy(const GridGeom& g, const EvalBuffers& b, double* energy, double self_e,
                          hipStream_t st);
 // Sub-bin counts set to zero (a fill kernel, so that the evaluation records

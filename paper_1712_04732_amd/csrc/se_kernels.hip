@@ -1095,10 +1095,11 @@ hipError_t launch_fold(const GridGeom& g, const EvalBuffers& b, bool f64, hipStr
 // contracts its plane separably (x, then y) and the group sums the planes
 // with shuffles.
 // ---------------------------------------------------------------------------
-template <typename T, int P>
+template <typename T, int P, int MODE = GM_ALL>
 __device__ __forceinline__ void stage_gather(const GridGeom& g, const EvalBuffers& b, T* __restrict__ phi,
                              T* __restrict__ force, int out_grad, double self_coef, int item,
-                             unsigned char* smem) {
+                             unsigned char* smem, int comp = 0) {
+  constexpr bool GRAD = MODE == GM_ALL;
   constexpr int G2 = Lanes<P>::G2, PPW = Lanes<P>::PPW;
   const int TX = g.T[0], TY = g.T[1], TZ = g.T[2];
   const int t_id = item;
@@ -1127,7 +1128,7 @@ __device__ __forceinline__ void stage_gather(const GridGeom& g, const EvalBuffer
   const int nr = (sz[1] - sz[0] + 1) * (sy[1] - sy[0] + 1);
   const int total = build_ranges(g, b, sz, 1, sy, 1, sx, 1, rstart, rpre);
   if (total == 0) {
-    if (threadIdx.x == 0) gst(b.epart)[t_id] = 0.0;
+    if (MODE != GM_COMP && threadIdx.x == 0) gst(b.epart)[t_id] = 0.0;
     return;
   }
 
@@ -1207,11 +1208,13 @@ __device__ __forceinline__ void stage_gather(const GridGeom& g, const EvalBuffer
       T wz = 0, dwz = 0;
       if (valid && iz < P) {
         wp[iz] = weight_reg<T, P>(g, crow, iz, f.fx);
-        wp[P + iz] = dweight_reg<T, P>(g, drow, iz, f.fx);
         wp[2 * P + iz] = weight_reg<T, P>(g, crow, iz, f.fy);
-        wp[3 * P + iz] = dweight_reg<T, P>(g, drow, iz, f.fy);
         wz = weight_reg<T, P>(g, crow, iz, f.fz);
-        dwz = dweight_reg<T, P>(g, drow, iz, f.fz);
+        if constexpr (GRAD) {
+          wp[P + iz] = dweight_reg<T, P>(g, drow, iz, f.fx);
+          wp[3 * P + iz] = dweight_reg<T, P>(g, drow, iz, f.fy);
+          dwz = dweight_reg<T, P>(g, drow, iz, f.fz);
+        }
       }
       wave_sync();
       T ph = 0, gx = 0, gy = 0, gz = 0;
@@ -1220,7 +1223,7 @@ __device__ __forceinline__ void stage_gather(const GridGeom& g, const EvalBuffer
 #pragma unroll
         for (int q = 0; q < P; ++q) {
           wx[q] = wp[q];
-          dwx[q] = wp[P + q];
+          dwx[q] = GRAD ? wp[P + q] : (T)0;
         }
         T s00 = 0, s01 = 0, s10 = 0;
         const T* plane = reg + (long long)(lz + iz) * RX * RY + (long long)ly * RX + lx;
@@ -1232,12 +1235,15 @@ __device__ __forceinline__ void stage_gather(const GridGeom& g, const EvalBuffer
           for (int ix = 0; ix < P; ++ix) {
             const T v = row[ix];
             r0 += wx[ix] * v;
-            r1 += dwx[ix] * v;
+            if constexpr (GRAD) r1 += dwx[ix] * v;
           }
-          const T wy = wp[2 * P + iy], dwy = wp[3 * P + iy];
+          const T wy = wp[2 * P + iy];
           s00 += wy * r0;
-          s01 += dwy * r0;
-          s10 += wy * r1;
+          if constexpr (GRAD) {
+            const T dwy = wp[3 * P + iy];
+            s01 += dwy * r0;
+            s10 += wy * r1;
+          }
         }
         ph = wz * s00;
         gx = wz * s10;
@@ -1245,42 +1251,52 @@ __device__ __forceinline__ void stage_gather(const GridGeom& g, const EvalBuffer
         gz = dwz * s00;
       }
       ph = group_sum<G2>(ph);
-      gx = group_sum<G2>(gx);
-      gy = group_sum<G2>(gy);
-      gz = group_sum<G2>(gz);
+      if constexpr (GRAD) {
+        gx = group_sum<G2>(gx);
+        gy = group_sum<G2>(gy);
+        gz = group_sum<G2>(gz);
+      }
       if (valid && iz == 0) {
         const int idx = ri[k];
-        const T pv = sc * ph + (T)(self_coef * (double)f.q);
-        if (phi) gst(phi)[idx] = pv;
-        if (force) {
+        if constexpr (MODE == GM_COMP) {
+          // force method 2: the grid holds the derivative along comp
           const T f0 = out_grad ? (T)1 : -f.q;
-          const auto fo = gst(force);
-          fo[3 * idx] = f0 * sc * gx;
-          fo[3 * idx + 1] = f0 * sc * gy;
-          fo[3 * idx + 2] = f0 * sc * gz;
+          gst(force)[3 * idx + comp] = f0 * sc * ph;
+        } else {
+          const T pv = sc * ph + (T)(self_coef * (double)f.q);
+          if (phi) gst(phi)[idx] = pv;
+          if (GRAD && force) {
+            const T f0 = out_grad ? (T)1 : -f.q;
+            const auto fo = gst(force);
+            fo[3 * idx] = f0 * sc * gx;
+            fo[3 * idx + 1] = f0 * sc * gy;
+            fo[3 * idx + 2] = f0 * sc * gz;
+          }
+          eacc += (double)f.q * (double)pv;
         }
-        eacc += (double)f.q * (double)pv;
       }
       wave_sync();
     }
   }
-  eacc = warp_sum(eacc);
-  if (lane == 0) ewave[wave] = eacc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int w = 0; w < nwaves; ++w) s += ewave[w];
-    gst(b.epart)[t_id] = s;
+  if constexpr (MODE != GM_COMP) {
+    eacc = warp_sum(eacc);
+    if (lane == 0) ewave[wave] = eacc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int w = 0; w < nwaves; ++w) s += ewave[w];
+      gst(b.epart)[t_id] = s;
+    }
   }
   __syncthreads();
 }
 
-template <typename T, int P>
+template <typename T, int P, int MODE>
 __global__ __launch_bounds__(kGatherBlock) void gather_kernel(GridGeom g, EvalBuffers b, T* __restrict__ phi,
                                                         T* __restrict__ force, int out_grad,
-                                                        double self_coef) {
+                                                        double self_coef, int comp) {
   extern __shared__ __align__(16) unsigned char smem[];
-  stage_gather<T, P>(g, b, phi, force, out_grad, self_coef, work_item(g.xcd), smem);
+  stage_gather<T, P, MODE>(g, b, phi, force, out_grad, self_coef, work_item(g.xcd), smem, comp);
 }
 
 template <typename T>
@@ -1295,26 +1311,37 @@ size_t gather_lds(const GridGeom& g) {
 
 template <typename T, int P>
 static void gather_launch(const GridGeom& g, const EvalBuffers& b, T* phi, T* force, int out_grad,
-                          double self_coef, hipStream_t st) {
+                          double self_coef, hipStream_t st, int mode, int comp) {
   const int ntiles = g.nt[0] * g.nt[1] * g.nt[2];
-  gather_kernel<T, P><<<dim3(ntiles), dim3(kGatherBlock), gather_lds<T>(g), st>>>(g, b, phi, force, out_grad,
-                                                                            self_coef);
+  const dim3 grid(ntiles), block(kGatherBlock);
+  const size_t lds = gather_lds<T>(g);
+  switch (mode) {
+    case GM_PHI:
+      gather_kernel<T, P, GM_PHI><<<grid, block, lds, st>>>(g, b, phi, force, out_grad, self_coef, comp);
+      break;
+    case GM_COMP:
+      gather_kernel<T, P, GM_COMP><<<grid, block, lds, st>>>(g, b, phi, force, out_grad, self_coef, comp);
+      break;
+    default:
+      gather_kernel<T, P, GM_ALL><<<grid, block, lds, st>>>(g, b, phi, force, out_grad, self_coef, comp);
+      break;
+  }
 }
 
 template <typename T>
 static hipError_t gather_dispatch(const GridGeom& g, const EvalBuffers& b, void* phi, void* force,
-                                  int out_grad, double self_coef, hipStream_t st) {
+                                  int out_grad, double self_coef, hipStream_t st, int mode, int comp) {
   T* p = reinterpret_cast<T*>(phi);
   T* f = reinterpret_cast<T*>(force);
   switch (g.P) {
-    case 2: gather_launch<T, 2>(g, b, p, f, out_grad, self_coef, st); break;
-    case 4: gather_launch<T, 4>(g, b, p, f, out_grad, self_coef, st); break;
-    case 6: gather_launch<T, 6>(g, b, p, f, out_grad, self_coef, st); break;
-    case 8: gather_launch<T, 8>(g, b, p, f, out_grad, self_coef, st); break;
-    case 10: gather_launch<T, 10>(g, b, p, f, out_grad, self_coef, st); break;
-    case 12: gather_launch<T, 12>(g, b, p, f, out_grad, self_coef, st); break;
-    case 14: gather_launch<T, 14>(g, b, p, f, out_grad, self_coef, st); break;
-    case 16: gather_launch<T, 16>(g, b, p, f, out_grad, self_coef, st); break;
+    case 2: gather_launch<T, 2>(g, b, p, f, out_grad, self_coef, st, mode, comp); break;
+    case 4: gather_launch<T, 4>(g, b, p, f, out_grad, self_coef, st, mode, comp); break;
+    case 6: gather_launch<T, 6>(g, b, p, f, out_grad, self_coef, st, mode, comp); break;
+    case 8: gather_launch<T, 8>(g, b, p, f, out_grad, self_coef, st, mode, comp); break;
+    case 10: gather_launch<T, 10>(g, b, p, f, out_grad, self_coef, st, mode, comp); break;
+    case 12: gather_launch<T, 12>(g, b, p, f, out_grad, self_coef, st, mode, comp); break;
+    case 14: gather_launch<T, 14>(g, b, p, f, out_grad, self_coef, st, mode, comp); break;
+    case 16: gather_launch<T, 16>(g, b, p, f, out_grad, self_coef, st, mode, comp); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1325,9 +1352,9 @@ size_t gather_lds_bytes(const GridGeom& g, bool f64) {
 }
 
 hipError_t launch_gather(const GridGeom& g, const EvalBuffers& b, bool f64, void* phi, void* force,
-                         int out_grad, double self_coef, hipStream_t st) {
-  return f64 ? gather_dispatch<double>(g, b, phi, force, out_grad, self_coef, st)
-             : gather_dispatch<float>(g, b, phi, force, out_grad, self_coef, st);
+                         int out_grad, double self_coef, hipStream_t st, int mode, int comp) {
+  return f64 ? gather_dispatch<double>(g, b, phi, force, out_grad, self_coef, st, mode, comp)
+             : gather_dispatch<float>(g, b, phi, force, out_grad, self_coef, st, mode, comp);
 }
 
 // E = 1/2 sum of the per-tile partials of q phi, in a fixed order (FP64).

@@ -182,6 +182,10 @@ struct se_plan {
   se::EvalBuffers buf{};
   std::vector<void*> allocs;
   std::vector<se::FftPass> passes;
+  // force method 2: for each direction d, the fused pass with i k_d and the
+  // two inverse passes, writing shadow copies of the spectrum buffers
+  std::vector<se::FftPass> ik_passes;
+  std::vector<std::pair<char*, size_t>> spec;   // spectrum buffers (workspace)
   int ntiles = 0;
   int nsbtot = 0;
   // tracing: HIP event pairs around launches of SE_PROFILE evaluations
@@ -228,11 +232,13 @@ struct se_plan {
     mv(b.sb_count); mv(b.sb_start); mv(b.sb_cursor); mv(b.p_key); mv(b.p_cell); mv(b.p_frac);
     mv(b.s_cell); mv(b.s_idx); mv(b.s_fq); mv(b.bsum); mv(b.stage); mv(b.qpart); mv(b.epart);
     mv(b.red); mv(b.grid); mv(b.vjp_phi); mv(b.vjp_grad);
-    for (se::FftPass& ps : passes)
-      for (se::FftClass& c : ps.cls) {
-        mv(c.in);
-        mv(c.out);
-      }
+    for (auto* list : {&passes, &ik_passes})
+      for (se::FftPass& ps : *list)
+        for (se::FftClass& c : ps.cls) {
+          mv(c.in);
+          mv(c.out);
+        }
+    for (auto& sb : spec) mv(sb.first);
     ws_base = base;
   }
 
@@ -290,6 +296,16 @@ struct se_plan {
       const double W = window_ft(k, info.h, p.P, p.window, p.shape);
       s[t] = std::exp(-k * k / (4.0 * p.xi * p.xi)) / (W * W) / n;
     }
+    return upload(s);
+  }
+
+  // Signed wavenumbers k = 2 pi m/(n h) of a length-n transform, m the signed
+  // frequency, with 0 at the Nyquist index of an even n (the derivative of a
+  // real grid stays real): the factor i k of force method 2.
+  const void* d_table(int n) {
+    std::vector<double> s(n);
+    for (int t = 0; t < n; ++t)
+      s[t] = (n % 2 == 0 && t == n / 2) ? 0.0 : 2.0 * kPi * signed_freq(t, n) / (n * info.h);
     return upload(s);
   }
 
@@ -532,6 +548,7 @@ se_status se_plan_destroy(se_plan* plan) {
 }
 
 static se_status build_passes(se_plan* pl, hipStream_t st);
+static void build_ik_passes(se_plan* pl);
 static se_status precompute_0p(se_plan* pl, hipStream_t st, const void** table);
 
 // Largest number of tile-box images (periodic copies included) that meet one
@@ -647,7 +664,7 @@ static se_status plan_create(const se_params* params, long n_max, void* hip_stre
   pl->n_max = n_max;
   (void)hipGetDevice(&pl->device);
   pl->lds_limit = lds_soft;
-  if (p.spread_mode < 0 || p.spread_mode > 3) {
+  if (p.spread_mode < 0 || p.spread_mode > 3 || p.force_method < 0 || p.force_method > 2) {
     delete pl;
     return SE_ERR_PARAM;
   }
@@ -855,6 +872,7 @@ static se_status plan_create(const se_params* params, long n_max, void* hip_stre
     }
     rc = build_passes(pl, st);
     if (rc != SE_OK) break;
+    if (p.force_method == 2) build_ik_passes(pl);
   } while (false);
   // table uploads are synchronous; the free-space precompute ran on st
   if (rc == SE_OK && hipStreamSynchronize(st) != hipSuccess) rc = SE_ERR_DEVICE;
@@ -880,10 +898,23 @@ static se_status build_passes(se_plan* pl, hipStream_t st) {
   const size_t ce = pl->f64 ? 16 : 8;
   std::vector<std::vector<int>> rg;
   auto fail = [&]() { return SE_ERR_NOMEM; };
+  // force method 2: signed-wavenumber tables and directions of a fused class
+  const bool m2 = p.force_method == 2;
+  bool dt_ok = true;
+  auto set_d = [&](se::FftClass& c, int nA, int nB, int nC, int dirA, int dirB) {
+    if (!m2) return;
+    c.dA = pl->d_table(nA);
+    c.dB = pl->d_table(nB);
+    c.dC = pl->d_table(nC);
+    c.dirA = dirA;
+    c.dirB = dirB;
+    dt_ok = dt_ok && c.dA && c.dB && c.dC;
+  };
 
   if (D == 3 || D == 2) {
     const int nx = M, Kx = M / 2 + 1;
     void* cb = pl->walloc(ce * (size_t)Kx * Gy * Gz);
+    pl->spec = {{(char*)cb, ce * (size_t)Kx * Gy * Gz}};
     const void* sepM = pl->sep_table(M);
     const void* k2M = pl->k2_table(M);
     if (!sepM || !k2M) return fail();
@@ -905,6 +936,7 @@ static se_status build_passes(se_plan* pl, hipStream_t st) {
       c.gmode = se::G_INVSQ;
       c.sA = c.sB = c.sC = sepM;
       c.kA = c.kB = c.kC = k2M;
+      set_d(c, M, M, M, 0, 1);
       p3.cls[0] = c;
       rg = {{0, 0, Kx, 0, Gy}};
       if (!finish_pass(pl, p3, se::K_FUSED, 1, rg)) return fail();
@@ -937,6 +969,9 @@ static se_status build_passes(se_plan* pl, hipStream_t st) {
       cJ.kA = cJ.kB = k2M;
       cJ.sC = sJt;
       cJ.kC = kJt;
+      set_d(c0, M, M, n0, 0, 1);
+      set_d(cI, M, M, nI, 0, 1);
+      set_d(cJ, M, M, Mt, 0, 1);
       p3.cls[0] = c0;
       p3.cls[1] = cI;
       p3.cls[2] = cJ;
@@ -964,13 +999,14 @@ static se_status build_passes(se_plan* pl, hipStream_t st) {
     rg = {{0, 0, Gy, 0, Gz}};
     if (!finish_pass(pl, p5, se::K_C2R, 1, rg)) return fail();
     pl->passes = {p1, p2, p3, p4, p5};
-    return SE_OK;
+    return dt_ok ? SE_OK : fail();
   }
 
   if (D == 0) {
     const int n = 2 * Mt, Kx = Mt + 1;
     void* cb = pl->walloc(ce * (size_t)Kx * Mt * Mt);
     void* cb2 = pl->walloc(ce * (size_t)Kx * n * Mt);
+    pl->spec = {{(char*)cb, ce * (size_t)Kx * Mt * Mt}, {(char*)cb2, ce * (size_t)Kx * n * Mt}};
     const void* sep = pl->sep_table(n);
     if (!sep) return fail();
     const void* table = nullptr;
@@ -993,6 +1029,7 @@ static se_status build_passes(se_plan* pl, hipStream_t st) {
     c.gd0 = c.gd1 = Mt + 1;
     c.fold0 = 0;
     c.fold1 = c.fold2 = n;
+    set_d(c, n, n, n, 0, 1);
     p3.cls[0] = c;
     rg = {{0, 0, Kx, 0, n}};
     if (!finish_pass(pl, p3, se::K_FUSED, 1, rg)) return fail();
@@ -1005,7 +1042,7 @@ static se_status build_passes(se_plan* pl, hipStream_t st) {
     rg = {{0, 0, Mt, 0, Mt}};
     if (!finish_pass(pl, p5, se::K_C2R, 1, rg)) return fail();
     pl->passes = {p1, p2, p3, p4, p5};
-    return SE_OK;
+    return dt_ok ? SE_OK : fail();
   }
 
   // D == 1: periodic x, free y and z.  Classes over k_x: zero mode (n0),
@@ -1016,6 +1053,8 @@ static se_status build_passes(se_plan* pl, hipStream_t st) {
   void* cb = pl->walloc(ce * (size_t)Kx * Mt * Mt);
   void* b0 = pl->walloc(ce * (size_t)n0 * Mt);
   void* bI = pl->walloc(ce * (size_t)std::max(1, nl) * nI * Mt);
+  pl->spec = {{(char*)cb, ce * (size_t)Kx * Mt * Mt}, {(char*)b0, ce * (size_t)n0 * Mt},
+              {(char*)bI, ce * (size_t)std::max(1, nl) * nI * Mt}};
   const void* sepM = pl->sep_table(M);
   const void* k2M = pl->k2_table(M);
   const void* s0t = pl->sep_table(n0);
@@ -1080,6 +1119,9 @@ static se_status build_passes(se_plan* pl, hipStream_t st) {
     cJ.kB = kJt;
     cJ.sC = sJt;
     cJ.kC = kJt;
+    set_d(c0, n0, M, n0, 1, 0);   // b0: y on the zero mode's grid, b1: x (k_x = 0)
+    set_d(cI, M, nI, nI, 0, 1);
+    set_d(cJ, M, Mt, Mt, 0, 1);
     p3.cls[0] = c0;
     p3.cls[1] = cI;
     p3.cls[2] = cJ;
@@ -1103,7 +1145,39 @@ static se_status build_passes(se_plan* pl, hipStream_t st) {
   rg = {{0, 0, Gy, 0, Gz}};
   if (!finish_pass(pl, p5, se::K_C2R, 1, rg)) return fail();
   pl->passes = {p1, p2, p3, p4, p5};
-  return SE_OK;
+  return dt_ok ? SE_OK : fail();
+}
+
+// Force method 2 (Section 7.2): per direction d, the fused pass with the
+// factor i k_d reads the forward spectrum and writes shadow copies of the
+// spectrum buffers, the inverse passes run on the shadows and the last one
+// writes the grid, so the forward spectrum serves all three directions.
+static void build_ik_passes(se_plan* pl) {
+  std::vector<std::pair<char*, char*>> sh;   // (buffer, shadow)
+  for (const auto& sb : pl->spec) sh.emplace_back(sb.first, (char*)pl->walloc(sb.second));
+  auto map = [&](const void* ptr) -> void* {
+    for (size_t k = 0; k < sh.size(); ++k) {
+      const char* b = sh[k].first;
+      if ((const char*)ptr >= b && (const char*)ptr < b + pl->spec[k].second)
+        return sh[k].second + ((const char*)ptr - b);
+    }
+    return const_cast<void*>(ptr);
+  };
+  pl->ik_passes.clear();
+  for (int d = 0; d < 3; ++d) {
+    se::FftPass f = pl->passes[2], i4 = pl->passes[3], i5 = pl->passes[4];
+    f.kind = se::K_FUSED_D;
+    f.deriv = d;
+    for (int c = 0; c < se::kMaxClasses; ++c) {
+      f.cls[c].out = map(f.cls[c].out);
+      i4.cls[c].in = map(i4.cls[c].in);
+      i4.cls[c].out = map(i4.cls[c].out);
+      i5.cls[c].in = map(i5.cls[c].in);
+    }
+    pl->ik_passes.push_back(f);
+    pl->ik_passes.push_back(i4);
+    pl->ik_passes.push_back(i5);
+  }
 }
 
 // Algorithm 3 in FP64 on the GPU: sample G_hat^{0P} on the (s0 Mt)^3 grid,
@@ -1181,7 +1255,7 @@ constexpr int kEventPool = 8192;
 }  // namespace
 
 static se_status eval_bound(se_plan* plan, long N, const void* xyz, const void* q, void* phi, void* force,
-                            double* energy, unsigned flags, void* hip_stream);
+                            double* energy, unsigned flags, void* hip_stream, int method);
 
 se_status se_plan_workspace_size(const se_plan* plan, size_t* bytes) {
   if (!plan || !bytes) return SE_ERR_ARG;
@@ -1209,12 +1283,13 @@ se_status se_eval(se_plan* plan, long N, const void* xyz, const void* q, void* p
   if (flags & ~(SE_IN_F32 | SE_ADD_SELF | SE_SYNC_CHECK | SE_OUT_GRAD | SE_ALLOW_NONNEUTRAL | SE_PROFILE))
     return SE_ERR_ARG;
   if (!plan->ws_bound) return SE_ERR_WORKSPACE;
-  return eval_bound(plan, N, xyz, q, phi, force, energy, flags, hip_stream);
+  return eval_bound(plan, N, xyz, q, phi, force, energy, flags, hip_stream, plan->p.force_method);
 }
 
-// se_eval on a plan whose work pointers point at a workspace.
+// se_eval on a plan whose work pointers point at a workspace; forces by
+// method 'method' (2: i k in the scaling step, else the window gradient).
 static se_status eval_bound(se_plan* plan, long N, const void* xyz, const void* q, void* phi, void* force,
-                            double* energy, unsigned flags, void* hip_stream) {
+                            double* energy, unsigned flags, void* hip_stream, int method) {
   hipStream_t st = (hipStream_t)hip_stream;
   const se::GridGeom& g = plan->geom;
   se::EvalBuffers& b = plan->buf;
@@ -1272,19 +1347,55 @@ static se_status eval_bound(se_plan* plan, long N, const void* xyz, const void* 
     const double R3 = (double)(g.T[0] + P - 1) * (g.T[1] + P - 1) * (g.T[2] + P - 1);
     end(4, plan->ntiles * R3 * re + G * re, plan->ntiles * R3);
   }
-  for (size_t i = 0; i < plan->passes.size(); ++i) {
-    const se::FftPass& ps = plan->passes[i];
+  const int np = (int)plan->passes.size();
+  const int s_gather = 5 + np;
+  auto run_pass = [&](const se::FftPass& ps, int site) -> bool {
     begin();
-    if (se::launch_fft(ps, f64, st) != hipSuccess) return SE_ERR_DEVICE;
-    end(5 + (int)i, ps.alg_bytes, ps.alg_flops);
-  }
-  const int s_gather = 5 + (int)plan->passes.size();
-  if (phi || force || energy) {
-    begin();
-    if (se::launch_gather(g, b, f64, phi, force, (flags & SE_OUT_GRAD) ? 1 : 0, self_coef, st) != hipSuccess)
-      return SE_ERR_DEVICE;
-    end(s_gather, N * 8.0 * re + G * re,
-        N * 2.0 * (6.0 * P * nu + 3.0 * P * P + (double)P * P * (2 * P + 4)));
+    if (se::launch_fft(ps, f64, st) != hipSuccess) return false;
+    end(site, ps.alg_bytes, ps.alg_flops);
+    return true;
+  };
+  const int og = (flags & SE_OUT_GRAD) ? 1 : 0;
+  // a gathering of values only (method 2 and the potential without forces)
+  const double val_bytes = N * 5.0 * re + G * re, val_flops = N * 2.0 * (3.0 * P * nu + P * P + (double)P * P * P);
+  if (method == 2 && force && plan->ik_passes.size() == 9) {
+    // force method 2 (Section 7.2): forward transforms once, then per
+    // direction d the scaling with i k_d, the inverse transforms and a
+    // gathering with the window itself into force column d
+    for (int i = 0; i < 2; ++i)
+      if (!run_pass(plan->passes[i], 5 + i)) return SE_ERR_DEVICE;
+    for (int d = 0; d < 3; ++d) {
+      for (int k = 0; k < 3; ++k)
+        if (!run_pass(plan->ik_passes[3 * d + k], k == 0 ? s_gather + 2 : s_gather + 3)) return SE_ERR_DEVICE;
+      begin();
+      if (se::launch_gather(g, b, f64, nullptr, force, og, 0.0, st, se::GM_COMP, d) != hipSuccess)
+        return SE_ERR_DEVICE;
+      end(s_gather + 4, val_bytes, val_flops);
+    }
+    // the potential (and the energy) from the plain scaling, last: the fused
+    // pass transforms the forward spectrum in place
+    if (phi || energy) {
+      for (int i = 2; i < np; ++i)
+        if (!run_pass(plan->passes[i], 5 + i)) return SE_ERR_DEVICE;
+      begin();
+      if (se::launch_gather(g, b, f64, phi, nullptr, og, self_coef, st, se::GM_PHI) != hipSuccess)
+        return SE_ERR_DEVICE;
+      end(s_gather, val_bytes, val_flops);
+    }
+  } else {
+    for (int i = 0; i < np; ++i)
+      if (!run_pass(plan->passes[i], 5 + i)) return SE_ERR_DEVICE;
+    if (phi || force || energy) {
+      begin();
+      const bool grad = force != nullptr;
+      if (se::launch_gather(g, b, f64, phi, force, og, self_coef, st, grad ? se::GM_ALL : se::GM_PHI) !=
+          hipSuccess)
+        return SE_ERR_DEVICE;
+      if (grad)
+        end(s_gather, N * 8.0 * re + G * re, N * 2.0 * (6.0 * P * nu + 3.0 * P * P + (double)P * P * (2 * P + 4)));
+      else
+        end(s_gather, val_bytes, val_flops);
+    }
   }
   if (energy) {
     begin();
@@ -1299,7 +1410,7 @@ se_status se_plan_profile(se_plan* plan, void* hip_stream, se_stage_record* out,
                           int reset) {
   if (!plan || !n || (cap > 0 && !out)) return SE_ERR_ARG;
   if (hipStreamSynchronize((hipStream_t)hip_stream) != hipSuccess) return SE_ERR_DEVICE;
-  const int nsites = 7 + (int)plan->passes.size();
+  const int nsites = 10 + (int)plan->passes.size();
   std::vector<se_stage_record> agg(nsites);
   std::vector<double> bsum(nsites, 0.0), fsum(nsites, 0.0);
   for (int s = 0; s < nsites; ++s) {
@@ -1316,7 +1427,10 @@ se_status se_plan_profile(se_plan* plan, void* hip_stream, se_stage_record* out,
       std::snprintf(buf, sizeof(buf), "%s_%d", kFftNames[plan->passes[s - 5].kind], s - 4);
       nm = buf;
     } else if (s == 5 + (int)plan->passes.size()) nm = "gather";
-    else nm = "energy";
+    else if (s == 6 + (int)plan->passes.size()) nm = "energy";
+    else if (s == 7 + (int)plan->passes.size()) nm = "ik_fused";
+    else if (s == 8 + (int)plan->passes.size()) nm = "ik_inverse";
+    else nm = "ik_gather";
     std::snprintf(r.name, sizeof(r.name), "%s", nm);
   }
   for (const auto& rec : plan->prof) {
@@ -1395,7 +1509,7 @@ se_status se_eval_static(se_plan* plan, long N, const void* xyz, const void* q, 
   const uintptr_t prev = plan->ws_base;
   const bool prev_bound = plan->ws_bound;
   plan->rebase((uintptr_t)base);
-  const se_status rc = eval_bound(plan, N, xyz, q, phi, force, energy, flags, hip_stream);
+  const se_status rc = eval_bound(plan, N, xyz, q, phi, force, energy, flags, hip_stream, plan->p.force_method);
   plan->rebase(prev);
   plan->ws_bound = prev_bound;
   return rc;
@@ -1424,8 +1538,10 @@ se_status se_eval_vjp(se_plan* plan, long N, const void* xyz, const void* q, con
   hipStream_t st = (hipStream_t)hip_stream;
   // Algorithm 4 with the cotangent as charges: A g and grad (A g)
   const unsigned ef = (flags & (SE_IN_F32 | SE_ADD_SELF)) | SE_OUT_GRAD | SE_ALLOW_NONNEUTRAL;
+  // method 1: the exact gradient of the discrete operator, which the
+  // symmetry argument above needs
   se_status rc = eval_bound(plan, N, xyz, g, plan->buf.vjp_phi, grad_x ? plan->buf.vjp_grad : nullptr, nullptr,
-                            ef, hip_stream);
+                            ef, hip_stream, 1);
   if (rc != SE_OK) return rc;
   if (se::launch_potential_vjp(N, (flags & SE_IN_F32) != 0, plan->f64, q, g, grad_phi, plan->buf.vjp_phi,
                                plan->buf.vjp_grad, grad_x, grad_q, st) != hipSuccess)
@@ -1508,7 +1624,8 @@ se_status se_batch_plan_create(const se_params* params, const long* N, int n_sys
   *out = nullptr;
   for (int s = 0; s < n_sys; ++s) {
     if (N[s] < 0) return SE_ERR_ARG;
-    if (params[s].P != params[0].P || params[s].window != params[0].window || params[s].prec != params[0].prec)
+    if (params[s].P != params[0].P || params[s].window != params[0].window || params[s].prec != params[0].prec ||
+        params[s].force_method == 2)
       return SE_ERR_UNSUPPORTED;
   }
   const int P = params[0].P;

@@ -298,3 +298,59 @@ def test_gradient_is_energy_derivative(D):
             em = se.energy(q, se.spectral_ewald(xm, q, p, grad=False, GR=GR)[0])
             fd = (ep - em) / (2 * eps)
             assert abs(fd - q[m] * g[m, d]) < 1e-6 * max(1.0, abs(fd))
+
+
+# --- force method 2 (Section 7.2): i k in the scaling step -----------------
+
+@pytest.mark.parametrize("D", [3, 2, 1, 0])
+def test_method2_gradient_against_direct(D):
+    """Force method 2 (derivative taken in Fourier space, window itself in
+    the gathering) at high-accuracy parameters equals the analytic gradient
+    of the direct k-space sum."""
+    x, q, Q = _sys(D, N=120)
+    L, xi, M = 1.0, 8.0, 40
+    B = se.B_scale(Q, xi, L)
+    p = se.with_aft_estimates(D, L, xi, M, 16, Q, 1e-16 * B, window="pkb")
+    phi, g2 = se.spectral_ewald(x, q, p, force_method=2)
+    ref, gref = direct.kspace(D, L, xi, x, q)
+    assert rel(phi, ref) < 5e-12
+    assert rel(g2, gref) < 5e-10
+
+
+def test_method2_error_curve_follows_the_potential():
+    """Fig. force (3P, L = 1, xi = 8, M = 64, PKB): method 2 has the error
+    curve of the potential, method 1 is offset and needs P + 2 for the same
+    error (Section 7.2)."""
+    x, q = wl.system(300, 1.0, 77, "uniform")
+    ref, gref = direct.kspace(3, 1.0, 8.0, x, q)
+    for P in (6, 8):
+        p = se.Params(D=3, L=1.0, xi=8.0, M=64, P=P, window="pkb")
+        phi, g1 = se.spectral_ewald(x, q, p, force_method=1)
+        _, g2 = se.spectral_ewald(x, q, p, force_method=2)
+        p2 = se.Params(D=3, L=1.0, xi=8.0, M=64, P=P + 2, window="pkb")
+        _, g1p = se.spectral_ewald(x, q, p2, force_method=1)
+        e_phi, e1, e2, e1p = rel(phi, ref), rel(g1, gref), rel(g2, gref), rel(g1p, gref)
+        assert e2 < 3 * e_phi and e_phi < 3 * e2        # same curve as the potential
+        assert e1 > 3 * e2                              # method 1 offset at equal P
+        assert e1p < 3 * e2                             # ... and recovered at P + 2
+
+
+def test_method2_derivative_of_a_single_mode():
+    """On a 3P grid holding one real Fourier mode cos(k.x), the i k step
+    returns -k_d sin(k.x) exactly (up to rounding): pins the sign and the
+    direction of each component independently of the gathering."""
+    p = se.Params(D=3, L=1.0, xi=1e6, M=16, P=4, window="gaussian")
+    n = np.array([2, -3, 5])
+    idx = np.arange(16) * p.h
+    X, Y, Z = np.meshgrid(idx, idx, idx, indexing="ij")
+    kvec = 2 * np.pi * n / p.L
+    arg = kvec[0] * X + kvec[1] * Y + kvec[2] * Z
+    # the scaling step multiplies by S(k) G(k); divide it out through the
+    # plain result so only the derivative factor is left
+    H = np.cos(arg)
+    base = se.scaled_convolution(H, p)
+    amp = base.ravel() @ np.cos(arg).ravel() / (np.cos(arg).ravel() @ np.cos(arg).ravel())
+    for d in range(3):
+        Hd = se.scaled_convolution(H, p, deriv=d)
+        want = -amp * kvec[d] * np.sin(arg)
+        assert np.max(np.abs(Hd - want)) < 1e-12 * np.max(np.abs(want))

@@ -165,6 +165,20 @@ se_status se_params_default(int D, double L, double xi, int M, int P, se_window 
 se_status se_params_for_tolerance(int D, double L, double xi, double Q, double tol_rel, int P,
                                   se_window window, se_precision prec, se_params* out);
 
+/* The whole parameter selection of Section 6 for a relative tolerance tol_rel
+ * (absolute rms tolerance eps = tol_rel * B) at a given xi: the grid
+ * M = 2 k_inf of Eq. (KP_kinf) (the inverse of the k-space estimate, by the
+ * Lambert W function), rounded up to an even integer with prime factors 2,
+ * 3, 5, 7 only; the window support P from the approximation estimates
+ * eps = 2 B e^{-(pi/2) P c} (Gaussian) or 10 B e^{-2.5 P} (PKB), rounded up
+ * to an even integer; when P > f_W(M/(xi L)) (error pollution, Eq.
+ * error_pollution) M is increased by 5 % and P by 4; then the rules of
+ * se_params_default (shape, nu, lambda, s0, s, n_l).
+ * Errors: SE_ERR_ARG for out == NULL; SE_ERR_PARAM for invalid inputs or a
+ * result beyond the supported sizes (P > 16, M >= 4096). */
+se_status se_params_recipe(int D, double L, double xi, double Q, double tol_rel, se_window window,
+                           se_precision prec, se_params* out);
+
 /* The error scale of Section 5.2, B = sqrt(Q) f_c(xi L) / L with f_c of
  * Eq. (fc-expression) and Q = sum of q^2: relative tolerances of the other
  * calls are tolerances on rms errors divided by B.  *B receives it (host).

@@ -171,6 +171,42 @@ class Params:
         return tuple(self.M if d < self.D else self.Mt for d in range(3))
 
 
+def kinf_for_tolerance(Q: float, xi: float, L: float, eps: float) -> float:
+    """Largest wavenumber index k_inf of Eq. (KP_kinf) for an absolute rms
+    tolerance eps: the inverse of Eq. (KP_fourier_space), through the
+    principal branch of the Lambert W function."""
+    arg = (4.0 / 3.0) * (Q / (math.pi * xi * L ** 3 * eps ** 2)) ** (2.0 / 3.0)
+    return math.sqrt(3.0) * xi * L / (2.0 * math.pi) * math.sqrt(float(special.lambertw(arg).real))
+
+
+def support_for_tolerance(window: str, B: float, eps: float) -> int:
+    """Window support P from the approximation estimates of Section 5.2,
+    eps = 2 B e^{-(pi/2) P c} (Gaussian, c^2 = 0.91) or 10 B e^{-2.5 P} (KB /
+    PKB), rounded up to an even integer (at least 2)."""
+    if window == "gaussian":
+        P = math.log(2.0 * B / eps) / ((math.pi / 2.0) * math.sqrt(0.91))
+    else:
+        P = math.log(10.0 * B / eps) / 2.5
+    return max(2, 2 * math.ceil(P / 2.0 - 1e-12))
+
+
+def recipe(D, L, xi, Q, eps, window="pkb") -> Params:
+    """The parameter selection of Section 6 for an absolute rms tolerance
+    eps at a given xi: M = 2 k_inf (Eq. KP_kinf), rounded up to an even
+    7-smooth integer; P from the approximation estimate; when P > f_W(M/(xi
+    L)) (error pollution, Eq. error_pollution) M grows by 5 % and P by 4; the
+    shape, nu, lambda, s0 rules; s and n_l from Eqs. (estimate-s),
+    (estimate-nl)."""
+    B = B_scale(Q, xi, L)
+    M = smooth_even_up(math.ceil(2.0 * kinf_for_tolerance(Q, xi, L, eps) - 1e-9))
+    P = support_for_tolerance(window, B, eps)
+    if P > pollution_bound(window, M / (xi * L)):
+        M = smooth_even_up(math.ceil(1.05 * M - 1e-9))
+        P += 4
+    M = max(M, smooth_even_up(P))
+    return with_aft_estimates(D, L, xi, M, P, Q, eps, window=window)
+
+
 def with_aft_estimates(D, L, xi, M, P, Q, eps, window="pkb", **kw) -> Params:
     """Params with s and n_l from Eqs. (estimate-s), (estimate-nl).
     s is kept >= 1 and n_l in [0, M/2]."""

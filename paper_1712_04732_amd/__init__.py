@@ -7,7 +7,7 @@ energy (api), and the build script (build_lib).
 """
 from . import _lib
 from .api import (EwaldEnergy, RealSpace, SEEnergy, SEPotential, SpectralEwald, SpectralEwaldBatch,
-                  params_for_tolerance)
+                  params_for_tolerance, params_recipe)
 
 __all__ = ["EwaldEnergy", "RealSpace", "SpectralEwald", "SpectralEwaldBatch", "SEEnergy", "SEPotential",
-           "params_for_tolerance", "_lib"]
+           "params_for_tolerance", "params_recipe", "_lib"]

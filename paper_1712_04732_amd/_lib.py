@@ -169,6 +169,8 @@ _SIGS = {
                                       ctypes.POINTER(ctypes.c_double)]),
     "se_rs_cutoff_for_tolerance": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                                   ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
+    "se_params_recipe": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.POINTER(se_params)]),
     "se_plan_workspace_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
     "se_plan_set_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
     "se_batch_plan_workspace_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
@@ -320,6 +322,14 @@ def se_params_for_tolerance(D, L, xi, Q, tol_rel, P, window, prec):
     out = se_params()
     _check(load().se_params_for_tolerance(int(D), float(L), float(xi), float(Q), float(tol_rel), int(P),
                                           int(window), int(prec), ctypes.byref(out)), "se_params_for_tolerance")
+    return out
+
+
+def se_params_recipe(D, L, xi, Q, tol_rel, window, prec):
+    """Section 6: M and P from the tolerance (with the error-pollution remedy)."""
+    out = se_params()
+    _check(load().se_params_recipe(int(D), float(L), float(xi), float(Q), float(tol_rel), int(window), int(prec),
+                                   ctypes.byref(out)), "se_params_recipe")
     return out
 
 

@@ -204,8 +204,15 @@ def _params(D, L_box, xi, M, P, window="pkb", prec="f64", Q=None, tol=None, s=No
 
 
 def params_for_tolerance(D, L_box, xi, Q, tol_rel, P=8, window="pkb", prec="f32"):
-    """Section 6 recipe: grid size and AFT parameters for a relative tolerance."""
+    """Grid size and AFT parameters for a relative tolerance at a given
+    window support P (Section 6 rules, P chosen by the caller)."""
     return L.se_params_for_tolerance(D, L_box, xi, Q, tol_rel, P, _WINDOWS[window], _PRECS[prec])
+
+
+def params_recipe(D, L_box, xi, Q, tol_rel, window="pkb", prec="f64"):
+    """The whole Section 6 recipe: M and P from the tolerance, with the
+    error-pollution remedy (M + 5 %, P + 4)."""
+    return L.se_params_recipe(D, L_box, xi, Q, tol_rel, _WINDOWS[window], _PRECS[prec])
 
 
 class SpectralEwaldBatch:

@@ -516,6 +516,33 @@ se_status se_rs_cutoff_for_tolerance(double L, double xi, double Q, double tol_r
   return SE_OK;
 }
 
+se_status se_params_recipe(int D, double L, double xi, double Q, double tol_rel, se_window window,
+                           se_precision prec, se_params* out) {
+  if (!out) return SE_ERR_ARG;
+  if (D < 0 || D > 3 || !(L > 0) || !(xi > 0) || !(Q > 0) || !(tol_rel > 0) || !std::isfinite(L) ||
+      !std::isfinite(xi) || !std::isfinite(Q) || (window != SE_WIN_GAUSSIAN && window != SE_WIN_PKB))
+    return SE_ERR_PARAM;
+  const double B = std::sqrt(Q) * fc(xi * L) / L;
+  const double eps = tol_rel * B;
+  // Eq. (KP_kinf): k_inf = sqrt(3) xi L / (2 pi) sqrt(W(4/3 [Q / (pi xi L^3 eps^2)]^(2/3)))
+  const double arg = 4.0 / 3.0 * std::pow(Q / (kPi * xi * L * L * L * eps * eps), 2.0 / 3.0);
+  const double kinf = std::sqrt(3.0) * xi * L / (2.0 * kPi) * std::sqrt(lambert_w0(arg));
+  if (!(2.0 * kinf < 4096.0)) return SE_ERR_PARAM;
+  int M = smooth_even_up((long)std::ceil(2.0 * kinf - 1e-9));
+  // window support from the approximation estimates (Section 5.2), rounded up to even
+  const double Pr = window == SE_WIN_GAUSSIAN ? std::log(2.0 * B / eps) / ((kPi / 2.0) * std::sqrt(0.91))
+                                              : std::log(10.0 * B / eps) / 2.5;
+  int P = std::max(2, 2 * (int)std::ceil(Pr / 2.0 - 1e-12));
+  // error pollution (Eq. error_pollution): 5 % more grid, P + 4
+  if (P > pollution_fw(window, M / (xi * L))) {
+    M = smooth_even_up((long)std::ceil(1.05 * M - 1e-9));
+    P += 4;
+  }
+  if (P > se::kMaxP || M >= 4096) return SE_ERR_PARAM;
+  M = std::max(M, smooth_even_up(P));
+  return se_params_default(D, L, xi, M, P, window, Q, eps, prec, out);
+}
+
 se_status se_params_for_tolerance(int D, double L, double xi, double Q, double tol_rel, int P, se_window window,
                                   se_precision prec, se_params* out) {
   if (!out) return SE_ERR_ARG;

@@ -220,3 +220,35 @@ def test_workspace_and_adjoint_entries_reject_bad_arguments():
     assert lib.se_energy_vjp(4, L.SE_F64, dummy, None, dummy, dummy, dummy, None, 0, None) == L.SE_ERR_ARG
     assert lib.se_energy_vjp(4, L.SE_F64, dummy, dummy, None, None, None, dummy, 0, None) == L.SE_ERR_ARG
     assert lib.se_energy_vjp(0, L.SE_F64, None, None, None, None, None, None, 0, None) == L.SE_OK
+
+
+@pytest.mark.parametrize("D", [3, 2, 1, 0])
+@pytest.mark.parametrize("window", ["pkb", "gaussian"])
+def test_recipe_matches_oracle(D, window):
+    """se_params_recipe (Section 6 with the error-pollution remedy) against
+    the oracle's independent recipe over a grid of systems and tolerances."""
+    w = L.SE_WIN_PKB if window == "pkb" else L.SE_WIN_GAUSSIAN
+    lib = L.load()
+    for Q, xi, Lb in ((3.32e4, 8.0, 1.0), (334.0, 6.0, 5.0), (31.4, 6.5, 1.0), (3.32e4, 3.0, 10.0)):
+        for tol in (1e-2, 1e-4, 1e-6, 1e-8, 1e-10):
+            B = se.B_scale(Q, xi, Lb)
+            ref = se.recipe(D, Lb, xi, Q, tol * B, window)
+            out = L.se_params()
+            st = lib.se_params_recipe(D, Lb, xi, Q, tol, w, L.SE_F64, ctypes.byref(out))
+            if ref.P > 16:
+                assert st == L.SE_ERR_PARAM
+                continue
+            assert st == L.SE_OK
+            assert (out.M, out.P) == (ref.M, ref.P), (Q, xi, Lb, tol)
+            assert out.nu == (ref.nu if window == "pkb" else 0)
+            if D in (1, 2):
+                assert out.n_l == ref.n_l and abs(out.s - ref.s) < 1e-12
+
+
+def test_recipe_rejects_bad_arguments():
+    lib = L.load()
+    out = L.se_params()
+    assert lib.se_params_recipe(3, 1.0, 8.0, 10.0, 1e-6, L.SE_WIN_PKB, L.SE_F64, None) == L.SE_ERR_ARG
+    for args in ((4, 1.0, 8.0, 10.0, 1e-6), (3, -1.0, 8.0, 10.0, 1e-6), (3, 1.0, 0.0, 10.0, 1e-6),
+                 (3, 1.0, 8.0, 0.0, 1e-6), (3, 1.0, 8.0, 10.0, 0.0), (3, 1.0, 8.0, 10.0, 1e-40)):
+        assert lib.se_params_recipe(*args, L.SE_WIN_PKB, L.SE_F64, ctypes.byref(out)) == L.SE_ERR_PARAM

@@ -354,3 +354,64 @@ def test_method2_derivative_of_a_single_mode():
         Hd = se.scaled_convolution(H, p, deriv=d)
         want = -amp * kvec[d] * np.sin(arg)
         assert np.max(np.abs(Hd - want)) < 1e-12 * np.max(np.abs(want))
+
+
+# --- the parameter recipe of Section 6 -------------------------------------
+
+@pytest.mark.parametrize("Q,xi,L,eps", [(3.32e4, 8.0, 1.0, 1e-10), (334.0, 6.0, 5.0, 1e-6), (31.4, 6.5, 1.0, 1e-12),
+                                        (1e6, 56.4, 1.0, 3e-4)])
+def test_kinf_inverts_the_kspace_estimate(Q, xi, L, eps):
+    """Eq. (KP_kinf) is the exact inverse of Eq. (KP_fourier_space): at
+    M = 2 k_inf the estimate equals the tolerance, and it lies above it at a
+    smaller grid."""
+    k = se.kinf_for_tolerance(Q, xi, L, eps)
+    assert abs(se.kp_kspace_error(Q, xi, L, 2 * k) / eps - 1) < 1e-10
+    assert se.kp_kspace_error(Q, xi, L, 2 * k * 0.98) > eps
+
+
+@pytest.mark.parametrize("window", ["pkb", "gaussian"])
+def test_support_rule_meets_the_estimate(window):
+    """P is the smallest even support whose approximation estimate
+    (Section 5.2) meets the tolerance."""
+    est = (lambda P, B: 10 * B * math.exp(-2.5 * P)) if window == "pkb" else (
+        lambda P, B: 2 * B * math.exp(-(math.pi / 2) * P * math.sqrt(0.91)))
+    for B in (0.3, 17.0, 450.0):
+        for rel_tol in (1e-3, 1e-6, 1e-9, 1e-12):
+            P = se.support_for_tolerance(window, B, rel_tol * B)
+            assert P % 2 == 0 and est(P, B) <= rel_tol * B * (1 + 1e-12)
+            assert P == 2 or est(P - 2, B) > rel_tol * B
+
+
+def test_recipe_pollution_remedy():
+    """When P > f_W(M/(xi L)) the recipe adds 5 % to M and 4 to P (Section 5.2
+    and Section 6); otherwise M = 2 k_inf and P from the estimate."""
+    Q, xi, L = 3.32e4, 8.0, 1.0
+    B = se.B_scale(Q, xi, L)
+    eps = 1e-10 * B
+    M0 = se.smooth_even_up(math.ceil(2 * se.kinf_for_tolerance(Q, xi, L, eps) - 1e-9))
+    P0 = se.support_for_tolerance("pkb", B, eps)
+    assert P0 > se.pollution_bound("pkb", M0 / (xi * L))      # a polluted case
+    p = se.recipe(3, L, xi, Q, eps, "pkb")
+    assert p.P == P0 + 4 and p.M == se.smooth_even_up(math.ceil(1.05 * M0))
+    # a loose tolerance at a small xi L is not polluted
+    eps2 = 1e-3 * se.B_scale(Q, 2.0, L)
+    M2 = se.smooth_even_up(math.ceil(2 * se.kinf_for_tolerance(Q, 2.0, L, eps2) - 1e-9))
+    P2 = se.support_for_tolerance("pkb", se.B_scale(Q, 2.0, L), eps2)
+    assert P2 <= se.pollution_bound("pkb", M2 / 2.0)
+    p2 = se.recipe(3, L, 2.0, Q, eps2, "pkb")
+    assert (p2.M, p2.P) == (max(M2, se.smooth_even_up(P2)), P2)
+
+
+@pytest.mark.parametrize("D,win,tol", [(3, "pkb", 1e-10), (3, "pkb", 1e-6), (2, "pkb", 1e-8), (0, "pkb", 1e-8),
+                                       (1, "gaussian", 1e-4), (3, "gaussian", 1e-5)])
+def test_recipe_reaches_the_tolerance(D, win, tol):
+    """Parameters from the recipe meet the tolerance against the direct sum
+    (the remedy 'should be enough to reach the error expected from the
+    estimates', Section 5.2)."""
+    x, q = wl.system(300, 1.0, 5 + D, "uniform")
+    Q = float((q * q).sum())
+    B = se.B_scale(Q, 8.0, 1.0)
+    p = se.recipe(D, 1.0, 8.0, Q, tol * B, win)
+    phi, _ = se.spectral_ewald(x, q, p, grad=False)
+    ref, _ = direct.kspace(D, 1.0, 8.0, x, q)
+    assert math.sqrt(np.mean((phi - ref) ** 2)) < 3 * tol * B

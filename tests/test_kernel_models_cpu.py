@@ -1,0 +1,382 @@
+"""CPU models of the index logic that keeps the kernels' memory accesses in
+bounds, each checked against brute force.  They restate, step for step, the
+enumeration the device code performs (fold images of the box-mode spreading,
+anchor pieces of the clipped spreading, the FFT slot walks and their
+reciprocal quotients, the real-space pair enumeration), so that the limits
+the planner enforces (at most kMaxFoldImages box images per direction, at
+most kMaxPieces anchor pieces, at most kMaxClipRanges particle ranges) are
+shown to cover every geometry it accepts.
+"""
+import math
+
+import numpy as np
+import pytest
+
+K_MAX_FOLD_IMAGES = 8   # se_internal.h
+K_MAX_PIECES = 4
+K_MAX_CLIP_RANGES = 512
+K_SB = 4
+K_FFT_BLOCK = 256
+
+
+# --- box-mode spreading: tile boxes that meet a tile (fold pass) ------------
+
+def box_of(G, T, nt, P, per, t, d):
+    """Tile u = t + d wrapped into [0, nt) with the image shift, and the box
+    origin u T + shift - (P/2 - 1); None past a free boundary."""
+    u, shift = t + d, 0
+    while u < 0:
+        if not per:
+            return None
+        u += nt
+        shift -= G
+    while u >= nt:
+        if not per:
+            return None
+        u -= nt
+        shift += G
+    return u, u * T + shift - (P // 2 - 1)
+
+
+def fold_images(G, T, P, per, t):
+    """The kernel's enumeration for tile t (one direction): offsets scanned
+    over +-reach, boxes kept if they meet [x0, x0 + ext)."""
+    nt = (G + T - 1) // T
+    RX = T + P - 1
+    emin = min(T, G - (nt - 1) * T) if per else T
+    reach = 2 + (T + P) // max(emin, 1)
+    x0, ext = t * T, min(T, G - t * T)
+    out = []
+    for d in range(-reach, reach + 1):
+        b = box_of(G, T, nt, P, per, t, d)
+        if b is None:
+            continue
+        u, o = b
+        if o < x0 + ext and o + RX > x0:
+            out.append((u, o))
+    return out
+
+
+def fold_brute(G, T, P, per, t):
+    """Every (tile, image) box that meets tile t: tiles u with origin
+    u T + k G - (P/2 - 1) for all images k (one image if not periodic)."""
+    nt = (G + T - 1) // T
+    RX = T + P - 1
+    x0, ext = t * T, min(T, G - t * T)
+    ks = range(-(RX // G) - 3, RX // G + 4) if per else (0,)
+    out = []
+    for u in range(nt):
+        for k in ks:
+            o = u * T + k * G - (P // 2 - 1)
+            if o < x0 + ext and o + RX > x0:
+                out.append((u, o))
+    return out
+
+
+def test_fold_enumeration_matches_brute_force():
+    """For every periodic or free direction of up to 70 grid points, tile
+    edges 4-32 (multiples of 4) and even P up to 16: the kernel's offset scan
+    finds exactly the boxes that meet the tile, each once; the planner's
+    count (the same scan, maximum over tiles) therefore bounds what the fold
+    kernel needs, and the plan is refused above kMaxFoldImages.  For the
+    tile edges the planner picks by default (4-16), no geometry needs more
+    than 7 images."""
+    most_default = 0
+    for P in range(2, 17, 2):
+        for T in range(4, 33, 4):
+            for G in range(max(P, 4), 71):
+                for per in (True, False):
+                    if not per and G < P:
+                        continue
+                    nt = (G + T - 1) // T
+                    counts = []
+                    for t in range(nt):
+                        k = fold_images(G, T, P, per, t)
+                        b = fold_brute(G, T, P, per, t)
+                        assert sorted(k) == sorted(b) and len(set(k)) == len(k), (P, T, G, per, t)
+                        counts.append(len(k))
+                    if T <= 16:
+                        most_default = max(most_default, max(counts))
+    assert most_default <= K_MAX_FOLD_IMAGES - 1
+
+
+# --- clipped spreading: anchor pieces of a tile ------------------------------
+
+def floor_div(a, b):
+    return a // b   # Python floors for b > 0, as the device helper does
+
+
+def anchor_pieces(G, per, lo, hi):
+    """The kernel's pieces (sub-bin segment, image shift) of anchor cells
+    [lo, hi] (unwrapped); at most K_MAX_PIECES."""
+    if not per:
+        lo, hi = max(lo, 0), min(hi, G - 1)
+        return [(lo // K_SB, hi // K_SB, 0, lo, hi)] if lo <= hi else []
+    out = []
+    k = floor_div(lo, G)
+    while k <= floor_div(hi, G) and len(out) < K_MAX_PIECES:
+        a, e = max(lo - k * G, 0), min(hi - k * G, G - 1)
+        if a <= e:
+            out.append((a // K_SB, e // K_SB, k * G, a, e))
+        k += 1
+    return out
+
+
+def clip_dim_max(G, T, P, per, pieces_only):
+    """The planner's bound: largest sub-bin count (or piece count) of any
+    tile, or a value above every limit when a tile needs more pieces."""
+    nt = (G + T - 1) // T
+    h = P // 2
+    most = 0
+    for t in range(nt):
+        o, e = t * T, min(T, G - t * T)
+        lo, hi = o - h, o + e - 1 + h - 1
+        if not per:
+            lo, hi = max(lo, 0), min(hi, G - 1)
+            cnt, npc = (hi // K_SB - lo // K_SB + 1, 1) if lo <= hi else (0, 0)
+        else:
+            cnt = npc = 0
+            for k in range(floor_div(lo, G), floor_div(hi, G) + 1):
+                a, b = max(lo - k * G, 0), min(hi - k * G, G - 1)
+                if a <= b:
+                    cnt += b // K_SB - a // K_SB + 1
+                    npc += 1
+        if npc > K_MAX_PIECES:
+            return 1 << 28
+        most = max(most, npc if pieces_only else cnt)
+    return most
+
+
+def test_clipped_anchor_pieces_match_brute_force():
+    """The anchors whose stencil c - P/2 + 1 .. c + P/2 meets a tile are the
+    cells [o - P/2, o + e - 1 + P/2 - 1]; the kernel's pieces cover exactly
+    these cells (as wrapped cell and image shift), each once, whenever the
+    planner accepts the geometry, and the planner's range bound covers every
+    tile's ranges."""
+    for P in range(2, 17, 2):
+        for T in range(4, 33, 4):
+            for G in range(max(P, 4), 71):
+                for per in (True, False):
+                    bound = clip_dim_max(G, T, P, per, False)
+                    if bound >= 1 << 28:
+                        continue        # refused by the planner (boxes and fold instead)
+                    nt = (G + T - 1) // T
+                    for t in range(nt):
+                        o, e = t * T, min(T, G - t * T)
+                        lo, hi = o - P // 2, o + e - 1 + P // 2 - 1
+                        pcs = anchor_pieces(G, per, lo, hi)
+                        assert len(pcs) <= K_MAX_PIECES
+                        got = sorted((c, sh) for (_, _, sh, a, b) in pcs for c in range(a, b + 1))
+                        want = sorted(((c % G, c - c % G) if per else (c, 0)) for c in range(lo, hi + 1)
+                                      if per or 0 <= c < G)
+                        assert got == want, (P, T, G, per, t)
+                        # every such anchor's stencil reaches the tile
+                        for c, sh in got:
+                            s0 = c + sh - P // 2 + 1
+                            assert s0 < o + e and s0 + P > o
+                        nsub = sum(s1 - s0 + 1 for (s0, s1, _, _, _) in pcs)
+                        assert nsub <= bound
+
+
+def test_clip_range_bound_is_an_upper_bound():
+    """Ranges per tile = z sub-bins x y sub-bins x x pieces, bounded by the
+    product of the per-direction maxima the planner checks against
+    kMaxClipRanges."""
+    rng = np.random.default_rng(3)
+    for _ in range(300):
+        P = int(rng.choice(range(2, 17, 2)))
+        T = [int(v) for v in rng.choice(range(4, 33, 4), 3)]
+        G = [int(v) for v in rng.integers(max(P, 4), 71, 3)]
+        per = [bool(v) for v in rng.integers(0, 2, 3)]
+        bz, by, bx = (clip_dim_max(G[2], T[2], P, per[2], False), clip_dim_max(G[1], T[1], P, per[1], False),
+                      clip_dim_max(G[0], T[0], P, per[0], True))
+        if max(bz, by, bx) >= 1 << 28:
+            continue
+        for tz in range((G[2] + T[2] - 1) // T[2]):
+            for ty in range((G[1] + T[1] - 1) // T[1]):
+                for tx in range((G[0] + T[0] - 1) // T[0]):
+                    n = 1
+                    for d, (t, sub) in enumerate(((tx, False), (ty, True), (tz, True))):
+                        o, e = t * T[d], min(T[d], G[d] - t * T[d])
+                        pcs = anchor_pieces(G[d], per[d], o - P // 2, o + e - 1 + P // 2 - 1)
+                        n *= sum(s1 - s0 + 1 for (s0, s1, _, _, _) in pcs) if sub else len(pcs)
+                    assert n <= bz * by * bx
+
+
+# --- FFT pencil blocks: slot walks by additions ------------------------------
+
+def _rcp(d):
+    return np.float32(1.0) / np.float32(d)
+
+
+def test_reciprocal_quotient_is_exact():
+    """fdiv(a, rcp(d)) = trunc((a + 1/2) rcp(d)) in FP32 equals a div d for
+    all dividends a < 2^13 (kFftCap) and divisors d <= 2^13, also when the
+    hardware reciprocal is off by two ulps either way."""
+    a = np.arange(8192, dtype=np.float32) + np.float32(0.5)
+    ai = np.arange(8192)
+    for d in range(1, 8193):
+        r0 = _rcp(d)
+        for r in (r0, np.nextafter(np.nextafter(r0, 0, dtype=np.float32), 0, dtype=np.float32),
+                  np.nextafter(np.nextafter(r0, 1, dtype=np.float32), 1, dtype=np.float32)):
+            q = (a * np.float32(r)).astype(np.int64)
+            assert np.array_equal(q, ai // d), d
+
+
+def slot_walk(n, lgB, gs0, gst, lt, lp, TF, steps):
+    """The kernel's per-thread walk over slots tid, tid + 256, ...: (t, p,
+    global offset, LDS index) after each step, for all 256 threads at once."""
+    tid = np.arange(K_FFT_BLOCK)
+    if TF:
+        q = K_FFT_BLOCK // n
+        r = K_FFT_BLOCK - q * n
+        p = tid // n
+        t = tid - p * n
+        dg, dgw = r * gst + q * gs0, gs0 - n * gst
+        dl, dlw = r * lt + q * lp, lp - n * lt
+    else:
+        dt = K_FFT_BLOCK >> lgB
+        p = tid & ((1 << lgB) - 1)
+        t = tid >> lgB
+        dg, dl = dt * gst, dt * lt
+    g = p * gs0 + t * gst
+    l = t * lt + p * lp
+    out = []
+    for _ in range(steps):
+        out.append((t.copy(), p.copy(), g.copy(), l.copy()))
+        if TF:
+            t, p, g, l = t + r, p + q, g + dg, l + dl
+            w = t >= n
+            t = np.where(w, t - n, t)
+            p = np.where(w, p + 1, p)
+            g = np.where(w, g + dgw, g)
+            l = np.where(w, l + dlw, l)
+        else:
+            t, g, l = t + dt, g + dg, l + dl
+    return out
+
+
+def _smooth_lengths(limit):
+    out = []
+    for n in range(2, limit + 1):
+        m = n
+        for f in (2, 3, 5, 7):
+            while m % f == 0:
+                m //= f
+        if m == 1:
+            out.append(n)
+    return out
+
+
+def test_slot_walk_equals_direct_indexing():
+    """Walking slots by additions gives, at every step, the slot's direct
+    coordinates: pencil-major (p = e div n, t = e mod n) when the transform
+    direction is contiguous, sample-major (t = e div B, p = e mod B)
+    otherwise, and the matching global offsets and LDS indices, for every
+    7-smooth length and pencil count of a block (n B <= 8192)."""
+    rng = np.random.default_rng(1)
+    for n in _smooth_lengths(8192):
+        for lgB in range(0, 7):
+            B = 1 << lgB
+            if n * B > 8192:
+                break
+            gs0, gst = int(rng.integers(1, 5000)), int(rng.integers(1, 5000))
+            lt, lp = B + 1, 1
+            steps = (n * B + K_FFT_BLOCK - 1) // K_FFT_BLOCK
+            for TF in (True, False):
+                walk = slot_walk(n, lgB, gs0, gst, lt, lp, TF, steps)
+                for k, (t, p, g, l) in enumerate(walk):
+                    e = np.arange(K_FFT_BLOCK) + k * K_FFT_BLOCK
+                    tt, pp = (e % n, e // n) if TF else (e >> lgB, e & (B - 1))
+                    assert np.array_equal(t, tt) and np.array_equal(p, pp), (n, lgB, TF, k)
+                    assert np.array_equal(g, pp * gs0 + tt * gst) and np.array_equal(l, tt * lt + pp * lp)
+
+
+# --- real space: the pair enumeration of the cell list ------------------------
+
+def rs_cells(L, rc, n_max, k=2):
+    by_n = max(1, int(math.floor(float(np.cbrt(max(1, n_max))) + 1e-9)))
+    c = int(max(1.0, min(math.floor(k * L / rc), by_n, 160)))
+    h = L / c
+    s = max(1, math.ceil(rc / h))
+    while s > 1 and (s - 1) * h >= rc:
+        s -= 1
+    while s * h < rc:
+        s += 1
+    return c, s
+
+
+def rs_candidates(D, c, s, L, rc, cells, t):
+    """The kernel's candidates for target t: (neighbour, image vector) in the
+    order it visits them."""
+    h = L / c
+    ix, iy, iz = cells[t]
+    out = []
+    by_cell = {}
+    for j, cc in enumerate(cells):
+        by_cell.setdefault(tuple(cc), []).append(j)
+    for dz in range(-s, s + 1):
+        uz = iz + dz
+        if D < 3 and not 0 <= uz < c:
+            continue
+        qz = uz // c
+        gz = max(0, abs(dz) - 1) * h
+        for dy in range(-s, s + 1):
+            uy = iy + dy
+            if D < 2 and not 0 <= uy < c:
+                continue
+            qy = uy // c
+            gy = max(0, abs(dy) - 1) * h
+            rem = rc * rc - gz * gz - gy * gy
+            if rem <= 0.0:
+                continue
+            dm = s
+            while dm > 1 and ((dm - 1) * h) ** 2 >= rem:
+                dm -= 1
+            xa, xb = ix - dm, ix + dm
+            if D < 1:
+                xa, xb = max(xa, 0), min(xb, c - 1)
+            for qx in range(xa // c, xb // c + 1):
+                lo, hi = max(xa, qx * c) - qx * c, min(xb, qx * c + c - 1) - qx * c
+                for cx in range(lo, hi + 1):
+                    for j in by_cell.get((cx, uy - qy * c, uz - qz * c), []):
+                        if (qx, qy, qz) == (0, 0, 0) and j == t:
+                            continue
+                        out.append((j, (qx, qy, qz)))
+    return out
+
+
+@pytest.mark.parametrize("D", [3, 2, 1, 0])
+@pytest.mark.parametrize("rc_over_L", [0.11, 0.3, 0.55, 1.1, 1.6])
+def test_real_space_enumeration_visits_each_pair_once(D, rc_over_L):
+    """Every pair within rc (periodic images included, the target itself at
+    zero shift excluded) is visited exactly once, for spans s = 1-3 and
+    cutoffs beyond the box."""
+    rng = np.random.default_rng(int(100 * rc_over_L) + D)
+    L, n = 1.0, 90
+    x = rng.random((n, 3)) * L
+    rc = rc_over_L * L
+    for k in (1, 2, 3):
+        c, s = rs_cells(L, rc, n, k)
+        h = L / c
+        cells = np.minimum((x / h).astype(int), c - 1)
+        K = math.ceil(rc / L) + 1
+        rng_img = range(-K, K + 1)
+        for t in range(0, n, 7):
+            cand = rs_candidates(D, c, s, L, rc, [tuple(v) for v in cells], t)
+            assert len(cand) == len(set(cand))
+            got = set()
+            for j, (qx, qy, qz) in cand:
+                shift = np.array([qx, qy, qz]) * L
+                if np.linalg.norm(x[t] - (x[j] + shift)) < rc:
+                    got.add((j, (qx, qy, qz)))
+            want = set()
+            for j in range(n):
+                for a in (rng_img if D >= 1 else (0,)):
+                    for b in (rng_img if D >= 2 else (0,)):
+                        for cz in (rng_img if D >= 3 else (0,)):
+                            if j == t and (a, b, cz) == (0, 0, 0):
+                                continue
+                            if np.linalg.norm(x[t] - x[j] - np.array([a, b, cz]) * L) < rc:
+                                want.add((j, (a, b, cz)))
+            assert got == want, (D, rc, k, t)

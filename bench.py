@@ -61,6 +61,48 @@ def roofline(stages, prec, workload_P=None):
     return r
 
 
+def stage_table(stages, prec, workload_P=None):
+    """Per-stage rooflines: algorithmic bytes and flops of one launch over its
+    average HIP-event time, as fractions of the HBM and vector peaks; the
+    binding fraction is the larger.  Stored HBM byte counts (rocprofv3
+    FETCH_SIZE + WRITE_SIZE, copy-calibrated) for the same sources and
+    workload add the counter-to-algorithmic ratio."""
+    traffic = {}
+    tpath = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tpath):
+        try:
+            sha = _source_sha()
+            traffic = {k: v for k, v in json.load(open(tpath)).items()
+                       if v.get("source_sha") == sha and v.get("P") == workload_P}
+        except Exception:
+            traffic = {}
+    rows = []
+    for r in stages:
+        t = max(r["ms_avg"], 1e-9) * 1e-3
+        bw, fl = r["bytes"] / t, r["flops"] / t
+        fh, fa = bw / HBM_PEAK, fl / ALU_PEAK[prec]
+        row = {"stage": r["name"], "ms_avg": r["ms_avg"], "alg_bytes": r["bytes"], "alg_flops": r["flops"],
+               "GB_s": bw / 1e9, "frac_hbm": fh, "TFLOP_s": fl / 1e12, "frac_alu": fa,
+               "bound": "hbm" if fh >= fa else "alu", "frac": max(fh, fa)}
+        ent = traffic.get(r["name"])
+        if ent and r["bytes"] > 0:
+            row["traffic"] = ent["bytes_per_launch"]
+            row["traffic_ratio"] = ent["bytes_per_launch"] / r["bytes"]
+        rows.append(row)
+    return rows
+
+
+def host_cpu():
+    """Model name of the host CPU (from /proc/cpuinfo)."""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def _source_sha(files=("se_kernels.hip", "se_fft.hip", "se_plan.cpp", "se_internal.h", "se_device.h")):
     """Hash of the kernel and planner sources without comments and blank lines
     (a stored HBM byte count stays valid across comment edits only)."""
@@ -136,17 +178,73 @@ def batch_cpu_baseline(systems, budget_s=10.0, per_sys_targets=256):
         tg = np.sort(np.random.default_rng(100 + k).choice(s["N"], size=T, replace=False))
         t0 = time.perf_counter()
         phi, grad = direct.kspace(s["D"], s["L"], s["xi"], s["x"], s["q"], targets=tg)
-        t_tot += time.perf_counter() - t0
+        dt = time.perf_counter() - t0
+        t_tot += dt
         n_tot += T
         used += 1
-        res.append((k, tg, phi, grad))
+        res.append((k, tg, phi, grad, dt))
         if t_tot > budget_s:
             break
     return {"value": n_tot / t_tot, "unit": "particles/s", "cores": cores, "kind": "oracle",
+            "systems": [r[0] for r in res],
             "sample": f"direct FP64 k-space sums (closed forms, potential and gradient) for {n_tot} "
                       f"targets: up to {per_sys_targets} per system of {used} systems (each periodicity "
                       f"in turn, cheapest first by N (xi L)^D), each against all of its sources, "
                       f"{t_tot:.1f} s"}, res
+
+
+def batch_o2_baseline(systems, params, budget_s=8.0):
+    """The discrete SE oracle (numpy FP64, one thread: the method's own
+    algorithm on the CPU) on whole batch systems, each periodicity in turn,
+    smallest grid first, until the time budget is used."""
+    from oracle import se_discrete as se
+    by_d = [sorted((k for k, s in enumerate(systems) if s["D"] == D),
+                   key=lambda k: params[k].M ** 3) for D in (0, 1, 2, 3)]
+    order = [lst[r] for r in range(max(len(l) for l in by_d)) for lst in by_d if r < len(lst)]
+    t_tot, n_tot, used = 0.0, 0, 0
+    for k in order:
+        s, pp = systems[k], params[k]
+        extra = {"s": pp.s, "n_l": pp.n_l} if s["D"] in (1, 2) else {}
+        p = se.Params(D=s["D"], L=s["L"], xi=s["xi"], M=pp.M, P=pp.P, window="pkb", **extra)
+        t0 = time.perf_counter()
+        se.spectral_ewald(s["x"], s["q"], p)
+        t_tot += time.perf_counter() - t0
+        n_tot += s["N"]
+        used += 1
+        if t_tot > budget_s:
+            break
+    return {"value": n_tot / t_tot, "unit": "particles/s", "cores": 1, "kind": "oracle (discrete SE, numpy)",
+            "sample": f"discrete SE oracle (Algorithms 1-4, FP64, numpy FFTs) on {used} whole systems "
+                      f"({n_tot} particles, potential and gradient, each periodicity in turn, smallest grid "
+                      f"first), {t_tot:.1f} s"}
+
+
+def oracle_one_core(res, budget_s=6.0):
+    """The direct oracle's batch sample timed with one thread, in a child
+    process (OpenMP takes its thread count when the library loads): the same
+    systems in the same order and the same targets as the all-core sample,
+    until the budget is used; the all-core rate over the same systems is
+    reported beside it."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        out = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-oracle-sample", str(budget_s)],
+                             env=env, capture_output=True, text=True, timeout=300)
+        one = json.loads(out.stdout.strip().splitlines()[-1])
+    except Exception as e:   # reported, not fatal: the main baseline stands
+        return {"error": str(e)[:200]}
+    same = [r for r in res if r[0] in set(one.get("systems", []))]
+    if same:
+        one["all_cores_same_sample"] = sum(len(r[1]) for r in same) / sum(r[4] for r in same)
+    return one
+
+
+def _cpu_oracle_sample(budget_s):
+    """Child process of oracle_one_core: no GPU, prints one JSON line."""
+    import workloads as wl
+    systems = wl.batch_systems()
+    cb, _ = batch_cpu_baseline(systems, budget_s=budget_s)
+    print(json.dumps(cb), flush=True)
 
 
 _KNOBS = ("tile3", "fft_cap", "xcd_tiles", "xcd_fft", "spread_mode")
@@ -262,6 +360,20 @@ def main_batch(args):
     ms64 = (time.perf_counter() - t0) * 1e3 / steps64
     print(f"bench: FP64 plain loop {ms64:.3f} ms/step", file=sys.stderr, flush=True)
 
+    # the same batch in FP64 (batching without the precision change)
+    b64 = SpectralEwaldBatch(p64, N)
+    o64b = b64(x, q)
+    for _ in range(args.warmup):
+        b64(x, q, out=o64b, check=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps64):
+        b64(x, q, out=o64b, check=False)
+    torch.cuda.synchronize()
+    ms64b = (time.perf_counter() - t0) * 1e3 / steps64
+    del b64, o64b
+    print(f"bench: FP64 batched {ms64b:.3f} ms/step", file=sys.stderr, flush=True)
+
     phi32 = out32[0].double().cpu().numpy()
     f32 = out32[1].double().cpu().numpy()
     e32 = out32[2].cpu().numpy()
@@ -309,28 +421,80 @@ def main_batch(args):
         "fp64_plain_value": tot / (ms64 * 1e-3),
         "fp64_plain_ms_per_step": ms64,
         "speedup_vs_fp64_plain": ms64 / ms32,
+        "fp64_batched_value": tot / (ms64b * 1e-3),
+        "fp64_batched_ms_per_step": ms64b,
+        "speedup_batching_fp64": ms64 / ms64b,
+        "speedup_precision_batched": ms64b / ms32,
         "roofline": roof,
+        "stages": stage_table(stages, "f32", cfg["P"]),
         "errors": err,
         "autotune": tune_rep,
     }
+    if not args.no_single:
+        result["single_systems"] = single_systems(args)
     if not args.no_cpu_baseline:
         cb, res = batch_cpu_baseline(systems)
+        cb["host_cpu"] = host_cpu()
+        cb["one_core"] = oracle_one_core(res)
+        cb["discrete_se"] = batch_o2_baseline(systems, p64)
         result["cpu_baseline"] = cb
         e_phi32, e_phi64, e_f32, ref_n = 0.0, 0.0, 0.0, 0.0
-        for k, tg, phi_o, grad_o in res:
+        for k, tg, phi_o, grad_o, _ in res:
             sl = offs[k] + tg
             e_phi32 += float(np.sum((phi32[sl] - phi_o) ** 2))
             e_phi64 += float(np.sum((phi64[sl] - phi_o) ** 2))
             e_f32 += float(np.sum((f32[sl] + systems[k]["q"][tg, None] * grad_o) ** 2))
             ref_n += float(np.sum(phi_o ** 2))
-        g_n = sum(float(np.sum((systems[k]["q"][tg, None] * grad_o) ** 2)) for k, tg, phi_o, grad_o in res)
+        g_n = sum(float(np.sum((systems[k]["q"][tg, None] * grad_o) ** 2)) for k, tg, phi_o, grad_o, _ in res)
         e_f64 = sum(float(np.sum((f64[offs[k] + tg] + systems[k]["q"][tg, None] * grad_o) ** 2))
-                    for k, tg, phi_o, grad_o in res)
+                    for k, tg, phi_o, grad_o, _ in res)
         err["phi_f32_vs_oracle"] = (e_phi32 / ref_n) ** 0.5
         err["phi_f64_vs_oracle"] = (e_phi64 / ref_n) ** 0.5
         err["force_f32_vs_oracle"] = (e_f32 / g_n) ** 0.5
         err["force_f64_vs_oracle"] = (e_f64 / g_n) ** 0.5
     print(json.dumps(result), flush=True)
+
+
+def single_systems(args, names=("C1_3P", "C2_0P", "C3_2P", "C4_1P")):
+    """The four single-system configurations in FP32 and FP64 (one plan each,
+    inputs resident): particles/s, per-stage rooflines of the FP32 run and the
+    FP32 error against FP64."""
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    from paper_1712_04732_amd import SpectralEwald, _lib
+    out = {}
+    dev = torch.device("cuda:0")
+    steps = max(5, args.steps // 2)
+    for name in names:
+        cfg = wl.CONFIGS[name]
+        D, N, L, M, P, xi, win = cfg["D"], cfg["N"], cfg["L"], cfg["M"], cfg["P"], cfg["xi"], cfg["window"]
+        x, q = wl.config_system(name)
+        Q = float((q * q).sum())
+        kw = dict(window=win, n_max=N)
+        if D in (1, 2):
+            kw.update(Q=Q, tol=1e-6 * _lib.se_error_scale(Q, xi, L))
+        x64 = torch.tensor(x, device=dev)
+        q64 = torch.tensor(q, device=dev)
+        row = {"workload": name, "D": D, "N": N, "M": M, "P": P, "window": win, "xi": xi}
+        res = {}
+        for prec in ("f32", "f64"):
+            plan = SpectralEwald(D, L, xi, M, P, prec=prec, **kw)
+            ms, o, st = run_path(plan, x64, q64, steps, args.warmup)
+            row[f"value_{prec}"] = N / (ms * 1e-3)
+            row[f"ms_per_step_{prec}"] = ms
+            if prec == "f32":
+                row["Mt"] = plan.info.Mt
+                row["stages_f32"] = stage_table(st, "f32", P)
+            res[prec] = [t.double().cpu().numpy() for t in o]
+            del plan
+        row["phi_f32_vs_f64"] = rel_rms(res["f32"][0], res["f64"][0])
+        row["force_f32_vs_f64"] = rel_rms(res["f32"][1], res["f64"][1])
+        out[name] = row
+        print(f"bench: {name} f32 {row['ms_per_step_f32']:.3f} ms ({row['value_f32']:.3g} particles/s), "
+              f"f64 {row['ms_per_step_f64']:.3f} ms", file=sys.stderr, flush=True)
+    return out
 
 
 def pairs_within(D, L, rc, x, n_sample=20000, seed=11):
@@ -565,11 +729,15 @@ def main():
                     help="time the real-space part instead (single-system workloads; default C4_1P)")
     ap.add_argument("--xi-balance", action="store_true",
                     help="time k space + real space against xi (single-system workloads; default C4_1P)")
+    ap.add_argument("--no-single", action="store_true", help="batch: skip the C1-C4 single-system lines")
+    ap.add_argument("--cpu-oracle-sample", type=float, default=None, help=argparse.SUPPRESS)
     ap.add_argument("--force-methods", action="store_true",
                     help="force method 1 vs method 2 against P on the paper's 3P workload (Section 7.2)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device 5 times (reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.cpu_oracle_sample is not None:
+        return _cpu_oracle_sample(args.cpu_oracle_sample)
     if args.copy_calibration:
         import torch
         a = torch.empty(64 << 20, dtype=torch.float32, device="cuda:0").fill_(1.0)

@@ -66,7 +66,11 @@ typedef enum {
   SE_ERR_WORKSPACE = 9    /* no workspace bound, or one too small or misaligned     */
 } se_status;
 
-typedef enum { SE_WIN_GAUSSIAN = 0, SE_WIN_PKB = 1 } se_window;
+/* Windows of Section 4: truncated Gaussian (Eq. gaussian), the KB window
+ * evaluated as the piecewise polynomial of Section 4.1 (PKB), and the
+ * exponential of semicircle (ES, Eq. expsemicirc_window), evaluated directly,
+ * whose Fourier transform the planner computes by quadrature. */
+typedef enum { SE_WIN_GAUSSIAN = 0, SE_WIN_PKB = 1, SE_WIN_ES = 2 } se_window;
 typedef enum { SE_F64 = 0, SE_F32 = 1 } se_precision;
 
 /* Parameters of one system (Algorithm 4 input list, Section 6 rules).
@@ -78,9 +82,11 @@ typedef struct {
   int M;              /* grid intervals per periodic side, even, 7-smooth        */
   int P;              /* window support in grid intervals, even, 2..16, P <= M   */
   se_window window;
-  double shape;       /* alpha (Gaussian) / beta (KB); <= 0 -> (pi/2) P 0.91 / 2.5 P */
+  double shape;       /* alpha (Gaussian) / beta (KB, ES); <= 0 -> (pi/2) P 0.91 /
+                         2.5 P (both KB and ES)                                  */
   int nu;             /* PKB polynomial degree; <= 0 -> min(P/2 + 2, 9)          */
-  double lambda;      /* free-direction extension factor; <= 0 -> Table lambda   */
+  double lambda;      /* free-direction extension factor; <= 0 -> Table lambda
+                         (the ES window takes the KB values)                     */
   double s0;          /* zero-mode / free-space upsampling; <= 0 -> 2 / 2.5 / 2.8 */
   double s;           /* AFT upsampling of the set I (Eq. I); <= 0 -> Eq. estimate-s */
   int n_l;            /* size of the set I; < 0 -> Eq. estimate-nl                */
@@ -112,6 +118,11 @@ typedef struct {
                          2 method 2, the scaling step times i k_d and steps 4-5
                          once per direction d, each gathering with the window
                          itself (single plans only)                            */
+  int deriv_fit;      /* PKB, method 1: 0 differentiates the PKB polynomial (the
+                         exact gradient of the discrete energy); 1 fits W'_KB
+                         by its own polynomial with the same P, beta, nu
+                         (Section 7.2; the gradient is then not the energy's
+                         exact derivative)                                      */
 } se_params;
 
 /* Derived sizes of a plan (read-only report). */

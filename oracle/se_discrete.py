@@ -48,6 +48,7 @@ LAMBDA = {  # Table lambda (Section 6)
     "gaussian": {0: 1.0, 1: 1.5, 2: 1.5},
     "pkb": {0: 1.3, 1: 2.4, 2: 2.4},
     "kb": {0: 1.3, 1: 2.4, 2: 2.4},
+    "es": {0: 1.3, 1: 2.4, 2: 2.4},   # the ES window approximates KB (Section 4): KB's values
 }
 S0 = {0: 2.8, 1: 2.5, 2: 2.0}  # Section 3.4 / Section 6
 
@@ -114,7 +115,8 @@ class Params:
     xi: float
     M: int
     P: int
-    window: str = "pkb"   # "gaussian", "pkb" (piecewise polynomial KB) or "kb" (exact KB)
+    window: str = "pkb"   # "gaussian", "pkb" (piecewise polynomial KB), "kb" (exact KB) or "es"
+    deriv_fit: bool = False     # PKB: fit W'_KB separately for the gradient (Section 7.2)
     shape: float | None = None  # alpha (Gaussian) or beta (KB); default from Section 6
     nu: int | None = None       # PKB degree; default min(P/2+2, 9)
     lam: float | None = None    # Table lambda
@@ -239,19 +241,52 @@ def kb_du(u, P, beta):
     return np.where(inside, val, 0.0)
 
 
-def pkb_coefficients(P, beta, nu):
+def pkb_coefficients(P, beta, nu, fn=None):
     """Coefficients c[i, j] of the PKB window (Section 4.1): on subinterval i
     of [-w, w] (i = 0..P-1, each of length h) the KB window is interpolated by
     sum_j c[i,j] xbar^j at the nu+1 Chebyshev points
-    xbar_k = cos(pi (k - 1/2)/(nu+1)), Eqs. (polynomial-ansatz), (polynomial-linsys)."""
+    xbar_k = cos(pi (k - 1/2)/(nu+1)), Eqs. (polynomial-ansatz), (polynomial-linsys).
+    fn replaces the KB window by another function of u (grid units), such as
+    its derivative for the separately fitted W'_KB of Section 7.2."""
+    fn = kb if fn is None else fn
     k = np.arange(1, nu + 2)
     xb = np.cos(np.pi * (k - 0.5) / (nu + 1))
     V = xb[:, None] ** np.arange(nu + 1)[None, :]
     c = np.empty((P, nu + 1))
     for i in range(P):
         u = -P / 2 + i + (xb + 1.0) / 2.0   # subinterval i in grid units
-        c[i] = np.linalg.solve(V, kb(u, P, beta))
+        c[i] = np.linalg.solve(V, fn(u, P, beta))
     return c
+
+
+def es(u, P, beta):
+    """ES window, Eq. (expsemicirc_window), in grid units u = x/h (w = P/2)."""
+    z = 2.0 * np.asarray(u, dtype=np.float64) / P
+    inside = np.abs(z) <= 1.0
+    return np.where(inside, np.exp(beta * (np.sqrt(np.where(inside, 1.0 - z * z, 0.0)) - 1.0)), 0.0)
+
+
+def es_du(u, P, beta):
+    """d/du of the ES window (0 at the end points, where it is not
+    differentiable)."""
+    z = 2.0 * np.asarray(u, dtype=np.float64) / P
+    inside = np.abs(z) < 1.0
+    sq = np.sqrt(np.where(inside, 1.0 - z * z, 1.0))
+    return np.where(inside, -es(u, P, beta) * beta * z * (2.0 / P) / sq, 0.0)
+
+
+def es_ft(k, h, P, beta):
+    """Fourier transform of the ES window, which has no closed form
+    (Section 4): int_{-w}^{w} W(x) cos(k x) dx by adaptive quadrature, after
+    x = w sin(theta), which removes the square-root end behaviour:
+    2 w int_0^{pi/2} e^{beta (cos theta - 1)} cos(k w sin theta) cos theta dtheta."""
+    from scipy import integrate
+    w = P * h / 2.0
+    out = []
+    for kk in np.atleast_1d(np.asarray(k, dtype=np.float64)).ravel():
+        f = lambda th: math.exp(beta * (math.cos(th) - 1.0)) * math.cos(kk * w * math.sin(th)) * math.cos(th)
+        out.append(2.0 * w * integrate.quad(f, 0.0, math.pi / 2, limit=500, epsabs=0.0, epsrel=2e-14)[0])
+    return np.reshape(np.array(out), np.shape(k))
 
 
 def window_ft(k, h, P, window, shape):
@@ -260,6 +295,8 @@ def window_ft(k, h, P, window, shape):
     Eq. (kaiser_ft).  k in physical units, w = P h / 2."""
     w = P * h / 2.0
     k = np.asarray(k, dtype=np.float64)
+    if window == "es":
+        return es_ft(k, h, P, shape)
     if window == "gaussian":
         a = shape
         return np.sqrt(np.pi / a) * w * np.exp(-k * k * w * w / (4.0 * a))
@@ -291,14 +328,22 @@ def weights_1d(t, p: Params):
     elif p.window == "kb":
         W = kb(u, P, p.shape)
         dWdt = -kb_du(u, P, p.shape)
+    elif p.window == "es":
+        W = es(u, P, p.shape)
+        dWdt = -es_du(u, P, p.shape)
     else:
         c = pkb_coefficients(P, p.shape, p.nu)    # (P, nu+1)
         xb = 1.0 - 2.0 * f                          # same for all P subintervals
         powers = xb[:, None] ** np.arange(p.nu + 1)[None, :]
         W = powers @ c.T
-        dpow = np.zeros_like(powers)
-        dpow[:, 1:] = np.arange(1, p.nu + 1)[None, :] * powers[:, :-1]
-        dWdt = -2.0 * (dpow @ c.T)                  # d xbar / dt = -2
+        if p.deriv_fit:
+            # Section 7.2: W'_KB fitted by the same procedure (same P, beta, nu);
+            # d/dt W(j - t) = -W'(u)
+            dWdt = -(powers @ pkb_coefficients(P, p.shape, p.nu, fn=kb_du).T)
+        else:
+            dpow = np.zeros_like(powers)
+            dpow[:, 1:] = np.arange(1, p.nu + 1)[None, :] * powers[:, :-1]
+            dWdt = -2.0 * (dpow @ c.T)              # d xbar / dt = -2
     return j0, W, dWdt / p.h
 
 

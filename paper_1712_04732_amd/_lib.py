@@ -25,6 +25,7 @@ SE_ERR_WORKSPACE = 9
 
 SE_WIN_GAUSSIAN = 0
 SE_WIN_PKB = 1
+SE_WIN_ES = 2
 SE_F64 = 0
 SE_F32 = 1
 
@@ -61,6 +62,7 @@ class se_params(ctypes.Structure):
         ("xcd_fft", ctypes.c_int),
         ("spread_mode", ctypes.c_int),
         ("force_method", ctypes.c_int),
+        ("deriv_fit", ctypes.c_int),
     ]
 
 

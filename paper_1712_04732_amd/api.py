@@ -10,7 +10,7 @@ import torch
 
 from . import _lib as L
 
-_WINDOWS = {"gaussian": L.SE_WIN_GAUSSIAN, "pkb": L.SE_WIN_PKB}
+_WINDOWS = {"gaussian": L.SE_WIN_GAUSSIAN, "pkb": L.SE_WIN_PKB, "es": L.SE_WIN_ES}
 _PRECS = {"f64": L.SE_F64, "f32": L.SE_F32}
 
 
@@ -52,7 +52,7 @@ class SpectralEwald:
 
     def __init__(self, D, L_box, xi, M, P, *, window="pkb", prec="f64", n_max=1 << 20,
                  Q=None, tol=None, shape=None, nu=None, lam=None, s0=None, s=None, n_l=None,
-                 tile=0, force_method=1):
+                 tile=0, force_method=1, deriv_fit=False):
         if not torch.cuda.is_available():
             raise RuntimeError("SpectralEwald needs a HIP device")
         L.load()
@@ -78,6 +78,7 @@ class SpectralEwald:
             p.n_l = n_l
         p.tile = tile
         p.force_method = force_method
+        p.deriv_fit = 1 if deriv_fit else 0
         self.params = p
         self.n_max = int(n_max)
         self.prec = prec

@@ -366,28 +366,8 @@ hipError_t launch_order(const GridGeom& g, const EvalBuffers& b, int nsbtot, boo
 //        (chain factor -2/h).
 //   Gaussian: u = i + 1 - P/2 - f (grid units), W = exp(-alpha (2u/P)^2),
 //        dW/dx = W 2 alpha (2/P)^2 u / h.
+//   ES: W = exp(beta (sqrt(1 - z^2) - 1)), z = 2u/P (beta held in alpha).
 // ---------------------------------------------------------------------------
-template <typename T, int P>
-__device__ __forceinline__ T weight_row(const GridGeom& g, const T* __restrict__ tab, int i, T f) {
-  if (g.window == 1) {
-    const T xb = (T)1 - (T)2 * f;
-    const int m = g.nu + 1;
-    T a = tab[i * m + g.nu];
-    for (int j = g.nu - 1; j >= 0; --j) a = a * xb + tab[i * m + j];
-    return a;
-  }
-  const T u = (T)(i + 1 - P / 2) - f;
-  return exp(-(T)g.alpha * ((T)4 / (T)(P * P)) * u * u);
-}
-
-template <typename T, int P>
-__device__ __forceinline__ T dweight_row(const GridGeom& g, const T* __restrict__ dtab, int i, T f) {
-  if (g.window == 1) return weight_row<T, P>(g, dtab, i, f);
-  const T u = (T)(i + 1 - P / 2) - f;
-  const T c2 = (T)4 / (T)(P * P);
-  return exp(-(T)g.alpha * c2 * u * u) * (T)2 * (T)g.alpha * c2 * u / (T)g.h;
-}
-
 // Segments are {first0, last0, first1, last1} in sub-bin units.
 __device__ __forceinline__ int seg_len(const int* seg, int ns) {
   int n = 0;
@@ -501,6 +481,11 @@ __device__ __forceinline__ T weight_reg(const GridGeom& g, const T* r, int i, T 
     return a;
   }
   const T u = (T)(i + 1 - P / 2) - f;
+  if (g.window == 2) {
+    // ES window, Eq. (expsemicirc_window): e^{beta (sqrt(1 - z^2) - 1)}, z = 2u/P
+    const T z = (T)2 * u / (T)P;
+    return exp((T)g.alpha * (sqrt(max((T)1 - z * z, (T)0)) - (T)1));
+  }
   return exp(-(T)g.alpha * ((T)4 / (T)(P * P)) * u * u);
 }
 
@@ -508,6 +493,14 @@ template <typename T, int P>
 __device__ __forceinline__ T dweight_reg(const GridGeom& g, const T* r, int i, T f) {
   if (g.window == 1) return weight_reg<T, P>(g, r, i, f);
   const T u = (T)(i + 1 - P / 2) - f;
+  if (g.window == 2) {
+    // d/dx of the ES window at u = grid point - particle: W beta z (2/P) / sqrt(1 - z^2) / h,
+    // 0 at the end points (not differentiable there)
+    const T z = (T)2 * u / (T)P, s2 = (T)1 - z * z;
+    if (!(s2 > (T)0)) return (T)0;
+    const T s = sqrt(s2);
+    return exp((T)g.alpha * (s - (T)1)) * (T)g.alpha * z * ((T)2 / (T)P) / (s * (T)g.h);
+  }
   const T c2 = (T)4 / (T)(P * P);
   return exp(-(T)g.alpha * c2 * u * u) * (T)2 * (T)g.alpha * c2 * u / (T)g.h;
 }
@@ -1147,36 +1140,86 @@ __device__ __forceinline__ void stage_gather(const GridGeom& g, const EvalBuffer
   load_batch(0);   // in flight together with the region below
 
   // stage the stencil region [x0 - P/2 + 1, x0 + TX + P/2 - 1] of the grid:
-  // each wavefront copies whole rows, 64 / RX rows at a time, and each lane
-  // keeps its x offset (wrapped once) for all rows
+  // rows of RX points are read as 16-byte chunks of V points (one chunk per
+  // lane, LR lanes per row, 64 / LR rows per wavefront at a time); a chunk
+  // inside [0, G0) is one load, a chunk across a periodic or free x boundary
+  // is read point by point.  The LDS rows keep pitch RX (a padded pitch would
+  // put the z planes of one particle's lanes on the same banks in the
+  // contraction below), so chunks are written point by point.  Rows advance
+  // by additions: the row index, its (y, z) place in the region and the
+  // wrapped grid coordinates need no division per load.
   const T* grid = reinterpret_cast<const T*>(b.grid);
   const int rx = x0 - P / 2 + 1, ry = y0 - P / 2 + 1, rz = z0 - P / 2 + 1;
   {
+    constexpr int V = 16 / (int)sizeof(T);
     constexpr int U = 8;  // rows in flight per lane
-    const int rpw = 64 / RX, sub = lane / RX, px = lane - sub * RX;
-    bool okx = sub < rpw;
-    const int gx = wrap_coord(g, 0, rx + px, &okx);
+    const int LR = (RX + V - 1) / V;
+    const int rpw = 64 / LR, sub = lane / LR, cpos = lane - sub * LR;
     const int nrows = RY * RZ, step = nwaves * rpw;
-    if (sub < rpw)
-      for (int r0 = wave * rpw + sub; r0 < nrows; r0 += U * step) {
-        T v[U];
+    const int G0 = g.G[0], G1 = g.G[1], G2y = g.G[2];
+    if (sub < rpw) {
+      const int xs = rx + cpos * V;                    // unwrapped x of the chunk's first point
+      const bool whole = xs >= 0 && xs + V <= G0;      // no x boundary inside the chunk
+      int gxv[V];
+      bool okxv[V];
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        okxv[e] = cpos * V + e < RX;
+        gxv[e] = wrap_coord(g, 0, xs + e, &okxv[e]);
+      }
+      const int step_q = step / RY, step_r = step - step_q * RY;
+      int row = wave * rpw + sub;
+      int py = row % RY, pz = row / RY;
+      auto wrapped = [&](int d, int c, int G, bool* ok) {
+        if (g.per[d]) {
+          while (c >= G) c -= G;
+          while (c < 0) c += G;
+        } else {
+          *ok = *ok && c >= 0 && c < G;
+        }
+        return c;
+      };
+      using C16 = T __attribute__((ext_vector_type(V)));   // one 16-byte chunk
+      while (row < nrows) {
+        C16 v[U];
+        int lrow[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const int row = r0 + u * step;
-          v[u] = (T)0;
+          v[u] = (C16)(T)0;
+          lrow[u] = row < nrows ? row : -1;
           if (row < nrows) {
-            const int py = row % RY, pz = row / RY;
-            bool ok = okx;
-            const int gy = wrap_coord(g, 1, ry + py, &ok), gz = wrap_coord(g, 2, rz + pz, &ok);
-            if (ok) v[u] = gld(grid)[((long long)gz * g.G[1] + gy) * g.G[0] + gx];
+            bool ok = true;
+            const int gy = wrapped(1, ry + py, G1, &ok), gz = wrapped(2, rz + pz, G2y, &ok);
+            if (ok) {
+              const T* src = grid + ((long long)gz * G1 + gy) * G0;
+              if (whole) {
+                // point-aligned, not chunk-aligned in memory: copied, not dereferenced as C16
+                __builtin_memcpy(&v[u], src + xs, sizeof(C16));
+              } else {
+#pragma unroll
+                for (int e = 0; e < V; ++e)
+                  if (okxv[e]) v[u][e] = gld(src)[gxv[e]];
+              }
+            }
+          }
+          row += step;
+          py += step_r;
+          pz += step_q;
+          if (py >= RY) {
+            py -= RY;
+            ++pz;
           }
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int row = r0 + u * step;
-          if (row < nrows) reg[row * RX + px] = v[u];
-        }
+        for (int u = 0; u < U; ++u)
+          if (lrow[u] >= 0) {
+            T* dst = reg + lrow[u] * RX + cpos * V;
+#pragma unroll
+            for (int e = 0; e < V; ++e)
+              if (cpos * V + e < RX) dst[e] = v[u][e];
+          }
       }
+    }
   }
 
   const int p = lane / G2, iz = lane % G2;

@@ -74,6 +74,18 @@ double bessel_i0(double x) {
   return s;
 }
 
+// Modified Bessel function I1 by its power series (x/2) sum (x^2/4)^k / (k! (k+1)!).
+double bessel_i1(double x) {
+  const double y = 0.25 * x * x;
+  double term = 0.5 * x, s = term;
+  for (int k = 1; k < 500; ++k) {
+    term *= y / ((double)k * (k + 1));
+    s += term;
+    if (std::fabs(term) < 1e-17 * std::fabs(s)) break;
+  }
+  return s;
+}
+
 // KB window in grid units u (w = P/2), Eq. (kaiser_window).
 double kb_window(double u, int P, double beta) {
   const double z = 2.0 * u / P;
@@ -81,11 +93,62 @@ double kb_window(double u, int P, double beta) {
   return bessel_i0(beta * std::sqrt(1.0 - z * z)) / bessel_i0(beta);
 }
 
+// d/du of the KB window (grid units): -I1(beta s) beta z (2/P) / (s I0(beta)),
+// s = sqrt(1 - z^2); 0 outside the support.
+double kb_window_du(double u, int P, double beta) {
+  const double z = 2.0 * u / P;
+  if (std::fabs(z) >= 1.0) return 0.0;
+  const double s = std::sqrt(1.0 - z * z);
+  return -bessel_i1(beta * s) * beta * z * (2.0 / P) / (s * bessel_i0(beta));
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton iteration on P_n).
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double t = std::cos(kPi * (i + 0.75) / (n + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = t;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (t * p1 - p0) / (t * t - 1.0);
+      const double dt = p1 / dp;
+      t -= dt;
+      if (std::fabs(dt) < 1e-16) break;
+    }
+    x[i] = -t;
+    x[n - 1 - i] = t;
+    w[i] = w[n - 1 - i] = 2.0 / ((1.0 - t * t) * dp * dp);
+  }
+}
+
+// Fourier transform of the ES window, Eq. (expsemicirc_window), which has no
+// closed form (Section 4): with x = w sin(theta),
+//   int_{-w}^{w} e^{beta (sqrt(1 - (x/w)^2) - 1)} cos(k x) dx
+//     = w int_{-pi/2}^{pi/2} e^{beta (cos theta - 1)} cos(k w sin theta) cos theta dtheta,
+// a smooth integrand, by 256-point Gauss-Legendre quadrature.
+double es_ft(double k, double w, double beta) {
+  static std::vector<double> gx, gw;
+  static std::once_flag once;
+  std::call_once(once, [] { gauss_legendre(256, gx, gw); });
+  double s = 0.0;
+  for (size_t i = 0; i < gx.size(); ++i) {
+    const double th = 0.5 * kPi * gx[i];
+    s += gw[i] * std::exp(beta * (std::cos(th) - 1.0)) * std::cos(k * w * std::sin(th)) * std::cos(th);
+  }
+  return 0.5 * kPi * w * s;
+}
+
 // 1D Fourier transform of the window used in the scaling step: Eq. (kaiser_ft)
 // for KB, the untruncated Gaussian transform for the Gaussian (Section 4).
 double window_ft(double k, double h, int P, int window, double shape) {
   const double w = P * h / 2.0;
   if (window == SE_WIN_GAUSSIAN) return std::sqrt(kPi / shape) * w * std::exp(-k * k * w * w / (4.0 * shape));
+  if (window == SE_WIN_ES) return es_ft(k, w, shape);
   const double d = shape * shape - k * k * w * w;
   const double sd = std::sqrt(std::fabs(d));
   double r;
@@ -125,7 +188,8 @@ bool solve(std::vector<double> A, std::vector<double> b, int m, std::vector<doub
 // PKB coefficients (Section 4.1): on subinterval i of [-w, w] the KB window
 // is interpolated at the nu+1 Chebyshev points xbar_k = cos(pi (k - 1/2)/(nu+1))
 // by sum_j c_ij xbar^j (Eqs. polynomial-ansatz, polynomial-linsys).
-bool pkb_coefficients(int P, double beta, int nu, std::vector<double>& c) {
+bool pkb_coefficients(int P, double beta, int nu, std::vector<double>& c,
+                      double (*fn)(double, int, double) = kb_window) {
   const int m = nu + 1;
   std::vector<double> V(m * m), xb(m);
   for (int k = 0; k < m; ++k) {
@@ -139,7 +203,7 @@ bool pkb_coefficients(int P, double beta, int nu, std::vector<double>& c) {
   c.assign((size_t)P * m, 0.0);
   for (int i = 0; i < P; ++i) {
     std::vector<double> rhs(m), sol;
-    for (int k = 0; k < m; ++k) rhs[k] = kb_window(-P / 2.0 + i + (xb[k] + 1.0) / 2.0, P, beta);
+    for (int k = 0; k < m; ++k) rhs[k] = fn(-P / 2.0 + i + (xb[k] + 1.0) / 2.0, P, beta);
     if (!solve(V, rhs, m, sol)) return false;
     for (int j = 0; j < m; ++j) c[(size_t)i * m + j] = sol[j];
   }
@@ -438,7 +502,7 @@ se_status se_params_default(int D, double L, double xi, int M, int P, se_window 
                             double tol, se_precision prec, se_params* out) {
   if (!out) return SE_ERR_ARG;
   if (!valid_base(D, L, xi, M, P) || !(tol > 0) || !(Q >= 0)) return SE_ERR_PARAM;
-  if (window != SE_WIN_GAUSSIAN && window != SE_WIN_PKB) return SE_ERR_PARAM;
+  if (window != SE_WIN_GAUSSIAN && window != SE_WIN_PKB && window != SE_WIN_ES) return SE_ERR_PARAM;
   se_params p{};
   p.D = D;
   p.L = L;
@@ -450,7 +514,7 @@ se_status se_params_default(int D, double L, double xi, int M, int P, se_window 
   p.nu = window == SE_WIN_PKB ? std::min(P / 2 + 2, 9) : 0;
   const double lam[2][3] = {{1.0, 1.5, 1.5}, {1.3, 2.4, 2.4}};  // Table lambda
   const double s0[3] = {2.8, 2.5, 2.0};
-  p.lambda = D < 3 ? lam[window == SE_WIN_PKB][D] : 0.0;
+  p.lambda = D < 3 ? lam[window != SE_WIN_GAUSSIAN][D] : 0.0;
   p.s0 = D < 3 ? s0[D] : 0.0;
   p.tol = tol;
   p.Q = Q;
@@ -477,7 +541,7 @@ static double kp_kspace(double Q, double xi, double L, int M) {
 }
 
 // Error-pollution bound f_W(x), Eq. (error_pollution).
-static double pollution_fw(se_window w, double x) {
+static double pollution_fw(se_window w, double x) {  // ES: the KB bound
   return w == SE_WIN_GAUSSIAN ? x * x + 0.2 * x + 2.25 : 0.7 * x * x + 0.2 * x + 1.8;
 }
 
@@ -520,7 +584,8 @@ se_status se_params_recipe(int D, double L, double xi, double Q, double tol_rel,
                            se_precision prec, se_params* out) {
   if (!out) return SE_ERR_ARG;
   if (D < 0 || D > 3 || !(L > 0) || !(xi > 0) || !(Q > 0) || !(tol_rel > 0) || !std::isfinite(L) ||
-      !std::isfinite(xi) || !std::isfinite(Q) || (window != SE_WIN_GAUSSIAN && window != SE_WIN_PKB))
+      !std::isfinite(xi) || !std::isfinite(Q) ||
+      (window != SE_WIN_GAUSSIAN && window != SE_WIN_PKB && window != SE_WIN_ES))
     return SE_ERR_PARAM;
   const double B = std::sqrt(Q) * fc(xi * L) / L;
   const double eps = tol_rel * B;
@@ -652,7 +717,8 @@ static se_status plan_create(const se_params* params, long n_max, void* hip_stre
   *out = nullptr;
   se_params p = *params;
   if (!valid_base(p.D, p.L, p.xi, p.M, p.P)) return SE_ERR_PARAM;
-  if (p.window != SE_WIN_GAUSSIAN && p.window != SE_WIN_PKB) return SE_ERR_PARAM;
+  if (p.window != SE_WIN_GAUSSIAN && p.window != SE_WIN_PKB && p.window != SE_WIN_ES) return SE_ERR_PARAM;
+  if (p.deriv_fit < 0 || p.deriv_fit > 1 || (p.deriv_fit && p.window != SE_WIN_PKB)) return SE_ERR_PARAM;
   if (p.prec != SE_F64 && p.prec != SE_F32) return SE_ERR_PARAM;
   if (!is_smooth(p.M)) return SE_ERR_PARAM;
   if (!(p.shape > 0)) p.shape = p.window == SE_WIN_GAUSSIAN ? (kPi / 2.0) * p.P * 0.91 : 2.5 * p.P;
@@ -665,7 +731,7 @@ static se_status plan_create(const se_params* params, long n_max, void* hip_stre
   if (p.D < 3) {
     const double lam[2][3] = {{1.0, 1.5, 1.5}, {1.3, 2.4, 2.4}};
     const double s0[3] = {2.8, 2.5, 2.0};
-    if (!(p.lambda > 0)) p.lambda = lam[p.window == SE_WIN_PKB][p.D];
+    if (!(p.lambda > 0)) p.lambda = lam[p.window != SE_WIN_GAUSSIAN][p.D];
     if (!(p.s0 > 0)) p.s0 = s0[p.D];
     // Section 3.4: the zero mode (2P, 1P) and the free-space transform (0P)
     // need s0 >= 1 + sqrt(d) for d = 3 - D free directions
@@ -741,7 +807,7 @@ static se_status plan_create(const se_params* params, long n_max, void* hip_stre
   }
   g.P = p.P;
   g.nu = p.nu;
-  g.window = p.window == SE_WIN_PKB ? 1 : 0;
+  g.window = p.window == SE_WIN_PKB ? 1 : (p.window == SE_WIN_ES ? 2 : 0);
   g.h = I.h;
   g.L = p.L;
   g.xi = p.xi;
@@ -849,11 +915,18 @@ static se_status plan_create(const se_params* params, long n_max, void* hip_stre
         rc = SE_ERR_PARAM;
         break;
       }
+      std::vector<double> cd;
+      if (p.deriv_fit && !pkb_coefficients(p.P, p.shape, p.nu, cd, kb_window_du)) {
+        rc = SE_ERR_PARAM;
+        break;
+      }
       for (int i = 0; i < p.P; ++i)
         for (int j = 0; j < m; ++j) {
           wt[(size_t)i * m + j] = c[(size_t)i * m + j];
-          // d/dx of sum c_j xbar^j with xbar = 1 - 2 frac(x/h): chain factor -2/h
-          if (j + 1 < m) wt[(size_t)p.P * m + (size_t)i * m + j] = (j + 1) * c[(size_t)i * m + j + 1] * (-2.0 / I.h);
+          if (p.deriv_fit)   // the fitted W'_KB(u), u = grid point minus particle: d/dx = -W'/h
+            wt[(size_t)p.P * m + (size_t)i * m + j] = -cd[(size_t)i * m + j] / I.h;
+          else if (j + 1 < m)   // d/dx of sum c_j xbar^j, xbar = 1 - 2 frac(x/h): chain factor -2/h
+            wt[(size_t)p.P * m + (size_t)i * m + j] = (j + 1) * c[(size_t)i * m + j + 1] * (-2.0 / I.h);
         }
     }
     pl->buf.wtab = pl->upload(wt);

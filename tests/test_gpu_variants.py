@@ -1,0 +1,126 @@
+"""Window variants on the GPU against the discrete oracle (same parameters:
+rounding only) and the direct Ewald oracle:
+
+  * the ES window of Section 4 (Eq. expsemicirc_window), evaluated directly
+    in the kernels, its Fourier transform by quadrature in the planner;
+  * forces with the separately fitted W'_KB polynomial of Section 7.2.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import direct
+from oracle import se_discrete as se
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1712_04732_amd import SpectralEwald, SpectralEwaldBatch, params_for_tolerance  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+def run(plan, x, q, dtype=torch.float64):
+    phi, g, E = plan(torch.tensor(x, dtype=dtype, device=DEV), torch.tensor(q, dtype=dtype, device=DEV),
+                     out_grad=True)
+    torch.cuda.synchronize()
+    return phi.double().cpu().numpy(), g.double().cpu().numpy(), float(E)
+
+
+@pytest.mark.parametrize("D,M,P", [(3, 32, 8), (2, 24, 8), (1, 30, 6), (0, 24, 8), (3, 28, 12)])
+def test_es_window_matches_discrete_oracle(D, M, P):
+    print(f"case ES vs O2 D={D} M={M} P={P}", flush=True)
+    N = 1200
+    x, q = wl.system(N, 1.0, 800 + D + M, "uniform")
+    kw = dict(s=2.0, n_l=3) if D in (1, 2) else {}
+    plan = SpectralEwald(D, 1.0, 8.0, M, P, window="es", prec="f64", n_max=N, **kw)
+    assert abs(plan.info.shape - 2.5 * P) < 1e-12
+    p = se.Params(D=D, L=1.0, xi=8.0, M=M, P=P, window="es", **kw)
+    phi, g, E = run(plan, x, q)
+    ref, gref = se.spectral_ewald(x, q, p)
+    assert rel(phi, ref) < 1e-12 and rel(g, gref) < 1e-11
+    p32 = SpectralEwald(D, 1.0, 8.0, M, P, window="es", prec="f32", n_max=N, **kw)
+    phi32, g32, _ = run(p32, x, q)   # FP64 inputs: cell offsets formed in FP64
+    print(f"ES FP32 vs FP64: phi {rel(phi32, phi):.2e} grad {rel(g32, g):.2e}")
+    assert rel(phi32, phi) < 2e-6 and rel(g32, g) < 5e-6
+
+
+@pytest.mark.parametrize("D", [3, 2, 1, 0])
+def test_es_window_error_against_direct(D):
+    """Nearly as accurate as the PKB window at equal support (within 3x), about
+    10 e^{-2.5P}."""
+    print(f"case ES vs direct D={D}", flush=True)
+    N = 300
+    x, q = wl.system(N, 1.0, 820 + D, "uniform")
+    Q = float((q * q).sum())
+    B = se.B_scale(Q, 8.0, 1.0)
+    ref, _ = direct.kspace(D, 1.0, 8.0, x, q)
+    for P in (6, 8, 10):
+        err = {}
+        for win in ("es", "pkb"):
+            pp = se.with_aft_estimates(D, 1.0, 8.0, 32, P, Q, 1e-15 * B, window=win)
+            kw = dict(s=pp.s, n_l=pp.n_l) if D in (1, 2) else {}
+            plan = SpectralEwald(D, 1.0, 8.0, 32, P, window=win, prec="f64", n_max=N, **kw)
+            phi, _, _ = run(plan, x, q)
+            err[win] = math.sqrt(np.mean((phi - ref) ** 2)) / B
+        est = 10 * math.exp(-2.5 * P)
+        print(f"P={P}: ES {err['es']:.2e} PKB {err['pkb']:.2e} estimate {est:.1e}")
+        assert est / 5 < err["es"] < 5 * est and err["es"] < 3 * err["pkb"]
+
+
+@pytest.mark.parametrize("D", [3, 2, 0])
+def test_separately_fitted_derivative(D):
+    """deriv_fit = 1: gradients from the separately fitted W'_KB polynomial
+    equal the oracle's (same fit), the potential is unchanged, and the
+    forces meet the direct oracle as closely as with the differentiated
+    polynomial."""
+    print(f"case W' fit D={D}", flush=True)
+    N = 800
+    x, q = wl.system(N, 1.0, 840 + D, "uniform")
+    kw = dict(s=2.0, n_l=3) if D in (1, 2) else {}
+    a = SpectralEwald(D, 1.0, 8.0, 32, 8, prec="f64", n_max=N, **kw)
+    b = SpectralEwald(D, 1.0, 8.0, 32, 8, prec="f64", n_max=N, deriv_fit=True, **kw)
+    pa, ga, _ = run(a, x, q)
+    pb, gb, _ = run(b, x, q)
+    assert np.array_equal(pa, pb)
+    p = se.Params(D=D, L=1.0, xi=8.0, M=32, P=8, window="pkb", deriv_fit=True, **kw)
+    _, gref = se.spectral_ewald(x, q, p)
+    assert rel(gb, gref) < 1e-11
+    if D != 2:
+        _, gd = direct.kspace(D, 1.0, 8.0, x, q)
+        ea, eb = rel(ga, gd), rel(gb, gd)
+        print(f"forces vs direct: differentiated {ea:.2e}, fitted {eb:.2e}")
+        assert eb < 2 * ea and ea < 2 * eb
+
+
+def test_es_window_in_a_batch():
+    print("case ES batch", flush=True)
+    params, xs, qs, sys_ = [], [], [], []
+    for k, D in enumerate((3, 2, 1, 0)):
+        n = 300 + 40 * k
+        x, q = wl.system(n, 1.0, 860 + k, "pm1")
+        xi = wl.batch_xi(n, 1.0)
+        params.append(params_for_tolerance(D, 1.0, xi, float(n), 1e-7, 8, "es", "f64"))
+        xs.append(x)
+        qs.append(q)
+        sys_.append((D, n, xi))
+    b = SpectralEwaldBatch(params, [s[1] for s in sys_])
+    phi, g, _ = b(torch.tensor(np.concatenate(xs), device=DEV), torch.tensor(np.concatenate(qs), device=DEV),
+                  out_grad=True)
+    torch.cuda.synchronize()
+    phi, g = phi.cpu().numpy(), g.cpu().numpy()
+    o = 0
+    for (D, n, xi), pp, x, q in zip(sys_, params, xs, qs):
+        kw = {"s": pp.s, "n_l": pp.n_l} if D in (1, 2) else {}
+        ref, gref = se.spectral_ewald(x, q, se.Params(D=D, L=1.0, xi=xi, M=pp.M, P=8, window="es", **kw))
+        assert rel(phi[o:o + n], ref) < 1e-12 and rel(g[o:o + n], gref) < 1e-11
+        o += n

@@ -252,3 +252,18 @@ def test_recipe_rejects_bad_arguments():
     for args in ((4, 1.0, 8.0, 10.0, 1e-6), (3, -1.0, 8.0, 10.0, 1e-6), (3, 1.0, 0.0, 10.0, 1e-6),
                  (3, 1.0, 8.0, 0.0, 1e-6), (3, 1.0, 8.0, 10.0, 0.0), (3, 1.0, 8.0, 10.0, 1e-40)):
         assert lib.se_params_recipe(*args, L.SE_WIN_PKB, L.SE_F64, ctypes.byref(out)) == L.SE_ERR_PARAM
+
+
+def test_es_window_rules():
+    """The ES window takes beta = 2.5 P, no polynomial degree and the KB
+    values of Table lambda; the W'_KB fit is refused for other windows."""
+    lib = L.load()
+    for D in (3, 2, 1, 0):
+        p = L.se_params_default(D, 1.0, 8.0, 32, 8, L.SE_WIN_ES, 100.0, 1e-8, L.SE_F64)
+        assert p.window == L.SE_WIN_ES and abs(p.shape - 20.0) < 1e-12 and p.nu == 0
+        if D < 3:
+            assert abs(p.lambda_ - (1.3 if D == 0 else 2.4)) < 1e-12
+    p = L.se_params()
+    p.D, p.L, p.xi, p.M, p.P, p.window, p.deriv_fit = 3, 1.0, 8.0, 32, 8, L.SE_WIN_ES, 1
+    plan = ctypes.c_void_p()
+    assert lib.se_plan_create(ctypes.byref(p), 10, None, ctypes.byref(plan)) == L.SE_ERR_PARAM

@@ -415,3 +415,71 @@ def test_recipe_reaches_the_tolerance(D, win, tol):
     phi, _ = se.spectral_ewald(x, q, p, grad=False)
     ref, _ = direct.kspace(D, 1.0, 8.0, x, q)
     assert math.sqrt(np.mean((phi - ref) ** 2)) < 3 * tol * B
+
+
+# --- window variants: the ES window and the separately fitted W'_KB ---------
+
+def test_es_transform_against_a_dense_sum():
+    """The ES transform (adaptive quadrature) against a dense trapezoidal sum
+    of the window, which converges fast because the window and its leading
+    derivatives are small at the ends."""
+    P, h, beta = 8, 1.0 / 32, 20.0
+    w = P * h / 2
+    xs = np.linspace(-w, w, 200001)
+    vals = se.es(xs / h, P, beta)
+    for k in (0.0, 17.0, 90.0, 200.0):
+        dense = np.trapezoid(vals * np.cos(k * xs), xs)
+        assert abs(se.es_ft(k, h, P, beta) - dense) < 1e-9 * abs(se.es_ft(0.0, h, P, beta))
+    # the derivative of the window, against central differences
+    u = np.linspace(-3.9, 3.9, 41)
+    fd = (se.es(u + 1e-6, P, beta) - se.es(u - 1e-6, P, beta)) / 2e-6
+    assert np.max(np.abs(se.es_du(u, P, beta) - fd)) < 1e-7
+
+
+@pytest.mark.parametrize("D", [3, 2, 1, 0])
+def test_es_window_error_against_direct(D):
+    """The ES window 'can achieve nearly as high precision as the KB window
+    with the same width' (Section 4): with beta = 2.5 P its error is within 2x
+    of the PKB window's at the same P, and within a factor 5 of the KB
+    estimate 10 e^{-2.5P} (truncation negligible)."""
+    x, q, Q = _sys(D, N=150)
+    L, xi, M = 1.0, 8.0, 32
+    B = se.B_scale(Q, xi, L)
+    ref, _ = direct.kspace(D, L, xi, x, q)
+    for P in (6, 8):
+        err = {}
+        for win in ("es", "pkb"):
+            p = se.with_aft_estimates(D, L, xi, M, P, Q, 1e-15 * B, window=win)
+            phi, _ = se.spectral_ewald(x, q, p, grad=False)
+            err[win] = math.sqrt(np.mean((phi - ref) ** 2)) / B
+        est = 10 * math.exp(-2.5 * P)
+        assert est / 5 < err["es"] < 5 * est and err["es"] < 2 * err["pkb"], (P, err)
+
+
+def test_separate_derivative_fit_converges_to_kb_derivative():
+    """The separately fitted W'_KB polynomial (Section 7.2) interpolates the
+    KB derivative: its error falls with nu, as the PKB fit's does."""
+    P, beta = 8, 20.0
+    t = np.random.default_rng(2).random(400) * 10
+    errs = []
+    for nu in (4, 6, 8, 10):
+        p = se.Params(D=3, L=1.0, xi=8.0, M=32, P=P, window="pkb", nu=nu, deriv_fit=True)
+        j0, W, dW = se.weights_1d(t, p)
+        u = (j0[:, None] + np.arange(P)[None, :]) - t[:, None]
+        exact = -se.kb_du(u, P, beta) / p.h
+        errs.append(np.max(np.abs(dW - exact)) / np.max(np.abs(exact)))
+    assert all(b < a / 5 for a, b in zip(errs, errs[1:])) and errs[-1] < 1e-7
+
+
+@pytest.mark.parametrize("D", [3, 0])
+def test_separate_derivative_fit_forces_against_direct(D):
+    """Forces with the separately fitted W'_KB meet the method-1 accuracy of
+    the differentiated polynomial (within 2x) at the paper's nu rule."""
+    x, q, Q = _sys(D, N=150)
+    ref, gref = direct.kspace(D, 1.0, 8.0, x, q)
+    e = []
+    for fit in (False, True):
+        p = se.Params(D=D, L=1.0, xi=8.0, M=32, P=8, window="pkb", deriv_fit=fit)
+        _, g = se.spectral_ewald(x, q, p)
+        e.append(rel(g, gref))
+    assert e[1] < 2 * e[0] and e[0] < 2 * e[1]

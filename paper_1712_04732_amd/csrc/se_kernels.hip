@@ -781,17 +781,31 @@ __device__ __forceinline__ void stage_spread_clip(const GridGeom& g, const EvalB
 
 // ---------------------------------------------------------------------------
 // Spreading by columns (no atomics, no staging, no fold).  One workgroup per
-// tile; thread c owns grid column (x0 + c mod TX, y0 + c / TX) of the tile and
-// keeps its TZ values in registers.  The particles whose stencils reach the
-// tile (periodic images included, as for the clipped mode) are taken in
-// batches: each thread evaluates the 3P window weights of one particle into
-// LDS, then every thread adds each stencil that covers its column, the z
-// offsets being the same for all threads (uniform branches, fixed register
-// indices).  Sums run in the compute precision in a fixed particle order.
+// tile.  The particles whose stencils reach the tile (periodic images
+// included, as for the clipped mode) are taken in batches: each thread
+// evaluates the 3P window weights of one particle into LDS.  Each thread then
+// owns two neighbouring grid columns (x0 + 2i, x0 + 2i + 1; y) and keeps their
+// TZ values in registers; the two halves of the workgroup take the even and
+// the odd visits of a batch, and add their sums at the end in a fixed order.
+// A visit's x weights sit in a row padded with a zero on each side, so both
+// columns of a thread read their weight without a range test; the z weights
+// are a whole row in the tile's z frame (zeros outside the stencil), so every
+// visit adds 2 x kColZ products to fixed registers.  Sums run in the compute
+// precision in a fixed particle order.
 // ---------------------------------------------------------------------------
+template <typename T, int P>
+struct ColLayout {
+  // per visit: the z row (kColZ), the zero-padded x row (P + 2), the y row (P);
+  // records 16-byte aligned
+  static constexpr int XO = kColZ, YO = kColZ + P + 2;
+  static constexpr int SW = (YO + P + 3) / 4 * 4;
+};
+
 template <typename T, int P>
 __device__ __forceinline__ void stage_spread_cols(const GridGeom& g, const EvalBuffers& b, int item,
                                                   unsigned char* smem) {
+  using Lay = ColLayout<T, P>;
+  constexpr int SW = Lay::SW, XO = Lay::XO, YO = Lay::YO;
   const int TX = g.T[0], TY = g.T[1], TZ = g.T[2];
   const int tz = item / (g.nt[0] * g.nt[1]);
   const int ty = (item / g.nt[0]) % g.nt[1];
@@ -805,9 +819,6 @@ __device__ __forceinline__ void stage_spread_cols(const GridGeom& g, const EvalB
   int* rsh = rpre + kMaxClipRanges + 4;                       // kMaxClipRanges
   int* org = rsh + kMaxClipRanges;                            // kColBatch packed origins
   T* wb = reinterpret_cast<T*>(org + kColBatch);              // kColBatch records of SW weights
-  // per visit: x and y stencil rows, then the z weights in the tile's z frame
-  // (zero outside the stencil); 16-byte aligned for P even
-  constexpr int SW = 2 * P + kColZ;
   __shared__ int pc_s0[3][kMaxPieces], pc_s1[3][kMaxPieces], pc_sh[3][kMaxPieces], pc_n[3];
 
   if (threadIdx.x < 3) {
@@ -837,11 +848,15 @@ __device__ __forceinline__ void stage_spread_cols(const GridGeom& g, const EvalB
   __syncthreads();
   const int total = prefix_ranges(rpre, nr);
 
-  const int c = threadIdx.x, cx = c % TX, cy = c / TX;
-  const bool own = c < TX * TY && cx < ex && cy < ey;
-  T acc[kColZ];
+  // column pair and visit parity of this thread (the parity is wavefront-uniform)
+  const int half = (int)threadIdx.x >= kBlock / 2 ? 1 : 0;
+  const int tc = threadIdx.x & (kBlock / 2 - 1);
+  const int TXh = TX / 2;
+  const int cx = 2 * (tc % TXh), cy = tc / TXh;
+  const bool own = tc < TXh * TY;
+  T acc0[kColZ], acc1[kColZ];
 #pragma unroll
-  for (int z = 0; z < kColZ; ++z) acc[z] = (T)0;
+  for (int z = 0; z < kColZ; ++z) acc0[z] = acc1[z] = (T)0;
 
   // weights: G2 lanes per particle, lane kr evaluates stencil row kr in x, y
   // and z with its coefficient row in registers
@@ -864,54 +879,78 @@ __device__ __forceinline__ void stage_spread_cols(const GridGeom& g, const EvalB
       const int oz = ((pc >> 20) & 1023) + pc_sh[2][code & 15] - P / 2 + 1 - z0;
       if (kr == 0) org[k] = (ox + 64) | ((oy + 64) << 8);
       T* w = wb + k * SW;
-      // the z row: zeros first, then the stencil rows over them (both by
-      // this particle's lanes of one wavefront, so in this order)
-      for (int z = kr; z < kColZ; z += G2) w[2 * P + z] = (T)0;
+      // zeros first (z row, x padding), then the stencil rows over them (both
+      // by this particle's lanes of one wavefront, so in this order)
+      for (int z = kr; z < kColZ; z += G2) w[z] = (T)0;
+      if (kr == 0) w[XO] = (T)0;
+      if (kr == 1 % G2) w[XO + P + 1] = (T)0;
       if (kr < P) {
-        w[kr] = weight_reg<T, P>(g, crow, kr, f.fx);
-        w[P + kr] = weight_reg<T, P>(g, crow, kr, f.fy);
+        w[XO + 1 + kr] = weight_reg<T, P>(g, crow, kr, f.fx);
+        w[YO + kr] = weight_reg<T, P>(g, crow, kr, f.fy);
         const int zz = oz + kr;
-        if ((unsigned)zz < (unsigned)kColZ) w[2 * P + zz] = f.q * weight_reg<T, P>(g, crow, kr, f.fz);
+        if ((unsigned)zz < (unsigned)kColZ) w[zz] = f.q * weight_reg<T, P>(g, crow, kr, f.fz);
       }
     }
     __syncthreads();
     // origins of 64 visits at a time, one per lane, broadcast by readlane;
     // all lanes stay active through the loop (readlane reads every lane's
-    // value), and each visit's stencil rows add to the own column's registers
+    // value); each half of the workgroup takes every other visit
     for (int k0 = 0; k0 < nb; k0 += 64) {
       const int my_org = org[min(k0 + (int)(threadIdx.x & 63), nb - 1)];
       const int kn = min(64, nb - k0);
-      {
-        for (int j = 0; j < kn; ++j) {
-          const int o = __builtin_amdgcn_readlane(my_org, j);
-          const int ox = (o & 255) - 64, oy = ((o >> 8) & 255) - 64;
-          const int dx = cx - ox, dy = cy - oy;
-          if (own && (unsigned)dx < (unsigned)P && (unsigned)dy < (unsigned)P) {
-            const T* w = wb + (k0 + j) * SW;
-            const T wxy = w[dx] * w[P + dy];
-            // the whole z row (zeros outside the stencil) with fixed register
-            // indices
-            const vec4<T>* wz4 = reinterpret_cast<const vec4<T>*>(w + 2 * P);
+      for (int j = half; j < kn; j += 2) {
+        const int o = __builtin_amdgcn_readlane(my_org, j);
+        const int ox = (o & 255) - 64, oy = ((o >> 8) & 255) - 64;
+        const int dx = cx - ox, dy = cy - oy;
+        // columns cx, cx + 1 meet the stencil's x range [0, P) when dx in [-1, P)
+        if (own && (unsigned)dy < (unsigned)P && (unsigned)(dx + 1) < (unsigned)(P + 1)) {
+          const T* w = wb + (k0 + j) * SW;
+          const T wy = w[YO + dy];
+          const T a0 = w[XO + 1 + dx] * wy, a1 = w[XO + 2 + dx] * wy;
+          const vec4<T>* wz4 = reinterpret_cast<const vec4<T>*>(w);
 #pragma unroll
-            for (int q = 0; q < kColZ / 4; ++q) {
-              const vec4<T> v = wz4[q];
-              acc[4 * q] += wxy * v.x;
-              acc[4 * q + 1] += wxy * v.y;
-              acc[4 * q + 2] += wxy * v.z;
-              acc[4 * q + 3] += wxy * v.w;
-            }
+          for (int q = 0; q < kColZ / 4; ++q) {
+            const vec4<T> v = wz4[q];
+            acc0[4 * q] += a0 * v.x;
+            acc0[4 * q + 1] += a0 * v.y;
+            acc0[4 * q + 2] += a0 * v.z;
+            acc0[4 * q + 3] += a0 * v.w;
+            acc1[4 * q] += a1 * v.x;
+            acc1[4 * q + 1] += a1 * v.y;
+            acc1[4 * q + 2] += a1 * v.z;
+            acc1[4 * q + 3] += a1 * v.w;
           }
         }
       }
     }
   }
-  if (own) {
+  // the odd-visit half hands its sums to the even-visit half through LDS
+  // (the weight records are consumed), which adds them in a fixed order
+  __syncthreads();
+  T* red = wb;   // kBlock / 2 threads x 2 kColZ values
+  if (half) {
+#pragma unroll
+    for (int z = 0; z < kColZ; ++z) {
+      red[z * (kBlock / 2) + tc] = acc0[z];
+      red[(kColZ + z) * (kBlock / 2) + tc] = acc1[z];
+    }
+  }
+  __syncthreads();
+  if (!half && own && cy < ey) {
+#pragma unroll
+    for (int z = 0; z < kColZ; ++z) {
+      acc0[z] += red[z * (kBlock / 2) + tc];
+      acc1[z] += red[(kColZ + z) * (kBlock / 2) + tc];
+    }
     T* grid = reinterpret_cast<T*>(b.grid);
     const long long base = ((long long)z0 * g.G[1] + y0 + cy) * g.G[0] + x0 + cx;
     const long long zs = (long long)g.G[0] * g.G[1];
 #pragma unroll
     for (int z = 0; z < kColZ; ++z)
-      if (z < ez) gst(grid)[base + z * zs] = acc[z];
+      if (z < ez) {
+        if (cx < ex) gst(grid)[base + z * zs] = acc0[z];
+        if (cx + 1 < ex) gst(grid)[base + z * zs + 1] = acc1[z];
+      }
   }
   __syncthreads();
 }
@@ -1028,8 +1067,11 @@ __global__ __launch_bounds__(kBlock) void fold_kernel(GridGeom g, EvalBuffers b)
 template <typename T>
 size_t spread_lds(const GridGeom& g) {
   const int P = g.P, nw = kBlock / 64;
-  if (g.clip == 2)
-    return sizeof(int) * (3 * kMaxClipRanges + 4 + kColBatch) + sizeof(T) * ((size_t)kColBatch * (2 * P + kColZ)) + 64;
+  if (g.clip == 2) {
+    const size_t sw = (size_t)(kColZ + 2 * P + 2 + 3) / 4 * 4;   // ColLayout::SW
+    return sizeof(int) * (3 * kMaxClipRanges + 4 + kColBatch) +
+           sizeof(T) * (kColBatch * sw > (size_t)kBlock * kColZ ? kColBatch * sw : (size_t)kBlock * kColZ) + 64;
+  }
   if (g.clip) {
     const size_t T3 = (size_t)g.T[0] * g.T[1] * g.T[2];
     return 8 * T3 + sizeof(T) * ((size_t)nw * g.chunk * (3 * P + 4)) +

@@ -183,12 +183,14 @@ __global__ __launch_bounds__(kRsBlock) void rs_scatter_kernel(long N, const int*
 // store the cell's charges in that order as records {x, y, z, q} with the
 // position taken from the cell's corner (so differences of nearby charges
 // keep the precision of the cell side, not of the box), and the charge's x
-// cell index in scx.
+// cell index in scx.  FP32 records come with an FP64 copy of the same
+// cell-relative position in spos64 (null for FP64 records).
 template <typename T, typename Tin>
 __global__ __launch_bounds__(kRsBlock) void rs_order_kernel(RsGeom g, const Tin* __restrict__ xyz,
                                                             const Tin* __restrict__ q,
                                                             const int* __restrict__ start, int* __restrict__ sidx,
-                                                            vec4<T>* __restrict__ spos, int* __restrict__ scx) {
+                                                            vec4<T>* __restrict__ spos, int* __restrict__ scx,
+                                                            vec4<double>* __restrict__ spos64) {
   __shared__ int key[kRsSortMax];
   const int cell = blockIdx.x;
   const int j0 = start[cell], j1 = start[cell + 1], n = j1 - j0;
@@ -222,7 +224,9 @@ __global__ __launch_bounds__(kRsBlock) void rs_order_kernel(RsGeom g, const Tin*
     double w[3], qi;
     int bad = 0;
     load_wrapped(xyz, q, o, g, w, &qi, &bad);
-    gst(spos)[j0 + i] = vec4<T>{(T)(w[0] - cx * g.h), (T)(w[1] - cy * g.h), (T)(w[2] - cz * g.h), (T)qi};
+    const double rx = w[0] - cx * g.h, ry = w[1] - cy * g.h, rz = w[2] - cz * g.h;
+    gst(spos)[j0 + i] = vec4<T>{(T)rx, (T)ry, (T)rz, (T)qi};
+    if (spos64) gst(spos64)[j0 + i] = vec4<double>{rx, ry, rz, 0.0};
     gst(scx)[j0 + i] = cx;
   }
 }
@@ -284,11 +288,18 @@ __device__ __forceinline__ int floor_div(int a, int c) { return a >= 0 ? a / c :
 // rows: for each (dy, dz) the cells ix - d .. ix + d that can hold a charge
 // within rc (d from the row's gaps) are consecutive in the cell order, so
 // their charges form one contiguous range per periodic image of x.
+//
+// FP32 records round each position to a few units in the last place of the
+// cell side, which is large against the difference of the closest pairs
+// (and their terms, ~1/r^2, dominate the forces): a pair closer than h/8
+// (a few in 10^4 of the pairs within rc) takes its difference again in FP64
+// from spos64 before the pair terms are evaluated in FP32.
 template <typename T, bool GRAD>
 __global__ __launch_bounds__(64) void rs_sum_kernel(RsGeom g, const int* __restrict__ start,
                                                     const int* __restrict__ sidx,
                                                     const vec4<T>* __restrict__ spos,
-                                                    const int* __restrict__ scx, RsOut out) {
+                                                    const int* __restrict__ scx,
+                                                    const vec4<double>* __restrict__ spos64, RsOut out) {
   const int cell = blockIdx.x, lane = threadIdx.x, c = g.c, s = g.s;
   const int ix = cell % c, iy = (cell / c) % c, iz = cell / (c * c);
   const int t0 = uni(gld(start)[cell]), t1 = uni(gld(start)[cell + 1]);
@@ -301,15 +312,28 @@ __global__ __launch_bounds__(64) void rs_sum_kernel(RsGeom g, const int* __restr
   const double h = g.h, rc2d = g.rc * g.rc;
   const T hT = (T)g.h;
   const T far = (T)(4.0 * g.L + 4.0 * g.rc + 1.0);   // padding charge, out of range of every target
+  const T near2 = (T)(g.h * g.h / 64.0);               // (h/8)^2: FP64 differences below it (FP32 records)
   double e_acc = 0.0;
   for (int tb = t0; tb < t1; tb += per) {
     const int k = tb + tl;
     const bool valid = k < t1;
     const vec4<T> tp = valid ? gld(spos)[k] : vec4<T>{(T)0, (T)0, (T)0, (T)0};
     T phi = 0, gx = 0, gy = 0, gz = 0;
-    auto pair = [&](T xj, T yj, T zj, T qn, bool self) {
-      const T dxv = tp.x - xj, dyv = tp.y - yj, dzv = tp.z - zj;
-      const T r2 = dxv * dxv + dyv * dyv + dzv * dzv;
+    // jslot: the neighbour's record; its cell is kxb + scx[jslot], iy + ky,
+    // iz + kz, unwrapped, counted from the target's cell
+    auto pair = [&](T xj, T yj, T zj, T qn, bool self, int jslot, int kxb, int ky, int kz) {
+      T dxv = tp.x - xj, dyv = tp.y - yj, dzv = tp.z - zj;
+      T r2 = dxv * dxv + dyv * dyv + dzv * dzv;
+      if constexpr (sizeof(T) == 4) {
+        if (r2 < near2 && valid && !self) {
+          const vec4<double> a = gld(spos64)[k], b = gld(spos64)[jslot];
+          const double sx = (double)(gld(scx)[jslot] + kxb) * h, sy = (double)ky * h, sz = (double)kz * h;
+          dxv = (T)(a.x - (b.x + sx));
+          dyv = (T)(a.y - (b.y + sy));
+          dzv = (T)(a.z - (b.z + sz));
+          r2 = dxv * dxv + dyv * dyv + dzv * dzv;
+        }
+      }
       if (r2 < rc2 && !self) {
         T ir, e, gauss;
         if constexpr (sizeof(T) == 4) {
@@ -369,14 +393,16 @@ __global__ __launch_bounds__(64) void rs_sum_kernel(RsGeom g, const int* __restr
               np.z += oz;
             }
             const int cntj = min(64, j1 - jb);
+            const int kxb = qx * c - ix;
             if (gsz == 1) {
               for (int u = 0; u < cntj; ++u)
-                pair(bcast(np.x, u), bcast(np.y, u), bcast(np.z, u), bcast(np.w, u), same && jb + u == k);
+                pair(bcast(np.x, u), bcast(np.y, u), bcast(np.z, u), bcast(np.w, u), same && jb + u == k, jb + u,
+                     kxb, dy, dz);
             } else {
               for (int u = 0; u < cntj; u += gsz) {
                 const int src = u + sub;   // <= 63: u is a multiple of gsz below 64
                 pair(__shfl(np.x, src, 64), __shfl(np.y, src, 64), __shfl(np.z, src, 64), __shfl(np.w, src, 64),
-                     same && jb + src == k);
+                     same && jb + src == k, jb + src, kxb, dy, dz);
               }
             }
           }
@@ -446,8 +472,9 @@ struct se_rs_plan {
   int ncell = 0, nscan = 0;
   // workspace (caller-owned, bound by se_rs_set_workspace): byte offsets of
   // the cell counts and starts, scan sums, per-charge cells, slots and
-  // sorted indices, per-cell energy partials and sorted records
-  size_t o_cnt = 0, o_start = 0, o_bsum = 0, o_cell = 0, o_slot = 0, o_sidx = 0, o_ep = 0, o_pos = 0;
+  // sorted indices, per-cell energy partials, sorted records and (FP32 plans)
+  // the records' FP64 positions
+  size_t o_cnt = 0, o_start = 0, o_bsum = 0, o_cell = 0, o_slot = 0, o_sidx = 0, o_ep = 0, o_pos = 0, o_pos64 = 0;
   size_t ws_bytes = 0;
   bool ws_bound = false;
   void* mem = nullptr;  // plan-owned: the device status word
@@ -457,6 +484,7 @@ struct se_rs_plan {
       *status = nullptr;
   double* epart = nullptr;
   void* spos = nullptr;
+  se::vec4<double>* spos64 = nullptr;
   size_t bytes = 0;
   // SE_PROFILE: four events per evaluation (start, pair sums start, pair
   // sums end, end), kept until se_rs_plan_profile reads them
@@ -519,7 +547,8 @@ se_status se_rs_plan_create(int D, double L, double xi, double rc, long n_max, s
   p->o_sidx = p->o_slot + up(4 * n);
   p->o_ep = p->o_sidx + up(4 * n);
   p->o_pos = p->o_ep + up(8 * nc);
-  p->ws_bytes = p->o_pos + up(rec * n);
+  p->o_pos64 = p->o_pos + up(rec * n);
+  p->ws_bytes = p->o_pos64 + (p->f64 ? 0 : up(32 * n));
   if (hipMalloc(&p->mem, 256) != hipSuccess) {
     delete p;
     return SE_ERR_NOMEM;
@@ -554,6 +583,7 @@ se_status se_rs_set_workspace(se_rs_plan* p, void* ptr, size_t bytes) {
   p->sidx = ptr ? (int*)(b + p->o_sidx) : nullptr;
   p->epart = ptr ? (double*)(b + p->o_ep) : nullptr;
   p->spos = ptr ? (void*)(b + p->o_pos) : nullptr;
+  p->spos64 = ptr && !p->f64 ? (se::vec4<double>*)(b + p->o_pos64) : nullptr;
   return SE_OK;
 }
 
@@ -626,25 +656,29 @@ se_status se_rs_eval(se_rs_plan* plan, long N, const void* xyz, const void* q, v
     auto* sp = (vec4<double>*)plan->spos;
     if (in32)
       rs_order_kernel<double, float><<<nc, kRsBlock, 0, st>>>(g, (const float*)xyz, (const float*)q, plan->start,
-                                                              plan->sidx, sp, plan->slot);
+                                                              plan->sidx, sp, plan->slot, nullptr);
     else
       rs_order_kernel<double, double><<<nc, kRsBlock, 0, st>>>(g, (const double*)xyz, (const double*)q,
-                                                               plan->start, plan->sidx, sp, plan->slot);
+                                                               plan->start, plan->sidx, sp, plan->slot, nullptr);
     mark(1);
-    if (force) rs_sum_kernel<double, true><<<nc, 64, 0, st>>>(g, plan->start, plan->sidx, sp, plan->slot, out);
-    else rs_sum_kernel<double, false><<<nc, 64, 0, st>>>(g, plan->start, plan->sidx, sp, plan->slot, out);
+    if (force)
+      rs_sum_kernel<double, true><<<nc, 64, 0, st>>>(g, plan->start, plan->sidx, sp, plan->slot, nullptr, out);
+    else
+      rs_sum_kernel<double, false><<<nc, 64, 0, st>>>(g, plan->start, plan->sidx, sp, plan->slot, nullptr, out);
     mark(2);
   } else {
     auto* sp = (vec4<float>*)plan->spos;
     if (in32)
       rs_order_kernel<float, float><<<nc, kRsBlock, 0, st>>>(g, (const float*)xyz, (const float*)q, plan->start,
-                                                             plan->sidx, sp, plan->slot);
+                                                             plan->sidx, sp, plan->slot, plan->spos64);
     else
       rs_order_kernel<float, double><<<nc, kRsBlock, 0, st>>>(g, (const double*)xyz, (const double*)q,
-                                                              plan->start, plan->sidx, sp, plan->slot);
+                                                              plan->start, plan->sidx, sp, plan->slot, plan->spos64);
     mark(1);
-    if (force) rs_sum_kernel<float, true><<<nc, 64, 0, st>>>(g, plan->start, plan->sidx, sp, plan->slot, out);
-    else rs_sum_kernel<float, false><<<nc, 64, 0, st>>>(g, plan->start, plan->sidx, sp, plan->slot, out);
+    if (force)
+      rs_sum_kernel<float, true><<<nc, 64, 0, st>>>(g, plan->start, plan->sidx, sp, plan->slot, plan->spos64, out);
+    else
+      rs_sum_kernel<float, false><<<nc, 64, 0, st>>>(g, plan->start, plan->sidx, sp, plan->slot, plan->spos64, out);
     mark(2);
   }
   if (energy) rs_energy_kernel<<<1, kRsBlock, 0, st>>>(plan->epart, nc, energy, acc ? 1 : 0);

@@ -3,7 +3,8 @@ FP64 oracle (oracle/ewald_direct.cpp), element by element:
 
   * FP64: relative rms 1e-13 in phi^R and grad phi^R, energy 1e-12 (the two sum
     the same pairs; only the order of the additions differs).
-  * FP32: relative rms 1e-5 (positions and sums rounded to FP32).
+  * FP32: relative rms 3e-6 in phi^R and grad phi^R, energy 1e-5 (records and
+    sums in FP32, the closest pairs' differences in FP64).
 
 Cutoffs are taken with xi rc = 4.8, so a pair that sits on the cutoff within
 rounding contributes below 1e-11 and cannot decide a comparison.  Cases: every
@@ -62,12 +63,13 @@ def test_parity_with_oracle(D, rc, prec):
     rs = RealSpace(D, L, xi, rc, prec=prec, n_max=N)
     phi, g, E = run(rs, x, q)
     pr, gr, Er = oracle(D, L, xi, rc, x, q)
-    tol = 1e-13 if prec == "f64" else 1e-5
+    # FP32: the largest of the 16 cases measured 9.8e-7 (phi), 9.5e-7 (grad), 2.4e-6 (energy)
+    tol_phi, tol_g, tol_e = (1e-13, 1e-12, 1e-12) if prec == "f64" else (3e-6, 3e-6, 1e-5)
     print(f"  cells {rs.cells} span {rs.span}: phi {rel(phi, pr):.2e} grad {rel(g, gr):.2e} "
           f"energy {abs(E - Er) / abs(Er):.2e}")
-    assert rel(phi, pr) < tol
-    assert rel(g, gr) < 10 * tol
-    assert abs(E - Er) <= (1e-12 if prec == "f64" else 1e-5) * abs(Er)
+    assert rel(phi, pr) < tol_phi
+    assert rel(g, gr) < tol_g
+    assert abs(E - Er) <= tol_e * abs(Er)
 
 
 @pytest.mark.parametrize("cells_per_rc", [1, 3])
@@ -222,8 +224,11 @@ def test_full_potential_madelung(D, const):
 def test_fp32_close_pairs():
     """FP32 at a dense uniform input (200 000 charges, closest pairs ~1e-4 apart):
     positions are kept relative to their cell's corner, so the pair
-    differences carry the precision of the cell side; forces against the FP64
-    path (itself checked against the oracle above) within 2e-5 rms."""
+    differences carry the precision of the cell side, and pairs closer than
+    an eighth of the cell side take their difference in FP64; forces against
+    the FP64 path (itself checked against the oracle above) within 1e-6 rms
+    (an FP32 emulation of the kernel on the CPU gives 2.6e-7; without the
+    FP64 differences it gives 4.7e-6)."""
     N, L, rc, D = 200000, 1.0, 0.06, 1
     xi = 3.2 / rc
     x, q = wl.system(N, L, 650, "normal")
@@ -233,7 +238,7 @@ def test_fp32_close_pairs():
         out[prec] = run(rs, x, q)
     e_phi, e_f = rel(out["f32"][0], out["f64"][0]), rel(out["f32"][1], out["f64"][1])
     print(f"fp32 vs fp64 real space, N={N}: phi {e_phi:.2e} grad {e_f:.2e}")
-    assert e_phi < 2e-5 and e_f < 2e-5
+    assert e_phi < 1e-5 and e_f < 1e-6
 
 
 @pytest.mark.parametrize("D", [3, 2, 1, 0])

@@ -257,12 +257,13 @@ __device__ __forceinline__ lds<vec2<T>>* fft_run(lds<vec2<T>>* b0, lds<vec2<T>>*
 }
 
 // The same stage in place: every thread first reads and transforms all its
-// butterflies (at most kFftInplaceCap / (R kFftBlock) of them, held in
-// registers), then, after a barrier, writes them back over the inputs.
+// butterflies (at most kFftIpIters(R) of them, held in registers; the
+// planner keeps (n / R) B within kFftIpIters(R) kFftBlock), then, after a
+// barrier, writes them back over the inputs.
 template <typename T, int R, bool FIRST, int SIGN>
 __device__ __forceinline__ void fft_stage_ip(lds<vec2<T>>* buf, const lds<vec2<T>>* __restrict__ tw, int n, int Ns,
                                              int tws, int lgB, int Bp) {
-  constexpr int IT = (kFftInplaceCap + R * kFftBlock - 1) / (R * kFftBlock);
+  constexpr int IT = kFftIpIters(R);
   const int nb = n / R;
   const int total = nb << lgB;
   const int mask = (1 << lgB) - 1;
@@ -384,6 +385,52 @@ __device__ __forceinline__ T scale_at(const FftClass& C, const ScaleRow<T>& r, i
       return s * gt[fold_index(t, C.fold2) * (C.gd1 * C.gd0) + r.g];
     default:
       return s;
+  }
+}
+
+// The scaling of Eq. (scale) over the samples t = t0, t0 + dt, ... of pencil
+// p in res (sample-major, pitch Bp), the same arithmetic as scale_at.  The
+// table entries of up to kScaleRound samples are loaded before any is used,
+// so a thread waits for one round of loads rather than one per sample.
+constexpr int kScaleRound = kFftInplaceCap / kFftBlock;
+
+template <typename T, int GM>
+__device__ __forceinline__ void scale_pencil(const FftClass& C, const ScaleRow<T>& row, lds<vec2<T>>* res, int p,
+                                             int t0, int dt, int n, int Bp) {
+  const T* sC = (const T*)C.sC;
+  const T* aux = GM == G_INVSQ ? (const T*)C.kC : (const T*)C.gtab;
+  for (int tb = t0; tb < n; tb += kScaleRound * dt) {
+    T a[kScaleRound], b[kScaleRound];
+#pragma unroll
+    for (int i = 0; i < kScaleRound; ++i) {
+      const int t = tb + i * dt;
+      a[i] = (T)0;
+      b[i] = (T)0;
+      if (t < n) {
+        a[i] = gld(sC)[t];
+        if constexpr (GM == G_INVSQ || GM == G_TAB1) b[i] = gld(aux)[t];
+        else if constexpr (GM == G_TAB2) b[i] = gld(aux)[fold_index(t, C.fold2) * C.gd0 + row.g];
+        else if constexpr (GM == G_TAB3) b[i] = gld(aux)[fold_index(t, C.fold2) * (C.gd1 * C.gd0) + row.g];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kScaleRound; ++i) {
+      const int t = tb + i * dt;
+      if (t < n) {
+        const T s = row.s * a[i];
+        T f;
+        if constexpr (GM == G_INVSQ) {
+          const T k2 = row.k2 + b[i];
+          f = k2 > (T)0 ? s / k2 : (T)0;
+        } else if constexpr (GM == G_NONE) {
+          f = s;
+        } else {
+          f = s * b[i];
+        }
+        const int l = __mul24(t, Bp) + p;
+        lput<T>(res, l, cscale(lget<T>(res, l), f));
+      }
+    }
   }
 }
 
@@ -631,8 +678,13 @@ __device__ __forceinline__ void stage_fft(const FftPass& P, int cls, int b0s, in
       const ScaleRow<T> row = scale_row<T>(C, b0s + p, b1);
       int t = threadIdx.x >> lgB;
       if constexpr (KIND == K_FUSED) {
-        for (int l = __mul24(t, Bp) + p; t < n; t += dt, l += dl)
-          lput<T>(res, l, cscale(lget<T>(res, l), scale_at<T>(C, row, t)));
+        switch (C.gmode) {
+          case G_INVSQ: scale_pencil<T, G_INVSQ>(C, row, res, p, t, dt, n, Bp); break;
+          case G_TAB1: scale_pencil<T, G_TAB1>(C, row, res, p, t, dt, n, Bp); break;
+          case G_TAB2: scale_pencil<T, G_TAB2>(C, row, res, p, t, dt, n, Bp); break;
+          case G_TAB3: scale_pencil<T, G_TAB3>(C, row, res, p, t, dt, n, Bp); break;
+          default: scale_pencil<T, G_NONE>(C, row, res, p, t, dt, n, Bp); break;
+        }
       } else {
         // force method 2 (Section 7.2): the scaling times i k_d; k_d is a
         // pencil constant for the A and B directions and varies along the

@@ -46,6 +46,14 @@ constexpr size_t kFftLdsSoft = 40 * 1024;
 // held in registers); passes with a larger samples cap alternate between two
 // buffers.
 constexpr int kFftInplaceCap = 2048;
+// Butterflies of radix R one thread holds in registers across an in-place
+// stage.  Radices 3, 5 and 7 hold fewer than kFftInplaceCap would need (it
+// sets the kernels' register count, hence their occupancy); the planner
+// takes fewer pencils per block for transform lengths with such a factor, so
+// that (n / R) B <= kFftIpIters(R) kFftBlock at every stage.
+constexpr int kFftIpIters(int R) {
+  return R == 5 || R == 7 ? 1 : (R == 3 ? 2 : (kFftInplaceCap + R * kFftBlock - 1) / (R * kFftBlock));
+}
 
 // Green's-function modes of the fused scaling pass (Eq. scale).
 enum GMode : int {

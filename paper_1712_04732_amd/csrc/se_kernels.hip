@@ -403,8 +403,27 @@ __device__ int build_ranges(const GridGeom& g, const EvalBuffers& b, const int* 
 }
 
 // Exclusive prefix of rpre[0..nr) in place, rpre[nr] = total; returns the
-// total.  All threads of the block call it; ends with a barrier.
+// total.  All threads of the block call it; ends with a barrier.  Up to 64
+// ranges (every tile of side <= 32 at kSB = 4) one wavefront scans them by
+// lane shuffles, so the block waits at one barrier instead of two per
+// doubling step.
 __device__ int prefix_ranges(int* rpre, int nr) {
+  if (nr <= 64) {
+    if (threadIdx.x < 64) {
+      const int lane = threadIdx.x;
+      const int c = lane < nr ? rpre[lane] : 0;
+      int v = c;   // inclusive prefix; lanes at and past nr add 0, so lane 63 holds the total
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int w = __shfl_up(v, o, 64);
+        if (lane >= o) v += w;
+      }
+      if (lane < nr) rpre[lane] = v - c;
+      if (lane == 63) rpre[nr] = v;
+    }
+    __syncthreads();
+    return rpre[nr];
+  }
   __shared__ int part[kMaxBlock];
   const int per = (nr + blockDim.x - 1) / blockDim.x;
   const int lo = min(nr, (int)threadIdx.x * per), hi = min(nr, lo + per);
@@ -461,6 +480,28 @@ struct Lanes {
   static constexpr int G2 = P <= 2 ? 2 : (P <= 4 ? 4 : (P <= 8 ? 8 : 16));
   static constexpr int PPW = 64 / G2;
 };
+
+// Gathering serves one particle with P lanes (one per stencil plane), so a
+// wavefront takes floor(64 / P) particles; a power-of-two group would leave
+// next_pow2(P) - P lanes of every group idle (6 of 16 at P = 10).
+template <int P>
+struct GatherLanes {
+  static constexpr int G = P < 2 ? 2 : P;
+  static constexpr int PPW = 64 / G;
+};
+
+// Sum over the G consecutive lanes of a group (lane iz of the group); the
+// result is complete at iz = 0.  Step o adds lane iz + o, which holds the
+// sum of lanes iz + o .. iz + 2o - 1 of the group, when it lies in the group.
+template <int G, typename T>
+__device__ __forceinline__ T segment_sum(T v, int iz) {
+#pragma unroll
+  for (int o = 1; o < G; o <<= 1) {
+    const T w = __shfl_down(v, o, 64);
+    if (iz + o < G) v += w;
+  }
+  return v;
+}
 
 // Row i of the PKB coefficient table (values or derivatives) in registers.
 template <typename T>
@@ -1125,17 +1166,16 @@ hipError_t launch_fold(const GridGeom& g, const EvalBuffers& b, bool f64, hipStr
 // Gathering, trapezoidal rule of Eq. (complete_integral), and the gradient of
 // Eq. (force-method-1).  One workgroup per tile stages the tile's stencil
 // region of the grid in LDS and takes the particles anchored in the tile.
-// A group of G2 = next_pow2(P) lanes serves one particle; lane iz owns the
-// z-plane iz of the stencil, evaluates row iz of the three weight vectors,
-// contracts its plane separably (x, then y) and the group sums the planes
-// with shuffles.
+// A group of P lanes serves one particle; lane iz owns the z-plane iz of the
+// stencil, evaluates row iz of the three weight vectors, contracts its plane
+// separably (x, then y) and the group sums the planes with shuffles.
 // ---------------------------------------------------------------------------
 template <typename T, int P, int MODE = GM_ALL>
 __device__ __forceinline__ void stage_gather(const GridGeom& g, const EvalBuffers& b, T* __restrict__ phi,
                              T* __restrict__ force, int out_grad, double self_coef, int item,
                              unsigned char* smem, int comp = 0) {
   constexpr bool GRAD = MODE == GM_ALL;
-  constexpr int G2 = Lanes<P>::G2, PPW = Lanes<P>::PPW;
+  constexpr int G2 = GatherLanes<P>::G, PPW = GatherLanes<P>::PPW;
   const int TX = g.T[0], TY = g.T[1], TZ = g.T[2];
   const int t_id = item;
   const int tz = t_id / (g.nt[0] * g.nt[1]);
@@ -1286,7 +1326,7 @@ __device__ __forceinline__ void stage_gather(const GridGeom& g, const EvalBuffer
     const int nb = min(kGatherBatch, total - b0);
     for (int base = wave * PPW; base < nb; base += nwaves * PPW) {
       const int k = base + p;
-      const bool valid = k < nb;
+      const bool valid = p < PPW && k < nb;   // lanes past PPW G2 serve no particle
       const Quad<T> f = valid ? rq[k] : Quad<T>{0, 0, 0, 0};
       const int pc = valid ? rc[k] : 0;
       const int lx = (pc & 1023) - x0, ly = ((pc >> 10) & 1023) - y0, lz = ((pc >> 20) & 1023) - z0;
@@ -1335,11 +1375,11 @@ __device__ __forceinline__ void stage_gather(const GridGeom& g, const EvalBuffer
         gy = wz * s01;
         gz = dwz * s00;
       }
-      ph = group_sum<G2>(ph);
+      ph = segment_sum<G2>(ph, iz);
       if constexpr (GRAD) {
-        gx = group_sum<G2>(gx);
-        gy = group_sum<G2>(gy);
-        gz = group_sum<G2>(gz);
+        gx = segment_sum<G2>(gx, iz);
+        gy = segment_sum<G2>(gy, iz);
+        gz = segment_sum<G2>(gz, iz);
       }
       if (valid && iz == 0) {
         const int idx = ri[k];
@@ -1387,10 +1427,10 @@ __global__ __launch_bounds__(kGatherBlock) void gather_kernel(GridGeom g, EvalBu
 template <typename T>
 size_t gather_lds(const GridGeom& g) {
   const int P = g.P, m = g.nu + 1, nw = kGatherBlock / 64;
-  const int G2 = P <= 2 ? 2 : (P <= 4 ? 4 : (P <= 8 ? 8 : 16));
+  const int G = P < 2 ? 2 : P;   // GatherLanes<P>::G
   const size_t R = (size_t)(g.T[0] + P - 1) * (g.T[1] + P - 1) * (g.T[2] + P - 1);
   (void)m;
-  return sizeof(T) * (R + (size_t)nw * (64 / G2) * 4 * P + 4 * kGatherBatch) +
+  return sizeof(T) * (R + (size_t)nw * (64 / G) * 4 * P + 4 * kGatherBatch) +
          sizeof(int) * (2 * kMaxOwnRanges + 4 + 2 * kGatherBatch) + 64;
 }
 

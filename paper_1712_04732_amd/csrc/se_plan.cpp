@@ -431,10 +431,22 @@ static bool finish_pass(se_plan* pl, se::FftPass& ps, int kind, int ncls,
   // in place unless the samples cap (or a single pencil) exceeds kFftInplaceCap
   ps.inplace = (cap <= se::kFftInplaceCap && ps.nmax <= se::kFftInplaceCap) ? 1 : 0;
   auto lds_of = [&](long B2) { return esz * (size_t)ps.nmax * (1 + (ps.inplace ? 1 : 2) * (B2 + 1)); };
+  // in place, every stage of every class keeps its butterflies within the
+  // registers the kernel holds for them (kFftIpIters)
+  auto fits_regs = [&](long B2) {
+    if (!ps.inplace) return true;
+    for (int c = 0; c < ncls; ++c)
+      for (int k = 0; k < ps.cls[c].nst; ++k) {
+        const int R = ps.cls[c].rad[k];
+        if ((long)(ps.cls[c].n / R) * B2 > (long)se::kFftIpIters(R) * se::kFftBlock) return false;
+      }
+    return true;
+  };
+  if (!fits_regs(1)) ps.inplace = 0;   // a single pencil needs more: alternate two buffers
   int lgB = 0;
   while (lgB < 6) {
     const long B2 = 2L << lgB;
-    if ((long)ps.nmax * B2 > cap || lds_of(B2) > std::min(pl->lds_limit, se::kFftLdsSoft)) break;
+    if ((long)ps.nmax * B2 > cap || lds_of(B2) > std::min(pl->lds_limit, se::kFftLdsSoft) || !fits_regs(B2)) break;
     ++lgB;
   }
   if (lds_of(1L << lgB) > pl->lds_max) return false;

@@ -542,6 +542,77 @@ def _rs_traffic(workload):
     return None
 
 
+# Kernels whose HBM counters become traffic.json entries: the FP32 C5 batch
+# stages (one launch per evaluation each; the transform kinds map one to one
+# onto the five transform stages of the batch) and the FP32 real-space pairs.
+TRAFFIC_KERNELS = {
+    "batch_stage_kernel<float, 10, 6>": ("spread", "C5_batch", "spreading (column mode)"),
+    "batch_fft_kernel<float, 2, unsigned int>": ("fft0", "C5_batch", "R2C transforms"),
+    "batch_fft_kernel<float, 0, unsigned int>": ("fft1", "C5_batch", "forward C2C transforms"),
+    "batch_fft_kernel<float, 4, unsigned int>": ("fft2", "C5_batch",
+                                                 "fused forward transform, scaling, inverse transform"),
+    "batch_fft_kernel<float, 1, unsigned int>": ("fft3", "C5_batch", "inverse C2C transforms"),
+    "batch_fft_kernel<float, 3, unsigned int>": ("fft4", "C5_batch", "C2R transforms"),
+    "batch_stage_kernel<float, 10, 13>": ("gather", "C5_batch", "gathering"),
+    "rs_sum_kernel<float, true>": ("rs_pairs", "C4_1P", "real-space pair sums"),
+}
+
+
+def _pmc_means(path, counter):
+    """Mean value per dispatch of one rocprofv3 --pmc counter (KiB) by kernel
+    name, from its counter_collection CSV."""
+    import csv
+    sums, cnt = {}, {}
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            if row["Counter_Name"] != counter:
+                continue
+            k = row["Kernel_Name"]
+            for short in TRAFFIC_KERNELS:
+                if short in k:
+                    k = short
+                    break
+            else:
+                if "copyBuffer" not in k:
+                    continue
+            sums[k] = sums.get(k, 0.0) + float(row["Counter_Value"])
+            cnt[k] = cnt.get(k, 0) + 1
+    return {k: sums[k] / cnt[k] for k in sums}
+
+
+def main_traffic_from(paths):
+    """profiles/traffic.json from four rocprofv3 --pmc runs (counter CSVs):
+    FETCH_SIZE and WRITE_SIZE of a workload run, and of --copy-calibration
+    (256 MiB read and written per copy), which scales each counter to bytes.
+    Entries carry the hash of the kernel sources they were taken on; the
+    bench reports them only while that hash matches."""
+    fetch, write, cfetch, cwrite = (_pmc_means(pth, c) for pth, c in
+                                    zip(paths, ("FETCH_SIZE", "WRITE_SIZE", "FETCH_SIZE", "WRITE_SIZE")))
+    copy_kib = (64 << 20) * 4 / 1024   # KiB read (and written) per copy of --copy-calibration
+    ck = [k for k in cfetch if "copyBuffer" in k]
+    if not ck or not [k for k in cwrite if "copyBuffer" in k]:
+        raise SystemExit("no copy kernel in the calibration counters")
+    fs = copy_kib / cfetch[ck[0]]
+    ws = copy_kib / cwrite[[k for k in cwrite if "copyBuffer" in k][0]]
+    tpath = os.path.join(ROOT, "profiles", "traffic.json")
+    out = json.load(open(tpath)) if os.path.exists(tpath) else {}
+    for k, (stage, workload, what) in TRAFFIC_KERNELS.items():
+        if k not in fetch or k not in write:
+            continue
+        sha = _source_sha(RS_SOURCES) if stage == "rs_pairs" else _source_sha()
+        ent = {"kernel": f"{k} ({what})", "workload": workload, "fetch_bytes": fetch[k] * 1024 * fs,
+               "write_bytes": write[k] * 1024 * ws, "fetch_scale": fs, "write_scale": ws, "source_sha": sha}
+        if workload == "C5_batch":
+            ent["P"] = 10
+        ent["bytes_per_launch"] = ent["fetch_bytes"] + ent["write_bytes"]
+        out[stage] = ent
+        print(f"{stage:8s} fetch {ent['fetch_bytes'] / 1e9:.3f} GB write {ent['write_bytes'] / 1e9:.3f} GB "
+              f"per launch ({k})", flush=True)
+    with open(tpath, "w") as f:
+        json.dump(out, f, indent=1)
+    print(f"copy calibration: FETCH_SIZE scale {fs:.3f}, WRITE_SIZE scale {ws:.3f}; wrote {tpath}", flush=True)
+
+
 def main_real_space(args):
     """The real-space part (Eq. real_space_ewald) on the GPU for one of the
     single-system workloads, at the cutoff of Eq. (KP_real_space) for the same
@@ -735,9 +806,15 @@ def main():
                     help="force method 1 vs method 2 against P on the paper's 3P workload (Section 7.2)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device 5 times (reference for HBM byte counters)")
+    ap.add_argument("--traffic-from", nargs=4, default=None,
+                    metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="write profiles/traffic.json from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE "
+                         "counter CSVs of a bench run and of --copy-calibration (no GPU needed)")
     args = ap.parse_args()
     if args.cpu_oracle_sample is not None:
         return _cpu_oracle_sample(args.cpu_oracle_sample)
+    if args.traffic_from:
+        return main_traffic_from(args.traffic_from)
     if args.copy_calibration:
         import torch
         a = torch.empty(64 << 20, dtype=torch.float32, device="cuda:0").fill_(1.0)

@@ -12,10 +12,10 @@
 // target's cell (periodic directions wrap with an image shift, free
 // directions stop at the box).  Cells whose nearest points are rc or more
 // apart are skipped.  One wavefront serves one cell: its lanes hold the
-// cell's targets (several lanes per target when the cell is small), each
-// neighbour chunk of 64 charges is loaded one per lane and handed to the
-// other lanes by readlane or lane permutes, so the pair loop has no memory
-// traffic and no LDS.  Charges are ordered by cell, and inside a cell by
+// cell's targets (several lanes per target when the cell is small); each
+// neighbour chunk of 64 charges is loaded one per lane, the charges within rc
+// of the target cell's box are packed into LDS, and every lane reads them
+// back from there in the pair loop.  Charges are ordered by cell, and inside a cell by
 // input index, so the sums are reproducible run to run.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -46,6 +46,13 @@ struct RsGeom {
 };
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// LDS writes of a wavefront made visible to its other lanes.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // Wrap a periodic coordinate into [0, L).
 __device__ __forceinline__ double wrap_periodic(double x, double L, double invL) {
@@ -231,18 +238,6 @@ __global__ __launch_bounds__(kRsBlock) void rs_order_kernel(RsGeom g, const Tin*
   }
 }
 
-template <typename T>
-__device__ __forceinline__ T bcast(T v, int lane) {
-  if constexpr (sizeof(T) == 4) {
-    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
-  } else {
-    const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-    return __builtin_bit_cast(T, ((long long)hi << 32) | (unsigned)lo);
-  }
-}
-
 // FP64 pairs use the device library's erfc, exp and sqrt.
 __device__ __forceinline__ double erfc_t(double x) { return erfc(x); }
 __device__ __forceinline__ double exp_t(double x) { return exp(x); }
@@ -287,7 +282,10 @@ __device__ __forceinline__ int floor_div(int a, int c) { return a >= 0 ? a / c :
 // g-th one) and add their partial sums at the end.  Neighbours are visited by
 // rows: for each (dy, dz) the cells ix - d .. ix + d that can hold a charge
 // within rc (d from the row's gaps) are consecutive in the cell order, so
-// their charges form one contiguous range per periodic image of x.
+// their charges form one contiguous range per periodic image of x.  Of each
+// chunk of 64 charges of a range only those within rc of the target cell's
+// box (about two in three at two cells per cutoff) enter the pair loop,
+// packed in chunk order.
 //
 // FP32 records round each position to a few units in the last place of the
 // cell side, which is large against the difference of the closest pairs
@@ -311,8 +309,11 @@ __global__ __launch_bounds__(64) void rs_sum_kernel(RsGeom g, const int* __restr
   const T c2 = (T)(2.0 * g.xi / 1.7724538509055160272981674833411452);
   const double h = g.h, rc2d = g.rc * g.rc;
   const T hT = (T)g.h;
-  const T far = (T)(4.0 * g.L + 4.0 * g.rc + 1.0);   // padding charge, out of range of every target
-  const T near2 = (T)(g.h * g.h / 64.0);               // (h/8)^2: FP64 differences below it (FP32 records)
+  const T near2 = (T)(g.h * g.h / 64.0);   // (h/8)^2: FP64 differences below it (FP32 records)
+  // rc^2 with a margin for the rounding of records near the cell's faces
+  const T box2 = (T)((g.rc * (1.0 + 1e-5) + 1e-5 * g.h) * (g.rc * (1.0 + 1e-5) + 1e-5 * g.h));
+  __shared__ vec4<T> crec[64];   // kept records of the current chunk
+  __shared__ int cslot[64];      // and their record slots
   double e_acc = 0.0;
   for (int tb = t0; tb < t1; tb += per) {
     const int k = tb + tl;
@@ -324,17 +325,17 @@ __global__ __launch_bounds__(64) void rs_sum_kernel(RsGeom g, const int* __restr
     auto pair = [&](T xj, T yj, T zj, T qn, bool self, int jslot, int kxb, int ky, int kz) {
       T dxv = tp.x - xj, dyv = tp.y - yj, dzv = tp.z - zj;
       T r2 = dxv * dxv + dyv * dyv + dzv * dzv;
-      if constexpr (sizeof(T) == 4) {
-        if (r2 < near2 && valid && !self) {
-          const vec4<double> a = gld(spos64)[k], b = gld(spos64)[jslot];
-          const double sx = (double)(gld(scx)[jslot] + kxb) * h, sy = (double)ky * h, sz = (double)kz * h;
-          dxv = (T)(a.x - (b.x + sx));
-          dyv = (T)(a.y - (b.y + sy));
-          dzv = (T)(a.z - (b.z + sz));
-          r2 = dxv * dxv + dyv * dyv + dzv * dzv;
-        }
-      }
       if (r2 < rc2 && !self) {
+        if constexpr (sizeof(T) == 4) {
+          if (r2 < near2 && valid) {
+            const vec4<double> a = gld(spos64)[k], b = gld(spos64)[jslot];
+            const double sx = (double)(gld(scx)[jslot] + kxb) * h, sy = (double)ky * h, sz = (double)kz * h;
+            dxv = (T)(a.x - (b.x + sx));
+            dyv = (T)(a.y - (b.y + sy));
+            dzv = (T)(a.z - (b.z + sz));
+            r2 = dxv * dxv + dyv * dyv + dzv * dzv;
+          }
+        }
         T ir, e, gauss;
         if constexpr (sizeof(T) == 4) {
           ir = __builtin_amdgcn_rsqf(r2);
@@ -383,28 +384,41 @@ __global__ __launch_bounds__(64) void rs_sum_kernel(RsGeom g, const int* __restr
           // neighbour positions relative to the target cell's corner: the
           // neighbour's unwrapped cell is (cx + qx c, iy + dy, iz + dz)
           const T oy = (T)dy * hT, oz = (T)dz * hT;
+          const int kxb = qx * c - ix;
           for (int jb = j0; jb < j1; jb += 64) {
+            // one record per lane, moved to the target cell's frame; only the
+            // records within rc of the cell's box [0, h)^3 can meet a target
             const int jn = jb + lane;
-            vec4<T> np = vec4<T>{far, far, far, (T)0};
+            bool keep = false;
+            vec4<T> np;
             if (jn < j1) {
               np = gld(spos)[jn];
-              np.x += (T)(gld(scx)[jn] + qx * c - ix) * hT;
+              np.x += (T)(gld(scx)[jn] + kxb) * hT;
               np.y += oy;
               np.z += oz;
+              const T ex = max(max(-np.x, np.x - hT), (T)0), ey = max(max(-np.y, np.y - hT), (T)0),
+                      ez = max(max(-np.z, np.z - hT), (T)0);
+              keep = ex * ex + ey * ey + ez * ez < box2;
             }
-            const int cntj = min(64, j1 - jb);
-            const int kxb = qx * c - ix;
-            if (gsz == 1) {
-              for (int u = 0; u < cntj; ++u)
-                pair(bcast(np.x, u), bcast(np.y, u), bcast(np.z, u), bcast(np.w, u), same && jb + u == k, jb + u,
-                     kxb, dy, dz);
-            } else {
-              for (int u = 0; u < cntj; u += gsz) {
-                const int src = u + sub;   // <= 63: u is a multiple of gsz below 64
-                pair(__shfl(np.x, src, 64), __shfl(np.y, src, 64), __shfl(np.z, src, 64), __shfl(np.w, src, 64),
-                     same && jb + src == k, jb + src, kxb, dy, dz);
+            // kept records packed in chunk order into LDS, read back by every lane
+            const unsigned long long m = __ballot(keep);
+            const int cnt = __popcll(m);
+            if (cnt == 0) continue;
+            if (keep) {
+              const int at = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0));
+              crec[at] = np;
+              cslot[at] = jn;
+            }
+            wave_sync();
+            for (int u0 = 0; u0 < cnt; u0 += gsz) {
+              const int u = u0 + sub;
+              if (u < cnt) {
+                const vec4<T> r = crec[u];
+                const int js = cslot[u];
+                pair(r.x, r.y, r.z, r.w, same && js == k, js, kxb, dy, dz);
               }
             }
+            wave_sync();   // before the next chunk overwrites crec
           }
         }
       }

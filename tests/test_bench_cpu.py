@@ -109,3 +109,39 @@ def test_real_space_traffic_only_for_matching_sources_and_workload():
     else:
         assert bench._rs_traffic(ent["workload"]) is None
     assert bench._rs_traffic("no such workload") is None
+
+
+def _pmc_csv(path, counter, rows):
+    hdr = ("Correlation_Id,Dispatch_Id,Agent_Id,Queue_Id,Process_Id,Thread_Id,Grid_Size,Kernel_Id,Kernel_Name,"
+           "Workgroup_Size,LDS_Block_Size,Scratch_Size,VGPR_Count,Accum_VGPR_Count,SGPR_Count,Counter_Name,"
+           "Counter_Value,Start_Timestamp,End_Timestamp")
+    with open(path, "w") as f:
+        f.write(hdr + "\n")
+        for i, (k, v) in enumerate(rows):
+            f.write(f'{i},{i},"Agent 1",1,1,1,256,{i},"{k}",256,0,0,8,0,32,"{counter}",{v},0,1\n')
+
+
+def test_traffic_from_counter_csvs(tmp_path, monkeypatch):
+    """--traffic-from: per-launch means of FETCH_SIZE and WRITE_SIZE (KiB) by
+    kernel, scaled so that the calibration copy reads and writes 256 MiB;
+    other kernels and the FP64 instances are ignored."""
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "_source_sha", lambda files=None: "abc")
+    k = "void se::batch_fft_kernel<float, 4, unsigned int>(se::SysDesc const*, int)"
+    k64 = "void se::batch_fft_kernel<double, 4, unsigned int>(se::SysDesc const*, int)"
+    g = "void se::batch_stage_kernel<float, 10, 13>(se::SysDesc const*, int)"
+    _pmc_csv(tmp_path / "f.csv", "FETCH_SIZE", [(k, 1000.0), (k, 3000.0), (k64, 9e9), (g, 500.0), ("other", 1.0)])
+    _pmc_csv(tmp_path / "w.csv", "WRITE_SIZE", [(k, 4000.0), (k, 4000.0), (g, 50.0)])
+    _pmc_csv(tmp_path / "cf.csv", "FETCH_SIZE", [("__amd_rocclr_copyBuffer", 131072.0)] * 5)
+    _pmc_csv(tmp_path / "cw.csv", "WRITE_SIZE", [("__amd_rocclr_copyBuffer", 262144.0)] * 5)
+    bench.main_traffic_from([str(tmp_path / n) for n in ("f.csv", "w.csv", "cf.csv", "cw.csv")])
+    out = json.load(open(prof / "traffic.json"))
+    assert set(out) == {"fft2", "gather"}
+    e = out["fft2"]
+    assert e["fetch_scale"] == pytest.approx(2.0) and e["write_scale"] == pytest.approx(1.0)
+    assert e["fetch_bytes"] == pytest.approx(2000.0 * 1024 * 2.0)
+    assert e["write_bytes"] == pytest.approx(4000.0 * 1024)
+    assert e["bytes_per_launch"] == pytest.approx(e["fetch_bytes"] + e["write_bytes"])
+    assert e["source_sha"] == "abc" and e["P"] == 10 and e["workload"] == "C5_batch"

@@ -351,7 +351,8 @@ def rs_candidates(D, c, s, L, rc, cells, t):
 def test_real_space_enumeration_visits_each_pair_once(D, rc_over_L):
     """Every pair within rc (periodic images included, the target itself at
     zero shift excluded) is visited exactly once, for spans s = 1-3 and
-    cutoffs beyond the box."""
+    cutoffs beyond the box, also after the kernel drops the candidates that
+    lie rc or more from the target cell's box."""
     rng = np.random.default_rng(int(100 * rc_over_L) + D)
     L, n = 1.0, 90
     x = rng.random((n, 3)) * L
@@ -366,8 +367,13 @@ def test_real_space_enumeration_visits_each_pair_once(D, rc_over_L):
             cand = rs_candidates(D, c, s, L, rc, [tuple(v) for v in cells], t)
             assert len(cand) == len(set(cand))
             got = set()
+            box2 = (rc * (1.0 + 1e-5) + 1e-5 * h) ** 2
             for j, (qx, qy, qz) in cand:
                 shift = np.array([qx, qy, qz]) * L
+                p = x[j] + shift - cells[t] * h   # in the target cell's frame
+                e = np.maximum(np.maximum(-p, p - h), 0.0)
+                if float(e @ e) >= box2:
+                    continue
                 if np.linalg.norm(x[t] - (x[j] + shift)) < rc:
                     got.add((j, (qx, qy, qz)))
             want = set()

@@ -860,6 +860,10 @@ __device__ __forceinline__ void stage_spread_cols(const GridGeom& g, const EvalB
   int* rsh = rpre + kMaxClipRanges + 4;                       // kMaxClipRanges
   int* org = rsh + kMaxClipRanges;                            // kColBatch packed origins
   T* wb = reinterpret_cast<T*>(org + kColBatch);              // kColBatch records of SW weights
+  constexpr int WBN = kColBatch * SW > kBlock * kColZ ? kColBatch * SW : kBlock * kColZ;
+  Quad<T>* pq = reinterpret_cast<Quad<T>*>(wb + WBN);          // kColBatch particle records
+  int* ppc = reinterpret_cast<int*>(pq + kColBatch);           // their packed cells
+  int* pcd = ppc + kColBatch;                                  // and image-shift codes
   __shared__ int pc_s0[3][kMaxPieces], pc_s1[3][kMaxPieces], pc_sh[3][kMaxPieces], pc_n[3];
 
   if (threadIdx.x < 3) {
@@ -908,12 +912,21 @@ __device__ __forceinline__ void stage_spread_cols(const GridGeom& g, const EvalB
   for (int v0 = 0; v0 < total; v0 += kColBatch) {
     const int nb = min(kColBatch, total - v0);
     if (v0 > 0) __syncthreads();   // the previous batch has been consumed
-    for (int k = pv; k < nb; k += per_pass) {
+    // the batch's particle records, at most one per thread, in one round of
+    // loads (the weight loop below would otherwise wait for a load per pass)
+    static_assert(kColBatch <= kBlock, "one record per thread");
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) {
       const int e = v0 + k;
       const int r = find_range(rpre, nr, e);
       const int i = rstart[r] + (e - rpre[r]);
-      const Quad<T> f = ld_quad<T>(b.s_fq, i);
-      const int pc = gld(b.s_cell)[i], code = rsh[r];
+      pq[k] = ld_quad<T>(b.s_fq, i);
+      ppc[k] = gld(b.s_cell)[i];
+      pcd[k] = rsh[r];
+    }
+    __syncthreads();
+    for (int k = pv; k < nb; k += per_pass) {
+      const Quad<T> f = pq[k];
+      const int pc = ppc[k], code = pcd[k];
       // stencil origin c + shift - P/2 + 1 in tile coordinates, each in [-P+1, T)
       const int ox = (pc & 1023) + pc_sh[0][code >> 8] - P / 2 + 1 - x0;
       const int oy = ((pc >> 10) & 1023) + pc_sh[1][(code >> 4) & 15] - P / 2 + 1 - y0;
@@ -1111,7 +1124,8 @@ size_t spread_lds(const GridGeom& g) {
   if (g.clip == 2) {
     const size_t sw = (size_t)(kColZ + 2 * P + 2 + 3) / 4 * 4;   // ColLayout::SW
     return sizeof(int) * (3 * kMaxClipRanges + 4 + kColBatch) +
-           sizeof(T) * (kColBatch * sw > (size_t)kBlock * kColZ ? kColBatch * sw : (size_t)kBlock * kColZ) + 64;
+           sizeof(T) * (kColBatch * sw > (size_t)kBlock * kColZ ? kColBatch * sw : (size_t)kBlock * kColZ) +
+           kColBatch * (4 * sizeof(T) + 2 * sizeof(int)) + 64;
   }
   if (g.clip) {
     const size_t T3 = (size_t)g.T[0] * g.T[1] * g.T[2];

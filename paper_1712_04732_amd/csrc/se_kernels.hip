@@ -483,11 +483,13 @@ struct Lanes {
 
 // Gathering serves one particle with P lanes (one per stencil plane), so a
 // wavefront takes floor(64 / P) particles; a power-of-two group would leave
-// next_pow2(P) - P lanes of every group idle (6 of 16 at P = 10).
-template <int P>
+// next_pow2(P) - P lanes of every group idle (6 of 16 at P = 10).  FP64
+// takes at most 4 particles per wavefront, which keeps the weight rows of
+// 8^3 tiles within the LDS budget.
+template <int P, typename T>
 struct GatherLanes {
   static constexpr int G = P < 2 ? 2 : P;
-  static constexpr int PPW = 64 / G;
+  static constexpr int PPW = sizeof(T) == 8 && 64 / G > 4 ? 4 : 64 / G;
 };
 
 // Sum over the G consecutive lanes of a group (lane iz of the group); the
@@ -1189,7 +1191,7 @@ __device__ __forceinline__ void stage_gather(const GridGeom& g, const EvalBuffer
                              T* __restrict__ force, int out_grad, double self_coef, int item,
                              unsigned char* smem, int comp = 0) {
   constexpr bool GRAD = MODE == GM_ALL;
-  constexpr int G2 = GatherLanes<P>::G, PPW = GatherLanes<P>::PPW;
+  constexpr int G2 = GatherLanes<P, T>::G, PPW = GatherLanes<P, T>::PPW;
   const int TX = g.T[0], TY = g.T[1], TZ = g.T[2];
   const int t_id = item;
   const int tz = t_id / (g.nt[0] * g.nt[1]);
@@ -1441,10 +1443,11 @@ __global__ __launch_bounds__(kGatherBlock) void gather_kernel(GridGeom g, EvalBu
 template <typename T>
 size_t gather_lds(const GridGeom& g) {
   const int P = g.P, m = g.nu + 1, nw = kGatherBlock / 64;
-  const int G = P < 2 ? 2 : P;   // GatherLanes<P>::G
+  const int G = P < 2 ? 2 : P;   // GatherLanes<P, T>
+  const int ppw = sizeof(T) == 8 && 64 / G > 4 ? 4 : 64 / G;
   const size_t R = (size_t)(g.T[0] + P - 1) * (g.T[1] + P - 1) * (g.T[2] + P - 1);
   (void)m;
-  return sizeof(T) * (R + (size_t)nw * (64 / G) * 4 * P + 4 * kGatherBatch) +
+  return sizeof(T) * (R + (size_t)nw * ppw * 4 * P + 4 * kGatherBatch) +
          sizeof(int) * (2 * kMaxOwnRanges + 4 + 2 * kGatherBatch) + 64;
 }
 

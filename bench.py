@@ -477,7 +477,9 @@ def single_systems(args, names=("C1_3P", "C2_0P", "C3_2P", "C4_1P")):
             kw.update(Q=Q, tol=1e-6 * _lib.se_error_scale(Q, xi, L))
         x64 = torch.tensor(x, device=dev)
         q64 = torch.tensor(q, device=dev)
-        row = {"workload": name, "D": D, "N": N, "M": M, "P": P, "window": win, "xi": xi}
+        row = {"workload": name, "D": D, "N": N, "M": M, "P": P, "window": win, "xi": xi,
+               "config": {"workload": name, "D": D, "N": N, "L": L, "M": M, "P": P, "window": win, "xi": xi,
+                          "charges": cfg["charges"], "outputs": "potential+force+energy"}}
         res = {}
         for prec in ("f32", "f64"):
             plan = SpectralEwald(D, L, xi, M, P, prec=prec, **kw)

@@ -349,6 +349,103 @@ int oracle_coulomb_free(long N, const double* x, const double* q, long T, const 
   return 0;
 }
 
+// Triply periodic rectangular box with sides Ls[0..2]: the periodic lattice
+// of Section 2 with a side per direction (the paper's remark that the domain
+// need not be a cube).  Real space, Eq. (real_space_ewald): images
+// (a Ls[0], b Ls[1], c Ls[2]) within rc, the n == m term at p = 0 excluded.
+int oracle_real_space_box3(const double* Ls, double xi, double rc, long N, const double* x, const double* q,
+                           long T, const long* tgt, double* phi, double* grad) {
+  if (!Ls || Ls[0] <= 0 || Ls[1] <= 0 || Ls[2] <= 0 || xi <= 0 || rc <= 0) return 1;
+  int ni[3];
+  for (int d = 0; d < 3; ++d) ni[d] = (int)std::ceil(rc / Ls[d]) + 1;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (long t = 0; t < T; ++t) {
+    const long m = tgt[t];
+    double s = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    for (long n = 0; n < N; ++n)
+      for (int a = -ni[0]; a <= ni[0]; ++a)
+        for (int b = -ni[1]; b <= ni[1]; ++b)
+          for (int c = -ni[2]; c <= ni[2]; ++c) {
+            if (n == m && a == 0 && b == 0 && c == 0) continue;
+            const double dx = x[3 * m] - x[3 * n] + a * Ls[0];
+            const double dy = x[3 * m + 1] - x[3 * n + 1] + b * Ls[1];
+            const double dz = x[3 * m + 2] - x[3 * n + 2] + c * Ls[2];
+            const double r = std::sqrt(dx * dx + dy * dy + dz * dz);
+            if (r >= rc) continue;
+            const double e = std::erfc(xi * r) / r;
+            s += q[n] * e;
+            const double dr = -e / r - 2.0 * xi / std::sqrt(kPi) * std::exp(-xi * xi * r * r) / r;
+            gx += q[n] * dr * dx / r;
+            gy += q[n] * dr * dy / r;
+            gz += q[n] * dr * dz / r;
+          }
+    phi[t] = s;
+    if (grad) {
+      grad[3 * t] = gx;
+      grad[3 * t + 1] = gy;
+      grad[3 * t + 2] = gz;
+    }
+  }
+  return 0;
+}
+
+// Fourier-space part of the rectangular triply periodic box, Eq.
+// (fourier_space_explicit_3P) with the box volume V = Ls[0] Ls[1] Ls[2] in
+// place of L^3 and k = 2 pi (n1/Ls[0], n2/Ls[1], n3/Ls[2]), |n_d| <= nmax[d]:
+//   (4 pi / V) sum_{k != 0} e^{-k^2/4xi^2}/k^2 Re(S(k) e^{i k.x_m}),
+// S(k) = sum_n q_n e^{-i k.x_n}; the k = 0 term is dropped as in the cube.
+int oracle_kspace_box3(const double* Ls, double xi, const int* nmax, long N, const double* x, const double* q,
+                       long T, const long* tgt, double* phi, double* grad) {
+  if (!Ls || !nmax || Ls[0] <= 0 || Ls[1] <= 0 || Ls[2] <= 0 || xi <= 0) return 1;
+  if (nmax[0] < 0 || nmax[1] < 0 || nmax[2] < 0) return 1;
+  const int sx = 2 * nmax[0] + 1, sy = 2 * nmax[1] + 1, sz = 2 * nmax[2] + 1;
+  const long nmodes = (long)sx * sy * sz;
+  std::vector<double> acc(4 * (size_t)T, 0.0);
+#pragma omp parallel
+  {
+    std::vector<double> loc(4 * (size_t)T, 0.0);
+#pragma omp for schedule(dynamic, 16)
+    for (long mode = 0; mode < nmodes; ++mode) {
+      const int a = (int)(mode / ((long)sy * sz)) - nmax[0];
+      const int b = (int)((mode / sz) % sy) - nmax[1];
+      const int c = (int)(mode % sz) - nmax[2];
+      if (a == 0 && b == 0 && c == 0) continue;
+      const double kx = 2.0 * kPi * a / Ls[0], ky = 2.0 * kPi * b / Ls[1], kz = 2.0 * kPi * c / Ls[2];
+      const double k2 = kx * kx + ky * ky + kz * kz;
+      const double f = std::exp(-k2 / (4.0 * xi * xi)) / k2;
+      if (f == 0.0) continue;
+      double sre = 0.0, sim = 0.0;
+      for (long n = 0; n < N; ++n) {
+        const double ph = kx * x[3 * n] + ky * x[3 * n + 1] + kz * x[3 * n + 2];
+        sre += q[n] * std::cos(ph);
+        sim -= q[n] * std::sin(ph);
+      }
+      for (long t = 0; t < T; ++t) {
+        const long m = tgt[t];
+        const double ph = kx * x[3 * m] + ky * x[3 * m + 1] + kz * x[3 * m + 2];
+        const double cr = std::cos(ph), ci = std::sin(ph);
+        const double re = sre * cr - sim * ci, im = sre * ci + sim * cr;
+        loc[4 * t] += f * re;
+        loc[4 * t + 1] -= f * kx * im;
+        loc[4 * t + 2] -= f * ky * im;
+        loc[4 * t + 3] -= f * kz * im;
+      }
+    }
+#pragma omp critical
+    for (size_t i = 0; i < loc.size(); ++i) acc[i] += loc[i];
+  }
+  const double c0 = 4.0 * kPi / (Ls[0] * Ls[1] * Ls[2]);
+  for (long t = 0; t < T; ++t) {
+    phi[t] = c0 * acc[4 * t];
+    if (grad) {
+      grad[3 * t] = c0 * acc[4 * t + 1];
+      grad[3 * t + 1] = c0 * acc[4 * t + 2];
+      grad[3 * t + 2] = c0 * acc[4 * t + 3];
+    }
+  }
+  return 0;
+}
+
 // Exposed for the tests that pin the quadrature: K0(a,b) and dK0/db.
 void oracle_incomplete_k0(double a, double b, double* k0, double* dk0_db) {
   incomplete_k0(a, b, k0, dk0_db);

@@ -123,10 +123,23 @@ class Params:
     s0: float | None = None
     s: float | None = None
     n_l: int | None = None
+    # triply periodic rectangular boxes: grid points along y and z (the box
+    # is M h x My h x Mz h, one grid spacing h = L/M); None: a cube
+    My: int | None = None
+    Mz: int | None = None
 
     def __post_init__(self):
         if self.M % 2 or self.P % 2 or self.P > self.M:
             raise ValueError("M and P must be even with P <= M (Section 3.3)")
+        if self.My is None:
+            self.My = self.M
+        if self.Mz is None:
+            self.Mz = self.M
+        if (self.My, self.Mz) != (self.M, self.M):
+            if self.D != 3:
+                raise ValueError("rectangular boxes are triply periodic here")
+            if self.My % 2 or self.Mz % 2 or self.P > min(self.My, self.Mz):
+                raise ValueError("My and Mz must be even and at least P")
         if self.shape is None:
             self.shape = (math.pi / 2) * self.P * 0.91 if self.window == "gaussian" else 2.5 * self.P
         if self.nu is None:
@@ -168,9 +181,19 @@ class Params:
         return smooth_even_up(math.ceil(self.s * self.Mt - 1e-9))
 
     @property
+    def Md(self):
+        """Grid points per periodic direction (M, My, Mz)."""
+        return (self.M, self.My, self.Mz)
+
+    @property
+    def Ld(self):
+        """Box side per periodic direction, Md[d] h (L itself where Md[d] = M)."""
+        return tuple(self.L if m == self.M else m * self.h for m in self.Md)
+
+    @property
     def grid_shape(self):
-        """Gridding grid: M points in periodic and Mt in free directions."""
-        return tuple(self.M if d < self.D else self.Mt for d in range(3))
+        """Gridding grid: M (My, Mz) points in periodic and Mt in free directions."""
+        return tuple(self.Md[d] if d < self.D else self.Mt for d in range(3))
 
 
 def kinf_for_tolerance(Q: float, xi: float, L: float, eps: float) -> float:
@@ -355,7 +378,7 @@ def grid_coords(x, p: Params):
     t = np.empty_like(x)
     for d in range(3):
         if d < p.D:
-            t[:, d] = np.mod(x[:, d], p.L) / p.h
+            t[:, d] = np.mod(x[:, d], p.Ld[d]) / p.h
         else:
             t[:, d] = x[:, d] / p.h + (p.Mt - p.M) // 2
     return t
@@ -377,7 +400,7 @@ def gridding(x, q, p: Params):
         j0, W, _ = parts[d]
         j = j0[:, None] + np.arange(p.P)[None, :]
         if d < p.D:
-            j = np.mod(j, p.M)
+            j = np.mod(j, p.Md[d])
         elif j.min() < 0 or j.max() >= p.Mt:
             raise ValueError("particle outside the box in a free direction")
         idx.append(j)
@@ -514,14 +537,14 @@ def scaled_convolution(H, p: Params, GR=None, deriv=None):
     D, M, Mt, L, h = p.D, p.M, p.Mt, p.L, p.h
     if D == 3:
         Hh = np.fft.fftn(H)
-        k = _periodic_k(M, L)
-        K2 = k[:, None, None] ** 2 + k[None, :, None] ** 2 + k[None, None, :] ** 2
-        sep = _sep(k, p)
-        S = sep[:, None, None] * sep[None, :, None] * sep[None, None, :]
+        # one wavenumber vector per direction, k = 2 pi n / L_d (a cube: all equal)
+        kx, ky, kz = (_periodic_k(m, l) for m, l in zip(p.Md, p.Ld))
+        K2 = kx[:, None, None] ** 2 + ky[None, :, None] ** 2 + kz[None, None, :] ** 2
+        S = _sep(kx, p)[:, None, None] * _sep(ky, p)[None, :, None] * _sep(kz, p)[None, None, :]
         with np.errstate(divide="ignore"):
             G = np.where(K2 == 0, 0.0, 1.0 / np.where(K2 == 0, 1.0, K2))  # Eq. (G_hat_3d)
-        ik = (np.reshape(_ik(k, deriv, 0), (-1, 1, 1)) * np.reshape(_ik(k, deriv, 1), (1, -1, 1))
-              * np.reshape(_ik(k, deriv, 2), (1, 1, -1)))
+        ik = (np.reshape(_ik(kx, deriv, 0), (-1, 1, 1)) * np.reshape(_ik(ky, deriv, 1), (1, -1, 1))
+              * np.reshape(_ik(kz, deriv, 2), (1, 1, -1)))
         return np.fft.ifftn(ik * S * G * Hh).real
 
     if D == 0:

@@ -185,3 +185,60 @@ def test_1p_closed_forms_against_quadrature():
         val = 2 * math.pi * integrate.quad(f, 1e-12, 60 * xi, limit=800, epsabs=1e-14)[0]
         tot += 4 * math.pi / ((2 * math.pi) ** 2 * L) * val
     assert abs(tot - phi[0]) <= 1e-8 * max(1.0, abs(phi[0]))
+
+
+# --- rectangular triply periodic boxes ---------------------------------------
+
+@pytest.mark.parametrize("xi", [3.0, 6.0])
+@pytest.mark.parametrize("reps", [(1, 1, 2), (2, 1, 3)])
+def test_box_madelung_rock_salt(xi, reps):
+    """Rock salt in a rectangular box made of reps[d] cubic cells of side 1
+    per direction: the Madelung constant per ion is the cube's."""
+    x1, q1, a = _lattice(3)
+    pts, qs = [], []
+    for i in range(reps[0]):
+        for j in range(reps[1]):
+            for k in range(reps[2]):
+                pts.append(x1 + np.array([i, j, k], dtype=float))
+                qs.append(q1)
+    x, q = np.concatenate(pts), np.concatenate(qs)
+    phi, g = direct.total_box3(np.array(reps, dtype=float), xi, x, q)
+    np.testing.assert_allclose(-phi * a / q, 1.747564594633182, rtol=0, atol=2e-11)
+    np.testing.assert_allclose(g, 0.0, atol=1e-9)   # every ion sits at a symmetric site
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_box_supercell_matches_cube(axis):
+    """A periodic system described by two copies of its cubic cell in a box
+    twice as long along one axis is the same system: each part of the split
+    (real space and Fourier space separately) at the original charges equals
+    the cube's (only the even modes along that axis carry a structure
+    factor)."""
+    x, q = wl.system(24, 1.0, 70 + axis, "uniform")
+    shift = np.zeros(3)
+    shift[axis] = 1.0
+    x2, q2 = np.concatenate([x, x + shift]), np.concatenate([q, q])
+    Ls = np.ones(3)
+    Ls[axis] = 2.0
+    xi = 5.0
+    tg = np.arange(len(q))
+    pk, gk = direct.kspace(3, 1.0, xi, x, q)
+    pk2, gk2 = direct.kspace_box3(Ls, xi, x2, q2, targets=tg)
+    np.testing.assert_allclose(pk2, pk, rtol=0, atol=1e-12 * np.abs(pk).max())
+    np.testing.assert_allclose(gk2, gk, rtol=0, atol=1e-11 * np.abs(gk).max())
+    rc = direct.real_space_cutoff(xi)
+    pr, gr = direct.real_space(3, 1.0, xi, rc, x, q)
+    pr2, gr2 = direct.real_space_box3(Ls, xi, rc, x2, q2, targets=tg)
+    np.testing.assert_allclose(pr2, pr, rtol=0, atol=1e-12 * np.abs(pr).max())
+    np.testing.assert_allclose(gr2, gr, rtol=0, atol=1e-11 * np.abs(gr).max())
+
+
+def test_box_xi_invariance():
+    """In a rectangular box the total potential does not depend on xi."""
+    x, q = wl.system(20, 1.0, 91, "uniform")
+    x = x * np.array([1.0, 0.75, 1.5])
+    Ls = np.array([1.0, 0.75, 1.5])
+    p1, g1 = direct.total_box3(Ls, 4.0, x, q)
+    p2, g2 = direct.total_box3(Ls, 8.0, x, q)
+    np.testing.assert_allclose(p1, p2, rtol=0, atol=1e-12 * np.abs(p1).max())
+    np.testing.assert_allclose(g1, g2, rtol=0, atol=1e-11 * np.abs(g1).max())

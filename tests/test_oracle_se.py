@@ -483,3 +483,45 @@ def test_separate_derivative_fit_forces_against_direct(D):
         _, g = se.spectral_ewald(x, q, p)
         e.append(rel(g, gref))
     assert e[1] < 2 * e[0] and e[0] < 2 * e[1]
+
+
+# --- rectangular triply periodic boxes ---------------------------------------
+
+@pytest.mark.parametrize("axis", [1, 2])
+def test_box_supercell_matches_cube(axis):
+    """Two copies of a cubic cell in a box twice as long along one axis, on a
+    grid twice as long there: the gridded charges are the cube's grid
+    repeated, so the SE potentials and gradients at the original charges
+    equal the cube's (to rounding)."""
+    x, q = wl.system(60, 1.0, 300 + axis, "uniform")
+    shift = np.zeros(3)
+    shift[axis] = 1.0
+    x2, q2 = np.concatenate([x, x + shift]), np.concatenate([q, q])
+    p = se.Params(D=3, L=1.0, xi=7.0, M=24, P=8)
+    kw = {"My": 48} if axis == 1 else {"Mz": 48}
+    p2 = se.Params(D=3, L=1.0, xi=7.0, M=24, P=8, **kw)
+    assert p2.Ld[axis] == 2.0
+    phi, g = se.spectral_ewald(x, q, p)
+    phi2, g2 = se.spectral_ewald(x2, q2, p2, targets=np.arange(len(q)))
+    assert rel(phi2, phi) < 1e-13 and rel(g2, g) < 1e-13
+
+
+def test_box_high_accuracy_against_direct():
+    """A 1 x 0.75 x 1.5 box (M = 40, 30, 60 at h = 1/40), PKB P = 16: the SE
+    result equals the direct rectangular-box sum to ~1e-12."""
+    rng = np.random.default_rng(515)
+    Ls = np.array([1.0, 0.75, 1.5])
+    x = rng.random((90, 3)) * Ls
+    q = rng.standard_normal(90)
+    q -= q.mean()
+    p = se.Params(D=3, L=1.0, xi=8.0, M=40, P=16, nu=9, My=30, Mz=60)
+    assert np.allclose(p.Ld, Ls)
+    phi, g = se.spectral_ewald(x, q, p)
+    ref, gref = direct.kspace_box3(Ls, 8.0, x, q)
+    assert rel(phi, ref) < 5e-12
+    assert rel(g, gref) < 5e-10
+
+
+def test_box_rejects_other_periodicities():
+    with pytest.raises(ValueError):
+        se.Params(D=2, L=1.0, xi=7.0, M=24, P=8, My=30, s=2.0, n_l=3)

@@ -718,13 +718,13 @@ __device__ __forceinline__ int4 work_record(const int4* rec, int item) {
 
 // FP32 transforms are bound by the latency of their load and store phases:
 // capping their registers at 72 (no spills) lets 7 workgroups share a CU
-// instead of 5-6.  FP64 transforms would spill under the cap and keep the
-// compiler's choice.
-template <typename T>
-constexpr int kFftMinWaves = sizeof(T) == 4 ? 7 : 1;
+// instead of 5-6.  FP64 transforms, and the 64-bit-offset variants, would
+// spill under the cap and keep the compiler's choice.
+template <typename T, typename OFF>
+constexpr int kFftMinWaves = sizeof(T) == 4 && sizeof(OFF) == 4 ? 7 : 1;
 
 template <typename T, int KIND, typename OFF>
-__global__ __launch_bounds__(kFftBlock, kFftMinWaves<T>) void fft_kernel(const FftPass P) {
+__global__ __launch_bounds__(kFftBlock, (kFftMinWaves<T, OFF>)) void fft_kernel(const FftPass P) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int4 r = work_record(P.items, work_item(P.xcd));
   stage_fft<T, KIND, OFF>(P, r.x, r.y, r.z, r.w, (lds<unsigned char>*)smem);
@@ -734,7 +734,7 @@ __global__ __launch_bounds__(kFftBlock, kFftMinWaves<T>) void fft_kernel(const F
 // b of the (stage, kind) list, {system * 4 + class, b0 start, b1, count}, so a
 // workgroup finds its system and pencils with one scalar load.
 template <typename T, int KIND, typename OFF>
-__global__ __launch_bounds__(kFftBlock, kFftMinWaves<T>) void batch_fft_kernel(const SysDesc* __restrict__ sys,
+__global__ __launch_bounds__(kFftBlock, (kFftMinWaves<T, OFF>)) void batch_fft_kernel(const SysDesc* __restrict__ sys,
                                                               const int4* __restrict__ rec, int pass, int xcd) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int4 r = work_record(rec, work_item(xcd));

@@ -77,7 +77,7 @@ typedef enum { SE_F64 = 0, SE_F32 = 1 } se_precision;
  * Fields marked "<= 0 -> default" take the paper's rule when left at 0. */
 typedef struct {
   int D;              /* periodic directions: 3, 2, 1 or 0                       */
-  double L;           /* cubic box side, > 0                                     */
+  double L;           /* box side along x (the cube's side), > 0                 */
   double xi;          /* Ewald parameter xi > 0 (Eq. gamma)                      */
   int M;              /* grid intervals per periodic side, even, 7-smooth        */
   int P;              /* window support in grid intervals, even, 2..16, P <= M   */
@@ -123,6 +123,11 @@ typedef struct {
                          by its own polynomial with the same P, beta, nu
                          (Section 7.2; the gradient is then not the energy's
                          exact derivative)                                      */
+  int My, Mz;         /* triply periodic rectangular boxes (Section 2 notes that
+                         the domain need not be a cube): grid intervals along y
+                         and z at the same spacing h = L/M, so the box is
+                         L x My h x Mz h; even, 7-smooth, >= P; <= 0 -> M (a
+                         cube).  D = 3 only (SE_ERR_PARAM otherwise)            */
 } se_params;
 
 /* Derived sizes of a plan (read-only report). */

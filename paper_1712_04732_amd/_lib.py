@@ -63,6 +63,8 @@ class se_params(ctypes.Structure):
         ("spread_mode", ctypes.c_int),
         ("force_method", ctypes.c_int),
         ("deriv_fit", ctypes.c_int),
+        ("My", ctypes.c_int),
+        ("Mz", ctypes.c_int),
     ]
 
 

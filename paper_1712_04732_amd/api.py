@@ -45,14 +45,15 @@ class SpectralEwald:
     force_method 1 differentiates the gathering window, 2 multiplies the
     scaling step by i k (Section 7.2); with 2 the autograd functions receive
     method 2's gradient, an approximation of the discrete energy's gradient
-    to the method's accuracy.
+    to the method's accuracy.  My, Mz (D = 3 only) make the box rectangular,
+    L x My h x Mz h at h = L/M.
 
     Call it with positions x (N,3) and charges q (N,) on the GPU.
     """
 
     def __init__(self, D, L_box, xi, M, P, *, window="pkb", prec="f64", n_max=1 << 20,
                  Q=None, tol=None, shape=None, nu=None, lam=None, s0=None, s=None, n_l=None,
-                 tile=0, force_method=1, deriv_fit=False):
+                 tile=0, force_method=1, deriv_fit=False, My=0, Mz=0):
         if not torch.cuda.is_available():
             raise RuntimeError("SpectralEwald needs a HIP device")
         L.load()
@@ -79,6 +80,8 @@ class SpectralEwald:
         p.tile = tile
         p.force_method = force_method
         p.deriv_fit = 1 if deriv_fit else 0
+        # triply periodic rectangular box L x My h x Mz h (h = L / M); 0: a cube
+        p.My, p.Mz = int(My), int(Mz)
         self.params = p
         self.n_max = int(n_max)
         self.prec = prec

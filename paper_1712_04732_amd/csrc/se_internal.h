@@ -136,6 +136,7 @@ struct GridGeom {
   int P, nu;
   int window;         // 0 Gaussian, 1 PKB
   double h, L, xi;
+  double Lp[3];       // box side per periodic direction (L, or M_d h in a rectangular 3P box)
   double alpha;       // Gaussian shape
   double scale;       // 4 pi h^3 (trapezoidal rule of Eq. complete_integral)
 };

@@ -87,7 +87,8 @@ __device__ __forceinline__ void stage_bin(const GridGeom& g, const EvalBuffers& 
         ci = g.per[d] ? 0 : g.d0[d];
         t = (double)ci;
       } else if (g.per[d]) {
-        const double xw = x - g.L * floor(x / g.L);
+        const double Ld = g.Lp[d];
+        const double xw = x - Ld * floor(x / Ld);
         t = xw / g.h;
         ci = (int)floor(t);
         if (ci >= g.G[d] || ci < 0) {  // xw rounded up to L

@@ -733,6 +733,14 @@ static se_status plan_create(const se_params* params, long n_max, void* hip_stre
   if (p.deriv_fit < 0 || p.deriv_fit > 1 || (p.deriv_fit && p.window != SE_WIN_PKB)) return SE_ERR_PARAM;
   if (p.prec != SE_F64 && p.prec != SE_F32) return SE_ERR_PARAM;
   if (!is_smooth(p.M)) return SE_ERR_PARAM;
+  // rectangular triply periodic boxes: My, Mz grid intervals at spacing L/M
+  if (p.My <= 0) p.My = p.M;
+  if (p.Mz <= 0) p.Mz = p.M;
+  if (p.My != p.M || p.Mz != p.M) {
+    if (p.D != 3) return SE_ERR_PARAM;
+    for (int m : {p.My, p.Mz})
+      if (m % 2 || m < p.P || m > 4096 || !is_smooth(m)) return SE_ERR_PARAM;
+  }
   if (!(p.shape > 0)) p.shape = p.window == SE_WIN_GAUSSIAN ? (kPi / 2.0) * p.P * 0.91 : 2.5 * p.P;
   if (p.window == SE_WIN_PKB) {
     if (p.nu <= 0) p.nu = std::min(p.P / 2 + 2, 9);
@@ -801,8 +809,9 @@ static se_status plan_create(const se_params* params, long n_max, void* hip_stre
   I.n0 = p.D < 3 ? smooth_even_up((long)std::ceil(p.s0 * I.Mt - 1e-9)) : 0;
   I.nI = (p.D == 1 || p.D == 2) ? smooth_even_up((long)std::ceil(p.s * I.Mt - 1e-9)) : 0;
   for (int d = 0; d < 3; ++d) {
-    I.grid[d] = d < p.D ? p.M : I.Mt;
-    I.nfft[d] = d < p.D ? p.M : (p.D == 0 ? 2 * I.Mt : I.Mt);
+    const int Md = d == 0 ? p.M : (d == 1 ? p.My : p.Mz);   // periodic grid length (My = Mz = M below 3P)
+    I.grid[d] = d < p.D ? Md : I.Mt;
+    I.nfft[d] = d < p.D ? Md : (p.D == 0 ? 2 * I.Mt : I.Mt);
   }
   if (I.Mt >= 1024) {
     delete pl;
@@ -822,6 +831,7 @@ static se_status plan_create(const se_params* params, long n_max, void* hip_stre
   g.window = p.window == SE_WIN_PKB ? 1 : (p.window == SE_WIN_ES ? 2 : 0);
   g.h = I.h;
   g.L = p.L;
+  for (int d = 0; d < 3; ++d) g.Lp[d] = I.grid[d] == p.M ? p.L : I.grid[d] * I.h;
   g.xi = p.xi;
   g.alpha = p.shape;
   g.scale = 4.0 * kPi * I.h * I.h * I.h;
@@ -1035,20 +1045,28 @@ static se_status build_passes(se_plan* pl, hipStream_t st) {
     p1.cls[0] = make_class(nx, Gx, Kx, pl->buf.grid, cb, 1, Gx, (long long)Gx * Gy, 1, Kx, (long long)Kx * Gy);
     rg = {{0, 0, Gy, 0, Gz}};
     if (!finish_pass(pl, p1, se::K_R2C, 1, rg)) return fail();
-    // y: complex forward
+    // y: complex forward (Gy = M, or My in a rectangular 3P box)
     se::FftPass p2{};
-    p2.cls[0] = make_class(M, M, M, cb, cb, Kx, 1, (long long)Kx * Gy, Kx, 1, (long long)Kx * Gy);
+    p2.cls[0] = make_class(Gy, Gy, Gy, cb, cb, Kx, 1, (long long)Kx * Gy, Kx, 1, (long long)Kx * Gy);
     rg = {{0, 0, Kx, 0, Gz}};
     if (!finish_pass(pl, p2, se::K_C2C_FWD, 1, rg)) return fail();
     // z: fused forward / scale / inverse
     se::FftPass p3{};
     const long long zst = (long long)Kx * Gy;
     if (D == 3) {
-      se::FftClass c = make_class(M, M, M, cb, cb, zst, 1, Kx, zst, 1, Kx);
+      // z pencils of length Gz; the separable vectors and squared wavenumbers
+      // of each direction come from its own transform length at spacing h
+      // (all M in a cube)
+      se::FftClass c = make_class(Gz, Gz, Gz, cb, cb, zst, 1, Kx, zst, 1, Kx);
       c.gmode = se::G_INVSQ;
-      c.sA = c.sB = c.sC = sepM;
-      c.kA = c.kB = c.kC = k2M;
-      set_d(c, M, M, M, 0, 1);
+      c.sA = sepM;
+      c.sB = Gy == M ? sepM : pl->sep_table(Gy);
+      c.sC = Gz == M ? sepM : pl->sep_table(Gz);
+      c.kA = k2M;
+      c.kB = Gy == M ? k2M : pl->k2_table(Gy);
+      c.kC = Gz == M ? k2M : pl->k2_table(Gz);
+      if (!c.sB || !c.sC || !c.kB || !c.kC) return fail();
+      set_d(c, M, Gy, Gz, 0, 1);
       p3.cls[0] = c;
       rg = {{0, 0, Kx, 0, Gy}};
       if (!finish_pass(pl, p3, se::K_FUSED, 1, rg)) return fail();

@@ -3,7 +3,9 @@ rounding only) and the direct Ewald oracle:
 
   * the ES window of Section 4 (Eq. expsemicirc_window), evaluated directly
     in the kernels, its Fourier transform by quadrature in the planner;
-  * forces with the separately fitted W'_KB polynomial of Section 7.2.
+  * forces with the separately fitted W'_KB polynomial of Section 7.2;
+  * triply periodic rectangular boxes (Section 2: the domain need not be a
+    cube), one grid spacing h with M, My, Mz points per side.
 """
 import math
 
@@ -124,3 +126,99 @@ def test_es_window_in_a_batch():
         ref, gref = se.spectral_ewald(x, q, se.Params(D=D, L=1.0, xi=xi, M=pp.M, P=8, window="es", **kw))
         assert rel(phi[o:o + n], ref) < 1e-12 and rel(g[o:o + n], gref) < 1e-11
         o += n
+
+
+def _box_system(N, Ls, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.random((N, 3)) * np.asarray(Ls)
+    q = rng.standard_normal(N)
+    q -= q.mean()
+    return x, q
+
+
+@pytest.mark.parametrize("My,Mz,window,P,fm", [(32, 48, "pkb", 8, 1), (24, 40, "gaussian", 8, 1),
+                                                (40, 30, "pkb", 10, 2), (32, 32, "es", 8, 1),
+                                                (18, 60, "pkb", 6, 1)])
+def test_rectangular_box_matches_discrete_oracle(My, Mz, window, P, fm):
+    """FP64 potentials and gradients in an L x My h x Mz h box against the
+    discrete oracle with the same parameters (rounding only); FP32 within the
+    FP32 bounds of the cube."""
+    print(f"case box M=32 My={My} Mz={Mz} {window} P={P} method {fm}", flush=True)
+    M, L, xi = 32, 1.0, 9.0
+    h = L / M
+    x, q = _box_system(900, (L, My * h, Mz * h), 900 + My + Mz)
+    p = se.Params(D=3, L=L, xi=xi, M=M, P=P, window=window, My=My, Mz=Mz)
+    ref, gref = se.spectral_ewald(x, q, p, force_method=fm)
+    plan = SpectralEwald(3, L, xi, M, P, window=window, prec="f64", n_max=len(q), My=My, Mz=Mz,
+                         force_method=fm)
+    assert tuple(plan.info.grid) == (M, My, Mz)
+    phi, g, _ = run(plan, x, q)
+    assert rel(phi, ref) < 1e-12 and rel(g, gref) < 1e-11
+    p32 = SpectralEwald(3, L, xi, M, P, window=window, prec="f32", n_max=len(q), My=My, Mz=Mz,
+                        force_method=fm)
+    phi32, g32, _ = run(p32, x, q)
+    assert rel(phi32, ref) < 1e-5 and rel(g32, gref) < 2e-5
+
+
+@pytest.mark.parametrize("axis", [1, 2])
+def test_rectangular_box_supercell_matches_cube(axis):
+    """Two copies of a cubic cell in a box twice as long along one axis are
+    the same periodic system: the GPU gives the cube's potentials and
+    gradients at the original charges."""
+    print(f"case box supercell axis={axis}", flush=True)
+    M, L, xi, P = 32, 1.0, 9.0, 8
+    x, q = _box_system(700, (1.0, 1.0, 1.0), 4100 + axis)
+    shift = np.zeros(3)
+    shift[axis] = 1.0
+    x2, q2 = np.concatenate([x, x + shift]), np.concatenate([q, q])
+    cube = SpectralEwald(3, L, xi, M, P, prec="f64", n_max=len(q))
+    kw = {"My": 2 * M} if axis == 1 else {"Mz": 2 * M}
+    box = SpectralEwald(3, L, xi, M, P, prec="f64", n_max=len(q2), **kw)
+    phi, g, E = run(cube, x, q)
+    phi2, g2, E2 = run(box, x2, q2)
+    n = len(q)
+    assert rel(phi2[:n], phi) < 1e-12 and rel(g2[:n], g) < 1e-11
+    assert abs(E2 - 2 * E) <= 1e-11 * abs(E)
+
+
+def test_rectangular_box_against_direct():
+    """PKB P = 16 in a 1 x 0.75 x 1.5 box: the GPU result equals the direct
+    rectangular-box Fourier sum to ~1e-12."""
+    print("case box vs direct", flush=True)
+    Ls = (1.0, 0.75, 1.5)
+    x, q = _box_system(300, Ls, 777)
+    plan = SpectralEwald(3, 1.0, 8.0, 40, 16, nu=9, prec="f64", n_max=len(q), My=30, Mz=60)
+    phi, g, _ = run(plan, x, q)
+    ref, gref = direct.kspace_box3(np.array(Ls), 8.0, x, q)
+    assert rel(phi, ref) < 5e-12 and rel(g, gref) < 5e-10
+
+
+def test_rectangular_boxes_in_a_batch():
+    """A batch holding rectangular and cubic 3P systems gives each system's
+    single-plan result."""
+    print("case box batch", flush=True)
+    M, L, xi, P = 24, 1.0, 8.0, 8
+    h = L / M
+    shapes = [(24, 40), (24, 24), (36, 18)]
+    systems = []
+    for k, (My, Mz) in enumerate(shapes):
+        x, q = _box_system(400 + 100 * k, (L, My * h, Mz * h), 60 + k)
+        systems.append((My, Mz, x, q))
+    from paper_1712_04732_amd import _lib
+    params = []
+    for My, Mz, x, q in systems:
+        pl = SpectralEwald(3, L, xi, M, P, prec="f64", n_max=len(q), My=My, Mz=Mz)
+        params.append(pl.params)
+    b = SpectralEwaldBatch(params, [len(s[3]) for s in systems])
+    xt = torch.tensor(np.concatenate([s[2] for s in systems]), device=DEV)
+    qt = torch.tensor(np.concatenate([s[3] for s in systems]), device=DEV)
+    phi, f, E = b(xt, qt)
+    o = 0
+    for k, (My, Mz, x, q) in enumerate(systems):
+        pl = SpectralEwald(3, L, xi, M, P, prec="f64", n_max=len(q), My=My, Mz=Mz)
+        p1, f1, e1 = pl(torch.tensor(x, device=DEV), torch.tensor(q, device=DEV))
+        sl = slice(o, o + len(q))
+        assert rel(phi[sl].cpu().numpy(), p1.cpu().numpy()) < 1e-13
+        assert rel(f[sl].cpu().numpy(), f1.cpu().numpy()) < 1e-12
+        assert abs(float(E[k]) - float(e1)) <= 1e-13 * abs(float(e1))
+        o += len(q)

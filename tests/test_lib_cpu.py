@@ -66,6 +66,19 @@ def test_plan_create_rejects_invalid_parameters(D, Lb, xi, M, P):
     assert not plan.value
 
 
+@pytest.mark.parametrize("D,My,Mz", [(2, 30, 0), (1, 0, 30), (0, 30, 30), (3, 31, 0), (3, 0, 38), (3, 6, 0)])
+def test_plan_create_rejects_invalid_rectangular_boxes(D, My, Mz):
+    """Rectangular boxes are triply periodic only, with even, 7-smooth grid
+    lengths of at least P along y and z."""
+    lib = L.load()
+    p = L.se_params()
+    p.D, p.L, p.xi, p.M, p.P, p.window = D, 1.0, 5.0, 32, 8, L.SE_WIN_PKB
+    p.My, p.Mz = My, Mz
+    plan = ctypes.c_void_p()
+    assert lib.se_plan_create(ctypes.byref(p), 10, None, ctypes.byref(plan)) == L.SE_ERR_PARAM
+    assert not plan.value
+
+
 def test_null_arguments():
     lib = L.load()
     assert lib.se_plan_create(None, 10, None, None) == L.SE_ERR_ARG

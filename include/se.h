@@ -459,6 +459,26 @@ se_status se_rs_cells(double L, double rc, long n_max, int cells_per_rc, int* ce
 se_status se_rs_plan_create(int D, double L, double xi, double rc, long n_max, se_precision prec,
                             int cells_per_rc, void* hip_stream, se_rs_plan** out);
 
+/* Cells and spans of a triply periodic rectangular box of sides Ls[0] x
+ * Ls[1] x Ls[2] (Section 2: the box need not be a cube), host only.  Per
+ * direction d: c_d = max(1, min(floor(cells_per_rc Ls[d] / rc),
+ * floor(Ls[d] cbrt(n_max / V)), 160)) with V the box volume (about one cell
+ * per charge at most), and the smallest s_d with s_d Ls[d] / c_d >= rc.
+ * Ls: host, 3 values; cells, span: host, 3 values each.
+ * Errors: SE_ERR_ARG for NULL pointers; SE_ERR_PARAM for a side or rc not
+ * positive and finite, n_max < 0 or cells_per_rc > 8. */
+se_status se_rs_cells_box(const double* Ls, double rc, long n_max, int cells_per_rc, int* cells, int* span);
+
+/* As se_rs_plan_create for D = 3 in a rectangular box of sides Ls[0] x Ls[1]
+ * x Ls[2] (host, 3 values; periodic coordinates wrapped per direction by
+ * its side), with the cells of se_rs_cells_box.  The same rectangular box
+ * is the one of a se_params with M, My, Mz grid points at spacing h = L / M:
+ * Ls = {L, My h, Mz h}.  se_rs_get_info reports the x direction.
+ * Errors: SE_ERR_ARG (Ls or out NULL), SE_ERR_PARAM (xi, prec, n_max, or as
+ * se_rs_cells_box), SE_ERR_NOMEM. */
+se_status se_rs_plan_create_box(const double* Ls, double xi, double rc, long n_max, se_precision prec,
+                                int cells_per_rc, void* hip_stream, se_rs_plan** out);
+
 /* Workspace of a real-space plan: size in bytes (host output), and binding
  * of a caller-owned block (device, 256-byte aligned, at least that size;
  * NULL unbinds).  As se_plan_workspace_size / se_plan_set_workspace.

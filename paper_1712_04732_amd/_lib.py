@@ -160,6 +160,11 @@ _SIGS = {
     "se_rs_plan_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_long, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                          ctypes.POINTER(ctypes.c_void_p)]),
+    "se_rs_cells_box": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.c_double, ctypes.c_long, ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "se_rs_plan_create_box": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_long, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                             ctypes.POINTER(ctypes.c_void_p)]),
     "se_rs_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                       ctypes.POINTER(ctypes.c_size_t)]),
     "se_rs_eval": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_long, ctypes.c_void_p, ctypes.c_void_p,
@@ -428,6 +433,24 @@ def se_rs_plan_create(D, L, xi, rc, n_max, prec, cells_per_rc=0, stream=0):
     _check(load().se_rs_plan_create(int(D), float(L), float(xi), float(rc), int(n_max), int(prec),
                                     int(cells_per_rc), ctypes.c_void_p(stream), ctypes.byref(plan)),
            "se_rs_plan_create")
+    return plan
+
+
+def se_rs_cells_box(Ls, rc, n_max, cells_per_rc=0):
+    """(cells, spans) per direction of the real-space cell list in a
+    rectangular box of sides Ls."""
+    sides = (ctypes.c_double * 3)(*[float(v) for v in Ls])
+    c, sp = (ctypes.c_int * 3)(), (ctypes.c_int * 3)()
+    _check(load().se_rs_cells_box(sides, float(rc), int(n_max), int(cells_per_rc), c, sp), "se_rs_cells_box")
+    return tuple(c), tuple(sp)
+
+
+def se_rs_plan_create_box(Ls, xi, rc, n_max, prec, cells_per_rc=0, stream=0):
+    plan = ctypes.c_void_p()
+    sides = (ctypes.c_double * 3)(*[float(v) for v in Ls])
+    _check(load().se_rs_plan_create_box(sides, float(xi), float(rc), int(n_max), int(prec), int(cells_per_rc),
+                                        ctypes.c_void_p(stream), ctypes.byref(plan)),
+           "se_rs_plan_create_box")
     return plan
 
 

@@ -91,6 +91,14 @@ class SpectralEwald:
         self.info = L.se_plan_get_info(self._plan)
         self._bind()
 
+    @property
+    def box(self):
+        """The box sides: (L, L, L) for a cube, (L, My h, Mz h) at h = L / M
+        for a rectangular one."""
+        p = self.params
+        h = p.L / p.M
+        return (p.L, p.My * h if p.My > 0 else p.L, p.Mz * h if p.Mz > 0 else p.L)
+
     def _bind(self):
         self.workspace = _workspace(L.se_plan_workspace_size(self._plan))
         L.se_plan_set_workspace(self._plan, self.workspace.data_ptr(), self.workspace.numel())
@@ -405,18 +413,30 @@ class RealSpace:
     """The real-space sum of the Ewald split, Eq. (real_space_ewald), with
     cutoff rc, on the GPU (cell list in the HIP library).  Adds to a k-space
     result of SpectralEwald (accumulate=True) to give the full potential of
-    Eq. (potential_split)."""
+    Eq. (potential_split).  L_box is the side of a cube, or, for D = 3, the
+    three sides of a rectangular box (SpectralEwald(..., My, Mz).box)."""
 
     def __init__(self, D, L_box, xi, rc, *, prec="f64", n_max=1 << 20, cells_per_rc=0):
         if not torch.cuda.is_available():
             raise RuntimeError("RealSpace needs a HIP device")
         L.load()
-        self.D, self.L, self.xi, self.rc = D, L_box, xi, rc
+        self.D, self.xi, self.rc = D, xi, rc
         self.prec = prec
         self.dtype = torch.float64 if prec == "f64" else torch.float32
         self.n_max = int(n_max)
-        self._plan = L.se_rs_plan_create(D, L_box, xi, rc, self.n_max, _PRECS[prec], cells_per_rc, _stream())
-        self.cells, self.span, self.device_bytes = L.se_rs_get_info(self._plan)
+        if isinstance(L_box, (tuple, list)):
+            if D != 3 or len(L_box) != 3:
+                raise ValueError("a rectangular box takes D = 3 and three sides")
+            self.L = self.box = tuple(float(v) for v in L_box)
+            self._plan = L.se_rs_plan_create_box(self.box, xi, rc, self.n_max, _PRECS[prec], cells_per_rc,
+                                                 _stream())
+            _, _, self.device_bytes = L.se_rs_get_info(self._plan)
+            self.cells, self.span = L.se_rs_cells_box(self.box, rc, self.n_max, cells_per_rc)
+        else:
+            self.L = L_box
+            self.box = (float(L_box),) * 3
+            self._plan = L.se_rs_plan_create(D, L_box, xi, rc, self.n_max, _PRECS[prec], cells_per_rc, _stream())
+            self.cells, self.span, self.device_bytes = L.se_rs_get_info(self._plan)
         self.workspace = _workspace(L.se_rs_workspace_size(self._plan))
         L.se_rs_set_workspace(self._plan, self.workspace.data_ptr(), self.workspace.numel())
 

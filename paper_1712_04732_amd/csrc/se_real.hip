@@ -7,10 +7,11 @@
 // the split in the same way).  It completes the k-space result of se_eval
 // into the full potential of Eq. (potential_split).
 //
-// Cell list: the box is cut into c^3 cells of side h = L/c >= rc/s; every
-// charge within rc of a target lies in the (2s+1)^3 cells around the
-// target's cell (periodic directions wrap with an image shift, free
-// directions stop at the box).  Cells whose nearest points are rc or more
+// Cell list: the box (a cube, or a triply periodic rectangular box with a
+// side per direction) is cut into c_d cells of side h_d = L_d/c_d >= rc/s_d
+// per direction; every charge within rc of a target lies in the
+// (2s_x+1)(2s_y+1)(2s_z+1) cells around the target's cell (periodic
+// directions wrap with an image shift, free directions stop at the box).  Cells whose nearest points are rc or more
 // apart are skipped.  One wavefront serves one cell: its lanes hold the
 // cell's targets (several lanes per target when the cell is small); each
 // neighbour chunk of 64 charges is loaded one per lane, the charges within rc
@@ -41,8 +42,10 @@ constexpr int kRsMaxCells = 160;    // most cells per direction
 
 struct RsGeom {
   int D;           // periodic directions: x; x, y; x, y, z
-  int c, s;        // cells per direction, neighbour span in cells
-  double L, h, rc, xi;
+  int c[3], s[3];  // cells and neighbour span in cells, per direction
+  double L[3];     // box side per direction
+  double h[3];     // cell side per direction, L[d] / c[d]
+  double rc, xi;
 };
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -72,7 +75,6 @@ __device__ __forceinline__ int cell_coord(double w, double inv_h, int c) {
 template <typename Tin>
 __device__ __forceinline__ void load_wrapped(const Tin* xyz, const Tin* q, long i, const RsGeom& g, double w[3],
                                              double* qi, int* bad) {
-  const double invL = 1.0 / g.L;
   *qi = (double)gld(q)[i];
   if (!isfinite(*qi)) *bad |= 1;
 #pragma unroll
@@ -82,10 +84,10 @@ __device__ __forceinline__ void load_wrapped(const Tin* xyz, const Tin* q, long 
       *bad |= 1;
       w[d] = 0.0;
     } else if (d < g.D) {
-      w[d] = wrap_periodic(x, g.L, invL);
+      w[d] = wrap_periodic(x, g.L[d], 1.0 / g.L[d]);
     } else {
-      if (!(x >= 0.0 && x < g.L)) *bad |= 2;
-      w[d] = x < 0.0 ? 0.0 : (x >= g.L ? 0.0 : x);
+      if (!(x >= 0.0 && x < g.L[d])) *bad |= 2;
+      w[d] = x < 0.0 ? 0.0 : (x >= g.L[d] ? 0.0 : x);
     }
   }
 }
@@ -102,9 +104,9 @@ __global__ __launch_bounds__(kRsBlock) void rs_bin_kernel(RsGeom g, long N, cons
   int bad = 0;
   load_wrapped(xyz, q, i, g, w, &qi, &bad);
   if (bad) atomicOr(status, bad);
-  const double inv_h = (double)g.c / g.L;
-  const int cell = (cell_coord(w[2], inv_h, g.c) * g.c + cell_coord(w[1], inv_h, g.c)) * g.c +
-                   cell_coord(w[0], inv_h, g.c);
+  const int cell = (cell_coord(w[2], g.c[2] / g.L[2], g.c[2]) * g.c[1] + cell_coord(w[1], g.c[1] / g.L[1], g.c[1])) *
+                       g.c[0] +
+                   cell_coord(w[0], g.c[0] / g.L[0], g.c[0]);
   gst(cell_of)[i] = cell;
   gst(slot)[i] = atomicAdd(cnt + cell, 1);
 }
@@ -202,7 +204,7 @@ __global__ __launch_bounds__(kRsBlock) void rs_order_kernel(RsGeom g, const Tin*
   const int cell = blockIdx.x;
   const int j0 = start[cell], j1 = start[cell + 1], n = j1 - j0;
   if (n <= 0) return;
-  const int cx = cell % g.c, cy = (cell / g.c) % g.c, cz = cell / (g.c * g.c);
+  const int cx = cell % g.c[0], cy = (cell / g.c[0]) % g.c[1], cz = cell / (g.c[0] * g.c[1]);
   if (n > 1 && n <= kRsSortMax) {
     int m = 1;
     while (m < n) m <<= 1;
@@ -231,7 +233,7 @@ __global__ __launch_bounds__(kRsBlock) void rs_order_kernel(RsGeom g, const Tin*
     double w[3], qi;
     int bad = 0;
     load_wrapped(xyz, q, o, g, w, &qi, &bad);
-    const double rx = w[0] - cx * g.h, ry = w[1] - cy * g.h, rz = w[2] - cz * g.h;
+    const double rx = w[0] - cx * g.h[0], ry = w[1] - cy * g.h[1], rz = w[2] - cz * g.h[2];
     gst(spos)[j0 + i] = vec4<T>{(T)rx, (T)ry, (T)rz, (T)qi};
     if (spos64) gst(spos64)[j0 + i] = vec4<double>{rx, ry, rz, 0.0};
     gst(scx)[j0 + i] = cx;
@@ -298,8 +300,9 @@ __global__ __launch_bounds__(64) void rs_sum_kernel(RsGeom g, const int* __restr
                                                     const vec4<T>* __restrict__ spos,
                                                     const int* __restrict__ scx,
                                                     const vec4<double>* __restrict__ spos64, RsOut out) {
-  const int cell = blockIdx.x, lane = threadIdx.x, c = g.c, s = g.s;
-  const int ix = cell % c, iy = (cell / c) % c, iz = cell / (c * c);
+  const int cell = blockIdx.x, lane = threadIdx.x;
+  const int cX = g.c[0], cY = g.c[1], cZ = g.c[2];
+  const int ix = cell % cX, iy = (cell / cX) % cY, iz = cell / (cX * cY);
   const int t0 = uni(gld(start)[cell]), t1 = uni(gld(start)[cell + 1]);
   const int n = t1 - t0;
   int lg = 0;
@@ -307,11 +310,12 @@ __global__ __launch_bounds__(64) void rs_sum_kernel(RsGeom g, const int* __restr
   const int gsz = 1 << lg, per = 64 >> lg, sub = lane & (gsz - 1), tl = lane >> lg;
   const T rc2 = (T)(g.rc * g.rc), xi = (T)g.xi, xi2 = (T)(g.xi * g.xi);
   const T c2 = (T)(2.0 * g.xi / 1.7724538509055160272981674833411452);
-  const double h = g.h, rc2d = g.rc * g.rc;
-  const T hT = (T)g.h;
-  const T near2 = (T)(g.h * g.h / 64.0);   // (h/8)^2: FP64 differences below it (FP32 records)
+  const double hx = g.h[0], hy = g.h[1], hz = g.h[2], rc2d = g.rc * g.rc;
+  const T hxT = (T)hx, hyT = (T)hy, hzT = (T)hz;
+  const double hmin = fmin(hx, fmin(hy, hz)), hmax = fmax(hx, fmax(hy, hz));
+  const T near2 = (T)(hmin * hmin / 64.0);   // (h/8)^2: FP64 differences below it (FP32 records)
   // rc^2 with a margin for the rounding of records near the cell's faces
-  const T box2 = (T)((g.rc * (1.0 + 1e-5) + 1e-5 * g.h) * (g.rc * (1.0 + 1e-5) + 1e-5 * g.h));
+  const T box2 = (T)((g.rc * (1.0 + 1e-5) + 1e-5 * hmax) * (g.rc * (1.0 + 1e-5) + 1e-5 * hmax));
   __shared__ vec4<T> crec[64];   // kept records of the current chunk
   __shared__ int cslot[64];      // and their record slots
   double e_acc = 0.0;
@@ -329,7 +333,7 @@ __global__ __launch_bounds__(64) void rs_sum_kernel(RsGeom g, const int* __restr
         if constexpr (sizeof(T) == 4) {
           if (r2 < near2 && valid) {
             const vec4<double> a = gld(spos64)[k], b = gld(spos64)[jslot];
-            const double sx = (double)(gld(scx)[jslot] + kxb) * h, sy = (double)ky * h, sz = (double)kz * h;
+            const double sx = (double)(gld(scx)[jslot] + kxb) * hx, sy = (double)ky * hy, sz = (double)kz * hz;
             dxv = (T)(a.x - (b.x + sx));
             dyv = (T)(a.y - (b.y + sy));
             dzv = (T)(a.z - (b.z + sz));
@@ -357,34 +361,34 @@ __global__ __launch_bounds__(64) void rs_sum_kernel(RsGeom g, const int* __restr
         }
       }
     };
-    for (int dz = -s; dz <= s; ++dz) {
+    for (int dz = -g.s[2]; dz <= g.s[2]; ++dz) {
       const int uz = iz + dz;
-      if (g.D < 3 && (uz < 0 || uz >= c)) continue;
-      const int qz = floor_div(uz, c);
-      const double gz_ = (double)max(0, abs(dz) - 1) * h;
-      for (int dy = -s; dy <= s; ++dy) {
+      if (g.D < 3 && (uz < 0 || uz >= cZ)) continue;
+      const int qz = floor_div(uz, cZ);
+      const double gz_ = (double)max(0, abs(dz) - 1) * hz;
+      for (int dy = -g.s[1]; dy <= g.s[1]; ++dy) {
         const int uy = iy + dy;
-        if (g.D < 2 && (uy < 0 || uy >= c)) continue;
-        const int qy = floor_div(uy, c);
-        const double gy_ = (double)max(0, abs(dy) - 1) * h;
+        if (g.D < 2 && (uy < 0 || uy >= cY)) continue;
+        const int qy = floor_div(uy, cY);
+        const double gy_ = (double)max(0, abs(dy) - 1) * hy;
         const double rem = rc2d - gz_ * gz_ - gy_ * gy_;
         if (rem <= 0.0) continue;
-        int dm = s;   // cells in x whose gap (|dx| - 1) h stays below the remaining reach
-        while (dm > 1 && ((dm - 1) * h) * ((dm - 1) * h) >= rem) --dm;
-        const int rowc = ((uz - qz * c) * c + (uy - qy * c)) * c;
+        int dm = g.s[0];   // cells in x whose gap (|dx| - 1) h_x stays below the remaining reach
+        while (dm > 1 && ((dm - 1) * hx) * ((dm - 1) * hx) >= rem) --dm;
+        const int rowc = ((uz - qz * cZ) * cY + (uy - qy * cY)) * cX;
         int xa = ix - dm, xb = ix + dm;
         if (g.D < 1) {
           xa = max(xa, 0);
-          xb = min(xb, c - 1);
+          xb = min(xb, cX - 1);
         }
-        for (int qx = floor_div(xa, c); qx <= floor_div(xb, c); ++qx) {
-          const int lo = max(xa, qx * c) - qx * c, hi = min(xb, qx * c + c - 1) - qx * c;
+        for (int qx = floor_div(xa, cX); qx <= floor_div(xb, cX); ++qx) {
+          const int lo = max(xa, qx * cX) - qx * cX, hi = min(xb, qx * cX + cX - 1) - qx * cX;
           const int j0 = uni(gld(start)[rowc + lo]), j1 = uni(gld(start)[rowc + hi + 1]);
           const bool same = qx == 0 && qy == 0 && qz == 0 && uy == iy && uz == iz;
           // neighbour positions relative to the target cell's corner: the
-          // neighbour's unwrapped cell is (cx + qx c, iy + dy, iz + dz)
-          const T oy = (T)dy * hT, oz = (T)dz * hT;
-          const int kxb = qx * c - ix;
+          // neighbour's unwrapped cell is (cx + qx c_x, iy + dy, iz + dz)
+          const T oy = (T)dy * hyT, oz = (T)dz * hzT;
+          const int kxb = qx * cX - ix;
           for (int jb = j0; jb < j1; jb += 64) {
             // one record per lane, moved to the target cell's frame; only the
             // records within rc of the cell's box [0, h)^3 can meet a target
@@ -393,11 +397,11 @@ __global__ __launch_bounds__(64) void rs_sum_kernel(RsGeom g, const int* __restr
             vec4<T> np;
             if (jn < j1) {
               np = gld(spos)[jn];
-              np.x += (T)(gld(scx)[jn] + kxb) * hT;
+              np.x += (T)(gld(scx)[jn] + kxb) * hxT;
               np.y += oy;
               np.z += oz;
-              const T ex = max(max(-np.x, np.x - hT), (T)0), ey = max(max(-np.y, np.y - hT), (T)0),
-                      ez = max(max(-np.z, np.z - hT), (T)0);
+              const T ex = max(max(-np.x, np.x - hxT), (T)0), ey = max(max(-np.y, np.y - hyT), (T)0),
+                      ez = max(max(-np.z, np.z - hzT), (T)0);
               keep = ex * ex + ey * ey + ez * ez < box2;
             }
             // kept records packed in chunk order into LDS, read back by every lane
@@ -510,45 +514,31 @@ struct se_rs_plan {
 
 namespace {
 constexpr int kRsEventPool = 4 * 1024;
-}
 
-extern "C" {
-
-se_status se_rs_cells(double L, double rc, long n_max, int cells_per_rc, int* cells, int* span) {
-  if (!cells || !span) return SE_ERR_ARG;
-  if (!(L > 0.0) || !(rc > 0.0) || !std::isfinite(L) || !std::isfinite(rc) || n_max < 0) return SE_ERR_PARAM;
-  const int k = cells_per_rc <= 0 ? 2 : cells_per_rc;
-  if (k > 8) return SE_ERR_PARAM;
-  // at most about one cell per charge, and kRsMaxCells per direction
-  const int by_n = std::max(1, (int)std::floor(std::cbrt((double)std::max(1L, n_max)) + 1e-9));
-  const double want = std::floor(k * L / rc);
-  const int c = (int)std::max(1.0, std::min({want, (double)by_n, (double)se::kRsMaxCells}));
-  const double h = L / c;
+// smallest s with s h >= rc (rounding of rc / h taken care of)
+int rs_span(double h, double rc) {
   int s = std::max(1, (int)std::ceil(rc / h));
-  while (s > 1 && (s - 1) * h >= rc) --s;   // rounding of rc / h
+  while (s > 1 && (s - 1) * h >= rc) --s;
   while (s * h < rc) ++s;
-  *cells = c;
-  *span = s;
-  return SE_OK;
+  return s;
 }
 
-se_status se_rs_plan_create(int D, double L, double xi, double rc, long n_max, se_precision prec,
-                            int cells_per_rc, void* hip_stream, se_rs_plan** out) {
-  (void)hip_stream;
-  if (!out) return SE_ERR_ARG;
-  *out = nullptr;
-  if (D < 0 || D > 3 || !(xi > 0.0) || !std::isfinite(xi) || (prec != SE_F64 && prec != SE_F32) ||
-      n_max > 0x7fffffffL)
-    return SE_ERR_PARAM;
-  int c, s;
-  const se_status st = se_rs_cells(L, rc, n_max, cells_per_rc, &c, &s);
-  if (st != SE_OK) return st;
+se_status rs_plan_make(int D, const int* c, const int* sp, const double* Ls, double xi, double rc, long n_max,
+                       se_precision prec, se_rs_plan** out) {
   se_rs_plan* p = new (std::nothrow) se_rs_plan();
   if (!p) return SE_ERR_NOMEM;
-  p->g = se::RsGeom{D, c, s, L, L / c, rc, xi};
+  p->g.D = D;
+  for (int d = 0; d < 3; ++d) {
+    p->g.c[d] = c[d];
+    p->g.s[d] = sp[d];
+    p->g.L[d] = Ls[d];
+    p->g.h[d] = Ls[d] / c[d];
+  }
+  p->g.rc = rc;
+  p->g.xi = xi;
   p->n_max = n_max;
   p->f64 = prec == SE_F64;
-  p->ncell = c * c * c;
+  p->ncell = c[0] * c[1] * c[2];
   p->nscan = (p->ncell + se::kRsScanItems - 1) / se::kRsScanItems;
   const size_t n = (size_t)std::max(1L, n_max), nc = (size_t)p->ncell;
   const size_t rec = p->f64 ? 32 : 16;
@@ -578,6 +568,73 @@ se_status se_rs_plan_create(int D, double L, double xi, double rc, long n_max, s
   return SE_OK;
 }
 
+bool rs_args_ok(int D, double xi, long n_max, se_precision prec) {
+  return D >= 0 && D <= 3 && xi > 0.0 && std::isfinite(xi) && (prec == SE_F64 || prec == SE_F32) &&
+         n_max <= 0x7fffffffL;
+}
+}  // namespace
+
+extern "C" {
+
+se_status se_rs_cells(double L, double rc, long n_max, int cells_per_rc, int* cells, int* span) {
+  if (!cells || !span) return SE_ERR_ARG;
+  if (!(L > 0.0) || !(rc > 0.0) || !std::isfinite(L) || !std::isfinite(rc) || n_max < 0) return SE_ERR_PARAM;
+  const int k = cells_per_rc <= 0 ? 2 : cells_per_rc;
+  if (k > 8) return SE_ERR_PARAM;
+  // at most about one cell per charge, and kRsMaxCells per direction
+  const int by_n = std::max(1, (int)std::floor(std::cbrt((double)std::max(1L, n_max)) + 1e-9));
+  const int c = (int)std::max(1.0, std::min({std::floor(k * L / rc), (double)by_n, (double)se::kRsMaxCells}));
+  *cells = c;
+  *span = rs_span(L / c, rc);
+  return SE_OK;
+}
+
+se_status se_rs_cells_box(const double* Ls, double rc, long n_max, int cells_per_rc, int* cells, int* span) {
+  if (!Ls || !cells || !span) return SE_ERR_ARG;
+  if (!(rc > 0.0) || !std::isfinite(rc) || n_max < 0) return SE_ERR_PARAM;
+  for (int d = 0; d < 3; ++d)
+    if (!(Ls[d] > 0.0) || !std::isfinite(Ls[d])) return SE_ERR_PARAM;
+  const int k = cells_per_rc <= 0 ? 2 : cells_per_rc;
+  if (k > 8) return SE_ERR_PARAM;
+  // at most about one cell per charge: cells per unit length at that density
+  const double V = Ls[0] * Ls[1] * Ls[2];
+  if (!(V > 0.0) || !std::isfinite(V)) return SE_ERR_PARAM;
+  const double per = std::cbrt((double)std::max(1L, n_max) / V);
+  for (int d = 0; d < 3; ++d) {
+    const double by_n = std::max(1.0, std::floor(Ls[d] * per + 1e-9));
+    cells[d] = (int)std::max(1.0, std::min({std::floor(k * Ls[d] / rc), by_n, (double)se::kRsMaxCells}));
+    span[d] = rs_span(Ls[d] / cells[d], rc);
+  }
+  return SE_OK;
+}
+
+se_status se_rs_plan_create(int D, double L, double xi, double rc, long n_max, se_precision prec,
+                            int cells_per_rc, void* hip_stream, se_rs_plan** out) {
+  (void)hip_stream;
+  if (!out) return SE_ERR_ARG;
+  *out = nullptr;
+  if (!rs_args_ok(D, xi, n_max, prec)) return SE_ERR_PARAM;
+  int c, s;
+  const se_status st = se_rs_cells(L, rc, n_max, cells_per_rc, &c, &s);
+  if (st != SE_OK) return st;
+  const int c3[3] = {c, c, c}, s3[3] = {s, s, s};
+  const double L3[3] = {L, L, L};
+  return rs_plan_make(D, c3, s3, L3, xi, rc, n_max, prec, out);
+}
+
+se_status se_rs_plan_create_box(const double* Ls, double xi, double rc, long n_max, se_precision prec,
+                                int cells_per_rc, void* hip_stream, se_rs_plan** out) {
+  (void)hip_stream;
+  if (!out) return SE_ERR_ARG;
+  *out = nullptr;
+  if (!Ls) return SE_ERR_ARG;
+  if (!rs_args_ok(3, xi, n_max, prec)) return SE_ERR_PARAM;
+  int c3[3], s3[3];
+  const se_status st = se_rs_cells_box(Ls, rc, n_max, cells_per_rc, c3, s3);
+  if (st != SE_OK) return st;
+  return rs_plan_make(3, c3, s3, Ls, xi, rc, n_max, prec, out);
+}
+
 se_status se_rs_workspace_size(const se_rs_plan* plan, size_t* bytes) {
   if (!plan || !bytes) return SE_ERR_ARG;
   *bytes = plan->ws_bytes;
@@ -603,8 +660,8 @@ se_status se_rs_set_workspace(se_rs_plan* p, void* ptr, size_t bytes) {
 
 se_status se_rs_get_info(const se_rs_plan* plan, int* cells, int* span, size_t* device_bytes) {
   if (!plan) return SE_ERR_ARG;
-  if (cells) *cells = plan->g.c;
-  if (span) *span = plan->g.s;
+  if (cells) *cells = plan->g.c[0];
+  if (span) *span = plan->g.s[0];
   if (device_bytes) *device_bytes = plan->bytes;
   return SE_OK;
 }

@@ -14,6 +14,9 @@ and empty cells; a cluster holding more charges than one cell sorts; empty and
 one-charge inputs; float32 inputs; accumulation; device status errors; and the
 full potential (real space + k space + self term, all on the GPU) against the
 Madelung constants of rock salt, the square lattice and the alternating chain.
+Triply periodic rectangular boxes: parity with the direct rectangular-box sum,
+equal sides reproducing the cube bit for bit, and rock salt's Madelung constant
+in a rectangular supercell.
 """
 import math
 
@@ -218,6 +221,92 @@ def test_full_potential_madelung(D, const):
     print(f"  madelung D={D}: {m[0]:.15f} (cells {rs.cells}, span {rs.span})")
     np.testing.assert_allclose(m, const, rtol=0, atol=1e-10)
     np.testing.assert_allclose(g.cpu().numpy(), 0.0, atol=1e-8)   # every ion sits at a symmetric site
+    assert abs(float(E) - 0.5 * float(np.dot(q, -const * q / a))) < 1e-9 * len(q)
+
+
+def _box_system(N, Ls, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.random((N, 3)) * np.asarray(Ls)
+    q = rng.standard_normal(N)
+    return x, q - q.mean()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("Ls,rc", [((1.0, 1.5, 0.5), 0.12), ((1.0, 1.5, 0.5), 0.3), ((1.0, 1.5, 0.5), 0.7),
+                                   ((0.6, 1.0, 1.9), 0.2), ((2.0, 0.35, 1.0), 0.45)])
+def test_rectangular_box_parity_with_oracle(Ls, rc, prec):
+    """Triply periodic rectangular boxes (cells, spans and wraps per
+    direction; cutoffs beyond the short side reach several images) against
+    the direct rectangular-box real-space sum, to the cube's bounds."""
+    print(f"case real space box {Ls} rc={rc} {prec}", flush=True)
+    N = 700
+    xi = 4.8 / rc
+    x, q = _box_system(N, Ls, 5100 + int(100 * rc))
+    rs = RealSpace(3, Ls, xi, rc, prec=prec, n_max=N)
+    phi, g, E = run(rs, x, q)
+    pr, gr = direct.real_space_box3(Ls, xi, rc, x, q)
+    Er = 0.5 * float(np.dot(q, pr))
+    tol_phi, tol_g = (1e-13, 1e-12) if prec == "f64" else (3e-6, 3e-6)
+    print(f"  cells {rs.cells} span {rs.span}: phi {rel(phi, pr):.2e} grad {rel(g, gr):.2e} "
+          f"energy {abs(E - Er) / abs(Er):.2e}")
+    assert rel(phi, pr) < tol_phi
+    assert rel(g, gr) < tol_g
+    if prec == "f64":
+        assert abs(E - Er) <= 1e-12 * abs(Er)
+    else:
+        # E^R sums q phi^R in FP64 over FP32 charges and potentials: the error
+        # is that of phi^R through the charges (Cauchy-Schwarz) plus the
+        # rounding of each charge; neutral random charges cancel most of E^R,
+        # so a relative bound on E^R alone would not follow from phi's
+        bound = 0.5 * (np.linalg.norm(q) * np.linalg.norm(phi - pr) + 2.0 ** -24 * np.abs(q * pr).sum())
+        assert abs(E - Er) <= 1.01 * bound + 1e-12 * abs(Er)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_rectangular_box_of_equal_sides_is_the_cube(prec):
+    """A box plan with three equal sides takes the cube's cells and gives the
+    cube plan's results bit for bit."""
+    N, L, rc = 2000, 1.3, 0.2
+    x, q = wl.system(N, L, 5200, "uniform")
+    cube = RealSpace(3, L, 4.0 / rc, rc, prec=prec, n_max=N)
+    box = RealSpace(3, (L, L, L), 4.0 / rc, rc, prec=prec, n_max=N)
+    assert box.cells == (cube.cells,) * 3 and box.span == (cube.span,) * 3
+    a, b = run(cube, x, q), run(box, x, q)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
+
+
+def test_full_potential_madelung_rectangular_box():
+    """Rock salt (spacing a = 1/4) in a 1 x 1.5 x 0.5 box, 4 x 6 x 2 ions:
+    the k-space part from se_eval in the rectangular box (M = 40, My = 60,
+    Mz = 20, PKB P = 16), the real-space part from the rectangular real-space
+    plan, plus the self term, give the rock-salt Madelung constant at every
+    ion and zero gradient."""
+    print("case madelung box", flush=True)
+    a = 0.25
+    Ls = (1.0, 1.5, 0.5)
+    n = (4, 6, 2)
+    off = np.array([0.1234, 0.2345, 0.3456]) * a
+    pts, qs = [], []
+    for i in range(n[0]):
+        for j in range(n[1]):
+            for k in range(n[2]):
+                pts.append(np.array([i, j, k]) * a + off)
+                qs.append((-1.0) ** (i + j + k))
+    x, q = np.array(pts), np.array(qs)
+    xi, M, P = 6.0, 40, 16
+    ks = SpectralEwald(3, 1.0, xi, M, P, window="pkb", prec="f64", n_max=len(q), My=60, Mz=20)
+    assert ks.box == Ls
+    rs = RealSpace(3, ks.box, xi, direct.real_space_cutoff(xi), prec="f64", n_max=len(q))
+    xt = torch.tensor(x, dtype=torch.float64, device=DEV)
+    qt = torch.tensor(q, dtype=torch.float64, device=DEV)
+    out = ks(xt, qt, add_self=True, out_grad=True)
+    phi, g, E = rs(xt, qt, out_grad=True, accumulate=True, out=out)
+    torch.cuda.synchronize()
+    m = -phi.cpu().numpy() * a / q
+    const = 1.747564594633182
+    print(f"  madelung box: {m[0]:.15f} (cells {rs.cells}, span {rs.span})")
+    np.testing.assert_allclose(m, const, rtol=0, atol=1e-10)
+    np.testing.assert_allclose(g.cpu().numpy(), 0.0, atol=1e-8)
     assert abs(float(E) - 0.5 * float(np.dot(q, -const * q / a))) < 1e-9 * len(q)
 
 

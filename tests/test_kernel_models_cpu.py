@@ -7,6 +7,7 @@ the planner enforces (at most kMaxFoldImages box images per direction, at
 most kMaxPieces anchor pieces, at most kMaxClipRanges particle ranges) are
 shown to cover every geometry it accepts.
 """
+import itertools
 import math
 
 import numpy as np
@@ -294,56 +295,97 @@ def test_slot_walk_equals_direct_indexing():
 
 # --- real space: the pair enumeration of the cell list ------------------------
 
-def rs_cells(L, rc, n_max, k=2):
-    by_n = max(1, int(math.floor(float(np.cbrt(max(1, n_max))) + 1e-9)))
-    c = int(max(1.0, min(math.floor(k * L / rc), by_n, 160)))
-    h = L / c
+def rs_span(h, rc):
     s = max(1, math.ceil(rc / h))
     while s > 1 and (s - 1) * h >= rc:
         s -= 1
     while s * h < rc:
         s += 1
-    return c, s
+    return s
 
 
-def rs_candidates(D, c, s, L, rc, cells, t):
+def rs_cells(L, rc, n_max, k=2):
+    by_n = max(1, int(math.floor(float(np.cbrt(max(1, n_max))) + 1e-9)))
+    c = int(max(1.0, min(math.floor(k * L / rc), by_n, 160)))
+    return c, rs_span(L / c, rc)
+
+
+def rs_cells_box(Ls, rc, n_max, k=2):
+    per = (max(1, n_max) / (Ls[0] * Ls[1] * Ls[2])) ** (1 / 3)
+    c = [int(max(1.0, min(math.floor(k * Ld / rc), max(1, math.floor(Ld * per + 1e-9)), 160))) for Ld in Ls]
+    return c, [rs_span(Ls[d] / c[d], rc) for d in range(3)]
+
+
+def rs_candidates(D, c, s, Ls, rc, cells, t):
     """The kernel's candidates for target t: (neighbour, image vector) in the
-    order it visits them."""
-    h = L / c
+    order it visits them; c, s and Ls per direction."""
+    h = [Ls[d] / c[d] for d in range(3)]
     ix, iy, iz = cells[t]
     out = []
     by_cell = {}
     for j, cc in enumerate(cells):
         by_cell.setdefault(tuple(cc), []).append(j)
-    for dz in range(-s, s + 1):
+    for dz in range(-s[2], s[2] + 1):
         uz = iz + dz
-        if D < 3 and not 0 <= uz < c:
+        if D < 3 and not 0 <= uz < c[2]:
             continue
-        qz = uz // c
-        gz = max(0, abs(dz) - 1) * h
-        for dy in range(-s, s + 1):
+        qz = uz // c[2]
+        gz = max(0, abs(dz) - 1) * h[2]
+        for dy in range(-s[1], s[1] + 1):
             uy = iy + dy
-            if D < 2 and not 0 <= uy < c:
+            if D < 2 and not 0 <= uy < c[1]:
                 continue
-            qy = uy // c
-            gy = max(0, abs(dy) - 1) * h
+            qy = uy // c[1]
+            gy = max(0, abs(dy) - 1) * h[1]
             rem = rc * rc - gz * gz - gy * gy
             if rem <= 0.0:
                 continue
-            dm = s
-            while dm > 1 and ((dm - 1) * h) ** 2 >= rem:
+            dm = s[0]
+            while dm > 1 and ((dm - 1) * h[0]) ** 2 >= rem:
                 dm -= 1
             xa, xb = ix - dm, ix + dm
             if D < 1:
-                xa, xb = max(xa, 0), min(xb, c - 1)
-            for qx in range(xa // c, xb // c + 1):
-                lo, hi = max(xa, qx * c) - qx * c, min(xb, qx * c + c - 1) - qx * c
+                xa, xb = max(xa, 0), min(xb, c[0] - 1)
+            for qx in range(xa // c[0], xb // c[0] + 1):
+                lo, hi = max(xa, qx * c[0]) - qx * c[0], min(xb, qx * c[0] + c[0] - 1) - qx * c[0]
                 for cx in range(lo, hi + 1):
-                    for j in by_cell.get((cx, uy - qy * c, uz - qz * c), []):
+                    for j in by_cell.get((cx, uy - qy * c[1], uz - qz * c[2]), []):
                         if (qx, qy, qz) == (0, 0, 0) and j == t:
                             continue
                         out.append((j, (qx, qy, qz)))
     return out
+
+
+def _check_enumeration(D, Ls, rc, n, seed, ks=(1, 2, 3), cells_of=None):
+    rng = np.random.default_rng(seed)
+    Ls = np.asarray(Ls, dtype=float)
+    x = rng.random((n, 3)) * Ls
+    for k in ks:
+        c, s = cells_of(k)
+        c, s = np.asarray(c), np.asarray(s)
+        h = Ls / c
+        cells = np.minimum((x / h).astype(int), c - 1)
+        K = [math.ceil(rc / Ls[d]) + 1 for d in range(3)]
+        for t in range(0, n, 7):
+            cand = rs_candidates(D, c, s, Ls, rc, [tuple(v) for v in cells], t)
+            assert len(cand) == len(set(cand))
+            got = set()
+            box2 = (rc * (1.0 + 1e-5) + 1e-5 * h.max()) ** 2
+            for j, (qx, qy, qz) in cand:
+                shift = np.array([qx, qy, qz]) * Ls
+                p = x[j] + shift - cells[t] * h   # in the target cell's frame
+                e = np.maximum(np.maximum(-p, p - h), 0.0)
+                if float(e @ e) >= box2:
+                    continue
+                if np.linalg.norm(x[t] - (x[j] + shift)) < rc:
+                    got.add((j, (qx, qy, qz)))
+            # brute force over every charge and image vector
+            img = np.array(list(itertools.product(*[range(-K[d], K[d] + 1) if D > d else (0,)
+                                                    for d in range(3)])))
+            r = np.linalg.norm(x[t][None, None, :] - x[:, None, :] - (img * Ls)[None, :, :], axis=2)
+            want = {(int(j), tuple(int(v) for v in img[m])) for j, m in zip(*np.nonzero(r < rc))
+                    if not (j == t and not img[m].any())}
+            assert got == want, (D, tuple(Ls), rc, k, t)
 
 
 @pytest.mark.parametrize("D", [3, 2, 1, 0])
@@ -353,36 +395,25 @@ def test_real_space_enumeration_visits_each_pair_once(D, rc_over_L):
     zero shift excluded) is visited exactly once, for spans s = 1-3 and
     cutoffs beyond the box, also after the kernel drops the candidates that
     lie rc or more from the target cell's box."""
-    rng = np.random.default_rng(int(100 * rc_over_L) + D)
     L, n = 1.0, 90
-    x = rng.random((n, 3)) * L
     rc = rc_over_L * L
-    for k in (1, 2, 3):
+
+    def cells_of(k):
         c, s = rs_cells(L, rc, n, k)
-        h = L / c
-        cells = np.minimum((x / h).astype(int), c - 1)
-        K = math.ceil(rc / L) + 1
-        rng_img = range(-K, K + 1)
-        for t in range(0, n, 7):
-            cand = rs_candidates(D, c, s, L, rc, [tuple(v) for v in cells], t)
-            assert len(cand) == len(set(cand))
-            got = set()
-            box2 = (rc * (1.0 + 1e-5) + 1e-5 * h) ** 2
-            for j, (qx, qy, qz) in cand:
-                shift = np.array([qx, qy, qz]) * L
-                p = x[j] + shift - cells[t] * h   # in the target cell's frame
-                e = np.maximum(np.maximum(-p, p - h), 0.0)
-                if float(e @ e) >= box2:
-                    continue
-                if np.linalg.norm(x[t] - (x[j] + shift)) < rc:
-                    got.add((j, (qx, qy, qz)))
-            want = set()
-            for j in range(n):
-                for a in (rng_img if D >= 1 else (0,)):
-                    for b in (rng_img if D >= 2 else (0,)):
-                        for cz in (rng_img if D >= 3 else (0,)):
-                            if j == t and (a, b, cz) == (0, 0, 0):
-                                continue
-                            if np.linalg.norm(x[t] - x[j] - np.array([a, b, cz]) * L) < rc:
-                                want.add((j, (a, b, cz)))
-            assert got == want, (D, rc, k, t)
+        return [c] * 3, [s] * 3
+
+    _check_enumeration(D, (L, L, L), rc, n, int(100 * rc_over_L) + D, cells_of=cells_of)
+
+
+@pytest.mark.parametrize("Ls", [(1.0, 1.5, 0.5), (0.6, 1.0, 1.9), (2.0, 0.35, 1.0)])
+@pytest.mark.parametrize("rc", [0.12, 0.3, 0.7, 1.3])
+def test_real_space_enumeration_in_rectangular_boxes(Ls, rc):
+    """The same in triply periodic rectangular boxes, with cells, spans and
+    cell sides per direction (spans differing between directions, cutoffs
+    beyond the short side)."""
+    n = 90
+
+    def cells_of(k):
+        return rs_cells_box(Ls, rc, n, k)
+
+    _check_enumeration(3, Ls, rc, n, int(1000 * rc + 10 * Ls[1]), cells_of=cells_of)

@@ -150,6 +150,35 @@ def test_real_space_cells_cover_the_cutoff(L, rc, n_max, k):
     assert c == max(1, min(math.floor(kk * L / rc), math.floor(max(1, n_max) ** (1 / 3) + 1e-9), 160))
 
 
+@pytest.mark.parametrize("Ls,rc,n_max,k", [((1.0, 1.25, 0.75), 0.071, 10**6, 0), ((1.0, 2.0, 0.5), 0.3, 1000, 2),
+                                           ((0.4, 1.0, 1.0), 0.5, 64, 1), ((1.0, 1.0, 3.0), 1e-4, 10**7, 8),
+                                           ((2.0, 1.5, 1.0), 2.5, 0, 0), ((1.0, 0.5, 0.25), 0.01, 5000, 3)])
+def test_real_space_box_cells_cover_the_cutoff(Ls, rc, n_max, k):
+    """Rectangular box: per direction, s_d cells of side L_d/c_d reach rc and
+    s_d - 1 do not; c_d follows the cells-per-cutoff, density and 160
+    limits, with about one cell per charge at most."""
+    c, s = L_.se_rs_cells_box(Ls, rc, n_max, k)
+    kk = 2 if k <= 0 else k
+    V = Ls[0] * Ls[1] * Ls[2]
+    for d in range(3):
+        h = Ls[d] / c[d]
+        assert 1 <= c[d] <= 160 and s[d] >= 1
+        assert s[d] * h >= rc and (s[d] == 1 or (s[d] - 1) * h < rc)
+        by_n = max(1, math.floor(Ls[d] * (max(1, n_max) / V) ** (1 / 3) + 1e-9))
+        assert c[d] == max(1, min(math.floor(kk * Ls[d] / rc), by_n, 160))
+    assert c[0] * c[1] * c[2] <= max(1, n_max) * (1 + 1e-6) or min(c) == 1
+
+
+@pytest.mark.parametrize("L", [1.0, 0.37, 3.0])
+@pytest.mark.parametrize("rc,n_max,k", [(0.071, 10**6, 0), (0.3, 1000, 2), (2.5, 64, 1), (1e-4, 10**7, 8),
+                                        (0.2, 3400, 3), (1.0 / 3.0, 27, 1), (0.05, 8000, 2)])
+def test_real_space_box_cells_of_a_cube_match_the_cube(L, rc, n_max, k):
+    """A rectangular box with equal sides gets the cube's cell list."""
+    c, s = L_.se_rs_cells(L, rc * L, n_max, k)
+    cb, sb = L_.se_rs_cells_box((L, L, L), rc * L, n_max, k)
+    assert cb == (c, c, c) and sb == (s, s, s)
+
+
 def test_real_space_cells_reject_invalid():
     lib = L.load()
     c, s = ctypes.c_int(), ctypes.c_int()
@@ -161,6 +190,20 @@ def test_real_space_cells_reject_invalid():
     assert lib.se_rs_plan_create(4, 1.0, 1.0, 0.1, 10, 0, 0, None, ctypes.byref(plan)) == L.SE_ERR_PARAM
     assert lib.se_rs_plan_create(3, 1.0, -1.0, 0.1, 10, 0, 0, None, ctypes.byref(plan)) == L.SE_ERR_PARAM
     assert lib.se_rs_plan_create(3, 1.0, 1.0, 0.1, 10, 5, 0, None, ctypes.byref(plan)) == L.SE_ERR_PARAM
+    c3, s3 = (ctypes.c_int * 3)(), (ctypes.c_int * 3)()
+    for Ls, rc, n, k in [((1.0, 0.0, 1.0), 0.1, 10, 0), ((1.0, 1.0, float("inf")), 0.1, 10, 0),
+                         ((1.0, 1.0, 1.0), -0.1, 10, 0), ((1.0, 1.0, 1.0), 0.1, -1, 0),
+                         ((1.0, 1.0, 1.0), 0.1, 10, 9), ((float("nan"), 1.0, 1.0), 0.1, 10, 0)]:
+        sides = (ctypes.c_double * 3)(*Ls)
+        assert lib.se_rs_cells_box(sides, rc, n, k, c3, s3) == L.SE_ERR_PARAM
+        assert lib.se_rs_plan_create_box(sides, 1.0, rc, n, 0, k, None, ctypes.byref(plan)) == L.SE_ERR_PARAM
+    sides = (ctypes.c_double * 3)(1.0, 2.0, 1.5)
+    assert lib.se_rs_cells_box(None, 0.1, 10, 0, c3, s3) == L.SE_ERR_ARG
+    assert lib.se_rs_cells_box(sides, 0.1, 10, 0, None, s3) == L.SE_ERR_ARG
+    assert lib.se_rs_plan_create_box(None, 1.0, 0.1, 10, 0, 0, None, ctypes.byref(plan)) == L.SE_ERR_ARG
+    assert lib.se_rs_plan_create_box(sides, 1.0, 0.1, 10, 0, 0, None, None) == L.SE_ERR_ARG
+    assert lib.se_rs_plan_create_box(sides, 0.0, 0.1, 10, 0, 0, None, ctypes.byref(plan)) == L.SE_ERR_PARAM
+    assert lib.se_rs_plan_create_box(sides, 1.0, 0.1, 10, 5, 0, None, ctypes.byref(plan)) == L.SE_ERR_PARAM
     assert lib.se_rs_eval(None, 0, None, None, None, None, None, 0, None) == L.SE_ERR_ARG
     assert lib.se_rs_plan_destroy(None) == L.SE_OK
 

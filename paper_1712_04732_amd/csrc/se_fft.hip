@@ -440,7 +440,7 @@ __device__ __forceinline__ void scale_pencil(const FftClass& C, const ScaleRow<T
 // memory (TF) and sample-major (t = e div B, p = e mod B) otherwise, so that
 // neighbouring lanes touch neighbouring addresses.  The thread tracks the
 // sample t, the pencil p, a global byte offset g = p gs0 + t gst and an LDS
-// index l = t lt + p lp, all advanced by additions (B <= 64 divides
+// index l = t lt + p lp, all advanced by additions (B <= 128 divides
 // kFftBlock).
 template <bool TF, typename OFF>
 struct SlotWalk {
@@ -658,7 +658,7 @@ __device__ __forceinline__ void stage_fft(const FftPass& P, int cls, int b0s, in
   const bool ip = P.inplace;
   lds<vec2<T>>* tw = reinterpret_cast<lds<vec2<T>>*>(smem);
   lds<vec2<T>>* buf = tw + P.nmax;
-  lds<vec2<T>>* buf2 = buf + P.nmax * ((1 << lgB) + 1);   // only if not in place
+  lds<vec2<T>>* buf2 = buf + P.nmax * Bp;   // only if not in place
 
   if (C.in_st == 1) fft_load<T, KIND, true, OFF>(C, b0s, b1, cnt, lgB, pair, Bp, buf, tw);
   else fft_load<T, KIND, false, OFF>(C, b0s, b1, cnt, lgB, pair, Bp, buf, tw);
@@ -744,7 +744,9 @@ __global__ __launch_bounds__(kFftBlock, (kFftMinWaves<T, OFF>)) void batch_fft_k
 size_t fft_lds_bytes(const FftPass& p, bool f64) {
   const size_t c = f64 ? 16 : 8;
   const size_t nbuf = p.inplace ? 1 : 2;
-  return c * ((size_t)p.nmax + nbuf * (((size_t)1 << p.lgB) + 1) * p.nmax);
+  // complex transforms per block: B, or B / 2 pencil pairs for the real passes
+  const bool pair = (p.kind == K_R2C || p.kind == K_C2R) && p.lgB > 0;
+  return c * ((size_t)p.nmax + nbuf * (((size_t)1 << (p.lgB - (pair ? 1 : 0))) + 1) * p.nmax);
 }
 
 template <typename T, typename OFF>

@@ -423,14 +423,18 @@ static bool finish_pass(se_plan* pl, se::FftPass& ps, int kind, int ncls,
   ps.kind = kind;
   ps.nmax = 0;
   for (int c = 0; c < ncls; ++c) ps.nmax = std::max(ps.nmax, ps.cls[c].n);
-  // pencils per block: the largest power of two B <= 64 with n B within the
-  // samples cap and the LDS budget (twiddles n, samples n (B + 1))
+  // pencils per block: the largest power of two B with n F within the
+  // samples cap, the LDS budget (twiddles n, samples n (F + 1)) and the
+  // registers of an in-place stage, where F is the number of complex
+  // transforms of a block: B, or B / 2 for the real passes, which pair two
+  // real pencils into one complex transform (F <= 64 either way)
   const size_t esz = pl->f64 ? 16 : 8;
-  // (LDS: twiddles n, two sample buffers n (B + 1))
+  const bool real = kind == se::K_R2C || kind == se::K_C2R;
+  auto cpx = [&](long B2) { return real && B2 >= 2 ? B2 / 2 : B2; };
   const long cap = pl->fft_cap > 0 ? pl->fft_cap : (pl->f64 ? 1024 : 2048);
   // in place unless the samples cap (or a single pencil) exceeds kFftInplaceCap
   ps.inplace = (cap <= se::kFftInplaceCap && ps.nmax <= se::kFftInplaceCap) ? 1 : 0;
-  auto lds_of = [&](long B2) { return esz * (size_t)ps.nmax * (1 + (ps.inplace ? 1 : 2) * (B2 + 1)); };
+  auto lds_of = [&](long B2) { return esz * (size_t)ps.nmax * (1 + (ps.inplace ? 1 : 2) * (cpx(B2) + 1)); };
   // in place, every stage of every class keeps its butterflies within the
   // registers the kernel holds for them (kFftIpIters)
   auto fits_regs = [&](long B2) {
@@ -438,15 +442,16 @@ static bool finish_pass(se_plan* pl, se::FftPass& ps, int kind, int ncls,
     for (int c = 0; c < ncls; ++c)
       for (int k = 0; k < ps.cls[c].nst; ++k) {
         const int R = ps.cls[c].rad[k];
-        if ((long)(ps.cls[c].n / R) * B2 > (long)se::kFftIpIters(R) * se::kFftBlock) return false;
+        if ((long)(ps.cls[c].n / R) * cpx(B2) > (long)se::kFftIpIters(R) * se::kFftBlock) return false;
       }
     return true;
   };
   if (!fits_regs(1)) ps.inplace = 0;   // a single pencil needs more: alternate two buffers
   int lgB = 0;
-  while (lgB < 6) {
+  while (lgB < (real ? 7 : 6)) {
     const long B2 = 2L << lgB;
-    if ((long)ps.nmax * B2 > cap || lds_of(B2) > std::min(pl->lds_limit, se::kFftLdsSoft) || !fits_regs(B2)) break;
+    if ((long)ps.nmax * cpx(B2) > cap || lds_of(B2) > std::min(pl->lds_limit, se::kFftLdsSoft) || !fits_regs(B2))
+      break;
     ++lgB;
   }
   if (lds_of(1L << lgB) > pl->lds_max) return false;

@@ -274,12 +274,13 @@ def test_slot_walk_equals_direct_indexing():
     coordinates: pencil-major (p = e div n, t = e mod n) when the transform
     direction is contiguous, sample-major (t = e div B, p = e mod B)
     otherwise, and the matching global offsets and LDS indices, for every
-    7-smooth length and pencil count of a block (n B <= 8192)."""
+    7-smooth length and pencil count of a block (n B <= 8192, and up to
+    B = 128 real pencils, n B <= 16384, for the paired real passes)."""
     rng = np.random.default_rng(1)
     for n in _smooth_lengths(8192):
-        for lgB in range(0, 7):
+        for lgB in range(0, 8):
             B = 1 << lgB
-            if n * B > 8192:
+            if n * B > (16384 if lgB > 0 else 8192):
                 break
             gs0, gst = int(rng.integers(1, 5000)), int(rng.integers(1, 5000))
             lt, lp = B + 1, 1

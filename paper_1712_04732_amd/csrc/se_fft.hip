@@ -172,26 +172,30 @@ __device__ __forceinline__ int rfl(int v) { return __builtin_amdgcn_readfirstlan
 // 2^13 2^-21 / d = 2^-8 / d, far inside the 1/(2d) that separates it from an
 // integer, so truncation is still exact.
 __device__ __forceinline__ float quot_recip(int d) { return __builtin_amdgcn_rcpf((float)d); }
+// The same for a divisor uniform over the workgroup, kept in a scalar register.
+__device__ __forceinline__ float quot_recip_u(int d) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(quot_recip(d))));
+}
 
-// One Stockham stage from src to dst over B = 2^lgB interleaved pencils stored
-// sample-major with pitch Bp (sample t of pencil p at t Bp + p).  Butterfly j
-// (pencil p) reads samples j + r n/R, multiplies input r by the twiddle
+// One Stockham stage from src to dst over F interleaved pencils stored
+// sample-major with pitch Bp (sample t of pencil p at t Bp + p).  Slot e holds
+// butterfly j = e div F of pencil p = e mod F; butterfly j reads samples j + r n/R, multiplies input r by the twiddle
 // exp(sign 2 pi i r k/(Ns R)) = tw[r k tws] (k = j mod Ns, tws = n/(Ns R)),
 // and writes outputs (j div Ns) Ns R + k + r Ns.  The first stage (Ns = 1)
 // has no twiddles.
 template <typename T, int R, bool FIRST, int SIGN>
 __device__ __forceinline__ void fft_stage(const lds<vec2<T>>* __restrict__ src, lds<vec2<T>>* __restrict__ dst,
-                                          const lds<vec2<T>>* __restrict__ tw, int n, int Ns, int tws, int lgB,
+                                          const lds<vec2<T>>* __restrict__ tw, int n, int Ns, int tws, int F,
                                           int Bp) {
   const int nb = n / R;
-  const int total = nb << lgB;
-  const int mask = (1 << lgB) - 1;
+  const int total = __mul24(nb, F);
+  const float inv_f = quot_recip_u(F);
   const int sstr = nb * Bp;   // between the inputs of a butterfly
   const int dstr = Ns * Bp;   // between its outputs
   const int nsr = Ns * R;
   const float inv_ns = quot_recip(Ns);
   for (int e = threadIdx.x; e < total; e += kFftBlock) {
-    const int j = e >> lgB, p = e & mask;
+    const int j = fdiv(e, inv_f), p = e - __mul24(j, F);
     const lds<vec2<T>>* s = src + (__mul24(j, Bp) + p);
     cx<T> v[R];
 #pragma unroll
@@ -219,14 +223,14 @@ __device__ __forceinline__ void fft_stage(const lds<vec2<T>>* __restrict__ src, 
 
 template <typename T, bool FIRST, int SIGN>
 __device__ __forceinline__ void fft_stage_r(int R, const lds<vec2<T>>* src, lds<vec2<T>>* dst,
-                                            const lds<vec2<T>>* tw, int n, int Ns, int tws, int lgB, int Bp) {
+                                            const lds<vec2<T>>* tw, int n, int Ns, int tws, int F, int Bp) {
   switch (R) {
-    case 2: fft_stage<T, 2, FIRST, SIGN>(src, dst, tw, n, Ns, tws, lgB, Bp); break;
-    case 3: fft_stage<T, 3, FIRST, SIGN>(src, dst, tw, n, Ns, tws, lgB, Bp); break;
-    case 4: fft_stage<T, 4, FIRST, SIGN>(src, dst, tw, n, Ns, tws, lgB, Bp); break;
-    case 5: fft_stage<T, 5, FIRST, SIGN>(src, dst, tw, n, Ns, tws, lgB, Bp); break;
-    case 7: fft_stage<T, 7, FIRST, SIGN>(src, dst, tw, n, Ns, tws, lgB, Bp); break;
-    default: fft_stage<T, 8, FIRST, SIGN>(src, dst, tw, n, Ns, tws, lgB, Bp); break;
+    case 2: fft_stage<T, 2, FIRST, SIGN>(src, dst, tw, n, Ns, tws, F, Bp); break;
+    case 3: fft_stage<T, 3, FIRST, SIGN>(src, dst, tw, n, Ns, tws, F, Bp); break;
+    case 4: fft_stage<T, 4, FIRST, SIGN>(src, dst, tw, n, Ns, tws, F, Bp); break;
+    case 5: fft_stage<T, 5, FIRST, SIGN>(src, dst, tw, n, Ns, tws, F, Bp); break;
+    case 7: fft_stage<T, 7, FIRST, SIGN>(src, dst, tw, n, Ns, tws, F, Bp); break;
+    default: fft_stage<T, 8, FIRST, SIGN>(src, dst, tw, n, Ns, tws, F, Bp); break;
   }
 }
 
@@ -234,7 +238,7 @@ __device__ __forceinline__ void fft_stage_r(int R, const lds<vec2<T>>* src, lds<
 // alternating between the two buffers; returns the buffer holding the result.
 template <typename T, int SIGN>
 __device__ __forceinline__ lds<vec2<T>>* fft_run(lds<vec2<T>>* b0, lds<vec2<T>>* b1, const lds<vec2<T>>* tw,
-                                                 const FftClass& C, int lgB, int Bp) {
+                                                 const FftClass& C, int F, int Bp) {
   lds<vec2<T>>* src = b0;
   lds<vec2<T>>* dst = b1;
   const int n = C.n, nst = C.nst;
@@ -244,8 +248,8 @@ __device__ __forceinline__ lds<vec2<T>>* fft_run(lds<vec2<T>>* b0, lds<vec2<T>>*
     const int R = (int)(radices & 15u);
     radices >>= 4;
     const int tws = rem / R;
-    if (s == 0) fft_stage_r<T, true, SIGN>(R, src, dst, tw, n, Ns, tws, lgB, Bp);
-    else fft_stage_r<T, false, SIGN>(R, src, dst, tw, n, Ns, tws, lgB, Bp);
+    if (s == 0) fft_stage_r<T, true, SIGN>(R, src, dst, tw, n, Ns, tws, F, Bp);
+    else fft_stage_r<T, false, SIGN>(R, src, dst, tw, n, Ns, tws, F, Bp);
     __syncthreads();
     lds<vec2<T>>* tmp = src;
     src = dst;
@@ -262,11 +266,11 @@ __device__ __forceinline__ lds<vec2<T>>* fft_run(lds<vec2<T>>* b0, lds<vec2<T>>*
 // barrier, writes them back over the inputs.
 template <typename T, int R, bool FIRST, int SIGN>
 __device__ __forceinline__ void fft_stage_ip(lds<vec2<T>>* buf, const lds<vec2<T>>* __restrict__ tw, int n, int Ns,
-                                             int tws, int lgB, int Bp) {
+                                             int tws, int F, int Bp) {
   constexpr int IT = kFftIpIters(R);
   const int nb = n / R;
-  const int total = nb << lgB;
-  const int mask = (1 << lgB) - 1;
+  const int total = __mul24(nb, F);
+  const float inv_f = quot_recip_u(F);
   const int sstr = nb * Bp;
   const int dstr = Ns * Bp;
   const int nsr = Ns * R;
@@ -278,7 +282,7 @@ __device__ __forceinline__ void fft_stage_ip(lds<vec2<T>>* buf, const lds<vec2<T
     const int e = threadIdx.x + it * kFftBlock;
     dofs[it] = -1;
     if (e < total) {
-      const int j = e >> lgB, p = e & mask;
+      const int j = fdiv(e, inv_f), p = e - __mul24(j, F);
       const lds<vec2<T>>* s = buf + (__mul24(j, Bp) + p);
 #pragma unroll
       for (int r = 0; r < R; ++r) v[it][r] = lget<T>(s, r * sstr);
@@ -312,20 +316,20 @@ __device__ __forceinline__ void fft_stage_ip(lds<vec2<T>>* buf, const lds<vec2<T
 
 template <typename T, bool FIRST, int SIGN>
 __device__ __forceinline__ void fft_stage_ip_r(int R, lds<vec2<T>>* buf, const lds<vec2<T>>* tw, int n, int Ns,
-                                               int tws, int lgB, int Bp) {
+                                               int tws, int F, int Bp) {
   switch (R) {
-    case 2: fft_stage_ip<T, 2, FIRST, SIGN>(buf, tw, n, Ns, tws, lgB, Bp); break;
-    case 3: fft_stage_ip<T, 3, FIRST, SIGN>(buf, tw, n, Ns, tws, lgB, Bp); break;
-    case 4: fft_stage_ip<T, 4, FIRST, SIGN>(buf, tw, n, Ns, tws, lgB, Bp); break;
-    case 5: fft_stage_ip<T, 5, FIRST, SIGN>(buf, tw, n, Ns, tws, lgB, Bp); break;
-    case 7: fft_stage_ip<T, 7, FIRST, SIGN>(buf, tw, n, Ns, tws, lgB, Bp); break;
-    default: fft_stage_ip<T, 8, FIRST, SIGN>(buf, tw, n, Ns, tws, lgB, Bp); break;
+    case 2: fft_stage_ip<T, 2, FIRST, SIGN>(buf, tw, n, Ns, tws, F, Bp); break;
+    case 3: fft_stage_ip<T, 3, FIRST, SIGN>(buf, tw, n, Ns, tws, F, Bp); break;
+    case 4: fft_stage_ip<T, 4, FIRST, SIGN>(buf, tw, n, Ns, tws, F, Bp); break;
+    case 5: fft_stage_ip<T, 5, FIRST, SIGN>(buf, tw, n, Ns, tws, F, Bp); break;
+    case 7: fft_stage_ip<T, 7, FIRST, SIGN>(buf, tw, n, Ns, tws, F, Bp); break;
+    default: fft_stage_ip<T, 8, FIRST, SIGN>(buf, tw, n, Ns, tws, F, Bp); break;
   }
 }
 
 // All stages of class C in place in buf.
 template <typename T, int SIGN>
-__device__ __forceinline__ void fft_run_ip(lds<vec2<T>>* buf, const lds<vec2<T>>* tw, const FftClass& C, int lgB,
+__device__ __forceinline__ void fft_run_ip(lds<vec2<T>>* buf, const lds<vec2<T>>* tw, const FftClass& C, int F,
                                            int Bp) {
   const int n = C.n, nst = C.nst;
   unsigned long long radices = C.radpack;
@@ -334,8 +338,8 @@ __device__ __forceinline__ void fft_run_ip(lds<vec2<T>>* buf, const lds<vec2<T>>
     const int R = (int)(radices & 15u);
     radices >>= 4;
     const int tws = rem / R;
-    if (s == 0) fft_stage_ip_r<T, true, SIGN>(R, buf, tw, n, Ns, tws, lgB, Bp);
-    else fft_stage_ip_r<T, false, SIGN>(R, buf, tw, n, Ns, tws, lgB, Bp);
+    if (s == 0) fft_stage_ip_r<T, true, SIGN>(R, buf, tw, n, Ns, tws, F, Bp);
+    else fft_stage_ip_r<T, false, SIGN>(R, buf, tw, n, Ns, tws, F, Bp);
     Ns *= R;
     rem = tws;
   }
@@ -440,59 +444,56 @@ __device__ __forceinline__ void scale_pencil(const FftClass& C, const ScaleRow<T
 // memory (TF) and sample-major (t = e div B, p = e mod B) otherwise, so that
 // neighbouring lanes touch neighbouring addresses.  The thread tracks the
 // sample t, the pencil p, a global byte offset g = p gs0 + t gst and an LDS
-// index l = t lt + p lp, all advanced by additions (B <= 128 divides
-// kFftBlock).
+// index l = t lt + p lp, all advanced by additions: a step of kFftBlock slots
+// moves the slow index (p if TF, else t) by q and the fast one by r, and a
+// fast index that passes its limit (n if TF, else B) wraps into the slow one.
 template <bool TF, typename OFF>
 struct SlotWalk {
-  int n, dt, q, r;
+  int lim, q, r;
   OFF dg, dgw;
   int dl, dlw;
   int t, p;
   OFF g;
   int l;
 
-  __device__ __forceinline__ SlotWalk(int n_, int lgB, OFF gs0, OFF gst, int lt, int lp) : n(n_) {
+  __device__ __forceinline__ SlotWalk(int n, int B, OFF gs0, OFF gst, int lt, int lp) {
     const int tid = threadIdx.x;
+    lim = TF ? n : B;
+    const float inv = quot_recip(lim);
+    // uniform: kept in scalar registers
+    q = rfl(fdiv(kFftBlock, inv));
+    r = kFftBlock - q * lim;
+    const int slow = fdiv(tid, inv), fast = tid - slow * lim;
     if constexpr (TF) {
-      const float inv_n = quot_recip(n);
-      q = fdiv(kFftBlock, inv_n);
-      r = kFftBlock - q * n;
-      p = fdiv(tid, inv_n);
-      t = tid - p * n;
+      p = slow;
+      t = fast;
       dg = (OFF)r * gst + (OFF)q * gs0;
       dgw = gs0 - (OFF)n * gst;
       dl = r * lt + q * lp;
       dlw = lp - n * lt;
-      dt = 0;
     } else {
-      dt = kFftBlock >> lgB;
-      p = tid & ((1 << lgB) - 1);
-      t = tid >> lgB;
-      dg = (OFF)dt * gst;
-      dl = dt * lt;
-      q = r = 0;
-      dgw = 0;
-      dlw = 0;
+      t = slow;
+      p = fast;
+      dg = (OFF)r * gs0 + (OFF)q * gst;
+      dgw = gst - (OFF)B * gs0;
+      dl = r * lp + q * lt;
+      dlw = lt - B * lp;
     }
     g = (OFF)p * gs0 + (OFF)t * gst;
     l = t * lt + p * lp;
   }
   __device__ __forceinline__ void step() {
-    if constexpr (TF) {
-      t += r;
-      p += q;
-      g += dg;
-      l += dl;
-      const bool w = t >= n;
-      t = w ? t - n : t;
-      p = w ? p + 1 : p;
-      g = w ? g + dgw : g;
-      l = w ? l + dlw : l;
-    } else {
-      t += dt;
-      g += dg;
-      l += dl;
-    }
+    int& fast = TF ? t : p;
+    int& slow = TF ? p : t;
+    fast += r;
+    slow += q;
+    g += dg;
+    l += dl;
+    const bool w = fast >= lim;
+    fast = w ? fast - lim : fast;
+    slow = w ? slow + 1 : slow;
+    g = w ? g + dgw : g;
+    l = w ? l + dlw : l;
   }
 };
 
@@ -512,7 +513,7 @@ constexpr int kSlotsInFlight = 8;   // global loads in flight per thread
 // Bp), zero padded from n_in to n; twiddles into tw.  C2R reads the stored
 // half spectrum (t <= n/2) and extends it by Hermitian symmetry.
 template <typename T, int KIND, bool TF, typename OFF>
-__device__ __forceinline__ void fft_load(const FftClass& C, int b0s, int b1, int cnt, int lgB, int pair, int Bp,
+__device__ __forceinline__ void fft_load(const FftClass& C, int b0s, int b1, int cnt, int B, int pair, int Bp,
                                          lds<vec2<T>>* buf, lds<vec2<T>>* tw) {
   constexpr int U = kSlotsInFlight;
   using V2 = vec2<T>;
@@ -531,12 +532,12 @@ __device__ __forceinline__ void fft_load(const FftClass& C, int b0s, int b1, int
     // once and gives, by Hermitian symmetry, Z_t = A_t + i B_t and, for
     // 0 < t < n - t, Z_{n-t} = conj(A_t) + i conj(B_t).
     constexpr OFF esz = 2 * sizeof(T);
-    const int lgF = lgB - pair;
+    const int F = pair ? B >> 1 : B;
     const char* base = (const char*)C.in + ((long long)b0s * C.in_s0 + (long long)b1 * C.in_s1) * (long long)esz;
     const OFF gs0 = (OFF)C.in_s0 * esz, gst = (OFF)C.in_st * esz;
     const OFF gsp = gs0 << pair;
-    const int nh = (n >> 1) + 1, total = nh << lgF, F = 1 << lgF;
-    SlotWalk<TF, OFF> w(nh, lgF, gsp, (OFF)0, Bp, 1);   // g tracks the pencil part only
+    const int nh = (n >> 1) + 1, total = nh * F;
+    SlotWalk<TF, OFF> w(nh, F, gsp, (OFF)0, Bp, 1);   // g tracks the pencil part only
     for (int e0 = 0; e0 < total; e0 += U * kFftBlock) {
       V2 va[U], vb[U];
       int lw[U], tt[U];
@@ -571,8 +572,8 @@ __device__ __forceinline__ void fft_load(const FftClass& C, int b0s, int b1, int
     constexpr OFF esz = RIN ? sizeof(T) : 2 * sizeof(T);
     const char* base = (const char*)C.in + ((long long)b0s * C.in_s0 + (long long)b1 * C.in_s1) * (long long)esz;
     const OFF gs0 = (OFF)C.in_s0 * esz, gst = (OFF)C.in_st * esz;
-    const int total = n << lgB, n_in = C.n_in, B = 1 << lgB;
-    SlotWalk<TF, OFF> w(n, lgB, gs0, gst, pair ? 2 * Bp : Bp, 1);
+    const int total = n * B, n_in = C.n_in;
+    SlotWalk<TF, OFF> w(n, B, gs0, gst, pair ? 2 * Bp : Bp, 1);
     lds<T>* fbuf = reinterpret_cast<lds<T>*>(buf);
     for (int e0 = 0; e0 < total; e0 += U * kFftBlock) {
       cx<T> v[U];
@@ -604,7 +605,7 @@ __device__ __forceinline__ void fft_load(const FftClass& C, int b0s, int b1, int
 
 // Store phase: the first n_out samples of pencils p < cnt from res.
 template <typename T, int KIND, bool TF, typename OFF>
-__device__ __forceinline__ void fft_store(const FftClass& C, int b0s, int b1, int cnt, int lgB, int pair, int Bp,
+__device__ __forceinline__ void fft_store(const FftClass& C, int b0s, int b1, int cnt, int B, int pair, int Bp,
                                           const lds<vec2<T>>* res) {
   constexpr int U = kSlotsInFlight;
   constexpr bool ROUT = (KIND == K_C2R);
@@ -612,12 +613,12 @@ __device__ __forceinline__ void fft_store(const FftClass& C, int b0s, int b1, in
   const int n = C.n, nout = C.n_out;
   char* base = (char*)C.out + ((long long)b0s * C.out_s0 + (long long)b1 * C.out_s1) * (long long)esz;
   const OFF gs0 = (OFF)C.out_s0 * esz, gst = (OFF)C.out_st * esz;
-  const int total = nout << lgB;
+  const int total = nout * B;
   // LDS index of slot (t, p): complex t Bp + p; for the real passes the float
   // index 2 t Bp + p (paired) or 2 (t Bp + p) (single pencil, C2R)
   const int lt = (KIND == K_R2C || KIND == K_C2R) ? 2 * Bp : Bp;
   const int lp = (KIND == K_C2R && !pair) ? 2 : 1;
-  SlotWalk<TF, OFF> w(nout, lgB, gs0, gst, lt, lp);
+  SlotWalk<TF, OFF> w(nout, B, gs0, gst, lt, lp);
   const lds<T>* fres = reinterpret_cast<const lds<T>*>(res);
   for (int e0 = 0; e0 < total; e0 += U * kFftBlock) {
 #pragma unroll
@@ -651,32 +652,34 @@ __device__ __forceinline__ void stage_fft(const FftPass& P, int cls, int b0s, in
                                           lds<unsigned char>* smem) {
   constexpr bool REAL = (KIND == K_R2C || KIND == K_C2R);
   const FftClass& C = P.cls[cls];
-  const int n = C.n, lgB = P.lgB;
-  // real passes with B >= 2 run B/2 complex transforms of pencil pairs
-  const int pair = (REAL && lgB > 0) ? 1 : 0;
-  const int lgF = lgB - pair, Bp = (1 << lgF) + 1;
+  const int n = C.n, B = P.B;
+  // real passes with B >= 2 (B even) run B/2 complex transforms of pencil pairs
+  const int pair = (REAL && B > 1) ? 1 : 0;
+  const int F = pair ? B >> 1 : B, Bp = F + 1;
   const bool ip = P.inplace;
   lds<vec2<T>>* tw = reinterpret_cast<lds<vec2<T>>*>(smem);
   lds<vec2<T>>* buf = tw + P.nmax;
   lds<vec2<T>>* buf2 = buf + P.nmax * Bp;   // only if not in place
 
-  if (C.in_st == 1) fft_load<T, KIND, true, OFF>(C, b0s, b1, cnt, lgB, pair, Bp, buf, tw);
-  else fft_load<T, KIND, false, OFF>(C, b0s, b1, cnt, lgB, pair, Bp, buf, tw);
+  if (C.in_st == 1) fft_load<T, KIND, true, OFF>(C, b0s, b1, cnt, B, pair, Bp, buf, tw);
+  else fft_load<T, KIND, false, OFF>(C, b0s, b1, cnt, B, pair, Bp, buf, tw);
   __syncthreads();
 
   constexpr int SIGN = (KIND == K_C2C_INV || KIND == K_C2R) ? +1 : -1;
   lds<vec2<T>>* res = buf;
-  if (ip) fft_run_ip<T, SIGN>(buf, tw, C, lgF, Bp);
-  else res = fft_run<T, SIGN>(buf, buf2, tw, C, lgF, Bp);
+  if (ip) fft_run_ip<T, SIGN>(buf, tw, C, F, Bp);
+  else res = fft_run<T, SIGN>(buf, buf2, tw, C, F, Bp);
 
   if constexpr (KIND == K_FUSED || KIND == K_FUSED_D) {
-    // scaling step, Eq. (scale), on the spectrum of each pencil; the block
-    // size is a multiple of B, so each thread keeps one pencil p throughout
-    const int p = threadIdx.x & ((1 << lgB) - 1);
-    const int dt = kFftBlock >> lgB, dl = dt * Bp;
-    if (p < cnt) {
+    // scaling step, Eq. (scale), on the spectrum of each pencil: thread
+    // (t0, p), tid = t0 B + p, takes samples t0, t0 + dt, ... of pencil p,
+    // dt = kFftBlock div B (the last kFftBlock mod B threads idle)
+    const float inv_b = quot_recip(B);
+    int t = fdiv(threadIdx.x, inv_b);
+    const int p = threadIdx.x - t * B;
+    const int dt = rfl(fdiv(kFftBlock, inv_b)), dl = dt * Bp;
+    if (p < cnt && t < dt) {
       const ScaleRow<T> row = scale_row<T>(C, b0s + p, b1);
-      int t = threadIdx.x >> lgB;
       if constexpr (KIND == K_FUSED) {
         switch (C.gmode) {
           case G_INVSQ: scale_pencil<T, G_INVSQ>(C, row, res, p, t, dt, n, Bp); break;
@@ -701,12 +704,12 @@ __device__ __forceinline__ void stage_fft(const FftPass& P, int cls, int b0s, in
       }
     }
     __syncthreads();
-    if (ip) fft_run_ip<T, +1>(buf, tw, C, lgB, Bp);
-    else res = fft_run<T, +1>(res, res == buf ? buf2 : buf, tw, C, lgB, Bp);
+    if (ip) fft_run_ip<T, +1>(buf, tw, C, F, Bp);
+    else res = fft_run<T, +1>(res, res == buf ? buf2 : buf, tw, C, F, Bp);
   }
 
-  if (C.out_st == 1) fft_store<T, KIND, true, OFF>(C, b0s, b1, cnt, lgB, pair, Bp, res);
-  else fft_store<T, KIND, false, OFF>(C, b0s, b1, cnt, lgB, pair, Bp, res);
+  if (C.out_st == 1) fft_store<T, KIND, true, OFF>(C, b0s, b1, cnt, B, pair, Bp, res);
+  else fft_store<T, KIND, false, OFF>(C, b0s, b1, cnt, B, pair, Bp, res);
 }
 
 // The work record {class, b0 start, b1, count}, the same for the whole
@@ -745,8 +748,8 @@ size_t fft_lds_bytes(const FftPass& p, bool f64) {
   const size_t c = f64 ? 16 : 8;
   const size_t nbuf = p.inplace ? 1 : 2;
   // complex transforms per block: B, or B / 2 pencil pairs for the real passes
-  const bool pair = (p.kind == K_R2C || p.kind == K_C2R) && p.lgB > 0;
-  return c * ((size_t)p.nmax + nbuf * (((size_t)1 << (p.lgB - (pair ? 1 : 0))) + 1) * p.nmax);
+  const bool pair = (p.kind == K_R2C || p.kind == K_C2R) && p.B > 1;
+  return c * ((size_t)p.nmax + nbuf * ((size_t)(pair ? p.B / 2 : p.B) + 1) * p.nmax);
 }
 
 template <typename T, typename OFF>

@@ -47,12 +47,11 @@ constexpr size_t kFftLdsSoft = 40 * 1024;
 // buffers.
 constexpr int kFftInplaceCap = 2048;
 // Butterflies of radix R one thread holds in registers across an in-place
-// stage.  Radices 3, 5 and 7 hold fewer than kFftInplaceCap would need (it
-// sets the kernels' register count, hence their occupancy); the planner
-// takes fewer pencils per block for transform lengths with such a factor, so
-// that (n / R) B <= kFftIpIters(R) kFftBlock at every stage.
+// stage: enough for kFftInplaceCap samples at every radix (R = 3 holds 3,
+// R = 5 and 7 hold 2); the planner keeps (n / R) F <= kFftIpIters(R)
+// kFftBlock at every stage (F complex transforms per block).
 constexpr int kFftIpIters(int R) {
-  return R == 5 || R == 7 ? 1 : (R == 3 ? 2 : (kFftInplaceCap + R * kFftBlock - 1) / (R * kFftBlock));
+  return R == 7 ? 2 : (R == 5 ? 2 : (R == 3 ? 3 : (kFftInplaceCap + R * kFftBlock - 1) / (R * kFftBlock)));
 }
 
 // Green's-function modes of the fused scaling pass (Eq. scale).
@@ -110,8 +109,7 @@ struct FftPass {
   FftClass cls[kMaxClasses];
   const int4* items;              // per block: {class, b0_start, b1, count}
   int nitems;
-  int B;                          // pencils per block, B = 2^lgB
-  int lgB;
+  int B;                          // pencils per block (even for the paired real passes when > 1)
   int nmax;                       // largest n (LDS sizing)
   int kind;
   int xcd;                        // item mapping: 0 plain, 1 one range per XCD, c >= 2 chunks of c

@@ -423,40 +423,52 @@ static bool finish_pass(se_plan* pl, se::FftPass& ps, int kind, int ncls,
   ps.kind = kind;
   ps.nmax = 0;
   for (int c = 0; c < ncls; ++c) ps.nmax = std::max(ps.nmax, ps.cls[c].n);
-  // pencils per block: the largest power of two B with n F within the
-  // samples cap, the LDS budget (twiddles n, samples n (F + 1)) and the
-  // registers of an in-place stage, where F is the number of complex
-  // transforms of a block: B, or B / 2 for the real passes, which pair two
-  // real pencils into one complex transform (F <= 64 either way)
+  // pencils per block B, with F complex transforms: B, or B / 2 for the
+  // real passes, which pair two real pencils into one complex transform.  F
+  // <= 64 is bounded by the samples cap (n F), the LDS budget (twiddles n,
+  // samples n (F + 1)) and the registers of an in-place stage; among the F
+  // up to that bound, the smallest that gives the fewest work items (so the
+  // items of a pencil range come out even)
   const size_t esz = pl->f64 ? 16 : 8;
   const bool real = kind == se::K_R2C || kind == se::K_C2R;
-  auto cpx = [&](long B2) { return real && B2 >= 2 ? B2 / 2 : B2; };
   const long cap = pl->fft_cap > 0 ? pl->fft_cap : (pl->f64 ? 1024 : 2048);
   // in place unless the samples cap (or a single pencil) exceeds kFftInplaceCap
   ps.inplace = (cap <= se::kFftInplaceCap && ps.nmax <= se::kFftInplaceCap) ? 1 : 0;
-  auto lds_of = [&](long B2) { return esz * (size_t)ps.nmax * (1 + (ps.inplace ? 1 : 2) * (cpx(B2) + 1)); };
+  auto lds_of = [&](long F) { return esz * (size_t)ps.nmax * (1 + (ps.inplace ? 1 : 2) * (F + 1)); };
   // in place, every stage of every class keeps its butterflies within the
   // registers the kernel holds for them (kFftIpIters)
-  auto fits_regs = [&](long B2) {
+  auto fits_regs = [&](long F) {
     if (!ps.inplace) return true;
     for (int c = 0; c < ncls; ++c)
       for (int k = 0; k < ps.cls[c].nst; ++k) {
         const int R = ps.cls[c].rad[k];
-        if ((long)(ps.cls[c].n / R) * cpx(B2) > (long)se::kFftIpIters(R) * se::kFftBlock) return false;
+        if ((long)(ps.cls[c].n / R) * F > (long)se::kFftIpIters(R) * se::kFftBlock) return false;
       }
     return true;
   };
   if (!fits_regs(1)) ps.inplace = 0;   // a single pencil needs more: alternate two buffers
-  int lgB = 0;
-  while (lgB < (real ? 7 : 6)) {
-    const long B2 = 2L << lgB;
-    if ((long)ps.nmax * cpx(B2) > cap || lds_of(B2) > std::min(pl->lds_limit, se::kFftLdsSoft) || !fits_regs(B2))
-      break;
-    ++lgB;
+  int fmax = 1;
+  while (fmax < 64) {
+    const long F = fmax + 1;
+    if ((long)ps.nmax * F > cap || lds_of(F) > std::min(pl->lds_limit, se::kFftLdsSoft) || !fits_regs(F)) break;
+    ++fmax;
   }
-  if (lds_of(1L << lgB) > pl->lds_max) return false;
-  ps.lgB = lgB;
-  ps.B = 1 << lgB;
+  if (lds_of(fmax) > pl->lds_max) return false;
+  auto items_of = [&](long B) {
+    long k = 0;
+    for (const auto& r : ranges) k += (long)(r[4] - r[3]) * ((r[2] - r[1] + B - 1) / B);
+    return k;
+  };
+  int fb = fmax;
+  long best = items_of(real ? 2L * fmax : fmax);
+  for (int F = fmax - 1; F >= 1; --F) {
+    const long k = items_of(real ? 2L * F : F);
+    if (k <= best) {
+      best = k;
+      fb = F;
+    }
+  }
+  ps.B = real ? 2 * fb : fb;
   // twiddle tables; 64-bit offsets if the B pencils of a workgroup span 4 GiB
   ps.wide = 0;
   for (int c = 0; c < ncls; ++c) {

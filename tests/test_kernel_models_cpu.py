@@ -224,36 +224,37 @@ def test_reciprocal_quotient_is_exact():
             assert np.array_equal(q, ai // d), d
 
 
-def slot_walk(n, lgB, gs0, gst, lt, lp, TF, steps):
+def slot_walk(n, B, gs0, gst, lt, lp, TF, steps):
     """The kernel's per-thread walk over slots tid, tid + 256, ...: (t, p,
-    global offset, LDS index) after each step, for all 256 threads at once."""
+    global offset, LDS index) after each step, for all 256 threads at once.
+    The fast index (t if TF, else p) runs to lim (n, else B); a step moves the
+    slow index by q and the fast one by r, wrapping the fast one."""
     tid = np.arange(K_FFT_BLOCK)
+    lim = n if TF else B
+    q = K_FFT_BLOCK // lim
+    r = K_FFT_BLOCK - q * lim
+    slow, fast = tid // lim, tid % lim
     if TF:
-        q = K_FFT_BLOCK // n
-        r = K_FFT_BLOCK - q * n
-        p = tid // n
-        t = tid - p * n
+        p, t = slow, fast
         dg, dgw = r * gst + q * gs0, gs0 - n * gst
         dl, dlw = r * lt + q * lp, lp - n * lt
     else:
-        dt = K_FFT_BLOCK >> lgB
-        p = tid & ((1 << lgB) - 1)
-        t = tid >> lgB
-        dg, dl = dt * gst, dt * lt
+        t, p = slow, fast
+        dg, dgw = r * gs0 + q * gst, gst - B * gs0
+        dl, dlw = r * lp + q * lt, lt - B * lp
     g = p * gs0 + t * gst
     l = t * lt + p * lp
     out = []
     for _ in range(steps):
         out.append((t.copy(), p.copy(), g.copy(), l.copy()))
-        if TF:
-            t, p, g, l = t + r, p + q, g + dg, l + dl
-            w = t >= n
-            t = np.where(w, t - n, t)
-            p = np.where(w, p + 1, p)
-            g = np.where(w, g + dgw, g)
-            l = np.where(w, l + dlw, l)
-        else:
-            t, g, l = t + dt, g + dg, l + dl
+        fast, slow = (t, p) if TF else (p, t)
+        fast, slow, g, l = fast + r, slow + q, g + dg, l + dl
+        w = fast >= lim
+        fast = np.where(w, fast - lim, fast)
+        slow = np.where(w, slow + 1, slow)
+        g = np.where(w, g + dgw, g)
+        l = np.where(w, l + dlw, l)
+        t, p = (fast, slow) if TF else (slow, fast)
     return out
 
 
@@ -274,23 +275,25 @@ def test_slot_walk_equals_direct_indexing():
     coordinates: pencil-major (p = e div n, t = e mod n) when the transform
     direction is contiguous, sample-major (t = e div B, p = e mod B)
     otherwise, and the matching global offsets and LDS indices, for every
-    7-smooth length and pencil count of a block (n B <= 8192, and up to
-    B = 128 real pencils, n B <= 16384, for the paired real passes)."""
+    7-smooth length with block pencil counts B = 1-64 and the even B up to
+    128 of the paired real passes (n B <= 8192, or 16384 for even B > 1),
+    every B for n <= 512 and a spread of them above."""
     rng = np.random.default_rng(1)
+    all_b = list(range(1, 65)) + list(range(66, 129, 2))
     for n in _smooth_lengths(8192):
-        for lgB in range(0, 8):
-            B = 1 << lgB
-            if n * B > (16384 if lgB > 0 else 8192):
-                break
+        Bs = all_b if n <= 512 else [1, 2, 3, 4, 5, 6, 7, 8, 9, 12, 16, 24, 32, 64, 128]
+        for B in Bs:
+            if n * B > (16384 if B % 2 == 0 else 8192):
+                continue
             gs0, gst = int(rng.integers(1, 5000)), int(rng.integers(1, 5000))
             lt, lp = B + 1, 1
             steps = (n * B + K_FFT_BLOCK - 1) // K_FFT_BLOCK
             for TF in (True, False):
-                walk = slot_walk(n, lgB, gs0, gst, lt, lp, TF, steps)
+                walk = slot_walk(n, B, gs0, gst, lt, lp, TF, steps)
                 for k, (t, p, g, l) in enumerate(walk):
                     e = np.arange(K_FFT_BLOCK) + k * K_FFT_BLOCK
-                    tt, pp = (e % n, e // n) if TF else (e >> lgB, e & (B - 1))
-                    assert np.array_equal(t, tt) and np.array_equal(p, pp), (n, lgB, TF, k)
+                    tt, pp = (e % n, e // n) if TF else (e // B, e % B)
+                    assert np.array_equal(t, tt) and np.array_equal(p, pp), (n, B, TF, k)
                     assert np.array_equal(g, pp * gs0 + tt * gst) and np.array_equal(l, tt * lt + pp * lp)
 
 

@@ -147,6 +147,9 @@ typedef struct {
   double h, shape, lambda, s0, s, R;
   size_t device_bytes; /* device memory held by the plan (tables, status word)         */
   size_t workspace_bytes; /* workspace an evaluation needs (se_plan_workspace_size)    */
+  int fft_block[5];   /* pencils per transform workgroup of each pass (real pencils,
+                         two per complex transform, for the real-to-complex and
+                         complex-to-real passes); 0 for a pass the plan lacks   */
 } se_plan_info;
 
 typedef struct se_plan se_plan;

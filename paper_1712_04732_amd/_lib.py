@@ -100,6 +100,7 @@ class se_plan_info(ctypes.Structure):
         ("R", ctypes.c_double),
         ("device_bytes", ctypes.c_size_t),
         ("workspace_bytes", ctypes.c_size_t),
+        ("fft_block", ctypes.c_int * 5),
     ]
 
 

@@ -1022,8 +1022,11 @@ static se_status plan_create(const se_params* params, long n_max, void* hip_stre
   I.device_bytes = pl->bytes;
   I.workspace_bytes = pl->ws_bytes;
   I.fft_wide = 0;
-  for (size_t k = 0; k < pl->passes.size(); ++k)
+  for (int k = 0; k < 5; ++k) I.fft_block[k] = 0;
+  for (size_t k = 0; k < pl->passes.size(); ++k) {
     if (pl->passes[k].wide) I.fft_wide |= 1 << k;
+    if (k < 5) I.fft_block[k] = pl->passes[k].B;
+  }
   *out = pl;
   return SE_OK;
 }

@@ -84,6 +84,31 @@ def test_fft_and_mapping_knobs_match_oracle(D, knobs):
     assert rel(phi, ref) < 1e-12 and rel(g, gref) < 1e-11
 
 
+@pytest.mark.parametrize("D,M", [(3, 42), (3, 70), (2, 30), (1, 36), (0, 28)])
+@pytest.mark.parametrize("cap", [0, 1024, 4096])
+def test_transform_blocks_of_any_pencil_count(D, M, cap):
+    """Transform workgroups hold any number of pencils, chosen so that a
+    pencil range splits into equal blocks, with partial blocks, odd counts
+    and the real passes' pencil pairs (in place at the default cap and 1024,
+    two alternating buffers at 4096): the discrete oracle's result in FP64
+    and within the FP32 bounds."""
+    print(f"case fft blocks D={D} M={M} cap={cap}", flush=True)
+    x, q = wl.system(400, 1.0, 80 + D + M, "uniform")
+    knobs = {"fft_cap": cap} if cap else {}
+    plan, p = _plan(D, M, 400, knobs)
+    blocks = list(plan.info.fft_block)
+    print(f"  blocks per pass {blocks}")
+    assert all(b >= 1 for b in blocks)
+    if D == 3 and M == 70 and cap == 0:
+        assert any(b & (b - 1) for b in blocks)   # not all powers of two
+    phi, g = _eval(plan, x, q)
+    ref, gref = _oracle(("blocks", D, M), x, q, p)
+    assert rel(phi, ref) < 1e-12 and rel(g, gref) < 1e-11
+    plan32, _ = _plan(D, M, 400, knobs, prec="f32")
+    phi32, g32 = _eval(plan32, x, q)
+    assert rel(phi32, ref) < 1e-5 and rel(g32, gref) < 2e-5
+
+
 def test_invalid_knobs_rejected():
     base = SpectralEwald(3, 1.0, 8.0, 32, 8, prec="f64", n_max=10)
     for edit in (lambda p: setattr(p, "fft_cap", 3000), lambda p: setattr(p, "fft_cap", 512)):

@@ -853,11 +853,11 @@ static se_status plan_create(const se_params* params, long n_max, void* hip_stre
   g.alpha = p.shape;
   g.scale = 4.0 * kPi * I.h * I.h * I.h;
   g.xcd = xcd_mode(p.xcd_tiles);
-  // spreading mode: clipped stencils straight into the grid for sparse grids
-  // (fewer than 0.1 particles per grid point), boxes and fold otherwise
+  // spreading mode: columns straight into the grid for sparse grids (fewer
+  // than 0.05 particles per grid point), boxes and fold otherwise
   {
     const double npts = (double)I.grid[0] * I.grid[1] * I.grid[2];
-    const bool sparse = (double)std::max(1L, n_max) < 0.1 * npts;
+    const bool sparse = (double)std::max(1L, n_max) < 0.05 * npts;
     const int mode = p.spread_mode > 0 ? p.spread_mode : (sparse ? 3 : 1);
     g.clip = mode - 1;
   }

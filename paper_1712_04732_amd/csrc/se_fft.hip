@@ -2,7 +2,7 @@
 // of Shamshirgar, Bagge, Tornberg, arXiv:1712.04732).
 //
 // One workgroup transforms B pencils of one length-n class at once: it loads
-// them into LDS (zero padding up to n), runs mixed-radix (2,3,4,5,7,8)
+// them into LDS (zero padding up to n), runs mixed-radix (2,3,4,5,6,7,8,9)
 // Stockham stages in place in one LDS buffer (each thread holds its
 // butterflies of a stage in registers across a barrier; blocks above 2048
 // samples alternate between two buffers instead), and stores the first n_out
@@ -129,11 +129,64 @@ __device__ __forceinline__ void dft_odd(cx<T>* v, int sign) {
   for (int m = 1; m < R; ++m) v[m] = out[m];
 }
 
+// Composite radix R = R1 R2 (6 = 2 x 3, 9 = 3 x 3) in registers: with
+// k = m + R2 q, X_k = sum_j exp(sign 2 pi i j q / R1) [exp(sign 2 pi i j m / R)
+// A_j(m)], where A_j is the length-R2 DFT of v_j, v_{j+R1}, ...  One stage of
+// radix R replaces two stages of radices R1 and R2 (one LDS round trip and
+// one barrier fewer).
+template <int R>
+struct MixedRoots;
+template <>
+struct MixedRoots<6> {   // exp(2 pi i t / 6), t = j m for j < 2, m < 3
+  static constexpr int R1 = 2, R2 = 3;
+  static constexpr double c[3] = {1.0, 0.5, -0.5};
+  static constexpr double s[3] = {0.0, 0.86602540378443864676, 0.86602540378443864676};
+};
+template <>
+struct MixedRoots<9> {   // exp(2 pi i t / 9), t = j m for j, m < 3
+  static constexpr int R1 = 3, R2 = 3;
+  static constexpr double c[5] = {1.0, 0.76604444311897803520, 0.17364817766693034885, 0.0,
+                                  -0.93969262078590838405};
+  static constexpr double s[5] = {0.0, 0.64278760968653932632, 0.98480775301220805936, 0.0,
+                                  0.34202014332566873304};
+};
+
+template <typename T, int R>
+__device__ __forceinline__ void dft(cx<T>* v, int sign);
+
+template <typename T, int R>
+__device__ __forceinline__ void dft_mixed(cx<T>* v, int sign) {
+  constexpr int R1 = MixedRoots<R>::R1, R2 = MixedRoots<R>::R2;
+  cx<T> a[R1][R2];
+#pragma unroll
+  for (int j = 0; j < R1; ++j) {
+#pragma unroll
+    for (int r = 0; r < R2; ++r) a[j][r] = v[j + R1 * r];
+    dft<T, R2>(a[j], sign);
+#pragma unroll
+    for (int m = 1; m < R2; ++m)
+      if (j > 0) {
+        const int t = j * m;
+        a[j][m] = cmul(a[j][m], cx<T>{(T)MixedRoots<R>::c[t], (T)(sign * MixedRoots<R>::s[t])});
+      }
+  }
+#pragma unroll
+  for (int m = 0; m < R2; ++m) {
+    cx<T> b[R1];
+#pragma unroll
+    for (int j = 0; j < R1; ++j) b[j] = a[j][m];
+    dft<T, R1>(b, sign);
+#pragma unroll
+    for (int q = 0; q < R1; ++q) v[m + R2 * q] = b[q];
+  }
+}
+
 template <typename T, int R>
 __device__ __forceinline__ void dft(cx<T>* v, int sign) {
   if constexpr (R == 2) dft2(v);
   else if constexpr (R == 4) dft4(v, sign);
   else if constexpr (R == 8) dft8(v, sign);
+  else if constexpr (R == 6 || R == 9) dft_mixed<T, R>(v, sign);
   else dft_odd<T, R>(v, sign);
 }
 
@@ -229,7 +282,9 @@ __device__ __forceinline__ void fft_stage_r(int R, const lds<vec2<T>>* src, lds<
     case 3: fft_stage<T, 3, FIRST, SIGN>(src, dst, tw, n, Ns, tws, F, Bp); break;
     case 4: fft_stage<T, 4, FIRST, SIGN>(src, dst, tw, n, Ns, tws, F, Bp); break;
     case 5: fft_stage<T, 5, FIRST, SIGN>(src, dst, tw, n, Ns, tws, F, Bp); break;
+    case 6: fft_stage<T, 6, FIRST, SIGN>(src, dst, tw, n, Ns, tws, F, Bp); break;
     case 7: fft_stage<T, 7, FIRST, SIGN>(src, dst, tw, n, Ns, tws, F, Bp); break;
+    case 9: fft_stage<T, 9, FIRST, SIGN>(src, dst, tw, n, Ns, tws, F, Bp); break;
     default: fft_stage<T, 8, FIRST, SIGN>(src, dst, tw, n, Ns, tws, F, Bp); break;
   }
 }
@@ -322,7 +377,9 @@ __device__ __forceinline__ void fft_stage_ip_r(int R, lds<vec2<T>>* buf, const l
     case 3: fft_stage_ip<T, 3, FIRST, SIGN>(buf, tw, n, Ns, tws, F, Bp); break;
     case 4: fft_stage_ip<T, 4, FIRST, SIGN>(buf, tw, n, Ns, tws, F, Bp); break;
     case 5: fft_stage_ip<T, 5, FIRST, SIGN>(buf, tw, n, Ns, tws, F, Bp); break;
+    case 6: fft_stage_ip<T, 6, FIRST, SIGN>(buf, tw, n, Ns, tws, F, Bp); break;
     case 7: fft_stage_ip<T, 7, FIRST, SIGN>(buf, tw, n, Ns, tws, F, Bp); break;
+    case 9: fft_stage_ip<T, 9, FIRST, SIGN>(buf, tw, n, Ns, tws, F, Bp); break;
     default: fft_stage_ip<T, 8, FIRST, SIGN>(buf, tw, n, Ns, tws, F, Bp); break;
   }
 }

@@ -48,18 +48,47 @@ bool is_smooth(long n) {
   return n == 1;
 }
 
-// Radix sequence for the Stockham stages (radices 8, 4, 2, 3, 5, 7).
+// Radix sequence for the Stockham stages: the fewest stages over the radices
+// 2-9 (each stage is one LDS round trip and one barrier; radices 6 and 9 are
+// composite butterflies, 2 x 3 and 3 x 3, in registers), found by a search
+// over the divisors of n.  Where the prime radices 8, 4, 2, 3, 5, 7 taken
+// greedily in that order need no more stages, that sequence; otherwise,
+// among the shortest, the one with the most eights, then nines, sixes,
+// sevens, fives and fours, run in the order 8, 4, 2, 9, 6, 3, 5, 7.
 bool radix_plan(int n, int* rad, int* nst) {
-  int k = 0, m = n;
-  for (int r : {8, 4, 2, 3, 5, 7}) {
-    while (m % r == 0) {
-      if (k >= se::kMaxStages) return false;
-      rad[k++] = r;
-      m /= r;
-    }
+  if (n < 1 || !is_smooth(n)) return false;
+  int greedy[64], ng = 0;
+  int rem = n;
+  for (int r : {8, 4, 2, 3, 5, 7})
+    for (; rem % r == 0 && ng < 64; rem /= r) greedy[ng++] = r;
+  static const int pref[] = {8, 9, 6, 7, 5, 4, 3, 2};
+  std::vector<int> best(n + 1, -1);   // fewest stages for each divisor m of n
+  best[1] = 0;
+  for (int m = 2; m <= n; ++m) {
+    if (n % m) continue;
+    for (int r : pref)
+      if (m % r == 0 && best[m / r] >= 0 && (best[m] < 0 || best[m / r] + 1 < best[m])) best[m] = best[m / r] + 1;
   }
+  if (best[n] < 0 || best[n] > se::kMaxStages) return false;
+  if (ng == best[n]) {
+    for (int k = 0; k < ng; ++k) rad[k] = greedy[k];
+    *nst = ng;
+    return true;
+  }
+  int cnt[10] = {0};
+  for (int m = n; m > 1;) {
+    for (int r : pref)
+      if (m % r == 0 && best[m / r] == best[m] - 1) {
+        ++cnt[r];
+        m /= r;
+        break;
+      }
+  }
+  int k = 0;
+  for (int r : {8, 4, 2, 9, 6, 3, 5, 7})
+    for (int i = 0; i < cnt[r]; ++i) rad[k++] = r;
   *nst = k;
-  return m == 1;
+  return true;
 }
 
 // Modified Bessel function I0 by its power series sum (x^2/4)^k / (k!)^2.

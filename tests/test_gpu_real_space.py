@@ -330,6 +330,30 @@ def test_fp32_close_pairs():
     assert e_phi < 1e-5 and e_f < 1e-6
 
 
+def test_fp32_close_pairs_rectangular_box():
+    """The same in a 1 x 0.55 x 0.3 box (100 000 charges, cells of three
+    different sides): records relative to the cell corner per direction, and
+    pairs closer than an eighth of the shortest cell side in FP64; forces
+    against the FP64 path (itself checked against the direct rectangular-box
+    sum above) within 1e-6 rms."""
+    N, Ls, rc = 100000, (1.0, 0.55, 0.3), 0.06
+    xi = 3.2 / rc
+    rng = np.random.default_rng(651)
+    x = rng.random((N, 3)) * np.asarray(Ls)
+    q = rng.standard_normal(N)
+    q -= q.mean()
+    out = {}
+    for prec in ("f64", "f32"):
+        rs = RealSpace(3, Ls, xi, rc, prec=prec, n_max=N)
+        out[prec] = run(rs, x, q)
+    print(f"cells {rs.cells} span {rs.span}")
+    h = [Ls[d] / rs.cells[d] for d in range(3)]
+    assert len({round(v, 12) for v in h}) == 3   # three different cell sides
+    e_phi, e_f = rel(out["f32"][0], out["f64"][0]), rel(out["f32"][1], out["f64"][1])
+    print(f"fp32 vs fp64 real space in a box, N={N}: phi {e_phi:.2e} grad {e_f:.2e}")
+    assert e_phi < 1e-5 and e_f < 1e-6
+
+
 @pytest.mark.parametrize("D", [3, 2, 1, 0])
 def test_total_energy_autograd_against_oracle(D):
     """EwaldEnergy (k space + real space + self term on the GPU): the energy

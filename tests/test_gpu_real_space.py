@@ -381,3 +381,31 @@ def test_total_energy_autograd_against_oracle(D):
     assert abs(float(E) - E_o) <= 1e-10 * abs(E_o)
     assert rel(qt.grad.cpu().numpy(), phi_o) < 1e-10
     assert rel(xt.grad.cpu().numpy(), q[:, None] * g_o) < 1e-9
+
+
+def test_total_energy_autograd_rectangular_box():
+    """EwaldEnergy in a 1 x 0.75 x 1.25 box (k space on the M = 40, My = 30,
+    Mz = 50 grid, PKB P = 16; real space on the box plan; self term): the
+    energy and its autograd gradients against the direct rectangular-box
+    oracle's total potential and gradient."""
+    print("case total energy box", flush=True)
+    from paper_1712_04732_amd import EwaldEnergy
+    N = 300
+    Ls = (1.0, 0.75, 1.25)
+    x, q = _box_system(N, Ls, 670)
+    xi, M, P = 8.0, 40, 16
+    ks = SpectralEwald(3, 1.0, xi, M, P, window="pkb", prec="f64", n_max=N, My=30, Mz=50)
+    assert ks.box == Ls
+    rs = RealSpace(3, ks.box, xi, direct.real_space_cutoff(xi), prec="f64", n_max=N)
+    xt = torch.tensor(x, dtype=torch.float64, device=DEV, requires_grad=True)
+    qt = torch.tensor(q, dtype=torch.float64, device=DEV, requires_grad=True)
+    E = EwaldEnergy.apply(xt, qt, ks, rs)
+    E.backward()
+    torch.cuda.synchronize()
+    phi_o, g_o = direct.total_box3(Ls, xi, x, q)
+    E_o = 0.5 * float(np.dot(q, phi_o))
+    E = E.detach()
+    print(f"  energy {float(E):.12f} oracle {E_o:.12f}")
+    assert abs(float(E) - E_o) <= 1e-10 * abs(E_o)
+    assert rel(qt.grad.cpu().numpy(), phi_o) < 1e-10
+    assert rel(xt.grad.cpu().numpy(), q[:, None] * g_o) < 1e-9

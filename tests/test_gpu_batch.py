@@ -81,6 +81,51 @@ def test_batch_equals_single_system_path():
         o += s["N"]
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_batch_evaluation_replays_from_a_graph(prec):
+    """A batch evaluation captured in a graph (no memory set or copy nodes in
+    the evaluation path) replays bit for bit what the eager call computes,
+    on new inputs written in place between replays, with eager evaluations
+    of the plan in between."""
+    print(f"case batch graph {prec}", flush=True)
+    systems, params = _batch(8, prec, seed=11)
+    b = SpectralEwaldBatch(params, [s["N"] for s in systems])
+    dt = torch.float32 if prec == "f32" else torch.float64
+    x0 = np.concatenate([s["x"] for s in systems])
+    q0 = np.concatenate([s["q"] for s in systems])
+    x = torch.tensor(x0, dtype=dt, device=DEV)
+    q = torch.tensor(q0, dtype=dt, device=DEV)
+    out = b(x, q)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(2):
+            b(x, q, out=out, check=False)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b(x, q, out=out, check=False)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5)
+    for k in range(3):
+        # new positions (a shift keeps each system in its box), same charges
+        shift = rng.uniform(-0.01, 0.01, size=3)
+        xs = x0.copy()
+        off = 0
+        for s_ in systems:
+            xs[off:off + s_["N"]] = np.mod(s_["x"] + shift, s_["L"]) if s_["D"] == 3 else s_["x"]
+            off += s_["N"]
+        x.copy_(torch.tensor(xs, dtype=dt))
+        ref = [t.clone() for t in b(x, q)]          # eager
+        for t in out:
+            t.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        for a, r in zip(out, ref):
+            assert torch.equal(a, r), k
+
+
 def test_batch_repeated_calls_and_status():
     print("case batch repeat", flush=True)
     systems, params = _batch(5, "f32", seed=3)

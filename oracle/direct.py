@@ -56,6 +56,10 @@ def _load():
                                                ctypes.c_long, lp, dp, dp]
         lib.oracle_kspace_box3.argtypes = [dp, ctypes.c_double, ip, ctypes.c_long, dp, dp, ctypes.c_long, lp,
                                            dp, dp]
+        lib.oracle_real_space_box2.argtypes = [dp, ctypes.c_double, ctypes.c_double, ctypes.c_long, dp, dp,
+                                               ctypes.c_long, lp, dp, dp]
+        lib.oracle_kspace_box2.argtypes = [dp, ctypes.c_double, ip, ctypes.c_long, dp, dp, ctypes.c_long, lp,
+                                           dp, dp]
         lib.oracle_incomplete_k0.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp]
         lib.oracle_incomplete_k0.restype = None
         lib.oracle_ein.argtypes = [ctypes.c_double]
@@ -199,6 +203,47 @@ def kspace_box3(Ls, xi, x, q, targets=None, tol=1e-18):
     if rc_:
         raise ValueError("oracle_kspace_box3 rejected its arguments")
     return phi, grad
+
+
+def real_space_box2(Ls, xi, rc, x, q, targets=None):
+    """phi^R and its gradient for the 2P lattice with rectangular cell Ls[0] x Ls[1]."""
+    lib = _load()
+    x, q, t = _prep(x, q, targets)
+    Ls = np.ascontiguousarray(Ls[:2], dtype=np.float64)
+    phi = np.zeros(t.shape[0])
+    grad = np.zeros((t.shape[0], 3))
+    rc_ = lib.oracle_real_space_box2(_dp(Ls), xi, rc, q.shape[0], _dp(x), _dp(q), t.shape[0],
+                                     t.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), _dp(phi), _dp(grad))
+    if rc_:
+        raise ValueError("oracle_real_space_box2 rejected its arguments")
+    return phi, grad
+
+
+def kspace_box2(Ls, xi, x, q, targets=None, tol=1e-18):
+    """phi^{2P,F} and its gradient for the rectangular 2P cell Ls[0] x Ls[1]."""
+    lib = _load()
+    x, q, t = _prep(x, q, targets)
+    Ls = np.ascontiguousarray(Ls[:2], dtype=np.float64)
+    nmax = np.ascontiguousarray([kspace_nmax(L, xi, tol) for L in Ls], dtype=np.int32)
+    phi = np.zeros(t.shape[0])
+    grad = np.zeros((t.shape[0], 3))
+    rc_ = lib.oracle_kspace_box2(_dp(Ls), xi, nmax.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), q.shape[0],
+                                 _dp(x), _dp(q), t.shape[0], t.ctypes.data_as(ctypes.POINTER(ctypes.c_long)),
+                                 _dp(phi), _dp(grad))
+    if rc_:
+        raise ValueError("oracle_kspace_box2 rejected its arguments")
+    return phi, grad
+
+
+def total_box2(Ls, xi, x, q, targets=None):
+    """phi (real + Fourier + self, Eq. potential_split) and its gradient for
+    the 2P lattice with rectangular cell Ls[0] x Ls[1] (z free)."""
+    rc = real_space_cutoff(xi)
+    pr, gr = real_space_box2(Ls, xi, rc, x, q, targets)
+    pk, gk = kspace_box2(Ls, xi, x, q, targets)
+    q = np.asarray(q, dtype=np.float64)
+    qs = q if targets is None else q[np.asarray(targets)]
+    return pr + pk + self_term(xi, qs), gr + gk
 
 
 def total_box3(Ls, xi, x, q, targets=None):

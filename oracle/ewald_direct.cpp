@@ -446,6 +446,92 @@ int oracle_kspace_box3(const double* Ls, double xi, const int* nmax, long N, con
   return 0;
 }
 
+// Doubly periodic lattice with a rectangular cell Ls[0] x Ls[1] in x, y and
+// z free (the paper's remark that the domain need not be a cube, with the
+// 2P sums of Section 2).  Real space, Eq. (real_space_ewald): images
+// (a Ls[0], b Ls[1], 0) within rc, the n == m term at p = 0 excluded.
+int oracle_real_space_box2(const double* Ls, double xi, double rc, long N, const double* x, const double* q,
+                           long T, const long* tgt, double* phi, double* grad) {
+  if (!Ls || Ls[0] <= 0 || Ls[1] <= 0 || xi <= 0 || rc <= 0) return 1;
+  const int na = (int)std::ceil(rc / Ls[0]) + 1, nb = (int)std::ceil(rc / Ls[1]) + 1;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (long t = 0; t < T; ++t) {
+    const long m = tgt[t];
+    double s = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    for (long n = 0; n < N; ++n)
+      for (int a = -na; a <= na; ++a)
+        for (int b = -nb; b <= nb; ++b) {
+          if (n == m && a == 0 && b == 0) continue;
+          const double dx = x[3 * m] - x[3 * n] + a * Ls[0];
+          const double dy = x[3 * m + 1] - x[3 * n + 1] + b * Ls[1];
+          const double dz = x[3 * m + 2] - x[3 * n + 2];
+          const double r = std::sqrt(dx * dx + dy * dy + dz * dz);
+          if (r >= rc) continue;
+          const double e = std::erfc(xi * r) / r;
+          s += q[n] * e;
+          const double dr = -e / r - 2.0 * xi / std::sqrt(kPi) * std::exp(-xi * xi * r * r) / r;
+          gx += q[n] * dr * dx / r;
+          gy += q[n] * dr * dy / r;
+          gz += q[n] * dr * dz / r;
+        }
+    phi[t] = s;
+    if (grad) {
+      grad[3 * t] = gx;
+      grad[3 * t + 1] = gy;
+      grad[3 * t + 2] = gz;
+    }
+  }
+  return 0;
+}
+
+// Fourier-space part for the rectangular 2P cell: Eqs. (2pno0) and (2p0)
+// with the cell area A = Ls[0] Ls[1] in place of L^2 and
+// k = 2 pi (n1/Ls[0], n2/Ls[1]), |n_d| <= nmax[d].
+int oracle_kspace_box2(const double* Ls, double xi, const int* nmax, long N, const double* x, const double* q,
+                       long T, const long* tgt, double* phi, double* grad) {
+  if (!Ls || !nmax || Ls[0] <= 0 || Ls[1] <= 0 || xi <= 0 || nmax[0] < 0 || nmax[1] < 0) return 1;
+  const double sqpi = std::sqrt(kPi), A = Ls[0] * Ls[1];
+#pragma omp parallel for schedule(dynamic, 1)
+  for (long t = 0; t < T; ++t) {
+    const long m = tgt[t];
+    double s = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    for (long n = 0; n < N; ++n) {
+      const double vx = x[3 * m] - x[3 * n], vy = x[3 * m + 1] - x[3 * n + 1];
+      const double z = x[3 * m + 2] - x[3 * n + 2];
+      double sn = 0.0, snx = 0.0, sny = 0.0, snz = 0.0;
+      for (int a = -nmax[0]; a <= nmax[0]; ++a)
+        for (int b = -nmax[1]; b <= nmax[1]; ++b) {
+          if (a == 0 && b == 0) continue;
+          const double kx = 2.0 * kPi * a / Ls[0], ky = 2.0 * kPi * b / Ls[1];
+          const double k = std::sqrt(kx * kx + ky * ky);
+          const double ap = k / (2.0 * xi) + xi * z, am = k / (2.0 * xi) - xi * z;
+          const double tp = ap > 27.0 ? 0.0 : std::exp(k * z) * std::erfc(ap);
+          const double tm = am > 27.0 ? 0.0 : std::exp(-k * z) * std::erfc(am);
+          const double c = std::cos(kx * vx + ky * vy), si = std::sin(kx * vx + ky * vy);
+          sn += c * (tp + tm) / k;
+          snx -= kx * si * (tp + tm) / k;
+          sny -= ky * si * (tp + tm) / k;
+          snz += c * (tp - tm);
+        }
+      const double cn = kPi / A;
+      const double c0 = -2.0 * sqpi / A;
+      const double s0 = c0 * (std::exp(-xi * xi * z * z) / xi + sqpi * z * std::erf(xi * z));
+      const double s0z = c0 * sqpi * std::erf(xi * z);
+      s += q[n] * (cn * sn + s0);
+      gx += q[n] * cn * snx;
+      gy += q[n] * cn * sny;
+      gz += q[n] * (cn * snz + s0z);
+    }
+    phi[t] = s;
+    if (grad) {
+      grad[3 * t] = gx;
+      grad[3 * t + 1] = gy;
+      grad[3 * t + 2] = gz;
+    }
+  }
+  return 0;
+}
+
 // Exposed for the tests that pin the quadrature: K0(a,b) and dK0/db.
 void oracle_incomplete_k0(double a, double b, double* k0, double* dk0_db) {
   incomplete_k0(a, b, k0, dk0_db);

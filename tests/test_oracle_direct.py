@@ -242,3 +242,57 @@ def test_box_xi_invariance():
     p2, g2 = direct.total_box3(Ls, 8.0, x, q)
     np.testing.assert_allclose(p1, p2, rtol=0, atol=1e-12 * np.abs(p1).max())
     np.testing.assert_allclose(g1, g2, rtol=0, atol=1e-11 * np.abs(g1).max())
+
+
+@pytest.mark.parametrize("xi", [3.0, 6.0])
+@pytest.mark.parametrize("reps", [(1, 2), (3, 1)])
+def test_box2_madelung_square_lattice(xi, reps):
+    """The alternating square lattice (spacing 1/2, one layer, z free) in a
+    doubly periodic rectangular cell of reps[0] x reps[1] unit cells: the
+    Madelung constant per ion is the square cell's."""
+    a = 0.5
+    off = np.array([0.1234, 0.2345, 0.3456])
+    pts, qs = [], []
+    for i in range(2 * reps[0]):
+        for j in range(2 * reps[1]):
+            pts.append(np.array([i * a + off[0], j * a + off[1], off[2]]))
+            qs.append((-1.0) ** (i + j))
+    x, q = np.array(pts), np.array(qs)
+    phi, g = direct.total_box2(np.array(reps, dtype=float), xi, x, q)
+    np.testing.assert_allclose(-phi * a / q, 1.615542626712880, rtol=0, atol=2e-11)
+    np.testing.assert_allclose(g, 0.0, atol=1e-9)
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_box2_supercell_matches_square_cell(axis):
+    """Two copies of a 2P unit cell in a cell twice as long along a periodic
+    axis: each part of the split at the original charges equals the square
+    cell's (the free direction untouched)."""
+    x, q = wl.system(20, 1.0, 170 + axis, "uniform")
+    shift = np.zeros(3)
+    shift[axis] = 1.0
+    x2, q2 = np.concatenate([x, x + shift]), np.concatenate([q, q])
+    Ls = np.ones(2)
+    Ls[axis] = 2.0
+    xi = 5.0
+    tg = np.arange(len(q))
+    pk, gk = direct.kspace(2, 1.0, xi, x, q)
+    pk2, gk2 = direct.kspace_box2(Ls, xi, x2, q2, targets=tg)
+    np.testing.assert_allclose(pk2, pk, rtol=0, atol=1e-12 * np.abs(pk).max())
+    np.testing.assert_allclose(gk2, gk, rtol=0, atol=1e-11 * np.abs(gk).max())
+    rc = direct.real_space_cutoff(xi)
+    pr, gr = direct.real_space(2, 1.0, xi, rc, x, q)
+    pr2, gr2 = direct.real_space_box2(Ls, xi, rc, x2, q2, targets=tg)
+    np.testing.assert_allclose(pr2, pr, rtol=0, atol=1e-12 * np.abs(pr).max())
+    np.testing.assert_allclose(gr2, gr, rtol=0, atol=1e-11 * np.abs(gr).max())
+
+
+def test_box2_xi_invariance():
+    """For a rectangular 2P cell the total potential does not depend on xi."""
+    x, q = wl.system(20, 1.0, 191, "uniform")
+    x = x * np.array([1.0, 0.6, 1.0])
+    Ls = np.array([1.0, 0.6])
+    p1, g1 = direct.total_box2(Ls, 4.0, x, q)
+    p2, g2 = direct.total_box2(Ls, 8.0, x, q)
+    np.testing.assert_allclose(p1, p2, rtol=0, atol=1e-12 * np.abs(p1).max())
+    np.testing.assert_allclose(g1, g2, rtol=0, atol=1e-11 * np.abs(g1).max())

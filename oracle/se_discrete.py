@@ -136,8 +136,10 @@ class Params:
         if self.Mz is None:
             self.Mz = self.M
         if (self.My, self.Mz) != (self.M, self.M):
-            if self.D != 3:
-                raise ValueError("rectangular boxes are triply periodic here")
+            # rectangular periodic cells: triply periodic boxes, or a doubly
+            # periodic cell M h x My h with the free direction of extent L
+            if self.D not in (2, 3) or (self.D == 2 and self.Mz != self.M):
+                raise ValueError("rectangular cells are triply periodic, or doubly periodic in x and y")
             if self.My % 2 or self.Mz % 2 or self.P > min(self.My, self.Mz):
                 raise ValueError("My and Mz must be even and at least P")
         if self.shape is None:
@@ -501,9 +503,12 @@ def _mode_classes(p: Params):
     and set J (Eq. J)."""
     n = np.fft.fftfreq(p.M, d=1.0 / p.M)   # signed integers
     if p.D == 2:
-        n1, n2 = np.meshgrid(n, n, indexing="ij")
+        n1, n2 = np.meshgrid(n, np.fft.fftfreq(p.My, d=1.0 / p.My), indexing="ij")
         zero = (n1 == 0) & (n2 == 0)
-        box = (np.abs(n1) <= p.n_l) & (np.abs(n2) <= p.n_l)
+        # the set I bounds the wavenumber, |k_d| <= 2 pi n_l / L, in each
+        # periodic direction: index n_l along x, n_l My / M along y (the
+        # same n_l for a square cell)
+        box = (np.abs(n1) <= p.n_l) & (np.abs(n2) <= (p.n_l * p.My) // p.M)
     else:
         zero = n == 0
         box = np.abs(n) <= p.n_l
@@ -563,26 +568,30 @@ def scaled_convolution(H, p: Params, GR=None, deriv=None):
     kp = _periodic_k(M, L)
     sep_p = _sep(kp, p)
     if D == 2:
-        # Algorithm 1, step 1: FFT in the periodic directions x, y
+        # Algorithm 1, step 1: FFT in the periodic directions x, y (y of
+        # length My, side My h, in a rectangular cell)
+        My = p.My
+        kq = _periodic_k(My, p.Ld[1])
+        sep_q = _sep(kq, p)
         Hk = np.fft.fft2(H, axes=(0, 1))
-        out = np.zeros((M, M, Mt), dtype=complex)
+        out = np.zeros((M, My, Mt), dtype=complex)
         for mask, length in ((zero, p.n0), (I, p.nI), (J, Mt)):
             if not mask.any():
                 continue
             sub = Hk[mask]                                  # (modes, Mt)
             Hs = _pad_fft(sub, (1,), length)                # Algorithm 1, steps 2-4
             kap = _free_k(length, h)
-            k1 = np.broadcast_to(kp[:, None], (M, M))[mask]
-            k2 = np.broadcast_to(kp[None, :], (M, M))[mask]
-            s12 = (np.broadcast_to(sep_p[:, None], (M, M)) * np.broadcast_to(sep_p[None, :], (M, M)))[mask]
+            k1 = np.broadcast_to(kp[:, None], (M, My))[mask]
+            k2 = np.broadcast_to(kq[None, :], (M, My))[mask]
+            s12 = (np.broadcast_to(sep_p[:, None], (M, My)) * np.broadcast_to(sep_q[None, :], (M, My)))[mask]
             kk2 = k1 ** 2 + k2 ** 2
             if mask is zero:
                 G = G_hat_2P_zero(kap, p.R)[None, :] * np.ones((sub.shape[0], 1))
             else:
                 G = 1.0 / (kk2[:, None] + kap[None, :] ** 2)    # Eq. (G_hat_2d), k != 0
             S = s12[:, None] * _sep(kap, p)[None, :] * G
-            ik12 = (np.broadcast_to(np.reshape(_ik(kp, deriv, 0), (-1, 1)), (M, M))
-                    * np.broadcast_to(np.reshape(_ik(kp, deriv, 1), (1, -1)), (M, M)))[mask]
+            ik12 = (np.broadcast_to(np.reshape(_ik(kp, deriv, 0), (-1, 1)), (M, My))
+                    * np.broadcast_to(np.reshape(_ik(kq, deriv, 1), (1, -1)), (M, My)))[mask]
             S = S * ik12[:, None] * np.reshape(_ik(kap, deriv, 2), (1, -1))
             out[mask] = _ifft_trunc(S * Hs, (1,), Mt)       # Algorithm 2, steps 1-4
         return np.fft.ifft2(out, axes=(0, 1)).real          # Algorithm 2, step 5

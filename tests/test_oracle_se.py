@@ -523,5 +523,49 @@ def test_box_high_accuracy_against_direct():
 
 
 def test_box_rejects_other_periodicities():
+    """Rectangular cells are triply periodic boxes or doubly periodic cells
+    (the free direction of a 2P cell keeps extent L)."""
     with pytest.raises(ValueError):
-        se.Params(D=2, L=1.0, xi=7.0, M=24, P=8, My=30, s=2.0, n_l=3)
+        se.Params(D=2, L=1.0, xi=7.0, M=24, P=8, Mz=30, s=2.0, n_l=3)
+    with pytest.raises(ValueError):
+        se.Params(D=1, L=1.0, xi=7.0, M=24, P=8, My=30, s=2.0, n_l=3)
+    with pytest.raises(ValueError):
+        se.Params(D=0, L=1.0, xi=7.0, M=24, P=8, My=30)
+    se.Params(D=2, L=1.0, xi=7.0, M=24, P=8, My=30, s=2.0, n_l=3)
+
+
+def test_box2_supercell_matches_square_cell():
+    """Two copies of a square 2P cell in a cell twice as long along y, on a
+    grid twice as long there: with the set I bounded by wavenumber (index
+    n_l My / M along y) the gridded charges, the mode classes and the
+    scaling are the square cell's repeated, so the SE potentials and
+    gradients at the original charges equal the square cell's (to
+    rounding)."""
+    x, q = wl.system(60, 1.0, 310, "uniform")
+    x2, q2 = np.concatenate([x, x + [0.0, 1.0, 0.0]]), np.concatenate([q, q])
+    Q = float((q * q).sum())
+    pp = se.with_aft_estimates(2, 1.0, 7.0, 24, 8, Q, 1e-14 * se.B_scale(Q, 7.0, 1.0), window="pkb")
+    p = se.Params(D=2, L=1.0, xi=7.0, M=24, P=8, s=pp.s, n_l=pp.n_l)
+    p2 = se.Params(D=2, L=1.0, xi=7.0, M=24, P=8, My=48, s=pp.s, n_l=pp.n_l)
+    assert p2.Ld[1] == 2.0 and p2.grid_shape == (24, 48, p.Mt)
+    phi, g = se.spectral_ewald(x, q, p)
+    phi2, g2 = se.spectral_ewald(x2, q2, p2, targets=np.arange(len(q)))
+    assert rel(phi2, phi) < 1e-13 and rel(g2, g) < 1e-13
+
+
+def test_box2_high_accuracy_against_direct():
+    """A 1 x 0.75 doubly periodic cell (M = 40, My = 30 at h = 1/40, z free),
+    PKB P = 16 with the AFT estimates at 1e-16: the SE result equals the
+    direct rectangular-cell 2P sum to ~1e-12."""
+    rng = np.random.default_rng(616)
+    Ls = np.array([1.0, 0.75, 1.0])
+    x = rng.random((90, 3)) * Ls
+    q = rng.standard_normal(90)
+    q -= q.mean()
+    Q = float((q * q).sum())
+    pp = se.with_aft_estimates(2, 1.0, 8.0, 40, 16, Q, 1e-16 * se.B_scale(Q, 8.0, 1.0), window="pkb")
+    p = se.Params(D=2, L=1.0, xi=8.0, M=40, P=16, nu=9, My=30, s=pp.s, n_l=pp.n_l)
+    phi, g = se.spectral_ewald(x, q, p)
+    ref, gref = direct.kspace_box2(Ls, 8.0, x, q)
+    assert rel(phi, ref) < 5e-12
+    assert rel(g, gref) < 5e-10

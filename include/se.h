@@ -123,11 +123,13 @@ typedef struct {
                          by its own polynomial with the same P, beta, nu
                          (Section 7.2; the gradient is then not the energy's
                          exact derivative)                                      */
-  int My, Mz;         /* triply periodic rectangular boxes (Section 2 notes that
-                         the domain need not be a cube): grid intervals along y
-                         and z at the same spacing h = L/M, so the box is
-                         L x My h x Mz h; even, 7-smooth, >= P; <= 0 -> M (a
-                         cube).  D = 3 only (SE_ERR_PARAM otherwise)            */
+  int My, Mz;         /* rectangular periodic cells (Section 2 notes that the
+                         domain need not be a cube): grid intervals along y
+                         and z at the same spacing h = L/M, so a triply
+                         periodic box is L x My h x Mz h and a doubly periodic
+                         cell L x My h (z free, extent L, Mz = M); even,
+                         7-smooth, >= P; <= 0 -> M.  D = 3 (My, Mz) or D = 2
+                         (My only); SE_ERR_PARAM otherwise                      */
 } se_params;
 
 /* Derived sizes of a plan (read-only report). */
@@ -472,14 +474,15 @@ se_status se_rs_plan_create(int D, double L, double xi, double rc, long n_max, s
  * positive and finite, n_max < 0 or cells_per_rc > 8. */
 se_status se_rs_cells_box(const double* Ls, double rc, long n_max, int cells_per_rc, int* cells, int* span);
 
-/* As se_rs_plan_create for D = 3 in a rectangular box of sides Ls[0] x Ls[1]
- * x Ls[2] (host, 3 values; periodic coordinates wrapped per direction by
- * its side), with the cells of se_rs_cells_box.  The same rectangular box
- * is the one of a se_params with M, My, Mz grid points at spacing h = L / M:
- * Ls = {L, My h, Mz h}.  se_rs_get_info reports the x direction.
- * Errors: SE_ERR_ARG (Ls or out NULL), SE_ERR_PARAM (xi, prec, n_max, or as
- * se_rs_cells_box), SE_ERR_NOMEM. */
-se_status se_rs_plan_create_box(const double* Ls, double xi, double rc, long n_max, se_precision prec,
+/* As se_rs_plan_create for periodicity D in a rectangular box of sides
+ * Ls[0] x Ls[1] x Ls[2] (host, 3 values): periodic coordinates wrapped by
+ * their direction's side, free ones in [0, Ls[d]); cells of
+ * se_rs_cells_box.  The rectangular cells of a se_params with M, My, Mz grid
+ * intervals at spacing h = L / M are Ls = {L, My h, Mz h} (D = 3) and
+ * Ls = {L, My h, L} (D = 2, z free).  se_rs_get_info reports the x direction.
+ * Errors: SE_ERR_ARG (Ls or out NULL), SE_ERR_PARAM (D, xi, prec, n_max, or
+ * as se_rs_cells_box), SE_ERR_NOMEM. */
+se_status se_rs_plan_create_box(int D, const double* Ls, double xi, double rc, long n_max, se_precision prec,
                                 int cells_per_rc, void* hip_stream, se_rs_plan** out);
 
 /* Workspace of a real-space plan: size in bytes (host output), and binding

@@ -163,7 +163,8 @@ _SIGS = {
                                          ctypes.POINTER(ctypes.c_void_p)]),
     "se_rs_cells_box": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.c_double, ctypes.c_long, ctypes.c_int,
                                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
-    "se_rs_plan_create_box": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.c_double, ctypes.c_double,
+    "se_rs_plan_create_box": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_double,
+                                             ctypes.c_double,
                                              ctypes.c_long, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                              ctypes.POINTER(ctypes.c_void_p)]),
     "se_rs_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
@@ -446,11 +447,11 @@ def se_rs_cells_box(Ls, rc, n_max, cells_per_rc=0):
     return tuple(c), tuple(sp)
 
 
-def se_rs_plan_create_box(Ls, xi, rc, n_max, prec, cells_per_rc=0, stream=0):
+def se_rs_plan_create_box(D, Ls, xi, rc, n_max, prec, cells_per_rc=0, stream=0):
     plan = ctypes.c_void_p()
     sides = (ctypes.c_double * 3)(*[float(v) for v in Ls])
-    _check(load().se_rs_plan_create_box(sides, float(xi), float(rc), int(n_max), int(prec), int(cells_per_rc),
-                                        ctypes.c_void_p(stream), ctypes.byref(plan)),
+    _check(load().se_rs_plan_create_box(int(D), sides, float(xi), float(rc), int(n_max), int(prec),
+                                        int(cells_per_rc), ctypes.c_void_p(stream), ctypes.byref(plan)),
            "se_rs_plan_create_box")
     return plan
 

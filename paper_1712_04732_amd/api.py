@@ -45,8 +45,9 @@ class SpectralEwald:
     force_method 1 differentiates the gathering window, 2 multiplies the
     scaling step by i k (Section 7.2); with 2 the autograd functions receive
     method 2's gradient, an approximation of the discrete energy's gradient
-    to the method's accuracy.  My, Mz (D = 3 only) make the box rectangular,
-    L x My h x Mz h at h = L/M.
+    to the method's accuracy.  My, Mz make the periodic cell rectangular at
+    h = L/M: a triply periodic box L x My h x Mz h (D = 3), or a doubly
+    periodic cell L x My h with z free (D = 2, My only).
 
     Call it with positions x (N,3) and charges q (N,) on the GPU.
     """
@@ -80,7 +81,7 @@ class SpectralEwald:
         p.tile = tile
         p.force_method = force_method
         p.deriv_fit = 1 if deriv_fit else 0
-        # triply periodic rectangular box L x My h x Mz h (h = L / M); 0: a cube
+        # rectangular periodic cell L x My h (x Mz h in 3P), h = L / M; 0: square
         p.My, p.Mz = int(My), int(Mz)
         self.params = p
         self.n_max = int(n_max)
@@ -413,8 +414,9 @@ class RealSpace:
     """The real-space sum of the Ewald split, Eq. (real_space_ewald), with
     cutoff rc, on the GPU (cell list in the HIP library).  Adds to a k-space
     result of SpectralEwald (accumulate=True) to give the full potential of
-    Eq. (potential_split).  L_box is the side of a cube, or, for D = 3, the
-    three sides of a rectangular box (SpectralEwald(..., My, Mz).box)."""
+    Eq. (potential_split).  L_box is the side of a cube, or the three sides
+    of a rectangular box (SpectralEwald(..., My, Mz).box: free directions
+    extend over their side)."""
 
     def __init__(self, D, L_box, xi, rc, *, prec="f64", n_max=1 << 20, cells_per_rc=0):
         if not torch.cuda.is_available():
@@ -425,10 +427,10 @@ class RealSpace:
         self.dtype = torch.float64 if prec == "f64" else torch.float32
         self.n_max = int(n_max)
         if isinstance(L_box, (tuple, list)):
-            if D != 3 or len(L_box) != 3:
-                raise ValueError("a rectangular box takes D = 3 and three sides")
+            if len(L_box) != 3:
+                raise ValueError("a rectangular box takes three sides")
             self.L = self.box = tuple(float(v) for v in L_box)
-            self._plan = L.se_rs_plan_create_box(self.box, xi, rc, self.n_max, _PRECS[prec], cells_per_rc,
+            self._plan = L.se_rs_plan_create_box(D, self.box, xi, rc, self.n_max, _PRECS[prec], cells_per_rc,
                                                  _stream())
             _, _, self.device_bytes = L.se_rs_get_info(self._plan)
             self.cells, self.span = L.se_rs_cells_box(self.box, rc, self.n_max, cells_per_rc)

@@ -779,11 +779,12 @@ static se_status plan_create(const se_params* params, long n_max, void* hip_stre
   if (p.deriv_fit < 0 || p.deriv_fit > 1 || (p.deriv_fit && p.window != SE_WIN_PKB)) return SE_ERR_PARAM;
   if (p.prec != SE_F64 && p.prec != SE_F32) return SE_ERR_PARAM;
   if (!is_smooth(p.M)) return SE_ERR_PARAM;
-  // rectangular triply periodic boxes: My, Mz grid intervals at spacing L/M
+  // rectangular periodic cells: My, Mz grid intervals at spacing L/M in a
+  // triply periodic box, My in a doubly periodic cell (z free, extent L)
   if (p.My <= 0) p.My = p.M;
   if (p.Mz <= 0) p.Mz = p.M;
   if (p.My != p.M || p.Mz != p.M) {
-    if (p.D != 3) return SE_ERR_PARAM;
+    if (p.D < 2 || (p.D == 2 && p.Mz != p.M)) return SE_ERR_PARAM;
     for (int m : {p.My, p.Mz})
       if (m % 2 || m < p.P || m > 4096 || !is_smooth(m)) return SE_ERR_PARAM;
   }
@@ -1122,42 +1123,54 @@ static se_status build_passes(se_plan* pl, hipStream_t st) {
     } else {
       // 2P: AFT classes, Algorithm 1 steps 2-4 / Algorithm 2 steps 1-3
       const int n0 = I.n0, nI = I.nI, nl = I.n_l;
+      // y of length Gy (My in a rectangular cell, side Gy h): its own
+      // separable vector and squared wavenumbers; the set I bounds the
+      // wavenumber, index n_l along x and n_l Gy / M along y
+      const int nly = (int)((long)nl * Gy / M);
+      const void* sepY = Gy == M ? sepM : pl->sep_table(Gy);
+      const void* k2Y = Gy == M ? k2M : pl->k2_table(Gy);
       const void* s0t = pl->sep_table(n0);
       const void* sIt = pl->sep_table(nI);
       const void* sJt = pl->sep_table(Mt);
       const void* kIt = pl->k2_table(nI);
       const void* kJt = pl->k2_table(Mt);
+      if (!sepY || !k2Y) return fail();
       std::vector<double> g0(n0);
       for (int t = 0; t < n0; ++t) g0[t] = g2p_zero(2.0 * kPi * signed_freq(t, n0) / (n0 * I.h), I.R);
       const void* g0t = pl->upload(g0);
       if (!s0t || !sIt || !sJt || !kIt || !kJt || !g0t) return fail();
       se::FftClass c0 = make_class(n0, Mt, Mt, cb, cb, zst, 1, Kx, zst, 1, Kx);
       c0.gmode = se::G_TAB1;
-      c0.sA = c0.sB = sepM;
+      c0.sA = sepM;
+      c0.sB = sepY;
       c0.sC = s0t;
       c0.gtab = g0t;
       se::FftClass cI = make_class(nI, Mt, Mt, cb, cb, zst, 1, Kx, zst, 1, Kx);
       cI.gmode = se::G_INVSQ;
-      cI.sA = cI.sB = sepM;
-      cI.kA = cI.kB = k2M;
+      cI.sA = sepM;
+      cI.sB = sepY;
+      cI.kA = k2M;
+      cI.kB = k2Y;
       cI.sC = sIt;
       cI.kC = kIt;
       se::FftClass cJ = make_class(Mt, Mt, Mt, cb, cb, zst, 1, Kx, zst, 1, Kx);
       cJ.gmode = se::G_INVSQ;
-      cJ.sA = cJ.sB = sepM;
-      cJ.kA = cJ.kB = k2M;
+      cJ.sA = sepM;
+      cJ.sB = sepY;
+      cJ.kA = k2M;
+      cJ.kB = k2Y;
       cJ.sC = sJt;
       cJ.kC = kJt;
-      set_d(c0, M, M, n0, 0, 1);
-      set_d(cI, M, M, nI, 0, 1);
-      set_d(cJ, M, M, Mt, 0, 1);
+      set_d(c0, M, Gy, n0, 0, 1);
+      set_d(cI, M, Gy, nI, 0, 1);
+      set_d(cJ, M, Gy, Mt, 0, 1);
       p3.cls[0] = c0;
       p3.cls[1] = cI;
       p3.cls[2] = cJ;
       rg.clear();
-      for (int ky = 0; ky < M; ++ky) {
-        const int sky = std::abs(signed_freq(ky, M) == M / 2 ? -M / 2 : signed_freq(ky, M));
-        if (sky <= nl) {
+      for (int ky = 0; ky < Gy; ++ky) {
+        const int sky = std::abs(signed_freq(ky, Gy) == Gy / 2 ? -Gy / 2 : signed_freq(ky, Gy));
+        if (sky <= nly) {
           if (ky == 0) {
             rg.push_back({0, 0, 1, ky, ky + 1});
             if (nl >= 1) rg.push_back({1, 1, std::min(nl, Kx - 1) + 1, ky, ky + 1});

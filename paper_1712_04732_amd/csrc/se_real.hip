@@ -7,8 +7,8 @@
 // the split in the same way).  It completes the k-space result of se_eval
 // into the full potential of Eq. (potential_split).
 //
-// Cell list: the box (a cube, or a triply periodic rectangular box with a
-// side per direction) is cut into c_d cells of side h_d = L_d/c_d >= rc/s_d
+// Cell list: the box (a cube, or a rectangular box with a side per
+// direction) is cut into c_d cells of side h_d = L_d/c_d >= rc/s_d
 // per direction; every charge within rc of a target lies in the
 // (2s_x+1)(2s_y+1)(2s_z+1) cells around the target's cell (periodic
 // directions wrap with an image shift, free directions stop at the box).  Cells whose nearest points are rc or more
@@ -622,17 +622,17 @@ se_status se_rs_plan_create(int D, double L, double xi, double rc, long n_max, s
   return rs_plan_make(D, c3, s3, L3, xi, rc, n_max, prec, out);
 }
 
-se_status se_rs_plan_create_box(const double* Ls, double xi, double rc, long n_max, se_precision prec,
+se_status se_rs_plan_create_box(int D, const double* Ls, double xi, double rc, long n_max, se_precision prec,
                                 int cells_per_rc, void* hip_stream, se_rs_plan** out) {
   (void)hip_stream;
   if (!out) return SE_ERR_ARG;
   *out = nullptr;
   if (!Ls) return SE_ERR_ARG;
-  if (!rs_args_ok(3, xi, n_max, prec)) return SE_ERR_PARAM;
+  if (!rs_args_ok(D, xi, n_max, prec)) return SE_ERR_PARAM;
   int c3[3], s3[3];
   const se_status st = se_rs_cells_box(Ls, rc, n_max, cells_per_rc, c3, s3);
   if (st != SE_OK) return st;
-  return rs_plan_make(3, c3, s3, Ls, xi, rc, n_max, prec, out);
+  return rs_plan_make(D, c3, s3, Ls, xi, rc, n_max, prec, out);
 }
 
 se_status se_rs_workspace_size(const se_rs_plan* plan, size_t* bytes) {

@@ -263,6 +263,57 @@ def test_rectangular_box_parity_with_oracle(Ls, rc, prec):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("Ls,rc", [((1.0, 0.6, 1.0), 0.15), ((1.0, 1.7, 0.8), 0.4)])
+def test_rectangular_2p_cell_parity_with_oracle(Ls, rc, prec):
+    """Doubly periodic rectangular cells (x, y periodic with their own
+    sides, z free over [0, Ls[2])) against the direct rectangular-cell
+    real-space sum, to the cube's bounds."""
+    print(f"case real space 2P cell {Ls} rc={rc} {prec}", flush=True)
+    N = 600
+    xi = 4.8 / rc
+    x, q = _box_system(N, Ls, 5300 + int(100 * rc))
+    rs = RealSpace(2, Ls, xi, rc, prec=prec, n_max=N)
+    phi, g, E = run(rs, x, q)
+    pr, gr = direct.real_space_box2(Ls, xi, rc, x, q)
+    tol_phi, tol_g = (1e-13, 1e-12) if prec == "f64" else (3e-6, 3e-6)
+    print(f"  cells {rs.cells} span {rs.span}: phi {rel(phi, pr):.2e} grad {rel(g, gr):.2e}")
+    assert rel(phi, pr) < tol_phi
+    assert rel(g, gr) < tol_g
+
+
+def test_full_potential_madelung_rectangular_2p_cell():
+    """The alternating square lattice (spacing 1/4, one layer, z free) in a
+    1 x 0.5 doubly periodic cell: k space on the M = 40, My = 20 grid (PKB
+    P = 16, AFT parameters at 1e-16), the real-space part on the 2P box plan
+    and the self term give the square-lattice Madelung constant at every
+    ion."""
+    print("case madelung 2P cell", flush=True)
+    a = 0.25
+    off = np.array([0.1234, 0.2345, 0.3456]) * a
+    pts, qs = [], []
+    for i in range(4):
+        for j in range(2):
+            pts.append(np.array([i * a + off[0], j * a + off[1], 0.5]))
+            qs.append((-1.0) ** (i + j))
+    x, q = np.array(pts), np.array(qs)
+    xi, M, P = 6.0, 40, 16
+    Q = float((q * q).sum())
+    pp = se.with_aft_estimates(2, 1.0, xi, M, P, Q, 1e-16 * se.B_scale(Q, xi, 1.0), window="pkb")
+    ks = SpectralEwald(2, 1.0, xi, M, P, window="pkb", prec="f64", n_max=len(q), My=20, s=pp.s, n_l=pp.n_l)
+    assert ks.box == (1.0, 0.5, 1.0)
+    rs = RealSpace(2, ks.box, xi, direct.real_space_cutoff(xi), prec="f64", n_max=len(q))
+    xt = torch.tensor(x, dtype=torch.float64, device=DEV)
+    qt = torch.tensor(q, dtype=torch.float64, device=DEV)
+    out = ks(xt, qt, add_self=True, out_grad=True)
+    phi, g, E = rs(xt, qt, out_grad=True, accumulate=True, out=out)
+    torch.cuda.synchronize()
+    m = -phi.cpu().numpy() * a / q
+    print(f"  madelung 2P cell: {m[0]:.15f} (cells {rs.cells}, span {rs.span})")
+    np.testing.assert_allclose(m, 1.615542626712880, rtol=0, atol=1e-10)
+    np.testing.assert_allclose(g.cpu().numpy(), 0.0, atol=1e-8)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_rectangular_box_of_equal_sides_is_the_cube(prec):
     """A box plan with three equal sides takes the cube's cells and gives the
     cube plan's results bit for bit."""

@@ -193,6 +193,66 @@ def test_rectangular_box_against_direct():
     assert rel(phi, ref) < 5e-12 and rel(g, gref) < 5e-10
 
 
+@pytest.mark.parametrize("My,window,P,fm", [(30, "pkb", 8, 1), (48, "gaussian", 8, 1), (20, "pkb", 8, 2),
+                                          (40, "es", 6, 1)])
+def test_rectangular_2p_cell_matches_discrete_oracle(My, window, P, fm):
+    """Doubly periodic cells L x My h (z free): FP64 potentials and gradients
+    against the discrete oracle with the same parameters (rounding only;
+    the set I of Algorithm 1 bounded by wavenumber in each periodic
+    direction on both sides); FP32 within the FP32 bounds."""
+    print(f"case 2P cell M=32 My={My} {window} P={P} method {fm}", flush=True)
+    M, L, xi = 32, 1.0, 9.0
+    h = L / M
+    x, q = _box_system(700, (L, My * h, L), 2200 + My)
+    Q = float((q * q).sum())
+    pp = se.with_aft_estimates(2, L, xi, M, P, Q, 1e-10 * se.B_scale(Q, xi, L), window=window)
+    p = se.Params(D=2, L=L, xi=xi, M=M, P=P, window=window, My=My, s=pp.s, n_l=pp.n_l)
+    ref, gref = se.spectral_ewald(x, q, p, force_method=fm)
+    plan = SpectralEwald(2, L, xi, M, P, window=window, prec="f64", n_max=len(q), My=My, s=pp.s, n_l=pp.n_l,
+                         force_method=fm)
+    assert tuple(plan.info.grid) == (M, My, p.Mt)
+    phi, g, _ = run(plan, x, q)
+    assert rel(phi, ref) < 1e-12 and rel(g, gref) < 1e-11
+    p32 = SpectralEwald(2, L, xi, M, P, window=window, prec="f32", n_max=len(q), My=My, s=pp.s, n_l=pp.n_l,
+                        force_method=fm)
+    phi32, g32, _ = run(p32, x, q)
+    assert rel(phi32, ref) < 1e-5 and rel(g32, gref) < 2e-5
+
+
+def test_rectangular_2p_supercell_matches_square_cell():
+    """Two copies of a square 2P cell in a cell twice as long along y give the
+    square cell's potentials and gradients at the original charges (the
+    set I bounded by wavenumber covers the same modes)."""
+    print("case 2P supercell", flush=True)
+    M, L, xi, P = 32, 1.0, 9.0, 8
+    x, q = _box_system(600, (1.0, 1.0, 1.0), 4300)
+    x2, q2 = np.concatenate([x, x + [0.0, 1.0, 0.0]]), np.concatenate([q, q])
+    Q = float((q * q).sum())
+    pp = se.with_aft_estimates(2, L, xi, M, P, Q, 1e-12 * se.B_scale(Q, xi, L), window="pkb")
+    cell = SpectralEwald(2, L, xi, M, P, prec="f64", n_max=len(q), s=pp.s, n_l=pp.n_l)
+    wide = SpectralEwald(2, L, xi, M, P, prec="f64", n_max=len(q2), My=2 * M, s=pp.s, n_l=pp.n_l)
+    phi, g, E = run(cell, x, q)
+    phi2, g2, E2 = run(wide, x2, q2)
+    n = len(q)
+    assert rel(phi2[:n], phi) < 1e-12 and rel(g2[:n], g) < 1e-11
+    assert abs(E2 - 2 * E) <= 1e-11 * abs(E)
+
+
+def test_rectangular_2p_cell_against_direct():
+    """PKB P = 16 in a 1 x 0.75 doubly periodic cell with AFT parameters at
+    1e-16: the GPU result equals the direct rectangular-cell 2P sum."""
+    print("case 2P cell vs direct", flush=True)
+    Ls = (1.0, 0.75, 1.0)
+    x, q = _box_system(300, Ls, 779)
+    Q = float((q * q).sum())
+    pp = se.with_aft_estimates(2, 1.0, 8.0, 40, 16, Q, 1e-16 * se.B_scale(Q, 8.0, 1.0), window="pkb")
+    plan = SpectralEwald(2, 1.0, 8.0, 40, 16, nu=9, prec="f64", n_max=len(q), My=30, s=pp.s, n_l=pp.n_l)
+    phi, g, _ = run(plan, x, q)
+    ref, gref = direct.kspace_box2(np.array(Ls), 8.0, x, q)
+    print(f"  vs direct phi {rel(phi, ref):.2e} grad {rel(g, gref):.2e}")
+    assert rel(phi, ref) < 5e-12 and rel(g, gref) < 5e-10
+
+
 def test_rectangular_boxes_in_a_batch():
     """A batch holding rectangular and cubic 3P systems gives each system's
     single-plan result."""

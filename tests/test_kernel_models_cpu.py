@@ -386,7 +386,9 @@ def _check_enumeration(D, Ls, rc, n, seed, ks=(1, 2, 3), cells_of=None):
             # brute force over every charge and image vector
             img = np.array(list(itertools.product(*[range(-K[d], K[d] + 1) if D > d else (0,)
                                                     for d in range(3)])))
-            r = np.linalg.norm(x[t][None, None, :] - x[:, None, :] - (img * Ls)[None, :, :], axis=2)
+            # the distance evaluated as the kernel's candidate test does, so
+            # that a pair at rc within rounding falls on the same side
+            r = np.linalg.norm(x[t][None, None, :] - (x[:, None, :] + (img * Ls)[None, :, :]), axis=2)
             want = {(int(j), tuple(int(v) for v in img[m])) for j, m in zip(*np.nonzero(r < rc))
                     if not (j == t and not img[m].any())}
             assert got == want, (D, tuple(Ls), rc, k, t)
@@ -409,15 +411,16 @@ def test_real_space_enumeration_visits_each_pair_once(D, rc_over_L):
     _check_enumeration(D, (L, L, L), rc, n, int(100 * rc_over_L) + D, cells_of=cells_of)
 
 
+@pytest.mark.parametrize("D", [3, 2])
 @pytest.mark.parametrize("Ls", [(1.0, 1.5, 0.5), (0.6, 1.0, 1.9), (2.0, 0.35, 1.0)])
 @pytest.mark.parametrize("rc", [0.12, 0.3, 0.7, 1.3])
-def test_real_space_enumeration_in_rectangular_boxes(Ls, rc):
-    """The same in triply periodic rectangular boxes, with cells, spans and
-    cell sides per direction (spans differing between directions, cutoffs
-    beyond the short side)."""
+def test_real_space_enumeration_in_rectangular_boxes(D, Ls, rc):
+    """The same in rectangular boxes, triply periodic or with z free, with
+    cells, spans and cell sides per direction (spans differing between
+    directions, cutoffs beyond the short side)."""
     n = 90
 
     def cells_of(k):
         return rs_cells_box(Ls, rc, n, k)
 
-    _check_enumeration(3, Ls, rc, n, int(1000 * rc + 10 * Ls[1]), cells_of=cells_of)
+    _check_enumeration(D, Ls, rc, n, int(1000 * rc + 10 * Ls[1]) + D, cells_of=cells_of)

@@ -66,10 +66,11 @@ def test_plan_create_rejects_invalid_parameters(D, Lb, xi, M, P):
     assert not plan.value
 
 
-@pytest.mark.parametrize("D,My,Mz", [(2, 30, 0), (1, 0, 30), (0, 30, 30), (3, 31, 0), (3, 0, 38), (3, 6, 0)])
+@pytest.mark.parametrize("D,My,Mz", [(2, 0, 30), (2, 30, 30), (1, 30, 0), (1, 0, 30), (0, 30, 30), (3, 31, 0),
+                                     (3, 0, 38), (3, 6, 0), (2, 31, 0), (2, 6, 0)])
 def test_plan_create_rejects_invalid_rectangular_boxes(D, My, Mz):
-    """Rectangular boxes are triply periodic only, with even, 7-smooth grid
-    lengths of at least P along y and z."""
+    """Rectangular cells are triply periodic boxes (My, Mz) or doubly periodic
+    cells (My only), with even, 7-smooth grid lengths of at least P."""
     lib = L.load()
     p = L.se_params()
     p.D, p.L, p.xi, p.M, p.P, p.window = D, 1.0, 5.0, 32, 8, L.SE_WIN_PKB
@@ -196,14 +197,16 @@ def test_real_space_cells_reject_invalid():
                          ((1.0, 1.0, 1.0), 0.1, 10, 9), ((float("nan"), 1.0, 1.0), 0.1, 10, 0)]:
         sides = (ctypes.c_double * 3)(*Ls)
         assert lib.se_rs_cells_box(sides, rc, n, k, c3, s3) == L.SE_ERR_PARAM
-        assert lib.se_rs_plan_create_box(sides, 1.0, rc, n, 0, k, None, ctypes.byref(plan)) == L.SE_ERR_PARAM
+        assert lib.se_rs_plan_create_box(3, sides, 1.0, rc, n, 0, k, None, ctypes.byref(plan)) == L.SE_ERR_PARAM
     sides = (ctypes.c_double * 3)(1.0, 2.0, 1.5)
     assert lib.se_rs_cells_box(None, 0.1, 10, 0, c3, s3) == L.SE_ERR_ARG
     assert lib.se_rs_cells_box(sides, 0.1, 10, 0, None, s3) == L.SE_ERR_ARG
-    assert lib.se_rs_plan_create_box(None, 1.0, 0.1, 10, 0, 0, None, ctypes.byref(plan)) == L.SE_ERR_ARG
-    assert lib.se_rs_plan_create_box(sides, 1.0, 0.1, 10, 0, 0, None, None) == L.SE_ERR_ARG
-    assert lib.se_rs_plan_create_box(sides, 0.0, 0.1, 10, 0, 0, None, ctypes.byref(plan)) == L.SE_ERR_PARAM
-    assert lib.se_rs_plan_create_box(sides, 1.0, 0.1, 10, 5, 0, None, ctypes.byref(plan)) == L.SE_ERR_PARAM
+    assert lib.se_rs_plan_create_box(3, None, 1.0, 0.1, 10, 0, 0, None, ctypes.byref(plan)) == L.SE_ERR_ARG
+    assert lib.se_rs_plan_create_box(3, sides, 1.0, 0.1, 10, 0, 0, None, None) == L.SE_ERR_ARG
+    assert lib.se_rs_plan_create_box(3, sides, 0.0, 0.1, 10, 0, 0, None, ctypes.byref(plan)) == L.SE_ERR_PARAM
+    assert lib.se_rs_plan_create_box(3, sides, 1.0, 0.1, 10, 5, 0, None, ctypes.byref(plan)) == L.SE_ERR_PARAM
+    assert lib.se_rs_plan_create_box(4, sides, 1.0, 0.1, 10, 0, 0, None, ctypes.byref(plan)) == L.SE_ERR_PARAM
+    assert lib.se_rs_plan_create_box(-1, sides, 1.0, 0.1, 10, 0, 0, None, ctypes.byref(plan)) == L.SE_ERR_PARAM
     assert lib.se_rs_eval(None, 0, None, None, None, None, None, 0, None) == L.SE_ERR_ARG
     assert lib.se_rs_plan_destroy(None) == L.SE_OK
 

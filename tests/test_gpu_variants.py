@@ -282,3 +282,38 @@ def test_rectangular_boxes_in_a_batch():
         assert rel(f[sl].cpu().numpy(), f1.cpu().numpy()) < 1e-12
         assert abs(float(E[k]) - float(e1)) <= 1e-13 * abs(float(e1))
         o += len(q)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_rectangular_2p_cells_in_a_batch(prec):
+    """A batch holding rectangular and square 2P cells with rectangular 3P
+    boxes gives each system's single-plan result (FP64 to rounding, FP32
+    bit for bit: the batch and a single plan run the same kernels on the
+    same work items)."""
+    print(f"case 2P cell batch {prec}", flush=True)
+    M, L, xi, P = 24, 1.0, 8.0, 8
+    h = L / M
+    kinds = [(2, 40, 0), (2, 24, 0), (3, 30, 18), (2, 16, 0)]
+    systems = []
+    for k, (D, My, Mz) in enumerate(kinds):
+        side = (L, My * h, (Mz or M) * h if D == 3 else L)
+        x, _ = _box_system(300 + 100 * k, side, 80 + k)
+        q = np.where(np.arange(len(x)) % 2 == 0, 1.0, -1.0)   # neutral, exact in FP32
+        systems.append((D, My, Mz, x, q))
+    dt = torch.float64 if prec == "f64" else torch.float32
+    plans = []
+    for D, My, Mz, x, q in systems:
+        kw = {"s": 2.5, "n_l": 3} if D == 2 else {}
+        plans.append(SpectralEwald(D, L, xi, M, P, prec=prec, n_max=len(q), My=My, Mz=Mz, **kw))
+    b = SpectralEwaldBatch([pl.params for pl in plans], [len(s[4]) for s in systems])
+    xt = torch.tensor(np.concatenate([s[3] for s in systems]), dtype=dt, device=DEV)
+    qt = torch.tensor(np.concatenate([s[4] for s in systems]), dtype=dt, device=DEV)
+    phi, f, E = b(xt, qt)
+    o = 0
+    for k, ((D, My, Mz, x, q), pl) in enumerate(zip(systems, plans)):
+        p1, f1, e1 = pl(torch.tensor(x, dtype=dt, device=DEV), torch.tensor(q, dtype=dt, device=DEV))
+        sl = slice(o, o + len(q))
+        tol = 1e-13 if prec == "f64" else 1e-6
+        assert rel(phi[sl].double().cpu().numpy(), p1.double().cpu().numpy()) < tol, k
+        assert rel(f[sl].double().cpu().numpy(), f1.double().cpu().numpy()) < 10 * tol, k
+        o += len(q)

@@ -455,26 +455,78 @@ def main_batch(args):
     print(json.dumps(result), flush=True)
 
 
-def single_systems(args, names=("C1_3P", "C2_0P", "C3_2P", "C4_1P")):
+SINGLE_SCHEDULE = os.path.join(ROOT, "paper_1712_04732_amd", "schedules", "single_systems.json")
+SINGLE_NAMES = ("C1_3P", "C2_0P", "C3_2P", "C4_1P")
+KNOBS = ("tile", "fft_cap", "xcd_tiles", "xcd_fft", "spread_mode")
+
+
+def _single_plan(name, prec, stored=None):
+    """The plan of a single-system configuration: default knobs, or the
+    autotuner's knobs stored for (name, prec) when given."""
+    import workloads as wl
+    from paper_1712_04732_amd import SpectralEwald, _lib
+    cfg = wl.CONFIGS[name]
+    D, N, L, M, P, xi, win = cfg["D"], cfg["N"], cfg["L"], cfg["M"], cfg["P"], cfg["xi"], cfg["window"]
+    kw = dict(window=win, n_max=N)
+    if D in (1, 2):
+        x, q = wl.config_system(name)
+        Q = float((q * q).sum())
+        kw.update(Q=Q, tol=1e-6 * _lib.se_error_scale(Q, xi, L))
+    plan = SpectralEwald(D, L, xi, M, P, prec=prec, **kw)
+    row = (stored or {}).get(name, {}).get(prec)
+    if row is None or row.get("M") != plan.params.M:
+        return plan, False
+    p = plan.params
+    for d in range(3):
+        p.tile3[d] = row["tile3"][d]
+    for k in KNOBS:
+        setattr(p, k, row[k])
+    return SpectralEwald.from_params(p, N), True
+
+
+def main_retune_singles(args):
+    """Run the single-plan autotuner on C1-C4 in both precisions and store the
+    chosen knobs (the single-system lines then time these plans)."""
+    import torch
+
+    import workloads as wl
+    dev = torch.device("cuda:0")
+    out = {}
+    for name in SINGLE_NAMES:
+        x, q = wl.config_system(name)
+        x64, q64 = torch.tensor(x, device=dev), torch.tensor(q, device=dev)
+        for prec in ("f32", "f64"):
+            plan, _ = _single_plan(name, prec)
+            tuned, rep = plan.autotune(x64, q64)
+            p = tuned.params
+            row = dict(M=p.M, tile3=list(p.tile3), **{k: getattr(p, k) for k in KNOBS})
+            out.setdefault(name, {})[prec] = row
+            print(f"bench: {name} {prec} autotuner {rep['candidates']} candidates: {rep['ms_default']:.3f} -> "
+                  f"{rep['ms_tuned']:.3f} ms {row}", file=sys.stderr, flush=True)
+    path = args.retune_singles
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    with open(path, "w") as f:
+        json.dump(dict(device="MI355X (gfx950)", systems=out), f, indent=1)
+
+
+def single_systems(args, names=SINGLE_NAMES):
     """The four single-system configurations in FP32 and FP64 (one plan each,
-    inputs resident): particles/s, per-stage rooflines of the FP32 run and the
-    FP32 error against FP64."""
+    inputs resident): particles/s with the stored autotuned knobs where
+    present (and with the default knobs beside them), per-stage rooflines of
+    the FP32 run and the FP32 error against FP64."""
     import numpy as np
     import torch
 
     import workloads as wl
-    from paper_1712_04732_amd import SpectralEwald, _lib
+    from paper_1712_04732_amd import _lib
     out = {}
     dev = torch.device("cuda:0")
     steps = max(5, args.steps // 2)
+    stored = json.load(open(SINGLE_SCHEDULE))["systems"] if os.path.exists(SINGLE_SCHEDULE) else {}
     for name in names:
         cfg = wl.CONFIGS[name]
         D, N, L, M, P, xi, win = cfg["D"], cfg["N"], cfg["L"], cfg["M"], cfg["P"], cfg["xi"], cfg["window"]
         x, q = wl.config_system(name)
-        Q = float((q * q).sum())
-        kw = dict(window=win, n_max=N)
-        if D in (1, 2):
-            kw.update(Q=Q, tol=1e-6 * _lib.se_error_scale(Q, xi, L))
         x64 = torch.tensor(x, device=dev)
         q64 = torch.tensor(q, device=dev)
         row = {"workload": name, "D": D, "N": N, "M": M, "P": P, "window": win, "xi": xi,
@@ -482,13 +534,19 @@ def single_systems(args, names=("C1_3P", "C2_0P", "C3_2P", "C4_1P")):
                           "charges": cfg["charges"], "outputs": "potential+force+energy"}}
         res = {}
         for prec in ("f32", "f64"):
-            plan = SpectralEwald(D, L, xi, M, P, prec=prec, **kw)
+            plan, tuned = _single_plan(name, prec, stored)
             # timed without per-stage events (for a small system their
             # records cost more than its kernels); the stage table comes
             # from a profiled run of its own
             ms, o, _ = run_path(plan, x64, q64, steps, args.warmup, profile=False)
             row[f"value_{prec}"] = N / (ms * 1e-3)
             row[f"ms_per_step_{prec}"] = ms
+            row[f"schedule_{prec}"] = "autotuned, stored" if tuned else "default"
+            if tuned:
+                dplan, _ = _single_plan(name, prec)
+                row[f"ms_per_step_{prec}_default"], _, _ = run_path(dplan, x64, q64, steps, args.warmup,
+                                                                    profile=False)
+                del dplan
             if prec == "f32":
                 row["Mt"] = plan.info.Mt
                 _, _, st = run_path(plan, x64, q64, steps, 0)
@@ -807,6 +865,8 @@ def main():
     ap.add_argument("--xi-balance", action="store_true",
                     help="time k space + real space against xi (single-system workloads; default C4_1P)")
     ap.add_argument("--no-single", action="store_true", help="batch: skip the C1-C4 single-system lines")
+    ap.add_argument("--retune-singles", default=None,
+                    help="run the single-plan autotuner on C1-C4 and write the chosen knobs to this path")
     ap.add_argument("--cpu-oracle-sample", type=float, default=None, help=argparse.SUPPRESS)
     ap.add_argument("--force-methods", action="store_true",
                     help="force method 1 vs method 2 against P on the paper's 3P workload (Section 7.2)")
@@ -838,6 +898,8 @@ def main():
         sys.exit(2)
     if args.real_space:
         return main_real_space(args)
+    if args.retune_singles:
+        return main_retune_singles(args)
     if args.xi_balance:
         return main_xi_balance(args)
     if args.force_methods:
